@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Throughput of the coherent-dedispersion correlator on one MI355X.
+
+One step = the whole pre-integrator stage over one synthetic stream of the
+36-antenna workload (64 x 1 MHz channels at 1.2-1.264 GHz, 2^20 complex-int8
+samples per channel and antenna, 256 trial DMs over 0-2000 pc cm^-3, 1 ms
+dumps, 10 injected pulses): overlap-save forward FFT, chirp generation, chirp
+multiply + inverse FFT for every DM, cross-multiply and integrate-and-dump of
+all 666 baselines, and the fetch of every dump record into device memory.
+The input is resident in HBM before the timed region.
+
+Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "antenna-samples×DM-trials/s correlated; % HBM/MFMA peak; learned vs plain speedup"
+UNIT = "antenna-samples*DM-trials/s"
+PEAKS = {  # MI355X published dense peaks
+    "hbm_gbs": 8000.0, "fp32_vector_tflops": 157.3, "fp32_mfma_tflops": 157.3, "fp16_mfma_tflops": 2500.0,
+    "fp8_mfma_tflops": 5000.0,
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("fft.hpp", "kernels.hpp", "ddx.hip"):
+        with open(os.path.join(ROOT, "paper_1109_3186_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def build_input(p, dev, chunk):
+    import torch
+
+    import synth
+    t0 = time.time()
+    x, pulses, fc, pos = synth.make_stream_device(p, dev)
+    s = p["samples"]
+    chunks = []
+    for s0 in range(0, s, chunk):
+        s1 = min(s, s0 + chunk)
+        chunks.append(x[..., 2 * s0:2 * s1].contiguous())
+    del x
+    torch.cuda.synchronize()
+    log("input built in %.1f s: %d chunks" % (time.time() - t0, len(chunks)))
+    return chunks, pulses, fc
+
+
+def cpu_baseline(chunks, fc, dms, lay, p, n_dm):
+    """The FP64 oracle on channel 0, n_dm DMs (first and last of the grid), all
+    antennas, the whole time span; units/s scaled to the metric's unit."""
+    import numpy as np
+
+    import oracle
+    x = np.concatenate([c[0].cpu().numpy() for c in chunks], axis=-1)[None]
+    bl = [{"fft_len": int(lay["fft_len"][0]), "valid": int(lay["valid"][0]), "lead": int(lay["lead"][0])}]
+    ds = [0, len(dms) - 1][:n_dm] if n_dm <= 2 else list(np.linspace(0, len(dms) - 1, n_dm).astype(int))
+    t0 = time.time()
+    out = oracle.run_oracle(x, fc[:1], p["f_s"], [dms], p["dump_len"], bl, chans=[0], dm_index=ds)
+    el = time.time() - t0
+    nd = next(iter(out.values())).shape[0]
+    units = p["m_ant"] * nd * p["dump_len"] * len(ds)
+    return {"value": units / el, "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": "channel 0 x %d DMs (trials %s) x %d antennas x %d samples, FP64 numpy, %.1f s "
+                      "(numpy FFT and einsum run single-threaded)" % (len(ds), ds, p["m_ant"], p["samples"], el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--corr", default="f32", choices=["f32", "f16", "e4m3"])
+    ap.add_argument("--chunk", type=int, default=1 << 18, help="samples per process_block call")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-dms", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (requested %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1109_3186_amd import Plan
+
+    dev = torch.device("cuda:0")
+    p = synth.c1_params()
+    chunks, pulses, fc = build_input(p, dev, args.chunk)
+    dms = synth.dm_grid(p["n_dm"], p["dm_max"])
+    plan = Plan(p["m_ant"], fc, p["f_s"], p["dump_len"], max_block_samples=args.chunk, in_dtype="ci8",
+                corr_dtype=args.corr, out_mode="packed")
+    plan.set_dm_trials(dms)
+    lay = plan.layout()
+    log("plan: N %d V %d..%d lead %d, ring %d dumps, %.1f GB device" % (
+        lay["fft_len"][0], lay["valid"].min(), lay["valid"].max(), lay["lead"][0], lay["ring_dumps"],
+        lay["device_bytes"] / 1e9))
+    out = torch.empty((lay["ring_dumps"], lay["record_elems"]), dtype=torch.complex64, device=dev)
+
+    def step():
+        plan.reset_stream()
+        got = 0
+        for i, ch in enumerate(chunks):
+            plan.process_block(ch, flush=(i == len(chunks) - 1))
+            _, nd, _ = plan.fetch(out=out)
+            got += nd
+        return got
+
+    for w in range(args.warmup):
+        n_dumps = step()
+        torch.cuda.synchronize()
+        log("warmup %d done (%d dumps)" % (w, n_dumps))
+    plan.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        n_dumps = step()
+        log("step %d enqueued" % k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = plan.profile()
+    plan.set_profiling(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    units = p["m_ant"] * n_dumps * p["dump_len"] * p["n_chan"] * p["n_dm"]
+    value = units / (ms / 1e3)
+    log("per step: %.1f ms, %.3e units/s; kernels: %s" % (
+        ms, value, {k: round(v["time_ms"] / args.steps, 1) for k, v in prof.items()}))
+
+    dom = max(prof, key=lambda k: prof[k]["time_ms"])
+    d = prof[dom]
+    per_launch_s = d["time_ms"] / 1e3 / max(d["launches"], 1)
+    if dom == "correlate":
+        bound, peak = "mfma", {"f32": PEAKS["fp32_mfma_tflops"], "f16": PEAKS["fp16_mfma_tflops"],
+                               "e4m3": PEAKS["fp8_mfma_tflops"]}[args.corr]
+    else:
+        bound, peak = "alu", PEAKS["fp32_vector_tflops"]
+    achieved = d["flops"] / max(d["launches"], 1) / per_launch_s / 1e12
+    roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": measured_traffic(dom, "c1"), "kernel": dom,
+                "avg_launch_ms": round(per_launch_s * 1e3, 4),
+                "kernels": {k: {"ms_per_step": round(v["time_ms"] / args.steps, 2),
+                                "launches_per_step": v["launches"] // args.steps,
+                                "tflops": round(v["flops"] / max(v["time_ms"], 1e-9) / 1e9, 2),
+                                "staged_gbs": round(v["bytes"] / max(v["time_ms"], 1e-9) / 1e6, 1)}
+                            for k, v in prof.items() if v["launches"]}}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a slice")
+        cpu = cpu_baseline(chunks, fc, dms, lay, p, args.cpu_dms)
+    rec = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f32", "f16": "f16", "e4m3": "e4m3"}[args.corr], "data": "synthetic",
+        "config": {"workload": "36 ant x 64 ch x 2^20 ci8 samples, 256 DMs 0-2000, N %d, 1 ms dumps"
+                               % lay["fft_len"][0],
+                   "n_ant": p["m_ant"], "n_chan": p["n_chan"], "samples": p["samples"], "n_dm": p["n_dm"],
+                   "dump_len": p["dump_len"], "fft_len": int(lay["fft_len"][0]), "chunk": args.chunk,
+                   "input": "ci8", "corr": args.corr, "parallelism": "none (1 GPU)"},
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,214 @@
+/* ddx: coherent-dedispersion correlator for AMD MI355X (gfx950).
+ *
+ * The pre-integrator stage of an antenna-coherent search for dispersed radio
+ * pulses (Bannister & Cornwell 2011, "The Chirpolator and The Chimageator"):
+ *
+ *   1. each antenna's complex baseband voltages (Sec. 3.2: complex Nyquist
+ *      sampling, f_s = channel bandwidth) are coherently dedispersed for every
+ *      trial DM: convolved with the inverse of the interstellar medium's
+ *      response (Sec. 2.3.2), derived from the delay law of Eq. dmdelay
+ *      (Sec. 2.1), using overlap-save FFT blocks;
+ *   2. every antenna pair is multiplied, one voltage by the other's conjugate
+ *      (the "mixing" of Sec. 3.2, Eq. xpq), and integrated and dumped at a
+ *      fixed cadence (the integrate-and-dump boundary of Sec. 5.1), giving
+ *      per-DM visibilities.  At DM = 0 a dump equals the k = 0 term of the block
+ *      partial DFT of Appendix A.3 (Eq. block_cic).
+ *
+ * Conventions shared by all calls:
+ *   - every function returns DDX_OK (0) or a negative DDX_E* status and never
+ *     aborts; ddx_last_error() holds a message for the last failure of a plan;
+ *   - units: Hz, seconds, pc cm^-3 as double; sample counts as int64_t;
+ *   - a plan is not thread-safe; separate plans are independent;
+ *   - memory owned by the plan: spectra, chirp tables, dedispersed voltages,
+ *     the dump ring, the input history.  Memory owned by the caller: inputs,
+ *     outputs, streams (a hipStream_t passed as void*, NULL = default stream).
+ *
+ * Readings where the paper is silent (the filter's form and sign, bin
+ * frequencies, blocking, normalisation, baseline order) are stated at the
+ * calls that depend on them.
+ */
+#ifndef DDX_H
+#define DDX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define DDX_OK 0
+#define DDX_EINVAL (-1)       /* invalid argument */
+#define DDX_ENOMEM (-2)       /* device allocation failed or max_device_bytes exceeded */
+#define DDX_EDEVICE (-3)      /* a HIP call or kernel launch failed */
+#define DDX_ESTATE (-4)       /* call not allowed in the plan's current state */
+#define DDX_ESIZE (-5)        /* caller buffer too small */
+#define DDX_EFULL (-6)        /* unfetched dumps would be overwritten */
+#define DDX_EUNSUPPORTED (-7) /* valid request this build does not implement */
+
+/* Input sample formats: interleaved (re, im). */
+#define DDX_IN_CI8 0  /* int8 re, int8 im: 2 bytes per sample */
+#define DDX_IN_CF32 1 /* float re, float im: 8 bytes per sample */
+
+/* Correlator input formats (the dedispersed voltages). */
+#define DDX_CORR_F32 0  /* FP32 voltages, FP32 MFMA, FP32 accumulate */
+#define DDX_CORR_F16 1  /* voltages x scale rounded to IEEE binary16 (RNE, saturating) */
+#define DDX_CORR_E4M3 2 /* voltages x scale rounded to OCP FP8 E4M3 (RNE, saturating to +-448) */
+
+/* Visibility layout within one dump record. */
+#define DDX_OUT_PACKED 0 /* upper triangle incl. autos, b(i,j) = i M - i(i-1)/2 + (j - i) */
+#define DDX_OUT_FULL 1   /* full M x M, row-major, V_ji = conj(V_ij) */
+
+/* ddx_process_block flags. */
+#define DDX_FLUSH 1 /* end of stream: zero-pad after the last sample and finish */
+
+typedef struct ddx_desc {
+  int32_t n_ant;               /* M >= 1 antennas */
+  int32_t n_chan;              /* C >= 1 channels */
+  const double* chan_freq_hz;  /* [C] sky frequency of each channel's DC bin, > samp_rate/2 */
+  double samp_rate_hz;         /* complex sample rate = channel bandwidth, > 0 */
+  int32_t sideband;            /* +1: bin offset f is sky f_c + f; -1: sky f_c - f */
+  int32_t in_dtype;            /* DDX_IN_* */
+  int32_t corr_dtype;          /* DDX_CORR_* */
+  int32_t dump_len;            /* L >= 1 samples per dump */
+  const int32_t* fft_len;      /* [C] power-of-two FFT lengths, or NULL / 0 entries = auto */
+  double k_dm;                 /* dispersion constant in s Hz^2 cm^3/pc; 0 = 4.148808e15 */
+  int64_t max_block_samples;   /* largest n one ddx_process_block call accepts, >= 1 */
+  size_t max_device_bytes;     /* cap on plan-owned device memory, 0 = none */
+  int32_t out_mode;            /* DDX_OUT_* */
+  const float* chan_scale;     /* [C] correlator-input scales (F16/E4M3), or NULL = rule */
+} ddx_desc;
+
+typedef struct ddx_plan ddx_plan;
+
+typedef struct ddx_layout {
+  int32_t n_ant, n_chan, n_baselines, dump_len, out_mode, corr_dtype, in_dtype, sideband;
+  double samp_rate_hz, k_dm;
+  const double* chan_freq_hz;  /* [C] */
+  const int32_t* fft_len;      /* [C] N_c */
+  const int32_t* valid;        /* [C] V_c: outputs kept per block, a multiple of L */
+  const int32_t* lead;         /* [C] block b reads samples [b V_c - lead_c, b V_c - lead_c + N_c) */
+  const int32_t* n_dm;         /* [C] D_c trial DMs */
+  const int64_t* dm_offset;    /* [C+1] prefix sums of D_c: position of (c, d) in a dump record */
+  const double* dm;            /* [dm_offset[C]] trial DMs, channel-major */
+  const double* delay_s;       /* [dm_offset[C]] K DM / f_c^2: channel-centre delay behind infinite frequency */
+  const int64_t* shift;        /* [dm_offset[C]] rint(K DM (f_c^-2 - f_top^-2) f_s): samples behind the highest channel */
+  const float* scale;          /* [C] correlator-input scale s_c (1 for F32) */
+  int64_t record_elems;        /* complex64 values per dump record = dm_offset[C] * n_baselines */
+  int64_t samples_in;          /* samples accepted so far per (channel, antenna) */
+  int64_t dumps_ready;         /* dumps complete in every channel */
+  int64_t dumps_fetched;       /* dumps already returned by ddx_fetch_visibilities */
+  int64_t ring_dumps;          /* capacity of the device dump ring */
+  size_t device_bytes;         /* plan-owned device memory */
+} ddx_layout;
+
+/* Create a plan from a descriptor (copied; the caller's arrays may be freed).
+ * Validates all fields and allocates nothing on the device.  *out is set only
+ * on success.  Errors: EINVAL (bad field), ENOMEM (host allocation). */
+int ddx_plan_create(const ddx_desc* desc, ddx_plan** out);
+
+/* Set the trial DMs of one channel (chan >= 0) or of all (chan = -1): n_dm >= 1
+ * finite values >= 0 in any order and spacing (uniform, or the geometric banks
+ * of Appendix A.4, Eq. Ti).  When every channel has its list, fixes the
+ * blocking of each channel from the largest DM:
+ *   - half-overlap A_c = ceil(max intra-channel smear) in samples, where the top
+ *     edge f_c + f_s/2 arrives K DM (f_c^-2 - (f_c + f_s/2)^-2) before the
+ *     centre and the bottom edge K DM ((f_c - f_s/2)^-2 - f_c^-2) after it
+ *     (Eq. dmdelay);
+ *   - N_c = the descriptor's FFT length, or the smallest power of two >= 256
+ *     keeping at least half of each block;
+ *   - V_c = L floor((N_c - 2 A_c) / L), lead_c = floor((N_c - V_c)/2);
+ * builds the FP64 tables and allocates device memory.  Returns ESTATE after the
+ * first ddx_process_block, EUNSUPPORTED for N_c > 32768, EINVAL if V_c < L. */
+int ddx_set_dm_trials(ddx_plan* plan, int32_t chan, const double* dm_pc_cm3, int32_t n_dm);
+
+/* Restrict dedispersion and correlation of channel chan (-1 = all) to the DMs
+ * with mask[d] != 0 (mask has D_c entries; NULL = all active).  Blocking is
+ * unchanged, so active DMs give results bitwise equal to a full sweep.
+ * Inactive DMs' visibilities are written as zeros.  Allowed between calls. */
+int ddx_set_active_dms(ddx_plan* plan, int32_t chan, const uint8_t* mask);
+
+/* Export the blocking, tables and stream counters.  Pointers refer to
+ * plan-owned host memory valid until the next ddx_set_dm_trials or
+ * ddx_plan_destroy.  Requires ddx_set_dm_trials for every channel (ESTATE). */
+int ddx_get_layout(const ddx_plan* plan, ddx_layout* out);
+
+/* Append n >= 0 samples per (channel, antenna) to the stream and enqueue all
+ * work they complete on hip_stream (asynchronous).
+ *   d_volts: DEVICE pointer, layout [C][M][n] samples of in_dtype, owned by the
+ *            caller and valid until the stream has passed this work.
+ * Block b of channel c covers output samples [b V_c, (b+1) V_c) and reads input
+ * [b V_c - lead_c, b V_c - lead_c + N_c); samples before 0 are zero.  A block
+ * runs once its whole input window has arrived, so results do not depend on
+ * how the stream is split into calls.  flags & DDX_FLUSH zero-pads after the
+ * last sample, runs the remaining blocks and ends the stream (later calls:
+ * ESTATE).  Per block and active DM d:
+ *   X = DFT_N(x_b) (unnormalised, exp(-2 pi i k n / N));
+ *   H[k] = exp(-2 pi i r), r = u - rint(u), u = K DM f_k^2 / (f_c^2 (f_c + f_k)),
+ *     f_k = sideband * (k < N/2 ? k : k - N) f_s / N, u and r in FP64;
+ *   y[b V + j] = (1/N) IDFT(X H)[lead + j], j < V;
+ * and for each complete dump m (samples [m L, (m+1) L)):
+ *   V_ij = sum_n y_i[n] conj(y_j[n])   (raw sum, input units squared; for
+ *   F16/E4M3 the voltages are s_c y rounded and the sums divided by s_c^2).
+ * A trailing partial dump is dropped.  Errors: EINVAL (n < 0, n >
+ * max_block_samples, NULL volts with n > 0), ESTATE (no DM trials, stream
+ * flushed), EFULL (the dump ring would overwrite unfetched dumps: fetch first),
+ * EDEVICE. */
+int ddx_process_block(ddx_plan* plan, const void* d_volts, int64_t n, int32_t flags, void* hip_stream);
+
+/* Copy every dump complete in all channels and not yet fetched to out (device
+ * or host memory, caller-owned), enqueued on hip_stream (a host destination is
+ * complete when the stream is synchronised).  Layout: [dump][channel][dm][baseline]
+ * complex64 (float re, float im); the record of one dump holds record_elems
+ * values, channel c / DM d at (dm_offset[c] + d) * n_baselines.
+ * *first_dump = absolute index of the first dump returned, *n_dumps = count.
+ * If cap_bytes is too small returns ESIZE with *n_dumps = the count required
+ * and copies nothing.  out may be NULL when no dump is ready. */
+int ddx_fetch_visibilities(ddx_plan* plan, void* out, size_t cap_bytes, int64_t* first_dump,
+                           int64_t* n_dumps, void* hip_stream);
+
+/* Start a new stream on the same plan: sample and dump counters, input history
+ * and unfetched dumps are discarded; DM trials, blocking, tables and device
+ * memory are kept.  Synchronises the plan's last stream first.  ESTATE before
+ * ddx_set_dm_trials. */
+int ddx_reset_stream(ddx_plan* plan);
+
+/* Kernel kinds timed by the profiler. */
+#define DDX_K_FORWARD 0  /* overlap-save gather + forward FFT */
+#define DDX_K_CHIRP 1    /* chirp table from the FP64 phase */
+#define DDX_K_DEDISP 2   /* chirp multiply + inverse FFT + discard (+ quantise) */
+#define DDX_K_CORR 3     /* cross-multiply + integrate-and-dump on MFMA */
+#define DDX_K_OTHER 4    /* history carry, zeroing of inactive DMs */
+#define DDX_N_KINDS 5
+
+typedef struct ddx_profile {
+  int64_t launches[DDX_N_KINDS];  /* kernel launches recorded per kind */
+  double time_ms[DDX_N_KINDS];    /* summed device time between the events around each launch */
+  double flops[DDX_N_KINDS];      /* algorithmic flops: 5 N log2 N per FFT, 6 N per chirp multiply,
+                                     8 L per baseline (i <= j) per dump */
+  double bytes[DDX_N_KINDS];      /* bytes each kernel must move as staged (inputs once + outputs) */
+} ddx_profile;
+
+/* on != 0: record a pair of hipEvents around every kernel launch on the
+ * launch's stream (adds a little host overhead); on = 0 stops recording.
+ * Turning it on clears earlier records. */
+int ddx_set_profiling(ddx_plan* plan, int32_t on);
+
+/* Synchronise the recorded events and sum them per kernel kind into *out. */
+int ddx_get_profile(ddx_plan* plan, ddx_profile* out);
+
+/* Synchronise the plan's last stream and free plan-owned memory.  NULL is a no-op. */
+int ddx_plan_destroy(ddx_plan* plan);
+
+/* Static description of a status code. */
+const char* ddx_strerror(int status);
+
+/* Message for the last failing call on this plan ("" if none). */
+const char* ddx_last_error(const ddx_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDX_H */

@@ -1,0 +1,12 @@
+"""MI355X (gfx950) coherent-dedispersion correlator.
+
+The path runs in the HIP library libddx.so (C ABI in include/ddx.h); this
+package holds its sources (csrc/), the in-tree build step (build.py) and a thin
+ctypes binding (binding.py).  There is no CPU fallback: without the built
+library every call raises.
+"""
+from .binding import (  # noqa: F401
+    Plan, DdxError, lib, LIB_PATH, SIGNATURES,
+    OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ESIZE, EFULL, EUNSUPPORTED,
+    IN_CI8, IN_CF32, CORR_F32, CORR_F16, CORR_E4M3, OUT_PACKED, OUT_FULL, FLUSH,
+)

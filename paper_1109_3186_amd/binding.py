@@ -1,0 +1,252 @@
+"""ctypes binding of libddx (include/ddx.h): argument marshalling only.
+
+Every step of the dedispersion/correlation path runs in the HIP library; this
+module only converts Python/numpy/torch arguments to C pointers and sizes and
+turns status codes into exceptions.  It fails loudly if the library is missing.
+"""
+import ctypes as ct
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libddx.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ESIZE, EFULL, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+IN_CI8, IN_CF32 = 0, 1
+CORR_F32, CORR_F16, CORR_E4M3 = 0, 1, 2
+OUT_PACKED, OUT_FULL = 0, 1
+FLUSH = 1
+
+_IN = {"ci8": IN_CI8, "cf32": IN_CF32}
+_CORR = {"f32": CORR_F32, "f16": CORR_F16, "e4m3": CORR_E4M3}
+_OUT = {"packed": OUT_PACKED, "full": OUT_FULL}
+
+
+class Desc(ct.Structure):
+    _fields_ = [
+        ("n_ant", ct.c_int32), ("n_chan", ct.c_int32), ("chan_freq_hz", ct.POINTER(ct.c_double)),
+        ("samp_rate_hz", ct.c_double), ("sideband", ct.c_int32), ("in_dtype", ct.c_int32),
+        ("corr_dtype", ct.c_int32), ("dump_len", ct.c_int32), ("fft_len", ct.POINTER(ct.c_int32)),
+        ("k_dm", ct.c_double), ("max_block_samples", ct.c_int64), ("max_device_bytes", ct.c_size_t),
+        ("out_mode", ct.c_int32), ("chan_scale", ct.POINTER(ct.c_float)),
+    ]
+
+
+class Layout(ct.Structure):
+    _fields_ = [
+        ("n_ant", ct.c_int32), ("n_chan", ct.c_int32), ("n_baselines", ct.c_int32), ("dump_len", ct.c_int32),
+        ("out_mode", ct.c_int32), ("corr_dtype", ct.c_int32), ("in_dtype", ct.c_int32), ("sideband", ct.c_int32),
+        ("samp_rate_hz", ct.c_double), ("k_dm", ct.c_double),
+        ("chan_freq_hz", ct.POINTER(ct.c_double)), ("fft_len", ct.POINTER(ct.c_int32)),
+        ("valid", ct.POINTER(ct.c_int32)), ("lead", ct.POINTER(ct.c_int32)), ("n_dm", ct.POINTER(ct.c_int32)),
+        ("dm_offset", ct.POINTER(ct.c_int64)), ("dm", ct.POINTER(ct.c_double)),
+        ("delay_s", ct.POINTER(ct.c_double)), ("shift", ct.POINTER(ct.c_int64)), ("scale", ct.POINTER(ct.c_float)),
+        ("record_elems", ct.c_int64), ("samples_in", ct.c_int64), ("dumps_ready", ct.c_int64),
+        ("dumps_fetched", ct.c_int64), ("ring_dumps", ct.c_int64), ("device_bytes", ct.c_size_t),
+    ]
+
+
+N_KINDS = 5
+KIND_NAMES = ["forward", "chirp", "dedisperse", "correlate", "other"]
+
+
+class Profile(ct.Structure):
+    _fields_ = [("launches", ct.c_int64 * N_KINDS), ("time_ms", ct.c_double * N_KINDS),
+                ("flops", ct.c_double * N_KINDS), ("bytes", ct.c_double * N_KINDS)]
+
+
+# Every entry point of include/ddx.h with its argument and result types.
+SIGNATURES = {
+    "ddx_plan_create": ([ct.POINTER(Desc), ct.POINTER(ct.c_void_p)], ct.c_int),
+    "ddx_set_dm_trials": ([ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_double), ct.c_int32], ct.c_int),
+    "ddx_set_active_dms": ([ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_uint8)], ct.c_int),
+    "ddx_get_layout": ([ct.c_void_p, ct.POINTER(Layout)], ct.c_int),
+    "ddx_process_block": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_void_p], ct.c_int),
+    "ddx_fetch_visibilities": ([ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.POINTER(ct.c_int64),
+                                ct.POINTER(ct.c_int64), ct.c_void_p], ct.c_int),
+    "ddx_reset_stream": ([ct.c_void_p], ct.c_int),
+    "ddx_set_profiling": ([ct.c_void_p, ct.c_int32], ct.c_int),
+    "ddx_get_profile": ([ct.c_void_p, ct.POINTER(Profile)], ct.c_int),
+    "ddx_plan_destroy": ([ct.c_void_p], ct.c_int),
+    "ddx_strerror": ([ct.c_int], ct.c_char_p),
+    "ddx_last_error": ([ct.c_void_p], ct.c_char_p),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libddx.so (built in-tree); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libddx.so not built: run __graft_entry__.build() (or python -m paper_1109_3186_amd.build)")
+        L = ct.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+class DdxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (lib().ddx_strerror(status).decode(), status, msg))
+        self.status = status
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ct.c_void_p(stream)
+    return ct.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """One ddx plan (see include/ddx.h for the semantics of every call)."""
+
+    def __init__(self, n_ant, chan_freqs, samp_rate, dump_len, max_block_samples, *, sideband=1, in_dtype="ci8",
+                 corr_dtype="f32", fft_len=None, k_dm=0.0, max_device_bytes=0, out_mode="packed", chan_scale=None):
+        L = lib()
+        fc = np.ascontiguousarray(chan_freqs, dtype=np.float64)
+        self._fc = fc
+        d = Desc()
+        d.n_ant = n_ant
+        d.n_chan = len(fc)
+        d.chan_freq_hz = fc.ctypes.data_as(ct.POINTER(ct.c_double))
+        d.samp_rate_hz = samp_rate
+        d.sideband = sideband
+        d.in_dtype = _IN[in_dtype]
+        d.corr_dtype = _CORR[corr_dtype]
+        d.dump_len = dump_len
+        if fft_len is not None:
+            self._fft = np.ascontiguousarray(np.broadcast_to(fft_len, fc.shape), dtype=np.int32)
+            d.fft_len = self._fft.ctypes.data_as(ct.POINTER(ct.c_int32))
+        d.k_dm = k_dm
+        d.max_block_samples = int(max_block_samples)
+        d.max_device_bytes = int(max_device_bytes)
+        d.out_mode = _OUT[out_mode]
+        if chan_scale is not None:
+            self._scale = np.ascontiguousarray(np.broadcast_to(chan_scale, fc.shape), dtype=np.float32)
+            d.chan_scale = self._scale.ctypes.data_as(ct.POINTER(ct.c_float))
+        h = ct.c_void_p()
+        rc = L.ddx_plan_create(ct.byref(d), ct.byref(h))
+        if rc != OK:
+            raise DdxError(rc, "ddx_plan_create")
+        self._h = h
+        self.n_ant = n_ant
+        self.in_dtype = in_dtype
+
+    def _check(self, rc, what):
+        if rc != OK:
+            raise DdxError(rc, "%s: %s" % (what, lib().ddx_last_error(self._h).decode()))
+
+    def set_dm_trials(self, dms, chan=-1):
+        a = np.ascontiguousarray(dms, dtype=np.float64)
+        self._check(lib().ddx_set_dm_trials(self._h, chan, a.ctypes.data_as(ct.POINTER(ct.c_double)), len(a)),
+                    "ddx_set_dm_trials")
+
+    def set_active_dms(self, mask, chan=-1):
+        if mask is None:
+            ptr = None
+        else:
+            m = np.ascontiguousarray(mask, dtype=np.uint8)
+            ptr = m.ctypes.data_as(ct.POINTER(ct.c_uint8))
+        self._check(lib().ddx_set_active_dms(self._h, chan, ptr), "ddx_set_active_dms")
+
+    def layout(self):
+        lay = Layout()
+        self._check(lib().ddx_get_layout(self._h, ct.byref(lay)), "ddx_get_layout")
+        C = lay.n_chan
+
+        def arr(ptr, n, dt):
+            return np.ctypeslib.as_array(ptr, shape=(n,)).astype(dt).copy()
+
+        off = arr(lay.dm_offset, C + 1, np.int64)
+        nd = int(off[-1])
+        return {
+            "n_ant": lay.n_ant, "n_chan": C, "n_baselines": lay.n_baselines, "dump_len": lay.dump_len,
+            "out_mode": lay.out_mode, "corr_dtype": lay.corr_dtype, "in_dtype": lay.in_dtype,
+            "sideband": lay.sideband, "samp_rate_hz": lay.samp_rate_hz, "k_dm": lay.k_dm,
+            "chan_freq_hz": arr(lay.chan_freq_hz, C, np.float64), "fft_len": arr(lay.fft_len, C, np.int64),
+            "valid": arr(lay.valid, C, np.int64), "lead": arr(lay.lead, C, np.int64),
+            "n_dm": arr(lay.n_dm, C, np.int64), "dm_offset": off, "dm": arr(lay.dm, nd, np.float64),
+            "delay_s": arr(lay.delay_s, nd, np.float64), "shift": arr(lay.shift, nd, np.int64),
+            "scale": arr(lay.scale, C, np.float32), "record_elems": lay.record_elems,
+            "samples_in": lay.samples_in, "dumps_ready": lay.dumps_ready, "dumps_fetched": lay.dumps_fetched,
+            "ring_dumps": lay.ring_dumps, "device_bytes": lay.device_bytes,
+        }
+
+    def process_block(self, volts, flush=False, stream=None):
+        """volts: torch device tensor, int8 [C, M, 2n] (ci8) or complex64 [C, M, n] (cf32), contiguous."""
+        if volts is None:
+            n, ptr = 0, None
+        else:
+            if not volts.is_cuda or not volts.is_contiguous():
+                raise ValueError("volts must be a contiguous device tensor")
+            import torch
+            if self.in_dtype == "ci8":
+                if volts.dtype != torch.int8:
+                    raise ValueError("ci8 plan needs an int8 tensor [C, M, 2n]")
+                n = volts.shape[-1] // 2
+            else:
+                if volts.dtype != torch.complex64:
+                    raise ValueError("cf32 plan needs a complex64 tensor [C, M, n]")
+                n = volts.shape[-1]
+            ptr = ct.c_void_p(volts.data_ptr())
+        rc = lib().ddx_process_block(self._h, ptr, int(n), FLUSH if flush else 0, _stream_handle(stream))
+        self._check(rc, "ddx_process_block")
+
+    def fetch(self, out=None, stream=None):
+        """Return (first_dump, n_dumps, tensor [n_dumps, record_elems] complex64 on the device)."""
+        import torch
+        first, nd = ct.c_int64(), ct.c_int64()
+        st = _stream_handle(stream)
+        rc = lib().ddx_fetch_visibilities(self._h, None, 0, ct.byref(first), ct.byref(nd), st)
+        if rc == OK and nd.value == 0:
+            return first.value, 0, None
+        if rc not in (OK, ESIZE):
+            self._check(rc, "ddx_fetch_visibilities")
+        need = nd.value
+        rec = self.layout()["record_elems"]
+        if out is None:
+            out = torch.empty((need, rec), dtype=torch.complex64, device="cuda")
+        elif out.numel() < need * rec or out.dtype != torch.complex64 or not out.is_contiguous():
+            raise ValueError("output tensor too small or not contiguous complex64")
+        rc = lib().ddx_fetch_visibilities(self._h, ct.c_void_p(out.data_ptr()), out.numel() * 8, ct.byref(first),
+                                          ct.byref(nd), st)
+        self._check(rc, "ddx_fetch_visibilities")
+        return first.value, nd.value, out.view(-1)[: need * rec].view(need, rec)
+
+    def reset_stream(self):
+        self._check(lib().ddx_reset_stream(self._h), "ddx_reset_stream")
+
+    def set_profiling(self, on):
+        self._check(lib().ddx_set_profiling(self._h, 1 if on else 0), "ddx_set_profiling")
+
+    def profile(self):
+        pr = Profile()
+        self._check(lib().ddx_get_profile(self._h, ct.byref(pr)), "ddx_get_profile")
+        return {KIND_NAMES[k]: {"launches": pr.launches[k], "time_ms": pr.time_ms[k], "flops": pr.flops[k],
+                                "bytes": pr.bytes[k]} for k in range(N_KINDS)}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ddx_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,244 @@
+// Register-resident, LDS-exchanged complex FFT for one workgroup (gfx950).
+//
+// One workgroup transforms one N-point sequence, N = 2^LOGN with 8 <= LOGN <= 15.
+// Each of the T = N / P threads keeps P points in registers.  The transform is a
+// Stockham auto-sort sequence of radix-R passes (R divides P): in a pass with
+// current sub-transform length NS, butterfly j (0 <= j < N/R) reads the points
+// j + r N/R, multiplies point r by exp(s 2 pi i r k / (NS R)) with k = j mod NS,
+// does an R-point DFT in registers and writes output q to
+// (j / NS) NS R + k + q NS.  Between passes the points travel through LDS, real
+// parts then imaginary parts, so that N = 32768 fits the 160 KB of one CU.
+//
+// Load pattern of the first pass and store pattern of the last pass are both
+// "point (t + u T) + r N / R at register u R + r", i.e. coalesced across threads,
+// and the output is in natural order.  The transform is unnormalised:
+// sum_n x[n] exp(s 2 pi i k n / N) with s = -1 (forward) or +1 (inverse).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ddx {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// sin(2 pi x) and cos(2 pi x) of an angle given in revolutions; the hardware
+// transcendental unit takes revolutions directly (measured max abs error
+// 1.24e-7 over [-1/2, 1/2)).
+__device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
+__device__ __forceinline__ float cos_rev(float x) { return __builtin_amdgcn_cosf(x); }
+
+// exp(S 2 pi i num / 2^LOGDEN) for 0 <= num < 2^LOGDEN, reduced exactly to [-1/2, 1/2).
+template <int LOGDEN, int S>
+__device__ __forceinline__ float2 twiddle(int num) {
+  float x = (float)num * (1.0f / (float)(1 << LOGDEN));
+  x = (x >= 0.5f) ? x - 1.0f : x;
+  return make_float2(cos_rev(x), (float)S * sin_rev(x));
+}
+
+// cos and sin of 2 pi m / 32, m = 0..15 (constants of the in-register butterflies)
+__device__ constexpr float kCos32[16] = {
+    1.000000000e+00f, 9.807852804e-01f, 9.238795325e-01f, 8.314696123e-01f,
+    7.071067812e-01f, 5.555702330e-01f, 3.826834324e-01f, 1.950903220e-01f,
+    0.0f,             -1.950903220e-01f, -3.826834324e-01f, -5.555702330e-01f,
+    -7.071067812e-01f, -8.314696123e-01f, -9.238795325e-01f, -9.807852804e-01f};
+__device__ constexpr float kSin32[16] = {
+    0.0f,             1.950903220e-01f, 3.826834324e-01f, 5.555702330e-01f,
+    7.071067812e-01f, 8.314696123e-01f, 9.238795325e-01f, 9.807852804e-01f,
+    1.000000000e+00f, 9.807852804e-01f, 9.238795325e-01f, 8.314696123e-01f,
+    7.071067812e-01f, 5.555702330e-01f, 3.826834324e-01f, 1.950903220e-01f};
+
+constexpr int bitrev(int i, int bits) {
+  int r = 0;
+  for (int b = 0; b < bits; ++b) r |= ((i >> b) & 1) << (bits - 1 - b);
+  return r;
+}
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
+// Multiply by exp(S 2 pi i m / 32) with m a compile-time constant after unrolling.
+template <int S>
+__device__ __forceinline__ float2 rot32(float2 a, int m) {
+  if (m == 0) return a;
+  if (m == 8) return S > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+  const float c = kCos32[m], s = (float)S * kSin32[m];
+  return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+}
+
+// In-place R-point DFT of v[0..R-1] (R = 2..32) by decimation in frequency:
+// natural-order input, output X[q] left in register bitrev(q).  Working in place
+// keeps the register footprint at the R points themselves.
+template <int R, int S>
+__device__ __forceinline__ void dft_reg(float2* v) {
+#pragma unroll
+  for (int h = R / 2; h >= 1; h >>= 1) {  // butterflies of length 2h
+#pragma unroll
+    for (int i = 0; i < R; i += 2 * h) {
+#pragma unroll
+      for (int j = 0; j < h; ++j) {
+        const float2 a = v[i + j], b = v[i + j + h];
+        v[i + j] = cadd(a, b);
+        v[i + j + h] = rot32<S>(csub(a, b), j * (16 / h));
+      }
+    }
+  }
+}
+
+// Register that holds DFT output q after dft_reg<R>.
+template <int R>
+__device__ __forceinline__ constexpr int out_reg(int q) { return bitrev(q, ilog2(R)); }
+
+// Radix plan per transform length: P points per thread, passes of radix R[i].
+template <int LOGN> struct Plan;
+template <> struct Plan<8>  { static constexpr int P = 16, NP = 2, R[3] = {16, 16, 1}; };
+template <> struct Plan<9>  { static constexpr int P = 16, NP = 3, R[3] = {16, 16, 2}; };
+template <> struct Plan<10> { static constexpr int P = 16, NP = 3, R[3] = {16, 16, 4}; };
+template <> struct Plan<11> { static constexpr int P = 16, NP = 3, R[3] = {16, 16, 8}; };
+template <> struct Plan<12> { static constexpr int P = 16, NP = 3, R[3] = {16, 16, 16}; };
+template <> struct Plan<13> { static constexpr int P = 16, NP = 4, R[4] = {16, 16, 16, 2}; };
+template <> struct Plan<14> { static constexpr int P = 16, NP = 4, R[4] = {16, 16, 16, 4}; };
+template <> struct Plan<15> { static constexpr int P = 64, NP = 3, R[3] = {32, 32, 32}; };
+
+template <int LOGN> struct Geo {
+  static constexpr int N = 1 << LOGN;
+  static constexpr int P = Plan<LOGN>::P;
+  static constexpr int T = N / P;  // threads per workgroup
+  static constexpr int NP = Plan<LOGN>::NP;
+  static constexpr int R0 = Plan<LOGN>::R[0];
+  static constexpr int RL = Plan<LOGN>::R[NP - 1];
+  // LDS floats for one half-exchange (one pad word per 32 against bank conflicts)
+  static constexpr int LDS_FLOATS = N + N / 32;
+};
+
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 5); }
+
+// Exchange through LDS between a pass of radix R at stride NS and the next of radix R2.
+// Addresses are written as a per-thread base plus compile-time offsets, split into
+// segments below 64 KB so that every access uses the instruction's immediate offset
+// instead of a register of its own.
+template <int STRIDE>  // offset r * STRIDE floats, segments of at most 16383 floats
+__device__ __forceinline__ float* lds_seg(float* base, int r) {
+  constexpr int SEG = STRIDE >= 16384 ? 1 : 16383 / STRIDE + 1;
+  return base + (r / SEG) * SEG * STRIDE;
+}
+
+template <int LOGN, int R, int NS, int R2>
+__device__ __forceinline__ void exchange(float2* v, float* lds, int t) {
+  using G = Geo<LOGN>;
+  // writes: output q of butterfly j goes to (j / NS) NS R + k + q NS
+  constexpr bool WLIN = (NS % 32 == 0) || (NS * R <= 32 && 32 % (NS * R) == 0) || (NS == 1 && R % 32 == 0);
+  // reads: point r of the next pass is t + u T + r N / R2
+  constexpr int RSTR = G::N / R2;
+  constexpr bool RLIN = RSTR % 32 == 0;
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+#pragma unroll
+    for (int u = 0; u < G::P / R; ++u) {
+      const int j = t + u * G::T;
+      const int k = j & (NS - 1);
+      const int base = (j / NS) * NS * R + k;
+      float* wb = lds + lds_pad(base);
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const float2 o = v[u * R + out_reg<R>(q)];
+        const float val = half ? o.y : o.x;
+        if constexpr (WLIN) {
+          constexpr int WSTR = NS + NS / 32;
+          lds_seg<WSTR>(wb, q)[(q % (WSTR >= 16384 ? 1 : 16383 / WSTR + 1)) * WSTR] = val;
+        } else {
+          lds[lds_pad(base + q * NS)] = val;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < G::P / R2; ++u) {
+      float* rb = lds + lds_pad(t + u * G::T);
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        float val;
+        if constexpr (RLIN) {
+          constexpr int STR = RSTR + RSTR / 32;
+          val = lds_seg<STR>(rb, r)[(r % (STR >= 16384 ? 1 : 16383 / STR + 1)) * STR];
+        } else {
+          val = lds[lds_pad(t + u * G::T + r * RSTR)];
+        }
+        if (half) v[u * R2 + r].y = val; else v[u * R2 + r].x = val;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// A zero the compiler cannot see through, computed after `dep`: indices offset by
+// it cannot be hoisted above the work that produced `dep` (empty asm, no code).
+__device__ __forceinline__ int opaque_zero(float dep) {
+  int z = 0;
+  asm volatile("; opaque %1" : "+v"(z) : "v"(dep));
+  return z;
+}
+
+// Force the R values of a butterfly group to be fully computed at this point
+// (empty asm, no code), so that later work ordered after it does not overlap it.
+template <int R>
+__device__ __forceinline__ void pin_regs(float2* v) {
+#pragma unroll
+  for (int i = 0; i < R; ++i) asm volatile("; pin %0 %1" : "+v"(v[i].x), "+v"(v[i].y));
+}
+
+template <int LOGN, int R, int NS, int S>
+__device__ __forceinline__ void pass(float2* v, int t) {
+  using G = Geo<LOGN>;
+  constexpr int LOGD = ilog2(NS * R);
+  int z = 0;
+#pragma unroll
+  for (int u = 0; u < G::P / R; ++u) {
+    if (NS > 1) {
+      const int k = (t + z + u * G::T) & (NS - 1);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[u * R + r] = cmul(v[u * R + r], twiddle<LOGD, S>(r * k));
+    }
+    dft_reg<R, S>(v + u * R);
+    // the next group's twiddles wait for this group's butterflies (register pressure)
+    if (u + 1 < G::P / R) {
+      pin_regs<R>(v + u * R);
+      z = opaque_zero(v[u * R].x);
+    }
+  }
+}
+
+// Passes 1.. of the transform (pass 0 is done by the caller, fused with its loads).
+template <int LOGN, int S, int PASS, int NS>
+struct Passes {
+  __device__ __forceinline__ static void run(float2* v, float* lds, int t) {
+    constexpr int RP = Plan<LOGN>::R[PASS - 1];
+    constexpr int R = Plan<LOGN>::R[PASS];
+    exchange<LOGN, RP, NS / RP, R>(v, lds, t);
+    pass<LOGN, R, NS, S>(v, t);
+    if constexpr (PASS + 1 < Plan<LOGN>::NP) Passes<LOGN, S, PASS + 1, NS * R>::run(v, lds, t);
+  }
+};
+
+// Full transform.  load(i) supplies input point i; the first pass runs group by
+// group as its points arrive.  On return output t + u T + q N / RL is in register
+// u RL + out_reg<RL>(q).
+template <int LOGN, int S, class Load>
+__device__ __forceinline__ void fft_workgroup(float2* v, float* lds, int t, Load load) {
+  using G = Geo<LOGN>;
+  int z = 0;
+#pragma unroll
+  for (int u = 0; u < G::P / G::R0; ++u) {
+#pragma unroll
+    for (int r = 0; r < G::R0; ++r) v[u * G::R0 + r] = load(t + z + u * G::T + r * (G::N / G::R0));
+    dft_reg<G::R0, S>(v + u * G::R0);
+    // loads of the next group wait for this group's butterflies (register pressure)
+    if (u + 1 < G::P / G::R0) {
+      pin_regs<G::R0>(v + u * G::R0);
+      z = opaque_zero(v[u * G::R0].x);
+    }
+  }
+  if constexpr (G::NP > 1) Passes<LOGN, S, 1, G::R0>::run(v, lds, t);
+}
+
+}  // namespace ddx

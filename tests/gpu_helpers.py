@@ -1,0 +1,92 @@
+"""Helpers shared by the GPU tests: run the HIP path through the C ABI and
+compare its visibilities with the FP64 oracle."""
+import sys
+
+import numpy as np
+
+import oracle
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(cfg, in_dtype="cf32", corr="f32", out_mode="packed", chunks=None, fft_len=None, mask=None,
+            max_block=None, chan_scale=None):
+    """Run a whole stream through the library; returns (vis [dumps, record] complex64 numpy, layout)."""
+    import torch
+
+    from paper_1109_3186_amd import Plan
+
+    x = cfg["volts"]
+    m_ant = x.shape[1]
+    s = x.shape[-1] // 2 if in_dtype == "ci8" else x.shape[-1]
+    chunks = [s] if chunks is None else chunks
+    assert sum(chunks) == s
+    mb = max(chunks) if max_block is None else max_block
+    dev = torch.device("cuda:0")
+    fl = fft_len if fft_len is not None else (cfg.get("fft_len") or None)
+    outs = []
+    with Plan(m_ant, cfg["chan_freqs"], cfg["f_s"], cfg["dump_len"], max_block_samples=mb, in_dtype=in_dtype,
+              corr_dtype=corr, out_mode=out_mode, fft_len=fl, chan_scale=chan_scale) as p:
+        for c, dms in enumerate(cfg["dm_lists"]):
+            p.set_dm_trials(dms, chan=c)
+        if mask is not None:
+            for c, mk in enumerate(mask):
+                p.set_active_dms(mk, chan=c)
+        lay = p.layout()
+        pos = 0
+        for i, n in enumerate(chunks):
+            if in_dtype == "ci8":
+                part = np.ascontiguousarray(x[..., 2 * pos:2 * (pos + n)])
+            else:
+                part = np.ascontiguousarray(x[..., pos:pos + n])
+            t = torch.from_numpy(part).to(dev)
+            p.process_block(t, flush=(i == len(chunks) - 1))
+            first, nd, vis = p.fetch()
+            if nd:
+                outs.append(vis.cpu().numpy())
+            torch.cuda.synchronize()
+            del t
+            pos += n
+        lay_end = p.layout()
+    vis = np.concatenate(outs, axis=0) if outs else np.zeros((0, lay["record_elems"]), np.complex64)
+    lay["dumps_ready"] = lay_end["dumps_ready"]
+    return vis, lay
+
+
+def blockings(lay):
+    return [{"fft_len": int(lay["fft_len"][c]), "valid": int(lay["valid"][c]), "lead": int(lay["lead"][c])}
+            for c in range(lay["n_chan"])]
+
+
+def select(vis, lay, c, d):
+    nbl = lay["n_baselines"]
+    o = int(lay["dm_offset"][c] + d)
+    return vis[:, o * nbl:(o + 1) * nbl]
+
+
+def norm_error(got, ref, m_ant):
+    """max |V_got - V_ref| / sqrt(V_ii V_jj) with the reference autocorrelations (packed layout)."""
+    iu, ju = np.triu_indices(m_ant)
+    auto = ref[:, iu == ju].real
+    norm = np.sqrt(np.maximum(auto[:, iu] * auto[:, ju], 1e-300))
+    return float(np.max(np.abs(got.astype(np.complex128) - ref) / norm)) if ref.size else 0.0
+
+
+def compare_with_oracle(cfg, vis, lay, pairs=None, quant=None, scales=None):
+    """Max normalised error over (channel, DM) pairs (all by default)."""
+    m_ant = cfg["volts"].shape[1]
+    bl = blockings(lay)
+    worst = 0.0
+    chans = sorted({c for c, _ in pairs}) if pairs else range(lay["n_chan"])
+    for c in chans:
+        ds = [d for cc, d in pairs if cc == c] if pairs else None
+        ref = oracle.run_oracle(cfg["volts"], cfg["chan_freqs"], cfg["f_s"], cfg["dm_lists"], cfg["dump_len"], bl,
+                                quant=quant, scales=scales, chans=[c], dm_index=ds)
+        for (cc, d), v in ref.items():
+            got = select(vis, lay, cc, d)
+            assert got.shape == v.shape, (got.shape, v.shape)
+            worst = max(worst, norm_error(got, v, m_ant))
+    return worst

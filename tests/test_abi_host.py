@@ -1,0 +1,131 @@
+"""Host-side checks of the C ABI: symbols, argument validation, call order.
+
+None of these calls touches the GPU: plan creation validates and allocates
+nothing on the device, and every failure below is detected on the host first.
+"""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1109_3186_amd as ddx
+from paper_1109_3186_amd import binding
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "ddx.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ddx_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 9
+    lib = ct.CDLL(ddx.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(binding.SIGNATURES)
+
+
+def _desc(**kw):
+    fc = np.array(kw.pop("fc", [1.4e9, 1.401e9]), dtype=np.float64)
+    d = binding.Desc()
+    d.n_ant = kw.pop("n_ant", 4)
+    d.n_chan = kw.pop("n_chan", len(fc))
+    d.chan_freq_hz = fc.ctypes.data_as(ct.POINTER(ct.c_double))
+    d.samp_rate_hz = kw.pop("fs", 1e6)
+    d.sideband = kw.pop("sideband", 1)
+    d.in_dtype = kw.pop("in_dtype", 0)
+    d.corr_dtype = kw.pop("corr_dtype", 0)
+    d.dump_len = kw.pop("dump_len", 64)
+    d.k_dm = kw.pop("k_dm", 0.0)
+    d.max_block_samples = kw.pop("max_block", 1 << 16)
+    d.max_device_bytes = kw.pop("max_bytes", 0)
+    d.out_mode = kw.pop("out_mode", 0)
+    assert not kw
+    return d, fc
+
+
+def _create(**kw):
+    d, fc = _desc(**kw)
+    h = ct.c_void_p()
+    rc = ddx.lib().ddx_plan_create(ct.byref(d), ct.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("bad", [
+    {"n_ant": 0}, {"n_chan": 0}, {"fs": 0.0}, {"fs": float("nan")}, {"sideband": 0}, {"in_dtype": 5},
+    {"corr_dtype": 9}, {"dump_len": 0}, {"max_block": 0}, {"out_mode": 3}, {"k_dm": -1.0},
+    {"fc": [1.4e9, float("inf")]}, {"fc": [1.4e9, 1e5]},
+])
+def test_create_rejects_invalid_fields(bad):
+    rc, h = _create(**bad)
+    assert rc == ddx.EINVAL and not h.value
+
+
+def test_create_null_arguments():
+    d, _ = _desc()
+    assert ddx.lib().ddx_plan_create(None, None) == ddx.EINVAL
+    assert ddx.lib().ddx_plan_create(ct.byref(d), None) == ddx.EINVAL
+
+
+def test_call_order_and_argument_errors():
+    rc, h = _create()
+    assert rc == ddx.OK and h.value
+    L = ddx.lib()
+    lay = binding.Layout()
+    assert L.ddx_get_layout(h, ct.byref(lay)) == ddx.ESTATE
+    assert L.ddx_process_block(h, None, 0, 0, None) == ddx.ESTATE
+    first, nd = ct.c_int64(), ct.c_int64()
+    assert L.ddx_fetch_visibilities(h, None, 0, ct.byref(first), ct.byref(nd), None) == ddx.ESTATE
+    assert L.ddx_set_active_dms(h, -1, None) == ddx.ESTATE
+    dm = np.array([0.0, -1.0])
+    assert L.ddx_set_dm_trials(h, -1, dm.ctypes.data_as(ct.POINTER(ct.c_double)), 2) == ddx.EINVAL
+    assert b"DM[1]" in L.ddx_last_error(h)
+    dm = np.array([0.0, float("nan")])
+    assert L.ddx_set_dm_trials(h, -1, dm.ctypes.data_as(ct.POINTER(ct.c_double)), 2) == ddx.EINVAL
+    assert L.ddx_set_dm_trials(h, -1, None, 1) == ddx.EINVAL
+    assert L.ddx_set_dm_trials(h, 7, dm.ctypes.data_as(ct.POINTER(ct.c_double)), 1) == ddx.EINVAL
+    # a DM so large the smear needs more than the supported FFT length
+    dm = np.array([1e6])
+    assert L.ddx_set_dm_trials(h, -1, dm.ctypes.data_as(ct.POINTER(ct.c_double)), 1) == ddx.EUNSUPPORTED
+    # setting only one channel leaves the plan not ready (no device work yet)
+    dm = np.array([10.0])
+    assert L.ddx_set_dm_trials(h, 0, dm.ctypes.data_as(ct.POINTER(ct.c_double)), 1) == ddx.OK
+    assert L.ddx_get_layout(h, ct.byref(lay)) == ddx.ESTATE
+    assert L.ddx_plan_destroy(h) == ddx.OK
+
+
+def test_fft_too_short_for_smear():
+    fc = np.array([0.7e9])
+    d, _ = _desc(fc=fc, n_chan=1)
+    fl = np.array([1024], dtype=np.int32)
+    d.fft_len = fl.ctypes.data_as(ct.POINTER(ct.c_int32))
+    h = ct.c_void_p()
+    assert ddx.lib().ddx_plan_create(ct.byref(d), ct.byref(h)) == ddx.OK
+    dm = np.array([500.0])
+    assert ddx.lib().ddx_set_dm_trials(h, -1, dm.ctypes.data_as(ct.POINTER(ct.c_double)), 1) == ddx.EINVAL
+    ddx.lib().ddx_plan_destroy(h)
+
+
+def test_unsupported_and_bad_fft_lengths():
+    d, fc = _desc()
+    fl = np.array([3000, 0], dtype=np.int32)
+    d.fft_len = fl.ctypes.data_as(ct.POINTER(ct.c_int32))
+    h = ct.c_void_p()
+    assert ddx.lib().ddx_plan_create(ct.byref(d), ct.byref(h)) == ddx.EINVAL
+    rc, h = _create(n_ant=300)
+    assert rc == ddx.EUNSUPPORTED
+
+
+def test_strerror_and_null_plan():
+    L = ddx.lib()
+    for s in (ddx.OK, ddx.EINVAL, ddx.ENOMEM, ddx.EDEVICE, ddx.ESTATE, ddx.ESIZE, ddx.EFULL, ddx.EUNSUPPORTED):
+        assert L.ddx_strerror(s) and L.ddx_strerror(s) != b"unknown status"
+    assert L.ddx_plan_destroy(None) == ddx.OK
+    assert L.ddx_process_block(None, None, 0, 0, None) == ddx.EINVAL
+    assert L.ddx_set_dm_trials(None, 0, None, 0) == ddx.EINVAL

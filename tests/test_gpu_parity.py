@@ -1,0 +1,149 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerance (FP32 path): normalised error |dV_ij| / sqrt(V_ii V_jj) <= 1e-5, with
+the oracle's autocorrelations; bitwise equality where the computation is the
+same (stream splits, repeated runs, active-DM subsets, Hermitian halves).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import blockings, compare_with_oracle, norm_error, run_gpu, say, select
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def c0():
+    return synth.make_c0()
+
+
+def test_c0_full_parity_and_pulse(gpu, c0):
+    say("C0: 8 ant, 1 ch, 65536 cf32, 16 DMs, N 4096, L 64")
+    vis, lay = run_gpu(c0, in_dtype="cf32")
+    assert lay["fft_len"][0] == 4096 and lay["valid"][0] == 3776 and lay["lead"][0] == 160
+    assert vis.shape[0] == 65536 // 64
+    err = compare_with_oracle(c0, vis, lay)
+    say("C0 max normalised error %.3e" % err)
+    assert err <= TOL
+
+
+def test_pulse_recovery_noise_free(gpu):
+    """A noise-free dispersed pulse (DM 50) comes back compact at its own trial only."""
+    cfg = synth.make_c0()
+    rng = np.random.Generator(np.random.PCG64(3))
+    x = np.zeros((1, 8, 65536), dtype=np.complex128)
+    n0, w = 30016, 64  # one whole dump
+    wave = synth.pulse_wave(rng, w, 20.0, 1.0)
+    synth.inject_pulse(x[0], 1.4e9, 1e6, 50.0, n0, wave, f_ref=1.4e9, phases=rng.random(8) * 2 * np.pi)
+    cfg = dict(cfg, volts=x.astype(np.complex64))
+    vis, lay = run_gpu(cfg)
+    iu, ju = np.triu_indices(8)
+    auto = iu == ju
+    total = float(np.sum(np.abs(x) ** 2))
+    frac = np.array([select(vis, lay, 0, d)[n0 // 64, auto].real.sum() / total for d in range(16)])
+    say("energy fraction in the pulse dump per trial:", np.round(frac, 4))
+    assert frac[8] >= 0.999
+    assert np.all(np.delete(frac, 8) < frac[8] - 0.01)
+
+
+def test_plan_blocking_matches_oracle_rule(gpu):
+    cfg = synth.make_small(seed=21, m_ant=3, n_chan=3, s=4000, f_lo=1.2e9, f_s=1e6, n_dm=4, dm_max=400.0,
+                           dump_len=100, n_pulses=0)
+    cfg["dm_lists"][1] = np.array([0.0, 50.0, 1200.0])
+    vis, lay = run_gpu(cfg)
+    for c in range(3):
+        ref = oracle.blocking(cfg["chan_freqs"][c], 1e6, max(cfg["dm_lists"][c]), 100)
+        assert (lay["fft_len"][c], lay["valid"][c], lay["lead"][c]) == (ref["fft_len"], ref["valid"], ref["lead"])
+    delta, shift = oracle.channel_delays(cfg["chan_freqs"], cfg["dm_lists"][0], 1e6)
+    np.testing.assert_allclose(lay["delay_s"][:4], delta[0], rtol=1e-15)
+    assert np.array_equal(lay["shift"][lay["dm_offset"][2]:lay["dm_offset"][2] + 4], shift[2])
+
+
+@pytest.mark.parametrize("out_mode", ["packed", "full"])
+def test_ci8_multichannel_ragged(gpu, out_mode):
+    cfg = synth.make_small(seed=22, m_ant=5, n_chan=3, s=50037, f_lo=1.2e9, f_s=1e6, n_dm=5, dm_max=300.0,
+                           dump_len=100, ci8=True, n_pulses=1)
+    say("ci8 5 ant 3 ch 50037 samples (ragged), mode", out_mode)
+    vis, lay = run_gpu(cfg, in_dtype="ci8", out_mode=out_mode)
+    assert vis.shape[0] == 50037 // 100
+    if out_mode == "full":
+        m = 5
+        full = vis.reshape(vis.shape[0], -1, m, m)
+        assert np.array_equal(full, np.conj(np.swapaxes(full, -1, -2)))
+        assert np.all(np.diagonal(full, axis1=-2, axis2=-1).imag == 0)
+        iu, ju = np.triu_indices(m)
+        vis = full[..., iu, ju].reshape(vis.shape[0], -1)
+        lay = dict(lay, n_baselines=m * (m + 1) // 2)
+    err = compare_with_oracle(cfg, vis, lay)
+    say("max normalised error %.3e" % err)
+    assert err <= TOL
+
+
+def test_many_fft_sizes(gpu):
+    """Every supported transform length 256 .. 32768, several tiles and a ragged tail."""
+    for n, dm in [(256, 2.0), (512, 5.0), (1024, 10.0), (2048, 30.0), (8192, 100.0), (16384, 200.0), (32768, 500.0)]:
+        cfg = synth.make_small(seed=23 + n, m_ant=3, n_chan=1, s=3 * n + 101, f_lo=1.3e9, f_s=1e6, n_dm=3,
+                               dm_max=dm, dump_len=16, n_pulses=0)
+        say("N =", n)
+        vis, lay = run_gpu(cfg, fft_len=n)
+        assert lay["fft_len"][0] == n
+        err = compare_with_oracle(cfg, vis, lay)
+        say("N %d max normalised error %.3e" % (n, err))
+        assert err <= TOL
+
+
+def test_split_invariance_and_determinism(gpu):
+    cfg = synth.make_small(seed=24, m_ant=4, n_chan=2, s=30000, f_lo=1.4e9, f_s=1e6, n_dm=6, dm_max=200.0,
+                           dump_len=64, ci8=True, n_pulses=1)
+    say("split invariance")
+    one, lay = run_gpu(cfg, in_dtype="ci8")
+    two, _ = run_gpu(cfg, in_dtype="ci8")
+    assert np.array_equal(one, two)
+    split, _ = run_gpu(cfg, in_dtype="ci8", chunks=[7000, 1, 12345, 3000, 30000 - 22346], max_block=12345)
+    assert split.shape == one.shape
+    assert np.array_equal(split, one)
+
+
+def test_dm0_is_plain_correlator(gpu):
+    cfg = synth.make_small(seed=25, m_ant=6, n_chan=1, s=12000, f_lo=1.4e9, f_s=1e6, n_dm=1, dm_max=1.0,
+                           dump_len=50, n_pulses=0)
+    cfg["dm_lists"] = [np.array([0.0])]
+    vis, lay = run_gpu(cfg)
+    x = cfg["volts"][0].astype(np.complex128)
+    ref = oracle.pack_upper(np.einsum("imn,jmn->mij", x.reshape(6, -1, 50), np.conj(x.reshape(6, -1, 50))))
+    assert norm_error(select(vis, lay, 0, 0), ref, 6) <= 1e-6
+
+
+def test_active_subset_bitwise(gpu):
+    cfg = synth.make_small(seed=26, m_ant=4, n_chan=2, s=20000, f_lo=1.3e9, f_s=1e6, n_dm=8, dm_max=300.0,
+                           dump_len=100, n_pulses=1)
+    full, lay = run_gpu(cfg)
+    mask = [np.array([1, 0, 0, 1, 1, 0, 1, 0], np.uint8), np.array([0, 0, 0, 0, 0, 0, 0, 1], np.uint8)]
+    part, _ = run_gpu(cfg, mask=mask)
+    for c in range(2):
+        for d in range(8):
+            a, b = select(part, lay, c, d), select(full, lay, c, d)
+            if mask[c][d]:
+                assert np.array_equal(a, b)
+            else:
+                assert np.all(a == 0)
+
+
+def test_covariance_scale_and_phase(gpu):
+    cfg = synth.make_small(seed=27, m_ant=4, n_chan=1, s=9000, f_lo=1.4e9, f_s=1e6, n_dm=2, dm_max=100.0,
+                           dump_len=100, n_pulses=0)
+    v0, lay = run_gpu(cfg)
+    rng = np.random.Generator(np.random.PCG64(5))
+    psi = rng.random(4) * 2 * np.pi
+    a = 0.5 - 1.25j
+    cfg2 = dict(cfg, volts=(cfg["volts"] * (a * np.exp(1j * psi))[None, :, None]).astype(np.complex64))
+    v1, _ = run_gpu(cfg2)
+    iu, ju = np.triu_indices(4)
+    rot = abs(a) ** 2 * np.exp(1j * (psi[iu] - psi[ju]))
+    for d in range(2):
+        ref = select(v0, lay, 0, d).astype(np.complex128) * rot[None, :]
+        assert norm_error(select(v1, lay, 0, d), ref, 4) <= 1e-5
