@@ -77,8 +77,16 @@ typedef struct ddx_desc {
   int64_t max_block_samples;   /* largest n one ddx_process_block call accepts, >= 1 */
   size_t max_device_bytes;     /* cap on plan-owned device memory, 0 = none */
   int32_t out_mode;            /* DDX_OUT_* */
-  const float* chan_scale;     /* [C] correlator-input scales (F16/E4M3), or NULL = rule */
+  const float* chan_scale;     /* [C] correlator-input scales (F16/E4M3), or NULL = rule below */
 } ddx_desc;
+
+/* Scale rule for F16/E4M3 when chan_scale is NULL: s_c = 2^rint(log2(t / sigma_c)),
+ * sigma_c the per-component RMS of channel c's samples [0, N_c - lead_c) over all
+ * antennas (the in-stream part of its first block window), t = 32 for E4M3 (about
+ * 10 sigma, and the int8 extreme 127 at sigma 16, stay below 448, the largest
+ * finite E4M3 value) and t = 4 for F16.  It is
+ * computed on the device when the channel's first block runs (so it does not
+ * depend on how the stream is split) and exported by ddx_get_layout. */
 
 typedef struct ddx_plan ddx_plan;
 

@@ -19,6 +19,13 @@ constexpr double kDefaultKdm = 4.148808e15;
 constexpr int kMaxLogN = 15;
 constexpr int kMinLogN = 8;
 constexpr int kMaxCorrAnt = 64;  // stacked-row Gram kernel: 2 M <= 128
+// Scale rule targets: E4M3 puts sigma near 32, so even after the power-of-two
+// rounding (up to x sqrt 2) about 10 sigma, and the int8 extreme 127 at sigma 16,
+// stay below its largest finite value 448; binary16 puts sigma near 4 (far from
+// both its subnormal range and its maximum).  Away from those extremes a power-of-
+// two scale does not change the relative rounding error of either format.
+constexpr float kScaleTargetE4M3 = 32.f;
+constexpr float kScaleTargetF16 = 4.f;
 
 struct Chan {
   double fc = 0;
@@ -76,6 +83,7 @@ struct ddx_plan {
   std::vector<int> n_active;
   float* scale_dev = nullptr;    // [C]
   hipStream_t last_stream = nullptr;
+  bool scale_pending = false;    // scale_dev holds rule scales not yet copied to lay_scale
   std::string err;
   // profiling
   bool profiling = false;
@@ -224,22 +232,25 @@ hipError_t launch_dedisp(int logn, int corr_dtype, const ddx::DedispArgs& a, hip
 }
 
 template <int NT>
-hipError_t launch_corr_nt(const ddx::CorrArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((ddx::k_correlate_f32<NT>), dim3(a.n_dumps * a.nd), dim3(256), 0, s, a);
+hipError_t launch_corr_nt(int corr_dtype, const ddx::CorrArgs& a, hipStream_t s) {
+  const dim3 g(a.n_dumps * a.nd), b(256);
+  if (corr_dtype == DDX_CORR_F32) hipLaunchKernelGGL((ddx::k_correlate<NT, 0>), g, b, 0, s, a);
+  else if (corr_dtype == DDX_CORR_F16) hipLaunchKernelGGL((ddx::k_correlate<NT, 1>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((ddx::k_correlate<NT, 2>), g, b, 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_corr(const ddx::CorrArgs& a, hipStream_t s) {
+hipError_t launch_corr(int corr_dtype, const ddx::CorrArgs& a, hipStream_t s) {
   const int nt = (2 * a.n_ant + 15) / 16;
   switch (nt) {
-    case 1: return launch_corr_nt<1>(a, s);
-    case 2: return launch_corr_nt<2>(a, s);
-    case 3: return launch_corr_nt<3>(a, s);
-    case 4: return launch_corr_nt<4>(a, s);
-    case 5: return launch_corr_nt<5>(a, s);
-    case 6: return launch_corr_nt<6>(a, s);
-    case 7: return launch_corr_nt<7>(a, s);
-    case 8: return launch_corr_nt<8>(a, s);
+    case 1: return launch_corr_nt<1>(corr_dtype, a, s);
+    case 2: return launch_corr_nt<2>(corr_dtype, a, s);
+    case 3: return launch_corr_nt<3>(corr_dtype, a, s);
+    case 4: return launch_corr_nt<4>(corr_dtype, a, s);
+    case 5: return launch_corr_nt<5>(corr_dtype, a, s);
+    case 6: return launch_corr_nt<6>(corr_dtype, a, s);
+    case 7: return launch_corr_nt<7>(corr_dtype, a, s);
+    case 8: return launch_corr_nt<8>(corr_dtype, a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -420,7 +431,6 @@ int ddx_plan_create(const ddx_desc* d, ddx_plan** out) {
     if (d->chan_scale && (!(d->chan_scale[c] > 0) || !std::isfinite(d->chan_scale[c]))) return DDX_EINVAL;
   }
   if (d->n_ant > kMaxCorrAnt) return DDX_EUNSUPPORTED;
-  if (d->corr_dtype != DDX_CORR_F32) return DDX_EUNSUPPORTED;
   ddx_plan* p = new (std::nothrow) ddx_plan;
   if (!p) return DDX_ENOMEM;
   p->M = d->n_ant;
@@ -488,6 +498,12 @@ int ddx_get_layout(const ddx_plan* pc, ddx_layout* o) {
   if (!pc || !o) return DDX_EINVAL;
   ddx_plan* p = const_cast<ddx_plan*>(pc);
   if (!p->ready) return fail(p, DDX_ESTATE, "set DM trials for every channel first");
+  if (p->scale_pending) {
+    HIPCHECK(p, hipStreamSynchronize(p->last_stream));
+    HIPCHECK(p, hipMemcpy(p->lay_scale.data(), p->scale_dev, p->C * sizeof(float), hipMemcpyDeviceToHost));
+    for (int i = 0; i < p->C; ++i) p->ch[i].scale = p->lay_scale[i];
+    p->scale_pending = false;
+  }
   std::memset(o, 0, sizeof *o);
   o->n_ant = p->M;
   o->n_chan = p->C;
@@ -571,6 +587,19 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
     const int64_t b0 = c.blocks_done, nb = b_end[i] - b0;
     if (nb <= 0) continue;
     src.hist_start = c.hist_start;
+    if (b0 == 0 && p->corr_dtype != DDX_CORR_F32 && !p->have_scale) {
+      // first block of the channel: fix its correlator-input scale from the block's window
+      const float target = p->corr_dtype == DDX_CORR_E4M3 ? kScaleTargetE4M3 : kScaleTargetF16;
+      const int64_t nwin = std::min<int64_t>(c.fft_len - c.lead, total);
+      HIPCHECK(p, timed(p, s, DDX_K_OTHER, 0.0, (double)nwin * p->M * in_bytes(p->in_dtype), [&] {
+        if (p->in_dtype == DDX_IN_CI8)
+          hipLaunchKernelGGL(ddx::k_scale<0>, dim3(1), dim3(1024), 0, s, src, i, p->M, nwin, target, p->scale_dev);
+        else
+          hipLaunchKernelGGL(ddx::k_scale<1>, dim3(1), dim3(1024), 0, s, src, i, p->M, nwin, target, p->scale_dev);
+        return hipGetLastError();
+      }));
+      p->scale_pending = true;
+    }
     ddx::FwdArgs fa{};
     fa.src = src;
     fa.spec = p->spec;
@@ -629,7 +658,7 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
         const double nbl_h = p->M * (p->M + 1) / 2.0;
         HIPCHECK(p, timed(p, s, DDX_K_CORR, (double)n_dumps * nd * 8.0 * p->L * nbl_h,
                           (double)n_dumps * nd * ((double)p->L * p->M * y_bytes(p->corr_dtype) + 8.0 * p->nbl),
-                          [&] { return launch_corr(ca, s); }));
+                          [&] { return launch_corr(p->corr_dtype, ca, s); }));
       }
     }
     const int n_inactive = (int)c.dm.size() - na;

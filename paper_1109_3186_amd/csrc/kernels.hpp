@@ -160,11 +160,59 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_dedisperse(DedispArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+constexpr int kCorrKC = 64;  // samples per LDS chunk
+
+template <int NT>  // 16 NT >= 2 M rows
+struct CorrGeo {
+  static constexpr int ROWS = 16 * NT;
+  static constexpr int NTILES = NT * (NT + 1) / 2;
+  static constexpr int TPW = (NTILES + 3) / 4;
+  static constexpr int GP = ROWS + 1;
+};
+
+// Per input format: sample type, MFMA shape and LDS layout of one chunk.
+//   T = 0: FP32 y, v_mfma_f32_16x16x4_f32; LDS k-major at[k][row] (one value per lane)
+//   T = 1: FP16 y, v_mfma_f32_16x16x32_f16; LDS row-major at[row][k] (8 consecutive k per lane)
+//   T = 2: E4M3 y, v_mfma_f32_16x16x32_fp8_fp8; LDS row-major bytes (8 consecutive k per lane)
+template <int T> struct CorrIn;
+template <> struct CorrIn<0> {
+  typedef float2 Y;      // one sample
+  typedef float4 Pair;   // two samples
+  typedef float E;       // one stored component
+  static constexpr int KSTEP = 4;
+};
+template <> struct CorrIn<1> {
+  typedef __half2 Y;
+  typedef uint2 Pair;
+  typedef _Float16 E;
+  static constexpr int KSTEP = 32;
+};
+template <> struct CorrIn<2> {
+  typedef uint16_t Y;
+  typedef uint32_t Pair;
+  typedef uint8_t E;
+  static constexpr int KSTEP = 32;
+};
+
+template <int T, int NT> struct CorrLds {
+  static constexpr int ROWS = 16 * NT;
+  // FP32: k-major, row pitch == 17 mod 32 words; FP16/E4M3: row-major, k pitch padded by 16 bytes
+  static constexpr int RP = ROWS + ((17 - (ROWS % 32)) + 32) % 32;
+  static constexpr int KP = kCorrKC + 16 / (int)sizeof(typename CorrIn<T>::E);
+  static constexpr int ELEMS = T == 0 ? kCorrKC * RP : ROWS * KP;
+  __device__ static int at(int row, int k) { return T == 0 ? k * RP + row : row * KP + k; }
+};
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+
 // Correlator: per (DM, dump) the Gram matrix of the stacked real rows
 // [Re y_0 .. Re y_{M-1}, Im y_0 .. Im y_{M-1}] over the L samples of the dump,
-// G = A A^T on FP32 MFMA (16x16x4) over the upper 16x16 tiles, then
-//   Re V_ij = G[i][j] + G[M+i][M+j],  Im V_ij = G[j][M+i] - G[i][M+j].
-// grid: n_dumps * nd workgroups of 256 threads (4 waves), logical id = m * nd + d.
+// G = A A^T on MFMA over the upper 16x16 tiles, FP32 accumulation, then
+//   Re V_ij = (G[i][j] + G[M+i][M+j]) / s^2,  Im V_ij = (G[j][M+i] - G[i][M+j]) / s^2
+// (s = correlator-input scale, 1 for FP32).  Samples are staged through LDS in
+// chunks of kCorrKC; the next chunk's global loads are issued before the current
+// chunk's MFMAs.  grid: n_dumps * nd workgroups of 256 threads (4 waves),
+// logical id = m * nd + d.
 struct CorrArgs {
   const void* y;
   int64_t y_stride;      // samples per (d, p) row
@@ -177,28 +225,39 @@ struct CorrArgs {
   int32_t n_dumps, nd, n_ant, dump_len, nbl, out_mode;
 };
 
-constexpr int kCorrKC = 32;  // samples per LDS chunk
+template <int T>
+__device__ __forceinline__ void store_pair(typename CorrIn<T>::E* at, int ia_re0, int ia_re1, int ia_im0, int ia_im1,
+                                           typename CorrIn<T>::Pair v) {
+  if constexpr (T == 0) {
+    at[ia_re0] = v.x; at[ia_im0] = v.y; at[ia_re1] = v.z; at[ia_im1] = v.w;
+  } else if constexpr (T == 1) {
+    const __half2 s0 = *reinterpret_cast<const __half2*>(&v.x), s1 = *reinterpret_cast<const __half2*>(&v.y);
+    at[ia_re0] = (_Float16)__low2float(s0);  // exact: the values are binary16 already
+    at[ia_im0] = (_Float16)__high2float(s0);
+    at[ia_re1] = (_Float16)__low2float(s1);
+    at[ia_im1] = (_Float16)__high2float(s1);
+  } else {
+    at[ia_re0] = (uint8_t)(v & 0xff); at[ia_im0] = (uint8_t)((v >> 8) & 0xff);
+    at[ia_re1] = (uint8_t)((v >> 16) & 0xff); at[ia_im1] = (uint8_t)(v >> 24);
+  }
+}
 
-template <int NT>  // 16 NT >= 2 M rows
-struct CorrGeo {
-  static constexpr int ROWS = 16 * NT;
-  static constexpr int RP = ROWS + ((17 - (ROWS % 32)) + 32) % 32;  // >= ROWS, == 17 mod 32
-  static constexpr int NTILES = NT * (NT + 1) / 2;
-  static constexpr int TPW = (NTILES + 3) / 4;
-  static constexpr int GP = ROWS + 1;
-};
-
-template <int NT>
-__global__ __launch_bounds__(256) void k_correlate_f32(CorrArgs a) {
+template <int NT, int T>
+__global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
   using C = CorrGeo<NT>;
-  __shared__ float at[kCorrKC * C::RP];
+  using In = CorrIn<T>;
+  using Ld = CorrLds<T, NT>;
+  typedef typename In::E E;
+  typedef typename In::Pair Pair;
+  constexpr int PPT = (8 * NT * (kCorrKC / 2) + 255) / 256;  // max sample pairs per thread per chunk (M <= 8 NT)
+  __shared__ E at[Ld::ELEMS];
   __shared__ float gram[C::ROWS * C::GP];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lin = blockIdx.x;
   const int d = lin % a.nd, m = lin / a.nd;
   const int M = a.n_ant, L = a.dump_len;
+  const int pairs = M * (kCorrKC / 2);
 
-  // tiles of this wave
   int ti[C::TPW], tj[C::TPW];
 #pragma unroll
   for (int i = 0; i < C::TPW; ++i) {
@@ -211,32 +270,74 @@ __global__ __launch_bounds__(256) void k_correlate_f32(CorrArgs a) {
 #pragma unroll
   for (int i = 0; i < C::TPW; ++i) acc[i] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  // zero the padding rows once
+  // padding rows 2M .. ROWS-1 stay zero
   for (int e = tid; e < kCorrKC * (C::ROWS - 2 * M); e += 256) {
-    const int n = e / (C::ROWS - 2 * M), r = 2 * M + e % (C::ROWS - 2 * M);
-    at[n * C::RP + r] = 0.f;
+    const int k = e / (C::ROWS - 2 * M), r = 2 * M + e % (C::ROWS - 2 * M);
+    at[Ld::at(r, k)] = (E)0;
   }
-  const float2* y = reinterpret_cast<const float2*>(a.y) + (size_t)d * M * a.y_stride + (size_t)m * L;
-  for (int k0 = 0; k0 < L; k0 += kCorrKC) {
-    for (int e = tid; e < M * kCorrKC; e += 256) {
-      const int p = e / kCorrKC, n = e % kCorrKC;
-      const float2 val = (k0 + n < L) ? y[(size_t)p * a.y_stride + k0 + n] : make_float2(0.f, 0.f);
-      at[n * C::RP + p] = val.x;
-      at[n * C::RP + M + p] = val.y;
-    }
-    __syncthreads();
+  const typename In::Y* y = reinterpret_cast<const typename In::Y*>(a.y) + (size_t)d * M * a.y_stride + (size_t)m * L;
+  // even dump length: pairs never straddle the end of the dump; odd: last pair loaded singly
+  auto load = [&](int k0, Pair* buf) {
 #pragma unroll
-    for (int kk = 0; kk < kCorrKC; kk += 4) {
-      const int kr = (kk + (lane >> 4)) * C::RP + (lane & 15);
+    for (int i = 0; i < PPT; ++i) {
+      const int e = tid + 256 * i;
+      Pair v{};
+      if (e < pairs) {
+        const int p = e / (kCorrKC / 2), k = k0 + 2 * (e % (kCorrKC / 2));
+        const typename In::Y* row = y + (size_t)p * a.y_stride + k;
+        if (k + 1 < L && ((((size_t)p * a.y_stride + (size_t)m * L + k) & 1) == 0)) {
+          v = *reinterpret_cast<const Pair*>(row);
+        } else {
+          typename In::Y s0{}, s1{};
+          if (k < L) s0 = row[0];
+          if (k + 1 < L) s1 = row[1];
+          typename In::Y tmp[2] = {s0, s1};
+          v = *reinterpret_cast<const Pair*>(tmp);
+        }
+      }
+      buf[i] = v;
+    }
+  };
+  auto stage = [&](const Pair* buf) {
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int e = tid + 256 * i;
+      if (e < pairs) {
+        const int p = e / (kCorrKC / 2), k = 2 * (e % (kCorrKC / 2));
+        store_pair<T>(at, Ld::at(p, k), Ld::at(p, k + 1), Ld::at(M + p, k), Ld::at(M + p, k + 1), buf[i]);
+      }
+    }
+  };
+  Pair buf[PPT];
+  load(0, buf);
+  for (int k0 = 0; k0 < L; k0 += kCorrKC) {
+    __syncthreads();  // previous chunk's MFMAs are done with at[]
+    stage(buf);
+    __syncthreads();
+    if (k0 + kCorrKC < L) load(k0 + kCorrKC, buf);  // in flight during the MFMAs below
+#pragma unroll
+    for (int kk = 0; kk < kCorrKC; kk += In::KSTEP) {
 #pragma unroll
       for (int i = 0; i < C::TPW; ++i) {
         if (wave + 4 * i < C::NTILES) {
-          const float av = at[kr + ti[i] * 16], bv = at[kr + tj[i] * 16];
-          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[i], 0, 0, 0);
+          const int ra = ti[i] * 16 + (lane & 15), rb = tj[i] * 16 + (lane & 15);
+          if constexpr (T == 0) {
+            const int kr = kk + (lane >> 4);
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(at[Ld::at(ra, kr)], at[Ld::at(rb, kr)], acc[i], 0, 0, 0);
+          } else if constexpr (T == 1) {
+            const int kr = kk + 8 * (lane >> 4);
+            const half8 av = *reinterpret_cast<const half8*>(&at[Ld::at(ra, kr)]);
+            const half8 bv = *reinterpret_cast<const half8*>(&at[Ld::at(rb, kr)]);
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, acc[i], 0, 0, 0);
+          } else {
+            const int kr = kk + 8 * (lane >> 4);
+            const long av = *reinterpret_cast<const long*>(&at[Ld::at(ra, kr)]);
+            const long bv = *reinterpret_cast<const long*>(&at[Ld::at(rb, kr)]);
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, acc[i], 0, 0, 0);
+          }
         }
       }
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < C::TPW; ++i) {
@@ -247,6 +348,11 @@ __global__ __launch_bounds__(256) void k_correlate_f32(CorrArgs a) {
     }
   }
   __syncthreads();
+  float inv = 1.f;
+  if constexpr (T != 0) {
+    const float s = *a.scale;
+    inv = 1.f / (s * s);  // s is a power of two: exact
+  }
   const int64_t dump = a.dump0 + m;
   float2* out = a.ring + (dump % a.ring_dumps) * a.rec_elems + (int64_t)a.dm_pos[d] * a.nbl;
   if (a.out_mode == 0) {
@@ -257,7 +363,7 @@ __global__ __launch_bounds__(256) void k_correlate_f32(CorrArgs a) {
       const int j = i + rem;
       const float re = gram[i * C::GP + j] + gram[(M + i) * C::GP + M + j];
       const float im = gram[j * C::GP + M + i] - gram[i * C::GP + M + j];
-      out[b] = make_float2(re, im);
+      out[b] = make_float2(re * inv, im * inv);
     }
   } else {
     for (int b = tid; b < M * M; b += 256) {
@@ -265,8 +371,38 @@ __global__ __launch_bounds__(256) void k_correlate_f32(CorrArgs a) {
       const int lo = i < j ? i : j, hi = i < j ? j : i;
       const float re = gram[lo * C::GP + hi] + gram[(M + lo) * C::GP + M + hi];
       const float im = gram[hi * C::GP + M + lo] - gram[lo * C::GP + M + hi];
-      out[b] = make_float2(re, i <= j ? im : -im);
+      out[b] = make_float2(re * inv, (i <= j ? im : -im) * inv);
     }
+  }
+}
+
+// Correlator-input scale of one channel from its first block window:
+// sigma^2 = sum |x|^2 / (2 M n) over samples [0, n) of every antenna (per-component
+// variance), s = 2^rint(log2(target / sigma)), 1 if the window is all zero.  One
+// workgroup of 1024 threads; fixed summation order, so the result does not depend
+// on how the stream was split.
+template <int IN>
+__global__ __launch_bounds__(1024) void k_scale(Source s, int32_t chan, int32_t n_ant, int64_t n, float target,
+                                                float* scale) {
+  __shared__ double part[1024];
+  double acc = 0.0;
+  for (int p = 0; p < n_ant; ++p) {
+    Source r = s;
+    r.row = chan * n_ant + p;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) {
+      const float2 v = load_sample<IN>(r, i);
+      acc += (double)v.x * v.x + (double)v.y * v.y;
+    }
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double var = part[0] / (2.0 * n_ant * (double)n);
+    scale[chan] = var > 0 ? (float)exp2(rint(log2((double)target / sqrt(var)))) : 1.f;
   }
 }
 

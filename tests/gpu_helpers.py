@@ -52,8 +52,7 @@ def run_gpu(cfg, in_dtype="cf32", corr="f32", out_mode="packed", chunks=None, ff
             pos += n
         lay_end = p.layout()
     vis = np.concatenate(outs, axis=0) if outs else np.zeros((0, lay["record_elems"]), np.complex64)
-    lay["dumps_ready"] = lay_end["dumps_ready"]
-    return vis, lay
+    return vis, lay_end
 
 
 def blockings(lay):
