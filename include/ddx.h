@@ -52,7 +52,8 @@ extern "C" {
 #define DDX_IN_CF32 1 /* float re, float im: 8 bytes per sample */
 
 /* Correlator input formats (the dedispersed voltages). */
-#define DDX_CORR_F32 0  /* FP32 voltages, FP32 MFMA, FP32 accumulate */
+#define DDX_CORR_F32 0  /* FP32 voltages; products from a two-term binary16 split (hi*hi + hi*lo
+                           + lo*hi) on FP16 MFMA, FP32 accumulate: FP32-level accuracy */
 #define DDX_CORR_F16 1  /* voltages x scale rounded to IEEE binary16 (RNE, saturating) */
 #define DDX_CORR_E4M3 2 /* voltages x scale rounded to OCP FP8 E4M3 (RNE, saturating to +-448) */
 
@@ -77,14 +78,15 @@ typedef struct ddx_desc {
   int64_t max_block_samples;   /* largest n one ddx_process_block call accepts, >= 1 */
   size_t max_device_bytes;     /* cap on plan-owned device memory, 0 = none */
   int32_t out_mode;            /* DDX_OUT_* */
-  const float* chan_scale;     /* [C] correlator-input scales (F16/E4M3), or NULL = rule below */
+  const float* chan_scale;     /* [C] power-of-two correlator-input scales, or NULL = rule below */
 } ddx_desc;
 
-/* Scale rule for F16/E4M3 when chan_scale is NULL: s_c = 2^rint(log2(t / sigma_c)),
+/* Scale rule when chan_scale is NULL (all correlator formats; the scale keeps
+ * the binary16 halves of F32 and the F16/E4M3 values in range): s_c = 2^rint(log2(t / sigma_c)),
  * sigma_c the per-component RMS of channel c's samples [0, N_c - lead_c) over all
  * antennas (the in-stream part of its first block window), t = 32 for E4M3 (about
  * 10 sigma, and the int8 extreme 127 at sigma 16, stay below 448, the largest
- * finite E4M3 value) and t = 4 for F16.  It is
+ * finite E4M3 value) and t = 4 for F16 and F32.  It is
  * computed on the device when the channel's first block runs (so it does not
  * depend on how the stream is split) and exported by ddx_get_layout. */
 
@@ -102,7 +104,7 @@ typedef struct ddx_layout {
   const double* dm;            /* [dm_offset[C]] trial DMs, channel-major */
   const double* delay_s;       /* [dm_offset[C]] K DM / f_c^2: channel-centre delay behind infinite frequency */
   const int64_t* shift;        /* [dm_offset[C]] rint(K DM (f_c^-2 - f_top^-2) f_s): samples behind the highest channel */
-  const float* scale;          /* [C] correlator-input scale s_c (1 for F32) */
+  const float* scale;          /* [C] correlator-input scale s_c */
   int64_t record_elems;        /* complex64 values per dump record = dm_offset[C] * n_baselines */
   int64_t samples_in;          /* samples accepted so far per (channel, antenna) */
   int64_t dumps_ready;         /* dumps complete in every channel */
@@ -157,8 +159,8 @@ int ddx_get_layout(const ddx_plan* plan, ddx_layout* out);
  *     f_k = sideband * (k < N/2 ? k : k - N) f_s / N, u and r in FP64;
  *   y[b V + j] = (1/N) IDFT(X H)[lead + j], j < V;
  * and for each complete dump m (samples [m L, (m+1) L)):
- *   V_ij = sum_n y_i[n] conj(y_j[n])   (raw sum, input units squared; for
- *   F16/E4M3 the voltages are s_c y rounded and the sums divided by s_c^2).
+ *   V_ij = sum_n y_i[n] conj(y_j[n])   (raw sum, input units squared; the
+ *   correlator works on s_c y -- rounded for F16/E4M3 -- and divides by s_c^2).
  * A trailing partial dump is dropped.  Errors: EINVAL (n < 0, n >
  * max_block_samples, NULL volts with n > 0), ESTATE (no DM trials, stream
  * flushed), EFULL (the dump ring would overwrite unfetched dumps: fetch first),

@@ -587,9 +587,9 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
     const int64_t b0 = c.blocks_done, nb = b_end[i] - b0;
     if (nb <= 0) continue;
     src.hist_start = c.hist_start;
-    if (b0 == 0 && p->corr_dtype != DDX_CORR_F32 && !p->have_scale) {
+    if (b0 == 0 && !p->have_scale) {
       // first block of the channel: fix its correlator-input scale from the block's window
-      const float target = p->corr_dtype == DDX_CORR_E4M3 ? kScaleTargetE4M3 : kScaleTargetF16;
+      const float target = p->corr_dtype == DDX_CORR_E4M3 ? kScaleTargetE4M3 : kScaleTargetF16;  // F32 too
       const int64_t nwin = std::min<int64_t>(c.fft_len - c.lead, total);
       HIPCHECK(p, timed(p, s, DDX_K_OTHER, 0.0, (double)nwin * p->M * in_bytes(p->in_dtype), [&] {
         if (p->in_dtype == DDX_IN_CI8)

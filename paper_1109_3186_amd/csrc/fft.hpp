@@ -187,6 +187,39 @@ __device__ __forceinline__ void pin_regs(float2* v) {
   for (int i = 0; i < R; ++i) asm volatile("; pin %0 %1" : "+v"(v[i].x), "+v"(v[i].y));
 }
 
+// Apply the twiddles exp(S 2 pi i r k / 2^LOGD), r = 1..R-1, to one butterfly group.
+// Powers w^1..w^7 of w = exp(S 2 pi i k / 2^LOGD) come from products of the exact
+// w^1 (depth <= 3); every eighth power w^{8a} is exact again and w^{8a+b} =
+// w^{8a} w^b, so no twiddle is more than four roundings from exact while only
+// R/8 of them need the transcendental unit.
+template <int LOGD, int R, int S>
+__device__ __forceinline__ void apply_twiddles(float2* v, int k) {
+  const float2 w1 = twiddle<LOGD, S>(k);
+  float2 wb[8];
+  wb[1] = w1;
+  if constexpr (R > 2) {
+    wb[2] = cmul(w1, w1);
+    wb[3] = cmul(wb[2], w1);
+  }
+  if constexpr (R > 4) {
+    wb[4] = cmul(wb[2], wb[2]);
+    wb[5] = cmul(wb[4], w1);
+    wb[6] = cmul(wb[3], wb[3]);
+    wb[7] = cmul(wb[6], w1);
+  }
+  constexpr int B = R < 8 ? R : 8;
+#pragma unroll
+  for (int b = 1; b < B; ++b) v[b] = cmul(v[b], wb[b]);
+#pragma unroll
+  for (int a = 1; a < R / 8; ++a) {
+    // 8 a k < 2^LOGD (k < 2^LOGD / R): exact anchor
+    const float2 wa = twiddle<LOGD, S>(8 * a * k);
+    v[8 * a] = cmul(v[8 * a], wa);
+#pragma unroll
+    for (int b = 1; b < 8; ++b) v[8 * a + b] = cmul(v[8 * a + b], cmul(wa, wb[b]));
+  }
+}
+
 template <int LOGN, int R, int NS, int S>
 __device__ __forceinline__ void pass(float2* v, int t) {
   using G = Geo<LOGN>;
@@ -194,11 +227,7 @@ __device__ __forceinline__ void pass(float2* v, int t) {
   int z = 0;
 #pragma unroll
   for (int u = 0; u < G::P / R; ++u) {
-    if (NS > 1) {
-      const int k = (t + z + u * G::T) & (NS - 1);
-#pragma unroll
-      for (int r = 1; r < R; ++r) v[u * R + r] = cmul(v[u * R + r], twiddle<LOGD, S>(r * k));
-    }
+    if (NS > 1) apply_twiddles<LOGD, R, S>(v + u * R, (t + z + u * G::T) & (NS - 1));
     dft_reg<R, S>(v + u * R);
     // the next group's twiddles wait for this group's butterflies (register pressure)
     if (u + 1 < G::P / R) {

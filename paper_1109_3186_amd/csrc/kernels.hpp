@@ -170,16 +170,20 @@ struct CorrGeo {
   static constexpr int GP = ROWS + 1;
 };
 
-// Per input format: sample type, MFMA shape and LDS layout of one chunk.
-//   T = 0: FP32 y, v_mfma_f32_16x16x4_f32; LDS k-major at[k][row] (one value per lane)
-//   T = 1: FP16 y, v_mfma_f32_16x16x32_f16; LDS row-major at[row][k] (8 consecutive k per lane)
-//   T = 2: E4M3 y, v_mfma_f32_16x16x32_fp8_fp8; LDS row-major bytes (8 consecutive k per lane)
+// Per input format: sample type, MFMA shape and LDS layout of one chunk.  All
+// three keep the chunk row-major in LDS, at[row][k], 8 consecutive k per lane.
+//   T = 0: FP32 y (times s), split on staging into binary16 hi = rn(y) and
+//          lo = rn(y - hi) in two LDS planes; each product is accumulated as
+//          hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_f16 (the dropped lo*lo
+//          term is below 2^-22 of the product), FP32 accumulation
+//   T = 1: FP16 y, v_mfma_f32_16x16x32_f16
+//   T = 2: E4M3 y, v_mfma_f32_16x16x32_fp8_fp8
 template <int T> struct CorrIn;
 template <> struct CorrIn<0> {
   typedef float2 Y;      // one sample
   typedef float4 Pair;   // two samples
-  typedef float E;       // one stored component
-  static constexpr int KSTEP = 4;
+  typedef _Float16 E;    // one stored component (per plane)
+  static constexpr int KSTEP = 32;
 };
 template <> struct CorrIn<1> {
   typedef __half2 Y;
@@ -196,11 +200,11 @@ template <> struct CorrIn<2> {
 
 template <int T, int NT> struct CorrLds {
   static constexpr int ROWS = 16 * NT;
-  // FP32: k-major, row pitch == 17 mod 32 words; FP16/E4M3: row-major, k pitch padded by 16 bytes
-  static constexpr int RP = ROWS + ((17 - (ROWS % 32)) + 32) % 32;
+  // row-major, k pitch padded by 16 bytes; FP32 keeps a second (lo) plane after the first
   static constexpr int KP = kCorrKC + 16 / (int)sizeof(typename CorrIn<T>::E);
-  static constexpr int ELEMS = T == 0 ? kCorrKC * RP : ROWS * KP;
-  __device__ static int at(int row, int k) { return T == 0 ? k * RP + row : row * KP + k; }
+  static constexpr int PLANE = ROWS * KP;
+  static constexpr int ELEMS = (T == 0 ? 2 : 1) * PLANE;
+  __device__ static int at(int row, int k) { return row * KP + k; }
 };
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
@@ -221,15 +225,24 @@ struct CorrArgs {
   int64_t ring_dumps;    // ring capacity in dumps
   int64_t dump0;         // absolute dump index of y sample 0
   const int32_t* dm_pos; // [nd] record position (dm_offset[c] + d) of each DM of the group
-  const float* scale;    // device scalar s_c (quantised inputs), ignored for FP32
+  const float* scale;    // device scalar s_c: correlator-input scale (all formats)
   int32_t n_dumps, nd, n_ant, dump_len, nbl, out_mode;
 };
 
-template <int T>
+// binary16 hi = rn(x) and lo = rn(x - hi); x - hi is exact in FP32
+__device__ __forceinline__ void split16(float x, _Float16& hi, _Float16& lo) {
+  hi = (_Float16)x;
+  lo = (_Float16)(x - (float)hi);
+}
+
+template <int T, int PLANE>
 __device__ __forceinline__ void store_pair(typename CorrIn<T>::E* at, int ia_re0, int ia_re1, int ia_im0, int ia_im1,
-                                           typename CorrIn<T>::Pair v) {
+                                           typename CorrIn<T>::Pair v, float s) {
   if constexpr (T == 0) {
-    at[ia_re0] = v.x; at[ia_im0] = v.y; at[ia_re1] = v.z; at[ia_im1] = v.w;
+    split16(v.x * s, at[ia_re0], at[PLANE + ia_re0]);
+    split16(v.y * s, at[ia_im0], at[PLANE + ia_im0]);
+    split16(v.z * s, at[ia_re1], at[PLANE + ia_re1]);
+    split16(v.w * s, at[ia_im1], at[PLANE + ia_im1]);
   } else if constexpr (T == 1) {
     const __half2 s0 = *reinterpret_cast<const __half2*>(&v.x), s1 = *reinterpret_cast<const __half2*>(&v.y);
     at[ia_re0] = (_Float16)__low2float(s0);  // exact: the values are binary16 already
@@ -270,11 +283,13 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
 #pragma unroll
   for (int i = 0; i < C::TPW; ++i) acc[i] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  // padding rows 2M .. ROWS-1 stay zero
+  // padding rows 2M .. ROWS-1 stay zero (both planes for FP32)
   for (int e = tid; e < kCorrKC * (C::ROWS - 2 * M); e += 256) {
     const int k = e / (C::ROWS - 2 * M), r = 2 * M + e % (C::ROWS - 2 * M);
     at[Ld::at(r, k)] = (E)0;
+    if constexpr (T == 0) at[Ld::PLANE + Ld::at(r, k)] = (E)0;
   }
+  const float s_in = *a.scale;
   const typename In::Y* y = reinterpret_cast<const typename In::Y*>(a.y) + (size_t)d * M * a.y_stride + (size_t)m * L;
   // even dump length: pairs never straddle the end of the dump; odd: last pair loaded singly
   auto load = [&](int k0, Pair* buf) {
@@ -285,7 +300,7 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
       if (e < pairs) {
         const int p = e / (kCorrKC / 2), k = k0 + 2 * (e % (kCorrKC / 2));
         const typename In::Y* row = y + (size_t)p * a.y_stride + k;
-        if (k + 1 < L && ((((size_t)p * a.y_stride + (size_t)m * L + k) & 1) == 0)) {
+        if (k + 1 < L && ((((size_t)(d * M + p) * a.y_stride + (size_t)m * L + k) & 1) == 0)) {
           v = *reinterpret_cast<const Pair*>(row);
         } else {
           typename In::Y s0{}, s1{};
@@ -304,7 +319,8 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
       const int e = tid + 256 * i;
       if (e < pairs) {
         const int p = e / (kCorrKC / 2), k = 2 * (e % (kCorrKC / 2));
-        store_pair<T>(at, Ld::at(p, k), Ld::at(p, k + 1), Ld::at(M + p, k), Ld::at(M + p, k + 1), buf[i]);
+        store_pair<T, Ld::PLANE>(at, Ld::at(p, k), Ld::at(p, k + 1), Ld::at(M + p, k), Ld::at(M + p, k + 1), buf[i],
+                                 s_in);
       }
     }
   };
@@ -322,8 +338,14 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
         if (wave + 4 * i < C::NTILES) {
           const int ra = ti[i] * 16 + (lane & 15), rb = tj[i] * 16 + (lane & 15);
           if constexpr (T == 0) {
-            const int kr = kk + (lane >> 4);
-            acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(at[Ld::at(ra, kr)], at[Ld::at(rb, kr)], acc[i], 0, 0, 0);
+            const int kr = kk + 8 * (lane >> 4);
+            const half8 ah = *reinterpret_cast<const half8*>(&at[Ld::at(ra, kr)]);
+            const half8 bh = *reinterpret_cast<const half8*>(&at[Ld::at(rb, kr)]);
+            const half8 al = *reinterpret_cast<const half8*>(&at[Ld::PLANE + Ld::at(ra, kr)]);
+            const half8 bl = *reinterpret_cast<const half8*>(&at[Ld::PLANE + Ld::at(rb, kr)]);
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, acc[i], 0, 0, 0);
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, acc[i], 0, 0, 0);
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, acc[i], 0, 0, 0);
           } else if constexpr (T == 1) {
             const int kr = kk + 8 * (lane >> 4);
             const half8 av = *reinterpret_cast<const half8*>(&at[Ld::at(ra, kr)]);
@@ -348,11 +370,7 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
     }
   }
   __syncthreads();
-  float inv = 1.f;
-  if constexpr (T != 0) {
-    const float s = *a.scale;
-    inv = 1.f / (s * s);  // s is a power of two: exact
-  }
+  const float inv = 1.f / (s_in * s_in);  // s is a power of two: exact
   const int64_t dump = a.dump0 + m;
   float2* out = a.ring + (dump % a.ring_dumps) * a.rec_elems + (int64_t)a.dm_pos[d] * a.nbl;
   if (a.out_mode == 0) {

@@ -115,7 +115,7 @@ def test_dm0_is_plain_correlator(gpu):
     vis, lay = run_gpu(cfg)
     x = cfg["volts"][0].astype(np.complex128)
     ref = oracle.pack_upper(np.einsum("imn,jmn->mij", x.reshape(6, -1, 50), np.conj(x.reshape(6, -1, 50))))
-    assert norm_error(select(vis, lay, 0, 0), ref, 6) <= 1e-6
+    assert norm_error(select(vis, lay, 0, 0), ref, 6) <= TOL
 
 
 def test_active_subset_bitwise(gpu):
