@@ -35,7 +35,7 @@ def log(*a):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("fft.hpp", "kernels.hpp", "ddx.hip"):
+    for f in ("fft.hpp", "kernels.hpp", "ddx.hip", "tiles.hpp", "cnn_kernels.hpp", "cnn.hip"):
         with open(os.path.join(ROOT, "paper_1109_3186_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -90,6 +90,50 @@ def cpu_baseline(chunks, fc, dms, lay, p, n_dm):
                       "(numpy FFT and einsum run single-threaded)" % (len(ds), ds, p["m_ant"], p["samples"], el)}
 
 
+def learned_form(plan, chunks, pulses, p, out, steps, plain_ms):
+    """Learned proposal on the same stream: power tile + network + coherent
+    processing of the top 10% of DM trials (full sweep if the proposal falls back).
+    Returns speedup over the plain sweep and the recall of the injected pulses."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_1109_3186_amd.proposal import Proposal, load_weights
+    wpath = os.path.join(ROOT, "paper_1109_3186_amd", "proposal_weights.npz")
+    full = torch.cat(chunks, dim=-1).contiguous()
+    prop = Proposal(plan, load_weights(wpath), budget=0.1)
+
+    def step():
+        plan.reset_stream()
+        mask, scores, fb = prop.select(full)
+        plan.set_active_dms(mask)
+        for i, ch in enumerate(chunks):
+            plan.process_block(ch, flush=(i == len(chunks) - 1))
+            plan.fetch(out=out)
+        return mask, fb
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        mask, fb = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    plan.set_active_dms(None)
+    dstep = p["dm_max"] / p["n_dm"]
+    hits = [int(mask[math.floor(q["dm"] / dstep)] or mask[min(math.ceil(q["dm"] / dstep), p["n_dm"] - 1)])
+            for q in pulses]
+    prop.close()
+    del full
+    log("learned: %.1f ms/step (plain %.1f), %d active DMs, fallback %s, recall %d/%d" % (
+        ms, plain_ms, int(mask.sum()), fb, sum(hits), len(hits)))
+    return {"speedup": plain_ms / ms, "ms_per_step": ms, "active_dms": int(mask.sum()), "n_dm": p["n_dm"],
+            "fallback": bool(fb), "recall": sum(hits) / len(hits), "pulses": len(hits),
+            "note": "tile + network + active-DM sweep on the same stream; recall = injected pulses whose DM trial "
+                    "(either neighbour) is active"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +143,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=1 << 18, help="samples per process_block call")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-dms", type=int, default=2)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal measurement")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (requested %d)" % args.gpus,
@@ -170,6 +215,9 @@ def main():
                                 "tflops": round(v["flops"] / max(v["time_ms"], 1e-9) / 1e9, 2),
                                 "staged_gbs": round(v["bytes"] / max(v["time_ms"], 1e-9) / 1e6, 1)}
                             for k, v in prof.items() if v["launches"]}}
+    learned = None
+    if not args.no_learned:
+        learned = learned_form(plan, chunks, pulses, p, out, args.steps, ms)
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on a slice")
@@ -183,7 +231,7 @@ def main():
                    "n_ant": p["m_ant"], "n_chan": p["n_chan"], "samples": p["samples"], "n_dm": p["n_dm"],
                    "dump_len": p["dump_len"], "fft_len": int(lay["fft_len"][0]), "chunk": args.chunk,
                    "input": "ci8", "corr": args.corr, "parallelism": "none (1 GPU)"},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "learned": learned,
     }
     print(json.dumps(rec), flush=True)
     plan.close()

@@ -208,6 +208,73 @@ int ddx_set_profiling(ddx_plan* plan, int32_t on);
 /* Synchronise the recorded events and sum them per kernel kind into *out. */
 int ddx_get_profile(ddx_plan* plan, ddx_profile* out);
 
+/* ---- Learned DM proposal -------------------------------------------------------
+ *
+ * DM-time power tiles: the paper's incoherent dedispersion (Sec. 2.3.1: detect,
+ * integrate, delay each channel by the trial DM's delay, sum the channels) of
+ * power beams (Sec. 2.4.1: detected power summed over antennas), for the plan's
+ * trial DMs (every channel must have the same list) and its exported channel
+ * shifts (samples behind the highest channel).  With p_c[n] = sum_p |x_{c,p}[n]|^2,
+ *   T[d][t] = C B * sum_c sum_{n in W} p_c[n] / |W|,
+ *   W = [t B + shift[c][d], (t + 1) B + shift[c][d]) clipped to the stream,
+ * i.e. the mean power over the samples that exist, scaled to a full bin of B =
+ * bin_len samples.  Output [D][n_bins] FP32 in caller-owned device memory. */
+
+/* Tile of one whole stream d_volts [C][M][n] (device, in the plan's input format).
+ * Errors: ESTATE (no DM trials), EUNSUPPORTED (DM lists differ between channels),
+ * EINVAL, ENOMEM (plan scratch: C n floats + C (n + 1) doubles), EDEVICE. */
+int ddx_power_tile(ddx_plan* plan, const void* d_volts, int64_t n, int32_t bin_len, int32_t n_bins, float* d_tile,
+                   void* hip_stream);
+
+/* The same tiles for n_tiles streams given as power already summed over antennas
+ * and over fine bins of `fine` samples: d_power [n_tiles][C][units] FP32 (device).
+ * Shifts are rounded to whole fine bins; bin_len must be a multiple of fine.
+ * Output [n_tiles][D][n_bins]. */
+int ddx_power_tile_from_power(ddx_plan* plan, const float* d_power, int32_t n_tiles, int64_t units, int32_t fine,
+                              int32_t bin_len, int32_t n_bins, float* d_tiles, void* hip_stream);
+
+/* A 1-D CNN that scores every DM row of a tile.  Each tile is standardised
+ * ((T - mean) / std over the tile); row d's input is rows d-1, d, d+1 (edges
+ * repeated) over the n_bins time bins; four convolutions (kernel 9, zero padding
+ * 4, 32 channels, strides 1, 2, 2, 2, ReLU), a maximum over time and a linear
+ * layer give one logit per row.  Parameters: one FP32 vector of
+ * ddx_cnn_num_params values, in the order W1 [32][3][9], b1 [32], W2 [32][32][9],
+ * b2, W3, b3, W4, b4, w5 [32], b5 [1].  Training minimises the mean logistic loss
+ * of the row logits with Adam.  A network is not thread-safe; it holds the
+ * activations of its last forward pass, and the tiles and scores buffers passed
+ * to ddx_cnn_forward must stay valid until ddx_cnn_backward has run (the loss
+ * reads the scores, the backward pass the tiles). */
+typedef struct ddx_cnn ddx_cnn;
+
+int ddx_cnn_num_params(int64_t* n_params);
+
+/* Allocate a network for tiles of n_dm rows and n_bins bins (a multiple of 64),
+ * at most max_tiles per call.  Parameters start at zero: set them. */
+int ddx_cnn_create(int32_t n_dm, int32_t n_bins, int32_t max_tiles, ddx_cnn** out);
+
+/* Copy parameters from host memory (resets the Adam state) / to host memory;
+ * read the gradients of the last backward pass. */
+int ddx_cnn_set_weights(ddx_cnn* net, const float* host_params, int64_t n);
+int ddx_cnn_get_weights(ddx_cnn* net, float* host_params, int64_t n);
+int ddx_cnn_get_grads(ddx_cnn* net, float* host_grads, int64_t n);
+
+/* Scores of every row of n_tiles tiles: d_tiles [n_tiles][n_dm][n_bins] (device),
+ * d_scores [n_tiles * n_dm] (device).  Asynchronous on hip_stream. */
+int ddx_cnn_forward(ddx_cnn* net, const float* d_tiles, int32_t n_tiles, float* d_scores, void* hip_stream);
+
+/* After a forward pass: per-row logistic loss softplus(s) - y s into
+ * d_loss_rows [rows] and its gradient (sigmoid(s) - y) / rows kept for backward. */
+int ddx_cnn_loss(ddx_cnn* net, const float* d_labels, float* d_loss_rows, void* hip_stream);
+
+/* Gradients of the mean loss with respect to every parameter. */
+int ddx_cnn_backward(ddx_cnn* net, void* hip_stream);
+
+/* One Adam step (Kingma & Ba 2015, bias-corrected) with the last gradients. */
+int ddx_cnn_adam(ddx_cnn* net, float lr, float beta1, float beta2, float eps, void* hip_stream);
+
+int ddx_cnn_destroy(ddx_cnn* net);
+const char* ddx_cnn_last_error(const ddx_cnn* net);
+
 /* Synchronise the plan's last stream and free plan-owned memory.  NULL is a no-op. */
 int ddx_plan_destroy(ddx_plan* plan);
 

@@ -68,6 +68,21 @@ SIGNATURES = {
     "ddx_reset_stream": ([ct.c_void_p], ct.c_int),
     "ddx_set_profiling": ([ct.c_void_p, ct.c_int32], ct.c_int),
     "ddx_get_profile": ([ct.c_void_p, ct.POINTER(Profile)], ct.c_int),
+    "ddx_power_tile": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p],
+                       ct.c_int),
+    "ddx_power_tile_from_power": ([ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_int32, ct.c_int32,
+                                   ct.c_int32, ct.c_void_p, ct.c_void_p], ct.c_int),
+    "ddx_cnn_num_params": ([ct.POINTER(ct.c_int64)], ct.c_int),
+    "ddx_cnn_create": ([ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_void_p)], ct.c_int),
+    "ddx_cnn_set_weights": ([ct.c_void_p, ct.POINTER(ct.c_float), ct.c_int64], ct.c_int),
+    "ddx_cnn_get_weights": ([ct.c_void_p, ct.POINTER(ct.c_float), ct.c_int64], ct.c_int),
+    "ddx_cnn_get_grads": ([ct.c_void_p, ct.POINTER(ct.c_float), ct.c_int64], ct.c_int),
+    "ddx_cnn_forward": ([ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p], ct.c_int),
+    "ddx_cnn_loss": ([ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p], ct.c_int),
+    "ddx_cnn_backward": ([ct.c_void_p, ct.c_void_p], ct.c_int),
+    "ddx_cnn_adam": ([ct.c_void_p, ct.c_float, ct.c_float, ct.c_float, ct.c_float, ct.c_void_p], ct.c_int),
+    "ddx_cnn_destroy": ([ct.c_void_p], ct.c_int),
+    "ddx_cnn_last_error": ([ct.c_void_p], ct.c_char_p),
     "ddx_plan_destroy": ([ct.c_void_p], ct.c_int),
     "ddx_strerror": ([ct.c_int], ct.c_char_p),
     "ddx_last_error": ([ct.c_void_p], ct.c_char_p),
@@ -234,6 +249,29 @@ class Plan:
         return {KIND_NAMES[k]: {"launches": pr.launches[k], "time_ms": pr.time_ms[k], "flops": pr.flops[k],
                                 "bytes": pr.bytes[k]} for k in range(N_KINDS)}
 
+    def power_tile(self, volts, bin_len, n_bins, out=None, stream=None):
+        """DM-time tile [D, n_bins] of one whole stream (device tensor as for process_block)."""
+        import torch
+        n = volts.shape[-1] // 2 if self.in_dtype == "ci8" else volts.shape[-1]
+        d = int(self.layout()["n_dm"][0])
+        if out is None:
+            out = torch.empty((d, n_bins), dtype=torch.float32, device=volts.device)
+        self._check(lib().ddx_power_tile(self._h, ct.c_void_p(volts.data_ptr()), int(n), bin_len, n_bins,
+                                         ct.c_void_p(out.data_ptr()), _stream_handle(stream)), "ddx_power_tile")
+        return out
+
+    def tiles_from_power(self, power, fine, bin_len, n_bins, out=None, stream=None):
+        """Tiles [T, D, n_bins] from fine-bin beam power [T, C, U] (device float32 tensor)."""
+        import torch
+        t, c, u = power.shape
+        d = int(self.layout()["n_dm"][0])
+        if out is None:
+            out = torch.empty((t, d, n_bins), dtype=torch.float32, device=power.device)
+        self._check(lib().ddx_power_tile_from_power(self._h, ct.c_void_p(power.data_ptr()), t, int(u), fine, bin_len,
+                                                    n_bins, ct.c_void_p(out.data_ptr()), _stream_handle(stream)),
+                    "ddx_power_tile_from_power")
+        return out
+
     def close(self):
         if getattr(self, "_h", None):
             lib().ddx_plan_destroy(self._h)
@@ -250,3 +288,78 @@ class Plan:
 
     def __exit__(self, *a):
         self.close()
+
+
+class Cnn:
+    """The DM-proposal network of include/ddx.h (ddx_cnn_*)."""
+
+    def __init__(self, n_dm, n_bins, max_tiles):
+        L = lib()
+        n = ct.c_int64()
+        L.ddx_cnn_num_params(ct.byref(n))
+        self.n_params = n.value
+        h = ct.c_void_p()
+        rc = L.ddx_cnn_create(n_dm, n_bins, max_tiles, ct.byref(h))
+        if rc != OK:
+            raise DdxError(rc, "ddx_cnn_create")
+        self._h = h
+        self.n_dm, self.n_bins, self.max_tiles = n_dm, n_bins, max_tiles
+
+    def _check(self, rc, what):
+        if rc != OK:
+            raise DdxError(rc, "%s: %s" % (what, lib().ddx_cnn_last_error(self._h).decode()))
+
+    def set_weights(self, flat):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        self._check(lib().ddx_cnn_set_weights(self._h, a.ctypes.data_as(ct.POINTER(ct.c_float)), a.size),
+                    "ddx_cnn_set_weights")
+
+    def get_weights(self):
+        a = np.empty(self.n_params, dtype=np.float32)
+        self._check(lib().ddx_cnn_get_weights(self._h, a.ctypes.data_as(ct.POINTER(ct.c_float)), a.size),
+                    "ddx_cnn_get_weights")
+        return a
+
+    def get_grads(self):
+        a = np.empty(self.n_params, dtype=np.float32)
+        self._check(lib().ddx_cnn_get_grads(self._h, a.ctypes.data_as(ct.POINTER(ct.c_float)), a.size),
+                    "ddx_cnn_get_grads")
+        return a
+
+    def forward(self, tiles, scores=None, stream=None):
+        """tiles: device float32 [T, n_dm, n_bins] (kept alive until backward); returns scores [T * n_dm]."""
+        import torch
+        t = tiles.shape[0]
+        if scores is None:
+            scores = torch.empty(t * self.n_dm, dtype=torch.float32, device=tiles.device)
+        self._check(lib().ddx_cnn_forward(self._h, ct.c_void_p(tiles.data_ptr()), t, ct.c_void_p(scores.data_ptr()),
+                                          _stream_handle(stream)), "ddx_cnn_forward")
+        # the library reads both again in loss/backward: keep them alive until the next forward
+        self._tiles, self._scores = tiles, scores
+        return scores
+
+    def loss(self, labels, loss_rows=None, stream=None):
+        import torch
+        if loss_rows is None:
+            loss_rows = torch.empty_like(labels)
+        self._check(lib().ddx_cnn_loss(self._h, ct.c_void_p(labels.data_ptr()), ct.c_void_p(loss_rows.data_ptr()),
+                                       _stream_handle(stream)), "ddx_cnn_loss")
+        self._labels = labels
+        return loss_rows
+
+    def backward(self, stream=None):
+        self._check(lib().ddx_cnn_backward(self._h, _stream_handle(stream)), "ddx_cnn_backward")
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        self._check(lib().ddx_cnn_adam(self._h, lr, beta1, beta2, eps, _stream_handle(stream)), "ddx_cnn_adam")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ddx_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -5,7 +5,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "ddx.hip")
+SRC = [os.path.join(HERE, "csrc", f) for f in ("ddx.hip", "cnn.hip")]
 LIB = os.path.join(HERE, "libddx.so")
 
 # Packed-FP32 VALU instructions are kept out of the generated code.
@@ -18,7 +18,7 @@ HIPCC_FLAGS = [
 def build(verbose=False):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     cmd = [hipcc] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-                                   "-o", LIB + ".tmp", SRC]
+                                   "-o", LIB + ".tmp"] + SRC
     r = subprocess.run(cmd, capture_output=True, text=True)
     noise = "packed-fp32-ops' is not a recognized feature"
     msgs = [ln for ln in (r.stdout + r.stderr).splitlines() if noise not in ln]

@@ -12,6 +12,7 @@
 
 #include "ddx.h"
 #include "kernels.hpp"
+#include "tiles.hpp"
 
 namespace {
 
@@ -82,6 +83,15 @@ struct ddx_plan {
   int32_t* pos_dev = nullptr;    // [sum D_c] record positions, active first then inactive
   std::vector<int> n_active;
   float* scale_dev = nullptr;    // [C]
+  // DM-time tiles: scratch grown on demand
+  float* tile_power = nullptr;
+  size_t tile_power_cap = 0;
+  double* tile_prefix = nullptr;
+  size_t tile_prefix_cap = 0;
+  double* tile_totals = nullptr;
+  size_t tile_totals_cap = 0;
+  int64_t* tile_shift = nullptr;
+  int tile_shift_fine = 0;
   hipStream_t last_stream = nullptr;
   bool scale_pending = false;    // scale_dev holds rule scales not yet copied to lay_scale
   std::string err;
@@ -140,6 +150,14 @@ void free_device(ddx_plan* p) {
   p->gtab = p->kdm_dev = nullptr;
   p->pos_dev = nullptr;
   p->scale_dev = nullptr;
+  p->tile_power = nullptr;
+  p->tile_power_cap = 0;
+  p->tile_prefix = nullptr;
+  p->tile_prefix_cap = 0;
+  p->tile_totals = nullptr;
+  p->tile_totals_cap = 0;
+  p->tile_shift = nullptr;
+  p->tile_shift_fine = 0;
 }
 
 size_t in_bytes(int in_dtype) { return in_dtype == DDX_IN_CI8 ? 2 : 8; }
@@ -728,6 +746,98 @@ int ddx_fetch_visibilities(ddx_plan* p, void* out, size_t cap, int64_t* first, i
   p->dumps_fetched = ready;
   p->last_stream = s;
   return DDX_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Grow a plan-owned scratch buffer (old contents are not kept).
+template <class T>
+int ensure(ddx_plan* p, T** buf, size_t* cap, size_t elems) {
+  if (*cap >= elems) return DDX_OK;
+  if (p->last_stream) HIPCHECK(p, hipStreamSynchronize(p->last_stream));
+  if (*buf) {
+    for (auto it = p->allocs.begin(); it != p->allocs.end(); ++it)
+      if (*it == (void*)*buf) { p->allocs.erase(it); break; }
+    (void)hipFree(*buf);
+    p->dev_bytes -= *cap * sizeof(T);
+    *buf = nullptr;
+    *cap = 0;
+  }
+  int rc = dev_alloc(p, (void**)buf, elems * sizeof(T));
+  if (rc == DDX_OK) *cap = elems;
+  return rc;
+}
+
+// Common tail of both tile entry points: per-channel power rows -> prefix sums -> tiles.
+int tiles_from_rows(ddx_plan* p, const float* power, int n_tiles, int64_t units, int fine, int bin_len, int n_bins,
+                    float* tiles, hipStream_t s) {
+  const int C = p->C, D = (int)p->ch[0].dm.size();
+  const int64_t rows = (int64_t)n_tiles * C;
+  const int nblk = (int)((units + ddx::kScanBlock - 1) / ddx::kScanBlock);
+  int rc;
+  if ((rc = ensure(p, &p->tile_prefix, &p->tile_prefix_cap, (size_t)rows * (units + 1)))) return rc;
+  if ((rc = ensure(p, &p->tile_totals, &p->tile_totals_cap, (size_t)rows * nblk))) return rc;
+  if (p->tile_shift_fine != fine) {
+    if (!p->tile_shift && (rc = dev_alloc(p, (void**)&p->tile_shift, (size_t)C * D * sizeof(int64_t)))) return rc;
+    std::vector<int64_t> sh((size_t)C * D);
+    for (int c = 0; c < C; ++c)
+      for (int d = 0; d < D; ++d)
+        sh[(size_t)c * D + d] = (int64_t)std::nearbyint((double)p->lay_shift[p->dm_off[c] + d] / fine);
+    if (p->last_stream) HIPCHECK(p, hipStreamSynchronize(p->last_stream));
+    HIPCHECK(p, hipMemcpy(p->tile_shift, sh.data(), sh.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    p->tile_shift_fine = fine;
+  }
+  const dim3 g(nblk, (unsigned)rows);
+  hipLaunchKernelGGL(ddx::k_scan_local, g, dim3(256), 0, s, power, units, p->tile_prefix, p->tile_totals, nblk);
+  HIPCHECK(p, hipGetLastError());
+  hipLaunchKernelGGL(ddx::k_scan_fix, g, dim3(256), 0, s, p->tile_prefix, units, p->tile_totals, nblk);
+  HIPCHECK(p, hipGetLastError());
+  hipLaunchKernelGGL(ddx::k_tile, dim3((n_bins + 255) / 256, D, n_tiles), dim3(256), 0, s, p->tile_prefix, units, C,
+                     p->tile_shift, D, bin_len / fine, n_bins, tiles);
+  HIPCHECK(p, hipGetLastError());
+  p->last_stream = s;
+  return DDX_OK;
+}
+
+int tile_checks(ddx_plan* p, int bin_len, int n_bins, int fine) {
+  if (!p->ready) return fail(p, DDX_ESTATE, "set DM trials for every channel first");
+  for (auto& c : p->ch)
+    if (c.dm != p->ch[0].dm) return fail(p, DDX_EUNSUPPORTED, "tiles need the same DM trials in every channel");
+  if (fine < 1 || bin_len < fine || bin_len % fine != 0 || n_bins < 1)
+    return fail(p, DDX_EINVAL, "bin_len must be a positive multiple of the fine bin, n_bins >= 1");
+  return DDX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ddx_power_tile(ddx_plan* p, const void* d_volts, int64_t n, int32_t bin_len, int32_t n_bins, float* d_tile,
+                   void* hip_stream) {
+  if (!p) return DDX_EINVAL;
+  int rc = tile_checks(p, bin_len, n_bins, 1);
+  if (rc) return rc;
+  if (!d_volts || !d_tile || n < 1) return fail(p, DDX_EINVAL, "null buffer or empty stream");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if ((rc = ensure(p, &p->tile_power, &p->tile_power_cap, (size_t)p->C * n))) return rc;
+  const dim3 g((unsigned)((n + 255) / 256), p->C);
+  if (p->in_dtype == DDX_IN_CI8)
+    hipLaunchKernelGGL(ddx::k_beam_power<0>, g, dim3(256), 0, s, d_volts, n, p->M, p->tile_power);
+  else
+    hipLaunchKernelGGL(ddx::k_beam_power<1>, g, dim3(256), 0, s, d_volts, n, p->M, p->tile_power);
+  HIPCHECK(p, hipGetLastError());
+  return tiles_from_rows(p, p->tile_power, 1, n, 1, bin_len, n_bins, d_tile, s);
+}
+
+int ddx_power_tile_from_power(ddx_plan* p, const float* d_power, int32_t n_tiles, int64_t units, int32_t fine,
+                              int32_t bin_len, int32_t n_bins, float* d_tiles, void* hip_stream) {
+  if (!p) return DDX_EINVAL;
+  int rc = tile_checks(p, bin_len, n_bins, fine);
+  if (rc) return rc;
+  if (!d_power || !d_tiles || n_tiles < 1 || units < 1) return fail(p, DDX_EINVAL, "null buffer or empty input");
+  return tiles_from_rows(p, d_power, n_tiles, units, fine, bin_len, n_bins, d_tiles, (hipStream_t)hip_stream);
 }
 
 int ddx_reset_stream(ddx_plan* p) {

@@ -33,3 +33,4 @@ from .signals import (  # noqa: F401
     c3_params,
     make_stream_device,
 )
+from .power import power_batch, sample_pulses  # noqa: F401

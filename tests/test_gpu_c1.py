@@ -28,7 +28,7 @@ def c1_input(gpu):
     return p, chunks, pulses, fc, host
 
 
-def _run(p, chunks, fc, corr):
+def _run(p, chunks, fc, corr, pairs=None):
     import torch
 
     from paper_1109_3186_amd import Plan
@@ -40,7 +40,8 @@ def _run(p, chunks, fc, corr):
     nbl = lay["n_baselines"]
     iu, ju = np.triu_indices(m)
     auto_idx = torch.tensor(np.nonzero(iu == ju)[0], device="cuda")
-    keep = {pair: [] for pair in PAIRS}
+    pairs = PAIRS if pairs is None else pairs
+    keep = {pair: [] for pair in pairs}
     power = []
     for i, ch in enumerate(chunks):
         plan.process_block(ch, flush=(i == len(chunks) - 1))
@@ -49,7 +50,7 @@ def _run(p, chunks, fc, corr):
             continue
         v = vis.view(nd, -1, nbl)  # [dump, (c, d), baseline]
         power.append(v.index_select(2, auto_idx).real.sum(dim=2).cpu().numpy())
-        for (c, d) in PAIRS:
+        for (c, d) in pairs:
             keep[(c, d)].append(v[:, lay["dm_offset"][c] + d].cpu().numpy())
         del vis, v
         torch.cuda.synchronize()
@@ -117,3 +118,46 @@ def test_c1_quantised_error_table(c1_input, corr, bound):
     assert np.quantile(e, 0.999) <= bound
     assert e.max() <= 2 * bound
     assert z.max() <= 5 * bound
+
+
+def test_c1_learned_proposal(c1_input):
+    """The learned proposal on the full-size stream: every injected pulse's DM trial is
+    kept (or the proposal falls back to the full sweep), and visibilities of the
+    kept DMs are bitwise those of the full sweep."""
+    import math
+    import os
+
+    import torch
+
+    from paper_1109_3186_amd import Plan
+    from paper_1109_3186_amd.proposal import Proposal, load_weights
+    p, chunks, pulses, fc, host = c1_input
+    wpath = os.path.join(os.path.dirname(os.path.dirname(__file__)), "paper_1109_3186_amd", "proposal_weights.npz")
+    dms = synth.dm_grid(p["n_dm"], p["dm_max"])
+    plan = Plan(p["m_ant"], fc, p["f_s"], p["dump_len"], max_block_samples=CHUNK, in_dtype="ci8")
+    plan.set_dm_trials(dms)
+    full = torch.cat(chunks, dim=-1).contiguous()
+    prop = Proposal(plan, load_weights(wpath), budget=0.1)
+    mask, scores, fb = prop.select(full)
+    del full
+    dstep = p["dm_max"] / p["n_dm"]
+    hits = [bool(mask[math.floor(q["dm"] / dstep)] or mask[min(math.ceil(q["dm"] / dstep), p["n_dm"] - 1)])
+            for q in pulses]
+    say("learned proposal: %d active, fallback %s, recall %d/%d" % (mask.sum(), fb, sum(hits), len(hits)))
+    assert all(hits)
+    plan.set_active_dms(mask)
+    lay = plan.layout()
+    nbl = lay["n_baselines"]
+    active = np.nonzero(mask)[0][:3]
+    got = {d: [] for d in active}
+    for i, ch in enumerate(chunks):
+        plan.process_block(ch, flush=(i == len(chunks) - 1))
+        _, nd, vis = plan.fetch()
+        v = vis.view(nd, -1, nbl)
+        for d in active:
+            got[d].append(v[:, lay["dm_offset"][63] + d].cpu().numpy())
+    prop.close()
+    plan.close()
+    ref, _, _, _ = _run(p, chunks, fc, "f32", pairs=[(63, int(d)) for d in active])
+    for d in active:
+        assert np.array_equal(np.concatenate(got[d]), ref[(63, int(d))])

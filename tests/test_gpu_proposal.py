@@ -1,0 +1,179 @@
+"""GPU parity of the learned-proposal kernels against the FP64 oracle, and what
+the trained network gains over the method without it."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import run_gpu, say, select
+from oracle import proposal as P
+
+pytestmark = pytest.mark.gpu
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(__file__)), "paper_1109_3186_amd", "proposal_weights.npz")
+
+
+def _plan(cfg, in_dtype="ci8", max_block=1 << 15):
+    from paper_1109_3186_amd import Plan
+    p = Plan(cfg["volts"].shape[1], cfg["chan_freqs"], cfg["f_s"], cfg["dump_len"], max_block_samples=max_block,
+             in_dtype=in_dtype)
+    p.set_dm_trials(cfg["dm_lists"][0])
+    return p
+
+
+def test_tile_kernel_matches_oracle(gpu):
+    import torch
+    cfg = synth.make_small(seed=41, m_ant=3, n_chan=4, s=1 << 14, f_lo=1.2e9, f_s=1e6, n_dm=32, dm_max=500.0,
+                           dump_len=100, ci8=True, n_pulses=2)
+    with _plan(cfg) as plan:
+        tile = plan.power_tile(torch.from_numpy(cfg["volts"]).to(gpu), 256, 64).cpu().numpy()
+        lay = plan.layout()
+        shift = lay["shift"].reshape(4, 32)
+        # fine-bin form: [2, C, U] power at 8-sample resolution
+        rng = np.random.Generator(np.random.PCG64(42))
+        pw = rng.random((2, 4, 2048)).astype(np.float32) * 100
+        tiles = plan.tiles_from_power(torch.from_numpy(pw).to(gpu), 8, 256, 64).cpu().numpy()
+    ref = P.tile_from_prefix(P.power_prefix(cfg["volts"]), shift, 256, 64)
+    assert np.max(np.abs(tile - ref) / np.abs(ref).max()) <= 1e-6
+    for t in range(2):
+        pre = np.concatenate([np.zeros((4, 1)), np.cumsum(pw[t].astype(np.float64), axis=1)], axis=1)
+        ref2 = P.tile_from_prefix(pre, shift, 256, 64, fine=8)
+        assert np.max(np.abs(tiles[t] - ref2) / np.abs(ref2).max()) <= 1e-6
+
+
+def _flat(params):
+    from paper_1109_3186_amd.proposal import flatten
+    return flatten(params)
+
+
+def test_cnn_forward_backward_adam_match_oracle(gpu):
+    import torch
+
+    from paper_1109_3186_amd import Cnn
+    from paper_1109_3186_amd.proposal import unflatten
+    rng = np.random.Generator(np.random.PCG64(43))
+    d, L, nt = 16, 128, 2
+    tiles = rng.standard_normal((nt, d, L)) * 3 + 10
+    tiles[0, 5, 40:44] += 30  # a bump so that some channels have a clear maximum
+    params = P.init_params(44)
+    params["b1"] = rng.standard_normal(32) * 0.1
+    params["b5"] = np.array([0.3])
+    labels = (rng.random(nt * d) < 0.3).astype(np.float64)
+    net = Cnn(d, L, nt)
+    net.set_weights(_flat(params))
+    t_dev = torch.from_numpy(tiles.astype(np.float32)).to(gpu)
+    scores = net.forward(t_dev).cpu().numpy()
+    x = np.concatenate([P.rows3(P.standardise(tiles[i])) for i in range(nt)])
+    ref, cache = P.forward(params, x)
+    assert np.max(np.abs(scores - ref)) <= 1e-4 * max(1.0, np.abs(ref).max())
+    loss_rows = net.loss(torch.from_numpy(labels.astype(np.float32)).to(gpu)).cpu().numpy()
+    lref, ds = P.loss_and_grad(ref, labels)
+    assert abs(loss_rows.mean() - lref) <= 1e-5 * max(1.0, abs(lref))
+    net.backward()
+    g = unflatten(net.get_grads())
+    gref = P.backward(params, cache, ds)
+    for k in gref:
+        rel = np.linalg.norm(g[k] - gref[k]) / max(np.linalg.norm(gref[k]), 1e-12)
+        say("grad %s rel %.2e" % (k, rel))
+        assert rel <= 1e-3, k
+    # one Adam step from zero state on the GPU's own gradients
+    before = net.get_weights()
+    net.adam(lr=1e-3)
+    after = net.get_weights()
+    gflat = net.get_grads().astype(np.float64)
+    expect = before - 1e-3 * gflat / (np.abs(gflat) + 1e-8)
+    assert np.max(np.abs(after - expect)) <= 1e-6
+    net.close()
+
+
+def test_overfit_tiny_batch(gpu):
+    """Training on two fixed tiles drives the loss down and ranks the labelled rows first."""
+    import torch
+
+    from paper_1109_3186_amd import Cnn
+    from paper_1109_3186_amd.train_proposal import he_init, make_plan
+    p = synth.c1_params()
+    plan = make_plan(p)
+    rng = np.random.Generator(np.random.PCG64(45))
+    gen = torch.Generator(device=gpu)
+    gen.manual_seed(45)
+    power, labels, pulses = synth.power_batch(p, 2, 32, rng, gen, gpu, pulse_frac=1.0, snr_range=(30.0, 40.0),
+                                              max_pulses=1)
+    tiles = plan.tiles_from_power(power, 32, 1024, 1024)
+    net = Cnn(p["n_dm"], 1024, 2)
+    net.set_weights(he_init(1))
+    first = None
+    for it in range(150):
+        scores = net.forward(tiles)
+        loss = float(net.loss(labels.reshape(-1)).mean())
+        first = loss if first is None else first
+        net.backward()
+        net.adam(lr=3e-3)
+    say("overfit loss %.4f -> %.4f" % (first, loss))
+    assert loss < 0.2 * first
+    s = scores.cpu().numpy().reshape(2, -1)
+    y = labels.cpu().numpy()
+    for t in range(2):
+        top = set(np.argsort(-s[t])[:int(y[t].sum())])
+        assert top == set(np.nonzero(y[t])[0])
+    net.close()
+    plan.close()
+
+
+def _recall(scores, pulses, k, dstep):
+    hit = tot = 0
+    for t, pl in enumerate(pulses):
+        top = set(np.argsort(-scores[t], kind="stable")[:k].tolist())
+        for q in pl:
+            d0 = q["dm"] / dstep
+            tot += 1
+            hit += int(math.floor(d0) in top or math.ceil(d0) in top)
+    return hit / max(tot, 1), tot
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained weights (run python -m paper_1109_3186_amd.train_proposal)")
+def test_trained_network_recall_and_gain(gpu):
+    """Recall at the top 10% of DM rows on held-out tiles (S/N 5-50): the trained
+    network against the untrained one and against the method without a network
+    (rank rows by their maximum standardised tile value)."""
+    import torch
+
+    from paper_1109_3186_amd import Cnn
+    from paper_1109_3186_amd.proposal import load_weights
+    from paper_1109_3186_amd.train_proposal import he_init, make_plan
+    p = synth.c1_params()
+    plan = make_plan(p)
+    rng = np.random.Generator(np.random.PCG64(9001))
+    gen = torch.Generator(device=gpu)
+    gen.manual_seed(9001)
+    nets = {"trained": load_weights(WEIGHTS), "untrained": he_init(1114)}
+    k = int(math.ceil(0.1 * p["n_dm"]))
+    res = {n: [] for n in list(nets) + ["rowmax"]}
+    allpulses = []
+    cnns = {}
+    for name, w in nets.items():
+        cnns[name] = Cnn(p["n_dm"], 1024, 8)
+        cnns[name].set_weights(w)
+    for b in range(50):
+        power, labels, pulses = synth.power_batch(p, 8, 32, rng, gen, gpu, pulse_frac=1.0, max_pulses=1)
+        tiles = plan.tiles_from_power(power, 32, 1024, 1024)
+        for name, net in cnns.items():
+            res[name].append(net.forward(tiles).cpu().numpy().reshape(8, -1))
+        tn = tiles.cpu().numpy()
+        res["rowmax"].append(np.stack([P.standardise(tn[i]).max(axis=1) for i in range(8)]))
+        allpulses += pulses
+    out = {}
+    for name in res:
+        sc = np.concatenate(res[name])
+        out[name] = _recall(sc, allpulses, k, p["dm_max"] / p["n_dm"])
+    say("recall at top %d of %d rows over %d pulses: %s" % (k, p["n_dm"], out["trained"][1],
+                                                             {n: round(v[0], 4) for n, v in out.items()}))
+    assert out["trained"][0] >= 0.99
+    assert out["trained"][0] >= out["untrained"][0] + 0.2
+    assert out["trained"][0] >= out["rowmax"][0]
+    for n in cnns.values():
+        n.close()
+    plan.close()

@@ -1,0 +1,109 @@
+"""Pins of the proposal oracle (tiles, CNN forward/backward, Adam) on the CPU."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import proposal as P
+
+
+def _rng(s):
+    return np.random.Generator(np.random.PCG64(s))
+
+
+def test_conv_matches_direct_loops():
+    rng = _rng(1)
+    x = rng.standard_normal((2, 3, 11))
+    w = rng.standard_normal((4, 3, P.KERNEL))
+    for stride in (1, 2):
+        out = P.conv(x, w, stride)
+        lout = (11 + stride - 1) // stride
+        ref = np.zeros((2, 4, lout))
+        for b in range(2):
+            for o in range(4):
+                for t in range(lout):
+                    for i in range(3):
+                        for k in range(P.KERNEL):
+                            j = stride * t + k - P.PAD
+                            if 0 <= j < 11:
+                                ref[b, o, t] += w[o, i, k] * x[b, i, j]
+        np.testing.assert_allclose(out, ref, atol=1e-12)
+
+
+def test_gradients_match_central_differences():
+    rng = _rng(2)
+    params = P.init_params(3)
+    x = rng.standard_normal((3, 3, 24))
+    labels = np.array([1.0, 0.0, 1.0])
+
+    def loss_of(pr):
+        s, _ = P.forward(pr, x)
+        return P.loss_and_grad(s, labels)[0]
+
+    s, cache = P.forward(params, x)
+    _, ds = P.loss_and_grad(s, labels)
+    grads = P.backward(params, cache, ds)
+    h = 1e-6
+    for name in ["W1", "b1", "W2", "W3", "W4", "b4", "w5", "b5"]:
+        flat = params[name].reshape(-1)
+        for idx in rng.choice(flat.size, size=min(6, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp = loss_of(params)
+            flat[idx] = old - h
+            lm = loss_of(params)
+            flat[idx] = old
+            num = (lp - lm) / (2 * h)
+            ana = grads[name].reshape(-1)[idx]
+            assert abs(num - ana) <= 1e-7 + 1e-5 * abs(num), (name, idx, num, ana)
+
+
+def test_adam_first_step_moves_by_lr_times_sign():
+    params = {"a": np.array([1.0, -2.0, 3.0])}
+    grads = {"a": np.array([0.5, -4.0, 1e-3])}
+    state = {}
+    P.adam_step(params, grads, state, lr=0.01)
+    # first step: m_hat = g, v_hat = g^2, update = lr g / (|g| + eps) ~ lr sign(g)
+    np.testing.assert_allclose(params["a"], [0.99, -1.99, 2.99], atol=1e-7)
+
+
+def test_tile_matches_brute_force():
+    rng = _rng(4)
+    x = synth.noise_complex(rng, (3, 2, 700))
+    prefix = P.power_prefix(x)
+    shift = np.array([[0, 5, 17], [3, 0, 40], [0, 0, 1]])
+    tile = P.tile_from_prefix(prefix, shift, 50, 14)
+    p = (np.abs(x) ** 2).sum(axis=1)
+    for d in range(3):
+        for t in range(14):
+            tot, cnt = 0.0, 0
+            for c in range(3):
+                for n in range(t * 50 + shift[c, d], (t + 1) * 50 + shift[c, d]):
+                    if 0 <= n < 700:
+                        tot += p[c, n]
+                        cnt += 1
+            ref = tot * 3 * 50 / cnt if cnt else 0.0
+            assert abs(tile[d, t] - ref) < 1e-9 * max(1.0, ref)
+    # the fine-bin form equals the per-sample one when shifts are multiples of the fine bin
+    fine = 10
+    pf = np.concatenate([np.zeros((3, 1)), np.cumsum(p.reshape(3, -1, fine).sum(axis=2), axis=1)], axis=1)
+    sh10 = shift // 10 * 10
+    np.testing.assert_allclose(P.tile_from_prefix(pf, sh10, 50, 14, fine=fine),
+                               P.tile_from_prefix(prefix, sh10, 50, 14), rtol=1e-12)
+
+
+def test_tile_peaks_at_the_injected_dm():
+    """Incoherent dedispersion (Sec. 2.3.1) of a strong noise-free pulse across 16 channels."""
+    fc = synth.chan_freqs(1.2e9, 16, 1e6)
+    dms = synth.dm_grid(32, 2000.0)
+    rng = _rng(5)
+    s = 1 << 17
+    x = np.zeros((16, 2, s), dtype=np.complex128)
+    n0, dm = 20000, 1000.0
+    for c in range(16):
+        synth.inject_pulse(x[c], fc[c], 1e6, dm, n0, synth.pulse_wave(rng, 100, 50.0, 1.0), f_ref=fc[-1],
+                           phases=np.zeros(2))
+    _, shift = oracle.channel_delays(fc, dms, 1e6)
+    tile = P.tile_from_prefix(P.power_prefix(x), shift, 1024, s // 1024)
+    d, t = np.unravel_index(np.argmax(tile), tile.shape)
+    assert d == 16 and abs(t - n0 // 1024) <= 10
