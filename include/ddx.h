@@ -65,7 +65,7 @@ extern "C" {
 #define DDX_FLUSH 1 /* end of stream: zero-pad after the last sample and finish */
 
 typedef struct ddx_desc {
-  int32_t n_ant;               /* M >= 1 antennas */
+  int32_t n_ant;               /* M antennas, 1 <= M <= 1024 (more: DDX_EUNSUPPORTED) */
   int32_t n_chan;              /* C >= 1 channels */
   const double* chan_freq_hz;  /* [C] sky frequency of each channel's DC bin, > samp_rate/2 */
   double samp_rate_hz;         /* complex sample rate = channel bandwidth, > 0 */

@@ -19,7 +19,8 @@ namespace {
 constexpr double kDefaultKdm = 4.148808e15;
 constexpr int kMaxLogN = 15;
 constexpr int kMinLogN = 8;
-constexpr int kMaxCorrAnt = 64;  // stacked-row Gram kernel: 2 M <= 128
+constexpr int kMaxStackedAnt = 64;  // stacked-row Gram kernel up to 2 M = 128 rows
+constexpr int kMaxCorrAnt = 1024;   // antenna-block kernel beyond
 // Scale rule targets: E4M3 puts sigma near 32, so even after the power-of-two
 // rounding (up to x sqrt 2) about 10 sigma, and the int8 extreme 127 at sigma 16,
 // stay below its largest finite value 448; binary16 puts sigma near 4 (far from
@@ -258,7 +259,17 @@ hipError_t launch_corr_nt(int corr_dtype, const ddx::CorrArgs& a, hipStream_t s)
   return hipGetLastError();
 }
 
+hipError_t launch_corr_blocks(int corr_dtype, const ddx::CorrArgs& a, hipStream_t s) {
+  const int nb = (a.n_ant + ddx::kBlkAnt - 1) / ddx::kBlkAnt;
+  const dim3 g(a.n_dumps * a.nd * (nb * (nb + 1) / 2)), b(256);
+  if (corr_dtype == DDX_CORR_F32) hipLaunchKernelGGL((ddx::k_correlate_blocks<0>), g, b, 0, s, a);
+  else if (corr_dtype == DDX_CORR_F16) hipLaunchKernelGGL((ddx::k_correlate_blocks<1>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((ddx::k_correlate_blocks<2>), g, b, 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_corr(int corr_dtype, const ddx::CorrArgs& a, hipStream_t s) {
+  if (a.n_ant > kMaxStackedAnt) return launch_corr_blocks(corr_dtype, a, s);
   const int nt = (2 * a.n_ant + 15) / 16;
   switch (nt) {
     case 1: return launch_corr_nt<1>(corr_dtype, a, s);

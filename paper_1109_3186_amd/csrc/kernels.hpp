@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 #include <stdint.h>
+#include <type_traits>
 
 #include "fft.hpp"
 
@@ -157,6 +158,110 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_dedisperse(DedispArgs a) {
       const int n = t + u * G::T + q * (G::N / G::RL);
       if (n >= a.lead && n < a.lead + a.valid) y[n - a.lead] = convert_y<OUT>(v[u * G::RL + out_reg<G::RL>(q)], scale);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Transforms longer than one workgroup's LDS: N = R * 32768 (R = 2, 4, 8), with
+// k = k1 + R k2 and n = n1 32768 + n2 (k1, n1 < R; k2, n2 < 32768):
+//   F[n] = sum_{k1} w_R^{n1 k1} [ w_N^{n2 k1} sum_{k2} w_32768^{n2 k2} Z[k1 + R k2] ],
+// w_M = exp(s 2 pi i / M).  Pass A: for each k1 a 32768-point transform of the
+// stride-R subsequence, times the twiddle w_N^{n2 k1}, stored as T[k1][n2].  Pass B:
+// for each n2 an R-point DFT over k1, giving F in natural order.
+constexpr int kBigLog = 15;
+constexpr int kBigN = 1 << kBigLog;
+
+// exp(S 2 pi i num / (R 2^15)), angle reduced exactly
+template <int R, int S>
+__device__ __forceinline__ float2 big_twiddle(int num) {
+  const int den = R * kBigN;
+  float x = (float)(num % den) * (1.0f / (float)den);
+  x = (x >= 0.5f) ? x - 1.0f : x;
+  return make_float2(cos_rev(x), (float)S * sin_rev(x));
+}
+
+// Pass A of the forward transform of every block: grid nblk * M * R workgroups,
+// (blk fastest, then k1, then p).  t[((p nblk + blk) R + k1) 2^15 + n2].
+template <int R, int IN>
+__global__ __launch_bounds__(Geo<kBigLog>::T) void k_forward_big_a(FwdArgs a, float2* __restrict__ tbuf) {
+  using G = Geo<kBigLog>;
+  extern __shared__ float lds[];
+  const int t = threadIdx.x;
+  const int blk = blockIdx.x % a.nblk, rest = blockIdx.x / a.nblk;
+  const int k1 = rest % R, p = rest / R;
+  Source s = a.src;
+  s.row = a.chan * a.n_ant + p;
+  const int64_t win0 = (a.b0 + blk) * (int64_t)a.valid - a.lead + k1;
+  float2 v[G::P];
+  fft_workgroup<kBigLog, -1>(v, lds, t, [&](int i) { return load_sample<IN>(s, win0 + (int64_t)R * i); });
+  float2* out = tbuf + (((size_t)p * a.nblk + blk) * R + k1) * kBigN + opaque_zero(v[0].x);
+#pragma unroll
+  for (int u = 0; u < G::P / G::RL; ++u)
+#pragma unroll
+    for (int q = 0; q < G::RL; ++q) {
+      const int n2 = t + u * G::T + q * (G::N / G::RL);
+      out[n2] = cmul(v[u * G::RL + out_reg<G::RL>(q)], big_twiddle<R, -1>(n2 * k1));
+    }
+}
+
+// Pass B of the forward transform: spec[(p nblk + blk) N + n1 2^15 + n2].
+// grid: (2^15 / 256, nblk * M).
+template <int R>
+__global__ __launch_bounds__(256) void k_forward_big_b(const float2* __restrict__ tbuf, float2* __restrict__ spec) {
+  const int n2 = blockIdx.x * 256 + threadIdx.x;
+  const size_t item = blockIdx.y;  // p * nblk + blk
+  float2 v[R];
+#pragma unroll
+  for (int k1 = 0; k1 < R; ++k1) v[k1] = tbuf[(item * R + k1) * kBigN + n2];
+  dft_reg<R, -1>(v);
+#pragma unroll
+  for (int n1 = 0; n1 < R; ++n1) spec[item * R * kBigN + (size_t)n1 * kBigN + n2] = v[out_reg<R>(n1)];
+}
+
+// Pass A of the chirp multiply + inverse transform: grid M * nblk * nd * R workgroups,
+// logical id ((p nblk + blk) nd + d) R + k1 (XCD-remapped).
+template <int R>
+__global__ __launch_bounds__(Geo<kBigLog>::T) void k_dedisperse_big_a(DedispArgs a, float2* __restrict__ tbuf) {
+  using G = Geo<kBigLog>;
+  extern __shared__ float lds[];
+  const int t = threadIdx.x;
+  const int lin = xcd_remap(blockIdx.x, gridDim.x);
+  const int k1 = lin % R;
+  const int item = lin / R;  // ((p nblk + blk) nd + d)
+  const int d = item % a.nd, pb = item / a.nd;
+  const float2* x = a.spec + (size_t)pb * R * kBigN + k1;
+  const float2* h = a.chirp + (size_t)d * R * kBigN + k1;
+  float2 v[G::P];
+  fft_workgroup<kBigLog, +1>(v, lds, t, [&](int i) { return cmul(x[(size_t)R * i], h[(size_t)R * i]); });
+  float2* out = tbuf + ((size_t)item * R + k1) * kBigN + opaque_zero(v[0].x);
+#pragma unroll
+  for (int u = 0; u < G::P / G::RL; ++u)
+#pragma unroll
+    for (int q = 0; q < G::RL; ++q) {
+      const int n2 = t + u * G::T + q * (G::N / G::RL);
+      out[n2] = cmul(v[u * G::RL + out_reg<G::RL>(q)], big_twiddle<R, +1>(n2 * k1));
+    }
+}
+
+// Pass B of the inverse transform + overlap-save discard + output conversion.
+// grid: (2^15 / 256, M * nblk * nd).
+template <int R, int OUT>
+__global__ __launch_bounds__(256) void k_dedisperse_big_b(DedispArgs a, const float2* __restrict__ tbuf) {
+  const int n2 = blockIdx.x * 256 + threadIdx.x;
+  const int item = blockIdx.y;
+  const int d = item % a.nd, pb = item / a.nd;
+  const int blk = pb % a.nblk, p = pb / a.nblk;
+  float2 v[R];
+#pragma unroll
+  for (int k1 = 0; k1 < R; ++k1) v[k1] = tbuf[((size_t)item * R + k1) * kBigN + n2];
+  dft_reg<R, +1>(v);
+  const float scale = (OUT == 0) ? 1.f : *a.scale;
+  typedef typename YType<OUT>::T YT;
+  YT* y = reinterpret_cast<YT*>(a.y) + ((size_t)d * a.n_ant + p) * a.y_stride + (size_t)blk * a.valid;
+#pragma unroll
+  for (int n1 = 0; n1 < R; ++n1) {
+    const int n = n1 * kBigN + n2;
+    if (n >= a.lead && n < a.lead + a.valid) y[n - a.lead] = convert_y<OUT>(v[out_reg<R>(n1)], scale);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -390,6 +495,168 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
       const float re = gram[lo * C::GP + hi] + gram[(M + lo) * C::GP + M + hi];
       const float im = gram[hi * C::GP + M + lo] - gram[lo * C::GP + M + hi];
       out[b] = make_float2(re * inv, (i <= j ? im : -im) * inv);
+    }
+  }
+}
+
+// Correlator for large arrays: the antennas are cut into blocks of 64; one
+// workgroup computes, for one (DM, dump), the 64 x 64 antenna block pair (I, J),
+// I <= J, as 4 x 4 complex 16 x 16 tiles, each from four real products on MFMA:
+//   Re V = Yr_I Yr_J^T + Yi_I Yi_J^T,   Im V = Yi_I Yr_J^T - Yr_I Yi_J^T
+// (FP32 form: every product as hi*hi + hi*lo + lo*hi of binary16 halves).  Wave w
+// owns row tile w of block I against the four column tiles of block J, so its
+// block-I fragments are read once per k-step.  Writes V_ij for i <= j < M only.
+// grid: n_dumps * nd * NB (NB + 1) / 2 workgroups (NB = ceil(M / 64)), 256 threads.
+constexpr int kBlkAnt = 64;
+
+template <int T> struct NegFrag;
+template <> struct NegFrag<0> {
+  __device__ static half8 neg(half8 v) { return -v; }
+};
+template <> struct NegFrag<1> {
+  __device__ static half8 neg(half8 v) { return -v; }
+};
+template <> struct NegFrag<2> {
+  __device__ static long neg(long v) { return v ^ (long)0x8080808080808080LL; }  // flip the 8 sign bits
+};
+
+template <int T>
+__global__ __launch_bounds__(256) void k_correlate_blocks(CorrArgs a) {
+  using In = CorrIn<T>;
+  typedef typename In::E E;
+  typedef typename In::Pair Pair;
+  typedef typename std::conditional<T == 2, long, half8>::type Frag;
+  constexpr int ROWS = 4 * kBlkAnt;  // Re I, Im I, Re J, Im J
+  constexpr int KP = kCorrKC + 16 / (int)sizeof(E);
+  constexpr int PLANE = ROWS * KP;
+  constexpr int PPT = (2 * kBlkAnt * (kCorrKC / 2)) / 256;  // sample pairs per thread per chunk
+  __shared__ E at[(T == 0 ? 2 : 1) * PLANE];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int M = a.n_ant, L = a.dump_len;
+  const int nb = (M + kBlkAnt - 1) / kBlkAnt, npair = nb * (nb + 1) / 2;
+  int lin = blockIdx.x;
+  int pr = lin % npair;
+  lin /= npair;
+  const int d = lin % a.nd, m = lin / a.nd;
+  int I = 0;
+  while (pr >= nb - I) { pr -= nb - I; ++I; }
+  const int J = I + pr;
+  const float s_in = *a.scale;
+
+  floatx4 are[4], aim[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) are[q] = aim[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  const typename In::Y* y = reinterpret_cast<const typename In::Y*>(a.y) + (size_t)d * M * a.y_stride + (size_t)m * L;
+  // thread e -> (local antenna la in [0, 128): 0..63 block I, 64..127 block J; sample pair)
+  auto ant_of = [&](int la) { return la < kBlkAnt ? I * kBlkAnt + la : J * kBlkAnt + (la - kBlkAnt); };
+  auto load = [&](int k0, Pair* buf) {
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int e = tid + 256 * i;
+      const int la = e / (kCorrKC / 2), k = k0 + 2 * (e % (kCorrKC / 2));
+      const int p = ant_of(la);
+      Pair v{};
+      if (p < M) {
+        const typename In::Y* row = y + (size_t)p * a.y_stride + k;
+        if (k + 1 < L && ((((size_t)(d * M + p) * a.y_stride + (size_t)m * L + k) & 1) == 0)) {
+          v = *reinterpret_cast<const Pair*>(row);
+        } else {
+          typename In::Y s0{}, s1{};
+          if (k < L) s0 = row[0];
+          if (k + 1 < L) s1 = row[1];
+          typename In::Y tmp[2] = {s0, s1};
+          v = *reinterpret_cast<const Pair*>(tmp);
+        }
+      }
+      buf[i] = v;
+    }
+  };
+  auto row_re = [](int la) { return la < kBlkAnt ? la : 2 * kBlkAnt + (la - kBlkAnt); };
+  auto stage = [&](const Pair* buf) {
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int e = tid + 256 * i;
+      const int la = e / (kCorrKC / 2), k = 2 * (e % (kCorrKC / 2));
+      const int rr = row_re(la), ri = rr + kBlkAnt;
+      store_pair<T, PLANE>(at, rr * KP + k, rr * KP + k + 1, ri * KP + k, ri * KP + k + 1, buf[i], s_in);
+    }
+  };
+  auto frag = [&](int plane, int row, int kr) -> Frag {
+    return *reinterpret_cast<const Frag*>(&at[plane * PLANE + row * KP + kr]);
+  };
+  Pair buf[PPT];
+  load(0, buf);
+  for (int k0 = 0; k0 < L; k0 += kCorrKC) {
+    __syncthreads();
+    stage(buf);
+    __syncthreads();
+    if (k0 + kCorrKC < L) load(k0 + kCorrKC, buf);
+#pragma unroll
+    for (int kk = 0; kk < kCorrKC; kk += In::KSTEP) {
+      const int kr = kk + 8 * (lane >> 4);
+      const int ra = wave * 16 + (lane & 15);  // row tile `wave` of block I
+      if constexpr (T == 0) {
+        const Frag rh = frag(0, ra, kr), rl = frag(1, ra, kr);
+        const Frag ih = frag(0, kBlkAnt + ra, kr), il = frag(1, kBlkAnt + ra, kr);
+        const Frag nrh = NegFrag<T>::neg(rh), nrl = NegFrag<T>::neg(rl);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int rb = 2 * kBlkAnt + q * 16 + (lane & 15);
+          const Frag jrh = frag(0, rb, kr), jrl = frag(1, rb, kr);
+          const Frag jih = frag(0, kBlkAnt + rb, kr), jil = frag(1, kBlkAnt + rb, kr);
+          are[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(rh, jrh, are[q], 0, 0, 0);
+          are[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(rh, jrl, are[q], 0, 0, 0);
+          are[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(rl, jrh, are[q], 0, 0, 0);
+          are[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ih, jih, are[q], 0, 0, 0);
+          are[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ih, jil, are[q], 0, 0, 0);
+          are[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(il, jih, are[q], 0, 0, 0);
+          aim[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ih, jrh, aim[q], 0, 0, 0);
+          aim[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ih, jrl, aim[q], 0, 0, 0);
+          aim[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(il, jrh, aim[q], 0, 0, 0);
+          aim[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(nrh, jih, aim[q], 0, 0, 0);
+          aim[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(nrh, jil, aim[q], 0, 0, 0);
+          aim[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(nrl, jih, aim[q], 0, 0, 0);
+        }
+      } else {
+        const Frag rr = frag(0, ra, kr), ii = frag(0, kBlkAnt + ra, kr);
+        const Frag nr = NegFrag<T>::neg(rr);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int rb = 2 * kBlkAnt + q * 16 + (lane & 15);
+          const Frag jr = frag(0, rb, kr), ji = frag(0, kBlkAnt + rb, kr);
+          if constexpr (T == 1) {
+            are[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(rr, jr, are[q], 0, 0, 0);
+            are[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ii, ji, are[q], 0, 0, 0);
+            aim[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ii, jr, aim[q], 0, 0, 0);
+            aim[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(nr, ji, aim[q], 0, 0, 0);
+          } else {
+            are[q] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(rr, jr, are[q], 0, 0, 0);
+            are[q] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ii, ji, are[q], 0, 0, 0);
+            aim[q] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ii, jr, aim[q], 0, 0, 0);
+            aim[q] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(nr, ji, aim[q], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  const float inv = 1.f / (s_in * s_in);
+  const int64_t dump = a.dump0 + m;
+  float2* out = a.ring + (dump % a.ring_dumps) * a.rec_elems + (int64_t)a.dm_pos[d] * a.nbl;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = I * kBlkAnt + wave * 16 + 4 * (lane >> 4) + r;
+      const int j = J * kBlkAnt + q * 16 + (lane & 15);
+      if (i >= M || j >= M || j < i) continue;
+      const float re = are[q][r] * inv, im = (i == j) ? 0.f : aim[q][r] * inv;  // autos are real
+      if (a.out_mode == 0) {
+        out[(int64_t)i * M - (int64_t)i * (i - 1) / 2 + (j - i)] = make_float2(re, im);
+      } else {
+        out[(int64_t)i * M + j] = make_float2(re, im);
+        if (i != j) out[(int64_t)j * M + i] = make_float2(re, -im);
+      }
     }
   }
 }

@@ -118,7 +118,7 @@ def test_unsupported_and_bad_fft_lengths():
     d.fft_len = fl.ctypes.data_as(ct.POINTER(ct.c_int32))
     h = ct.c_void_p()
     assert ddx.lib().ddx_plan_create(ct.byref(d), ct.byref(h)) == ddx.EINVAL
-    rc, h = _create(n_ant=300)
+    rc, h = _create(n_ant=2000)
     assert rc == ddx.EUNSUPPORTED
 
 

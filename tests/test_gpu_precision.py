@@ -22,33 +22,9 @@ import pytest
 
 import oracle
 import synth
-from gpu_helpers import blockings, norm_error, run_gpu, say, select
+from gpu_helpers import blockings, norm_error, quant_errors as _errors, run_gpu, say, select
 
 pytestmark = pytest.mark.gpu
-
-
-def _errors(cfg, vis, lay, quant, scales, skip_dm0=True):
-    """Normalised errors vs the emulating and the exact oracle, DM-0 trials apart."""
-    m_ant = cfg["volts"].shape[1]
-    bl = blockings(lay)
-    emu, exact, dm0 = [], [], [np.zeros(0)]
-    for c in range(lay["n_chan"]):
-        rq = oracle.run_oracle(cfg["volts"], cfg["chan_freqs"], cfg["f_s"], cfg["dm_lists"], cfg["dump_len"], bl,
-                               quant=quant, scales=scales, chans=[c])
-        rx = oracle.run_oracle(cfg["volts"], cfg["chan_freqs"], cfg["f_s"], cfg["dm_lists"], cfg["dump_len"], bl,
-                               chans=[c])
-        iu, ju = np.triu_indices(m_ant)
-        for (cc, d), vq in rq.items():
-            got = select(vis, lay, cc, d).astype(np.complex128)
-            vx = rx[(cc, d)]
-            auto = vx[:, iu == ju].real
-            norm = np.sqrt(auto[:, iu] * auto[:, ju])
-            if skip_dm0 and cfg["dm_lists"][cc][d] == 0:
-                dm0.append((np.abs(got - vx) / norm).ravel())
-                continue
-            emu.append((np.abs(got - vq) / norm).ravel())
-            exact.append((np.abs(got - vx) / norm).ravel())
-    return np.concatenate(emu), np.concatenate(exact), np.concatenate(dm0)
 
 
 @pytest.mark.parametrize("quant", ["f16", "e4m3"])
