@@ -150,8 +150,9 @@ def correlate_dumps(y, dump_len):
     """
     m_ant, s = y.shape
     nd = s // dump_len
-    yy = y[:, :nd * dump_len].reshape(m_ant, nd, dump_len)
-    return np.einsum("imn,jmn->mij", yy, np.conj(yy))
+    # per dump m the L-sample block Y_m [M, L]; V[m] = Y_m Y_m^H (a matrix product)
+    ym = y[:, :nd * dump_len].reshape(m_ant, nd, dump_len).transpose(1, 0, 2)
+    return ym @ np.conj(ym).transpose(0, 2, 1)
 
 
 def packed_index(i, j, m_ant):
