@@ -79,6 +79,13 @@ typedef struct ddx_desc {
   size_t max_device_bytes;     /* cap on plan-owned device memory, 0 = none */
   int32_t out_mode;            /* DDX_OUT_* */
   const float* chan_scale;     /* [C] power-of-two correlator-input scales, or NULL = rule below */
+  /* Schedule (all 0 = automatic; see ddx_process_block for the work list): */
+  int32_t wave_units;          /* (channel, DM, block) units per wave, >= 0 */
+  int32_t dm_group;            /* DMs of one channel run back to back on each block, >= 0 */
+  /* Dump records (see ddx_fetch_visibilities): */
+  int32_t compact_records;     /* 0: every (channel, DM) in every record; 1: only the active ones */
+  int32_t max_record_pairs;    /* compact records: capacity in (channel, DM) pairs, 0 = all */
+  int64_t ring_dumps;          /* device dump ring capacity in dumps, 0 = enough for any call */
 } ddx_desc;
 
 /* Scale rule when chan_scale is NULL (all correlator formats; the scale keeps
@@ -100,17 +107,23 @@ typedef struct ddx_layout {
   const int32_t* valid;        /* [C] V_c: outputs kept per block, a multiple of L */
   const int32_t* lead;         /* [C] block b reads samples [b V_c - lead_c, b V_c - lead_c + N_c) */
   const int32_t* n_dm;         /* [C] D_c trial DMs */
-  const int64_t* dm_offset;    /* [C+1] prefix sums of D_c: position of (c, d) in a dump record */
+  const int64_t* dm_offset;    /* [C+1] prefix sums of D_c: index of (c, d) in the per-DM tables */
   const double* dm;            /* [dm_offset[C]] trial DMs, channel-major */
   const double* delay_s;       /* [dm_offset[C]] K DM / f_c^2: channel-centre delay behind infinite frequency */
   const int64_t* shift;        /* [dm_offset[C]] rint(K DM (f_c^-2 - f_top^-2) f_s): samples behind the highest channel */
   const float* scale;          /* [C] correlator-input scale s_c */
-  int64_t record_elems;        /* complex64 values per dump record = dm_offset[C] * n_baselines */
+  const int32_t* record_pos;   /* [dm_offset[C]] slot of (c, d) in a dump record, -1 if not stored */
+  int64_t record_pairs;        /* (channel, DM) slots per dump record */
+  int64_t record_elems;        /* complex64 values per dump record = record_pairs * n_baselines */
   int64_t samples_in;          /* samples accepted so far per (channel, antenna) */
   int64_t dumps_ready;         /* dumps complete in every channel */
   int64_t dumps_fetched;       /* dumps already returned by ddx_fetch_visibilities */
   int64_t ring_dumps;          /* capacity of the device dump ring */
   size_t device_bytes;         /* plan-owned device memory */
+  int32_t wave_units;          /* units per wave in use */
+  int32_t dm_group;            /* DMs per block group in use */
+  int32_t compact_records;     /* as in the descriptor */
+  int32_t pad;
 } ddx_layout;
 
 /* Create a plan from a descriptor (copied; the caller's arrays may be freed).
@@ -127,16 +140,20 @@ int ddx_plan_create(const ddx_desc* desc, ddx_plan** out);
  *     centre and the bottom edge K DM ((f_c - f_s/2)^-2 - f_c^-2) after it
  *     (Eq. dmdelay);
  *   - N_c = the descriptor's FFT length, or the smallest power of two >= 256
- *     keeping at least half of each block;
+ *     keeping at least half of each block (N_c <= 2^18);
  *   - V_c = L floor((N_c - 2 A_c) / L), lead_c = floor((N_c - V_c)/2);
  * builds the FP64 tables and allocates device memory.  Returns ESTATE after the
- * first ddx_process_block, EUNSUPPORTED for N_c > 32768, EINVAL if V_c < L. */
+ * first ddx_process_block, EUNSUPPORTED for N_c > 2^18, EINVAL if V_c < L. */
 int ddx_set_dm_trials(ddx_plan* plan, int32_t chan, const double* dm_pc_cm3, int32_t n_dm);
 
 /* Restrict dedispersion and correlation of channel chan (-1 = all) to the DMs
  * with mask[d] != 0 (mask has D_c entries; NULL = all active).  Blocking is
  * unchanged, so active DMs give results bitwise equal to a full sweep.
- * Inactive DMs' visibilities are written as zeros.  Allowed between calls. */
+ * Full records: inactive DMs' visibilities are written as zeros; allowed
+ * between calls.  Compact records: the record holds the active (channel, DM)
+ * pairs only, channel-major in DM order (record_pos in the layout); the mask
+ * may change only when every dump produced so far has been fetched (ESTATE
+ * otherwise), and EINVAL if more pairs than max_record_pairs would be active. */
 int ddx_set_active_dms(ddx_plan* plan, int32_t chan, const uint8_t* mask);
 
 /* Export the blocking, tables and stream counters.  Pointers refer to
@@ -161,7 +178,17 @@ int ddx_get_layout(const ddx_plan* plan, ddx_layout* out);
  * and for each complete dump m (samples [m L, (m+1) L)):
  *   V_ij = sum_n y_i[n] conj(y_j[n])   (raw sum, input units squared; the
  *   correlator works on s_c y -- rounded for F16/E4M3 -- and divides by s_c^2).
- * A trailing partial dump is dropped.  Errors: EINVAL (n < 0, n >
+ * A trailing partial dump is dropped.
+ *
+ * Schedule: one call lists its work for all channels at once and copies the
+ * lists to the device: the (channel, block) items of the forward transforms
+ * (one launch per transform length), and the units (channel, active DM, block)
+ * in the order channel, DM group, block, DM.  Units are cut into waves of
+ * wave_units (a wave holds one transform length); each wave is one chirp launch,
+ * one dedispersion launch (two for N_c > 2^15) and one correlator launch over
+ * all its units' dumps, whatever channels and DMs they belong to.
+ *
+ * Errors: EINVAL (n < 0, n >
  * max_block_samples, NULL volts with n > 0), ESTATE (no DM trials, stream
  * flushed), EFULL (the dump ring would overwrite unfetched dumps: fetch first),
  * EDEVICE. */
@@ -171,7 +198,8 @@ int ddx_process_block(ddx_plan* plan, const void* d_volts, int64_t n, int32_t fl
  * or host memory, caller-owned), enqueued on hip_stream (a host destination is
  * complete when the stream is synchronised).  Layout: [dump][channel][dm][baseline]
  * complex64 (float re, float im); the record of one dump holds record_elems
- * values, channel c / DM d at (dm_offset[c] + d) * n_baselines.
+ * values, channel c / DM d at record_pos[dm_offset[c] + d] * n_baselines (full
+ * records: record_pos = dm_offset[c] + d).
  * *first_dump = absolute index of the first dump returned, *n_dumps = count.
  * If cap_bytes is too small returns ESIZE with *n_dumps = the count required
  * and copies nothing.  out may be NULL when no dump is ready. */

@@ -30,6 +30,8 @@ class Desc(ct.Structure):
         ("corr_dtype", ct.c_int32), ("dump_len", ct.c_int32), ("fft_len", ct.POINTER(ct.c_int32)),
         ("k_dm", ct.c_double), ("max_block_samples", ct.c_int64), ("max_device_bytes", ct.c_size_t),
         ("out_mode", ct.c_int32), ("chan_scale", ct.POINTER(ct.c_float)),
+        ("wave_units", ct.c_int32), ("dm_group", ct.c_int32), ("compact_records", ct.c_int32),
+        ("max_record_pairs", ct.c_int32), ("ring_dumps", ct.c_int64),
     ]
 
 
@@ -42,8 +44,10 @@ class Layout(ct.Structure):
         ("valid", ct.POINTER(ct.c_int32)), ("lead", ct.POINTER(ct.c_int32)), ("n_dm", ct.POINTER(ct.c_int32)),
         ("dm_offset", ct.POINTER(ct.c_int64)), ("dm", ct.POINTER(ct.c_double)),
         ("delay_s", ct.POINTER(ct.c_double)), ("shift", ct.POINTER(ct.c_int64)), ("scale", ct.POINTER(ct.c_float)),
+        ("record_pos", ct.POINTER(ct.c_int32)), ("record_pairs", ct.c_int64),
         ("record_elems", ct.c_int64), ("samples_in", ct.c_int64), ("dumps_ready", ct.c_int64),
         ("dumps_fetched", ct.c_int64), ("ring_dumps", ct.c_int64), ("device_bytes", ct.c_size_t),
+        ("wave_units", ct.c_int32), ("dm_group", ct.c_int32), ("compact_records", ct.c_int32), ("pad", ct.c_int32),
     ]
 
 
@@ -125,7 +129,8 @@ class Plan:
     """One ddx plan (see include/ddx.h for the semantics of every call)."""
 
     def __init__(self, n_ant, chan_freqs, samp_rate, dump_len, max_block_samples, *, sideband=1, in_dtype="ci8",
-                 corr_dtype="f32", fft_len=None, k_dm=0.0, max_device_bytes=0, out_mode="packed", chan_scale=None):
+                 corr_dtype="f32", fft_len=None, k_dm=0.0, max_device_bytes=0, out_mode="packed", chan_scale=None,
+                 wave_units=0, dm_group=0, compact_records=False, max_record_pairs=0, ring_dumps=0):
         L = lib()
         fc = np.ascontiguousarray(chan_freqs, dtype=np.float64)
         self._fc = fc
@@ -148,6 +153,11 @@ class Plan:
         if chan_scale is not None:
             self._scale = np.ascontiguousarray(np.broadcast_to(chan_scale, fc.shape), dtype=np.float32)
             d.chan_scale = self._scale.ctypes.data_as(ct.POINTER(ct.c_float))
+        d.wave_units = int(wave_units)
+        d.dm_group = int(dm_group)
+        d.compact_records = 1 if compact_records else 0
+        d.max_record_pairs = int(max_record_pairs)
+        d.ring_dumps = int(ring_dumps)
         h = ct.c_void_p()
         rc = L.ddx_plan_create(ct.byref(d), ct.byref(h))
         if rc != OK:
@@ -191,9 +201,11 @@ class Plan:
             "valid": arr(lay.valid, C, np.int64), "lead": arr(lay.lead, C, np.int64),
             "n_dm": arr(lay.n_dm, C, np.int64), "dm_offset": off, "dm": arr(lay.dm, nd, np.float64),
             "delay_s": arr(lay.delay_s, nd, np.float64), "shift": arr(lay.shift, nd, np.int64),
-            "scale": arr(lay.scale, C, np.float32), "record_elems": lay.record_elems,
+            "scale": arr(lay.scale, C, np.float32), "record_pos": arr(lay.record_pos, nd, np.int64),
+            "record_pairs": lay.record_pairs, "record_elems": lay.record_elems,
             "samples_in": lay.samples_in, "dumps_ready": lay.dumps_ready, "dumps_fetched": lay.dumps_fetched,
-            "ring_dumps": lay.ring_dumps, "device_bytes": lay.device_bytes,
+            "ring_dumps": lay.ring_dumps, "device_bytes": lay.device_bytes, "wave_units": lay.wave_units,
+            "dm_group": lay.dm_group, "compact_records": lay.compact_records,
         }
 
     def process_block(self, volts, flush=False, stream=None):

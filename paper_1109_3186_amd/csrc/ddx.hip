@@ -1,4 +1,4 @@
-// Host side of the ddx C ABI: plan state, blocking, tables, launches.
+// Host side of the ddx C ABI: plan state, blocking, tables, work lists, launches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,10 +17,12 @@
 namespace {
 
 constexpr double kDefaultKdm = 4.148808e15;
-constexpr int kMaxLogN = 15;
+constexpr int kMaxLogN = 18;        // two-pass transforms above 2^15
 constexpr int kMinLogN = 8;
 constexpr int kMaxStackedAnt = 64;  // stacked-row Gram kernel up to 2 M = 128 rows
 constexpr int kMaxCorrAnt = 1024;   // antenna-block kernel beyond
+constexpr int kDefaultDmGroup = 16;
+constexpr size_t kAutoYBytes = size_t(2) << 30;  // dedispersed voltages of one wave, automatic schedule
 // Scale rule targets: E4M3 puts sigma near 32, so even after the power-of-two
 // rounding (up to x sqrt 2) about 10 sigma, and the int8 extreme 127 at sigma 16,
 // stay below its largest finite value 448; binary16 puts sigma near 4 (far from
@@ -41,6 +43,22 @@ struct Chan {
   int64_t hist_start = 0;  // absolute index of history element 0
 };
 
+// Host copies of one call's work lists, packed into one upload.
+struct Wave {
+  int logn;
+  size_t u0, nu;      // units [u0, u0 + nu)
+  size_t c0, nc;      // chirp items [c0, c0 + nc)
+  int max_dumps;
+  int64_t spectra;    // distinct (channel, block) spectra the wave reads
+  int64_t y_samples;  // dedispersed samples it writes (all antennas)
+  int64_t dumps;      // (unit, dump) pairs it correlates
+  double fft_n;       // N of its transforms
+};
+struct FwdLaunch {
+  int logn;
+  size_t i0, n;       // forward items [i0, i0 + n)
+};
+
 }  // namespace
 
 struct ddx_plan {
@@ -50,8 +68,9 @@ struct ddx_plan {
   int64_t max_block = 0;
   size_t max_bytes = 0;
   std::vector<int> fft_req;
-  std::vector<float> scale_req;
   bool have_scale = false;
+  int wave_req = 0, group_req = 0, compact = 0, max_pairs_req = 0;
+  int64_t ring_req = 0;
   std::vector<Chan> ch;
   int nbl = 0;
   // derived
@@ -60,7 +79,9 @@ struct ddx_plan {
   std::vector<int64_t> dm_off, lay_shift;
   std::vector<double> lay_dm, lay_delay, lay_fc;
   std::vector<float> lay_scale;
-  int64_t rec_elems = 0;
+  std::vector<int32_t> rec_pos;  // [sum D_c] record slot of (c, d), -1 if not stored
+  int64_t rec_pairs = 0, rec_elems = 0, cap_pairs = 0;
+  int wave_units = 0, dm_group = 0;
   // stream
   int64_t recv = 0;
   int64_t dumps_fetched = 0;
@@ -70,20 +91,26 @@ struct ddx_plan {
   void* hist[2] = {nullptr, nullptr};
   int hist_cur = 0;
   int64_t hist_cap = 0;
-  float2* spec = nullptr;
+  float2* spec = nullptr;      // spectra of every block one call runs, all channels
   size_t spec_elems = 0;
-  float2* chirp = nullptr;
-  void* ybuf = nullptr;
+  float2* tb = nullptr;        // intermediate rows of the two-pass transforms
+  size_t tb_elems = 0;
+  float2* chirp = nullptr;     // [wave_units][max N]
+  void* ybuf = nullptr;        // [wave_units][M][y_stride]
   int64_t y_stride = 0;
-  int dm_group = 8;
   float2* ring = nullptr;
   int64_t ring_dumps = 0;
-  double* gtab = nullptr;        // [sum N_c] FP64 g_c[k]
+  double* gtab = nullptr;      // [sum N_c] FP64 g_c[k]
   std::vector<int64_t> gtab_off;
-  double* kdm_dev = nullptr;     // [sum D_c] K DM for the active list (compacted per channel)
-  int32_t* pos_dev = nullptr;    // [sum D_c] record positions, active first then inactive
+  int32_t* slots_dev = nullptr;  // [sum D_c] per channel: active slots, then inactive slots
   std::vector<int> n_active;
   float* scale_dev = nullptr;    // [C]
+  char* items_dev = nullptr;     // work lists of one call
+  size_t items_cap = 0;
+  char* stage[2] = {nullptr, nullptr};  // pinned host staging of the work lists
+  hipEvent_t stage_ev[2] = {nullptr, nullptr};
+  bool stage_used[2] = {false, false};
+  int stage_cur = 0;
   // DM-time tiles: scratch grown on demand
   float* tile_power = nullptr;
   size_t tile_power_cap = 0;
@@ -142,15 +169,28 @@ int dev_alloc(ddx_plan* p, void** ptr, size_t bytes) {
 }
 
 void free_device(ddx_plan* p) {
+  for (int i = 0; i < 2; ++i) {
+    if (p->stage_ev[i]) {
+      (void)hipEventSynchronize(p->stage_ev[i]);
+      (void)hipEventDestroy(p->stage_ev[i]);
+      p->stage_ev[i] = nullptr;
+    }
+    if (p->stage[i]) (void)hipHostFree(p->stage[i]);
+    p->stage[i] = nullptr;
+    p->stage_used[i] = false;
+  }
   for (void* a : p->allocs) (void)hipFree(a);
   p->allocs.clear();
   p->dev_bytes = 0;
   p->hist[0] = p->hist[1] = nullptr;
-  p->spec = p->chirp = p->ring = nullptr;
+  p->spec = p->tb = p->chirp = p->ring = nullptr;
+  p->spec_elems = p->tb_elems = 0;
   p->ybuf = nullptr;
-  p->gtab = p->kdm_dev = nullptr;
-  p->pos_dev = nullptr;
+  p->gtab = nullptr;
+  p->slots_dev = nullptr;
   p->scale_dev = nullptr;
+  p->items_dev = nullptr;
+  p->items_cap = 0;
   p->tile_power = nullptr;
   p->tile_power_cap = 0;
   p->tile_prefix = nullptr;
@@ -199,9 +239,9 @@ template <int LOGN>
 size_t fft_lds_bytes() { return sizeof(float) * ddx::Geo<LOGN>::LDS_FLOATS; }
 
 template <int LOGN>
-hipError_t launch_forward_n(int in_dtype, const ddx::FwdArgs& a, hipStream_t s) {
+hipError_t launch_forward_n(int in_dtype, const ddx::FwdArgs& a, int n_items, hipStream_t s) {
   using G = ddx::Geo<LOGN>;
-  dim3 grid(a.nblk * a.n_ant), block(G::T);
+  dim3 grid(n_items * a.n_ant), block(G::T);
   if (in_dtype == DDX_IN_CI8)
     hipLaunchKernelGGL((ddx::k_forward<LOGN, 0>), grid, block, fft_lds_bytes<LOGN>(), s, a);
   else
@@ -212,7 +252,7 @@ hipError_t launch_forward_n(int in_dtype, const ddx::FwdArgs& a, hipStream_t s) 
 template <int LOGN>
 hipError_t launch_dedisp_n(int corr_dtype, const ddx::DedispArgs& a, hipStream_t s) {
   using G = ddx::Geo<LOGN>;
-  dim3 grid(a.n_ant * a.nblk * a.nd), block(G::T);
+  dim3 grid(a.n_ant * a.n_units), block(G::T);
   if (corr_dtype == DDX_CORR_F32)
     hipLaunchKernelGGL((ddx::k_dedisperse<LOGN, 0>), grid, block, fft_lds_bytes<LOGN>(), s, a);
   else if (corr_dtype == DDX_CORR_F16)
@@ -222,18 +262,36 @@ hipError_t launch_dedisp_n(int corr_dtype, const ddx::DedispArgs& a, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_forward(int logn, int in_dtype, const ddx::FwdArgs& a, hipStream_t s) {
+hipError_t launch_forward(int logn, int in_dtype, const ddx::FwdArgs& a, int n_items, hipStream_t s) {
   switch (logn) {
-    case 8: return launch_forward_n<8>(in_dtype, a, s);
-    case 9: return launch_forward_n<9>(in_dtype, a, s);
-    case 10: return launch_forward_n<10>(in_dtype, a, s);
-    case 11: return launch_forward_n<11>(in_dtype, a, s);
-    case 12: return launch_forward_n<12>(in_dtype, a, s);
-    case 13: return launch_forward_n<13>(in_dtype, a, s);
-    case 14: return launch_forward_n<14>(in_dtype, a, s);
-    case 15: return launch_forward_n<15>(in_dtype, a, s);
+    case 8: return launch_forward_n<8>(in_dtype, a, n_items, s);
+    case 9: return launch_forward_n<9>(in_dtype, a, n_items, s);
+    case 10: return launch_forward_n<10>(in_dtype, a, n_items, s);
+    case 11: return launch_forward_n<11>(in_dtype, a, n_items, s);
+    case 12: return launch_forward_n<12>(in_dtype, a, n_items, s);
+    case 13: return launch_forward_n<13>(in_dtype, a, n_items, s);
+    case 14: return launch_forward_n<14>(in_dtype, a, n_items, s);
+    case 15: return launch_forward_n<15>(in_dtype, a, n_items, s);
   }
   return hipErrorInvalidValue;
+}
+
+// Two-pass forward transform of n_items items whose spectra and intermediate
+// rows are consecutive from items[0].spec and tb offset 0.
+hipError_t launch_forward_big(int logn, int in_dtype, ddx::FwdArgs a, const ddx::FwdItem* first_host, int n_items,
+                              float2* tb, hipStream_t s) {
+  const int logr = logn - ddx::kBigLog;
+  const dim3 gpre(ddx::kBigN / 256, n_items * a.n_ant);
+  if (in_dtype == DDX_IN_CI8)
+    hipLaunchKernelGGL(ddx::k_forward_big_pre<0>, gpre, dim3(256), 0, s, a, tb, logr);
+  else
+    hipLaunchKernelGGL(ddx::k_forward_big_pre<1>, gpre, dim3(256), 0, s, a, tb, logr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned rows = (unsigned)((size_t)n_items * a.n_ant << logr);
+  hipLaunchKernelGGL(ddx::k_fft_rows, dim3(rows), dim3(ddx::Geo<ddx::kBigLog>::T), fft_lds_bytes<ddx::kBigLog>(), s,
+                     (const float2*)tb, a.spec + first_host->spec);
+  return hipGetLastError();
 }
 
 hipError_t launch_dedisp(int logn, int corr_dtype, const ddx::DedispArgs& a, hipStream_t s) {
@@ -247,39 +305,51 @@ hipError_t launch_dedisp(int logn, int corr_dtype, const ddx::DedispArgs& a, hip
     case 14: return launch_dedisp_n<14>(corr_dtype, a, s);
     case 15: return launch_dedisp_n<15>(corr_dtype, a, s);
   }
+  if (logn <= kMaxLogN) {
+    const unsigned ga = (unsigned)((size_t)a.n_units * a.n_ant << a.logr);
+    hipLaunchKernelGGL(ddx::k_dedisperse_big_a, dim3(ga), dim3(ddx::Geo<ddx::kBigLog>::T),
+                       fft_lds_bytes<ddx::kBigLog>(), s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 gb(ddx::kBigN / 256, a.n_units * a.n_ant);
+    if (corr_dtype == DDX_CORR_F32) hipLaunchKernelGGL(ddx::k_dedisperse_big_b<0>, gb, dim3(256), 0, s, a);
+    else if (corr_dtype == DDX_CORR_F16) hipLaunchKernelGGL(ddx::k_dedisperse_big_b<1>, gb, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(ddx::k_dedisperse_big_b<2>, gb, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   return hipErrorInvalidValue;
 }
 
 template <int NT>
-hipError_t launch_corr_nt(int corr_dtype, const ddx::CorrArgs& a, hipStream_t s) {
-  const dim3 g(a.n_dumps * a.nd), b(256);
+hipError_t launch_corr_nt(int corr_dtype, const ddx::CorrArgs& a, int n_units, hipStream_t s) {
+  const dim3 g(n_units * a.max_dumps), b(256);
   if (corr_dtype == DDX_CORR_F32) hipLaunchKernelGGL((ddx::k_correlate<NT, 0>), g, b, 0, s, a);
   else if (corr_dtype == DDX_CORR_F16) hipLaunchKernelGGL((ddx::k_correlate<NT, 1>), g, b, 0, s, a);
   else hipLaunchKernelGGL((ddx::k_correlate<NT, 2>), g, b, 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_corr_blocks(int corr_dtype, const ddx::CorrArgs& a, hipStream_t s) {
+hipError_t launch_corr_blocks(int corr_dtype, const ddx::CorrArgs& a, int n_units, hipStream_t s) {
   const int nb = (a.n_ant + ddx::kBlkAnt - 1) / ddx::kBlkAnt;
-  const dim3 g(a.n_dumps * a.nd * (nb * (nb + 1) / 2)), b(256);
+  const dim3 g(n_units * a.max_dumps * (nb * (nb + 1) / 2)), b(256);
   if (corr_dtype == DDX_CORR_F32) hipLaunchKernelGGL((ddx::k_correlate_blocks<0>), g, b, 0, s, a);
   else if (corr_dtype == DDX_CORR_F16) hipLaunchKernelGGL((ddx::k_correlate_blocks<1>), g, b, 0, s, a);
   else hipLaunchKernelGGL((ddx::k_correlate_blocks<2>), g, b, 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_corr(int corr_dtype, const ddx::CorrArgs& a, hipStream_t s) {
-  if (a.n_ant > kMaxStackedAnt) return launch_corr_blocks(corr_dtype, a, s);
+hipError_t launch_corr(int corr_dtype, const ddx::CorrArgs& a, int n_units, hipStream_t s) {
+  if (a.n_ant > kMaxStackedAnt) return launch_corr_blocks(corr_dtype, a, n_units, s);
   const int nt = (2 * a.n_ant + 15) / 16;
   switch (nt) {
-    case 1: return launch_corr_nt<1>(corr_dtype, a, s);
-    case 2: return launch_corr_nt<2>(corr_dtype, a, s);
-    case 3: return launch_corr_nt<3>(corr_dtype, a, s);
-    case 4: return launch_corr_nt<4>(corr_dtype, a, s);
-    case 5: return launch_corr_nt<5>(corr_dtype, a, s);
-    case 6: return launch_corr_nt<6>(corr_dtype, a, s);
-    case 7: return launch_corr_nt<7>(corr_dtype, a, s);
-    case 8: return launch_corr_nt<8>(corr_dtype, a, s);
+    case 1: return launch_corr_nt<1>(corr_dtype, a, n_units, s);
+    case 2: return launch_corr_nt<2>(corr_dtype, a, n_units, s);
+    case 3: return launch_corr_nt<3>(corr_dtype, a, n_units, s);
+    case 4: return launch_corr_nt<4>(corr_dtype, a, n_units, s);
+    case 5: return launch_corr_nt<5>(corr_dtype, a, n_units, s);
+    case 6: return launch_corr_nt<6>(corr_dtype, a, n_units, s);
+    case 7: return launch_corr_nt<7>(corr_dtype, a, n_units, s);
+    case 8: return launch_corr_nt<8>(corr_dtype, a, n_units, s);
   }
   return hipErrorInvalidValue;
 }
@@ -310,7 +380,7 @@ hipError_t timed(ddx_plan* p, hipStream_t s, int kind, double flops, double byte
   return e;
 }
 
-double fft_flops(int n) { return 5.0 * n * std::log2((double)n); }
+double fft_flops(double n) { return 5.0 * n * std::log2(n); }
 
 // ---- layout tables ------------------------------------------------------------------------
 
@@ -343,64 +413,106 @@ void build_layout(ddx_plan* p) {
       p->lay_shift.push_back((int64_t)std::nearbyint(p->kdm * d * (inv - invt) * p->fs));
     }
   }
-  p->rec_elems = p->dm_off[p->C] * p->nbl;
 }
 
-// Upload the active-DM lists (K DM compacted, active first) of every channel.
+// Record slots of the active DMs (compact records: active pairs numbered in
+// order; full records: dm_offset[c] + d) and the per-channel slot table on the
+// device (active slots first, then inactive ones, which k_zero_dm clears).
 int upload_active(ddx_plan* p, hipStream_t s) {
-  std::vector<double> kdm(p->dm_off[p->C]);
-  std::vector<int32_t> pos(p->dm_off[p->C]);
+  const int64_t total = p->dm_off[p->C];
+  std::vector<int32_t> slots(total);
+  p->rec_pos.assign(total, -1);
   p->n_active.assign(p->C, 0);
+  int64_t next = 0;
   for (int i = 0; i < p->C; ++i) {
     Chan& c = p->ch[i];
-    int64_t o = p->dm_off[i];
+    const int64_t o = p->dm_off[i];
     int na = 0;
-    for (size_t d = 0; d < c.dm.size(); ++d)
-      if (c.active[d]) { kdm[o + na] = p->kdm * c.dm[d]; pos[o + na] = (int32_t)(o + d); ++na; }
+    for (size_t d = 0; d < c.dm.size(); ++d) {
+      if (!c.active[d]) continue;
+      const int32_t pos = (int32_t)(p->compact ? next++ : o + (int64_t)d);
+      p->rec_pos[o + d] = pos;
+      slots[o + na++] = pos;
+    }
     int k = na;
     for (size_t d = 0; d < c.dm.size(); ++d)
-      if (!c.active[d]) { kdm[o + k] = p->kdm * c.dm[d]; pos[o + k] = (int32_t)(o + d); ++k; }
+      if (!c.active[d]) {
+        if (!p->compact) p->rec_pos[o + d] = (int32_t)(o + d);
+        slots[o + k++] = (int32_t)(o + d);
+      }
     p->n_active[i] = na;
   }
-  HIPCHECK(p, hipMemcpyAsync(p->kdm_dev, kdm.data(), kdm.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  HIPCHECK(p, hipMemcpyAsync(p->pos_dev, pos.data(), pos.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  p->rec_pairs = p->compact ? next : total;
+  p->rec_elems = p->rec_pairs * p->nbl;
+  HIPCHECK(p, hipMemcpyAsync(p->slots_dev, slots.data(), slots.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   HIPCHECK(p, hipStreamSynchronize(s));
   return DDX_OK;
 }
+
+// Largest number of blocks of channel c that one call can run: the history (< N)
+// plus the chunk, plus one for rounding.
+int64_t max_blocks(const ddx_plan* p, const Chan& c) { return (p->max_block + c.fft_len) / c.valid + 2; }
+
+size_t align_up(size_t n) { return (n + 255) & ~size_t(255); }
 
 int setup_device(ddx_plan* p) {
   free_device(p);
   build_layout(p);
   int rc;
   int maxn = 0, maxv = 0, maxd = 0;
-  int64_t maxblk = 0, sum_n = 0;
+  int64_t sum_n = 0, spec_elems = 0, max_units = 0, max_fwd = 0, max_zero = 0, big_rows = 0;
   for (auto& c : p->ch) {
     maxn = std::max(maxn, c.fft_len);
     maxv = std::max(maxv, c.valid);
     maxd = std::max(maxd, (int)c.dm.size());
     sum_n += c.fft_len;
-    // blocks one call can complete: history (< N) plus the chunk, plus one for rounding
-    maxblk = std::max(maxblk, (p->max_block + c.fft_len) / c.valid + 2);
+    const int64_t nb = max_blocks(p, c);
+    spec_elems += (int64_t)p->M * nb * c.fft_len;
+    max_fwd += nb;
+    max_units += nb * (int64_t)c.dm.size();
+    max_zero += nb * c.valid / p->L + 1;
+    if (c.logn > ddx::kBigLog) big_rows = std::max<int64_t>(big_rows, (int64_t)p->M * c.fft_len);
   }
   p->hist_cap = maxn;
   const size_t ib = in_bytes(p->in_dtype);
   for (int i = 0; i < 2; ++i)
     if ((rc = dev_alloc(p, &p->hist[i], (size_t)p->C * p->M * p->hist_cap * ib))) return rc;
-  int64_t spec_elems = 0;
-  for (auto& c : p->ch) spec_elems = std::max(spec_elems, (int64_t)p->M * ((p->max_block + c.fft_len) / c.valid + 2) * c.fft_len);
   p->spec_elems = (size_t)spec_elems;
   if ((rc = dev_alloc(p, (void**)&p->spec, p->spec_elems * sizeof(float2)))) return rc;
-  if ((rc = dev_alloc(p, (void**)&p->chirp, (size_t)maxd * maxn * sizeof(float2)))) return rc;
-  // dedispersed voltages of one DM group: [dm_group][M][blocks * V]
-  p->y_stride = 0;
-  for (auto& c : p->ch) p->y_stride = std::max(p->y_stride, ((p->max_block + c.fft_len) / c.valid + 2) * c.valid);
-  const size_t per_dm = (size_t)p->M * p->y_stride * y_bytes(p->corr_dtype);
-  p->dm_group = (int)std::max<size_t>(1, std::min<size_t>(16, ((size_t)2 << 30) / std::max<size_t>(per_dm, 1)));
-  p->dm_group = std::min(p->dm_group, maxd);
-  if ((rc = dev_alloc(p, &p->ybuf, per_dm * p->dm_group))) return rc;
-  // dump ring: dumps one call can produce plus what a lagging channel holds back
-  p->ring_dumps = (p->max_block + p->L - 1) / p->L + (2 * (int64_t)maxn + maxv) / p->L + 4;
-  if ((rc = dev_alloc(p, (void**)&p->ring, (size_t)p->ring_dumps * p->rec_elems * sizeof(float2)))) return rc;
+  // schedule: DM group and wave size
+  p->y_stride = maxv;
+  const size_t per_unit = (size_t)p->M * p->y_stride * y_bytes(p->corr_dtype);
+  p->dm_group = p->group_req ? p->group_req : kDefaultDmGroup;
+  p->dm_group = std::max(1, std::min(p->dm_group, maxd));
+  if (p->wave_req) {
+    p->wave_units = p->wave_req;
+  } else {
+    p->wave_units = (int)std::max<size_t>(1, std::min<size_t>(1024, kAutoYBytes / std::max<size_t>(per_unit, 1)));
+  }
+  p->wave_units = (int)std::min<int64_t>(p->wave_units, std::max<int64_t>(max_units, 1));
+  if ((rc = dev_alloc(p, &p->ybuf, per_unit * p->wave_units))) return rc;
+  if ((rc = dev_alloc(p, (void**)&p->chirp, (size_t)p->wave_units * maxn * sizeof(float2)))) return rc;
+  // two-pass transforms: intermediate rows of one wave (dedispersion); the forward
+  // transform runs its items in chunks of the same size
+  p->tb_elems = (size_t)big_rows * p->wave_units;
+  if (p->tb_elems && (rc = dev_alloc(p, (void**)&p->tb, p->tb_elems * sizeof(float2)))) return rc;
+  // dump ring
+  p->cap_pairs = p->compact && p->max_pairs_req ? p->max_pairs_req : p->dm_off[p->C];
+  p->ring_dumps = p->ring_req ? p->ring_req
+                              : (p->max_block + p->L - 1) / p->L + (2 * (int64_t)maxn + maxv) / p->L + 4;
+  if ((rc = dev_alloc(p, (void**)&p->ring, (size_t)p->ring_dumps * p->cap_pairs * p->nbl * sizeof(float2)))) return rc;
+  // work lists of one call
+  p->items_cap = align_up(max_fwd * sizeof(ddx::FwdItem)) + align_up(max_units * sizeof(ddx::UnitItem)) +
+                 align_up(max_units * sizeof(ddx::ChirpItem)) + align_up(max_zero * sizeof(ddx::ZeroItem));
+  if ((rc = dev_alloc(p, (void**)&p->items_dev, p->items_cap))) return rc;
+  for (int i = 0; i < 2; ++i) {
+    if (hipHostMalloc((void**)&p->stage[i], p->items_cap, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      p->stage[i] = nullptr;
+      return fail(p, DDX_ENOMEM, "pinned staging of %zu bytes", p->items_cap);
+    }
+    HIPCHECK(p, hipEventCreateWithFlags(&p->stage_ev[i], hipEventDisableTiming));
+  }
   // FP64 tables
   p->gtab_off.assign(p->C + 1, 0);
   std::vector<double> g(sum_n);
@@ -414,11 +526,16 @@ int setup_device(ddx_plan* p) {
     }
   }
   if ((rc = dev_alloc(p, (void**)&p->gtab, g.size() * sizeof(double)))) return rc;
-  if ((rc = dev_alloc(p, (void**)&p->kdm_dev, p->dm_off[p->C] * sizeof(double)))) return rc;
-  if ((rc = dev_alloc(p, (void**)&p->pos_dev, p->dm_off[p->C] * sizeof(int32_t)))) return rc;
+  if ((rc = dev_alloc(p, (void**)&p->slots_dev, p->dm_off[p->C] * sizeof(int32_t)))) return rc;
   if ((rc = dev_alloc(p, (void**)&p->scale_dev, p->C * sizeof(float)))) return rc;
   HIPCHECK(p, hipMemcpy(p->gtab, g.data(), g.size() * sizeof(double), hipMemcpyHostToDevice));
   HIPCHECK(p, hipMemcpy(p->scale_dev, p->lay_scale.data(), p->C * sizeof(float), hipMemcpyHostToDevice));
+  if (p->compact) {
+    int64_t na = 0;
+    for (auto& c : p->ch) for (uint8_t a : c.active) na += a;
+    if (na > p->cap_pairs)
+      for (auto& c : p->ch) std::fill(c.active.begin(), c.active.end(), 0);  // the caller selects a subset
+  }
   if ((rc = upload_active(p, nullptr))) return rc;
   return DDX_OK;
 }
@@ -453,6 +570,8 @@ int ddx_plan_create(const ddx_desc* d, ddx_plan** out) {
   if (d->dump_len < 1 || d->max_block_samples < 1) return DDX_EINVAL;
   if (d->out_mode != DDX_OUT_PACKED && d->out_mode != DDX_OUT_FULL) return DDX_EINVAL;
   if (d->k_dm < 0 || !std::isfinite(d->k_dm)) return DDX_EINVAL;
+  if (d->wave_units < 0 || d->dm_group < 0 || d->max_record_pairs < 0 || d->ring_dumps < 0) return DDX_EINVAL;
+  if (d->compact_records != 0 && d->compact_records != 1) return DDX_EINVAL;
   for (int c = 0; c < d->n_chan; ++c) {
     const double f = d->chan_freq_hz[c];
     if (!std::isfinite(f) || !(f > 0.5 * d->samp_rate_hz)) return DDX_EINVAL;
@@ -473,6 +592,11 @@ int ddx_plan_create(const ddx_desc* d, ddx_plan** out) {
   p->kdm = d->k_dm == 0 ? kDefaultKdm : d->k_dm;
   p->max_block = d->max_block_samples;
   p->max_bytes = d->max_device_bytes;
+  p->wave_req = d->wave_units;
+  p->group_req = d->dm_group;
+  p->compact = d->compact_records;
+  p->max_pairs_req = d->max_record_pairs;
+  p->ring_req = d->ring_dumps;
   p->nbl = d->out_mode == DDX_OUT_PACKED ? d->n_ant * (d->n_ant + 1) / 2 : d->n_ant * d->n_ant;
   p->ch.resize(p->C);
   p->fft_req.assign(p->C, 0);
@@ -517,6 +641,19 @@ int ddx_set_active_dms(ddx_plan* p, int32_t chan, const uint8_t* mask) {
   if (!p->ready) return fail(p, DDX_ESTATE, "set DM trials first");
   if (chan < -1 || chan >= p->C) return fail(p, DDX_EINVAL, "channel %d out of range", chan);
   const int c0 = chan < 0 ? 0 : chan, c1 = chan < 0 ? p->C : chan + 1;
+  if (p->compact) {
+    int64_t done = 0;
+    for (auto& c : p->ch) done = std::max(done, c.dumps_done);
+    if (done > p->dumps_fetched)
+      return fail(p, DDX_ESTATE, "compact records: fetch every dump before changing the active DMs");
+    int64_t na = 0;
+    for (int c = 0; c < p->C; ++c)
+      for (size_t d = 0; d < p->ch[c].dm.size(); ++d)
+        na += (c >= c0 && c < c1) ? (mask ? mask[d] != 0 : 1) : p->ch[c].active[d];
+    if (na > p->cap_pairs)
+      return fail(p, DDX_EINVAL, "%lld active (channel, DM) pairs exceed the record capacity %lld", (long long)na,
+                  (long long)p->cap_pairs);
+  }
   for (int c = c0; c < c1; ++c)
     for (size_t d = 0; d < p->ch[c].dm.size(); ++d) p->ch[c].active[d] = mask ? (mask[d] != 0) : 1;
   if (p->last_stream) HIPCHECK(p, hipStreamSynchronize(p->last_stream));
@@ -554,6 +691,8 @@ int ddx_get_layout(const ddx_plan* pc, ddx_layout* o) {
   o->delay_s = p->lay_delay.data();
   o->shift = p->lay_shift.data();
   o->scale = p->lay_scale.data();
+  o->record_pos = p->rec_pos.data();
+  o->record_pairs = p->rec_pairs;
   o->record_elems = p->rec_elems;
   o->samples_in = p->recv;
   int64_t ready = INT64_MAX;
@@ -562,8 +701,185 @@ int ddx_get_layout(const ddx_plan* pc, ddx_layout* o) {
   o->dumps_fetched = p->dumps_fetched;
   o->ring_dumps = p->ring_dumps;
   o->device_bytes = p->dev_bytes;
+  o->wave_units = p->wave_units;
+  o->dm_group = p->dm_group;
+  o->compact_records = p->compact;
   return DDX_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// One call's work lists (see ddx_process_block in ddx.h).
+struct CallLists {
+  std::vector<ddx::FwdItem> fwd;
+  std::vector<FwdLaunch> fwd_launch;
+  std::vector<ddx::UnitItem> units;
+  std::vector<ddx::ChirpItem> chirps;
+  std::vector<Wave> waves;
+  std::vector<ddx::ZeroItem> zeros;
+};
+
+// Build the lists for blocks [b0[c], b_end[c]) of every channel; out_end[c] is the
+// end of the channel's output this call (complete dumps only are correlated).
+void build_lists(ddx_plan* p, const std::vector<int64_t>& b_end, const std::vector<int64_t>& out_end, CallLists& w) {
+  const int M = p->M;
+  // transform-length classes, ascending
+  std::vector<int> classes;
+  for (int i = 0; i < p->C; ++i)
+    if (b_end[i] > p->ch[i].blocks_done) classes.push_back(p->ch[i].logn);
+  std::sort(classes.begin(), classes.end());
+  classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
+  // forward items and spectrum offsets: class, channel, block.  Two-pass lengths
+  // run in chunks of `chunk` items whose intermediate rows start at offset 0.
+  std::vector<size_t> fwd_first(p->C, 0);
+  int64_t off = 0;
+  for (int logn : classes) {
+    FwdLaunch fl{logn, w.fwd.size(), 0};
+    const size_t per = (size_t)M << logn;
+    const size_t chunk = logn > ddx::kBigLog ? std::max<size_t>(1, p->tb_elems / per) : 1;
+    for (int i = 0; i < p->C; ++i) {
+      Chan& c = p->ch[i];
+      if (c.logn != logn || b_end[i] <= c.blocks_done) continue;
+      fwd_first[i] = w.fwd.size();
+      for (int64_t b = c.blocks_done; b < b_end[i]; ++b) {
+        ddx::FwdItem it{};
+        it.win0 = b * (int64_t)c.valid - c.lead;
+        it.spec = off;
+        it.tb = logn > ddx::kBigLog ? (int64_t)(((w.fwd.size() - fl.i0) % chunk) * per) : 0;
+        it.hist_start = c.hist_start;
+        it.chan = i;
+        w.fwd.push_back(it);
+        off += (int64_t)per;
+      }
+    }
+    fl.n = w.fwd.size() - fl.i0;
+    w.fwd_launch.push_back(fl);
+  }
+  // units: class, channel, DM group, block, DM; waves of wave_units within a class
+  std::vector<int32_t> slot_of(p->dm_off[p->C], -1);
+  std::vector<int64_t> slot_wave(p->dm_off[p->C], -1);
+  std::vector<int64_t> spec_wave(w.fwd.size(), -1);
+  const int64_t maxn = *std::max_element(p->lay_fft.begin(), p->lay_fft.end());
+  for (int logn : classes) {
+    Wave cur{};
+    bool open = false;
+    auto close = [&]() {
+      if (open && cur.nu) w.waves.push_back(cur);
+      open = false;
+    };
+    for (int i = 0; i < p->C; ++i) {
+      Chan& c = p->ch[i];
+      if (c.logn != logn || b_end[i] <= c.blocks_done) continue;
+      // the channel's active DMs, in DM order
+      std::vector<int> act;
+      for (size_t d = 0; d < c.dm.size(); ++d)
+        if (c.active[d]) act.push_back((int)d);
+      for (size_t g0 = 0; g0 < act.size(); g0 += p->dm_group) {
+        const size_t g1 = std::min(act.size(), g0 + p->dm_group);
+        for (int64_t b = c.blocks_done; b < b_end[i]; ++b) {
+          const int64_t first = b * c.valid / p->L;
+          const int64_t last = std::min(b * c.valid + c.valid, out_end[i]) / p->L;
+          if (last <= first) continue;
+          for (size_t k = g0; k < g1; ++k) {
+            const int d = act[k];
+            if (!open || cur.nu == (size_t)p->wave_units) {
+              close();
+              cur = Wave{};
+              cur.logn = logn;
+              cur.u0 = w.units.size();
+              cur.c0 = w.chirps.size();
+              cur.fft_n = c.fft_len;
+              open = true;
+            }
+            const int64_t wid = (int64_t)w.waves.size();
+            const int64_t pair = p->dm_off[i] + d;
+            if (slot_wave[pair] != wid) {
+              slot_wave[pair] = wid;
+              slot_of[pair] = (int32_t)cur.nc;
+              ddx::ChirpItem ci{};
+              ci.g = p->gtab_off[i];
+              ci.out = (int64_t)cur.nc * maxn;
+              ci.kdm = p->kdm * c.dm[d];
+              ci.n = c.fft_len;
+              ci.logr = c.logn > ddx::kBigLog ? c.logn - ddx::kBigLog : 0;
+              w.chirps.push_back(ci);
+              ++cur.nc;
+            }
+            const size_t sidx = fwd_first[i] + (size_t)(b - c.blocks_done);
+            if (spec_wave[sidx] != wid) { spec_wave[sidx] = wid; ++cur.spectra; }
+            ddx::UnitItem u{};
+            u.spec = w.fwd[sidx].spec;
+            u.chirp = (int64_t)slot_of[pair] * maxn;
+            u.y = (int64_t)cur.nu * M * p->y_stride;
+            u.tb = (int64_t)cur.nu * M * c.fft_len;
+            u.dump0 = first;
+            u.rec = (int64_t)p->rec_pos[pair] * p->nbl;
+            u.chan = i;
+            u.valid = c.valid;
+            u.lead = c.lead;
+            u.n_dumps = (int32_t)(last - first);
+            w.units.push_back(u);
+            ++cur.nu;
+            cur.max_dumps = std::max(cur.max_dumps, u.n_dumps);
+            cur.y_samples += (int64_t)M * c.valid;
+            cur.dumps += u.n_dumps;
+          }
+        }
+      }
+    }
+    close();
+  }
+  // full records: zero the inactive DMs' slots of every dump the call completes
+  if (!p->compact) {
+    for (int i = 0; i < p->C; ++i) {
+      Chan& c = p->ch[i];
+      const int n_in = (int)c.dm.size() - p->n_active[i];
+      if (n_in <= 0) continue;
+      const int64_t m0 = c.blocks_done * c.valid / p->L, m1 = out_end[i] / p->L;
+      for (int64_t m = m0; m < m1; ++m) {
+        ddx::ZeroItem z{};
+        z.rec = (m % p->ring_dumps) * p->rec_elems;
+        z.pos = (int32_t)(p->dm_off[i] + p->n_active[i]);
+        z.n = n_in;
+        w.zeros.push_back(z);
+      }
+    }
+  }
+}
+
+// Copy the lists into the pinned staging buffer and on to the device (stream
+// ordered: the previous call's kernels have read the device copy before this
+// copy overwrites it).  Returns the device addresses of the four lists.
+int upload_lists(ddx_plan* p, const CallLists& w, hipStream_t s, ddx::FwdItem** fwd, ddx::UnitItem** units,
+                 ddx::ChirpItem** chirps, ddx::ZeroItem** zeros) {
+  const size_t o1 = align_up(w.fwd.size() * sizeof(ddx::FwdItem));
+  const size_t o2 = o1 + align_up(w.units.size() * sizeof(ddx::UnitItem));
+  const size_t o3 = o2 + align_up(w.chirps.size() * sizeof(ddx::ChirpItem));
+  const size_t bytes = o3 + w.zeros.size() * sizeof(ddx::ZeroItem);
+  if (bytes > p->items_cap) return fail(p, DDX_EINVAL, "internal: work lists of %zu bytes exceed %zu", bytes, p->items_cap);
+  const int k = p->stage_cur;
+  if (p->stage_used[k]) HIPCHECK(p, hipEventSynchronize(p->stage_ev[k]));
+  char* h = p->stage[k];
+  if (!w.fwd.empty()) std::memcpy(h, w.fwd.data(), w.fwd.size() * sizeof(ddx::FwdItem));
+  if (!w.units.empty()) std::memcpy(h + o1, w.units.data(), w.units.size() * sizeof(ddx::UnitItem));
+  if (!w.chirps.empty()) std::memcpy(h + o2, w.chirps.data(), w.chirps.size() * sizeof(ddx::ChirpItem));
+  if (!w.zeros.empty()) std::memcpy(h + o3, w.zeros.data(), w.zeros.size() * sizeof(ddx::ZeroItem));
+  if (bytes) HIPCHECK(p, hipMemcpyAsync(p->items_dev, h, bytes, hipMemcpyHostToDevice, s));
+  HIPCHECK(p, hipEventRecord(p->stage_ev[k], s));
+  p->stage_used[k] = true;
+  p->stage_cur = 1 - k;
+  *fwd = reinterpret_cast<ddx::FwdItem*>(p->items_dev);
+  *units = reinterpret_cast<ddx::UnitItem*>(p->items_dev + o1);
+  *chirps = reinterpret_cast<ddx::ChirpItem*>(p->items_dev + o2);
+  *zeros = reinterpret_cast<ddx::ZeroItem*>(p->items_dev + o3);
+  return DDX_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags, void* hip_stream) {
   if (!p) return DDX_EINVAL;
@@ -577,8 +893,8 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
   const int64_t total = p->recv + n;
 
   // Blocks each channel can run now, and the dumps they complete.
-  std::vector<int64_t> b_end(p->C), dumps_new(p->C);
-  int64_t fetched_floor = p->dumps_fetched;
+  std::vector<int64_t> b_end(p->C), dumps_new(p->C), out_end(p->C);
+  const int64_t fetched_floor = p->dumps_fetched;
   for (int i = 0; i < p->C; ++i) {
     Chan& c = p->ch[i];
     int64_t be;
@@ -590,18 +906,27 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
     }
     be = std::max(be, c.blocks_done);
     b_end[i] = be;
-    int64_t out_end = be * (int64_t)c.valid;
-    if (flush) out_end = std::min(out_end, total);
-    dumps_new[i] = std::max(c.dumps_done, out_end / p->L);
+    out_end[i] = be * (int64_t)c.valid;
+    if (flush) out_end[i] = std::min(out_end[i], total);
+    dumps_new[i] = std::max(c.dumps_done, out_end[i] / p->L);
     if (dumps_new[i] - fetched_floor > p->ring_dumps)
       return fail(p, DDX_EFULL, "channel %d would hold %lld unfetched dumps, ring has %lld", i,
                   (long long)(dumps_new[i] - fetched_floor), (long long)p->ring_dumps);
-    const int64_t nb = be - c.blocks_done;
-    if ((nb * (int64_t)p->M * c.fft_len) > (int64_t)p->spec_elems)
-      return fail(p, DDX_EINVAL, "internal: %lld blocks exceed the spectrum buffer", (long long)nb);
+    if (be - c.blocks_done > max_blocks(p, c))
+      return fail(p, DDX_EINVAL, "internal: %lld blocks exceed the spectrum buffer", (long long)(be - c.blocks_done));
   }
+  if (p->started && p->last_stream != s) HIPCHECK(p, hipStreamSynchronize(p->last_stream));
   p->started = true;
   p->last_stream = s;
+
+  CallLists w;
+  build_lists(p, b_end, out_end, w);
+  ddx::FwdItem* fwd_dev;
+  ddx::UnitItem* units_dev;
+  ddx::ChirpItem* chirps_dev;
+  ddx::ZeroItem* zeros_dev;
+  int rc = upload_lists(p, w, s, &fwd_dev, &units_dev, &chirps_dev, &zeros_dev);
+  if (rc) return rc;
 
   ddx::Source src{};
   src.chunk = d_volts;
@@ -611,94 +936,97 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
   src.chunk_start = p->recv;
   src.chunk_len = n;
 
+  // correlator-input scale of each channel, fixed from its first block window
   for (int i = 0; i < p->C; ++i) {
     Chan& c = p->ch[i];
-    const int64_t b0 = c.blocks_done, nb = b_end[i] - b0;
-    if (nb <= 0) continue;
+    if (b_end[i] <= c.blocks_done || c.blocks_done != 0 || p->have_scale) continue;
+    const float target = p->corr_dtype == DDX_CORR_E4M3 ? kScaleTargetE4M3 : kScaleTargetF16;  // F32 too
+    const int64_t nwin = std::min<int64_t>(c.fft_len - c.lead, total);
     src.hist_start = c.hist_start;
-    if (b0 == 0 && !p->have_scale) {
-      // first block of the channel: fix its correlator-input scale from the block's window
-      const float target = p->corr_dtype == DDX_CORR_E4M3 ? kScaleTargetE4M3 : kScaleTargetF16;  // F32 too
-      const int64_t nwin = std::min<int64_t>(c.fft_len - c.lead, total);
-      HIPCHECK(p, timed(p, s, DDX_K_OTHER, 0.0, (double)nwin * p->M * in_bytes(p->in_dtype), [&] {
-        if (p->in_dtype == DDX_IN_CI8)
-          hipLaunchKernelGGL(ddx::k_scale<0>, dim3(1), dim3(1024), 0, s, src, i, p->M, nwin, target, p->scale_dev);
-        else
-          hipLaunchKernelGGL(ddx::k_scale<1>, dim3(1), dim3(1024), 0, s, src, i, p->M, nwin, target, p->scale_dev);
-        return hipGetLastError();
-      }));
-      p->scale_pending = true;
-    }
-    ddx::FwdArgs fa{};
-    fa.src = src;
-    fa.spec = p->spec;
-    fa.b0 = b0;
-    fa.nblk = (int)nb;
-    fa.n_ant = p->M;
-    fa.valid = c.valid;
-    fa.lead = c.lead;
-    fa.chan = i;
-    HIPCHECK(p, timed(p, s, DDX_K_FORWARD, (double)nb * p->M * fft_flops(c.fft_len),
-                      (double)nb * p->M * c.fft_len * (in_bytes(p->in_dtype) + 8.0),
-                      [&] { return launch_forward(c.logn, p->in_dtype, fa, s); }));
-    const int na = p->n_active[i];
-    const int64_t dump0 = b0 * (int64_t)c.valid / p->L;
-    const int n_dumps = (int)(dumps_new[i] - dump0);
-    if (na > 0) {
-      dim3 g((c.fft_len + 255) / 256, na);
-      HIPCHECK(p, timed(p, s, DDX_K_CHIRP, 0.0, (double)c.fft_len * (8.0 + 8.0 * na), [&] {
-        hipLaunchKernelGGL(ddx::k_chirp, g, dim3(256), 0, s, p->gtab + p->gtab_off[i], p->kdm_dev + p->dm_off[i],
-                           p->chirp, c.fft_len, 1.0f / (float)c.fft_len);
-        return hipGetLastError();
-      }));
-    }
-    for (int g0 = 0; g0 < na; g0 += p->dm_group) {
-      const int nd = std::min(p->dm_group, na - g0);
-      ddx::DedispArgs da{};
-      da.spec = p->spec;
-      da.chirp = p->chirp + (size_t)g0 * c.fft_len;
-      da.y = p->ybuf;
-      da.y_stride = p->y_stride;
-      da.scale = p->scale_dev + i;
-      da.n_ant = p->M;
-      da.nblk = (int)nb;
-      da.nd = nd;
-      da.valid = c.valid;
-      da.lead = c.lead;
-      HIPCHECK(p, timed(p, s, DDX_K_DEDISP, (double)nb * p->M * nd * (fft_flops(c.fft_len) + 6.0 * c.fft_len),
-                        8.0 * c.fft_len * ((double)nb * p->M + nd) + (double)nd * p->M * nb * c.valid * y_bytes(p->corr_dtype),
-                        [&] { return launch_dedisp(c.logn, p->corr_dtype, da, s); }));
-      if (n_dumps > 0) {
-        ddx::CorrArgs ca{};
-        ca.y = p->ybuf;
-        ca.y_stride = p->y_stride;
-        ca.ring = p->ring;
-        ca.rec_elems = p->rec_elems;
-        ca.ring_dumps = p->ring_dumps;
-        ca.dump0 = dump0;
-        ca.dm_pos = p->pos_dev + p->dm_off[i] + g0;
-        ca.scale = p->scale_dev + i;
-        ca.n_dumps = n_dumps;
-        ca.nd = nd;
-        ca.n_ant = p->M;
-        ca.dump_len = p->L;
-        ca.nbl = p->nbl;
-        ca.out_mode = p->out_mode;
-        const double nbl_h = p->M * (p->M + 1) / 2.0;
-        HIPCHECK(p, timed(p, s, DDX_K_CORR, (double)n_dumps * nd * 8.0 * p->L * nbl_h,
-                          (double)n_dumps * nd * ((double)p->L * p->M * y_bytes(p->corr_dtype) + 8.0 * p->nbl),
-                          [&] { return launch_corr(p->corr_dtype, ca, s); }));
+    HIPCHECK(p, timed(p, s, DDX_K_OTHER, 0.0, (double)nwin * p->M * in_bytes(p->in_dtype), [&] {
+      if (p->in_dtype == DDX_IN_CI8)
+        hipLaunchKernelGGL(ddx::k_scale<0>, dim3(1), dim3(1024), 0, s, src, i, p->M, nwin, target, p->scale_dev);
+      else
+        hipLaunchKernelGGL(ddx::k_scale<1>, dim3(1), dim3(1024), 0, s, src, i, p->M, nwin, target, p->scale_dev);
+      return hipGetLastError();
+    }));
+    p->scale_pending = true;
+  }
+
+  // forward transforms, one launch per transform length (two-pass lengths in chunks
+  // that fit the intermediate buffer)
+  ddx::FwdArgs fa{};
+  fa.src = src;
+  fa.spec = p->spec;
+  fa.n_ant = p->M;
+  for (const FwdLaunch& fl : w.fwd_launch) {
+    const double nn = 1 << fl.logn;
+    if (fl.logn <= ddx::kBigLog) {
+      fa.items = fwd_dev + fl.i0;
+      HIPCHECK(p, timed(p, s, DDX_K_FORWARD, (double)fl.n * p->M * fft_flops(nn),
+                        (double)fl.n * p->M * nn * (in_bytes(p->in_dtype) + 8.0),
+                        [&] { return launch_forward(fl.logn, p->in_dtype, fa, (int)fl.n, s); }));
+    } else {
+      const size_t per = (size_t)p->M << fl.logn;
+      const size_t chunk = std::max<size_t>(1, p->tb_elems / per);
+      for (size_t i0 = 0; i0 < fl.n; i0 += chunk) {
+        // the chunk's spectra are consecutive and its intermediate rows start at 0
+        const size_t cnt = std::min(chunk, fl.n - i0);
+        const std::vector<ddx::FwdItem>& fv = w.fwd;
+        fa.items = fwd_dev + fl.i0 + i0;
+        HIPCHECK(p, timed(p, s, DDX_K_FORWARD, (double)cnt * p->M * fft_flops(nn),
+                          (double)cnt * p->M * nn * (in_bytes(p->in_dtype) + 8.0),
+                          [&] { return launch_forward_big(fl.logn, p->in_dtype, fa, &fv[fl.i0 + i0], (int)cnt, p->tb, s); }));
       }
     }
-    const int n_inactive = (int)c.dm.size() - na;
-    if (n_inactive > 0 && n_dumps > 0) {
-      const int64_t tot = (int64_t)n_dumps * n_inactive * p->nbl;
-      HIPCHECK(p, timed(p, s, DDX_K_OTHER, 0.0, 8.0 * tot, [&] {
-        hipLaunchKernelGGL(ddx::k_zero_dm, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, p->ring, p->rec_elems,
-                           p->ring_dumps, dump0, n_dumps, p->pos_dev + p->dm_off[i] + na, n_inactive, p->nbl);
-        return hipGetLastError();
-      }));
-    }
+  }
+
+  // waves: chirps, dedispersion, correlation
+  const double nbl_h = p->M * (p->M + 1) / 2.0;
+  for (const Wave& wv : w.waves) {
+    const double nn = wv.fft_n;
+    HIPCHECK(p, timed(p, s, DDX_K_CHIRP, 0.0, (double)wv.nc * nn * 16.0, [&] {
+      hipLaunchKernelGGL(ddx::k_chirp, dim3((unsigned)((wv.fft_n + 255) / 256), (unsigned)wv.nc), dim3(256), 0, s,
+                         (const ddx::ChirpItem*)(chirps_dev + wv.c0), (const double*)p->gtab, p->chirp);
+      return hipGetLastError();
+    }));
+    ddx::DedispArgs da{};
+    da.spec = p->spec;
+    da.chirp = p->chirp;
+    da.y = p->ybuf;
+    da.tb = p->tb;
+    da.units = units_dev + wv.u0;
+    da.scale = p->scale_dev;
+    da.y_stride = p->y_stride;
+    da.n_ant = p->M;
+    da.n_units = (int)wv.nu;
+    da.logr = wv.logn > ddx::kBigLog ? wv.logn - ddx::kBigLog : 0;
+    HIPCHECK(p, timed(p, s, DDX_K_DEDISP, (double)wv.nu * p->M * (fft_flops(nn) + 6.0 * nn),
+                      8.0 * nn * ((double)wv.spectra * p->M + wv.nc) + (double)wv.y_samples * y_bytes(p->corr_dtype),
+                      [&] { return launch_dedisp(wv.logn, p->corr_dtype, da, s); }));
+    ddx::CorrArgs ca{};
+    ca.y = p->ybuf;
+    ca.ring = p->ring;
+    ca.units = units_dev + wv.u0;
+    ca.scale = p->scale_dev;
+    ca.y_stride = p->y_stride;
+    ca.rec_elems = p->rec_elems;
+    ca.ring_dumps = p->ring_dumps;
+    ca.max_dumps = wv.max_dumps;
+    ca.n_ant = p->M;
+    ca.dump_len = p->L;
+    ca.nbl = p->nbl;
+    ca.out_mode = p->out_mode;
+    HIPCHECK(p, timed(p, s, DDX_K_CORR, (double)wv.dumps * 8.0 * p->L * nbl_h,
+                      (double)wv.dumps * ((double)p->L * p->M * y_bytes(p->corr_dtype) + 8.0 * p->nbl),
+                      [&] { return launch_corr(p->corr_dtype, ca, (int)wv.nu, s); }));
+  }
+  if (!w.zeros.empty()) {
+    HIPCHECK(p, timed(p, s, DDX_K_OTHER, 0.0, 8.0 * (double)w.zeros.size() * w.zeros[0].n * p->nbl, [&] {
+      hipLaunchKernelGGL(ddx::k_zero_dm, dim3((unsigned)w.zeros.size()), dim3(256), 0, s, p->ring,
+                         (const ddx::ZeroItem*)zeros_dev, (const int32_t*)p->slots_dev, p->nbl);
+      return hipGetLastError();
+    }));
   }
 
   // Carry the unconsumed tail of every row into the other history buffer.
@@ -748,7 +1076,7 @@ int ddx_fetch_visibilities(ddx_plan* p, void* out, size_t cap, int64_t* first, i
   if (!out) return fail(p, DDX_EINVAL, "null output");
   hipStream_t s = (hipStream_t)hip_stream;
   int64_t k = 0;
-  while (k < avail) {
+  while (k < avail && rec > 0) {
     const int64_t slot = (p->dumps_fetched + k) % p->ring_dumps;
     const int64_t cnt = std::min(avail - k, p->ring_dumps - slot);
     HIPCHECK(p, hipMemcpyAsync((char*)out + rec * k, p->ring + slot * p->rec_elems, rec * cnt, hipMemcpyDefault, s));
@@ -760,6 +1088,7 @@ int ddx_fetch_visibilities(ddx_plan* p, void* out, size_t cap, int64_t* first, i
 }
 
 }  // extern "C"
+
 
 namespace {
 

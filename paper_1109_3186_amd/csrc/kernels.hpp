@@ -56,13 +56,48 @@ __device__ __forceinline__ float2 load_sample(const Source& s, int64_t abs) {
 }
 
 // ---------------------------------------------------------------------------
-// Forward FFT of every overlap-save block of one channel.
-// grid: nblk * M workgroups (block fastest); output spec[(p * nblk + blk) * N + k].
+// Work items of one ddx_process_block call.  The host lists them (all channels,
+// all active DMs, all blocks the call completes) and copies the lists to the
+// device; each launch below walks one list.  Offsets are in elements.
+struct FwdItem {        // one overlap-save block of one channel, all M antennas
+  int64_t win0;         // absolute sample index of the block window's first sample
+  int64_t spec;         // spectrum of antenna 0 (antenna p at + p N)
+  int64_t tb;           // two-pass transforms: intermediate rows of antenna 0 (antenna p at + p N)
+  int64_t hist_start;   // absolute sample index of the channel's history element 0
+  int32_t chan;
+  int32_t pad;
+};
+struct ChirpItem {      // one (channel, DM) of a wave
+  int64_t g;            // the channel's g table
+  int64_t out;          // chirp slot
+  double kdm;           // K DM
+  int32_t n;            // N_c
+  int32_t logr;         // N_c = 2^(15 + logr) for two-pass transforms, else 0
+};
+struct UnitItem {       // one (channel, DM, block), all M antennas
+  int64_t spec;         // spectrum of antenna 0 of the block
+  int64_t chirp;        // chirp of the DM
+  int64_t y;            // output row of antenna 0 (antenna p at + p y_stride)
+  int64_t tb;           // two-pass transforms: intermediate rows of antenna 0
+  int64_t dump0;        // absolute index of the block's first dump (b V / L)
+  int64_t rec;          // offset of the (channel, DM) slot within a dump record
+  int32_t chan, valid, lead;
+  int32_t n_dumps;      // complete dumps of the block this call
+};
+struct ZeroItem {       // the inactive-DM slots of one (channel, dump) record
+  int64_t rec;          // offset of the dump's record in the ring
+  int32_t pos;          // first of the channel's inactive slots in the slot table
+  int32_t n;            // inactive DMs of the channel
+};
+
+// ---------------------------------------------------------------------------
+// Forward FFT of the overlap-save blocks of a list of (channel, block) items.
+// grid: n_items * M workgroups (antenna fastest).  spec[it.spec + p N + k] = X[k].
 struct FwdArgs {
   Source src;
+  const FwdItem* items;
   float2* spec;
-  int64_t b0;  // absolute index of the first block
-  int32_t nblk, n_ant, valid, lead, chan;
+  int32_t n_ant;
 };
 
 template <int LOGN, int IN>
@@ -70,14 +105,15 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_forward(FwdArgs a) {
   using G = Geo<LOGN>;
   extern __shared__ float lds[];
   const int t = threadIdx.x;
-  const int blk = blockIdx.x % a.nblk, p = blockIdx.x / a.nblk;
+  const int p = blockIdx.x % a.n_ant;
+  const FwdItem w = a.items[blockIdx.x / a.n_ant];
   Source s = a.src;
-  s.row = a.chan * a.n_ant + p;
-  const int64_t win0 = (a.b0 + blk) * (int64_t)a.valid - a.lead;
+  s.row = w.chan * a.n_ant + p;
+  s.hist_start = w.hist_start;
   float2 v[G::P];
-  fft_workgroup<LOGN, -1>(v, lds, t, [&](int i) { return load_sample<IN>(s, win0 + i); });
+  fft_workgroup<LOGN, -1>(v, lds, t, [&](int i) { return load_sample<IN>(s, w.win0 + i); });
   // output addresses are formed only now (otherwise they are hoisted and held in registers)
-  float2* out = a.spec + ((size_t)p * a.nblk + blk) * G::N + opaque_zero(v[0].x);
+  float2* out = a.spec + w.spec + (size_t)p * G::N + opaque_zero(v[0].x);
 #pragma unroll
   for (int u = 0; u < G::P / G::RL; ++u)
 #pragma unroll
@@ -85,16 +121,20 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_forward(FwdArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Chirp table H[d][k] = exp(-2 pi i r) / N with r = u - rint(u), u = kdm[d] * g[k]
-// in FP64 (g[k] = f_k^2 / (f_c^2 (f_c + f_k)), kdm[d] = K DM_d).
-__global__ __launch_bounds__(256) void k_chirp(const double* __restrict__ g, const double* __restrict__ kdm,
-                                               float2* __restrict__ h, int n, float inv_n) {
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  const int d = blockIdx.y;
-  if (k >= n) return;
-  const double u = kdm[d] * g[k];
+// Chirp tables of a wave's (channel, DM) pairs: H[k] = exp(-2 pi i r) / N with
+// r = u - rint(u), u = kdm * g[k] in FP64 (g[k] = f_k^2 / (f_c^2 (f_c + f_k))).
+// Two-pass lengths store bin k1 + R k2 at position k1 2^15 + k2 (the order in
+// which their spectra are kept).  grid: (ceil(max N / 256), n_items).
+__global__ __launch_bounds__(256) void k_chirp(const ChirpItem* __restrict__ items, const double* __restrict__ g,
+                                               float2* __restrict__ h) {
+  const ChirpItem w = items[blockIdx.y];
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= w.n) return;
+  const int k = w.logr ? ((q >> 15) + (q & 32767) * (1 << w.logr)) : q;
+  const double u = w.kdm * g[w.g + k];
   const float r = (float)(u - rint(u));
-  h[(size_t)d * n + k] = make_float2(cos_rev(r) * inv_n, -sin_rev(r) * inv_n);
+  const float inv_n = 1.0f / (float)w.n;  // power of two: exact
+  h[w.out + q] = make_float2(cos_rev(r) * inv_n, -sin_rev(r) * inv_n);
 }
 
 // ---------------------------------------------------------------------------
@@ -121,16 +161,19 @@ __device__ __forceinline__ typename YType<OUT>::T convert_y(float2 v, float scal
   }
 }
 
-// Chirp multiply, inverse FFT and overlap-save discard for nd DMs of one channel.
-// grid: M * nblk * nd workgroups, logical id = (p * nblk + blk) * nd + d (XCD-remapped).
-// y[(d * M + p) * y_stride + blk * V + j] = IDFT(X H)[lead + j] for j < V.
+// Chirp multiply, inverse FFT and overlap-save discard for a wave of units.
+// grid: M * n_units workgroups, logical id = p * n_units + u (XCD-remapped), so
+// neighbouring ids share a spectrum (units run DM-fastest within a block).
+// y[u.y + p y_stride + j] = IDFT(X H)[lead + j] for j < V.
 struct DedispArgs {
   const float2* spec;
-  const float2* chirp;  // [nd][N] (already offset to the first DM of the group)
+  const float2* chirp;
   void* y;
+  float2* tb;           // two-pass transforms: intermediate rows
+  const UnitItem* units;
+  const float* scale;   // [C] correlator-input scales
   int64_t y_stride;
-  const float* scale;   // device scalar: correlator-input scale of this channel
-  int32_t n_ant, nblk, nd, valid, lead;
+  int32_t n_ant, n_units, logr;
 };
 
 template <int LOGN, int OUT>
@@ -139,129 +182,142 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_dedisperse(DedispArgs a) {
   extern __shared__ float lds[];
   const int t = threadIdx.x;
   const int lin = xcd_remap(blockIdx.x, gridDim.x);
-  const int d = lin % a.nd;
-  const int rest = lin / a.nd;
-  const int blk = rest % a.nblk, p = rest / a.nblk;
-  const float2* x = a.spec + ((size_t)p * a.nblk + blk) * G::N;
-  const float2* h = a.chirp + (size_t)d * G::N;
+  const int p = lin / a.n_units;
+  const UnitItem w = a.units[lin % a.n_units];
+  const float2* x = a.spec + w.spec + (size_t)p * G::N;
+  const float2* h = a.chirp + w.chirp;
   float2 v[G::P];
   fft_workgroup<LOGN, +1>(v, lds, t, [&](int i) { return cmul(x[i], h[i]); });
-  const float scale = (OUT == 0) ? 1.f : *a.scale;
+  const float scale = (OUT == 0) ? 1.f : a.scale[w.chan];
   typedef typename YType<OUT>::T YT;
   // output addresses are formed only now (otherwise they are hoisted and held in registers)
-  YT* y = reinterpret_cast<YT*>(a.y) + ((size_t)d * a.n_ant + p) * a.y_stride + (size_t)blk * a.valid +
-          opaque_zero(v[0].x);
+  YT* y = reinterpret_cast<YT*>(a.y) + w.y + (size_t)p * a.y_stride + opaque_zero(v[0].x);
 #pragma unroll
   for (int u = 0; u < G::P / G::RL; ++u)
 #pragma unroll
     for (int q = 0; q < G::RL; ++q) {
       const int n = t + u * G::T + q * (G::N / G::RL);
-      if (n >= a.lead && n < a.lead + a.valid) y[n - a.lead] = convert_y<OUT>(v[u * G::RL + out_reg<G::RL>(q)], scale);
+      if (n >= w.lead && n < w.lead + w.valid) y[n - w.lead] = convert_y<OUT>(v[u * G::RL + out_reg<G::RL>(q)], scale);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Transforms longer than one workgroup's LDS: N = R * 32768 (R = 2, 4, 8), with
-// k = k1 + R k2 and n = n1 32768 + n2 (k1, n1 < R; k2, n2 < 32768):
-//   F[n] = sum_{k1} w_R^{n1 k1} [ w_N^{n2 k1} sum_{k2} w_32768^{n2 k2} Z[k1 + R k2] ],
-// w_M = exp(s 2 pi i / M).  Pass A: for each k1 a 32768-point transform of the
-// stride-R subsequence, times the twiddle w_N^{n2 k1}, stored as T[k1][n2].  Pass B:
-// for each n2 an R-point DFT over k1, giving F in natural order.
+// Transforms longer than one workgroup's LDS: N = R 2^15 (R = 2, 4, 8).
+// Forward, input index n = n1 2^15 + n2 and output index k = k1 + R k2
+// (n1, k1 < R; n2, k2 < 2^15):
+//   X[k1 + R k2] = sum_{n2} w_{2^15}^{-k2 n2} [ w_N^{-k1 n2} sum_{n1} w_R^{-k1 n1} x[n1 2^15 + n2] ],
+// an R-point DFT per n2 with a twiddle (k_forward_big_pre), then a 2^15-point FFT
+// per (antenna, k1) row (k_fft_rows).  The spectrum is kept as rows [k1][k2].
+// Inverse of Z = X H, output index n = n1 2^15 + n2:
+//   y[n1 2^15 + n2] = sum_{k1} w_R^{k1 n1} [ w_N^{k1 n2} sum_{k2} w_{2^15}^{k2 n2} Z[k1 + R k2] ],
+// a 2^15-point FFT per row [k1] with a twiddle on its outputs (k_dedisperse_big_a),
+// then an R-point DFT per n2 (k_dedisperse_big_b), which writes y in natural order.
 constexpr int kBigLog = 15;
 constexpr int kBigN = 1 << kBigLog;
 
-// exp(S 2 pi i num / (R 2^15)), angle reduced exactly
-template <int R, int S>
-__device__ __forceinline__ float2 big_twiddle(int num) {
-  const int den = R * kBigN;
-  float x = (float)(num % den) * (1.0f / (float)den);
+// exp(S 2 pi i num / 2^(15 + logr)) for 0 <= num < 2^(15 + logr), reduced exactly
+template <int S>
+__device__ __forceinline__ float2 big_twiddle(int num, int logr) {
+  float x = (float)num * (1.0f / (float)(kBigN << logr));
   x = (x >= 0.5f) ? x - 1.0f : x;
   return make_float2(cos_rev(x), (float)S * sin_rev(x));
 }
 
-// Pass A of the forward transform of every block: grid nblk * M * R workgroups,
-// (blk fastest, then k1, then p).  t[((p nblk + blk) R + k1) 2^15 + n2].
 template <int R, int IN>
-__global__ __launch_bounds__(Geo<kBigLog>::T) void k_forward_big_a(FwdArgs a, float2* __restrict__ tbuf) {
+__device__ __forceinline__ void forward_big_pre(const Source& s, int64_t win0, int n2, float2* row0) {
+  float2 v[R];
+#pragma unroll
+  for (int n1 = 0; n1 < R; ++n1) v[n1] = load_sample<IN>(s, win0 + (int64_t)n1 * kBigN + n2);
+  dft_reg<R, -1>(v);
+#pragma unroll
+  for (int k1 = 0; k1 < R; ++k1)
+    row0[(size_t)k1 * kBigN + n2] = cmul(v[out_reg<R>(k1)], big_twiddle<-1>(k1 * n2, ilog2(R)));
+}
+
+// grid: (2^15 / 256, n_items * M).  tb[it.tb + (p R + k1) 2^15 + n2].
+template <int IN>
+__global__ __launch_bounds__(256) void k_forward_big_pre(FwdArgs a, float2* __restrict__ tb, int logr) {
+  const int n2 = blockIdx.x * 256 + threadIdx.x;
+  const int p = blockIdx.y % a.n_ant;
+  const FwdItem w = a.items[blockIdx.y / a.n_ant];
+  Source s = a.src;
+  s.row = w.chan * a.n_ant + p;
+  s.hist_start = w.hist_start;
+  float2* row0 = tb + w.tb + ((size_t)p << (kBigLog + logr));
+  if (logr == 1) forward_big_pre<2, IN>(s, w.win0, n2, row0);
+  else if (logr == 2) forward_big_pre<4, IN>(s, w.win0, n2, row0);
+  else forward_big_pre<8, IN>(s, w.win0, n2, row0);
+}
+
+// Forward 2^15-point FFT of n_rows consecutive rows: dst[r 2^15 + k] from src[r 2^15 + n].
+// grid: n_rows workgroups.
+__global__ __launch_bounds__(Geo<kBigLog>::T) void k_fft_rows(const float2* __restrict__ src, float2* __restrict__ dst) {
   using G = Geo<kBigLog>;
   extern __shared__ float lds[];
   const int t = threadIdx.x;
-  const int blk = blockIdx.x % a.nblk, rest = blockIdx.x / a.nblk;
-  const int k1 = rest % R, p = rest / R;
-  Source s = a.src;
-  s.row = a.chan * a.n_ant + p;
-  const int64_t win0 = (a.b0 + blk) * (int64_t)a.valid - a.lead + k1;
+  const float2* x = src + (size_t)blockIdx.x * kBigN;
   float2 v[G::P];
-  fft_workgroup<kBigLog, -1>(v, lds, t, [&](int i) { return load_sample<IN>(s, win0 + (int64_t)R * i); });
-  float2* out = tbuf + (((size_t)p * a.nblk + blk) * R + k1) * kBigN + opaque_zero(v[0].x);
+  fft_workgroup<kBigLog, -1>(v, lds, t, [&](int i) { return x[i]; });
+  float2* out = dst + (size_t)blockIdx.x * kBigN + opaque_zero(v[0].x);
 #pragma unroll
   for (int u = 0; u < G::P / G::RL; ++u)
 #pragma unroll
-    for (int q = 0; q < G::RL; ++q) {
-      const int n2 = t + u * G::T + q * (G::N / G::RL);
-      out[n2] = cmul(v[u * G::RL + out_reg<G::RL>(q)], big_twiddle<R, -1>(n2 * k1));
-    }
+    for (int q = 0; q < G::RL; ++q) out[t + u * G::T + q * (G::N / G::RL)] = v[u * G::RL + out_reg<G::RL>(q)];
 }
 
-// Pass B of the forward transform: spec[(p nblk + blk) N + n1 2^15 + n2].
-// grid: (2^15 / 256, nblk * M).
-template <int R>
-__global__ __launch_bounds__(256) void k_forward_big_b(const float2* __restrict__ tbuf, float2* __restrict__ spec) {
-  const int n2 = blockIdx.x * 256 + threadIdx.x;
-  const size_t item = blockIdx.y;  // p * nblk + blk
-  float2 v[R];
-#pragma unroll
-  for (int k1 = 0; k1 < R; ++k1) v[k1] = tbuf[(item * R + k1) * kBigN + n2];
-  dft_reg<R, -1>(v);
-#pragma unroll
-  for (int n1 = 0; n1 < R; ++n1) spec[item * R * kBigN + (size_t)n1 * kBigN + n2] = v[out_reg<R>(n1)];
-}
-
-// Pass A of the chirp multiply + inverse transform: grid M * nblk * nd * R workgroups,
-// logical id ((p nblk + blk) nd + d) R + k1 (XCD-remapped).
-template <int R>
-__global__ __launch_bounds__(Geo<kBigLog>::T) void k_dedisperse_big_a(DedispArgs a, float2* __restrict__ tbuf) {
+// Inverse pass A over a wave of units of one length N = 2^(15 + logr): row (p, k1)
+// of unit u times the chirp's row k1, inverse 2^15-point FFT, times w_N^{k1 n2}.
+// grid: n_units * M * R workgroups, logical id = (p R + k1) n_units + u (XCD-remapped).
+__global__ __launch_bounds__(Geo<kBigLog>::T) void k_dedisperse_big_a(DedispArgs a) {
   using G = Geo<kBigLog>;
   extern __shared__ float lds[];
   const int t = threadIdx.x;
   const int lin = xcd_remap(blockIdx.x, gridDim.x);
-  const int k1 = lin % R;
-  const int item = lin / R;  // ((p nblk + blk) nd + d)
-  const int d = item % a.nd, pb = item / a.nd;
-  const float2* x = a.spec + (size_t)pb * R * kBigN + k1;
-  const float2* h = a.chirp + (size_t)d * R * kBigN + k1;
+  const UnitItem w = a.units[lin % a.n_units];
+  const int row = lin / a.n_units;  // p R + k1
+  const int k1 = row & ((1 << a.logr) - 1);
+  const float2* x = a.spec + w.spec + (size_t)row * kBigN;
+  const float2* h = a.chirp + w.chirp + (size_t)k1 * kBigN;
   float2 v[G::P];
-  fft_workgroup<kBigLog, +1>(v, lds, t, [&](int i) { return cmul(x[(size_t)R * i], h[(size_t)R * i]); });
-  float2* out = tbuf + ((size_t)item * R + k1) * kBigN + opaque_zero(v[0].x);
+  fft_workgroup<kBigLog, +1>(v, lds, t, [&](int i) { return cmul(x[i], h[i]); });
+  float2* out = a.tb + w.tb + (size_t)row * kBigN + opaque_zero(v[0].x);
 #pragma unroll
   for (int u = 0; u < G::P / G::RL; ++u)
 #pragma unroll
     for (int q = 0; q < G::RL; ++q) {
       const int n2 = t + u * G::T + q * (G::N / G::RL);
-      out[n2] = cmul(v[u * G::RL + out_reg<G::RL>(q)], big_twiddle<R, +1>(n2 * k1));
+      out[n2] = cmul(v[u * G::RL + out_reg<G::RL>(q)], big_twiddle<+1>(k1 * n2, a.logr));
     }
 }
 
-// Pass B of the inverse transform + overlap-save discard + output conversion.
-// grid: (2^15 / 256, M * nblk * nd).
 template <int R, int OUT>
-__global__ __launch_bounds__(256) void k_dedisperse_big_b(DedispArgs a, const float2* __restrict__ tbuf) {
-  const int n2 = blockIdx.x * 256 + threadIdx.x;
-  const int item = blockIdx.y;
-  const int d = item % a.nd, pb = item / a.nd;
-  const int blk = pb % a.nblk, p = pb / a.nblk;
+__device__ __forceinline__ void dedisperse_big_b(const float2* t0, int n2, int lead, int valid, float scale,
+                                                 typename YType<OUT>::T* y) {
   float2 v[R];
 #pragma unroll
-  for (int k1 = 0; k1 < R; ++k1) v[k1] = tbuf[((size_t)item * R + k1) * kBigN + n2];
+  for (int k1 = 0; k1 < R; ++k1) v[k1] = t0[(size_t)k1 * kBigN + n2];
   dft_reg<R, +1>(v);
-  const float scale = (OUT == 0) ? 1.f : *a.scale;
-  typedef typename YType<OUT>::T YT;
-  YT* y = reinterpret_cast<YT*>(a.y) + ((size_t)d * a.n_ant + p) * a.y_stride + (size_t)blk * a.valid;
 #pragma unroll
   for (int n1 = 0; n1 < R; ++n1) {
     const int n = n1 * kBigN + n2;
-    if (n >= a.lead && n < a.lead + a.valid) y[n - a.lead] = convert_y<OUT>(v[out_reg<R>(n1)], scale);
+    if (n >= lead && n < lead + valid) y[n - lead] = convert_y<OUT>(v[out_reg<R>(n1)], scale);
   }
+}
+
+// Inverse pass B: R-point DFT over k1, overlap-save discard, output conversion.
+// grid: (2^15 / 256, n_units * M), blockIdx.y = p * n_units + u.
+template <int OUT>
+__global__ __launch_bounds__(256) void k_dedisperse_big_b(DedispArgs a) {
+  const int n2 = blockIdx.x * 256 + threadIdx.x;
+  const int p = blockIdx.y / a.n_units;
+  const UnitItem w = a.units[blockIdx.y % a.n_units];
+  const float2* t0 = a.tb + w.tb + ((size_t)p << (kBigLog + a.logr));
+  const float scale = (OUT == 0) ? 1.f : a.scale[w.chan];
+  typedef typename YType<OUT>::T YT;
+  YT* y = reinterpret_cast<YT*>(a.y) + w.y + (size_t)p * a.y_stride;
+  if (a.logr == 1) dedisperse_big_b<2, OUT>(t0, n2, w.lead, w.valid, scale, y);
+  else if (a.logr == 2) dedisperse_big_b<4, OUT>(t0, n2, w.lead, w.valid, scale, y);
+  else dedisperse_big_b<8, OUT>(t0, n2, w.lead, w.valid, scale, y);
 }
 
 // ---------------------------------------------------------------------------
@@ -320,19 +376,35 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 //   Re V_ij = (G[i][j] + G[M+i][M+j]) / s^2,  Im V_ij = (G[j][M+i] - G[i][M+j]) / s^2
 // (s = correlator-input scale, 1 for FP32).  Samples are staged through LDS in
 // chunks of kCorrKC; the next chunk's global loads are issued before the current
-// chunk's MFMAs.  grid: n_dumps * nd workgroups of 256 threads (4 waves),
-// logical id = m * nd + d.
+// chunk's MFMAs.  grid: n_units * max_dumps workgroups of 256 threads (4 waves),
+// one per (unit, dump); workgroups past a unit's last dump exit at once.
 struct CorrArgs {
   const void* y;
-  int64_t y_stride;      // samples per (d, p) row
   float2* ring;
+  const UnitItem* units;
+  const float* scale;    // [C] correlator-input scales s_c (all formats)
+  int64_t y_stride;      // samples per antenna row of y
   int64_t rec_elems;     // complex values per dump record
   int64_t ring_dumps;    // ring capacity in dumps
-  int64_t dump0;         // absolute dump index of y sample 0
-  const int32_t* dm_pos; // [nd] record position (dm_offset[c] + d) of each DM of the group
-  const float* scale;    // device scalar s_c: correlator-input scale (all formats)
-  int32_t n_dumps, nd, n_ant, dump_len, nbl, out_mode;
+  int32_t max_dumps;     // dumps per unit covered by the grid
+  int32_t n_ant, dump_len, nbl, out_mode;
 };
+
+// The (unit, dump) of workgroup `item`; false when the unit has fewer dumps.
+struct CorrJob {
+  int64_t yoff;   // element offset in y of the dump's first sample, antenna 0
+  float2* out;    // the (channel, DM) slot of the dump's record
+  int32_t chan;
+};
+__device__ __forceinline__ bool corr_job(const CorrArgs& a, int item, CorrJob& j) {
+  const UnitItem w = a.units[item / a.max_dumps];
+  const int m = item % a.max_dumps;
+  if (m >= w.n_dumps) return false;
+  j.yoff = w.y + (int64_t)m * a.dump_len;
+  j.out = a.ring + ((w.dump0 + m) % a.ring_dumps) * a.rec_elems + w.rec;
+  j.chan = w.chan;
+  return true;
+}
 
 // binary16 hi = rn(x) and lo = rn(x - hi); x - hi is exact in FP32
 __device__ __forceinline__ void split16(float x, _Float16& hi, _Float16& lo) {
@@ -371,8 +443,8 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
   __shared__ E at[Ld::ELEMS];
   __shared__ float gram[C::ROWS * C::GP];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int lin = blockIdx.x;
-  const int d = lin % a.nd, m = lin / a.nd;
+  CorrJob w;
+  if (!corr_job(a, blockIdx.x, w)) return;
   const int M = a.n_ant, L = a.dump_len;
   const int pairs = M * (kCorrKC / 2);
 
@@ -394,9 +466,9 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
     at[Ld::at(r, k)] = (E)0;
     if constexpr (T == 0) at[Ld::PLANE + Ld::at(r, k)] = (E)0;
   }
-  const float s_in = *a.scale;
-  const typename In::Y* y = reinterpret_cast<const typename In::Y*>(a.y) + (size_t)d * M * a.y_stride + (size_t)m * L;
-  // even dump length: pairs never straddle the end of the dump; odd: last pair loaded singly
+  const float s_in = a.scale[w.chan];
+  const typename In::Y* y = reinterpret_cast<const typename In::Y*>(a.y) + w.yoff;
+  // pairs that are 2-sample aligned and inside the dump are loaded as one vector, others singly
   auto load = [&](int k0, Pair* buf) {
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
@@ -405,7 +477,7 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
       if (e < pairs) {
         const int p = e / (kCorrKC / 2), k = k0 + 2 * (e % (kCorrKC / 2));
         const typename In::Y* row = y + (size_t)p * a.y_stride + k;
-        if (k + 1 < L && ((((size_t)(d * M + p) * a.y_stride + (size_t)m * L + k) & 1) == 0)) {
+        if (k + 1 < L && ((((size_t)w.yoff + (size_t)p * a.y_stride + k) & 1) == 0)) {
           v = *reinterpret_cast<const Pair*>(row);
         } else {
           typename In::Y s0{}, s1{};
@@ -476,8 +548,7 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
   }
   __syncthreads();
   const float inv = 1.f / (s_in * s_in);  // s is a power of two: exact
-  const int64_t dump = a.dump0 + m;
-  float2* out = a.ring + (dump % a.ring_dumps) * a.rec_elems + (int64_t)a.dm_pos[d] * a.nbl;
+  float2* out = w.out;
   if (a.out_mode == 0) {
     for (int b = tid; b < a.nbl; b += 256) {
       // invert b = i M - i (i - 1) / 2 + (j - i)
@@ -506,7 +577,8 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
 // (FP32 form: every product as hi*hi + hi*lo + lo*hi of binary16 halves).  Wave w
 // owns row tile w of block I against the four column tiles of block J, so its
 // block-I fragments are read once per k-step.  Writes V_ij for i <= j < M only.
-// grid: n_dumps * nd * NB (NB + 1) / 2 workgroups (NB = ceil(M / 64)), 256 threads.
+// grid: n_units * max_dumps * NB (NB + 1) / 2 workgroups (NB = ceil(M / 64)),
+// 256 threads, block pair fastest.
 constexpr int kBlkAnt = 64;
 
 template <int T> struct NegFrag;
@@ -534,20 +606,19 @@ __global__ __launch_bounds__(256) void k_correlate_blocks(CorrArgs a) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int M = a.n_ant, L = a.dump_len;
   const int nb = (M + kBlkAnt - 1) / kBlkAnt, npair = nb * (nb + 1) / 2;
-  int lin = blockIdx.x;
-  int pr = lin % npair;
-  lin /= npair;
-  const int d = lin % a.nd, m = lin / a.nd;
+  int pr = blockIdx.x % npair;
+  CorrJob w;
+  if (!corr_job(a, blockIdx.x / npair, w)) return;
   int I = 0;
   while (pr >= nb - I) { pr -= nb - I; ++I; }
   const int J = I + pr;
-  const float s_in = *a.scale;
+  const float s_in = a.scale[w.chan];
 
   floatx4 are[4], aim[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) are[q] = aim[q] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  const typename In::Y* y = reinterpret_cast<const typename In::Y*>(a.y) + (size_t)d * M * a.y_stride + (size_t)m * L;
+  const typename In::Y* y = reinterpret_cast<const typename In::Y*>(a.y) + w.yoff;
   // thread e -> (local antenna la in [0, 128): 0..63 block I, 64..127 block J; sample pair)
   auto ant_of = [&](int la) { return la < kBlkAnt ? I * kBlkAnt + la : J * kBlkAnt + (la - kBlkAnt); };
   auto load = [&](int k0, Pair* buf) {
@@ -559,7 +630,7 @@ __global__ __launch_bounds__(256) void k_correlate_blocks(CorrArgs a) {
       Pair v{};
       if (p < M) {
         const typename In::Y* row = y + (size_t)p * a.y_stride + k;
-        if (k + 1 < L && ((((size_t)(d * M + p) * a.y_stride + (size_t)m * L + k) & 1) == 0)) {
+        if (k + 1 < L && ((((size_t)w.yoff + (size_t)p * a.y_stride + k) & 1) == 0)) {
           v = *reinterpret_cast<const Pair*>(row);
         } else {
           typename In::Y s0{}, s1{};
@@ -641,8 +712,7 @@ __global__ __launch_bounds__(256) void k_correlate_blocks(CorrArgs a) {
     }
   }
   const float inv = 1.f / (s_in * s_in);
-  const int64_t dump = a.dump0 + m;
-  float2* out = a.ring + (dump % a.ring_dumps) * a.rec_elems + (int64_t)a.dm_pos[d] * a.nbl;
+  float2* out = w.out;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
 #pragma unroll
@@ -692,16 +762,13 @@ __global__ __launch_bounds__(1024) void k_scale(Source s, int32_t chan, int32_t 
 }
 
 // Zero the record slots of inactive DMs for the dumps of one call.
-__global__ void k_zero_dm(float2* ring, int64_t rec_elems, int64_t ring_dumps, int64_t dump0, int32_t n_dumps,
-                          const int32_t* dm_pos, int32_t n_pos, int32_t nbl) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t total = (int64_t)n_dumps * n_pos * nbl;
-  if (e >= total) return;
-  const int b = (int)(e % nbl);
-  const int64_t rest = e / nbl;
-  const int k = (int)(rest % n_pos);
-  const int64_t m = rest / n_pos;
-  ring[((dump0 + m) % ring_dumps) * rec_elems + (int64_t)dm_pos[k] * nbl + b] = make_float2(0.f, 0.f);
+// grid: one workgroup of 256 threads per item.
+__global__ __launch_bounds__(256) void k_zero_dm(float2* ring, const ZeroItem* items, const int32_t* slots,
+                                                 int32_t nbl) {
+  const ZeroItem w = items[blockIdx.x];
+  const int64_t total = (int64_t)w.n * nbl;
+  for (int64_t e = threadIdx.x; e < total; e += 256)
+    ring[w.rec + (int64_t)slots[w.pos + e / nbl] * nbl + e % nbl] = make_float2(0.f, 0.f);
 }
 
 // Carry the unconsumed input tail of one channel into the next history buffer.

@@ -13,7 +13,7 @@ def say(*a):
 
 
 def run_gpu(cfg, in_dtype="cf32", corr="f32", out_mode="packed", chunks=None, fft_len=None, mask=None,
-            max_block=None, chan_scale=None):
+            max_block=None, chan_scale=None, **plan_kw):
     """Run a whole stream through the library; returns (vis [dumps, record] complex64 numpy, layout)."""
     import torch
 
@@ -29,7 +29,7 @@ def run_gpu(cfg, in_dtype="cf32", corr="f32", out_mode="packed", chunks=None, ff
     fl = fft_len if fft_len is not None else (cfg.get("fft_len") or None)
     outs = []
     with Plan(m_ant, cfg["chan_freqs"], cfg["f_s"], cfg["dump_len"], max_block_samples=mb, in_dtype=in_dtype,
-              corr_dtype=corr, out_mode=out_mode, fft_len=fl, chan_scale=chan_scale) as p:
+              corr_dtype=corr, out_mode=out_mode, fft_len=fl, chan_scale=chan_scale, **plan_kw) as p:
         for c, dms in enumerate(cfg["dm_lists"]):
             p.set_dm_trials(dms, chan=c)
         if mask is not None:
@@ -61,8 +61,10 @@ def blockings(lay):
 
 
 def select(vis, lay, c, d):
+    """Visibilities of (channel c, DM d) from fetched records (its record slot)."""
     nbl = lay["n_baselines"]
-    o = int(lay["dm_offset"][c] + d)
+    o = int(lay["record_pos"][lay["dm_offset"][c] + d])
+    assert o >= 0, "(channel %d, DM %d) is not stored in the records" % (c, d)
     return vis[:, o * nbl:(o + 1) * nbl]
 
 

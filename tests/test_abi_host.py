@@ -129,3 +129,28 @@ def test_strerror_and_null_plan():
     assert L.ddx_plan_destroy(None) == ddx.OK
     assert L.ddx_process_block(None, None, 0, 0, None) == ddx.EINVAL
     assert L.ddx_set_dm_trials(None, 0, None, 0) == ddx.EINVAL
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of ddx_desc, ddx_layout and ddx_profile have the C sizes and field offsets."""
+    structs = {"ddx_desc": binding.Desc, "ddx_layout": binding.Layout, "ddx_profile": binding.Profile}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ddx.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            if f == "pad":
+                continue
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0; }")
+    src = tmp_path / "sizes.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "sizes"
+    import subprocess
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(ln.split()[:2]): int(ln.split()[2]) for ln in out if ln}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ct.sizeof(py), cname
+        for f, _ in py._fields_:
+            if f != "pad":
+                assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

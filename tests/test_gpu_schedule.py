@@ -1,0 +1,124 @@
+"""GPU tests of the batched schedule: work lists over all channels, waves of
+(channel, DM, block) units, two-pass transforms above 2^15 points, channels of
+different transform lengths in one plan, and compact dump records.
+
+Parity as elsewhere (1e-5 normalised against the FP64 oracle); the schedule
+itself must not change any result, so different wave sizes and DM groups are
+compared bitwise.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import compare_with_oracle, run_gpu, say, select
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.mark.parametrize("n", [1 << 16, 1 << 17, 1 << 18])
+def test_two_pass_transform_lengths(gpu, n):
+    """N = 2^16..2^18 (R = 2, 4, 8 rows of 2^15), several blocks and a ragged tail."""
+    cfg = synth.make_small(seed=60 + n % 97, m_ant=3, n_chan=1, s=2 * n + 12345, f_lo=1.3e9, f_s=1e6, n_dm=3,
+                           dm_max=500.0, dump_len=64, n_pulses=0)
+    say("two-pass N =", n)
+    vis, lay = run_gpu(cfg, fft_len=n)
+    assert lay["fft_len"][0] == n
+    err = compare_with_oracle(cfg, vis, lay)
+    say("N %d max normalised error %.3e" % (n, err))
+    assert err <= TOL
+
+
+def test_mixed_lengths_one_plan(gpu):
+    """Channels with 2^12-, 2^15- and 2^17-point blocks and uneven DM lists in one plan,
+    streamed in uneven chunks."""
+    cfg = synth.make_small(seed=64, m_ant=4, n_chan=3, s=300001, f_lo=0.7e9, f_s=1e6, n_dm=2, dm_max=50.0,
+                           dump_len=100, ci8=True, n_pulses=1)
+    cfg["dm_lists"] = [np.array([0.0, 20.0, 45.0]), np.array([500.0, 10.0]),
+                       np.array([0.0, 500.0, 1200.0, 2500.0])]
+    vis, lay = run_gpu(cfg, in_dtype="ci8", chunks=[70000, 1, 130000, 100000], max_block=130000)
+    say("lengths", lay["fft_len"], "valid", lay["valid"])
+    assert list(lay["fft_len"]) == [4096, 32768, 131072]
+    for c in range(3):
+        ref = oracle.blocking(cfg["chan_freqs"][c], 1e6, max(cfg["dm_lists"][c]), 100)
+        assert (lay["fft_len"][c], lay["valid"][c], lay["lead"][c]) == (ref["fft_len"], ref["valid"], ref["lead"])
+    err = compare_with_oracle(cfg, vis, lay)
+    say("mixed lengths max normalised error %.3e" % err)
+    assert err <= TOL
+
+
+def test_schedule_does_not_change_results(gpu):
+    cfg = synth.make_small(seed=65, m_ant=5, n_chan=3, s=40000, f_lo=1.3e9, f_s=1e6, n_dm=7, dm_max=300.0,
+                           dump_len=100, ci8=True, n_pulses=1)
+    cfg["dm_lists"][1] = cfg["dm_lists"][1][:3]
+    ref, lay = run_gpu(cfg, in_dtype="ci8")
+    say("auto schedule: wave_units %d dm_group %d" % (lay["wave_units"], lay["dm_group"]))
+    for wu, dg in [(1, 1), (5, 3), (16, 16), (1000, 2)]:
+        got, l2 = run_gpu(cfg, in_dtype="ci8", wave_units=wu, dm_group=dg)
+        assert l2["wave_units"] <= wu and l2["dm_group"] == min(dg, 7)
+        assert np.array_equal(got, ref), (wu, dg)
+
+
+def test_compact_records_match_full(gpu):
+    cfg = synth.make_small(seed=66, m_ant=4, n_chan=2, s=25000, f_lo=1.3e9, f_s=1e6, n_dm=6, dm_max=300.0,
+                           dump_len=100, n_pulses=1)
+    full, lay = run_gpu(cfg)
+    mask = [np.array([0, 1, 0, 0, 1, 1], np.uint8), np.array([1, 0, 0, 0, 0, 0], np.uint8)]
+    comp, lc = run_gpu(cfg, mask=mask, compact_records=True, max_record_pairs=4)
+    assert lc["record_pairs"] == 4 and comp.shape[1] == 4 * lc["n_baselines"]
+    pos = lc["record_pos"]
+    assert list(pos) == [-1, 0, -1, -1, 1, 2, 3, -1, -1, -1, -1, -1]
+    for c in range(2):
+        for d in range(6):
+            if mask[c][d]:
+                assert np.array_equal(select(comp, lc, c, d), select(full, lay, c, d))
+
+
+def test_compact_records_state_rules(gpu):
+    import torch
+
+    from paper_1109_3186_amd import DdxError, Plan
+    cfg = synth.make_small(seed=67, m_ant=3, n_chan=2, s=20000, f_lo=1.3e9, f_s=1e6, n_dm=4, dm_max=200.0,
+                           dump_len=100, n_pulses=0)
+    with Plan(3, cfg["chan_freqs"], 1e6, 100, max_block_samples=20000, in_dtype="cf32", compact_records=True,
+              max_record_pairs=3) as p:
+        p.set_dm_trials(cfg["dm_lists"][0])
+        lay = p.layout()
+        assert lay["record_pairs"] == 0  # 8 pairs exceed the capacity: nothing active until chosen
+        with pytest.raises(DdxError):
+            p.set_active_dms(np.ones(4, np.uint8), chan=0)  # 4 > 3
+        p.set_active_dms(np.array([1, 0, 1, 0], np.uint8), chan=0)
+        p.set_active_dms(np.array([0, 0, 0, 1], np.uint8), chan=1)
+        assert p.layout()["record_pairs"] == 3
+        x = torch.from_numpy(cfg["volts"][:, :, :10000].copy()).cuda()
+        p.process_block(x)
+        torch.cuda.synchronize()
+        if p.layout()["dumps_ready"] > 0:
+            with pytest.raises(DdxError):
+                p.set_active_dms(np.array([0, 0, 0, 0], np.uint8), chan=1)  # unfetched dumps
+        p.fetch()
+        torch.cuda.synchronize()
+        with pytest.raises(DdxError):
+            p.set_active_dms(np.array([0, 0, 1, 1], np.uint8), chan=1)  # 2 + 2 > 3
+        p.set_active_dms(np.array([0, 1, 0, 0], np.uint8), chan=1)
+        lay = p.layout()
+        assert lay["record_pairs"] == 3 and list(lay["record_pos"]) == [0, -1, 1, -1, -1, 2, -1, -1]
+
+
+def test_c3_shape_sampled(gpu):
+    """256 antennas at 0.7 GHz with per-channel DM grids up to 3000 (two-pass 2^18 and
+    2^17 blocks, antenna-block correlator), sampled (channel, DM) pairs against the oracle."""
+    p3 = synth.c3_params()
+    cfg = synth.make_small(seed=68, m_ant=256, n_chan=2, s=200000, f_lo=p3["f_lo"], f_s=1e6, n_dm=3,
+                           dm_max=3000.0, dump_len=1000, ci8=True, n_pulses=1, radius_m=2500.0)
+    cfg["dm_lists"] = [np.array([0.0, 750.0, 1500.0, 2250.0, 2990.0]), np.arange(3) * 3000.0 / 3]
+    say("C3 shape: 256 ant, 2 ch at 0.7 GHz, 200000 ci8 samples, DMs 5 + 3 up to 2990")
+    vis, lay = run_gpu(cfg, in_dtype="ci8")
+    say("lengths", lay["fft_len"], "valid", lay["valid"], "dumps", vis.shape[0])
+    assert list(lay["fft_len"]) == [1 << 18, 1 << 17]
+    assert vis.shape[0] == 200
+    err = compare_with_oracle(cfg, vis, lay, pairs=[(0, 4), (1, 1)])
+    say("C3 shape max normalised error %.3e" % err)
+    assert err <= TOL
