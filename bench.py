@@ -79,15 +79,17 @@ def cpu_baseline(chunks, fc, dms, lay, p, n_dm):
     import oracle
     x = np.concatenate([c[0].cpu().numpy() for c in chunks], axis=-1)[None]
     bl = [{"fft_len": int(lay["fft_len"][0]), "valid": int(lay["valid"][0]), "lead": int(lay["lead"][0])}]
-    ds = [0, len(dms) - 1][:n_dm] if n_dm <= 2 else list(np.linspace(0, len(dms) - 1, n_dm).astype(int))
-    t0 = time.time()
-    out = oracle.run_oracle(x, fc[:1], p["f_s"], [dms], p["dump_len"], bl, chans=[0], dm_index=ds)
-    el = time.time() - t0
+    from threadpoolctl import threadpool_limits
+    ds = [0, len(dms) - 1][:n_dm] if n_dm <= 2 else [int(v) for v in np.linspace(0, len(dms) - 1, n_dm).round()]
+    with threadpool_limits(limits=1):  # the BLAS matrix products of the dumps on one thread, like the FFTs
+        t0 = time.time()
+        out = oracle.run_oracle(x, fc[:1], p["f_s"], [dms], p["dump_len"], bl, chans=[0], dm_index=ds)
+        el = time.time() - t0
     nd = next(iter(out.values())).shape[0]
     units = p["m_ant"] * nd * p["dump_len"] * len(ds)
     return {"value": units / el, "unit": UNIT, "cores": 1, "kind": "oracle",
-            "sample": "channel 0 x %d DMs (trials %s) x %d antennas x %d samples, FP64 numpy, %.1f s "
-                      "(numpy FFT and einsum run single-threaded)" % (len(ds), ds, p["m_ant"], p["samples"], el)}
+            "sample": "channel 0 x %d DMs (trials %s) x %d antennas x %d samples, FP64 numpy on one thread, "
+                      "%.1f s" % (len(ds), ds, p["m_ant"], p["samples"], el)}
 
 
 def learned_form(plan, chunks, pulses, p, out, steps, plain_ms):
@@ -134,6 +136,126 @@ def learned_form(plan, chunks, pulses, p, out, steps, plain_ms):
                     "(either neighbour) is active"}
 
 
+def run_c3(args, dev):
+    """The batched sparse-array workload: 256 antennas, 32 x 1 MHz channels at
+    0.7-0.732 GHz, 2^18 ci8 samples, per-channel DM grids of 512..1536 trials over
+    0-3000 (transform lengths 2^17 / 2^18, two-pass).  Its 2.26 TB of visibilities
+    cannot be held, so one step runs the stream once per DM window: every channel's
+    DM list is cut into `passes` contiguous windows, the plan's compact records
+    hold one window's (channel, DM) pairs, and each pass fetches its dumps into a
+    device buffer that the next pass reuses."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1109_3186_amd import Plan, autotune
+
+    p = synth.c3_params()
+    t0 = time.time()
+    x, pulses, fc, pos = synth.make_stream_device(p, dev)
+    torch.cuda.synchronize()
+    log("C3 input built in %.1f s" % (time.time() - t0))
+    s, L, M = p["samples"], p["dump_len"], p["m_ant"]
+    dms = [synth.dm_grid(n, p["dm_max"]) for n in p["n_dm"]]
+    kw = {}
+    if args.autotune:
+        tuned = autotune.tune(M, fc, p["f_s"], L, dms, corr_dtype=args.corr, max_block=s, log=log)
+        kw = autotune.plan_kwargs(tuned)
+        log("tuned (%s): lengths %s wave %d group %d" % (tuned["source"], sorted(set(tuned["fft_len"])),
+                                                          tuned["wave_units"], tuned["dm_group"]))
+    passes = args.passes or math.ceil(sum(p["n_dm"]) / 512)
+    windows = [np.array_split(np.arange(n), passes) for n in p["n_dm"]]
+    max_pairs = max(sum(len(windows[c][k]) for c in range(p["n_chan"])) for k in range(passes))
+    ring = s // L + 2
+    plan = Plan(M, fc, p["f_s"], L, max_block_samples=s, in_dtype="ci8", corr_dtype=args.corr, out_mode="packed",
+                compact_records=True, max_record_pairs=max_pairs, ring_dumps=ring, **kw)
+    for c, d in enumerate(dms):
+        plan.set_dm_trials(d, chan=c)
+    lay = plan.layout()
+    nbl = lay["n_baselines"]
+    log("C3 plan: lengths %s, %d passes of <= %d pairs, ring %d dumps, %.1f GB device" % (
+        sorted(set(int(n) for n in lay["fft_len"])), passes, max_pairs, ring, lay["device_bytes"] / 1e9))
+    out = torch.empty((ring, max_pairs * nbl), dtype=torch.complex64, device=dev)
+    masks = []
+    for k in range(passes):
+        mk = []
+        for c, n in enumerate(p["n_dm"]):
+            m = np.zeros(n, np.uint8)
+            m[windows[c][k]] = 1
+            mk.append(m)
+        masks.append(mk)
+
+    def step():
+        got = 0
+        for k in range(passes):
+            plan.reset_stream()
+            for c in range(p["n_chan"]):
+                plan.set_active_dms(masks[k][c], chan=c)
+            plan.process_block(x, flush=True)
+            _, nd, _ = plan.fetch(out=out)
+            got += nd
+        return got
+
+    for w in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log("warmup %d done" % w)
+    plan.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        got = step()
+        log("step %d enqueued" % k)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    prof = plan.profile()
+    plan.set_profiling(False)
+    n_dumps = got // passes
+    units = M * n_dumps * L * sum(p["n_dm"])
+    value = units / (ms / 1e3)
+    log("C3 per step: %.1f ms, %.3e units/s; kernels: %s" % (
+        ms, value, {k: round(v["time_ms"] / args.steps, 1) for k, v in prof.items()}))
+    roofline = roofline_of(prof, args)
+    rec = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.corr, "data": "synthetic",
+        "config": {"workload": "256 ant x 32 ch x 2^18 ci8 samples, 512..1536 DMs per channel 0-3000, "
+                               "N %s, 1 ms dumps, %d DM-window passes" % (
+                                   "/".join(str(n) for n in sorted(set(int(v) for v in lay["fft_len"]))), passes),
+                   "n_ant": M, "n_chan": p["n_chan"], "samples": s, "n_dm_total": int(sum(p["n_dm"])),
+                   "dump_len": L, "passes": passes, "input": "ci8", "corr": args.corr,
+                   "schedule": {"wave_units": lay["wave_units"], "dm_group": lay["dm_group"],
+                                "autotuned": bool(args.autotune)}, "parallelism": "none (1 GPU)"},
+        "roofline": roofline, "cpu_baseline": None, "learned": None,
+    }
+    print(json.dumps(rec), flush=True)
+    plan.close()
+
+
+def roofline_of(prof, args):
+    """Roofline of the dominant kernel kind from the library's event timings."""
+    dom = max(prof, key=lambda k: prof[k]["time_ms"])
+    d = prof[dom]
+    per_launch_s = d["time_ms"] / 1e3 / max(d["launches"], 1)
+    if dom == "correlate":
+        bound, peak = "mfma", {"f32": PEAKS["fp32_mfma_tflops"], "f16": PEAKS["fp16_mfma_tflops"],
+                               "e4m3": PEAKS["fp8_mfma_tflops"]}[args.corr]
+    else:
+        bound, peak = "alu", PEAKS["fp32_vector_tflops"]
+    achieved = d["flops"] / max(d["launches"], 1) / per_launch_s / 1e12
+    return {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": measured_traffic(dom, args.workload), "kernel": dom,
+            "avg_launch_ms": round(per_launch_s * 1e3, 4),
+            "kernels": {k: {"ms_per_step": round(v["time_ms"] / args.steps, 2),
+                            "launches_per_step": v["launches"] // args.steps,
+                            "tflops": round(v["flops"] / max(v["time_ms"], 1e-9) / 1e9, 2),
+                            "staged_gbs": round(v["bytes"] / max(v["time_ms"], 1e-9) / 1e6, 1)}
+                        for k, v in prof.items() if v["launches"]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,8 +264,18 @@ def main():
     ap.add_argument("--corr", default="f32", choices=["f32", "f16", "e4m3"])
     ap.add_argument("--chunk", type=int, default=1 << 18, help="samples per process_block call")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-dms", type=int, default=2)
+    ap.add_argument("--cpu-dms", type=int, default=12, help="DM trials of the oracle's timed slice")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal measurement")
+    ap.add_argument("--wave-units", type=int, default=0, help="schedule: units per wave (0 = automatic)")
+    ap.add_argument("--dm-group", type=int, default=0, help="schedule: DMs per block group (0 = automatic)")
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3"],
+                    help="c1: 36-antenna headline workload (default); c3: 256-antenna batched sparse array")
+    ap.add_argument("--autotune", action="store_true", help="use the autotuned lengths and schedule (cached)")
+    ap.add_argument("--passes", type=int, default=0, help="c3: DM-window passes (0 = ceil(sum D / 512))")
+    ap.add_argument("--channels", type=int, default=0,
+                    help="run only the first CHANNELS channels (a smaller workload for counter runs; 0 = all)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="before the steps, run one elementwise copy kernel of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (requested %d)" % args.gpus,
@@ -157,16 +289,35 @@ def main():
     from paper_1109_3186_amd import Plan
 
     dev = torch.device("cuda:0")
+    if args.workload == "c3":
+        return run_c3(args, dev)
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)
+        dst = torch.mul(src, 1.0)  # reads and writes copy_calibration MiB each
+        torch.cuda.synchronize()
+        log("copy calibration: %d MiB read, %d MiB written by one elementwise kernel" % (
+            args.copy_calibration, args.copy_calibration))
+        del src, dst
     p = synth.c1_params()
+    if args.channels:
+        p["n_chan"] = min(args.channels, p["n_chan"])
     chunks, pulses, fc = build_input(p, dev, args.chunk)
     dms = synth.dm_grid(p["n_dm"], p["dm_max"])
+    kw = {"wave_units": args.wave_units, "dm_group": args.dm_group}
+    if args.autotune:
+        from paper_1109_3186_amd import autotune
+        tuned = autotune.tune(p["m_ant"], fc, p["f_s"], p["dump_len"], [dms] * p["n_chan"], corr_dtype=args.corr,
+                              max_block=args.chunk, log=log)
+        kw = autotune.plan_kwargs(tuned)
+        log("tuned (%s): lengths %s wave %d group %d" % (tuned["source"], sorted(set(tuned["fft_len"])),
+                                                          tuned["wave_units"], tuned["dm_group"]))
     plan = Plan(p["m_ant"], fc, p["f_s"], p["dump_len"], max_block_samples=args.chunk, in_dtype="ci8",
-                corr_dtype=args.corr, out_mode="packed")
+                corr_dtype=args.corr, out_mode="packed", **kw)
     plan.set_dm_trials(dms)
     lay = plan.layout()
-    log("plan: N %d V %d..%d lead %d, ring %d dumps, %.1f GB device" % (
+    log("plan: N %d V %d..%d lead %d, ring %d dumps, %.1f GB device, wave %d units, DM group %d" % (
         lay["fft_len"][0], lay["valid"].min(), lay["valid"].max(), lay["lead"][0], lay["ring_dumps"],
-        lay["device_bytes"] / 1e9))
+        lay["device_bytes"] / 1e9, lay["wave_units"], lay["dm_group"]))
     out = torch.empty((lay["ring_dumps"], lay["record_elems"]), dtype=torch.complex64, device=dev)
 
     def step():
@@ -198,23 +349,7 @@ def main():
     log("per step: %.1f ms, %.3e units/s; kernels: %s" % (
         ms, value, {k: round(v["time_ms"] / args.steps, 1) for k, v in prof.items()}))
 
-    dom = max(prof, key=lambda k: prof[k]["time_ms"])
-    d = prof[dom]
-    per_launch_s = d["time_ms"] / 1e3 / max(d["launches"], 1)
-    if dom == "correlate":
-        bound, peak = "mfma", {"f32": PEAKS["fp32_mfma_tflops"], "f16": PEAKS["fp16_mfma_tflops"],
-                               "e4m3": PEAKS["fp8_mfma_tflops"]}[args.corr]
-    else:
-        bound, peak = "alu", PEAKS["fp32_vector_tflops"]
-    achieved = d["flops"] / max(d["launches"], 1) / per_launch_s / 1e12
-    roofline = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": measured_traffic(dom, "c1"), "kernel": dom,
-                "avg_launch_ms": round(per_launch_s * 1e3, 4),
-                "kernels": {k: {"ms_per_step": round(v["time_ms"] / args.steps, 2),
-                                "launches_per_step": v["launches"] // args.steps,
-                                "tflops": round(v["flops"] / max(v["time_ms"], 1e-9) / 1e9, 2),
-                                "staged_gbs": round(v["bytes"] / max(v["time_ms"], 1e-9) / 1e6, 1)}
-                            for k, v in prof.items() if v["launches"]}}
+    roofline = roofline_of(prof, args)
     learned = None
     if not args.no_learned:
         learned = learned_form(plan, chunks, pulses, p, out, args.steps, ms)
@@ -226,8 +361,8 @@ def main():
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"f32": "f32", "f16": "f16", "e4m3": "e4m3"}[args.corr], "data": "synthetic",
-        "config": {"workload": "36 ant x 64 ch x 2^20 ci8 samples, 256 DMs 0-2000, N %d, 1 ms dumps"
-                               % lay["fft_len"][0],
+        "config": {"workload": "36 ant x %d ch x 2^20 ci8 samples, 256 DMs 0-2000, N %d, 1 ms dumps"
+                               % (p["n_chan"], lay["fft_len"][0]),
                    "n_ant": p["m_ant"], "n_chan": p["n_chan"], "samples": p["samples"], "n_dm": p["n_dm"],
                    "dump_len": p["dump_len"], "fft_len": int(lay["fft_len"][0]), "chunk": args.chunk,
                    "input": "ci8", "corr": args.corr, "parallelism": "none (1 GPU)"},

@@ -153,7 +153,9 @@ int ddx_set_dm_trials(ddx_plan* plan, int32_t chan, const double* dm_pc_cm3, int
  * between calls.  Compact records: the record holds the active (channel, DM)
  * pairs only, channel-major in DM order (record_pos in the layout); the mask
  * may change only when every dump produced so far has been fetched (ESTATE
- * otherwise), and EINVAL if more pairs than max_record_pairs would be active. */
+ * otherwise), and EINVAL if more pairs than max_record_pairs would be active.
+ * Host state only: no device work and no synchronisation; the next
+ * ddx_process_block takes the new set. */
 int ddx_set_active_dms(ddx_plan* plan, int32_t chan, const uint8_t* mask);
 
 /* Export the blocking, tables and stream counters.  Pointers refer to

@@ -165,6 +165,7 @@ class Plan:
         self._h = h
         self.n_ant = n_ant
         self.in_dtype = in_dtype
+        self.max_block = int(max_block_samples)
 
     def _check(self, rc, what):
         if rc != OK:

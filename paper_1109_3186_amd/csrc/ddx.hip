@@ -102,9 +102,10 @@ struct ddx_plan {
   int64_t ring_dumps = 0;
   double* gtab = nullptr;      // [sum N_c] FP64 g_c[k]
   std::vector<int64_t> gtab_off;
-  int32_t* slots_dev = nullptr;  // [sum D_c] per channel: active slots, then inactive slots
+  std::vector<int32_t> slots;    // [sum D_c] per channel: active record slots, then inactive ones
   std::vector<int> n_active;
   float* scale_dev = nullptr;    // [C]
+  double* scale_part = nullptr;  // [C][M] partial power sums of the scale rule
   char* items_dev = nullptr;     // work lists of one call
   size_t items_cap = 0;
   char* stage[2] = {nullptr, nullptr};  // pinned host staging of the work lists
@@ -187,8 +188,8 @@ void free_device(ddx_plan* p) {
   p->spec_elems = p->tb_elems = 0;
   p->ybuf = nullptr;
   p->gtab = nullptr;
-  p->slots_dev = nullptr;
   p->scale_dev = nullptr;
+  p->scale_part = nullptr;
   p->items_dev = nullptr;
   p->items_cap = 0;
   p->tile_power = nullptr;
@@ -416,11 +417,13 @@ void build_layout(ddx_plan* p) {
 }
 
 // Record slots of the active DMs (compact records: active pairs numbered in
-// order; full records: dm_offset[c] + d) and the per-channel slot table on the
-// device (active slots first, then inactive ones, which k_zero_dm clears).
-int upload_active(ddx_plan* p, hipStream_t s) {
+// order; full records: dm_offset[c] + d) and the per-channel slot table (active
+// slots first, then inactive ones, which k_zero_dm clears).  Host state only:
+// the next ddx_process_block copies what its kernels need.
+void update_active(ddx_plan* p) {
   const int64_t total = p->dm_off[p->C];
-  std::vector<int32_t> slots(total);
+  std::vector<int32_t>& slots = p->slots;
+  slots.assign(total, 0);
   p->rec_pos.assign(total, -1);
   p->n_active.assign(p->C, 0);
   int64_t next = 0;
@@ -444,9 +447,6 @@ int upload_active(ddx_plan* p, hipStream_t s) {
   }
   p->rec_pairs = p->compact ? next : total;
   p->rec_elems = p->rec_pairs * p->nbl;
-  HIPCHECK(p, hipMemcpyAsync(p->slots_dev, slots.data(), slots.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  HIPCHECK(p, hipStreamSynchronize(s));
-  return DDX_OK;
 }
 
 // Largest number of blocks of channel c that one call can run: the history (< N)
@@ -503,7 +503,8 @@ int setup_device(ddx_plan* p) {
   if ((rc = dev_alloc(p, (void**)&p->ring, (size_t)p->ring_dumps * p->cap_pairs * p->nbl * sizeof(float2)))) return rc;
   // work lists of one call
   p->items_cap = align_up(max_fwd * sizeof(ddx::FwdItem)) + align_up(max_units * sizeof(ddx::UnitItem)) +
-                 align_up(max_units * sizeof(ddx::ChirpItem)) + align_up(max_zero * sizeof(ddx::ZeroItem));
+                 align_up(max_units * sizeof(ddx::ChirpItem)) + align_up(max_zero * sizeof(ddx::ZeroItem)) +
+                 align_up(p->dm_off[p->C] * sizeof(int32_t)) + p->C * sizeof(ddx::ScaleItem);
   if ((rc = dev_alloc(p, (void**)&p->items_dev, p->items_cap))) return rc;
   for (int i = 0; i < 2; ++i) {
     if (hipHostMalloc((void**)&p->stage[i], p->items_cap, hipHostMallocDefault) != hipSuccess) {
@@ -526,8 +527,8 @@ int setup_device(ddx_plan* p) {
     }
   }
   if ((rc = dev_alloc(p, (void**)&p->gtab, g.size() * sizeof(double)))) return rc;
-  if ((rc = dev_alloc(p, (void**)&p->slots_dev, p->dm_off[p->C] * sizeof(int32_t)))) return rc;
   if ((rc = dev_alloc(p, (void**)&p->scale_dev, p->C * sizeof(float)))) return rc;
+  if ((rc = dev_alloc(p, (void**)&p->scale_part, (size_t)p->C * p->M * sizeof(double)))) return rc;
   HIPCHECK(p, hipMemcpy(p->gtab, g.data(), g.size() * sizeof(double), hipMemcpyHostToDevice));
   HIPCHECK(p, hipMemcpy(p->scale_dev, p->lay_scale.data(), p->C * sizeof(float), hipMemcpyHostToDevice));
   if (p->compact) {
@@ -536,7 +537,7 @@ int setup_device(ddx_plan* p) {
     if (na > p->cap_pairs)
       for (auto& c : p->ch) std::fill(c.active.begin(), c.active.end(), 0);  // the caller selects a subset
   }
-  if ((rc = upload_active(p, nullptr))) return rc;
+  update_active(p);
   return DDX_OK;
 }
 
@@ -656,8 +657,8 @@ int ddx_set_active_dms(ddx_plan* p, int32_t chan, const uint8_t* mask) {
   }
   for (int c = c0; c < c1; ++c)
     for (size_t d = 0; d < p->ch[c].dm.size(); ++d) p->ch[c].active[d] = mask ? (mask[d] != 0) : 1;
-  if (p->last_stream) HIPCHECK(p, hipStreamSynchronize(p->last_stream));
-  return upload_active(p, p->last_stream);
+  update_active(p);
+  return DDX_OK;
 }
 
 int ddx_get_layout(const ddx_plan* pc, ddx_layout* o) {
@@ -719,6 +720,7 @@ struct CallLists {
   std::vector<ddx::ChirpItem> chirps;
   std::vector<Wave> waves;
   std::vector<ddx::ZeroItem> zeros;
+  std::vector<ddx::ScaleItem> scales;
 };
 
 // Build the lists for blocks [b0[c], b_end[c]) of every channel; out_end[c] is the
@@ -853,11 +855,14 @@ void build_lists(ddx_plan* p, const std::vector<int64_t>& b_end, const std::vect
 // ordered: the previous call's kernels have read the device copy before this
 // copy overwrites it).  Returns the device addresses of the four lists.
 int upload_lists(ddx_plan* p, const CallLists& w, hipStream_t s, ddx::FwdItem** fwd, ddx::UnitItem** units,
-                 ddx::ChirpItem** chirps, ddx::ZeroItem** zeros) {
+                 ddx::ChirpItem** chirps, ddx::ZeroItem** zeros, int32_t** slots, ddx::ScaleItem** scales) {
   const size_t o1 = align_up(w.fwd.size() * sizeof(ddx::FwdItem));
   const size_t o2 = o1 + align_up(w.units.size() * sizeof(ddx::UnitItem));
   const size_t o3 = o2 + align_up(w.chirps.size() * sizeof(ddx::ChirpItem));
-  const size_t bytes = o3 + w.zeros.size() * sizeof(ddx::ZeroItem);
+  const size_t o4 = o3 + align_up(w.zeros.size() * sizeof(ddx::ZeroItem));
+  const size_t n_slots = w.zeros.empty() ? 0 : p->slots.size();
+  const size_t o5 = o4 + align_up(n_slots * sizeof(int32_t));
+  const size_t bytes = o5 + w.scales.size() * sizeof(ddx::ScaleItem);
   if (bytes > p->items_cap) return fail(p, DDX_EINVAL, "internal: work lists of %zu bytes exceed %zu", bytes, p->items_cap);
   const int k = p->stage_cur;
   if (p->stage_used[k]) HIPCHECK(p, hipEventSynchronize(p->stage_ev[k]));
@@ -866,6 +871,8 @@ int upload_lists(ddx_plan* p, const CallLists& w, hipStream_t s, ddx::FwdItem** 
   if (!w.units.empty()) std::memcpy(h + o1, w.units.data(), w.units.size() * sizeof(ddx::UnitItem));
   if (!w.chirps.empty()) std::memcpy(h + o2, w.chirps.data(), w.chirps.size() * sizeof(ddx::ChirpItem));
   if (!w.zeros.empty()) std::memcpy(h + o3, w.zeros.data(), w.zeros.size() * sizeof(ddx::ZeroItem));
+  if (n_slots) std::memcpy(h + o4, p->slots.data(), n_slots * sizeof(int32_t));
+  if (!w.scales.empty()) std::memcpy(h + o5, w.scales.data(), w.scales.size() * sizeof(ddx::ScaleItem));
   if (bytes) HIPCHECK(p, hipMemcpyAsync(p->items_dev, h, bytes, hipMemcpyHostToDevice, s));
   HIPCHECK(p, hipEventRecord(p->stage_ev[k], s));
   p->stage_used[k] = true;
@@ -874,6 +881,8 @@ int upload_lists(ddx_plan* p, const CallLists& w, hipStream_t s, ddx::FwdItem** 
   *units = reinterpret_cast<ddx::UnitItem*>(p->items_dev + o1);
   *chirps = reinterpret_cast<ddx::ChirpItem*>(p->items_dev + o2);
   *zeros = reinterpret_cast<ddx::ZeroItem*>(p->items_dev + o3);
+  *slots = reinterpret_cast<int32_t*>(p->items_dev + o4);
+  *scales = reinterpret_cast<ddx::ScaleItem*>(p->items_dev + o5);
   return DDX_OK;
 }
 
@@ -921,11 +930,24 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
 
   CallLists w;
   build_lists(p, b_end, out_end, w);
+  // correlator-input scale of each channel whose first block runs now (window [0, N - lead))
+  if (!p->have_scale)
+    for (int i = 0; i < p->C; ++i) {
+      Chan& c = p->ch[i];
+      if (b_end[i] <= c.blocks_done || c.blocks_done != 0) continue;
+      ddx::ScaleItem si{};
+      si.n = std::min<int64_t>(c.fft_len - c.lead, total);
+      si.hist_start = c.hist_start;
+      si.chan = i;
+      w.scales.push_back(si);
+    }
   ddx::FwdItem* fwd_dev;
   ddx::UnitItem* units_dev;
   ddx::ChirpItem* chirps_dev;
   ddx::ZeroItem* zeros_dev;
-  int rc = upload_lists(p, w, s, &fwd_dev, &units_dev, &chirps_dev, &zeros_dev);
+  int32_t* slots_dev;
+  ddx::ScaleItem* scales_dev;
+  int rc = upload_lists(p, w, s, &fwd_dev, &units_dev, &chirps_dev, &zeros_dev, &slots_dev, &scales_dev);
   if (rc) return rc;
 
   ddx::Source src{};
@@ -936,18 +958,22 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
   src.chunk_start = p->recv;
   src.chunk_len = n;
 
-  // correlator-input scale of each channel, fixed from its first block window
-  for (int i = 0; i < p->C; ++i) {
-    Chan& c = p->ch[i];
-    if (b_end[i] <= c.blocks_done || c.blocks_done != 0 || p->have_scale) continue;
+  if (!w.scales.empty()) {
     const float target = p->corr_dtype == DDX_CORR_E4M3 ? kScaleTargetE4M3 : kScaleTargetF16;  // F32 too
-    const int64_t nwin = std::min<int64_t>(c.fft_len - c.lead, total);
-    src.hist_start = c.hist_start;
-    HIPCHECK(p, timed(p, s, DDX_K_OTHER, 0.0, (double)nwin * p->M * in_bytes(p->in_dtype), [&] {
+    double bytes = 0;
+    for (auto& si : w.scales) bytes += (double)si.n * p->M * in_bytes(p->in_dtype);
+    const int ns = (int)w.scales.size();
+    HIPCHECK(p, timed(p, s, DDX_K_OTHER, 0.0, bytes, [&] {
       if (p->in_dtype == DDX_IN_CI8)
-        hipLaunchKernelGGL(ddx::k_scale<0>, dim3(1), dim3(1024), 0, s, src, i, p->M, nwin, target, p->scale_dev);
+        hipLaunchKernelGGL(ddx::k_scale_part<0>, dim3(ns * p->M), dim3(256), 0, s, src,
+                           (const ddx::ScaleItem*)scales_dev, p->M, p->scale_part);
       else
-        hipLaunchKernelGGL(ddx::k_scale<1>, dim3(1), dim3(1024), 0, s, src, i, p->M, nwin, target, p->scale_dev);
+        hipLaunchKernelGGL(ddx::k_scale_part<1>, dim3(ns * p->M), dim3(256), 0, s, src,
+                           (const ddx::ScaleItem*)scales_dev, p->M, p->scale_part);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(ddx::k_scale_final, dim3(ns), dim3(64), 0, s, (const ddx::ScaleItem*)scales_dev,
+                         (const double*)p->scale_part, p->M, target, p->scale_dev);
       return hipGetLastError();
     }));
     p->scale_pending = true;
@@ -1024,7 +1050,7 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
   if (!w.zeros.empty()) {
     HIPCHECK(p, timed(p, s, DDX_K_OTHER, 0.0, 8.0 * (double)w.zeros.size() * w.zeros[0].n * p->nbl, [&] {
       hipLaunchKernelGGL(ddx::k_zero_dm, dim3((unsigned)w.zeros.size()), dim3(256), 0, s, p->ring,
-                         (const ddx::ZeroItem*)zeros_dev, (const int32_t*)p->slots_dev, p->nbl);
+                         (const ddx::ZeroItem*)zeros_dev, (const int32_t*)slots_dev, p->nbl);
       return hipGetLastError();
     }));
   }

@@ -731,34 +731,49 @@ __global__ __launch_bounds__(256) void k_correlate_blocks(CorrArgs a) {
   }
 }
 
-// Correlator-input scale of one channel from its first block window:
+// Correlator-input scale of a channel from its first block window:
 // sigma^2 = sum |x|^2 / (2 M n) over samples [0, n) of every antenna (per-component
-// variance), s = 2^rint(log2(target / sigma)), 1 if the window is all zero.  One
-// workgroup of 1024 threads; fixed summation order, so the result does not depend
-// on how the stream was split.
+// variance), s = 2^rint(log2(target / sigma)), 1 if the window is all zero.  Two
+// launches per call for every channel whose first block runs: partial sums per
+// (channel, antenna), then one sum per channel over antennas in order.  The
+// summation order is fixed, so the result does not depend on how the stream was split.
+struct ScaleItem {
+  int64_t n;           // window length
+  int64_t hist_start;  // absolute index of the channel's history element 0
+  int32_t chan, pad;
+};
+
+// grid: n_items * M workgroups of 256 (antenna fastest); part[item * M + p].
 template <int IN>
-__global__ __launch_bounds__(1024) void k_scale(Source s, int32_t chan, int32_t n_ant, int64_t n, float target,
-                                                float* scale) {
-  __shared__ double part[1024];
+__global__ __launch_bounds__(256) void k_scale_part(Source s, const ScaleItem* items, int32_t n_ant, double* part) {
+  __shared__ double red[256];
+  const ScaleItem w = items[blockIdx.x / n_ant];
+  const int p = blockIdx.x % n_ant;
+  s.row = w.chan * n_ant + p;
+  s.hist_start = w.hist_start;
   double acc = 0.0;
-  for (int p = 0; p < n_ant; ++p) {
-    Source r = s;
-    r.row = chan * n_ant + p;
-    for (int64_t i = threadIdx.x; i < n; i += 1024) {
-      const float2 v = load_sample<IN>(r, i);
-      acc += (double)v.x * v.x + (double)v.y * v.y;
-    }
+  for (int64_t i = threadIdx.x; i < w.n; i += 256) {
+    const float2 v = load_sample<IN>(s, i);
+    acc += (double)v.x * v.x + (double)v.y * v.y;
   }
-  part[threadIdx.x] = acc;
+  red[threadIdx.x] = acc;
   __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    const double var = part[0] / (2.0 * n_ant * (double)n);
-    scale[chan] = var > 0 ? (float)exp2(rint(log2((double)target / sqrt(var)))) : 1.f;
-  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// grid: n_items workgroups of 64; one thread per item sums its antennas in order.
+__global__ __launch_bounds__(64) void k_scale_final(const ScaleItem* items, const double* part, int32_t n_ant,
+                                                    float target, float* scale) {
+  if (threadIdx.x != 0) return;
+  const ScaleItem w = items[blockIdx.x];
+  double tot = 0.0;
+  for (int p = 0; p < n_ant; ++p) tot += part[(int64_t)blockIdx.x * n_ant + p];
+  const double var = tot / (2.0 * n_ant * (double)w.n);
+  scale[w.chan] = var > 0 ? (float)exp2(rint(log2((double)target / sqrt(var)))) : 1.f;
 }
 
 // Zero the record slots of inactive DMs for the dumps of one call.

@@ -91,6 +91,34 @@ def dispersed_segment(wave, f_c, f_s, dm, f_ref, delays=None, phases=None, k_dm=
     return ishift - pad, seg
 
 
+def dispersed_segment_device(wave, f_c, f_s, dm, f_ref, delays, device, k_dm=K_DM_SKY):
+    """dispersed_segment with per-antenna geometric delays, evaluated on a torch
+    device in float64 (the same phases; the inverse FFTs of all antennas at once).
+    Returns (offset, seg) with seg a complex128 tensor [M, Nseg]."""
+    import torch
+
+    wave = np.asarray(wave, dtype=np.complex128)
+    w = wave.shape[0]
+    early, late = _smear(f_c, f_s, dm, k_dm)
+    gmax = float(np.max(np.abs(delays))) * f_s
+    centre = k_dm * dm * (1.0 / (f_c * f_c) - 1.0 / (f_ref * f_ref)) * f_s
+    ishift = int(math.floor(centre))
+    frac = centre - ishift
+    pad = int(math.ceil(early + gmax)) + 256
+    span = pad + w + int(math.ceil(late + gmax + 1.0)) + 256
+    nseg = 1 << int(math.ceil(math.log2(2 * span)))
+    buf = np.zeros(nseg, dtype=np.complex128)
+    buf[pad:pad + w] = wave
+    spec = torch.from_numpy(np.fft.fft(buf)).to(device)
+    f = np.fft.fftfreq(nseg, 1.0 / f_s)
+    cyc = k_dm * dm * (f / (f_c * f_c) - f / (f_c * (f_c + f))) - f * (frac / f_s)
+    c = torch.from_numpy(cyc).to(device)[None, :] - torch.from_numpy(f_c + f).to(device)[None, :] * \
+        torch.from_numpy(np.asarray(delays, np.float64)).to(device)[:, None]
+    ph = torch.remainder(c, 1.0) * (2.0 * math.pi)
+    seg = torch.fft.ifft(spec[None, :] * torch.polar(torch.ones_like(ph), ph), dim=-1)
+    return ishift - pad, seg
+
+
 def inject_pulse(stream, f_c, f_s, dm, n0, wave, f_ref, delays=None, phases=None, k_dm=K_DM_SKY):
     """Add the dispersed pulse to stream [M, S] (complex, in place); returns the stream."""
     off, seg = dispersed_segment(wave, f_c, f_s, dm, f_ref, delays, phases, k_dm)
@@ -216,13 +244,14 @@ def make_stream_device(p, device, chans=None):
             wrng = np.random.Generator(np.random.PCG64(pl["wave_seed"] + int(c)))
             wave = pulse_wave(wrng, pl["width"], pl["snr"], power)
             delays = (pos[:, 0] * pl["lm"][0] + pos[:, 1] * pl["lm"][1]) / C_LIGHT
-            off, seg = dispersed_segment(wave, fc[c], f_s, pl["dm"], f_ref, delays=delays)
+            off, seg = dispersed_segment_device(wave, fc[c], f_s, pl["dm"], f_ref, delays, device)
             a = pl["n0"] + off
             lo, hi = max(a, 0), min(a + seg.shape[-1], s)
             if hi > lo:
                 part = seg[:, lo - a:hi - a]
-                re[:, lo:hi] += torch.from_numpy(part.real.astype(np.float32)).to(device)
-                im[:, lo:hi] += torch.from_numpy(part.imag.astype(np.float32)).to(device)
+                re[:, lo:hi] += part.real.to(torch.float32)
+                im[:, lo:hi] += part.imag.to(torch.float32)
+            del seg
         out[ci, :, 0::2] = torch.clamp(torch.round(re), -127, 127).to(torch.int8)
         out[ci, :, 1::2] = torch.clamp(torch.round(im), -127, 127).to(torch.int8)
         del re, im

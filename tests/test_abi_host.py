@@ -154,3 +154,11 @@ def test_struct_layouts_match_header(tmp_path):
         for f, _ in py._fields_:
             if f != "pad":
                 assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_autotune_dm_sampling_keeps_the_largest():
+    from paper_1109_3186_amd.autotune import _sample_dms
+    d = np.linspace(0, 3000, 1536, endpoint=False)[::-1].copy()  # largest first
+    s = _sample_dms(d, 16)
+    assert d.max() in s and len(s) <= 17 and len(np.unique(s)) == len(s)
+    assert np.array_equal(_sample_dms(d[:5], 16), d[:5])

@@ -414,3 +414,4 @@ def test_quantised_correlation_error_scale():
     assert np.max(np.abs(vq - v) / norm) < 1e-2
     vh = oracle.correlate_dumps(oracle.quantize(x / 16.0, "f16"), 1000) * 256.0
     assert np.max(np.abs(vh - v) / norm) < 1e-4
+
