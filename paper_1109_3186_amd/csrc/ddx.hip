@@ -250,10 +250,16 @@ hipError_t launch_forward_n(int in_dtype, const ddx::FwdArgs& a, int n_items, hi
   return hipGetLastError();
 }
 
+// units rounded up to whole tiles of the dedispersion launch order
+int tiled_units(int n_units) {
+  if (ddx::kUnitTile <= 1) return n_units;
+  return (n_units + ddx::kUnitTile - 1) / ddx::kUnitTile * ddx::kUnitTile;
+}
+
 template <int LOGN>
 hipError_t launch_dedisp_n(int corr_dtype, const ddx::DedispArgs& a, hipStream_t s) {
   using G = ddx::Geo<LOGN>;
-  dim3 grid(a.n_ant * a.n_units), block(G::T);
+  dim3 grid(tiled_units(a.n_units) * a.n_ant), block(G::T);
   if (corr_dtype == DDX_CORR_F32)
     hipLaunchKernelGGL((ddx::k_dedisperse<LOGN, 0>), grid, block, fft_lds_bytes<LOGN>(), s, a);
   else if (corr_dtype == DDX_CORR_F16)
@@ -307,7 +313,7 @@ hipError_t launch_dedisp(int logn, int corr_dtype, const ddx::DedispArgs& a, hip
     case 15: return launch_dedisp_n<15>(corr_dtype, a, s);
   }
   if (logn <= kMaxLogN) {
-    const unsigned ga = (unsigned)((size_t)a.n_units * a.n_ant << a.logr);
+    const unsigned ga = (unsigned)((size_t)tiled_units(a.n_units) * a.n_ant << a.logr);
     hipLaunchKernelGGL(ddx::k_dedisperse_big_a, dim3(ga), dim3(ddx::Geo<ddx::kBigLog>::T),
                        fft_lds_bytes<ddx::kBigLog>(), s, a);
     hipError_t e = hipGetLastError();

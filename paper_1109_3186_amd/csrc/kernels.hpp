@@ -7,6 +7,10 @@
 
 #include "fft.hpp"
 
+#ifndef DDX_NT_STORE
+#define DDX_NT_STORE 1
+#endif
+
 namespace ddx {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -161,9 +165,52 @@ __device__ __forceinline__ typename YType<OUT>::T convert_y(float2 v, float scal
   }
 }
 
+// Order of a wave's workgroups: logical ids (XCD-remapped, so a run of ids shares
+// one XCD's L2) take kUnitTile units fastest, then the rows (antennas, or antenna
+// x k1 rows of a two-pass transform), then the next tile of units.  Units run
+// DM-fastest within a block, so the 32 workgroups one XCD runs at a time read 8
+// spectra and 4 chirps (3 MB, inside its 4 MB L2), and the 4 chirps stay in L2
+// while every antenna passes over them.  (Tiles of 2 to 8 units measured alike on
+// the 36-antenna workload, 1 unit and whole-wave order were 5-15 % slower.)
+#ifndef DDX_UNIT_TILE
+#define DDX_UNIT_TILE 4
+#endif
+constexpr int kUnitTile = DDX_UNIT_TILE;  // 0: all units of the wave fastest
+
+__device__ __forceinline__ bool unit_row(int lin, int n_units, int n_rows, int& row, int& u) {
+  if constexpr (kUnitTile == 0) {
+    u = lin % n_units;
+    row = lin / n_units;
+    return true;
+  }
+  const int t = kUnitTile > 0 ? kUnitTile : 1;
+  const int ul = lin % t;
+  lin /= t;
+  row = lin % n_rows;
+  u = (lin / n_rows) * t + ul;
+  return u < n_units;
+}
+
+// Dedispersed output stores bypass L2 retention (the spectra and chirps are what
+// the next workgroups re-read).
+template <class T>
+__device__ __forceinline__ void store_stream(T* p, T v) {
+#if DDX_NT_STORE
+  if constexpr (sizeof(T) == 8) {
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    __builtin_nontemporal_store(*reinterpret_cast<const f2v*>(&v), reinterpret_cast<f2v*>(p));
+  } else if constexpr (sizeof(T) == 4) {
+    __builtin_nontemporal_store(*reinterpret_cast<const unsigned int*>(&v), reinterpret_cast<unsigned int*>(p));
+  } else {
+    __builtin_nontemporal_store(*reinterpret_cast<const unsigned short*>(&v), reinterpret_cast<unsigned short*>(p));
+  }
+#else
+  *p = v;
+#endif
+}
+
 // Chirp multiply, inverse FFT and overlap-save discard for a wave of units.
-// grid: M * n_units workgroups, logical id = p * n_units + u (XCD-remapped), so
-// neighbouring ids share a spectrum (units run DM-fastest within a block).
+// grid: ceil(n_units / kUnitTile) kUnitTile M workgroups (see unit_row).
 // y[u.y + p y_stride + j] = IDFT(X H)[lead + j] for j < V.
 struct DedispArgs {
   const float2* spec;
@@ -181,9 +228,9 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_dedisperse(DedispArgs a) {
   using G = Geo<LOGN>;
   extern __shared__ float lds[];
   const int t = threadIdx.x;
-  const int lin = xcd_remap(blockIdx.x, gridDim.x);
-  const int p = lin / a.n_units;
-  const UnitItem w = a.units[lin % a.n_units];
+  int p, ui;
+  if (!unit_row(xcd_remap(blockIdx.x, gridDim.x), a.n_units, a.n_ant, p, ui)) return;
+  const UnitItem w = a.units[ui];
   const float2* x = a.spec + w.spec + (size_t)p * G::N;
   const float2* h = a.chirp + w.chirp;
   float2 v[G::P];
@@ -197,7 +244,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_dedisperse(DedispArgs a) {
 #pragma unroll
     for (int q = 0; q < G::RL; ++q) {
       const int n = t + u * G::T + q * (G::N / G::RL);
-      if (n >= w.lead && n < w.lead + w.valid) y[n - w.lead] = convert_y<OUT>(v[u * G::RL + out_reg<G::RL>(q)], scale);
+      if (n >= w.lead && n < w.lead + w.valid) store_stream(y + (n - w.lead), convert_y<OUT>(v[u * G::RL + out_reg<G::RL>(q)], scale));
     }
 }
 
@@ -267,14 +314,14 @@ __global__ __launch_bounds__(Geo<kBigLog>::T) void k_fft_rows(const float2* __re
 
 // Inverse pass A over a wave of units of one length N = 2^(15 + logr): row (p, k1)
 // of unit u times the chirp's row k1, inverse 2^15-point FFT, times w_N^{k1 n2}.
-// grid: n_units * M * R workgroups, logical id = (p R + k1) n_units + u (XCD-remapped).
+// grid: ceil(n_units / kUnitTile) kUnitTile M R workgroups (see unit_row, rows p R + k1).
 __global__ __launch_bounds__(Geo<kBigLog>::T) void k_dedisperse_big_a(DedispArgs a) {
   using G = Geo<kBigLog>;
   extern __shared__ float lds[];
   const int t = threadIdx.x;
-  const int lin = xcd_remap(blockIdx.x, gridDim.x);
-  const UnitItem w = a.units[lin % a.n_units];
-  const int row = lin / a.n_units;  // p R + k1
+  int row, ui;  // row = p R + k1
+  if (!unit_row(xcd_remap(blockIdx.x, gridDim.x), a.n_units, a.n_ant << a.logr, row, ui)) return;
+  const UnitItem w = a.units[ui];
   const int k1 = row & ((1 << a.logr) - 1);
   const float2* x = a.spec + w.spec + (size_t)row * kBigN;
   const float2* h = a.chirp + w.chirp + (size_t)k1 * kBigN;
@@ -300,7 +347,7 @@ __device__ __forceinline__ void dedisperse_big_b(const float2* t0, int n2, int l
 #pragma unroll
   for (int n1 = 0; n1 < R; ++n1) {
     const int n = n1 * kBigN + n2;
-    if (n >= lead && n < lead + valid) y[n - lead] = convert_y<OUT>(v[out_reg<R>(n1)], scale);
+    if (n >= lead && n < lead + valid) store_stream(y + (n - lead), convert_y<OUT>(v[out_reg<R>(n1)], scale));
   }
 }
 
