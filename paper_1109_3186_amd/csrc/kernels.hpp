@@ -487,8 +487,11 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
   typedef typename In::E E;
   typedef typename In::Pair Pair;
   constexpr int PPT = (8 * NT * (kCorrKC / 2) + 255) / 256;  // max sample pairs per thread per chunk (M <= 8 NT)
-  __shared__ E at[Ld::ELEMS];
-  __shared__ float gram[C::ROWS * C::GP];
+  // the staged chunks and, after the last MFMA, the Gram matrix share one LDS buffer
+  constexpr int AT_BYTES = Ld::ELEMS * (int)sizeof(E), GRAM_BYTES = C::ROWS * C::GP * 4;
+  __shared__ __align__(16) char smem[AT_BYTES > GRAM_BYTES ? AT_BYTES : GRAM_BYTES];
+  E* at = reinterpret_cast<E*>(smem);
+  float* gram = reinterpret_cast<float*>(smem);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   CorrJob w;
   if (!corr_job(a, blockIdx.x, w)) return;
@@ -548,21 +551,16 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
       }
     }
   };
-  Pair buf[PPT];
-  load(0, buf);
-  for (int k0 = 0; k0 < L; k0 += kCorrKC) {
-    __syncthreads();  // previous chunk's MFMAs are done with at[]
-    stage(buf);
-    __syncthreads();
-    if (k0 + kCorrKC < L) load(k0 + kCorrKC, buf);  // in flight during the MFMAs below
+  // two chunks in flight: chunk k+2's loads are issued before chunk k's MFMAs
+  auto mfma_chunk = [&]() {
 #pragma unroll
     for (int kk = 0; kk < kCorrKC; kk += In::KSTEP) {
 #pragma unroll
       for (int i = 0; i < C::TPW; ++i) {
         if (wave + 4 * i < C::NTILES) {
           const int ra = ti[i] * 16 + (lane & 15), rb = tj[i] * 16 + (lane & 15);
+          const int kr = kk + 8 * (lane >> 4);
           if constexpr (T == 0) {
-            const int kr = kk + 8 * (lane >> 4);
             const half8 ah = *reinterpret_cast<const half8*>(&at[Ld::at(ra, kr)]);
             const half8 bh = *reinterpret_cast<const half8*>(&at[Ld::at(rb, kr)]);
             const half8 al = *reinterpret_cast<const half8*>(&at[Ld::PLANE + Ld::at(ra, kr)]);
@@ -571,12 +569,10 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
             acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, acc[i], 0, 0, 0);
             acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, acc[i], 0, 0, 0);
           } else if constexpr (T == 1) {
-            const int kr = kk + 8 * (lane >> 4);
             const half8 av = *reinterpret_cast<const half8*>(&at[Ld::at(ra, kr)]);
             const half8 bv = *reinterpret_cast<const half8*>(&at[Ld::at(rb, kr)]);
             acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, acc[i], 0, 0, 0);
           } else {
-            const int kr = kk + 8 * (lane >> 4);
             const long av = *reinterpret_cast<const long*>(&at[Ld::at(ra, kr)]);
             const long bv = *reinterpret_cast<const long*>(&at[Ld::at(rb, kr)]);
             acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, acc[i], 0, 0, 0);
@@ -584,7 +580,22 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
         }
       }
     }
+  };
+  auto chunk = [&](Pair* buf, int k0) {
+    __syncthreads();  // previous chunk's MFMAs are done with at[]
+    stage(buf);
+    __syncthreads();
+    if (k0 + 2 * kCorrKC < L) load(k0 + 2 * kCorrKC, buf);
+    mfma_chunk();
+  };
+  Pair buf0[PPT], buf1[PPT];
+  load(0, buf0);
+  if (kCorrKC < L) load(kCorrKC, buf1);
+  for (int k0 = 0; k0 < L; k0 += 2 * kCorrKC) {
+    chunk(buf0, k0);
+    if (k0 + kCorrKC < L) chunk(buf1, k0 + kCorrKC);
   }
+  __syncthreads();  // every wave is done with at[] before the Gram matrix overwrites it
 #pragma unroll
   for (int i = 0; i < C::TPW; ++i) {
     if (wave + 4 * i < C::NTILES) {
