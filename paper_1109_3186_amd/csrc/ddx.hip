@@ -812,6 +812,7 @@ void build_lists(ddx_plan* p, const std::vector<int64_t>& b_end, const std::vect
               ci.kdm = p->kdm * c.dm[d];
               ci.n = c.fft_len;
               ci.logr = c.logn > ddx::kBigLog ? c.logn - ddx::kBigLog : 0;
+              ci.chan = i;
               w.chirps.push_back(ci);
               ++cur.nc;
             }
@@ -1019,7 +1020,8 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
     const double nn = wv.fft_n;
     HIPCHECK(p, timed(p, s, DDX_K_CHIRP, 0.0, (double)wv.nc * nn * 16.0, [&] {
       hipLaunchKernelGGL(ddx::k_chirp, dim3((unsigned)((wv.fft_n + 255) / 256), (unsigned)wv.nc), dim3(256), 0, s,
-                         (const ddx::ChirpItem*)(chirps_dev + wv.c0), (const double*)p->gtab, p->chirp);
+                         (const ddx::ChirpItem*)(chirps_dev + wv.c0), (const double*)p->gtab,
+                         (const float*)p->scale_dev, p->chirp);
       return hipGetLastError();
     }));
     ddx::DedispArgs da{};
@@ -1028,7 +1030,6 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
     da.y = p->ybuf;
     da.tb = p->tb;
     da.units = units_dev + wv.u0;
-    da.scale = p->scale_dev;
     da.y_stride = p->y_stride;
     da.n_ant = p->M;
     da.n_units = (int)wv.nu;

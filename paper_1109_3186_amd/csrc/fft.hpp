@@ -10,8 +10,9 @@
 // parts then imaginary parts, so that N = 32768 fits the 160 KB of one CU.
 //
 // Load pattern of the first pass and store pattern of the last pass are both
-// "point (t + u T) + r N / R at register u R + r", i.e. coalesced across threads,
-// and the output is in natural order.  The transform is unnormalised:
+// "point (t + u T) + r N / R", i.e. coalesced across threads (held in register
+// u R + in_reg(r) before a pass's DFT, u R + out_reg(q) after it), and the output
+// is in natural order.  The transform is unnormalised:
 // sum_n x[n] exp(s 2 pi i k n / N) with s = -1 (forward) or +1 (inverse).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -66,28 +67,43 @@ __device__ __forceinline__ float2 rot32(float2 a, int m) {
   return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
 }
 
-// In-place R-point DFT of v[0..R-1] (R = 2..32) by decimation in frequency:
-// natural-order input, output X[q] left in register bitrev(q).  Working in place
-// keeps the register footprint at the R points themselves.
+// In-place R-point DFT of v[0..R-1] (R = 2..32) by decimation in time: input
+// point r is held in register in_reg(r) = bitrev(r), output X[q] in register
+// out_reg(q) = q.  Working in place keeps the register footprint at the R points
+// themselves.  A butterfly of length 2h takes a and b w (w = W_{2h}^j):
+//   a' = a + b w in four FMAs, b' = a - b w = 2 a - a' in two,
+// instead of a + b, a - b and a complex product (eight instructions); w = 1 and
+// w = +-i are additions only.
 template <int R, int S>
 __device__ __forceinline__ void dft_reg(float2* v) {
 #pragma unroll
-  for (int h = R / 2; h >= 1; h >>= 1) {  // butterflies of length 2h
+  for (int h = 1; h < R; h <<= 1) {  // butterflies of length 2h
 #pragma unroll
     for (int i = 0; i < R; i += 2 * h) {
 #pragma unroll
       for (int j = 0; j < h; ++j) {
         const float2 a = v[i + j], b = v[i + j + h];
-        v[i + j] = cadd(a, b);
-        v[i + j + h] = rot32<S>(csub(a, b), j * (16 / h));
+        const int m = j * (16 / h);  // W_{2h}^j = W_32^m
+        if (m == 0 || m == 8) {
+          const float2 t = rot32<S>(b, m);
+          v[i + j] = cadd(a, t);
+          v[i + j + h] = csub(a, t);
+        } else {
+          const float c = kCos32[m], s = (float)S * kSin32[m];
+          const float2 o = make_float2(fmaf(b.x, c, fmaf(-b.y, s, a.x)), fmaf(b.x, s, fmaf(b.y, c, a.y)));
+          v[i + j] = o;
+          v[i + j + h] = make_float2(fmaf(2.f, a.x, -o.x), fmaf(2.f, a.y, -o.y));
+        }
       }
     }
   }
 }
 
-// Register that holds DFT output q after dft_reg<R>.
+// Register that holds DFT input point r before dft_reg<R>, and output q after it.
 template <int R>
-__device__ __forceinline__ constexpr int out_reg(int q) { return bitrev(q, ilog2(R)); }
+__device__ __forceinline__ constexpr int in_reg(int r) { return bitrev(r, ilog2(R)); }
+template <int R>
+__device__ __forceinline__ constexpr int out_reg(int q) { return q; }
 
 // Radix plan per transform length: P points per thread, passes of radix R[i].
 template <int LOGN> struct Plan;
@@ -164,7 +180,7 @@ __device__ __forceinline__ void exchange(float2* v, float* lds, int t) {
         } else {
           val = lds[lds_pad(t + u * G::T + r * RSTR)];
         }
-        if (half) v[u * R2 + r].y = val; else v[u * R2 + r].x = val;
+        if (half) v[u * R2 + in_reg<R2>(r)].y = val; else v[u * R2 + in_reg<R2>(r)].x = val;
       }
     }
     __syncthreads();
@@ -209,14 +225,14 @@ __device__ __forceinline__ void apply_twiddles(float2* v, int k) {
   }
   constexpr int B = R < 8 ? R : 8;
 #pragma unroll
-  for (int b = 1; b < B; ++b) v[b] = cmul(v[b], wb[b]);
+  for (int b = 1; b < B; ++b) v[in_reg<R>(b)] = cmul(v[in_reg<R>(b)], wb[b]);
 #pragma unroll
   for (int a = 1; a < R / 8; ++a) {
     // 8 a k < 2^LOGD (k < 2^LOGD / R): exact anchor
     const float2 wa = twiddle<LOGD, S>(8 * a * k);
-    v[8 * a] = cmul(v[8 * a], wa);
+    v[in_reg<R>(8 * a)] = cmul(v[in_reg<R>(8 * a)], wa);
 #pragma unroll
-    for (int b = 1; b < 8; ++b) v[8 * a + b] = cmul(v[8 * a + b], cmul(wa, wb[b]));
+    for (int b = 1; b < 8; ++b) v[in_reg<R>(8 * a + b)] = cmul(v[in_reg<R>(8 * a + b)], cmul(wa, wb[b]));
   }
 }
 
@@ -259,7 +275,7 @@ __device__ __forceinline__ void fft_workgroup(float2* v, float* lds, int t, Load
 #pragma unroll
   for (int u = 0; u < G::P / G::R0; ++u) {
 #pragma unroll
-    for (int r = 0; r < G::R0; ++r) v[u * G::R0 + r] = load(t + z + u * G::T + r * (G::N / G::R0));
+    for (int r = 0; r < G::R0; ++r) v[u * G::R0 + in_reg<G::R0>(r)] = load(t + z + u * G::T + r * (G::N / G::R0));
     dft_reg<G::R0, S>(v + u * G::R0);
     // loads of the next group wait for this group's butterflies (register pressure)
     if (u + 1 < G::P / G::R0) {

@@ -59,6 +59,13 @@ __device__ __forceinline__ float2 load_sample(const Source& s, int64_t abs) {
   }
 }
 
+// Element at a 32-bit byte offset from a base pointer (lets the compiler use the
+// scalar-base + 32-bit vector-offset form of global loads).
+template <class T>
+__device__ __forceinline__ T at_byte(const T* base, unsigned off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+
 // ---------------------------------------------------------------------------
 // Work items of one ddx_process_block call.  The host lists them (all channels,
 // all active DMs, all blocks the call completes) and copies the lists to the
@@ -77,6 +84,7 @@ struct ChirpItem {      // one (channel, DM) of a wave
   double kdm;           // K DM
   int32_t n;            // N_c
   int32_t logr;         // N_c = 2^(15 + logr) for two-pass transforms, else 0
+  int32_t chan, pad;
 };
 struct UnitItem {       // one (channel, DM, block), all M antennas
   int64_t spec;         // spectrum of antenna 0 of the block
@@ -125,42 +133,45 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_forward(FwdArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Chirp tables of a wave's (channel, DM) pairs: H[k] = exp(-2 pi i r) / N with
+// Chirp tables of a wave's (channel, DM) pairs: H[k] = s_c exp(-2 pi i r) / N with
 // r = u - rint(u), u = kdm * g[k] in FP64 (g[k] = f_k^2 / (f_c^2 (f_c + f_k))).
+// Folding the correlator-input scale s_c (a power of two) and 1/N in here makes the
+// inverse transforms produce s_c y directly, with the same bits as scaling afterwards.
 // Two-pass lengths store bin k1 + R k2 at position k1 2^15 + k2 (the order in
 // which their spectra are kept).  grid: (ceil(max N / 256), n_items).
 __global__ __launch_bounds__(256) void k_chirp(const ChirpItem* __restrict__ items, const double* __restrict__ g,
-                                               float2* __restrict__ h) {
+                                               const float* __restrict__ scale, float2* __restrict__ h) {
   const ChirpItem w = items[blockIdx.y];
   const int q = blockIdx.x * 256 + threadIdx.x;
   if (q >= w.n) return;
   const int k = w.logr ? ((q >> 15) + (q & 32767) * (1 << w.logr)) : q;
   const double u = w.kdm * g[w.g + k];
   const float r = (float)(u - rint(u));
-  const float inv_n = 1.0f / (float)w.n;  // power of two: exact
-  h[w.out + q] = make_float2(cos_rev(r) * inv_n, -sin_rev(r) * inv_n);
+  const float f = scale[w.chan] * (1.0f / (float)w.n);  // powers of two: exact
+  h[w.out + q] = make_float2(cos_rev(r) * f, -sin_rev(r) * f);
 }
 
 // ---------------------------------------------------------------------------
-// Output conversion of the dedispersed voltages.
+// Output conversion of the dedispersed voltages (already s_c y).
 template <int OUT> struct YType;
 template <> struct YType<0> { typedef float2 T; };   // FP32
 template <> struct YType<1> { typedef __half2 T; };  // binary16 pair
 template <> struct YType<2> { typedef uint16_t T; }; // two E4M3 bytes (re low, im high)
 
 template <int OUT>
-__device__ __forceinline__ typename YType<OUT>::T convert_y(float2 v, float scale) {
+__device__ __forceinline__ typename YType<OUT>::T convert_y(float2 v) {
   if constexpr (OUT == 0) {
     return v;
   } else if constexpr (OUT == 1) {
     const float m = 65504.f;
-    const float re = fminf(fmaxf(v.x * scale, -m), m), im = fminf(fmaxf(v.y * scale, -m), m);
+    const float re = fminf(fmaxf(v.x, -m), m), im = fminf(fmaxf(v.y, -m), m);
     return __halves2half2(__float2half_rn(re), __float2half_rn(im));
   } else {
     const float m = 448.f;
-    const float re = fminf(fmaxf(v.x * scale, -m), m), im = fminf(fmaxf(v.y * scale, -m), m);
-    // hardware conversion rounds to nearest even; the clamp above makes it saturate
-    const int packed = __builtin_amdgcn_cvt_pk_fp8_f32(re, im, 0, false);
+    const float re = fminf(fmaxf(v.x, -m), m), im = fminf(fmaxf(v.y, -m), m);
+    // hardware conversion rounds to nearest even; the clamp above makes it saturate.
+    // It writes the low 16 bits only; the high half (passed in, unused) is re's bits.
+    const int packed = __builtin_amdgcn_cvt_pk_fp8_f32(re, im, __float_as_int(re), false);
     return (uint16_t)(packed & 0xffff);
   }
 }
@@ -209,6 +220,11 @@ __device__ __forceinline__ void store_stream(T* p, T v) {
 #endif
 }
 
+template <class T>
+__device__ __forceinline__ void store_stream_at(T* base, unsigned byte_off, T v) {
+  store_stream(reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off), v);
+}
+
 // Chirp multiply, inverse FFT and overlap-save discard for a wave of units.
 // grid: ceil(n_units / kUnitTile) kUnitTile M workgroups (see unit_row).
 // y[u.y + p y_stride + j] = IDFT(X H)[lead + j] for j < V.
@@ -218,7 +234,6 @@ struct DedispArgs {
   void* y;
   float2* tb;           // two-pass transforms: intermediate rows
   const UnitItem* units;
-  const float* scale;   // [C] correlator-input scales
   int64_t y_stride;
   int32_t n_ant, n_units, logr;
 };
@@ -234,17 +249,19 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_dedisperse(DedispArgs a) {
   const float2* x = a.spec + w.spec + (size_t)p * G::N;
   const float2* h = a.chirp + w.chirp;
   float2 v[G::P];
-  fft_workgroup<LOGN, +1>(v, lds, t, [&](int i) { return cmul(x[i], h[i]); });
-  const float scale = (OUT == 0) ? 1.f : a.scale[w.chan];
+  // 32-bit byte offsets from a uniform base: each load needs one 32-bit add, not a 64-bit address
+  fft_workgroup<LOGN, +1>(v, lds, t, [&](int i) { return cmul(at_byte(x, 8u * (unsigned)i), at_byte(h, 8u * (unsigned)i)); });
   typedef typename YType<OUT>::T YT;
   // output addresses are formed only now (otherwise they are hoisted and held in registers)
-  YT* y = reinterpret_cast<YT*>(a.y) + w.y + (size_t)p * a.y_stride + opaque_zero(v[0].x);
+  YT* y = reinterpret_cast<YT*>(a.y) + w.y + (size_t)p * a.y_stride;
+  const int z = opaque_zero(v[0].x);
 #pragma unroll
   for (int u = 0; u < G::P / G::RL; ++u)
 #pragma unroll
     for (int q = 0; q < G::RL; ++q) {
-      const int n = t + u * G::T + q * (G::N / G::RL);
-      if (n >= w.lead && n < w.lead + w.valid) store_stream(y + (n - w.lead), convert_y<OUT>(v[u * G::RL + out_reg<G::RL>(q)], scale));
+      const unsigned j = (unsigned)(t + z + u * G::T + q * (G::N / G::RL) - w.lead);  // kept iff j < V
+      if (j < (unsigned)w.valid)
+        store_stream_at(y, j * (unsigned)sizeof(YT), convert_y<OUT>(v[u * G::RL + out_reg<G::RL>(q)]));
     }
 }
 
@@ -274,7 +291,7 @@ template <int R, int IN>
 __device__ __forceinline__ void forward_big_pre(const Source& s, int64_t win0, int n2, float2* row0) {
   float2 v[R];
 #pragma unroll
-  for (int n1 = 0; n1 < R; ++n1) v[n1] = load_sample<IN>(s, win0 + (int64_t)n1 * kBigN + n2);
+  for (int n1 = 0; n1 < R; ++n1) v[in_reg<R>(n1)] = load_sample<IN>(s, win0 + (int64_t)n1 * kBigN + n2);
   dft_reg<R, -1>(v);
 #pragma unroll
   for (int k1 = 0; k1 < R; ++k1)
@@ -304,7 +321,7 @@ __global__ __launch_bounds__(Geo<kBigLog>::T) void k_fft_rows(const float2* __re
   const int t = threadIdx.x;
   const float2* x = src + (size_t)blockIdx.x * kBigN;
   float2 v[G::P];
-  fft_workgroup<kBigLog, -1>(v, lds, t, [&](int i) { return x[i]; });
+  fft_workgroup<kBigLog, -1>(v, lds, t, [&](int i) { return at_byte(x, 8u * (unsigned)i); });
   float2* out = dst + (size_t)blockIdx.x * kBigN + opaque_zero(v[0].x);
 #pragma unroll
   for (int u = 0; u < G::P / G::RL; ++u)
@@ -326,7 +343,8 @@ __global__ __launch_bounds__(Geo<kBigLog>::T) void k_dedisperse_big_a(DedispArgs
   const float2* x = a.spec + w.spec + (size_t)row * kBigN;
   const float2* h = a.chirp + w.chirp + (size_t)k1 * kBigN;
   float2 v[G::P];
-  fft_workgroup<kBigLog, +1>(v, lds, t, [&](int i) { return cmul(x[i], h[i]); });
+  fft_workgroup<kBigLog, +1>(v, lds, t,
+                             [&](int i) { return cmul(at_byte(x, 8u * (unsigned)i), at_byte(h, 8u * (unsigned)i)); });
   float2* out = a.tb + w.tb + (size_t)row * kBigN + opaque_zero(v[0].x);
 #pragma unroll
   for (int u = 0; u < G::P / G::RL; ++u)
@@ -338,16 +356,16 @@ __global__ __launch_bounds__(Geo<kBigLog>::T) void k_dedisperse_big_a(DedispArgs
 }
 
 template <int R, int OUT>
-__device__ __forceinline__ void dedisperse_big_b(const float2* t0, int n2, int lead, int valid, float scale,
+__device__ __forceinline__ void dedisperse_big_b(const float2* t0, int n2, int lead, int valid,
                                                  typename YType<OUT>::T* y) {
   float2 v[R];
 #pragma unroll
-  for (int k1 = 0; k1 < R; ++k1) v[k1] = t0[(size_t)k1 * kBigN + n2];
+  for (int k1 = 0; k1 < R; ++k1) v[in_reg<R>(k1)] = t0[(size_t)k1 * kBigN + n2];
   dft_reg<R, +1>(v);
 #pragma unroll
   for (int n1 = 0; n1 < R; ++n1) {
     const int n = n1 * kBigN + n2;
-    if (n >= lead && n < lead + valid) store_stream(y + (n - lead), convert_y<OUT>(v[out_reg<R>(n1)], scale));
+    if (n >= lead && n < lead + valid) store_stream(y + (n - lead), convert_y<OUT>(v[out_reg<R>(n1)]));
   }
 }
 
@@ -359,12 +377,11 @@ __global__ __launch_bounds__(256) void k_dedisperse_big_b(DedispArgs a) {
   const int p = blockIdx.y / a.n_units;
   const UnitItem w = a.units[blockIdx.y % a.n_units];
   const float2* t0 = a.tb + w.tb + ((size_t)p << (kBigLog + a.logr));
-  const float scale = (OUT == 0) ? 1.f : a.scale[w.chan];
   typedef typename YType<OUT>::T YT;
   YT* y = reinterpret_cast<YT*>(a.y) + w.y + (size_t)p * a.y_stride;
-  if (a.logr == 1) dedisperse_big_b<2, OUT>(t0, n2, w.lead, w.valid, scale, y);
-  else if (a.logr == 2) dedisperse_big_b<4, OUT>(t0, n2, w.lead, w.valid, scale, y);
-  else dedisperse_big_b<8, OUT>(t0, n2, w.lead, w.valid, scale, y);
+  if (a.logr == 1) dedisperse_big_b<2, OUT>(t0, n2, w.lead, w.valid, y);
+  else if (a.logr == 2) dedisperse_big_b<4, OUT>(t0, n2, w.lead, w.valid, y);
+  else dedisperse_big_b<8, OUT>(t0, n2, w.lead, w.valid, y);
 }
 
 // ---------------------------------------------------------------------------
@@ -418,10 +435,11 @@ template <int T, int NT> struct CorrLds {
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 
 // Correlator: per (DM, dump) the Gram matrix of the stacked real rows
-// [Re y_0 .. Re y_{M-1}, Im y_0 .. Im y_{M-1}] over the L samples of the dump,
+// [Re y_0 .. Re y_{M-1}, Im y_0 .. Im y_{M-1}] over the L samples of the dump
+// (the stored voltages are s y, s = the channel's correlator-input scale),
 // G = A A^T on MFMA over the upper 16x16 tiles, FP32 accumulation, then
-//   Re V_ij = (G[i][j] + G[M+i][M+j]) / s^2,  Im V_ij = (G[j][M+i] - G[i][M+j]) / s^2
-// (s = correlator-input scale, 1 for FP32).  Samples are staged through LDS in
+//   Re V_ij = (G[i][j] + G[M+i][M+j]) / s^2,  Im V_ij = (G[j][M+i] - G[i][M+j]) / s^2.
+// Samples are staged through LDS in
 // chunks of kCorrKC; the next chunk's global loads are issued before the current
 // chunk's MFMAs.  grid: n_units * max_dumps workgroups of 256 threads (4 waves),
 // one per (unit, dump); workgroups past a unit's last dump exit at once.
@@ -461,12 +479,12 @@ __device__ __forceinline__ void split16(float x, _Float16& hi, _Float16& lo) {
 
 template <int T, int PLANE>
 __device__ __forceinline__ void store_pair(typename CorrIn<T>::E* at, int ia_re0, int ia_re1, int ia_im0, int ia_im1,
-                                           typename CorrIn<T>::Pair v, float s) {
+                                           typename CorrIn<T>::Pair v) {
   if constexpr (T == 0) {
-    split16(v.x * s, at[ia_re0], at[PLANE + ia_re0]);
-    split16(v.y * s, at[ia_im0], at[PLANE + ia_im0]);
-    split16(v.z * s, at[ia_re1], at[PLANE + ia_re1]);
-    split16(v.w * s, at[ia_im1], at[PLANE + ia_im1]);
+    split16(v.x, at[ia_re0], at[PLANE + ia_re0]);
+    split16(v.y, at[ia_im0], at[PLANE + ia_im0]);
+    split16(v.z, at[ia_re1], at[PLANE + ia_re1]);
+    split16(v.w, at[ia_im1], at[PLANE + ia_im1]);
   } else if constexpr (T == 1) {
     const __half2 s0 = *reinterpret_cast<const __half2*>(&v.x), s1 = *reinterpret_cast<const __half2*>(&v.y);
     at[ia_re0] = (_Float16)__low2float(s0);  // exact: the values are binary16 already
@@ -546,8 +564,7 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
       const int e = tid + 256 * i;
       if (e < pairs) {
         const int p = e / (kCorrKC / 2), k = 2 * (e % (kCorrKC / 2));
-        store_pair<T, Ld::PLANE>(at, Ld::at(p, k), Ld::at(p, k + 1), Ld::at(M + p, k), Ld::at(M + p, k + 1), buf[i],
-                                 s_in);
+        store_pair<T, Ld::PLANE>(at, Ld::at(p, k), Ld::at(p, k + 1), Ld::at(M + p, k), Ld::at(M + p, k + 1), buf[i]);
       }
     }
   };
@@ -708,7 +725,7 @@ __global__ __launch_bounds__(256) void k_correlate_blocks(CorrArgs a) {
       const int e = tid + 256 * i;
       const int la = e / (kCorrKC / 2), k = 2 * (e % (kCorrKC / 2));
       const int rr = row_re(la), ri = rr + kBlkAnt;
-      store_pair<T, PLANE>(at, rr * KP + k, rr * KP + k + 1, ri * KP + k, ri * KP + k + 1, buf[i], s_in);
+      store_pair<T, PLANE>(at, rr * KP + k, rr * KP + k + 1, ri * KP + k, ri * KP + k + 1, buf[i]);
     }
   };
   auto frag = [&](int plane, int row, int kr) -> Frag {
