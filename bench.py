@@ -236,24 +236,41 @@ def run_c3(args, dev):
 
 
 def roofline_of(prof, args):
-    """Roofline of the dominant kernel kind from the library's event timings."""
+    """Roofline of the dominant kernel kind from the library's event timings.
+
+    Dedispersion (A4): bound by HBM at these sizes (5.9 flop per staged byte, below
+    the FP32 ridge of 19.7): achieved = staged bytes per launch (a spectrum read per
+    unit and antenna, the chirps, the dedispersed voltages written: 8 N / V + b_y per
+    unit) / launch time; its algorithmic FLOP rate against the VALU peak is given
+    beside it.  Correlator (A6): MFMA, against the peak of its input format.
+    `traffic` = HBM bytes per launch from the committed counter run (null if the
+    kernels changed since)."""
     dom = max(prof, key=lambda k: prof[k]["time_ms"])
     d = prof[dom]
-    per_launch_s = d["time_ms"] / 1e3 / max(d["launches"], 1)
+    n = max(d["launches"], 1)
+    per_launch_s = d["time_ms"] / 1e3 / n
+    tflops = d["flops"] / n / per_launch_s / 1e12
+    traffic = measured_traffic(dom, args.workload)
     if dom == "correlate":
-        bound, peak = "mfma", {"f32": PEAKS["fp32_mfma_tflops"], "f16": PEAKS["fp16_mfma_tflops"],
-                               "e4m3": PEAKS["fp8_mfma_tflops"]}[args.corr]
+        peak = {"f32": PEAKS["fp32_mfma_tflops"], "f16": PEAKS["fp16_mfma_tflops"],
+                "e4m3": PEAKS["fp8_mfma_tflops"]}[args.corr]
+        r = {"bound": "mfma", "achieved": round(tflops, 2), "peak": peak, "unit": "TFLOP/s",
+             "frac": round(tflops / peak, 4)}
     else:
-        bound, peak = "alu", PEAKS["fp32_vector_tflops"]
-    achieved = d["flops"] / max(d["launches"], 1) / per_launch_s / 1e12
-    return {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": measured_traffic(dom, args.workload), "kernel": dom,
-            "avg_launch_ms": round(per_launch_s * 1e3, 4),
-            "kernels": {k: {"ms_per_step": round(v["time_ms"] / args.steps, 2),
-                            "launches_per_step": v["launches"] // args.steps,
-                            "tflops": round(v["flops"] / max(v["time_ms"], 1e-9) / 1e9, 2),
-                            "staged_gbs": round(v["bytes"] / max(v["time_ms"], 1e-9) / 1e6, 1)}
-                        for k, v in prof.items() if v["launches"]}}
+        gbs = d["bytes"] / n / per_launch_s / 1e9
+        r = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
+             "frac": round(gbs / PEAKS["hbm_gbs"], 4),
+             "alu": {"achieved": round(tflops, 2), "peak": PEAKS["fp32_vector_tflops"], "unit": "TFLOP/s",
+                     "frac": round(tflops / PEAKS["fp32_vector_tflops"], 4)}}
+    r.update({"traffic": traffic, "kernel": dom, "avg_launch_ms": round(per_launch_s * 1e3, 4)})
+    if traffic:
+        r["traffic_gbs"] = round(traffic / per_launch_s / 1e9, 1)
+    r["kernels"] = {k: {"ms_per_step": round(v["time_ms"] / args.steps, 2),
+                        "launches_per_step": v["launches"] // args.steps,
+                        "tflops": round(v["flops"] / max(v["time_ms"], 1e-9) / 1e9, 2),
+                        "staged_gbs": round(v["bytes"] / max(v["time_ms"], 1e-9) / 1e6, 1)}
+                    for k, v in prof.items() if v["launches"]}
+    return r
 
 
 def main():

@@ -227,7 +227,10 @@ typedef struct ddx_profile {
   double time_ms[DDX_N_KINDS];    /* summed device time between the events around each launch */
   double flops[DDX_N_KINDS];      /* algorithmic flops: 5 N log2 N per FFT, 6 N per chirp multiply,
                                      8 L per baseline (i <= j) per dump */
-  double bytes[DDX_N_KINDS];      /* bytes each kernel must move as staged (inputs once + outputs) */
+  double bytes[DDX_N_KINDS];      /* bytes as staged through memory: forward = input + spectra;
+                                     dedispersion = one spectrum read per (DM, block, antenna),
+                                     one chirp per wave, the dedispersed voltages written;
+                                     correlator = its dumps' voltages read + visibilities */
 } ddx_profile;
 
 /* on != 0: record a pair of hipEvents around every kernel launch on the

@@ -179,26 +179,22 @@ __device__ __forceinline__ typename YType<OUT>::T convert_y(float2 v) {
 // Order of a wave's workgroups: logical ids (XCD-remapped, so a run of ids shares
 // one XCD's L2) take kUnitTile units fastest, then the rows (antennas, or antenna
 // x k1 rows of a two-pass transform), then the next tile of units.  Units run
-// DM-fastest within a block, so the 32 workgroups one XCD runs at a time read 8
-// spectra and 4 chirps (3 MB, inside its 4 MB L2), and the 4 chirps stay in L2
-// while every antenna passes over them.  (Tiles of 2 to 8 units measured alike on
-// the 36-antenna workload, 1 unit and whole-wave order were 5-15 % slower.)
-#ifndef DDX_UNIT_TILE
-#define DDX_UNIT_TILE 4
-#endif
-constexpr int kUnitTile = DDX_UNIT_TILE;  // 0: all units of the wave fastest
+// DM-fastest within a block, so the workgroups one XCD runs at a time read a few
+// spectra and 4 chirps, and the 4 chirps stay in L2 while every antenna passes over
+// them.  Measured on the 36-antenna workload: tiles of 2 to 8 units alike, 1 unit
+// and whole-wave order 5-15 % slower, and grouping 8-9 antennas to keep their
+// spectra for a whole DM group 3 % slower (more HBM reads, not fewer).
+constexpr int kUnitTile = 4;
+
+__host__ __device__ __forceinline__ int order_units(int n_units) {  // units covered by the grid
+  return (n_units + kUnitTile - 1) / kUnitTile * kUnitTile;
+}
 
 __device__ __forceinline__ bool unit_row(int lin, int n_units, int n_rows, int& row, int& u) {
-  if constexpr (kUnitTile == 0) {
-    u = lin % n_units;
-    row = lin / n_units;
-    return true;
-  }
-  const int t = kUnitTile > 0 ? kUnitTile : 1;
-  const int ul = lin % t;
-  lin /= t;
+  const int ul = lin % kUnitTile;
+  lin /= kUnitTile;
   row = lin % n_rows;
-  u = (lin / n_rows) * t + ul;
+  u = (lin / n_rows) * kUnitTile + ul;
   return u < n_units;
 }
 
@@ -226,7 +222,7 @@ __device__ __forceinline__ void store_stream_at(T* base, unsigned byte_off, T v)
 }
 
 // Chirp multiply, inverse FFT and overlap-save discard for a wave of units.
-// grid: ceil(n_units / kUnitTile) kUnitTile M workgroups (see unit_row).
+// grid: order_units(n_units) x M workgroups (see unit_row).
 // y[u.y + p y_stride + j] = IDFT(X H)[lead + j] for j < V.
 struct DedispArgs {
   const float2* spec;
@@ -331,7 +327,7 @@ __global__ __launch_bounds__(Geo<kBigLog>::T) void k_fft_rows(const float2* __re
 
 // Inverse pass A over a wave of units of one length N = 2^(15 + logr): row (p, k1)
 // of unit u times the chirp's row k1, inverse 2^15-point FFT, times w_N^{k1 n2}.
-// grid: ceil(n_units / kUnitTile) kUnitTile M R workgroups (see unit_row, rows p R + k1).
+// grid: order_units(n_units) x M R workgroups (see unit_row, rows p R + k1).
 __global__ __launch_bounds__(Geo<kBigLog>::T) void k_dedisperse_big_a(DedispArgs a) {
   using G = Geo<kBigLog>;
   extern __shared__ float lds[];
