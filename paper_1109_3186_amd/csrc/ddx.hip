@@ -14,10 +14,6 @@
 #include "kernels.hpp"
 #include "tiles.hpp"
 
-#ifndef DDX_OVERLAP
-#define DDX_OVERLAP 0
-#endif
-
 namespace {
 
 constexpr double kDefaultKdm = 4.148808e15;
@@ -101,11 +97,6 @@ struct ddx_plan {
   size_t tb_elems = 0;
   float2* chirp = nullptr;     // [wave_units][max N]
   void* ybuf = nullptr;        // [wave_units][M][y_stride]
-  void* ybuf2 = nullptr;       // second wave buffer when the correlator runs on its own stream
-  hipStream_t corr_stream = nullptr;            // plan-owned, default priority
-  hipEvent_t y_ready[2] = {nullptr, nullptr};   // dedispersion of a wave done
-  hipEvent_t y_free[2] = {nullptr, nullptr};    // correlation of a wave done
-  hipEvent_t corr_done = nullptr;
   int64_t y_stride = 0;
   float2* ring = nullptr;
   int64_t ring_dumps = 0;
@@ -196,7 +187,6 @@ void free_device(ddx_plan* p) {
   p->spec = p->tb = p->chirp = p->ring = nullptr;
   p->spec_elems = p->tb_elems = 0;
   p->ybuf = nullptr;
-  p->ybuf2 = nullptr;
   p->gtab = nullptr;
   p->scale_dev = nullptr;
   p->scale_part = nullptr;
@@ -264,7 +254,7 @@ hipError_t launch_forward_n(int in_dtype, const ddx::FwdArgs& a, int n_items, hi
 template <int LOGN>
 hipError_t launch_dedisp_n(int corr_dtype, const ddx::DedispArgs& a, hipStream_t s) {
   using G = ddx::Geo<LOGN>;
-  dim3 grid(ddx::order_units(a.n_units) * a.n_ant), block(G::T);
+  dim3 grid(ddx::order_units(a.n_units, a.tile) * a.n_ant), block(G::T);
   if (corr_dtype == DDX_CORR_F32)
     hipLaunchKernelGGL((ddx::k_dedisperse<LOGN, 0>), grid, block, fft_lds_bytes<LOGN>(), s, a);
   else if (corr_dtype == DDX_CORR_F16)
@@ -318,7 +308,7 @@ hipError_t launch_dedisp(int logn, int corr_dtype, const ddx::DedispArgs& a, hip
     case 15: return launch_dedisp_n<15>(corr_dtype, a, s);
   }
   if (logn <= kMaxLogN) {
-    const unsigned ga = (unsigned)((size_t)ddx::order_units(a.n_units) * a.n_ant << a.logr);
+    const unsigned ga = (unsigned)((size_t)ddx::order_units(a.n_units, a.tile) * a.n_ant << a.logr);
     hipLaunchKernelGGL(ddx::k_dedisperse_big_a, dim3(ga), dim3(ddx::Geo<ddx::kBigLog>::T),
                        fft_lds_bytes<ddx::kBigLog>(), s, a);
     hipError_t e = hipGetLastError();
@@ -502,15 +492,7 @@ int setup_device(ddx_plan* p) {
   }
   p->wave_units = (int)std::min<int64_t>(p->wave_units, std::max<int64_t>(max_units, 1));
   if ((rc = dev_alloc(p, &p->ybuf, per_unit * p->wave_units))) return rc;
-  if (DDX_OVERLAP) {
-    if ((rc = dev_alloc(p, &p->ybuf2, per_unit * p->wave_units))) return rc;
-    if (!p->corr_stream) HIPCHECK(p, hipStreamCreateWithFlags(&p->corr_stream, hipStreamNonBlocking));
-    for (int i = 0; i < 2; ++i) {
-      if (!p->y_ready[i]) HIPCHECK(p, hipEventCreateWithFlags(&p->y_ready[i], hipEventDisableTiming));
-      if (!p->y_free[i]) HIPCHECK(p, hipEventCreateWithFlags(&p->y_free[i], hipEventDisableTiming));
-    }
-    if (!p->corr_done) HIPCHECK(p, hipEventCreateWithFlags(&p->corr_done, hipEventDisableTiming));
-  }
+
   if ((rc = dev_alloc(p, (void**)&p->chirp, (size_t)p->wave_units * maxn * sizeof(float2)))) return rc;
   // two-pass transforms: intermediate rows of one wave (dedispersion); the forward
   // transform runs its items in chunks of the same size
@@ -1028,16 +1010,11 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
     }
   }
 
-  // waves: chirps, dedispersion, correlation.  With a separate correlator stream the
-  // correlation of wave i overlaps the dedispersion of wave i + 1 (two voltage buffers).
+  // waves: chirps, dedispersion, correlation.  (A second stream for the correlator,
+  // overlapping it with the next wave's dedispersion, measured no faster: both
+  // kernels are limited by the same memory system.)
   const double nbl_h = p->M * (p->M + 1) / 2.0;
-  const bool two = p->corr_stream != nullptr;
-  hipStream_t sc = two ? p->corr_stream : s;
-  for (size_t wi = 0; wi < w.waves.size(); ++wi) {
-    const Wave& wv = w.waves[wi];
-    const int slot = (int)(wi & 1);
-    void* yb = (two && slot) ? p->ybuf2 : p->ybuf;
-    if (two && wi >= 2) HIPCHECK(p, hipStreamWaitEvent(s, p->y_free[slot], 0));
+  for (const Wave& wv : w.waves) {
     const double nn = wv.fft_n;
     HIPCHECK(p, timed(p, s, DDX_K_CHIRP, 0.0, (double)wv.nc * nn * 16.0, [&] {
       hipLaunchKernelGGL(ddx::k_chirp, dim3((unsigned)((wv.fft_n + 255) / 256), (unsigned)wv.nc), dim3(256), 0, s,
@@ -1048,22 +1025,19 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
     ddx::DedispArgs da{};
     da.spec = p->spec;
     da.chirp = p->chirp;
-    da.y = yb;
+    da.y = p->ybuf;
     da.tb = p->tb;
     da.units = units_dev + wv.u0;
     da.y_stride = p->y_stride;
     da.n_ant = p->M;
     da.n_units = (int)wv.nu;
     da.logr = wv.logn > ddx::kBigLog ? wv.logn - ddx::kBigLog : 0;
+    da.tile = ddx::unit_tile(da.n_units);
     HIPCHECK(p, timed(p, s, DDX_K_DEDISP, (double)wv.nu * p->M * (fft_flops(nn) + 6.0 * nn),
                       8.0 * nn * ((double)wv.nu * p->M + wv.nc) + (double)wv.y_samples * y_bytes(p->corr_dtype),
                       [&] { return launch_dedisp(wv.logn, p->corr_dtype, da, s); }));
-    if (two) {
-      HIPCHECK(p, hipEventRecord(p->y_ready[slot], s));
-      HIPCHECK(p, hipStreamWaitEvent(sc, p->y_ready[slot], 0));
-    }
     ddx::CorrArgs ca{};
-    ca.y = yb;
+    ca.y = p->ybuf;
     ca.ring = p->ring;
     ca.units = units_dev + wv.u0;
     ca.scale = p->scale_dev;
@@ -1075,14 +1049,9 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
     ca.dump_len = p->L;
     ca.nbl = p->nbl;
     ca.out_mode = p->out_mode;
-    HIPCHECK(p, timed(p, sc, DDX_K_CORR, (double)wv.dumps * 8.0 * p->L * nbl_h,
+    HIPCHECK(p, timed(p, s, DDX_K_CORR, (double)wv.dumps * 8.0 * p->L * nbl_h,
                       (double)wv.dumps * ((double)p->L * p->M * y_bytes(p->corr_dtype) + 8.0 * p->nbl),
-                      [&] { return launch_corr(p->corr_dtype, ca, (int)wv.nu, sc); }));
-    if (two) HIPCHECK(p, hipEventRecord(p->y_free[slot], sc));
-  }
-  if (two && !w.waves.empty()) {  // the caller's stream continues after every correlation
-    HIPCHECK(p, hipEventRecord(p->corr_done, sc));
-    HIPCHECK(p, hipStreamWaitEvent(s, p->corr_done, 0));
+                      [&] { return launch_corr(p->corr_dtype, ca, (int)wv.nu, s); }));
   }
   if (!w.zeros.empty()) {
     HIPCHECK(p, timed(p, s, DDX_K_OTHER, 0.0, 8.0 * (double)w.zeros.size() * w.zeros[0].n * p->nbl, [&] {
@@ -1288,12 +1257,8 @@ int ddx_get_profile(ddx_plan* p, ddx_profile* out) {
 int ddx_plan_destroy(ddx_plan* p) {
   if (!p) return DDX_OK;
   if (p->last_stream || p->started) (void)hipStreamSynchronize(p->last_stream);
-  if (p->corr_stream) (void)hipStreamSynchronize(p->corr_stream);
   for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
-  for (hipEvent_t e : {p->y_ready[0], p->y_ready[1], p->y_free[0], p->y_free[1], p->corr_done})
-    if (e) (void)hipEventDestroy(e);
   free_device(p);
-  if (p->corr_stream) (void)hipStreamDestroy(p->corr_stream);
   delete p;
   return DDX_OK;
 }

@@ -177,8 +177,9 @@ __device__ __forceinline__ typename YType<OUT>::T convert_y(float2 v) {
 }
 
 // Order of a wave's workgroups: logical ids (XCD-remapped, so a run of ids shares
-// one XCD's L2) take kUnitTile units fastest, then the rows (antennas, or antenna
-// x k1 rows of a two-pass transform), then the next tile of units.  Units run
+// one XCD's L2) take `tile` units fastest (4; a wave of fewer than 8 units is one
+// tile, so no workgroup idles), then the rows (antennas, or antenna x k1 rows of a
+// two-pass transform), then the next tile of units.  Units run
 // DM-fastest within a block, so the workgroups one XCD runs at a time read a few
 // spectra and 4 chirps, and the 4 chirps stay in L2 while every antenna passes over
 // them.  Measured on the 36-antenna workload: tiles of 2 to 8 units alike, 1 unit
@@ -186,15 +187,16 @@ __device__ __forceinline__ typename YType<OUT>::T convert_y(float2 v) {
 // spectra for a whole DM group 3 % slower (more HBM reads, not fewer).
 constexpr int kUnitTile = 4;
 
-__host__ __device__ __forceinline__ int order_units(int n_units) {  // units covered by the grid
-  return (n_units + kUnitTile - 1) / kUnitTile * kUnitTile;
+__host__ __device__ __forceinline__ int unit_tile(int n_units) { return n_units < 2 * kUnitTile ? n_units : kUnitTile; }
+__host__ __device__ __forceinline__ int order_units(int n_units, int tile) {  // units covered by the grid
+  return (n_units + tile - 1) / tile * tile;
 }
 
-__device__ __forceinline__ bool unit_row(int lin, int n_units, int n_rows, int& row, int& u) {
-  const int ul = lin % kUnitTile;
-  lin /= kUnitTile;
+__device__ __forceinline__ bool unit_row(int lin, int n_units, int n_rows, int tile, int& row, int& u) {
+  const int ul = lin % tile;
+  lin /= tile;
   row = lin % n_rows;
-  u = (lin / n_rows) * kUnitTile + ul;
+  u = (lin / n_rows) * tile + ul;
   return u < n_units;
 }
 
@@ -222,7 +224,7 @@ __device__ __forceinline__ void store_stream_at(T* base, unsigned byte_off, T v)
 }
 
 // Chirp multiply, inverse FFT and overlap-save discard for a wave of units.
-// grid: order_units(n_units) x M workgroups (see unit_row).
+// grid: order_units(n_units, tile) x M workgroups (see unit_row).
 // y[u.y + p y_stride + j] = IDFT(X H)[lead + j] for j < V.
 struct DedispArgs {
   const float2* spec;
@@ -231,7 +233,7 @@ struct DedispArgs {
   float2* tb;           // two-pass transforms: intermediate rows
   const UnitItem* units;
   int64_t y_stride;
-  int32_t n_ant, n_units, logr;
+  int32_t n_ant, n_units, logr, tile;
 };
 
 template <int LOGN, int OUT>
@@ -240,7 +242,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_dedisperse(DedispArgs a) {
   extern __shared__ float lds[];
   const int t = threadIdx.x;
   int p, ui;
-  if (!unit_row(xcd_remap(blockIdx.x, gridDim.x), a.n_units, a.n_ant, p, ui)) return;
+  if (!unit_row(xcd_remap(blockIdx.x, gridDim.x), a.n_units, a.n_ant, a.tile, p, ui)) return;
   const UnitItem w = a.units[ui];
   const float2* x = a.spec + w.spec + (size_t)p * G::N;
   const float2* h = a.chirp + w.chirp;
@@ -327,13 +329,13 @@ __global__ __launch_bounds__(Geo<kBigLog>::T) void k_fft_rows(const float2* __re
 
 // Inverse pass A over a wave of units of one length N = 2^(15 + logr): row (p, k1)
 // of unit u times the chirp's row k1, inverse 2^15-point FFT, times w_N^{k1 n2}.
-// grid: order_units(n_units) x M R workgroups (see unit_row, rows p R + k1).
+// grid: order_units(n_units, tile) x M R workgroups (see unit_row, rows p R + k1).
 __global__ __launch_bounds__(Geo<kBigLog>::T) void k_dedisperse_big_a(DedispArgs a) {
   using G = Geo<kBigLog>;
   extern __shared__ float lds[];
   const int t = threadIdx.x;
   int row, ui;  // row = p R + k1
-  if (!unit_row(xcd_remap(blockIdx.x, gridDim.x), a.n_units, a.n_ant << a.logr, row, ui)) return;
+  if (!unit_row(xcd_remap(blockIdx.x, gridDim.x), a.n_units, a.n_ant << a.logr, a.tile, row, ui)) return;
   const UnitItem w = a.units[ui];
   const int k1 = row & ((1 << a.logr) - 1);
   const float2* x = a.spec + w.spec + (size_t)row * kBigN;
