@@ -431,6 +431,7 @@ template <int T, int NT> struct CorrLds {
 };
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 
 // Correlator: per (DM, dump) the Gram matrix of the stacked real rows
 // [Re y_0 .. Re y_{M-1}, Im y_0 .. Im y_{M-1}] over the L samples of the dump
@@ -475,23 +476,29 @@ __device__ __forceinline__ void split16(float x, _Float16& hi, _Float16& lo) {
   lo = (_Float16)(x - (float)hi);
 }
 
+// Stage two consecutive samples (k, k + 1; k even) of one antenna: the Re row gets
+// (re0, re1) and the Im row (im0, im1), each written as one packed LDS store (4
+// bytes for binary16 values, 2 for E4M3) instead of one store per value.
 template <int T, int PLANE>
-__device__ __forceinline__ void store_pair(typename CorrIn<T>::E* at, int ia_re0, int ia_re1, int ia_im0, int ia_im1,
-                                           typename CorrIn<T>::Pair v) {
+__device__ __forceinline__ void store_pair(typename CorrIn<T>::E* at, int ia_re, int ia_im, typename CorrIn<T>::Pair v) {
   if constexpr (T == 0) {
-    split16(v.x, at[ia_re0], at[PLANE + ia_re0]);
-    split16(v.y, at[ia_im0], at[PLANE + ia_im0]);
-    split16(v.z, at[ia_re1], at[PLANE + ia_re1]);
-    split16(v.w, at[ia_im1], at[PLANE + ia_im1]);
+    _Float16 h0, l0, h1, l1;
+    split16(v.x, h0, l0);
+    split16(v.z, h1, l1);
+    *reinterpret_cast<half2v*>(&at[ia_re]) = half2v{h0, h1};
+    *reinterpret_cast<half2v*>(&at[PLANE + ia_re]) = half2v{l0, l1};
+    split16(v.y, h0, l0);
+    split16(v.w, h1, l1);
+    *reinterpret_cast<half2v*>(&at[ia_im]) = half2v{h0, h1};
+    *reinterpret_cast<half2v*>(&at[PLANE + ia_im]) = half2v{l0, l1};
   } else if constexpr (T == 1) {
-    const __half2 s0 = *reinterpret_cast<const __half2*>(&v.x), s1 = *reinterpret_cast<const __half2*>(&v.y);
-    at[ia_re0] = (_Float16)__low2float(s0);  // exact: the values are binary16 already
-    at[ia_im0] = (_Float16)__high2float(s0);
-    at[ia_re1] = (_Float16)__low2float(s1);
-    at[ia_im1] = (_Float16)__high2float(s1);
+    // v.x = (re0, im0), v.y = (re1, im1) as binary16 pairs
+    *reinterpret_cast<uint32_t*>(&at[ia_re]) = (v.x & 0xffffu) | (v.y << 16);
+    *reinterpret_cast<uint32_t*>(&at[ia_im]) = (v.x >> 16) | (v.y & 0xffff0000u);
   } else {
-    at[ia_re0] = (uint8_t)(v & 0xff); at[ia_im0] = (uint8_t)((v >> 8) & 0xff);
-    at[ia_re1] = (uint8_t)((v >> 16) & 0xff); at[ia_im1] = (uint8_t)(v >> 24);
+    // v = re0 | im0 << 8 | re1 << 16 | im1 << 24
+    *reinterpret_cast<uint16_t*>(&at[ia_re]) = (uint16_t)((v & 0xffu) | ((v >> 8) & 0xff00u));
+    *reinterpret_cast<uint16_t*>(&at[ia_im]) = (uint16_t)(((v >> 8) & 0xffu) | ((v >> 16) & 0xff00u));
   }
 }
 
@@ -562,7 +569,7 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
       const int e = tid + 256 * i;
       if (e < pairs) {
         const int p = e / (kCorrKC / 2), k = 2 * (e % (kCorrKC / 2));
-        store_pair<T, Ld::PLANE>(at, Ld::at(p, k), Ld::at(p, k + 1), Ld::at(M + p, k), Ld::at(M + p, k + 1), buf[i]);
+        store_pair<T, Ld::PLANE>(at, Ld::at(p, k), Ld::at(M + p, k), buf[i]);
       }
     }
   };
@@ -723,7 +730,7 @@ __global__ __launch_bounds__(256) void k_correlate_blocks(CorrArgs a) {
       const int e = tid + 256 * i;
       const int la = e / (kCorrKC / 2), k = 2 * (e % (kCorrKC / 2));
       const int rr = row_re(la), ri = rr + kBlkAnt;
-      store_pair<T, PLANE>(at, rr * KP + k, rr * KP + k + 1, ri * KP + k, ri * KP + k + 1, buf[i]);
+      store_pair<T, PLANE>(at, rr * KP + k, ri * KP + k, buf[i]);
     }
   };
   auto frag = [&](int plane, int row, int kr) -> Frag {
