@@ -85,7 +85,7 @@ def compare_with_oracle(cfg, vis, lay, pairs=None, quant=None, scales=None):
     for c in chans:
         ds = [d for cc, d in pairs if cc == c] if pairs else None
         ref = oracle.run_oracle(cfg["volts"], cfg["chan_freqs"], cfg["f_s"], cfg["dm_lists"], cfg["dump_len"], bl,
-                                quant=quant, scales=scales, chans=[c], dm_index=ds)
+                                sideband=int(lay["sideband"]), quant=quant, scales=scales, chans=[c], dm_index=ds)
         for (cc, d), v in ref.items():
             got = select(vis, lay, cc, d)
             assert got.shape == v.shape, (got.shape, v.shape)
