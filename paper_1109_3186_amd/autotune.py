@@ -13,9 +13,11 @@ noise, the workload's own channels and DM grids):
   (DMs run back to back on one spectrum block).
 
 Throughput is measured as antenna-samples x DM trials per second over a whole
-short stream (process_block + fetch into device memory).  Results are cached in
-a JSON file keyed by the device, the library build and the workload, so a later
-run with the same key costs nothing.
+short stream (process_block + fetch into device memory), processed in calls of
+the workload's own size (max_block), so that the block count of each length is
+the one the workload will see.  Results are cached in a JSON file keyed by the
+device, the workload and TUNE_VERSION (raised when the search or the kernels'
+trade-offs change), so a later run with the same key costs nothing.
 """
 import hashlib
 import json
@@ -25,23 +27,17 @@ import time
 
 import numpy as np
 
-from .binding import LIB_PATH, DdxError, Plan
+from .binding import DdxError, Plan
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 MAX_LEN = 1 << 18
-
-
-def _lib_hash():
-    h = hashlib.sha256()
-    with open(LIB_PATH, "rb") as f:
-        h.update(f.read())
-    return h.hexdigest()[:16]
+TUNE_VERSION = 2
 
 
 def workload_key(n_ant, chan_freqs, samp_rate, dump_len, dm_lists, corr_dtype, in_dtype, max_block):
     import torch
     desc = {
-        "device": torch.cuda.get_device_name(0), "lib": _lib_hash(), "n_ant": int(n_ant),
+        "device": torch.cuda.get_device_name(0), "version": TUNE_VERSION, "n_ant": int(n_ant),
         "chan_freqs": [float(f) for f in chan_freqs], "samp_rate": float(samp_rate), "dump_len": int(dump_len),
         "dms": hashlib.sha256(np.concatenate([np.asarray(d, np.float64) for d in dm_lists]).tobytes()).hexdigest()[:16],
         "n_dm": [int(len(d)) for d in dm_lists], "corr": corr_dtype, "in": in_dtype, "max_block": int(max_block),
@@ -124,13 +120,14 @@ def tune(n_ant, chan_freqs, samp_rate, dump_len, dm_lists, corr_dtype="f32", in_
         rep = min(members, key=lambda c: auto_v[c])  # longest smear of the group
         dms = _sample_dms(dm_lists[rep], dm_sample)
         cands = [n for n in (n0 // 2, n0, 2 * n0, 4 * n0) if 256 <= n <= MAX_LEN]
-        s = max(4 * max(cands), 1 << 17)
+        # the workload's call size when it holds a block of every candidate, else four blocks
+        s = max_block if max_block >= max(cands) else max(4 * max(cands), 1 << 17)
         x = _noise(1, n_ant, s, in_dtype, seed=1113)
         rates = {}
         for n in cands:
             try:
                 with Plan(n_ant, chan_freqs[rep:rep + 1], samp_rate, dump_len, max_block_samples=s,
-                          in_dtype=in_dtype, corr_dtype=corr_dtype, fft_len=n, ring_dumps=s // dump_len + 2) as p:
+                          in_dtype=in_dtype, corr_dtype=corr_dtype, fft_len=n, ring_dumps=s // dump_len + 4) as p:
                     p.set_dm_trials(dms)
                     t = _time_stream(p, x)
                     rates[n] = n_ant * s * len(dms) / t
@@ -203,11 +200,13 @@ if __name__ == "__main__":
     ap.add_argument("workload", choices=["c1", "c3"])
     ap.add_argument("--corr", default="f32", choices=["f32", "f16", "e4m3"])
     ap.add_argument("--force", action="store_true")
+    ap.add_argument("--cache", default=DEFAULT_CACHE, help="JSON cache file")
     a = ap.parse_args()
     p = synth.c1_params() if a.workload == "c1" else synth.c3_params()
     fc = synth.chan_freqs(p["f_lo"], p["n_chan"], p["f_s"])
     nd = p["n_dm"] if isinstance(p["n_dm"], list) else [p["n_dm"]] * p["n_chan"]
     dms = [synth.dm_grid(n, p["dm_max"]) for n in nd]
-    res = tune(p["m_ant"], fc, p["f_s"], p["dump_len"], dms, corr_dtype=a.corr, max_block=1 << 18,
-               force=a.force, log=lambda *m: print(*m, flush=True))
+    res = tune(p["m_ant"], fc, p["f_s"], p["dump_len"], dms, corr_dtype=a.corr,
+               max_block=(1 << 18) if a.workload == "c1" else p["samples"], cache=a.cache, force=a.force,
+               log=lambda *m: print(*m, flush=True))
     print(json.dumps({k: res[k] for k in ("fft_len", "wave_units", "dm_group", "source")}))
