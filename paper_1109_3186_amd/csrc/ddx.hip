@@ -237,11 +237,11 @@ int blocking(ddx_plan* p, Chan& c, int fft_req) {
 // ---- kernel dispatch over template parameters ------------------------------------------
 
 template <int LOGN>
-size_t fft_lds_bytes() { return sizeof(float) * ddx::Geo<LOGN>::LDS_FLOATS; }
+size_t fft_lds_bytes() { return sizeof(float) * ddx::Geo<ddx::Plan<LOGN>>::LDS_FLOATS; }
 
 template <int LOGN>
 hipError_t launch_forward_n(int in_dtype, const ddx::FwdArgs& a, int n_items, hipStream_t s) {
-  using G = ddx::Geo<LOGN>;
+  using G = ddx::Geo<ddx::Plan<LOGN>>;
   dim3 grid(n_items * a.n_ant), block(G::T);
   if (in_dtype == DDX_IN_CI8)
     hipLaunchKernelGGL((ddx::k_forward<LOGN, 0>), grid, block, fft_lds_bytes<LOGN>(), s, a);
@@ -253,14 +253,17 @@ hipError_t launch_forward_n(int in_dtype, const ddx::FwdArgs& a, int n_items, hi
 
 template <int LOGN>
 hipError_t launch_dedisp_n(int corr_dtype, const ddx::DedispArgs& a, hipStream_t s) {
-  using G = ddx::Geo<LOGN>;
-  dim3 grid(ddx::order_units(a.n_units, a.tile) * a.n_ant), block(G::T);
+  const dim3 grid(ddx::order_units(a.n_units, a.tile) * a.n_ant);
+  auto block = [](auto out) { return dim3(ddx::Geo<ddx::DedispPlan<LOGN, decltype(out)::value>>::T); };
   if (corr_dtype == DDX_CORR_F32)
-    hipLaunchKernelGGL((ddx::k_dedisperse<LOGN, 0>), grid, block, fft_lds_bytes<LOGN>(), s, a);
+    hipLaunchKernelGGL((ddx::k_dedisperse<LOGN, 0>), grid, block(std::integral_constant<int, 0>()),
+                       fft_lds_bytes<LOGN>(), s, a);
   else if (corr_dtype == DDX_CORR_F16)
-    hipLaunchKernelGGL((ddx::k_dedisperse<LOGN, 1>), grid, block, fft_lds_bytes<LOGN>(), s, a);
+    hipLaunchKernelGGL((ddx::k_dedisperse<LOGN, 1>), grid, block(std::integral_constant<int, 1>()),
+                       fft_lds_bytes<LOGN>(), s, a);
   else
-    hipLaunchKernelGGL((ddx::k_dedisperse<LOGN, 2>), grid, block, fft_lds_bytes<LOGN>(), s, a);
+    hipLaunchKernelGGL((ddx::k_dedisperse<LOGN, 2>), grid, block(std::integral_constant<int, 2>()),
+                       fft_lds_bytes<LOGN>(), s, a);
   return hipGetLastError();
 }
 
@@ -291,7 +294,7 @@ hipError_t launch_forward_big(int logn, int in_dtype, ddx::FwdArgs a, const ddx:
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const unsigned rows = (unsigned)((size_t)n_items * a.n_ant << logr);
-  hipLaunchKernelGGL(ddx::k_fft_rows, dim3(rows), dim3(ddx::Geo<ddx::kBigLog>::T), fft_lds_bytes<ddx::kBigLog>(), s,
+  hipLaunchKernelGGL(ddx::k_fft_rows, dim3(rows), dim3(ddx::Geo<ddx::RowPlan>::T), fft_lds_bytes<ddx::kBigLog>(), s,
                      (const float2*)tb, a.spec + first_host->spec);
   return hipGetLastError();
 }
@@ -309,7 +312,7 @@ hipError_t launch_dedisp(int logn, int corr_dtype, const ddx::DedispArgs& a, hip
   }
   if (logn <= kMaxLogN) {
     const unsigned ga = (unsigned)((size_t)ddx::order_units(a.n_units, a.tile) * a.n_ant << a.logr);
-    hipLaunchKernelGGL(ddx::k_dedisperse_big_a, dim3(ga), dim3(ddx::Geo<ddx::kBigLog>::T),
+    hipLaunchKernelGGL(ddx::k_dedisperse_big_a, dim3(ga), dim3(ddx::Geo<ddx::Plan<ddx::kBigLog>>::T),
                        fft_lds_bytes<ddx::kBigLog>(), s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -110,23 +110,31 @@ template <int R>
 __device__ __forceinline__ constexpr int out_reg(int q) { return q; }
 
 // Radix plan per transform length: P points per thread, passes of radix R[i].
+template <int LOGN_, int P_, int NP_, int R0, int R1, int R2, int R3 = 1>
+struct PlanDef {
+  static constexpr int LOGN = LOGN_, P = P_, NP = NP_;
+  static constexpr int R[4] = {R0, R1, R2, R3};
+};
 template <int LOGN> struct Plan;
-template <> struct Plan<8>  { static constexpr int P = 16, NP = 2, R[3] = {16, 16, 1}; };
-template <> struct Plan<9>  { static constexpr int P = 16, NP = 3, R[3] = {16, 16, 2}; };
-template <> struct Plan<10> { static constexpr int P = 16, NP = 3, R[3] = {16, 16, 4}; };
-template <> struct Plan<11> { static constexpr int P = 16, NP = 3, R[3] = {16, 16, 8}; };
-template <> struct Plan<12> { static constexpr int P = 16, NP = 3, R[3] = {16, 16, 16}; };
-template <> struct Plan<13> { static constexpr int P = 16, NP = 4, R[4] = {16, 16, 16, 2}; };
-template <> struct Plan<14> { static constexpr int P = 16, NP = 4, R[4] = {16, 16, 16, 4}; };
-template <> struct Plan<15> { static constexpr int P = 64, NP = 3, R[3] = {32, 32, 32}; };
+template <> struct Plan<8> : PlanDef<8, 16, 2, 16, 16, 1> {};
+template <> struct Plan<9> : PlanDef<9, 16, 3, 16, 16, 2> {};
+template <> struct Plan<10> : PlanDef<10, 16, 3, 16, 16, 4> {};
+template <> struct Plan<11> : PlanDef<11, 16, 3, 16, 16, 8> {};
+template <> struct Plan<12> : PlanDef<12, 16, 3, 16, 16, 16> {};
+template <> struct Plan<13> : PlanDef<13, 16, 4, 16, 16, 16, 2> {};
+template <> struct Plan<14> : PlanDef<14, 16, 4, 16, 16, 16, 4> {};
+template <> struct Plan<15> : PlanDef<15, 64, 3, 32, 32, 32> {};
+// 32768 points over 1024 threads of 32 points: four waves per SIMD at 128 VGPRs
+// instead of two at ~205, for kernels whose register use allows it.
+struct Plan15Wide : PlanDef<15, 32, 3, 32, 32, 32> {};
 
-template <int LOGN> struct Geo {
-  static constexpr int N = 1 << LOGN;
-  static constexpr int P = Plan<LOGN>::P;
+template <class PL> struct Geo {
+  static constexpr int N = 1 << PL::LOGN;
+  static constexpr int P = PL::P;
   static constexpr int T = N / P;  // threads per workgroup
-  static constexpr int NP = Plan<LOGN>::NP;
-  static constexpr int R0 = Plan<LOGN>::R[0];
-  static constexpr int RL = Plan<LOGN>::R[NP - 1];
+  static constexpr int NP = PL::NP;
+  static constexpr int R0 = PL::R[0];
+  static constexpr int RL = PL::R[NP - 1];
   // LDS floats for one half-exchange (one pad word per 32 against bank conflicts)
   static constexpr int LDS_FLOATS = N + N / 32;
 };
@@ -143,9 +151,9 @@ __device__ __forceinline__ float* lds_seg(float* base, int r) {
   return base + (r / SEG) * SEG * STRIDE;
 }
 
-template <int LOGN, int R, int NS, int R2>
+template <class PL, int R, int NS, int R2>
 __device__ __forceinline__ void exchange(float2* v, float* lds, int t) {
-  using G = Geo<LOGN>;
+  using G = Geo<PL>;
   // writes: output q of butterfly j goes to (j / NS) NS R + k + q NS
   constexpr bool WLIN = (NS % 32 == 0) || (NS * R <= 32 && 32 % (NS * R) == 0) || (NS == 1 && R % 32 == 0);
   // reads: point r of the next pass is t + u T + r N / R2
@@ -240,9 +248,9 @@ __device__ __forceinline__ void apply_twiddles(float2* v, int k) {
   }
 }
 
-template <int LOGN, int R, int NS, int S>
+template <class PL, int R, int NS, int S>
 __device__ __forceinline__ void pass(float2* v, int t) {
-  using G = Geo<LOGN>;
+  using G = Geo<PL>;
   constexpr int LOGD = ilog2(NS * R);
   int z = 0;
 #pragma unroll
@@ -258,23 +266,23 @@ __device__ __forceinline__ void pass(float2* v, int t) {
 }
 
 // Passes 1.. of the transform (pass 0 is done by the caller, fused with its loads).
-template <int LOGN, int S, int PASS, int NS>
+template <class PL, int S, int PASS, int NS>
 struct Passes {
   __device__ __forceinline__ static void run(float2* v, float* lds, int t) {
-    constexpr int RP = Plan<LOGN>::R[PASS - 1];
-    constexpr int R = Plan<LOGN>::R[PASS];
-    exchange<LOGN, RP, NS / RP, R>(v, lds, t);
-    pass<LOGN, R, NS, S>(v, t);
-    if constexpr (PASS + 1 < Plan<LOGN>::NP) Passes<LOGN, S, PASS + 1, NS * R>::run(v, lds, t);
+    constexpr int RP = PL::R[PASS - 1];
+    constexpr int R = PL::R[PASS];
+    exchange<PL, RP, NS / RP, R>(v, lds, t);
+    pass<PL, R, NS, S>(v, t);
+    if constexpr (PASS + 1 < PL::NP) Passes<PL, S, PASS + 1, NS * R>::run(v, lds, t);
   }
 };
 
 // Full transform.  load(i) supplies input point i; the first pass runs group by
 // group as its points arrive.  On return output t + u T + q N / RL is in register
 // u RL + out_reg<RL>(q).
-template <int LOGN, int S, class Load>
+template <class PL, int S, class Load>
 __device__ __forceinline__ void fft_workgroup(float2* v, float* lds, int t, Load load) {
-  using G = Geo<LOGN>;
+  using G = Geo<PL>;
   int z = 0;
 #pragma unroll
   for (int u = 0; u < G::P / G::R0; ++u) {
@@ -289,7 +297,7 @@ __device__ __forceinline__ void fft_workgroup(float2* v, float* lds, int t, Load
     }
 #endif
   }
-  if constexpr (G::NP > 1) Passes<LOGN, S, 1, G::R0>::run(v, lds, t);
+  if constexpr (G::NP > 1) Passes<PL, S, 1, G::R0>::run(v, lds, t);
 }
 
 }  // namespace ddx

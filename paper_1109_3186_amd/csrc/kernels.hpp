@@ -10,6 +10,9 @@
 #ifndef DDX_NT_STORE
 #define DDX_NT_STORE 1
 #endif
+#ifndef DDX_RANGED_STORE
+#define DDX_RANGED_STORE 1
+#endif
 
 namespace ddx {
 
@@ -113,8 +116,8 @@ struct FwdArgs {
 };
 
 template <int LOGN, int IN>
-__global__ __launch_bounds__(Geo<LOGN>::T) void k_forward(FwdArgs a) {
-  using G = Geo<LOGN>;
+__global__ __launch_bounds__(Geo<Plan<LOGN>>::T) void k_forward(FwdArgs a) {
+  using G = Geo<Plan<LOGN>>;
   extern __shared__ float lds[];
   const int t = threadIdx.x;
   const int p = blockIdx.x % a.n_ant;
@@ -123,7 +126,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_forward(FwdArgs a) {
   s.row = w.chan * a.n_ant + p;
   s.hist_start = w.hist_start;
   float2 v[G::P];
-  fft_workgroup<LOGN, -1>(v, lds, t, [&](int i) { return load_sample<IN>(s, w.win0 + i); });
+  fft_workgroup<Plan<LOGN>, -1>(v, lds, t, [&](int i) { return load_sample<IN>(s, w.win0 + i); });
   // output addresses are formed only now (otherwise they are hoisted and held in registers)
   float2* out = a.spec + w.spec + (size_t)p * G::N + opaque_zero(v[0].x);
 #pragma unroll
@@ -223,6 +226,33 @@ __device__ __forceinline__ void store_stream_at(T* base, unsigned byte_off, T v)
   store_stream(reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off), v);
 }
 
+// Buffer resource over `bytes` bytes at `base` (raw, stride 0, 32-bit data format).
+// A store whose byte offset is at or past `bytes` is dropped by the hardware's range
+// check, so a store that is kept only for some lanes needs no branch around it.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t range_rsrc(void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, 0x00020000);
+}
+
+template <class T>
+__device__ __forceinline__ void store_ranged(__amdgpu_buffer_rsrc_t r, unsigned byte_off, T v) {
+  constexpr int aux = DDX_NT_STORE ? 2 : 0;  // 2: non-temporal
+  if constexpr (sizeof(T) == 8) {
+    typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(*reinterpret_cast<const u2v*>(&v), r, byte_off, 0, aux);
+  } else if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(*reinterpret_cast<const unsigned int*>(&v), r, byte_off, 0, aux);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b16(*reinterpret_cast<const unsigned short*>(&v), r, byte_off, 0, aux);
+  }
+}
+
+// FFT plan of k_dedisperse: the 1024-thread form of the 32768-point plan for the
+// binary16 and E4M3 outputs (their VALU work gains from the extra waves: 2293 ->
+// 2077 ms per 36-antenna E4M3 step), the 512-thread form for FP32 output, which
+// measured no faster with it.
+template <int LOGN, int OUT>
+using DedispPlan = typename std::conditional<LOGN == 15 && OUT != 0, Plan15Wide, Plan<LOGN>>::type;
+
 // Chirp multiply, inverse FFT and overlap-save discard for a wave of units.
 // grid: order_units(n_units, tile) x M workgroups (see unit_row).
 // y[u.y + p y_stride + j] = IDFT(X H)[lead + j] for j < V.
@@ -237,8 +267,8 @@ struct DedispArgs {
 };
 
 template <int LOGN, int OUT>
-__global__ __launch_bounds__(Geo<LOGN>::T) void k_dedisperse(DedispArgs a) {
-  using G = Geo<LOGN>;
+__global__ __launch_bounds__((Geo<DedispPlan<LOGN, OUT>>::T)) void k_dedisperse(DedispArgs a) {
+  using G = Geo<DedispPlan<LOGN, OUT>>;
   extern __shared__ float lds[];
   const int t = threadIdx.x;
   int p, ui;
@@ -248,11 +278,23 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_dedisperse(DedispArgs a) {
   const float2* h = a.chirp + w.chirp;
   float2 v[G::P];
   // 32-bit byte offsets from a uniform base: each load needs one 32-bit add, not a 64-bit address
-  fft_workgroup<LOGN, +1>(v, lds, t, [&](int i) { return cmul(at_byte(x, 8u * (unsigned)i), at_byte(h, 8u * (unsigned)i)); });
+  fft_workgroup<DedispPlan<LOGN, OUT>, +1>(v, lds, t,
+                                           [&](int i) { return cmul(at_byte(x, 8u * (unsigned)i), at_byte(h, 8u * (unsigned)i)); });
   typedef typename YType<OUT>::T YT;
   // output addresses are formed only now (otherwise they are hoisted and held in registers)
   YT* y = reinterpret_cast<YT*>(a.y) + w.y + (size_t)p * a.y_stride;
   const int z = opaque_zero(v[0].x);
+#if DDX_RANGED_STORE
+  // points outside [lead, lead + V) get the offset V (unsigned wrap included) and are dropped
+  const __amdgpu_buffer_rsrc_t yr = range_rsrc(y, (unsigned)w.valid * (unsigned)sizeof(YT));
+#pragma unroll
+  for (int u = 0; u < G::P / G::RL; ++u)
+#pragma unroll
+    for (int q = 0; q < G::RL; ++q) {
+      const unsigned j = min((unsigned)(t + z + u * G::T + q * (G::N / G::RL) - w.lead), (unsigned)w.valid);
+      store_ranged(yr, j * (unsigned)sizeof(YT), convert_y<OUT>(v[u * G::RL + out_reg<G::RL>(q)]));
+    }
+#else
 #pragma unroll
   for (int u = 0; u < G::P / G::RL; ++u)
 #pragma unroll
@@ -261,6 +303,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_dedisperse(DedispArgs a) {
       if (j < (unsigned)w.valid)
         store_stream_at(y, j * (unsigned)sizeof(YT), convert_y<OUT>(v[u * G::RL + out_reg<G::RL>(q)]));
     }
+#endif
 }
 
 // ---------------------------------------------------------------------------
@@ -276,6 +319,10 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_dedisperse(DedispArgs a) {
 // then an R-point DFT per n2 (k_dedisperse_big_b), which writes y in natural order.
 constexpr int kBigLog = 15;
 constexpr int kBigN = 1 << kBigLog;
+#ifndef DDX_ROWS_WIDE
+#define DDX_ROWS_WIDE 0
+#endif
+using RowPlan = typename std::conditional<DDX_ROWS_WIDE != 0, Plan15Wide, Plan<kBigLog>>::type;
 
 // exp(S 2 pi i num / 2^(15 + logr)) for 0 <= num < 2^(15 + logr), reduced exactly
 template <int S>
@@ -313,13 +360,13 @@ __global__ __launch_bounds__(256) void k_forward_big_pre(FwdArgs a, float2* __re
 
 // Forward 2^15-point FFT of n_rows consecutive rows: dst[r 2^15 + k] from src[r 2^15 + n].
 // grid: n_rows workgroups.
-__global__ __launch_bounds__(Geo<kBigLog>::T) void k_fft_rows(const float2* __restrict__ src, float2* __restrict__ dst) {
-  using G = Geo<kBigLog>;
+__global__ __launch_bounds__(Geo<RowPlan>::T) void k_fft_rows(const float2* __restrict__ src, float2* __restrict__ dst) {
+  using G = Geo<RowPlan>;
   extern __shared__ float lds[];
   const int t = threadIdx.x;
   const float2* x = src + (size_t)blockIdx.x * kBigN;
   float2 v[G::P];
-  fft_workgroup<kBigLog, -1>(v, lds, t, [&](int i) { return at_byte(x, 8u * (unsigned)i); });
+  fft_workgroup<RowPlan, -1>(v, lds, t, [&](int i) { return at_byte(x, 8u * (unsigned)i); });
   float2* out = dst + (size_t)blockIdx.x * kBigN + opaque_zero(v[0].x);
 #pragma unroll
   for (int u = 0; u < G::P / G::RL; ++u)
@@ -330,8 +377,8 @@ __global__ __launch_bounds__(Geo<kBigLog>::T) void k_fft_rows(const float2* __re
 // Inverse pass A over a wave of units of one length N = 2^(15 + logr): row (p, k1)
 // of unit u times the chirp's row k1, inverse 2^15-point FFT, times w_N^{k1 n2}.
 // grid: order_units(n_units, tile) x M R workgroups (see unit_row, rows p R + k1).
-__global__ __launch_bounds__(Geo<kBigLog>::T) void k_dedisperse_big_a(DedispArgs a) {
-  using G = Geo<kBigLog>;
+__global__ __launch_bounds__(Geo<Plan<kBigLog>>::T) void k_dedisperse_big_a(DedispArgs a) {
+  using G = Geo<Plan<kBigLog>>;
   extern __shared__ float lds[];
   const int t = threadIdx.x;
   int row, ui;  // row = p R + k1
@@ -341,7 +388,7 @@ __global__ __launch_bounds__(Geo<kBigLog>::T) void k_dedisperse_big_a(DedispArgs
   const float2* x = a.spec + w.spec + (size_t)row * kBigN;
   const float2* h = a.chirp + w.chirp + (size_t)k1 * kBigN;
   float2 v[G::P];
-  fft_workgroup<kBigLog, +1>(v, lds, t,
+  fft_workgroup<Plan<kBigLog>, +1>(v, lds, t,
                              [&](int i) { return cmul(at_byte(x, 8u * (unsigned)i), at_byte(h, 8u * (unsigned)i)); });
   float2* out = a.tb + w.tb + (size_t)row * kBigN + opaque_zero(v[0].x);
 #pragma unroll
