@@ -335,11 +335,15 @@ hipError_t launch_corr_nt(int corr_dtype, const ddx::CorrArgs& a, int n_units, h
 }
 
 hipError_t launch_corr_blocks(int corr_dtype, const ddx::CorrArgs& a, int n_units, hipStream_t s) {
-  const int nb = (a.n_ant + ddx::kBlkAnt - 1) / ddx::kBlkAnt;
-  const dim3 g(n_units * a.max_dumps * (nb * (nb + 1) / 2)), b(256);
-  if (corr_dtype == DDX_CORR_F32) hipLaunchKernelGGL((ddx::k_correlate_blocks<0>), g, b, 0, s, a);
-  else if (corr_dtype == DDX_CORR_F16) hipLaunchKernelGGL((ddx::k_correlate_blocks<1>), g, b, 0, s, a);
-  else hipLaunchKernelGGL((ddx::k_correlate_blocks<2>), g, b, 0, s, a);
+  constexpr int BA = ddx::kBlkAnt;
+  const int nb = (a.n_ant + BA - 1) / BA;
+  const dim3 g(n_units * a.max_dumps * (nb * (nb + 1) / 2)), b(ddx::corr_block_threads(BA));
+  if (corr_dtype == DDX_CORR_F32)
+    hipLaunchKernelGGL((ddx::k_correlate_blocks<0, BA>), g, b, ddx::corr_block_lds<0>(BA), s, a);
+  else if (corr_dtype == DDX_CORR_F16)
+    hipLaunchKernelGGL((ddx::k_correlate_blocks<1, BA>), g, b, ddx::corr_block_lds<1>(BA), s, a);
+  else
+    hipLaunchKernelGGL((ddx::k_correlate_blocks<2, BA>), g, b, ddx::corr_block_lds<2>(BA), s, a);
   return hipGetLastError();
 }
 
@@ -494,7 +498,8 @@ int setup_device(ddx_plan* p) {
     p->wave_units = (int)std::max<size_t>(1, std::min<size_t>(1024, kAutoYBytes / std::max<size_t>(per_unit, 1)));
   }
   p->wave_units = (int)std::min<int64_t>(p->wave_units, std::max<int64_t>(max_units, 1));
-  if ((rc = dev_alloc(p, &p->ybuf, per_unit * p->wave_units))) return rc;
+  // + 256 bytes: the correlator's pair loads may read one sample past a unit's rows
+  if ((rc = dev_alloc(p, &p->ybuf, per_unit * p->wave_units + 256))) return rc;
 
   if ((rc = dev_alloc(p, (void**)&p->chirp, (size_t)p->wave_units * maxn * sizeof(float2)))) return rc;
   // two-pass transforms: intermediate rows of one wave (dedispersion); the forward

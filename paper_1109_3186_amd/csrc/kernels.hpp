@@ -503,9 +503,10 @@ struct CorrArgs {
 
 // The (unit, dump) of workgroup `item`; false when the unit has fewer dumps.
 struct CorrJob {
-  int64_t yoff;   // element offset in y of the dump's first sample, antenna 0
-  float2* out;    // the (channel, DM) slot of the dump's record
+  int64_t yoff;      // element offset in y of the dump's first sample, antenna 0
+  float2* out;       // the (channel, DM) slot of the dump's record
   int32_t chan;
+  int32_t dump_off;  // samples from the unit's row start to the dump's first sample
 };
 __device__ __forceinline__ bool corr_job(const CorrArgs& a, int item, CorrJob& j) {
   const UnitItem w = a.units[item / a.max_dumps];
@@ -514,7 +515,35 @@ __device__ __forceinline__ bool corr_job(const CorrArgs& a, int item, CorrJob& j
   j.yoff = w.y + (int64_t)m * a.dump_len;
   j.out = a.ring + ((w.dump0 + m) % a.ring_dumps) * a.rec_elems + w.rec;
   j.chan = w.chan;
+  j.dump_off = m * a.dump_len;
   return true;
+}
+
+// Byte offset that lies past every correlator load resource (ranges are at most
+// 2^31 + 8 bytes) without wrapping when the access size is added.
+constexpr unsigned kCorrSkip = 0xC0000000u;
+
+// Samples (k, k + 1) of one antenna row (k even) as one load through a buffer
+// resource: the caller passes an offset past the resource's range for a row past M
+// or k past the dump, which the hardware's range check turns into zeros, and
+// `second` false when k + 1 is past the dump, which zeroes the second sample.
+template <int T>
+__device__ __forceinline__ typename CorrIn<T>::Pair load_pair(__amdgpu_buffer_rsrc_t r, unsigned off, bool second) {
+  typename CorrIn<T>::Pair v;
+  if constexpr (T == 0) {
+    typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+    const u4v u = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    v = make_float4(__uint_as_float(u.x), __uint_as_float(u.y), second ? __uint_as_float(u.z) : 0.f,
+                    second ? __uint_as_float(u.w) : 0.f);
+  } else if constexpr (T == 1) {
+    typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+    const u2v u = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    v = make_uint2(u.x, second ? u.y : 0u);
+  } else {
+    const unsigned u = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+    v = second ? u : (u & 0xffffu);
+  }
+  return v;
 }
 
 // binary16 hi = rn(x) and lo = rn(x - hi); x - hi is exact in FP32
@@ -587,27 +616,19 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
     if constexpr (T == 0) at[Ld::PLANE + Ld::at(r, k)] = (E)0;
   }
   const float s_in = a.scale[w.chan];
-  const typename In::Y* y = reinterpret_cast<const typename In::Y*>(a.y) + w.yoff;
-  // pairs that are 2-sample aligned and inside the dump are loaded as one vector, others singly
+  typedef typename In::Y Y;
+  const Y* y = reinterpret_cast<const Y*>(a.y) + w.yoff;
+  // one pair load per (antenna, sample pair) through a resource over the unit's rows
+  // from the chunk's first sample on (see load_pair; the range is at most 2^31 + 8 bytes)
   auto load = [&](int k0, Pair* buf) {
+    const unsigned span = ((unsigned)M * (unsigned)a.y_stride - (unsigned)(w.dump_off + k0) + 1u) * (unsigned)sizeof(Y);
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(const_cast<Y*>(y + k0), (short)0, (int)span, 0x00020000);
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
       const int e = tid + 256 * i;
-      Pair v{};
-      if (e < pairs) {
-        const int p = e / (kCorrKC / 2), k = k0 + 2 * (e % (kCorrKC / 2));
-        const typename In::Y* row = y + (size_t)p * a.y_stride + k;
-        if (k + 1 < L && ((((size_t)w.yoff + (size_t)p * a.y_stride + k) & 1) == 0)) {
-          v = *reinterpret_cast<const Pair*>(row);
-        } else {
-          typename In::Y s0{}, s1{};
-          if (k < L) s0 = row[0];
-          if (k + 1 < L) s1 = row[1];
-          typename In::Y tmp[2] = {s0, s1};
-          v = *reinterpret_cast<const Pair*>(tmp);
-        }
-      }
-      buf[i] = v;
+      const int p = e / (kCorrKC / 2), kl = 2 * (e % (kCorrKC / 2)), k = k0 + kl;
+      const unsigned off = (e < pairs && k < L) ? ((unsigned)p * (unsigned)a.y_stride + (unsigned)kl) * (unsigned)sizeof(Y) : kCorrSkip;
+      buf[i] = load_pair<T>(r, off, k + 1 < L);
     }
   };
   auto stage = [&](const Pair* buf) {
@@ -697,16 +718,31 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
   }
 }
 
-// Correlator for large arrays: the antennas are cut into blocks of 64; one
-// workgroup computes, for one (DM, dump), the 64 x 64 antenna block pair (I, J),
-// I <= J, as 4 x 4 complex 16 x 16 tiles, each from four real products on MFMA:
+// Correlator for large arrays: the antennas are cut into blocks of BA (64 or 128);
+// one workgroup computes, for one (DM, dump), the BA x BA antenna block pair
+// (I, J), I <= J, as complex 16 x 16 tiles, each from four real products on MFMA:
 //   Re V = Yr_I Yr_J^T + Yi_I Yi_J^T,   Im V = Yi_I Yr_J^T - Yr_I Yi_J^T
-// (FP32 form: every product as hi*hi + hi*lo + lo*hi of binary16 halves).  Wave w
-// owns row tile w of block I against the four column tiles of block J, so its
-// block-I fragments are read once per k-step.  Writes V_ij for i <= j < M only.
-// grid: n_units * max_dumps * NB (NB + 1) / 2 workgroups (NB = ceil(M / 64)),
-// 256 threads, block pair fastest.
-constexpr int kBlkAnt = 64;
+// (FP32 form: every product as hi*hi + hi*lo + lo*hi of binary16 halves).  Each
+// wave owns RT row tiles of block I against four column tiles of block J (BA = 64:
+// 4 waves, RT = 1; BA = 128: 8 waves, RT = 2), so its block-I fragments are read
+// once per k-step; in a diagonal pair (I = J) tiles wholly below the diagonal are
+// skipped.  Chunks of kCorrKC samples of both blocks are staged through LDS, the
+// next chunk's loads in flight during the current chunk's MFMAs.  Writes V_ij for
+// i <= j < M only.
+// grid: n_units * max_dumps * NB (NB + 1) / 2 workgroups (NB = ceil(M / BA)),
+// corr_block_threads(BA) threads, corr_block_lds<T>(BA) bytes of dynamic LDS,
+// block pair fastest.
+#ifndef DDX_BLK_ANT
+#define DDX_BLK_ANT 128
+#endif
+constexpr int kBlkAnt = DDX_BLK_ANT;
+
+__host__ __device__ constexpr int corr_block_threads(int ba) { return ba == 128 ? 512 : 256; }
+template <int T>
+__host__ __device__ constexpr int corr_block_lds(int ba) {
+  // rows Re I, Im I, Re J, Im J; k pitch padded by 16 bytes; FP32 keeps a lo plane
+  return (T == 0 ? 2 : 1) * 4 * ba * (kCorrKC + 16 / (T == 2 ? 1 : 2)) * (T == 2 ? 1 : 2);
+}
 
 template <int T> struct NegFrag;
 template <> struct NegFrag<0> {
@@ -719,20 +755,27 @@ template <> struct NegFrag<2> {
   __device__ static long neg(long v) { return v ^ (long)0x8080808080808080LL; }  // flip the 8 sign bits
 };
 
-template <int T>
-__global__ __launch_bounds__(256) void k_correlate_blocks(CorrArgs a) {
+template <int T, int BA>
+__global__ __launch_bounds__(corr_block_threads(BA)) void k_correlate_blocks(CorrArgs a) {
   using In = CorrIn<T>;
   typedef typename In::E E;
   typedef typename In::Pair Pair;
   typedef typename std::conditional<T == 2, long, half8>::type Frag;
-  constexpr int ROWS = 4 * kBlkAnt;  // Re I, Im I, Re J, Im J
+  constexpr int NTH = corr_block_threads(BA), NW = NTH / 64;
+  constexpr int TS = BA / 16;          // tiles per block side
+  constexpr int CG = TS / 4;           // column groups of 4 tiles
+  constexpr int RT = TS / (NW / CG);   // row tiles per wave
+  constexpr int ROWS = 4 * BA;         // Re I, Im I, Re J, Im J
   constexpr int KP = kCorrKC + 16 / (int)sizeof(E);
   constexpr int PLANE = ROWS * KP;
-  constexpr int PPT = (2 * kBlkAnt * (kCorrKC / 2)) / 256;  // sample pairs per thread per chunk
-  __shared__ E at[(T == 0 ? 2 : 1) * PLANE];
+  constexpr int PPT = (2 * BA * (kCorrKC / 2)) / NTH;  // sample pairs per thread per chunk
+  static_assert(corr_block_lds<T>(BA) == (T == 0 ? 2 : 1) * PLANE * (int)sizeof(E), "LDS size");
+  extern __shared__ __align__(16) char smem_blk[];
+  E* at = reinterpret_cast<E*>(smem_blk);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int cg = wave % CG, rg = wave / CG;
   const int M = a.n_ant, L = a.dump_len;
-  const int nb = (M + kBlkAnt - 1) / kBlkAnt, npair = nb * (nb + 1) / 2;
+  const int nb = (M + BA - 1) / BA, npair = nb * (nb + 1) / 2;
   int pr = blockIdx.x % npair;
   CorrJob w;
   if (!corr_job(a, blockIdx.x / npair, w)) return;
@@ -741,48 +784,48 @@ __global__ __launch_bounds__(256) void k_correlate_blocks(CorrArgs a) {
   const int J = I + pr;
   const float s_in = a.scale[w.chan];
 
-  floatx4 are[4], aim[4];
+  floatx4 are[RT][4], aim[RT][4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) are[q] = aim[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int x = 0; x < RT; ++x)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) are[x][q] = aim[x][q] = floatx4{0.f, 0.f, 0.f, 0.f};
 
   const typename In::Y* y = reinterpret_cast<const typename In::Y*>(a.y) + w.yoff;
-  // thread e -> (local antenna la in [0, 128): 0..63 block I, 64..127 block J; sample pair)
-  auto ant_of = [&](int la) { return la < kBlkAnt ? I * kBlkAnt + la : J * kBlkAnt + (la - kBlkAnt); };
+  // thread e -> (local antenna la in [0, 2 BA): block I then block J; sample pair)
+  auto ant_of = [&](int la) { return la < BA ? I * BA + la : J * BA + (la - BA); };
+  // resource over the unit's rows from the chunk's first sample to the end of the
+  // unit (plus the one-sample overhang of an odd dump's last pair, which is zeroed;
+  // the buffer is padded for it).  M y_stride <= 2^28 samples, so the range is at
+  // most 2^31 + 8 bytes and the skip offset kCorrSkip lies past it.
+  typedef typename In::Y Y;
   auto load = [&](int k0, Pair* buf) {
+    const unsigned span = ((unsigned)M * (unsigned)a.y_stride - (unsigned)(w.dump_off + k0) + 1u) * (unsigned)sizeof(Y);
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(const_cast<Y*>(y + k0), (short)0, (int)span, 0x00020000);
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-      const int e = tid + 256 * i;
-      const int la = e / (kCorrKC / 2), k = k0 + 2 * (e % (kCorrKC / 2));
+      const int e = tid + NTH * i;
+      const int la = e / (kCorrKC / 2), kl = 2 * (e % (kCorrKC / 2)), k = k0 + kl;
       const int p = ant_of(la);
-      Pair v{};
-      if (p < M) {
-        const typename In::Y* row = y + (size_t)p * a.y_stride + k;
-        if (k + 1 < L && ((((size_t)w.yoff + (size_t)p * a.y_stride + k) & 1) == 0)) {
-          v = *reinterpret_cast<const Pair*>(row);
-        } else {
-          typename In::Y s0{}, s1{};
-          if (k < L) s0 = row[0];
-          if (k + 1 < L) s1 = row[1];
-          typename In::Y tmp[2] = {s0, s1};
-          v = *reinterpret_cast<const Pair*>(tmp);
-        }
-      }
-      buf[i] = v;
+      const unsigned off = (p < M && k < L) ? ((unsigned)p * (unsigned)a.y_stride + (unsigned)kl) * (unsigned)sizeof(Y) : kCorrSkip;
+      buf[i] = load_pair<T>(r, off, k + 1 < L);
     }
   };
-  auto row_re = [](int la) { return la < kBlkAnt ? la : 2 * kBlkAnt + (la - kBlkAnt); };
+  auto row_re = [](int la) { return la < BA ? la : 2 * BA + (la - BA); };
   auto stage = [&](const Pair* buf) {
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + NTH * i;
       const int la = e / (kCorrKC / 2), k = 2 * (e % (kCorrKC / 2));
-      const int rr = row_re(la), ri = rr + kBlkAnt;
+      const int rr = row_re(la), ri = rr + BA;
       store_pair<T, PLANE>(at, rr * KP + k, ri * KP + k, buf[i]);
     }
   };
   auto frag = [&](int plane, int row, int kr) -> Frag {
     return *reinterpret_cast<const Frag*>(&at[plane * PLANE + row * KP + kr]);
   };
+  // tile (row tile rt, column tile ct) is needed unless the pair is diagonal and the
+  // tile lies wholly below the diagonal (wave-uniform)
+  auto needed = [&](int rt, int ct) { return I != J || ct >= rt; };
   Pair buf[PPT];
   load(0, buf);
   for (int k0 = 0; k0 < L; k0 += kCorrKC) {
@@ -793,46 +836,75 @@ __global__ __launch_bounds__(256) void k_correlate_blocks(CorrArgs a) {
 #pragma unroll
     for (int kk = 0; kk < kCorrKC; kk += In::KSTEP) {
       const int kr = kk + 8 * (lane >> 4);
-      const int ra = wave * 16 + (lane & 15);  // row tile `wave` of block I
       if constexpr (T == 0) {
-        const Frag rh = frag(0, ra, kr), rl = frag(1, ra, kr);
-        const Frag ih = frag(0, kBlkAnt + ra, kr), il = frag(1, kBlkAnt + ra, kr);
-        const Frag nrh = NegFrag<T>::neg(rh), nrl = NegFrag<T>::neg(rl);
+        Frag rh[RT], rl[RT], ih[RT], il[RT];
+#pragma unroll
+        for (int x = 0; x < RT; ++x) {
+          const int ra = (rg * RT + x) * 16 + (lane & 15);
+          rh[x] = frag(0, ra, kr);
+          rl[x] = frag(1, ra, kr);
+          ih[x] = frag(0, BA + ra, kr);
+          il[x] = frag(1, BA + ra, kr);
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int rb = 2 * kBlkAnt + q * 16 + (lane & 15);
+          const int ct = cg * 4 + q;
+          const int rb = 2 * BA + ct * 16 + (lane & 15);
           const Frag jrh = frag(0, rb, kr), jrl = frag(1, rb, kr);
-          const Frag jih = frag(0, kBlkAnt + rb, kr), jil = frag(1, kBlkAnt + rb, kr);
-          are[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(rh, jrh, are[q], 0, 0, 0);
-          are[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(rh, jrl, are[q], 0, 0, 0);
-          are[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(rl, jrh, are[q], 0, 0, 0);
-          are[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ih, jih, are[q], 0, 0, 0);
-          are[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ih, jil, are[q], 0, 0, 0);
-          are[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(il, jih, are[q], 0, 0, 0);
-          aim[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ih, jrh, aim[q], 0, 0, 0);
-          aim[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ih, jrl, aim[q], 0, 0, 0);
-          aim[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(il, jrh, aim[q], 0, 0, 0);
-          aim[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(nrh, jih, aim[q], 0, 0, 0);
-          aim[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(nrh, jil, aim[q], 0, 0, 0);
-          aim[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(nrl, jih, aim[q], 0, 0, 0);
+          const Frag jih = frag(0, BA + rb, kr), jil = frag(1, BA + rb, kr);
+          // Im V takes -Yr_I Yi_J^T: the column fragment is negated (once per tile column)
+          const Frag njih = NegFrag<T>::neg(jih), njil = NegFrag<T>::neg(jil);
+#pragma unroll
+          for (int x = 0; x < RT; ++x) {
+            if (!needed(rg * RT + x, ct)) continue;
+            floatx4 r = are[x][q], m = aim[x][q];
+            r = __builtin_amdgcn_mfma_f32_16x16x32_f16(rh[x], jrh, r, 0, 0, 0);
+            r = __builtin_amdgcn_mfma_f32_16x16x32_f16(rh[x], jrl, r, 0, 0, 0);
+            r = __builtin_amdgcn_mfma_f32_16x16x32_f16(rl[x], jrh, r, 0, 0, 0);
+            r = __builtin_amdgcn_mfma_f32_16x16x32_f16(ih[x], jih, r, 0, 0, 0);
+            r = __builtin_amdgcn_mfma_f32_16x16x32_f16(ih[x], jil, r, 0, 0, 0);
+            r = __builtin_amdgcn_mfma_f32_16x16x32_f16(il[x], jih, r, 0, 0, 0);
+            m = __builtin_amdgcn_mfma_f32_16x16x32_f16(ih[x], jrh, m, 0, 0, 0);
+            m = __builtin_amdgcn_mfma_f32_16x16x32_f16(ih[x], jrl, m, 0, 0, 0);
+            m = __builtin_amdgcn_mfma_f32_16x16x32_f16(il[x], jrh, m, 0, 0, 0);
+            m = __builtin_amdgcn_mfma_f32_16x16x32_f16(rh[x], njih, m, 0, 0, 0);
+            m = __builtin_amdgcn_mfma_f32_16x16x32_f16(rh[x], njil, m, 0, 0, 0);
+            m = __builtin_amdgcn_mfma_f32_16x16x32_f16(rl[x], njih, m, 0, 0, 0);
+            are[x][q] = r;
+            aim[x][q] = m;
+          }
         }
       } else {
-        const Frag rr = frag(0, ra, kr), ii = frag(0, kBlkAnt + ra, kr);
-        const Frag nr = NegFrag<T>::neg(rr);
+        Frag rr[RT], ii[RT];
+#pragma unroll
+        for (int x = 0; x < RT; ++x) {
+          const int ra = (rg * RT + x) * 16 + (lane & 15);
+          rr[x] = frag(0, ra, kr);
+          ii[x] = frag(0, BA + ra, kr);
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int rb = 2 * kBlkAnt + q * 16 + (lane & 15);
-          const Frag jr = frag(0, rb, kr), ji = frag(0, kBlkAnt + rb, kr);
-          if constexpr (T == 1) {
-            are[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(rr, jr, are[q], 0, 0, 0);
-            are[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ii, ji, are[q], 0, 0, 0);
-            aim[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ii, jr, aim[q], 0, 0, 0);
-            aim[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(nr, ji, aim[q], 0, 0, 0);
-          } else {
-            are[q] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(rr, jr, are[q], 0, 0, 0);
-            are[q] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ii, ji, are[q], 0, 0, 0);
-            aim[q] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ii, jr, aim[q], 0, 0, 0);
-            aim[q] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(nr, ji, aim[q], 0, 0, 0);
+          const int ct = cg * 4 + q;
+          const int rb = 2 * BA + ct * 16 + (lane & 15);
+          const Frag jr = frag(0, rb, kr), ji = frag(0, BA + rb, kr);
+          const Frag nji = NegFrag<T>::neg(ji);
+#pragma unroll
+          for (int x = 0; x < RT; ++x) {
+            if (!needed(rg * RT + x, ct)) continue;
+            floatx4 r = are[x][q], m = aim[x][q];
+            if constexpr (T == 1) {
+              r = __builtin_amdgcn_mfma_f32_16x16x32_f16(rr[x], jr, r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_16x16x32_f16(ii[x], ji, r, 0, 0, 0);
+              m = __builtin_amdgcn_mfma_f32_16x16x32_f16(ii[x], jr, m, 0, 0, 0);
+              m = __builtin_amdgcn_mfma_f32_16x16x32_f16(rr[x], nji, m, 0, 0, 0);
+            } else {
+              r = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(rr[x], jr, r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ii[x], ji, r, 0, 0, 0);
+              m = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ii[x], jr, m, 0, 0, 0);
+              m = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(rr[x], nji, m, 0, 0, 0);
+            }
+            are[x][q] = r;
+            aim[x][q] = m;
           }
         }
       }
@@ -841,21 +913,23 @@ __global__ __launch_bounds__(256) void k_correlate_blocks(CorrArgs a) {
   const float inv = 1.f / (s_in * s_in);
   float2* out = w.out;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int x = 0; x < RT; ++x)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = I * kBlkAnt + wave * 16 + 4 * (lane >> 4) + r;
-      const int j = J * kBlkAnt + q * 16 + (lane & 15);
-      if (i >= M || j >= M || j < i) continue;
-      const float re = are[q][r] * inv, im = (i == j) ? 0.f : aim[q][r] * inv;  // autos are real
-      if (a.out_mode == 0) {
-        out[(int64_t)i * M - (int64_t)i * (i - 1) / 2 + (j - i)] = make_float2(re, im);
-      } else {
-        out[(int64_t)i * M + j] = make_float2(re, im);
-        if (i != j) out[(int64_t)j * M + i] = make_float2(re, -im);
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = I * BA + (rg * RT + x) * 16 + 4 * (lane >> 4) + r;
+        const int j = J * BA + (cg * 4 + q) * 16 + (lane & 15);
+        if (i >= M || j >= M || j < i) continue;
+        const float re = are[x][q][r] * inv, im = (i == j) ? 0.f : aim[x][q][r] * inv;  // autos are real
+        if (a.out_mode == 0) {
+          out[(int64_t)i * M - (int64_t)i * (i - 1) / 2 + (j - i)] = make_float2(re, im);
+        } else {
+          out[(int64_t)i * M + j] = make_float2(re, im);
+          if (i != j) out[(int64_t)j * M + i] = make_float2(re, -im);
+        }
       }
     }
-  }
 }
 
 // Correlator-input scale of a channel from its first block window:
