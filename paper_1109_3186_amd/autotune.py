@@ -31,7 +31,7 @@ from .binding import DdxError, Plan
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 MAX_LEN = 1 << 18
-TUNE_VERSION = 2
+TUNE_VERSION = 3
 
 
 def workload_key(n_ant, chan_freqs, samp_rate, dump_len, dm_lists, corr_dtype, in_dtype, max_block):
