@@ -264,6 +264,8 @@ struct DedispArgs {
   const UnitItem* units;
   int64_t y_stride;
   int32_t n_ant, n_units, logr, tile;
+  int32_t ant0;         // two-pass transforms: first antenna of the launch's group (n_ant antennas)
+  int32_t pad;
 };
 
 template <int LOGN, int OUT>
@@ -374,9 +376,11 @@ __global__ __launch_bounds__(Geo<RowPlan>::T) void k_fft_rows(const float2* __re
     for (int q = 0; q < G::RL; ++q) out[t + u * G::T + q * (G::N / G::RL)] = v[u * G::RL + out_reg<G::RL>(q)];
 }
 
-// Inverse pass A over a wave of units of one length N = 2^(15 + logr): row (p, k1)
-// of unit u times the chirp's row k1, inverse 2^15-point FFT, times w_N^{k1 n2}.
-// grid: order_units(n_units, tile) x M R workgroups (see unit_row, rows p R + k1).
+// Inverse pass A over a wave of units of one length N = 2^(15 + logr), for the
+// antennas ant0 .. ant0 + n_ant - 1: row (p, k1) of unit u times the chirp's row k1,
+// inverse 2^15-point FFT, times w_N^{k1 n2}.  The intermediate rows are indexed by
+// the antenna within the group, so a group's rows reuse the same tb region.
+// grid: order_units(n_units, tile) x n_ant R workgroups (see unit_row, rows p R + k1).
 __global__ __launch_bounds__(Geo<Plan<kBigLog>>::T) void k_dedisperse_big_a(DedispArgs a) {
   using G = Geo<Plan<kBigLog>>;
   extern __shared__ float lds[];
@@ -385,7 +389,7 @@ __global__ __launch_bounds__(Geo<Plan<kBigLog>>::T) void k_dedisperse_big_a(Dedi
   if (!unit_row(xcd_remap(blockIdx.x, gridDim.x), a.n_units, a.n_ant << a.logr, a.tile, row, ui)) return;
   const UnitItem w = a.units[ui];
   const int k1 = row & ((1 << a.logr) - 1);
-  const float2* x = a.spec + w.spec + (size_t)row * kBigN;
+  const float2* x = a.spec + w.spec + ((size_t)row + ((size_t)a.ant0 << a.logr)) * kBigN;
   const float2* h = a.chirp + w.chirp + (size_t)k1 * kBigN;
   float2 v[G::P];
   fft_workgroup<Plan<kBigLog>, +1>(v, lds, t,
@@ -415,7 +419,7 @@ __device__ __forceinline__ void dedisperse_big_b(const float2* t0, int n2, int l
 }
 
 // Inverse pass B: R-point DFT over k1, overlap-save discard, output conversion.
-// grid: (2^15 / 256, n_units * M), blockIdx.y = p * n_units + u.
+// grid: (2^15 / 256, n_units * n_ant), blockIdx.y = p * n_units + u, antenna ant0 + p.
 template <int OUT>
 __global__ __launch_bounds__(256) void k_dedisperse_big_b(DedispArgs a) {
   const int n2 = blockIdx.x * 256 + threadIdx.x;
@@ -423,7 +427,7 @@ __global__ __launch_bounds__(256) void k_dedisperse_big_b(DedispArgs a) {
   const UnitItem w = a.units[blockIdx.y % a.n_units];
   const float2* t0 = a.tb + w.tb + ((size_t)p << (kBigLog + a.logr));
   typedef typename YType<OUT>::T YT;
-  YT* y = reinterpret_cast<YT*>(a.y) + w.y + (size_t)p * a.y_stride;
+  YT* y = reinterpret_cast<YT*>(a.y) + w.y + (size_t)(a.ant0 + p) * a.y_stride;
   if (a.logr == 1) dedisperse_big_b<2, OUT>(t0, n2, w.lead, w.valid, y);
   else if (a.logr == 2) dedisperse_big_b<4, OUT>(t0, n2, w.lead, w.valid, y);
   else dedisperse_big_b<8, OUT>(t0, n2, w.lead, w.valid, y);

@@ -1,5 +1,5 @@
 """Edge cases of the HIP path: lower sideband, one antenna, the largest array,
-one-sample dumps, empty calls, NaN input, and the error statuses that need a
+odd dump lengths in the stacked correlator, one-sample dumps, empty calls, NaN input, and the error statuses that need a
 device (ring full, fetch buffer too small, device-memory cap).  Parity bar as in
 test_gpu_parity: 1e-5 normalised against the FP64 oracle."""
 import ctypes as ct
@@ -43,6 +43,20 @@ def test_largest_array(gpu):
     assert vis.shape == (3, 2 * 1024 * 1025 // 2)
     err = compare_with_oracle(cfg, vis, lay)
     say("1024 antennas: max normalised error %.3e" % err)
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("m_ant,dump_len", [(33, 75), (64, 101)])
+def test_stacked_correlator_odd_dumps(gpu, m_ant, dump_len):
+    """The stacked-row correlator at a padded tile count (33 antennas: 66 of 80
+    rows) and at its largest array (64), with odd dump lengths: every dump's last
+    sample pair straddles the dump's end and its second sample must be read as 0."""
+    cfg = synth.make_small(seed=87 + m_ant, m_ant=m_ant, n_chan=2, s=6007, f_lo=1.3e9, f_s=1e6, n_dm=3,
+                           dm_max=150.0, dump_len=dump_len, ci8=True, n_pulses=1)
+    vis, lay = run_gpu(cfg, in_dtype="ci8")
+    assert vis.shape[0] == 6007 // dump_len
+    err = compare_with_oracle(cfg, vis, lay)
+    say("stacked correlator, M %d, L %d: max normalised error %.3e" % (m_ant, dump_len, err))
     assert err <= TOL
 
 

@@ -1,9 +1,11 @@
 """GPU parity of the antenna-block correlator, used above 64 antennas.
 
-Antennas are cut into blocks of 64 and every block pair (I <= J) is one
-workgroup of complex 16 x 16 MFMA tiles.  Cases: a lone antenna in the last
-block (65), a half-filled last block (80, 130), odd and even dump lengths, both
-output layouts, and the reduced-precision inputs.  Tolerances as for the
+Antennas are cut into blocks of 128 and every block pair (I <= J) is one
+workgroup of complex 16 x 16 MFMA tiles.  Cases: one partly filled block (65,
+80), a second block with two antennas (130), two blocks with an off-diagonal
+pair (200, and 256 = two full blocks), odd and even dump lengths (an odd one
+makes a dump's last sample pair straddle its end), both output layouts, and the
+reduced-precision inputs.  Tolerances as for the
 stacked-row correlator: 1e-5 normalised for FP32, and for binary16 / E4M3 the
 bounds of the precision tests.
 """
@@ -23,7 +25,7 @@ def _cfg(seed, m_ant, s, dump_len, n_chan=2, n_dm=3, ci8=True):
                             dm_max=150.0, dump_len=dump_len, ci8=ci8, n_pulses=1)
 
 
-@pytest.mark.parametrize("m_ant,dump_len", [(65, 99), (80, 100), (130, 64)])
+@pytest.mark.parametrize("m_ant,dump_len", [(65, 99), (80, 100), (130, 64), (200, 99), (256, 77)])
 def test_block_correlator_fp32(gpu, m_ant, dump_len):
     cfg = _cfg(40 + m_ant, m_ant, 7001, dump_len)
     say("block correlator: %d antennas, L %d, ci8, 2 ch, 3 DMs" % (m_ant, dump_len))
