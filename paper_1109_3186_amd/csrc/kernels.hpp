@@ -529,23 +529,35 @@ constexpr unsigned kCorrSkip = 0xC0000000u;
 
 // Samples (k, k + 1) of one antenna row (k even) as one load through a buffer
 // resource: the caller passes an offset past the resource's range for a row past M
-// or k past the dump, which the hardware's range check turns into zeros, and
-// `second` false when k + 1 is past the dump, which zeroes the second sample.
+// or k past the dump, which the hardware's range check turns into zeros.  The
+// value is used only when it is staged (a chunk later), so nothing waits for it here.
 template <int T>
-__device__ __forceinline__ typename CorrIn<T>::Pair load_pair(__amdgpu_buffer_rsrc_t r, unsigned off, bool second) {
+__device__ __forceinline__ typename CorrIn<T>::Pair load_pair(__amdgpu_buffer_rsrc_t r, unsigned off) {
   typename CorrIn<T>::Pair v;
   if constexpr (T == 0) {
     typedef unsigned int u4v __attribute__((ext_vector_type(4)));
     const u4v u = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
-    v = make_float4(__uint_as_float(u.x), __uint_as_float(u.y), second ? __uint_as_float(u.z) : 0.f,
-                    second ? __uint_as_float(u.w) : 0.f);
+    v = make_float4(__uint_as_float(u.x), __uint_as_float(u.y), __uint_as_float(u.z), __uint_as_float(u.w));
   } else if constexpr (T == 1) {
     typedef unsigned int u2v __attribute__((ext_vector_type(2)));
     const u2v u = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
-    v = make_uint2(u.x, second ? u.y : 0u);
+    v = make_uint2(u.x, u.y);
   } else {
-    const unsigned u = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
-    v = second ? u : (u & 0xffffu);
+    v = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+  }
+  return v;
+}
+
+// The pair with its second sample zeroed when `second` is false (k + 1 past the
+// dump: the load read one sample beyond it).
+template <int T>
+__device__ __forceinline__ typename CorrIn<T>::Pair clip_pair(typename CorrIn<T>::Pair v, bool second) {
+  if constexpr (T == 0) {
+    if (!second) v.z = v.w = 0.f;
+  } else if constexpr (T == 1) {
+    if (!second) v.y = 0u;
+  } else {
+    if (!second) v &= 0xffffu;
   }
   return v;
 }
@@ -624,25 +636,24 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
   const Y* y = reinterpret_cast<const Y*>(a.y) + w.yoff;
   // one pair load per (antenna, sample pair) through a resource over the unit's rows
   // from the chunk's first sample on (see load_pair; the range is at most 2^31 + 8 bytes)
-  auto load = [&](int k0, Pair* buf) {
+  auto rsrc_at = [&](int k0) {
     const unsigned span = ((unsigned)M * (unsigned)a.y_stride - (unsigned)(w.dump_off + k0) + 1u) * (unsigned)sizeof(Y);
-    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(const_cast<Y*>(y + k0), (short)0, (int)span, 0x00020000);
-#pragma unroll
-    for (int i = 0; i < PPT; ++i) {
-      const int e = tid + 256 * i;
-      const int p = e / (kCorrKC / 2), kl = 2 * (e % (kCorrKC / 2)), k = k0 + kl;
-      const unsigned off = (e < pairs && k < L) ? ((unsigned)p * (unsigned)a.y_stride + (unsigned)kl) * (unsigned)sizeof(Y) : kCorrSkip;
-      buf[i] = load_pair<T>(r, off, k + 1 < L);
-    }
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<Y*>(y + k0), (short)0, (int)span, 0x00020000);
   };
-  auto stage = [&](const Pair* buf) {
-#pragma unroll
-    for (int i = 0; i < PPT; ++i) {
-      const int e = tid + 256 * i;
-      if (e < pairs) {
-        const int p = e / (kCorrKC / 2), k = 2 * (e % (kCorrKC / 2));
-        store_pair<T, Ld::PLANE>(at, Ld::at(p, k), Ld::at(M + p, k), buf[i]);
-      }
+  // every call issues its loads (past the last chunk they read zeros through the
+  // skip offset), so the count of loads in flight is the same on every path and
+  // each staging waits only for its own chunk
+  auto load_one = [&](__amdgpu_buffer_rsrc_t r, int k0, int i) {
+    const int e = tid + 256 * i;
+    const int p = e / (kCorrKC / 2), kl = 2 * (e % (kCorrKC / 2)), k = k0 + kl;
+    const unsigned off = (e < pairs && k < L) ? ((unsigned)p * (unsigned)a.y_stride + (unsigned)kl) * (unsigned)sizeof(Y) : kCorrSkip;
+    return load_pair<T>(r, off);
+  };
+  auto stage_one = [&](int i, int k0, const Pair& v) {
+    const int e = tid + 256 * i;
+    if (e < pairs) {
+      const int p = e / (kCorrKC / 2), k = 2 * (e % (kCorrKC / 2));
+      store_pair<T, Ld::PLANE>(at, Ld::at(p, k), Ld::at(M + p, k), clip_pair<T>(v, k0 + k + 1 < L));
     }
   };
   // two chunks in flight: chunk k+2's loads are issued before chunk k's MFMAs
@@ -675,16 +686,28 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
       }
     }
   };
+  // each staged pair's registers are refilled with chunk k+2 at once, so those
+  // loads are in flight during the rest of the staging as well as the MFMAs
   auto chunk = [&](Pair* buf, int k0) {
     __syncthreads();  // previous chunk's MFMAs are done with at[]
-    stage(buf);
+    const int kn = k0 + 2 * kCorrKC;  // at or past L: the loads read zeros
+    const __amdgpu_buffer_rsrc_t r = rsrc_at(kn < L ? kn : 0);
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      stage_one(i, k0, buf[i]);
+      buf[i] = load_one(r, kn, i);
+    }
     __syncthreads();
-    if (k0 + 2 * kCorrKC < L) load(k0 + 2 * kCorrKC, buf);
     mfma_chunk();
   };
   Pair buf0[PPT], buf1[PPT];
-  load(0, buf0);
-  if (kCorrKC < L) load(kCorrKC, buf1);
+  {
+    const __amdgpu_buffer_rsrc_t r0 = rsrc_at(0), r1 = rsrc_at(kCorrKC < L ? kCorrKC : 0);
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) buf0[i] = load_one(r0, 0, i);
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) buf1[i] = load_one(r1, kCorrKC, i);
+  }
   for (int k0 = 0; k0 < L; k0 += 2 * kCorrKC) {
     chunk(buf0, k0);
     if (k0 + kCorrKC < L) chunk(buf1, k0 + kCorrKC);
@@ -801,27 +824,23 @@ __global__ __launch_bounds__(corr_block_threads(BA)) void k_correlate_blocks(Cor
   // the buffer is padded for it).  M y_stride <= 2^28 samples, so the range is at
   // most 2^31 + 8 bytes and the skip offset kCorrSkip lies past it.
   typedef typename In::Y Y;
-  auto load = [&](int k0, Pair* buf) {
+  auto rsrc_at = [&](int k0) {
     const unsigned span = ((unsigned)M * (unsigned)a.y_stride - (unsigned)(w.dump_off + k0) + 1u) * (unsigned)sizeof(Y);
-    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(const_cast<Y*>(y + k0), (short)0, (int)span, 0x00020000);
-#pragma unroll
-    for (int i = 0; i < PPT; ++i) {
-      const int e = tid + NTH * i;
-      const int la = e / (kCorrKC / 2), kl = 2 * (e % (kCorrKC / 2)), k = k0 + kl;
-      const int p = ant_of(la);
-      const unsigned off = (p < M && k < L) ? ((unsigned)p * (unsigned)a.y_stride + (unsigned)kl) * (unsigned)sizeof(Y) : kCorrSkip;
-      buf[i] = load_pair<T>(r, off, k + 1 < L);
-    }
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<Y*>(y + k0), (short)0, (int)span, 0x00020000);
+  };
+  auto load_one = [&](__amdgpu_buffer_rsrc_t r, int k0, int i) {
+    const int e = tid + NTH * i;
+    const int la = e / (kCorrKC / 2), kl = 2 * (e % (kCorrKC / 2)), k = k0 + kl;
+    const int p = ant_of(la);
+    const unsigned off = (p < M && k < L) ? ((unsigned)p * (unsigned)a.y_stride + (unsigned)kl) * (unsigned)sizeof(Y) : kCorrSkip;
+    return load_pair<T>(r, off);
   };
   auto row_re = [](int la) { return la < BA ? la : 2 * BA + (la - BA); };
-  auto stage = [&](const Pair* buf) {
-#pragma unroll
-    for (int i = 0; i < PPT; ++i) {
-      const int e = tid + NTH * i;
-      const int la = e / (kCorrKC / 2), k = 2 * (e % (kCorrKC / 2));
-      const int rr = row_re(la), ri = rr + BA;
-      store_pair<T, PLANE>(at, rr * KP + k, ri * KP + k, buf[i]);
-    }
+  auto stage_one = [&](int i, int k0, const Pair& v) {
+    const int e = tid + NTH * i;
+    const int la = e / (kCorrKC / 2), k = 2 * (e % (kCorrKC / 2));
+    const int rr = row_re(la), ri = rr + BA;
+    store_pair<T, PLANE>(at, rr * KP + k, ri * KP + k, clip_pair<T>(v, k0 + k + 1 < L));
   };
   auto frag = [&](int plane, int row, int kr) -> Frag {
     return *reinterpret_cast<const Frag*>(&at[plane * PLANE + row * KP + kr]);
@@ -830,12 +849,23 @@ __global__ __launch_bounds__(corr_block_threads(BA)) void k_correlate_blocks(Cor
   // tile lies wholly below the diagonal (wave-uniform)
   auto needed = [&](int rt, int ct) { return I != J || ct >= rt; };
   Pair buf[PPT];
-  load(0, buf);
+  {
+    const __amdgpu_buffer_rsrc_t r = rsrc_at(0);
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) buf[i] = load_one(r, 0, i);
+  }
   for (int k0 = 0; k0 < L; k0 += kCorrKC) {
     __syncthreads();
-    stage(buf);
+    // each staged pair's registers are refilled with the next chunk at once, so
+    // those loads are in flight during the rest of the staging and the MFMAs
+    const int kn = k0 + kCorrKC;  // at or past L: the loads read zeros (same count on every path)
+    const __amdgpu_buffer_rsrc_t r = rsrc_at(kn < L ? kn : 0);
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      stage_one(i, k0, buf[i]);
+      buf[i] = load_one(r, kn, i);
+    }
     __syncthreads();
-    if (k0 + kCorrKC < L) load(k0 + kCorrKC, buf);
 #pragma unroll
     for (int kk = 0; kk < kCorrKC; kk += In::KSTEP) {
       const int kr = kk + 8 * (lane >> 4);
