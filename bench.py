@@ -92,10 +92,13 @@ def cpu_baseline(chunks, fc, dms, lay, p, n_dm):
                       "%.1f s" % (len(ds), ds, p["m_ant"], p["samples"], el)}
 
 
-def learned_form(plan, chunks, pulses, p, out, steps, plain_ms):
+def learned_form(make_plan, dms, chunks, pulses, p, out, steps, plain_ms):
     """Learned proposal on the same stream: power tile + network + coherent
     processing of the top 10% of DM trials (full sweep if the proposal falls back).
-    Returns speedup over the plain sweep and the recall of the injected pulses."""
+    Its plan keeps compact records, so the visibilities produced and fetched are
+    those of the proposed DMs only (the plain sweep's full records would carry
+    zeros for every other DM).  Returns speedup over the plain sweep and the
+    recall of the injected pulses."""
     import math
 
     import numpy as np
@@ -104,6 +107,8 @@ def learned_form(plan, chunks, pulses, p, out, steps, plain_ms):
     from paper_1109_3186_amd.proposal import Proposal, load_weights
     wpath = os.path.join(ROOT, "paper_1109_3186_amd", "proposal_weights.npz")
     full = torch.cat(chunks, dim=-1).contiguous()
+    plan = make_plan(compact_records=True)
+    plan.set_dm_trials(dms)
     prop = Proposal(plan, load_weights(wpath), budget=0.1)
 
     def step():
@@ -122,17 +127,18 @@ def learned_form(plan, chunks, pulses, p, out, steps, plain_ms):
         mask, fb = step()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
-    plan.set_active_dms(None)
     dstep = p["dm_max"] / p["n_dm"]
     hits = [int(mask[math.floor(q["dm"] / dstep)] or mask[min(math.ceil(q["dm"] / dstep), p["n_dm"] - 1)])
             for q in pulses]
     prop.close()
+    plan.close()
     del full
     log("learned: %.1f ms/step (plain %.1f), %d active DMs, fallback %s, recall %d/%d" % (
         ms, plain_ms, int(mask.sum()), fb, sum(hits), len(hits)))
     return {"speedup": plain_ms / ms, "ms_per_step": ms, "active_dms": int(mask.sum()), "n_dm": p["n_dm"],
             "fallback": bool(fb), "recall": sum(hits) / len(hits), "pulses": len(hits),
-            "note": "tile + network + active-DM sweep on the same stream; recall = injected pulses whose DM trial "
+            "note": "tile + network + active-DM sweep on the same stream, records of the proposed DMs only; "
+                    "recall = injected pulses whose DM trial "
                     "(either neighbour) is active"}
 
 
@@ -328,8 +334,11 @@ def main():
         kw = autotune.plan_kwargs(tuned)
         log("tuned (%s): lengths %s wave %d group %d" % (tuned["source"], sorted(set(tuned["fft_len"])),
                                                           tuned["wave_units"], tuned["dm_group"]))
-    plan = Plan(p["m_ant"], fc, p["f_s"], p["dump_len"], max_block_samples=args.chunk, in_dtype="ci8",
-                corr_dtype=args.corr, out_mode="packed", **kw)
+    def make_plan(**extra):
+        return Plan(p["m_ant"], fc, p["f_s"], p["dump_len"], max_block_samples=args.chunk, in_dtype="ci8",
+                    corr_dtype=args.corr, out_mode="packed", **kw, **extra)
+
+    plan = make_plan()
     plan.set_dm_trials(dms)
     lay = plan.layout()
     log("plan: N %d V %d..%d lead %d, ring %d dumps, %.1f GB device, wave %d units, DM group %d" % (
@@ -369,7 +378,7 @@ def main():
     roofline = roofline_of(prof, args)
     learned = None
     if not args.no_learned:
-        learned = learned_form(plan, chunks, pulses, p, out, args.steps, ms)
+        learned = learned_form(make_plan, dms, chunks, pulses, p, out, args.steps, ms)
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on a slice")
