@@ -489,10 +489,10 @@ typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 // (the stored voltages are s y, s = the channel's correlator-input scale),
 // G = A A^T on MFMA over the upper 16x16 tiles, FP32 accumulation, then
 //   Re V_ij = (G[i][j] + G[M+i][M+j]) / s^2,  Im V_ij = (G[j][M+i] - G[i][M+j]) / s^2.
-// Samples are staged through LDS in
-// chunks of kCorrKC; the next chunk's global loads are issued before the current
-// chunk's MFMAs.  grid: n_units * max_dumps workgroups of 256 threads (4 waves),
-// one per (unit, dump); workgroups past a unit's last dump exit at once.
+// Samples are staged through LDS in chunks of kCorrKC with two chunks in flight:
+// chunk k + 2's loads are issued while chunk k is staged, before its MFMAs.
+// grid: n_units * max_dumps workgroups of 256 threads (4 waves), one per
+// (unit, dump); workgroups past a unit's last dump exit at once.
 struct CorrArgs {
   const void* y;
   float2* ring;
@@ -656,7 +656,6 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
       store_pair<T, Ld::PLANE>(at, Ld::at(p, k), Ld::at(M + p, k), clip_pair<T>(v, k0 + k + 1 < L));
     }
   };
-  // two chunks in flight: chunk k+2's loads are issued before chunk k's MFMAs
   auto mfma_chunk = [&]() {
 #pragma unroll
     for (int kk = 0; kk < kCorrKC; kk += In::KSTEP) {
