@@ -13,7 +13,11 @@ what Bannister & Cornwell (2011), "The Chirpolator and The Chimageator", define:
   "mixing" of Sec. 3.2, Eq. xpq), integrated and dumped at a fixed cadence
   (Sec. 5.1, the integrate-and-dump boundary of the cost model);
 * the block partial DFT of Appendix A.3 (Eq. block_cic), whose k = 0 term is
-  the integrate-and-dump of the mixed product.
+  the integrate-and-dump of the mixed product;
+* in ``oracle.chirpolator``, the Chirpolator pre-integrator itself (Sec. 3.2,
+  App. A.3): mixing of antenna pairs, block partial DFTs over the bins
+  |k| <= kmax, the block CIC moving sum, the closed form of a mixed chirp's DFT,
+  the DFT factorisation across lengths and the shared negative-bin products.
 
 Everything is numpy in float64 / complex128.  The oracle shares no code with the
 GPU path; only the seeded input generators (package ``synth``) serve both.
