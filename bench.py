@@ -142,6 +142,73 @@ def learned_form(make_plan, dms, chunks, pulses, p, out, steps, plain_ms):
                     "(either neighbour) is active"}
 
 
+def run_chirp(args, dev):
+    """The Chirpolator pre-integrator (Sec. 3.2, App. A.3) on one complex baseband
+    stream: 36 antennas (630 pairs), 2^22 samples of unit-variance noise, sliding
+    DFT of length N = 2^16 sampled every L = 1024 samples, bins -100..100 (the
+    paper's k0,max ~ 100 for the longest baselines).  One step = one call over the
+    whole stream (partial DFTs of every block, then the block CIC)."""
+    import numpy as np
+    import torch
+
+    from paper_1109_3186_amd import Chirp
+    M, n, N, L, kmax = 36, 1 << 22, 1 << 16, 1024, 100
+    g = torch.Generator(device=dev)
+    g.manual_seed(1109)
+    volts = torch.randn((M, n), dtype=torch.complex64, device=dev, generator=g)
+    c = Chirp(M, N, L, kmax, max_samples=n)
+    shape = c.output_shape(n)
+    out = torch.empty(shape, dtype=torch.complex64, device=dev)
+    for _ in range(args.warmup):
+        c.preintegrate(volts, out=out)
+    torch.cuda.synchronize()
+    t0e, t1e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    t0e.record()
+    for _ in range(args.steps):
+        c.preintegrate(volts, out=out)
+    t1e.record()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ev_ms = t0e.elapsed_time(t1e) / args.steps
+    pairs, bins = shape[1], shape[2]
+    nb = n // L
+    units = pairs * nb * L * bins
+    value = units / (ms / 1e3)
+    flops = 8.0 * units  # one complex multiply-add per (pair, sample, bin)
+    tf = flops / (ev_ms / 1e3) / 1e12
+    c.close()
+    log("chirpolator: %.1f ms/step, %.3e pair-sample-bins/s, %.1f TFLOP/s" % (ms, value, tf))
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the FP64 oracle on one pair over the first 1024 blocks, one thread
+        from threadpoolctl import threadpool_limits
+
+        from oracle import chirpolator as och
+        nbs = 1024
+        s01 = volts[:2, :nbs * L].cpu().numpy().astype(np.complex128)
+        with threadpool_limits(1):
+            tc = time.perf_counter()
+            och.block_cic(och.block_partial_dft(och.mix(s01, 0, 1), N, L, och.bins(kmax)), N, L)
+            tc = time.perf_counter() - tc
+        cpu = {"value": nbs * L * bins / tc, "unit": "pair-samples*bins/s", "cores": 1, "kind": "oracle",
+               "sample": "pair (0, 1), first %d blocks, all %d bins, FP64 numpy on one thread, %.1f s" % (
+                   nbs, bins, tc)}
+        log("oracle slice: %.1f s" % tc)
+    rec = {"metric": "pair-samples x DFT bins/s pre-integrated (Chirpolator)", "value": value,
+           "unit": "pair-samples*bins/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "Chirpolator pre-integrator: 36 ant (630 pairs) x 2^22 cf32 samples, N 2^16, "
+                                  "L 1024, bins -100..100", "n_ant": M, "samples": n, "fft_len": N, "block_len": L,
+                      "kmax": kmax, "parallelism": "none (1 GPU)"},
+           "roofline": {"bound": "alu", "achieved": round(tf, 2), "peak": PEAKS["fp32_vector_tflops"],
+                        "unit": "TFLOP/s", "frac": round(tf / PEAKS["fp32_vector_tflops"], 4), "traffic": None,
+                        "kernel": "partial DFT + block CIC (one call)", "avg_call_ms": round(ev_ms, 3)},
+           "cpu_baseline": cpu}
+    print(json.dumps(rec), flush=True)
+
+
 def run_c3(args, dev):
     """The batched sparse-array workload: 256 antennas, 32 x 1 MHz channels at
     0.7-0.732 GHz, 2^18 ci8 samples, per-channel DM grids of 512..1536 trials over
@@ -291,8 +358,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal measurement")
     ap.add_argument("--wave-units", type=int, default=0, help="schedule: units per wave (0 = automatic)")
     ap.add_argument("--dm-group", type=int, default=0, help="schedule: DMs per block group (0 = automatic)")
-    ap.add_argument("--workload", default="c1", choices=["c1", "c3"],
-                    help="c1: 36-antenna headline workload (default); c3: 256-antenna batched sparse array")
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "chirp"],
+                    help="c1: 36-antenna headline workload (default); c3: 256-antenna batched sparse array; "
+                         "chirp: the Chirpolator pre-integrator")
     ap.add_argument("--autotune", action="store_true", help="use the autotuned lengths and schedule (cached)")
     ap.add_argument("--passes", type=int, default=0, help="c3: DM-window passes (0 = ceil(sum D / 512))")
     ap.add_argument("--channels", type=int, default=0,
@@ -314,6 +382,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "c3":
         return run_c3(args, dev)
+    if args.workload == "chirp":
+        return run_chirp(args, dev)
     if args.copy_calibration:
         src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)
         dst = torch.mul(src, 1.0)  # reads and writes copy_calibration MiB each

@@ -308,6 +308,41 @@ int ddx_cnn_adam(ddx_cnn* net, float lr, float beta1, float beta2, float eps, vo
 int ddx_cnn_destroy(ddx_cnn* net);
 const char* ddx_cnn_last_error(const ddx_cnn* net);
 
+/* ---- Chirpolator pre-integrator (Sec. 3.2, App. A.3) ----------------------------
+ * For every antenna pair p < q (row-major: (0,1), (0,2), ..., (M-2,M-1)) of one
+ * complex baseband stream s [M][n]:
+ *   x_pq[n] = s_p[n] s_q[n]^*                                     (Sec. 3.2, Eq. xpq)
+ *   V_k[m]  = sum_{j<L} exp(-2 pi i (j + m L) k / N) x_pq[j + m L]  (App. A.3, block partial DFT)
+ *   S_k[m]  = S_k[m-1] + V_k[m] - V_k[m - N/L]                    (App. A.3, Eq. block_cic)
+ * for the bins k = -kmax..kmax and the complete blocks m of the stream, from zero
+ * state, so S_k[m] is bin k of the DFT of the N samples ending with block m (phase
+ * referenced to sample 0).  Only complete windows are returned: m = N/L - 1 ..
+ * n/L - 1.  FP32 products, FP32 sums over a block, FP64 moving sum, FP32 output.
+ * One pre-integrator serves one DFT length N (one DM bank); it is not thread-safe. */
+typedef struct ddx_chirp ddx_chirp;
+
+/* n_ant in [2, 1024]; block_len L >= 1; fft_n N a multiple of L; 0 <= kmax with
+ * 2 kmax + 1 <= N; max_samples >= N bounds n per call (it sizes the partial-DFT
+ * workspace: (max_samples / L) (M (M-1) / 2) (2 kmax + 1) complex64).  EINVAL for
+ * out-of-range arguments, ENOMEM / EDEVICE for device failures. */
+int ddx_chirp_create(int32_t n_ant, int32_t fft_n, int32_t block_len, int32_t kmax, int64_t max_samples,
+                     ddx_chirp** out);
+
+/* Shape of the output of a call with n samples: *n_windows = max(0, n/L - N/L + 1)
+ * complete windows, *n_pairs = M (M-1) / 2, *n_bins = 2 kmax + 1. */
+int ddx_chirp_output_shape(const ddx_chirp* c, int64_t n, int64_t* n_windows, int32_t* n_pairs, int32_t* n_bins);
+
+/* d_volts: DEVICE [M][n] complex64 (float re, float im), caller-owned; d_out:
+ * DEVICE [n_windows][n_pairs][n_bins] complex64, bin index k + kmax.  Asynchronous
+ * on hip_stream; the inputs must stay valid until the stream has passed the work.
+ * A stream shorter than one window returns DDX_OK and writes nothing.  EINVAL for
+ * n outside [0, max_samples] or a NULL buffer, EDEVICE for launch failures. */
+int ddx_chirp_preintegrate(ddx_chirp* c, const void* d_volts, int64_t n, void* d_out, void* hip_stream);
+
+/* Synchronises the device and frees the pre-integrator.  NULL is a no-op. */
+int ddx_chirp_destroy(ddx_chirp* c);
+const char* ddx_chirp_last_error(const ddx_chirp* c);
+
 /* Synchronise the plan's last stream and free plan-owned memory.  NULL is a no-op. */
 int ddx_plan_destroy(ddx_plan* plan);
 

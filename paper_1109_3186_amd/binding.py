@@ -87,6 +87,13 @@ SIGNATURES = {
     "ddx_cnn_adam": ([ct.c_void_p, ct.c_float, ct.c_float, ct.c_float, ct.c_float, ct.c_void_p], ct.c_int),
     "ddx_cnn_destroy": ([ct.c_void_p], ct.c_int),
     "ddx_cnn_last_error": ([ct.c_void_p], ct.c_char_p),
+    "ddx_chirp_create": ([ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int64, ct.POINTER(ct.c_void_p)],
+                         ct.c_int),
+    "ddx_chirp_output_shape": ([ct.c_void_p, ct.c_int64, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32),
+                                ct.POINTER(ct.c_int32)], ct.c_int),
+    "ddx_chirp_preintegrate": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p], ct.c_int),
+    "ddx_chirp_destroy": ([ct.c_void_p], ct.c_int),
+    "ddx_chirp_last_error": ([ct.c_void_p], ct.c_char_p),
     "ddx_plan_destroy": ([ct.c_void_p], ct.c_int),
     "ddx_strerror": ([ct.c_int], ct.c_char_p),
     "ddx_last_error": ([ct.c_void_p], ct.c_char_p),
@@ -370,6 +377,64 @@ class Cnn:
         if getattr(self, "_h", None):
             lib().ddx_cnn_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Chirp:
+    """The Chirpolator pre-integrator of include/ddx.h (ddx_chirp_*): for every
+    antenna pair p < q, bins -kmax..kmax of the sliding DFT of length N, sampled
+    every L samples, of the mixed product s_p s_q^*."""
+
+    def __init__(self, n_ant, fft_n, block_len, kmax, max_samples):
+        h = ct.c_void_p()
+        rc = lib().ddx_chirp_create(n_ant, fft_n, block_len, kmax, max_samples, ct.byref(h))
+        if rc != OK:
+            raise DdxError(rc, "ddx_chirp_create")
+        self._h = h
+        self.n_ant, self.fft_n, self.block_len, self.kmax, self.max_samples = n_ant, fft_n, block_len, kmax, max_samples
+
+    def _check(self, rc, what):
+        if rc != OK:
+            raise DdxError(rc, "%s: %s" % (what, lib().ddx_chirp_last_error(self._h).decode()))
+
+    def output_shape(self, n):
+        w, p, b = ct.c_int64(), ct.c_int32(), ct.c_int32()
+        self._check(lib().ddx_chirp_output_shape(self._h, int(n), ct.byref(w), ct.byref(p), ct.byref(b)),
+                    "ddx_chirp_output_shape")
+        return w.value, p.value, b.value
+
+    def preintegrate(self, volts, out=None, stream=None):
+        """volts: device complex64 [M, n]; returns device complex64 [windows, pairs, bins]."""
+        import torch
+        if volts.dtype != torch.complex64 or volts.dim() != 2 or volts.shape[0] != self.n_ant:
+            raise DdxError(EINVAL, "volts must be complex64 [%d, n]" % self.n_ant)
+        volts = volts.contiguous()
+        n = volts.shape[1]
+        shape = self.output_shape(n)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.complex64, device=volts.device)
+        elif tuple(out.shape) != shape or out.dtype != torch.complex64 or not out.is_contiguous():
+            raise DdxError(EINVAL, "out must be contiguous complex64 %s" % (shape,))
+        self._check(lib().ddx_chirp_preintegrate(self._h, ct.c_void_p(volts.data_ptr()), n,
+                                                 ct.c_void_p(out.data_ptr()), _stream_handle(stream)),
+                    "ddx_chirp_preintegrate")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ddx_chirp_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
     def __del__(self):
         try:

@@ -162,3 +162,17 @@ def test_autotune_dm_sampling_keeps_the_largest():
     s = _sample_dms(d, 16)
     assert d.max() in s and len(s) <= 17 and len(np.unique(s)) == len(s)
     assert np.array_equal(_sample_dms(d[:5], 16), d[:5])
+
+
+def test_chirp_create_rejects_invalid_arguments():
+    """Argument checks of ddx_chirp_create run before any device call."""
+    L = ct.CDLL(ddx.LIB_PATH)
+    for args in [(1, 64, 16, 4, 1000), (2000, 64, 16, 4, 1000), (4, 60, 16, 4, 1000), (4, 64, 0, 4, 1000),
+                 (4, 64, 16, -1, 1000), (4, 64, 16, 32, 1000), (4, 64, 16, 4, 63)]:
+        h = ct.c_void_p()
+        assert L.ddx_chirp_create(*[ct.c_int32(a) for a in args[:4]], ct.c_int64(args[4]), ct.byref(h)) == \
+            binding.EINVAL, args
+        assert not h.value
+    assert L.ddx_chirp_create(4, 64, 16, 4, ct.c_int64(1000), None) == binding.EINVAL
+    assert L.ddx_chirp_destroy(None) == binding.OK
+    assert L.ddx_chirp_preintegrate(None, None, ct.c_int64(0), None, None) == binding.EINVAL

@@ -1,0 +1,65 @@
+"""GPU parity of the Chirpolator pre-integrator (ddx_chirp_*, Sec. 3.2 and App. A.3)
+against the FP64 oracle (oracle/chirpolator.py): ragged pair and bin tiles, block
+lengths that are not a multiple of the LDS chunk, a partial last block, L = 1 with a
+single bin, and the DFT of a mixed linear chirp against its closed form (Eq. phidn).
+Bound: FP32 products and block sums, FP64 moving sum -> 1e-5 of the output's RMS."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import say
+from oracle import chirpolator as och
+from paper_1109_3186_amd import Chirp
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _run(s, n_win, L, kmax):
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(np.ascontiguousarray(s.astype(np.complex64))).to(dev)
+    with Chirp(s.shape[0], n_win, L, kmax, max_samples=s.shape[1]) as c:
+        out = c.preintegrate(x)
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("m_ant,n_win,L,kmax,extra", [(5, 160, 40, 37, 17), (20, 192, 32, 70, 0), (3, 24, 8, 0, 5),
+                                                      (4, 6, 1, 0, 0), (12, 4000, 1000, 12, 999)])
+def test_preintegrator_matches_oracle(gpu, m_ant, n_win, L, kmax, extra):
+    nb = n_win // L + 6
+    s = synth.noise_complex(np.random.Generator(np.random.PCG64(90 + m_ant)), (m_ant, nb * L + extra))
+    say("chirpolator: M %d N %d L %d kmax %d, %d samples" % (m_ant, n_win, L, kmax, s.shape[1]))
+    got = _run(s, n_win, L, kmax)
+    ref = och.preintegrate(s, n_win, L, kmax)
+    assert got.shape == ref.shape
+    err = np.max(np.abs(got - ref)) / np.sqrt(np.mean(np.abs(ref) ** 2))
+    say("max error / rms %.3e" % err)
+    assert err <= TOL
+
+
+def test_mixed_chirp_closed_form_on_gpu(gpu):
+    """Two antennas receive a linear chirp, q later by tau: the first complete
+    window's bins are Phi(k - k0) D_N(k - k0), k0 = fdot tau N / f_s (Eq. phidn)."""
+    f_s, n_win, L, tau, k0 = 1e6, 4096, 256, 2.5e-6, 3.37
+    fdot = k0 * f_s / (tau * n_win)
+    s = np.stack([och.linear_chirp(n_win, fdot, f_s), och.linear_chirp(n_win, fdot, f_s, tau)])
+    got = _run(s, n_win, L, 12)[0, 0]
+    ref = och.mixed_chirp_dft(och.bins(12), n_win, fdot, tau, f_s)
+    err = np.max(np.abs(got - ref)) / n_win
+    say("mixed chirp: peak |S| / N %.4f, max error / N %.2e" % (np.max(np.abs(got)) / n_win, err))
+    assert err <= 2e-6
+
+
+def test_short_stream_and_bad_arguments(gpu):
+    from paper_1109_3186_amd import DdxError
+    with Chirp(3, 64, 16, 4, max_samples=1000) as c:
+        assert c.output_shape(63) == (0, 3, 9)
+        x = torch.zeros((3, 63), dtype=torch.complex64, device="cuda:0")
+        assert c.preintegrate(x).shape == (0, 3, 9)
+        with pytest.raises(DdxError):
+            c.preintegrate(torch.zeros((3, 1001), dtype=torch.complex64, device="cuda:0"))
+        with pytest.raises(DdxError):
+            c.preintegrate(torch.zeros((2, 100), dtype=torch.complex64, device="cuda:0"))
