@@ -175,7 +175,9 @@ def run_chirp(args, dev):
     nb = n // L
     units = pairs * nb * L * bins
     value = units / (ms / 1e3)
-    flops = 8.0 * units  # one complex multiply-add per (pair, sample, bin)
+    # bins k and -k share their four products (App. A.3, Eqs. fpos, fneg): four FMAs
+    # per (pair, sample, k > 0), two for k = 0
+    flops = 2.0 * pairs * nb * L * (4 * kmax + 2)
     tf = flops / (ev_ms / 1e3) / 1e12
     c.close()
     log("chirpolator: %.1f ms/step, %.3e pair-sample-bins/s, %.1f TFLOP/s" % (ms, value, tf))

@@ -8,9 +8,13 @@
 //
 // The twiddle of sample n + m L factors as w_k[n] exp(-2 pi i ((m mod R) L k mod N) / N)
 // with R = N / L, so one table W[n][k] (n < L) and one phase table P[m mod R][k],
-// both computed in FP64 on the host and stored in FP32, serve every block.  Per block
-// the partial DFTs of all pairs are a complex product [pairs x L] x [L x bins], done
-// in 64 x 64 output tiles with the mixing fused into the staging of the left operand.
+// both computed in FP64 on the host and stored in FP32, serve every block.  Bins k
+// and -k share their products (App. A.3, Eqs. fpos, fneg): with x = a + i b and
+// w_k = c - i d, the four sums P = sum a c, Q = sum b d, R = sum a d, T = sum b c give
+//   V_k = (P + Q) + i (T - R),   V_-k = (P - Q) + i (R + T),
+// one FMA per sum and sample, half the work of two separate complex products.  Per
+// block the partial DFTs of all pairs are then a product [pairs x L] x [L x (kmax+1)]
+// in 64 x 64 tiles, the mixing fused into the staging of the pair operand.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -33,16 +37,16 @@ constexpr int kChunk = 32;   // samples per LDS chunk
 struct PartialArgs {
   const float2* s;        // [M][n] complex samples
   const int2* pq;         // [nbl] (p, q)
-  const float2* w;        // [L_pad][K_pad] w_k[n]
-  const float2* ph;       // [R][K_pad] block phase
-  float2* v;              // [nb][nbl][K] partial DFTs
+  const float2* w;        // [L_pad][K_pad] (c, d) of w_k[n] = c - i d, k = 0..kmax
+  const float2* ph;       // [R][K_pad] (c, d) of the block phase of bin k >= 0
+  float2* v;              // [nb][nbl][2 kmax + 1] partial DFTs, bin index k + kmax
   int64_t n_samp;         // samples per antenna row of s
-  int32_t nbl, K, K_pad, L, R, n_ptiles, n_ktiles;
+  int32_t nbl, kmax, K_pad, L, R, n_ptiles, n_ktiles;
 };
 
 // grid: nb * n_ptiles * n_ktiles workgroups of 256 threads (block slowest).
 // Thread (tp, tk) = (tid / 16, tid % 16) accumulates pairs 4 tp .. 4 tp + 3 of the
-// tile against bins 4 tk .. 4 tk + 3.
+// tile against bins +-(4 tk .. 4 tk + 3) of the tile.
 __global__ __launch_bounds__(256) void k_partial(PartialArgs a) {
   __shared__ float2 xs[kChunk][kTileP];
   __shared__ float2 ws[kChunk][kTileK];
@@ -53,11 +57,11 @@ __global__ __launch_bounds__(256) void k_partial(PartialArgs a) {
   const int p0 = pt * kTileP, k0 = kt * kTileK;
   const int tp = tid >> 4, tk = tid & 15;
   const int64_t base = (int64_t)m * a.L;
-  float2 acc[4][4];
+  float4 acc[4][4];  // (P, Q, R, T) per pair and bin pair
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = make_float2(0.f, 0.f);
+    for (int j = 0; j < 4; ++j) acc[i][j] = make_float4(0.f, 0.f, 0.f, 0.f);
 
   for (int n0 = 0; n0 < a.L; n0 += kChunk) {
     __syncthreads();
@@ -95,37 +99,53 @@ __global__ __launch_bounds__(256) void k_partial(PartialArgs a) {
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          acc[i][j].x = fmaf(xv[i].x, wv[j].x, fmaf(-xv[i].y, wv[j].y, acc[i][j].x));
-          acc[i][j].y = fmaf(xv[i].x, wv[j].y, fmaf(xv[i].y, wv[j].x, acc[i][j].y));
+          acc[i][j].x = fmaf(xv[i].x, wv[j].x, acc[i][j].x);  // P += a c
+          acc[i][j].y = fmaf(xv[i].y, wv[j].y, acc[i][j].y);  // Q += b d
+          acc[i][j].z = fmaf(xv[i].x, wv[j].y, acc[i][j].z);  // R += a d
+          acc[i][j].w = fmaf(xv[i].y, wv[j].x, acc[i][j].w);  // T += b c
         }
     }
   }
-  // block phase and store
+  // V_+-k, times the block phase exp(-+ i phi) = c -+ i d, stored at bin index kmax +- k
   const float2* ph = a.ph + (int64_t)(m % a.R) * a.K_pad;
+  const int K = 2 * a.kmax + 1;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int k = k0 + 4 * tk + j;
-    if (k >= a.K) continue;
+    if (k > a.kmax) continue;
     const float2 f = ph[k];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int pair = p0 + 4 * tp + i;
       if (pair >= a.nbl) continue;
-      const float2 u = acc[i][j];
-      a.v[((int64_t)m * a.nbl + pair) * a.K + k] = make_float2(u.x * f.x - u.y * f.y, u.x * f.y + u.y * f.x);
+      const float4 u = acc[i][j];
+      const float pr = u.x + u.y, pi = u.w - u.z;  // V_k
+      const float nr = u.x - u.y, ni = u.z + u.w;  // V_-k
+      float2* row = a.v + ((int64_t)m * a.nbl + pair) * K + a.kmax;
+      row[k] = make_float2(pr * f.x + pi * f.y, pi * f.x - pr * f.y);
+      if (k > 0) row[-k] = make_float2(nr * f.x - ni * f.y, ni * f.x + nr * f.y);
     }
   }
 }
 
 // Eq. block_cic per (pair, bin), FP64 running sum from zero state; writes the full
-// windows m >= R - 1 as out[m - R + 1][pair][k].  grid: ceil(nbl K / 256) x 256.
+// windows m >= R - 1 as out[m - R + 1][pair][k].  The blocks are cut into segments
+// of seg blocks run in parallel: a segment starts from S[m0 - 1], the sum of the R
+// blocks before it, then follows the recursion.
+// grid: (ceil(cols / 256), ceil(nb / seg)) x 256.
 __global__ __launch_bounds__(256) void k_cic(const float2* __restrict__ v, float2* __restrict__ out, int64_t cols,
-                                             int32_t nb, int32_t R) {
+                                             int32_t nb, int32_t R, int32_t seg) {
   const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (c >= cols) return;
+  const int m0 = blockIdx.y * seg, m1 = min(nb, m0 + seg);
   double re = 0.0, im = 0.0;
+  for (int m = max(0, m0 - R); m < m0; ++m) {
+    const float2 add = v[(int64_t)m * cols + c];
+    re += add.x;
+    im += add.y;
+  }
 #pragma unroll 8
-  for (int m = 0; m < nb; ++m) {
+  for (int m = m0; m < m1; ++m) {
     const float2 add = v[(int64_t)m * cols + c];
     re += add.x;
     im += add.y;
@@ -187,24 +207,25 @@ int ddx_chirp_create(int32_t n_ant, int32_t fft_n, int32_t block_len, int32_t km
   c->L = block_len;
   c->kmax = kmax;
   c->K = 2 * kmax + 1;
-  c->K_pad = (c->K + chirp::kTileK - 1) / chirp::kTileK * chirp::kTileK;
+  c->K_pad = (kmax + 1 + chirp::kTileK - 1) / chirp::kTileK * chirp::kTileK;
   c->L_pad = (c->L + chirp::kChunk - 1) / chirp::kChunk * chirp::kChunk;
   c->R = fft_n / block_len;
   c->nbl = n_ant * (n_ant - 1) / 2;
   c->max_samples = max_samples;
   c->max_blocks = max_samples / block_len;
-  // FP64 tables: w_k[n] = exp(-2 pi i (n k mod N) / N), P[r][k] = exp(-2 pi i (r L k mod N) / N)
+  // FP64 tables for k = 0..kmax, as (c, d) with exp(-2 pi i u / N) = c - i d:
+  // w_k[n] with u = n k mod N, P[r][k] with u = r L k mod N
   std::vector<float2> w((size_t)c->L_pad * c->K_pad, make_float2(0.f, 0.f));
   std::vector<float2> ph((size_t)c->R * c->K_pad, make_float2(0.f, 0.f));
   auto tw = [&](int64_t num) {
     const int64_t r = ((num % c->N) + c->N) % c->N;
-    const double ang = -2.0 * M_PI * (double)r / (double)c->N;
+    const double ang = 2.0 * M_PI * (double)r / (double)c->N;
     return make_float2((float)std::cos(ang), (float)std::sin(ang));
   };
   for (int n = 0; n < c->L; ++n)
-    for (int j = 0; j < c->K; ++j) w[(size_t)n * c->K_pad + j] = tw((int64_t)n * (j - kmax));
+    for (int j = 0; j <= kmax; ++j) w[(size_t)n * c->K_pad + j] = tw((int64_t)n * j);
   for (int r = 0; r < c->R; ++r)
-    for (int j = 0; j < c->K; ++j) ph[(size_t)r * c->K_pad + j] = tw((int64_t)r * c->L * (j - kmax));
+    for (int j = 0; j <= kmax; ++j) ph[(size_t)r * c->K_pad + j] = tw((int64_t)r * c->L * j);
   std::vector<int2> pq;
   for (int p = 0; p < n_ant; ++p)
     for (int q = p + 1; q < n_ant; ++q) pq.push_back(make_int2(p, q));
@@ -255,7 +276,7 @@ int ddx_chirp_preintegrate(ddx_chirp* c, const void* d_volts, int64_t n, void* d
   a.v = c->v;
   a.n_samp = n;
   a.nbl = c->nbl;
-  a.K = c->K;
+  a.kmax = c->kmax;
   a.K_pad = c->K_pad;
   a.L = c->L;
   a.R = c->R;
@@ -267,8 +288,10 @@ int ddx_chirp_preintegrate(ddx_chirp* c, const void* d_volts, int64_t n, void* d
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return cfail(c, DDX_EDEVICE, "k_partial: %s", hipGetErrorString(e));
   const int64_t cols = (int64_t)c->nbl * c->K;
-  hipLaunchKernelGGL(chirp::k_cic, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, s, (const float2*)c->v,
-                     (float2*)d_out, cols, (int32_t)nb, (int32_t)c->R);
+  // segments of at least 256 blocks (the R-block restart costs R / seg extra reads), at most 65535
+  const int64_t seg = std::max<int64_t>(256, (nb + 65534) / 65535);
+  hipLaunchKernelGGL(chirp::k_cic, dim3((unsigned)((cols + 255) / 256), (unsigned)((nb + seg - 1) / seg)), dim3(256), 0,
+                     s, (const float2*)c->v, (float2*)d_out, cols, (int32_t)nb, (int32_t)c->R, (int32_t)seg);
   e = hipGetLastError();
   if (e != hipSuccess) return cfail(c, DDX_EDEVICE, "k_cic: %s", hipGetErrorString(e));
   return DDX_OK;
