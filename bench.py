@@ -181,6 +181,42 @@ def run_chirp(args, dev):
     tf = flops / (ev_ms / 1e3) / 1e12
     c.close()
     log("chirpolator: %.1f ms/step, %.3e pair-sample-bins/s, %.1f TFLOP/s" % (ms, value, tf))
+    # the bank of lengths N0 d, d = 1..8 (N0 = N / 8), with the factorisation, against
+    # the same eight lengths computed directly one by one
+    import math
+
+    from paper_1109_3186_amd import ChirpBank
+    n0, n_len = N // 8, 8
+
+    def timed(run):
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            run()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / args.steps
+
+    bank = ChirpBank(M, n0, n_len, L, kmax, max_samples=n)
+    _, _, total = bank.layout(n)
+    bout = torch.empty(total, dtype=torch.complex64, device=dev)
+    ms_bank = timed(lambda: bank.run(volts, out=bout))
+    bank.close()
+    del bout
+    ms_direct = 0.0
+    for d in range(1, n_len + 1):
+        cd = Chirp(M, n0 * d, L, kmax, max_samples=n)
+        od = torch.empty(cd.output_shape(n), dtype=torch.complex64, device=dev)
+        ms_direct += timed(lambda: cd.preintegrate(volts, out=od))
+        cd.close()
+        del od
+    frac = sum(1 for d in range(1, n_len + 1) for kk in range(-kmax, kmax + 1) if math.gcd(abs(kk), d) > 1) / (
+        n_len * (2 * kmax + 1))
+    log("chirpolator bank of %d lengths: %.1f ms against %.1f ms direct (%.1f %% of bins factorised)" % (
+        n_len, ms_bank, ms_direct, 100 * frac))
+    bank_rec = {"n0": n0, "lengths": n_len, "ms_bank": round(ms_bank, 2), "ms_direct": round(ms_direct, 2),
+                "speedup": round(ms_direct / ms_bank, 3), "factorised_fraction": round(frac, 4)}
     cpu = None
     if not args.no_cpu_baseline:
         # the FP64 oracle on one pair over the first 1024 blocks, one thread
@@ -207,7 +243,7 @@ def run_chirp(args, dev):
            "roofline": {"bound": "alu", "achieved": round(tf, 2), "peak": PEAKS["fp32_vector_tflops"],
                         "unit": "TFLOP/s", "frac": round(tf / PEAKS["fp32_vector_tflops"], 4), "traffic": None,
                         "kernel": "partial DFT + block CIC (one call)", "avg_call_ms": round(ev_ms, 3)},
-           "cpu_baseline": cpu}
+           "cpu_baseline": cpu, "bank": bank_rec}
     print(json.dumps(rec), flush=True)
 
 

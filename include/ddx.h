@@ -343,6 +343,30 @@ int ddx_chirp_preintegrate(ddx_chirp* c, const void* d_volts, int64_t n, void* d
 int ddx_chirp_destroy(ddx_chirp* c);
 const char* ddx_chirp_last_error(const ddx_chirp* c);
 
+/* A bank of the same pre-integrator over the window lengths N = n0 d, d = 1 ..
+ * n_len (App. A.3, a DFT length per DM trial), with the factorisation of App. A.3
+ * ("Factorizing the DFTs"): a bin k that shares a factor with d is formed, for the
+ * smallest prime p dividing gcd(|k|, d) (gcd(0, d) = d), as the sum of p adjacent
+ * windows of bin k / p of length n0 d / p; the other bins are computed directly.
+ * Constraints as for ddx_chirp_create with N = n0, plus 1 <= n_len <= 64 and
+ * max_samples >= n0 n_len.  Not thread-safe. */
+typedef struct ddx_chirp_bank ddx_chirp_bank;
+
+int ddx_chirp_bank_create(int32_t n_ant, int32_t n0, int32_t n_len, int32_t block_len, int32_t kmax,
+                          int64_t max_samples, ddx_chirp_bank** out);
+
+/* Output layout of a call with n samples: length d's windows [n/L - n0 d/L + 1]
+ * (or 0) x [pairs] x [2 kmax + 1] complex64 start at element offsets[d - 1];
+ * windows and offsets are host arrays of n_len entries; *total = all elements. */
+int ddx_chirp_bank_layout(const ddx_chirp_bank* b, int64_t n, int64_t* windows, int64_t* offsets, int64_t* total);
+
+/* d_volts: DEVICE [M][n] complex64; d_out: DEVICE, *total complex64 in the layout
+ * above.  Asynchronous on hip_stream.  Errors as for ddx_chirp_preintegrate. */
+int ddx_chirp_bank_run(ddx_chirp_bank* b, const void* d_volts, int64_t n, void* d_out, void* hip_stream);
+
+int ddx_chirp_bank_destroy(ddx_chirp_bank* b);
+const char* ddx_chirp_bank_last_error(const ddx_chirp_bank* b);
+
 /* Synchronise the plan's last stream and free plan-owned memory.  NULL is a no-op. */
 int ddx_plan_destroy(ddx_plan* plan);
 

@@ -163,3 +163,40 @@ def pos_neg_products(a, b, c, d):
     products ac, bd, ad, bc.  Returns (r_k, r_-k, multiplications, additions)."""
     ac, bd, ad, bc = a * c, b * d, a * d, b * c
     return complex(ac + bd, bc - ad), complex(ac - bd, ad + bc), 4, 4
+
+
+def bank_direct(s, n0, n_len, L, kmax):
+    """The pre-integrator for every window length n0 d, d = 1 .. n_len (a DFT length
+    per DM trial, App. A.3), each from its definition."""
+    return [preintegrate(s, n0 * d, L, kmax) for d in range(1, n_len + 1)]
+
+
+def _smallest_prime(x):
+    p = 2
+    while p * p <= x:
+        if x % p == 0:
+            return p
+        p += 1
+    return x
+
+
+def bank_factorised(s, n0, n_len, L, kmax):
+    """The same bank with App. A.3's factorisation at block resolution: a bin k of
+    length n0 d with p = the smallest prime factor of gcd(|k|, d) > 1 is the sum of
+    the p windows of bin k / p of length n0 d / p that tile its window; with each
+    length's output starting at its first complete window, window w of length d
+    takes windows w + (p - 1 - j) n0 (d / p) / L, j < p, of length d / p."""
+    ks = bins(kmax)
+    out = []
+    for d in range(1, n_len + 1):
+        full = preintegrate(s, n0 * d, L, kmax)
+        for j, k in enumerate(ks):
+            g = math.gcd(abs(int(k)), d)
+            if g == 1:
+                continue
+            p = _smallest_prime(g)
+            short, rs = out[d // p - 1], n0 * (d // p) // L
+            for w in range(full.shape[0]):
+                full[w, :, j] = sum(short[w + (p - 1 - i) * rs, :, kmax + int(k) // p] for i in range(p))
+        out.append(full)
+    return out

@@ -94,6 +94,13 @@ SIGNATURES = {
     "ddx_chirp_preintegrate": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p], ct.c_int),
     "ddx_chirp_destroy": ([ct.c_void_p], ct.c_int),
     "ddx_chirp_last_error": ([ct.c_void_p], ct.c_char_p),
+    "ddx_chirp_bank_create": ([ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int64,
+                               ct.POINTER(ct.c_void_p)], ct.c_int),
+    "ddx_chirp_bank_layout": ([ct.c_void_p, ct.c_int64, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64),
+                               ct.POINTER(ct.c_int64)], ct.c_int),
+    "ddx_chirp_bank_run": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p], ct.c_int),
+    "ddx_chirp_bank_destroy": ([ct.c_void_p], ct.c_int),
+    "ddx_chirp_bank_last_error": ([ct.c_void_p], ct.c_char_p),
     "ddx_plan_destroy": ([ct.c_void_p], ct.c_int),
     "ddx_strerror": ([ct.c_int], ct.c_char_p),
     "ddx_last_error": ([ct.c_void_p], ct.c_char_p),
@@ -428,6 +435,62 @@ class Chirp:
     def close(self):
         if getattr(self, "_h", None):
             lib().ddx_chirp_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ChirpBank:
+    """The bank of pre-integrators over window lengths n0 d, d = 1..n_len, with the
+    DFT factorisation of include/ddx.h (ddx_chirp_bank_*)."""
+
+    def __init__(self, n_ant, n0, n_len, block_len, kmax, max_samples):
+        h = ct.c_void_p()
+        rc = lib().ddx_chirp_bank_create(n_ant, n0, n_len, block_len, kmax, max_samples, ct.byref(h))
+        if rc != OK:
+            raise DdxError(rc, "ddx_chirp_bank_create")
+        self._h = h
+        self.n_ant, self.n0, self.n_len, self.block_len, self.kmax = n_ant, n0, n_len, block_len, kmax
+
+    def _check(self, rc, what):
+        if rc != OK:
+            raise DdxError(rc, "%s: %s" % (what, lib().ddx_chirp_bank_last_error(self._h).decode()))
+
+    def layout(self, n):
+        w = (ct.c_int64 * self.n_len)()
+        o = (ct.c_int64 * self.n_len)()
+        t = ct.c_int64()
+        self._check(lib().ddx_chirp_bank_layout(self._h, int(n), w, o, ct.byref(t)), "ddx_chirp_bank_layout")
+        return list(w), list(o), t.value
+
+    def run(self, volts, out=None, stream=None):
+        """volts: device complex64 [M, n]; returns a list of device views [windows_d, pairs, bins], d = 1..n_len."""
+        import torch
+        if volts.dtype != torch.complex64 or volts.dim() != 2 or volts.shape[0] != self.n_ant:
+            raise DdxError(EINVAL, "volts must be complex64 [%d, n]" % self.n_ant)
+        volts = volts.contiguous()
+        n = volts.shape[1]
+        wins, offs, total = self.layout(n)
+        if out is None:
+            out = torch.empty(max(total, 1), dtype=torch.complex64, device=volts.device)
+        self._check(lib().ddx_chirp_bank_run(self._h, ct.c_void_p(volts.data_ptr()), n, ct.c_void_p(out.data_ptr()),
+                                             _stream_handle(stream)), "ddx_chirp_bank_run")
+        pairs, bins = self.n_ant * (self.n_ant - 1) // 2, 2 * self.kmax + 1
+        return [out[o:o + w * pairs * bins].view(w, pairs, bins) for w, o in zip(wins, offs)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ddx_chirp_bank_destroy(self._h)
             self._h = None
 
     def __enter__(self):

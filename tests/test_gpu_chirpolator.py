@@ -1,7 +1,9 @@
 """GPU parity of the Chirpolator pre-integrator (ddx_chirp_*, Sec. 3.2 and App. A.3)
 against the FP64 oracle (oracle/chirpolator.py): ragged pair and bin tiles, block
 lengths that are not a multiple of the LDS chunk, a partial last block, L = 1 with a
-single bin, and the DFT of a mixed linear chirp against its closed form (Eq. phidn).
+single bin, the DFT of a mixed linear chirp against its closed form (Eq. phidn), and
+the bank of window lengths n0 d with the factorisation (ddx_chirp_bank_*) against
+every length computed from its definition.
 Bound: FP32 products and block sums, FP64 moving sum -> 1e-5 of the output's RMS."""
 import numpy as np
 import pytest
@@ -9,7 +11,7 @@ import torch
 
 from gpu_helpers import say
 from oracle import chirpolator as och
-from paper_1109_3186_amd import Chirp
+from paper_1109_3186_amd import Chirp, ChirpBank
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -74,3 +76,22 @@ def test_short_stream_and_bad_arguments(gpu):
             c.preintegrate(torch.zeros((3, 1001), dtype=torch.complex64, device="cuda:0"))
         with pytest.raises(DdxError):
             c.preintegrate(torch.zeros((2, 100), dtype=torch.complex64, device="cuda:0"))
+
+
+@pytest.mark.parametrize("m_ant,n0,n_len,L,kmax", [(4, 24, 6, 8, 5), (10, 64, 8, 16, 20), (3, 8, 12, 8, 3)])
+def test_bank_matches_oracle(gpu, m_ant, n0, n_len, L, kmax):
+    nb = n0 * n_len // L + 7
+    s = synth.noise_complex(np.random.Generator(np.random.PCG64(98 + m_ant)), (m_ant, nb * L + 3))
+    say("chirpolator bank: M %d n0 %d lengths %d L %d kmax %d" % (m_ant, n0, n_len, L, kmax))
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(np.ascontiguousarray(s.astype(np.complex64))).to(dev)
+    with ChirpBank(m_ant, n0, n_len, L, kmax, max_samples=s.shape[1]) as b:
+        outs = b.run(x)
+        torch.cuda.synchronize()
+        got = [o.cpu().numpy() for o in outs]
+    ref = och.bank_direct(s, n0, n_len, L, kmax)
+    for d, (g, r) in enumerate(zip(got, ref), start=1):
+        assert g.shape == r.shape, d
+        err = np.max(np.abs(g - r)) / np.sqrt(np.mean(np.abs(r) ** 2))
+        assert err <= TOL, (d, err)
+    say("bank: all %d lengths within %.0e" % (n_len, TOL))

@@ -125,3 +125,18 @@ def test_preintegrate_shape_and_pairs():
     p, q = ch.pairs(m_ant)[4]
     ref = ch.sliding_dft(ch.mix(s, p, q), n_win, L, ch.bins(kmax))[n_win // L - 1:]
     np.testing.assert_allclose(out[:, 4], ref, atol=1e-11)
+
+
+def test_bank_factorisation_at_block_resolution():
+    """The bank built with App. A.3's factorisation (block-resolution window offsets)
+    equals every length computed from its definition; at these sizes 23 of the
+    6 x 11 (d, k) bins are factorised (d = 2: 5, 3: 3, 4: 5, 5: 3, 6: 7)."""
+    m_ant, n0, n_len, L, kmax = 3, 12, 6, 4, 5
+    s = synth.noise_complex(_rng(6), (m_ant, (n0 * n_len // L + 5) * L))
+    direct = ch.bank_direct(s, n0, n_len, L, kmax)
+    fact = ch.bank_factorised(s, n0, n_len, L, kmax)
+    for a, b in zip(direct, fact):
+        assert a.shape == b.shape
+        np.testing.assert_allclose(b, a, atol=1e-10)
+    n_fact = sum(1 for d in range(1, n_len + 1) for k in range(-kmax, kmax + 1) if math.gcd(abs(k), d) > 1)
+    assert n_fact == 23
