@@ -179,8 +179,27 @@ def run_chirp(args, dev):
     # per (pair, sample, k > 0), two for k = 0
     flops = 2.0 * pairs * nb * L * (4 * kmax + 2)
     tf = flops / (ev_ms / 1e3) / 1e12
+    # per-pair bin budgets from the array geometry: 36 antennas in a 3 km-radius disk,
+    # budget ceil(kmax b_pq / b_max) (the tone of a pair sits at k0 = B tau, tau <= b / c)
+    import synth
+    pos = synth.antenna_positions(np.random.Generator(np.random.PCG64(36)), M, 3000.0)
+    blen = np.array([np.hypot(*(pos[p] - pos[q])) for p in range(M) for q in range(p + 1, M)])
+    budgets = np.minimum(kmax, np.ceil(kmax * blen / blen.max())).astype(np.int32)
+    c.set_pair_bins(budgets)
+    for _ in range(args.warmup):
+        c.preintegrate(volts, out=out)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    for _ in range(args.steps):
+        c.preintegrate(volts, out=out)
+    torch.cuda.synchronize()
+    ms_budget = (time.perf_counter() - tb) * 1e3 / args.steps
+    c.set_pair_bins(None)
+    budget_rec = {"mean_bins": round(float(np.mean(2 * budgets + 1)), 1), "ms": round(ms_budget, 2),
+                  "speedup": round(ms / ms_budget, 3)}
     c.close()
-    log("chirpolator: %.1f ms/step, %.3e pair-sample-bins/s, %.1f TFLOP/s" % (ms, value, tf))
+    log("chirpolator: %.1f ms/step, %.3e pair-sample-bins/s, %.1f TFLOP/s; with per-pair budgets (mean %.1f of %d "
+        "bins) %.1f ms" % (ms, value, tf, budget_rec["mean_bins"], 2 * kmax + 1, ms_budget))
     # the bank of lengths N0 d, d = 1..8 (N0 = N / 8), with the factorisation, against
     # the same eight lengths computed directly one by one
     import math
@@ -243,7 +262,7 @@ def run_chirp(args, dev):
            "roofline": {"bound": "alu", "achieved": round(tf, 2), "peak": PEAKS["fp32_vector_tflops"],
                         "unit": "TFLOP/s", "frac": round(tf / PEAKS["fp32_vector_tflops"], 4), "traffic": None,
                         "kernel": "partial DFT + block CIC (one call)", "avg_call_ms": round(ev_ms, 3)},
-           "cpu_baseline": cpu, "bank": bank_rec}
+           "cpu_baseline": cpu, "bank": bank_rec, "pair_budgets": budget_rec}
     print(json.dumps(rec), flush=True)
 
 

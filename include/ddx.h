@@ -339,6 +339,14 @@ int ddx_chirp_output_shape(const ddx_chirp* c, int64_t n, int64_t* n_windows, in
  * n outside [0, max_samples] or a NULL buffer, EDEVICE for launch failures. */
 int ddx_chirp_preintegrate(ddx_chirp* c, const void* d_volts, int64_t n, void* d_out, void* hip_stream);
 
+/* Per-pair bin budgets (Sec. "compute only DFTs required on a baseline basis"):
+ * kmax_pair [M (M-1) / 2] host array in pair order, 0 <= kmax_pair <= kmax, or NULL
+ * for kmax everywhere.  Bins |k| > kmax_pair of a pair are not computed and are
+ * written as zero.  Pairs are processed in descending budget order, so tiles of
+ * pairs whose budgets are all below a tile of bins are skipped.  Synchronises the
+ * device; EINVAL for an out-of-range budget. */
+int ddx_chirp_set_pair_bins(ddx_chirp* c, const int32_t* kmax_pair);
+
 /* Synchronises the device and frees the pre-integrator.  NULL is a no-op. */
 int ddx_chirp_destroy(ddx_chirp* c);
 const char* ddx_chirp_last_error(const ddx_chirp* c);
@@ -363,6 +371,9 @@ int ddx_chirp_bank_layout(const ddx_chirp_bank* b, int64_t n, int64_t* windows, 
 /* d_volts: DEVICE [M][n] complex64; d_out: DEVICE, *total complex64 in the layout
  * above.  Asynchronous on hip_stream.  Errors as for ddx_chirp_preintegrate. */
 int ddx_chirp_bank_run(ddx_chirp_bank* b, const void* d_volts, int64_t n, void* d_out, void* hip_stream);
+
+/* Per-pair bin budgets for every length of the bank, as ddx_chirp_set_pair_bins. */
+int ddx_chirp_bank_set_pair_bins(ddx_chirp_bank* b, const int32_t* kmax_pair);
 
 int ddx_chirp_bank_destroy(ddx_chirp_bank* b);
 const char* ddx_chirp_bank_last_error(const ddx_chirp_bank* b);

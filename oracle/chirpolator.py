@@ -89,17 +89,30 @@ def sliding_dft(x, n_win, L, ks):
     return out
 
 
-def preintegrate(s, n_win, L, kmax):
+def preintegrate(s, n_win, L, kmax, pair_kmax=None):
     """The pre-integrator on a stream: S[m, pair, k] for every pair p < q, every bin
-    -kmax..kmax and every block m whose window is complete (m >= N/L - 1)."""
+    -kmax..kmax and every block m whose window is complete (m >= N/L - 1).  With
+    per-pair budgets (App. A.3, "compute only DFTs required on a baseline basis")
+    the bins |k| > pair_kmax[pair] are left at zero."""
     ks = bins(kmax)
     prs = pairs(np.asarray(s).shape[0])
     first = n_win // L - 1
     out = []
-    for p, q in prs:
+    for i, (p, q) in enumerate(prs):
         v = block_partial_dft(mix(s, p, q), n_win, L, ks)
-        out.append(block_cic(v, n_win, L)[first:])
+        sp = block_cic(v, n_win, L)[first:]
+        if pair_kmax is not None:
+            sp[:, np.abs(ks) > pair_kmax[i]] = 0
+        out.append(sp)
     return np.stack(out, axis=1)
+
+
+def pair_bin_budgets(positions, kmax):
+    """Bin budget per pair p < q proportional to the baseline length (the tone of a
+    pair sits at k0 = B tau with tau <= b_pq / c, Eq. f0): ceil(kmax b_pq / b_max)."""
+    pos = np.asarray(positions, dtype=np.float64)
+    b = np.array([np.hypot(*(pos[p] - pos[q])) for p, q in pairs(pos.shape[0])])
+    return np.minimum(kmax, np.ceil(kmax * b / b.max())).astype(np.int32)
 
 
 def dirichlet(x, n):

@@ -92,6 +92,8 @@ SIGNATURES = {
     "ddx_chirp_output_shape": ([ct.c_void_p, ct.c_int64, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32),
                                 ct.POINTER(ct.c_int32)], ct.c_int),
     "ddx_chirp_preintegrate": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p], ct.c_int),
+    "ddx_chirp_set_pair_bins": ([ct.c_void_p, ct.POINTER(ct.c_int32)], ct.c_int),
+    "ddx_chirp_bank_set_pair_bins": ([ct.c_void_p, ct.POINTER(ct.c_int32)], ct.c_int),
     "ddx_chirp_destroy": ([ct.c_void_p], ct.c_int),
     "ddx_chirp_last_error": ([ct.c_void_p], ct.c_char_p),
     "ddx_chirp_bank_create": ([ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int64,
@@ -409,6 +411,15 @@ class Chirp:
         if rc != OK:
             raise DdxError(rc, "%s: %s" % (what, lib().ddx_chirp_last_error(self._h).decode()))
 
+    def set_pair_bins(self, kmax_pair=None):
+        """Per-pair bin budgets (row-major pair order), None = kmax for every pair."""
+        if kmax_pair is None:
+            self._check(lib().ddx_chirp_set_pair_bins(self._h, None), "ddx_chirp_set_pair_bins")
+            return
+        a = np.ascontiguousarray(kmax_pair, dtype=np.int32)
+        self._check(lib().ddx_chirp_set_pair_bins(self._h, a.ctypes.data_as(ct.POINTER(ct.c_int32))),
+                    "ddx_chirp_set_pair_bins")
+
     def output_shape(self, n):
         w, p, b = ct.c_int64(), ct.c_int32(), ct.c_int32()
         self._check(lib().ddx_chirp_output_shape(self._h, int(n), ct.byref(w), ct.byref(p), ct.byref(b)),
@@ -465,6 +476,15 @@ class ChirpBank:
     def _check(self, rc, what):
         if rc != OK:
             raise DdxError(rc, "%s: %s" % (what, lib().ddx_chirp_bank_last_error(self._h).decode()))
+
+    def set_pair_bins(self, kmax_pair=None):
+        """Per-pair bin budgets for every length (row-major pair order), None = kmax."""
+        if kmax_pair is None:
+            self._check(lib().ddx_chirp_bank_set_pair_bins(self._h, None), "ddx_chirp_bank_set_pair_bins")
+            return
+        a = np.ascontiguousarray(kmax_pair, dtype=np.int32)
+        self._check(lib().ddx_chirp_bank_set_pair_bins(self._h, a.ctypes.data_as(ct.POINTER(ct.c_int32))),
+                    "ddx_chirp_bank_set_pair_bins")
 
     def layout(self, n):
         w = (ct.c_int64 * self.n_len)()

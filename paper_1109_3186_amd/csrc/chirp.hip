@@ -41,7 +41,9 @@ struct PartialArgs {
   const float2* w;        // [L_pad][K_pad] (c, d) of w_k[n] = c - i d, k = klist[j]
   const float2* ph;       // [R][K_pad] (c, d) of the block phase of bin klist[j]
   const int2* cols;       // [n_list] columns of V for +k and -k (-1: none, k = 0)
-  float2* v;              // [nb][nbl][Kc] partial DFTs
+  const int* klist;       // [n_list] the listed bins k >= 0, ascending
+  const int* tile_bins;   // [n_ptiles] largest bin budget of a pair tile
+  float2* v;              // [nb][nbl][Kc] partial DFTs (pairs in budget order)
   int64_t n_samp;         // samples per antenna row of s
   int32_t nbl, n_list, Kc, K_pad, L, R, n_ptiles, n_ktiles;
 };
@@ -57,6 +59,9 @@ __global__ __launch_bounds__(256) void k_partial(PartialArgs a) {
   const int pt = (blockIdx.x / a.n_ktiles) % a.n_ptiles;
   const int m = blockIdx.x / (a.n_ktiles * a.n_ptiles);
   const int p0 = pt * kTileP, k0 = kt * kTileK;
+  // pairs are sorted by bin budget: a tile whose smallest bin exceeds every budget
+  // of its pairs has nothing to compute (the CIC writes those bins as zero)
+  if (k0 < a.n_list && a.klist[k0] > a.tile_bins[pt]) return;
   const int tp = tid >> 4, tk = tid & 15;
   const int64_t base = (int64_t)m * a.L;
   float4 acc[4][4];  // (P, Q, R, T) per pair and bin pair
@@ -137,12 +142,19 @@ __global__ __launch_bounds__(256) void k_partial(PartialArgs a) {
 // blocks before it, then follows the recursion.
 // grid: (ceil(cols / 256), ceil(nb / seg)) x 256.
 __global__ __launch_bounds__(256) void k_cic(const float2* __restrict__ v, float2* __restrict__ out,
-                                             const int* __restrict__ cmap, int64_t cols, int32_t Kc, int32_t K,
+                                             const int* __restrict__ cmap, const int* __restrict__ perm,
+                                             const int* __restrict__ budget, int64_t cols, int32_t Kc, int32_t K,
                                              int32_t nb, int32_t R, int32_t seg) {
   const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (c >= cols) return;
-  const int64_t oc = (c / Kc) * K + cmap[c % Kc];  // (pair, bin) of out
-  const int64_t orow = (int64_t)(cols / Kc) * K;   // out elements per window
+  const int sp = (int)(c / Kc), bin = cmap[c % Kc];      // pair in budget order, output bin index
+  const int64_t oc = (int64_t)perm[sp] * K + bin;       // (pair, bin) of out
+  const int64_t orow = (int64_t)(cols / Kc) * K;        // out elements per window
+  if (abs(bin - (K - 1) / 2) > budget[sp]) {            // beyond the pair's bin budget: zero
+    for (int m = max(R - 1, (int)blockIdx.y * seg); m < min(nb, ((int)blockIdx.y + 1) * seg); ++m)
+      out[(int64_t)(m - R + 1) * orow + oc] = make_float2(0.f, 0.f);
+    return;
+  }
   const int m0 = blockIdx.y * seg, m1 = min(nb, m0 + seg);
   double re = 0.0, im = 0.0;
   for (int m = max(0, m0 - R); m < m0; ++m) {
@@ -171,8 +183,9 @@ __global__ __launch_bounds__(256) void k_cic(const float2* __restrict__ v, float
 // length d / p (Rs = its N / L).  items: (k, p) of the bins formed this way.
 // grid: ceil(windows nbl n_items / 256) x 256.
 __global__ __launch_bounds__(256) void k_factor(const float2* __restrict__ src, float2* __restrict__ dst,
-                                                const int2* __restrict__ items, int32_t n_items, int64_t windows,
-                                                int32_t nbl, int32_t K, int32_t kmax, int32_t Rs) {
+                                                const int2* __restrict__ items, const int* __restrict__ budget_canon,
+                                                int32_t n_items, int64_t windows, int32_t nbl, int32_t K, int32_t kmax,
+                                                int32_t Rs) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= windows * nbl * n_items) return;
   const int it = (int)(t % n_items);
@@ -180,6 +193,10 @@ __global__ __launch_bounds__(256) void k_factor(const float2* __restrict__ src, 
   const int pair = (int)(wp % nbl);
   const int64_t w = wp / nbl;
   const int2 kp = items[it];
+  if (abs(kp.x) > budget_canon[pair]) {  // beyond the pair's bin budget
+    dst[(w * nbl + pair) * K + kmax + kp.x] = make_float2(0.f, 0.f);
+    return;
+  }
   const int ks = kmax + kp.x / kp.y;
   double re = 0.0, im = 0.0;
   for (int j = 0; j < kp.y; ++j) {
@@ -202,12 +219,17 @@ struct Stage {
   float2* ph = nullptr;  // [R][K_pad]
   int2* cols = nullptr;  // [n_list]
   int* cmap = nullptr;   // [Kc] output bin index of each column of V
+  int* klist = nullptr;  // [n_list] the listed bins k >= 0
 };
 
 struct Common {
   int M = 0, L = 0, kmax = 0, K = 0, L_pad = 0, nbl = 0;
   int64_t max_samples = 0, max_blocks = 0;
-  int2* pq = nullptr;
+  int2* pq = nullptr;           // [nbl] pairs in budget order (descending)
+  int* perm = nullptr;          // [nbl] budget order -> row-major pair index
+  int* budget = nullptr;        // [nbl] bin budget, budget order
+  int* budget_canon = nullptr;  // [nbl] bin budget, row-major pair order
+  int* tile_bins = nullptr;     // [pair tiles] largest budget of the tile
   float2* v = nullptr;   // [max_blocks][nbl][max Kc]
   std::vector<void*> allocs;
   std::string err;
@@ -278,7 +300,7 @@ int make_stage(Common& c, int n, const std::vector<int>& klist, Stage& st) {
   st.Kc = (int)cmap.size();
   int rc;
   if ((rc = upload(c, &st.w, w)) || (rc = upload(c, &st.ph, ph)) || (rc = upload(c, &st.cols, cols)) ||
-      (rc = upload(c, &st.cmap, cmap)))
+      (rc = upload(c, &st.cmap, cmap)) || (rc = upload(c, &st.klist, klist.empty() ? std::vector<int>{0} : klist)))
     return rc;
   return DDX_OK;
 }
@@ -295,8 +317,13 @@ int make_common(Common& c, int n_ant, int block_len, int kmax, int64_t max_sampl
   std::vector<int2> pq;
   for (int p = 0; p < n_ant; ++p)
     for (int q = p + 1; q < n_ant; ++q) pq.push_back(make_int2(p, q));
+  std::vector<int> perm(c.nbl), budget(c.nbl, kmax);
+  for (int i = 0; i < c.nbl; ++i) perm[i] = i;
+  std::vector<int> tiles((c.nbl + chirp::kTileP - 1) / chirp::kTileP, kmax);
   int rc;
-  if ((rc = upload(c, &c.pq, pq))) return rc;
+  if ((rc = upload(c, &c.pq, pq)) || (rc = upload(c, &c.perm, perm)) || (rc = upload(c, &c.budget, budget)) ||
+      (rc = upload(c, &c.budget_canon, budget)) || (rc = upload(c, &c.tile_bins, tiles)))
+    return rc;
   const size_t vb = (size_t)c.max_blocks * c.nbl * max_kc * sizeof(float2);
   if (hipMalloc((void**)&c.v, std::max<size_t>(vb, 256)) != hipSuccess) {
     (void)hipGetLastError();
@@ -316,6 +343,8 @@ int run_stage(Common& c, const Stage& st, const float2* volts, int64_t n, float2
   a.w = st.w;
   a.ph = st.ph;
   a.cols = st.cols;
+  a.klist = st.klist;
+  a.tile_bins = c.tile_bins;
   a.v = c.v;
   a.n_samp = n;
   a.nbl = c.nbl;
@@ -335,8 +364,8 @@ int run_stage(Common& c, const Stage& st, const float2* volts, int64_t n, float2
   // segments of at least 256 blocks (the R-block restart costs R / seg extra reads), at most 65535
   const int64_t seg = std::max<int64_t>(256, (nb + 65534) / 65535);
   hipLaunchKernelGGL(chirp::k_cic, dim3((unsigned)((cols + 255) / 256), (unsigned)((nb + seg - 1) / seg)), dim3(256), 0,
-                     s, (const float2*)c.v, out, (const int*)st.cmap, cols, (int32_t)st.Kc, (int32_t)c.K,
-                     (int32_t)nb, (int32_t)st.R, (int32_t)seg);
+                     s, (const float2*)c.v, out, (const int*)st.cmap, (const int*)c.perm, (const int*)c.budget, cols,
+                     (int32_t)st.Kc, (int32_t)c.K, (int32_t)nb, (int32_t)st.R, (int32_t)seg);
   e = hipGetLastError();
   if (e != hipSuccess) return cfail(&c.err, DDX_EDEVICE, "k_cic: %s", hipGetErrorString(e));
   return DDX_OK;
@@ -346,6 +375,39 @@ int smallest_prime_factor(int x) {
   for (int p = 2; p * p <= x; ++p)
     if (x % p == 0) return p;
   return x;
+}
+
+// Per-pair bin budgets (NULL: kmax for every pair): pairs sorted by budget,
+// descending and stable, for the tile skip of k_partial; synchronous uploads.
+int set_budgets(Common& c, const int32_t* host) {
+  std::vector<int> budget(c.nbl, c.kmax);
+  if (host)
+    for (int i = 0; i < c.nbl; ++i) {
+      if (host[i] < 0 || host[i] > c.kmax) return cfail(&c.err, DDX_EINVAL, "pair %d: bin budget %d not in [0, %d]", i, host[i], c.kmax);
+      budget[i] = host[i];
+    }
+  std::vector<int> perm(c.nbl);
+  for (int i = 0; i < c.nbl; ++i) perm[i] = i;
+  std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return budget[x] > budget[y]; });
+  std::vector<int2> rowmajor, pq(c.nbl);
+  for (int p = 0; p < c.M; ++p)
+    for (int q = p + 1; q < c.M; ++q) rowmajor.push_back(make_int2(p, q));
+  std::vector<int> bs(c.nbl), tiles((c.nbl + chirp::kTileP - 1) / chirp::kTileP, 0);
+  for (int i = 0; i < c.nbl; ++i) {
+    pq[i] = rowmajor[perm[i]];
+    bs[i] = budget[perm[i]];
+    tiles[i / chirp::kTileP] = std::max(tiles[i / chirp::kTileP], bs[i]);
+  }
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(c.pq, pq.data(), pq.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c.perm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c.budget, bs.data(), bs.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c.budget_canon, budget.data(), budget.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c.tile_bins, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    return cfail(&c.err, DDX_EDEVICE, "bin budget upload failed");
+  }
+  return DDX_OK;
 }
 
 }  // namespace
@@ -403,6 +465,16 @@ int ddx_chirp_preintegrate(ddx_chirp* h, const void* d_volts, int64_t n, void* d
   if (n / h->c.L < h->st.R) return DDX_OK;  // no complete window
   if (!d_volts || !d_out) return cfail(&h->c.err, DDX_EINVAL, "NULL device buffer");
   return run_stage(h->c, h->st, (const float2*)d_volts, n, (float2*)d_out, (hipStream_t)hip_stream);
+}
+
+int ddx_chirp_set_pair_bins(ddx_chirp* h, const int32_t* kmax_pair) {
+  if (!h) return DDX_EINVAL;
+  return set_budgets(h->c, kmax_pair);
+}
+
+int ddx_chirp_bank_set_pair_bins(ddx_chirp_bank* b, const int32_t* kmax_pair) {
+  if (!b) return DDX_EINVAL;
+  return set_budgets(b->c, kmax_pair);
 }
 
 const char* ddx_chirp_last_error(const ddx_chirp* h) { return h ? h->c.err.c_str() : "NULL pre-integrator"; }
@@ -502,7 +574,8 @@ int ddx_chirp_bank_run(ddx_chirp_bank* b, const void* d_volts, int64_t n, void* 
       const int64_t threads = win[d - 1] * b->c.nbl * ni;
       hipLaunchKernelGGL(chirp::k_factor, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
                          (const float2*)(out + off[d / p - 1]), out + off[d - 1], (const int2*)b->fac[d - 1][g].second,
-                         (int32_t)ni, win[d - 1], (int32_t)b->c.nbl, (int32_t)b->c.K, (int32_t)b->c.kmax,
+                         (const int*)b->c.budget_canon, (int32_t)ni, win[d - 1], (int32_t)b->c.nbl, (int32_t)b->c.K,
+                         (int32_t)b->c.kmax,
                          (int32_t)((int64_t)b->n0 * (d / p) / b->c.L));
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return cfail(&b->c.err, DDX_EDEVICE, "k_factor: %s", hipGetErrorString(e));

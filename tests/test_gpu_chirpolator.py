@@ -95,3 +95,59 @@ def test_bank_matches_oracle(gpu, m_ant, n0, n_len, L, kmax):
         err = np.max(np.abs(g - r)) / np.sqrt(np.mean(np.abs(r) ** 2))
         assert err <= TOL, (d, err)
     say("bank: all %d lengths within %.0e" % (n_len, TOL))
+
+
+def _run_budget(s, n_win, L, kmax, budgets):
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(np.ascontiguousarray(s.astype(np.complex64))).to(dev)
+    with Chirp(s.shape[0], n_win, L, kmax, max_samples=s.shape[1]) as c:
+        c.set_pair_bins(budgets)
+        out = c.preintegrate(x)
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("kind", ["geometry", "two_groups"])
+def test_pair_bin_budgets(gpu, kind):
+    """Per-pair bin budgets: bins beyond a pair's budget are exactly zero, the others
+    equal the oracle; 'two_groups' makes whole (pair tile, bin tile) blocks skip."""
+    m_ant, n_win, L, kmax = 20, 192, 32, 70
+    rng = np.random.Generator(np.random.PCG64(120))
+    s = synth.noise_complex(rng, (m_ant, (n_win // L + 6) * L + 11))
+    nbl = m_ant * (m_ant - 1) // 2
+    if kind == "geometry":
+        budgets = och.pair_bin_budgets(synth.antenna_positions(rng, m_ant, 3000.0), kmax)
+    else:
+        budgets = np.full(nbl, 5, dtype=np.int32)
+        budgets[rng.permutation(nbl)[:64]] = kmax
+    got = _run_budget(s, n_win, L, kmax, budgets)
+    ref = och.preintegrate(s, n_win, L, kmax, pair_kmax=budgets)
+    ks = och.bins(kmax)
+    beyond = np.abs(ks)[None, :] > budgets[:, None]
+    assert np.all(got[:, beyond] == 0)
+    err = np.max(np.abs(got - ref)) / np.sqrt(np.mean(np.abs(ref[:, ~beyond]) ** 2))
+    say("budgets (%s): %d of %d pair-bins computed, max error / rms %.3e" % (kind, (~beyond).sum(), beyond.size, err))
+    assert err <= TOL
+
+
+def test_bank_with_pair_bin_budgets(gpu):
+    m_ant, n0, n_len, L, kmax = 10, 64, 8, 16, 20
+    rng = np.random.Generator(np.random.PCG64(121))
+    s = synth.noise_complex(rng, (m_ant, (n0 * n_len // L + 5) * L))
+    budgets = rng.integers(0, kmax + 1, m_ant * (m_ant - 1) // 2).astype(np.int32)
+    x = torch.from_numpy(np.ascontiguousarray(s.astype(np.complex64))).to("cuda:0")
+    with ChirpBank(m_ant, n0, n_len, L, kmax, max_samples=s.shape[1]) as b:
+        b.set_pair_bins(budgets)
+        got = [o.cpu().numpy() for o in b.run(x)]
+    for d, g in enumerate(got, start=1):
+        ref = och.preintegrate(s, n0 * d, L, kmax, pair_kmax=budgets)
+        err = np.max(np.abs(g - ref)) / np.sqrt(np.mean(np.abs(ref) ** 2))
+        assert err <= TOL, (d, err)
+
+
+def test_pair_bin_budget_rejected(gpu):
+    from paper_1109_3186_amd import DdxError
+    with Chirp(3, 64, 16, 4, max_samples=1000) as c:
+        with pytest.raises(DdxError):
+            c.set_pair_bins(np.array([4, 5, 1], dtype=np.int32))
+        c.set_pair_bins(None)
