@@ -176,3 +176,17 @@ def test_chirp_create_rejects_invalid_arguments():
     assert L.ddx_chirp_create(4, 64, 16, 4, ct.c_int64(1000), None) == binding.EINVAL
     assert L.ddx_chirp_destroy(None) == binding.OK
     assert L.ddx_chirp_preintegrate(None, None, ct.c_int64(0), None, None) == binding.EINVAL
+
+
+def test_chirp_bank_create_rejects_invalid_arguments():
+    L = ct.CDLL(ddx.LIB_PATH)
+    for args in [(1, 64, 4, 16, 4, 1000), (4, 60, 4, 16, 4, 1000), (4, 64, 0, 16, 4, 1000), (4, 64, 65, 16, 4, 10 ** 6),
+                 (4, 64, 4, 16, 40, 1000), (4, 64, 4, 16, 4, 255)]:
+        h = ct.c_void_p()
+        rc = L.ddx_chirp_bank_create(*[ct.c_int32(a) for a in args[:5]], ct.c_int64(args[5]), ct.byref(h))
+        assert rc == binding.EINVAL, args
+        assert not h.value
+    assert L.ddx_chirp_bank_destroy(None) == binding.OK
+    assert L.ddx_chirp_bank_run(None, None, ct.c_int64(0), None, None) == binding.EINVAL
+    assert L.ddx_chirp_bank_set_pair_bins(None, None) == binding.EINVAL
+    assert L.ddx_chirp_set_pair_bins(None, None) == binding.EINVAL
