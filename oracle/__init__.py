@@ -17,7 +17,10 @@ what Bannister & Cornwell (2011), "The Chirpolator and The Chimageator", define:
 * in ``oracle.chirpolator``, the Chirpolator pre-integrator itself (Sec. 3.2,
   App. A.3): mixing of antenna pairs, block partial DFTs over the bins
   |k| <= kmax, the block CIC moving sum, the closed form of a mixed chirp's DFT,
-  the DFT factorisation across lengths and the shared negative-bin products.
+  the DFT factorisation across lengths and the shared negative-bin products;
+* in ``oracle.imaging``, the post-integrator detection image P(theta) and
+  E(theta) (Sec. 3.3, 3.4, App. A.1): 3-D baseline delays, the tone bin k0',
+  the matched filter over 2F + 1 bins and the vector sum over pairs.
 
 Everything is numpy in float64 / complex128.  The oracle shares no code with the
 GPU path; only the seeded input generators (package ``synth``) serve both.
