@@ -198,6 +198,7 @@ def run_chirp(args, dev):
     budget_rec = {"mean_bins": round(float(np.mean(2 * budgets + 1)), 1), "ms": round(ms_budget, 2),
                   "speedup": round(ms / ms_budget, 3)}
     c.close()
+    image_rec = image_leg(args, dev, out, pos, N, L, kmax)
     log("chirpolator: %.1f ms/step, %.3e pair-sample-bins/s, %.1f TFLOP/s; with per-pair budgets (mean %.1f of %d "
         "bins) %.1f ms" % (ms, value, tf, budget_rec["mean_bins"], 2 * kmax + 1, ms_budget))
     # the bank of lengths N0 d, d = 1..8 (N0 = N / 8), with the factorisation, against
@@ -262,8 +263,65 @@ def run_chirp(args, dev):
            "roofline": {"bound": "alu", "achieved": round(tf, 2), "peak": PEAKS["fp32_vector_tflops"],
                         "unit": "TFLOP/s", "frac": round(tf / PEAKS["fp32_vector_tflops"], 4), "traffic": None,
                         "kernel": "partial DFT + block CIC (one call)", "avg_call_ms": round(ev_ms, 3)},
-           "cpu_baseline": cpu, "bank": bank_rec, "pair_budgets": budget_rec}
+           "cpu_baseline": cpu, "bank": bank_rec, "pair_budgets": budget_rec, "image": image_rec}
     print(json.dumps(rec), flush=True)
+
+
+def image_leg(args, dev, bins, pos2d, N, L, kmax):
+    """The post-integrator image (Sec. 3.3, 3.4, App. A.1) on the pre-integrator's
+    output: 256 x 256 directions over +-0.01 in l and m (16 x 16 tiles), F = 2, one
+    image every 16 windows (4 per window length), the 36-antenna disk with heights
+    of +-20 m; the chirp rate puts the longest baseline's tone at bin kmax - F at
+    the field's corner.  Timed with HIP events on the launch stream; the weights
+    are made once per plan, outside the timed region."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1109_3186_amd import Image
+    F, n_side, lmax, w_step, f_s = 2, 256, 0.01, 16, 1e6
+    M = pos2d.shape[0]
+    heights = np.random.Generator(np.random.PCG64(37)).uniform(-20.0, 20.0, M)
+    ant = np.concatenate([pos2d, heights[:, None]], axis=1)
+    b_max = max(np.linalg.norm(ant[p] - ant[q]) for p in range(M) for q in range(p + 1, M))
+    fdot = (kmax - F) * f_s * 299792458.0 / (N * b_max * lmax * np.sqrt(2.0))
+    pix = synth.direction_grid(lmax, n_side)
+    h = Image(ant, pix, fdot, f_s, N, L, kmax, F)
+    n_img = h.output_count(bins.shape[0], w_step)
+    for _ in range(args.warmup):
+        h.run(bins, w_step=w_step)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        h.run(bins, w_step=w_step)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    h.close()
+    pairs = M * (M - 1) // 2
+    terms = float(pix.shape[0]) * pairs * n_img * (2 * F + 1)
+    tf = 8.0 * terms / (ms / 1e3) / 1e12   # one complex multiply-add per tap
+    log("image: %d directions x %d images, F %d: %.2f ms, %.1f TFLOP/s" % (pix.shape[0], n_img, F, ms, tf))
+    rec = {"directions": int(pix.shape[0]), "images": int(n_img), "half_width": F, "w_step": w_step,
+           "ms_per_call": round(ms, 3), "direction_pair_images_per_s": pix.shape[0] * pairs * n_img / (ms / 1e3),
+           "roofline": {"bound": "alu", "achieved": round(tf, 2), "peak": PEAKS["fp32_vector_tflops"],
+                        "unit": "TFLOP/s", "frac": round(tf / PEAKS["fp32_vector_tflops"], 4), "traffic": None,
+                        "kernel": "k_image"}}
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import imaging as oim
+        sub = pix[:16]
+        rows = bins[:1].cpu().numpy().astype(np.complex128)
+        with threadpool_limits(1):
+            tc = time.perf_counter()
+            oim.image(rows, ant, sub, fdot, f_s, N, L, kmax, F)
+            tc = time.perf_counter() - tc
+        rec["cpu_baseline"] = {"value": sub.shape[0] * pairs / tc, "unit": "direction-pair-images/s", "cores": 1,
+                               "kind": "oracle", "sample": "16 directions x 1 image, FP64 numpy on one thread, "
+                                                           "%.1f s" % tc}
+    return rec
 
 
 def run_c3(args, dev):

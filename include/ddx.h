@@ -378,6 +378,54 @@ int ddx_chirp_bank_set_pair_bins(ddx_chirp_bank* b, const int32_t* kmax_pair);
 int ddx_chirp_bank_destroy(ddx_chirp_bank* b);
 const char* ddx_chirp_bank_last_error(const ddx_chirp_bank* b);
 
+/* ---- Post-integrator imaging (Sec. 3.3, 3.4, App. A.1) ----------------------
+ * The detection image of the Chirpolator from the pre-integrator's bins: for
+ * each window and each direction (l, m),
+ *   P = sum_{p<q} sum_{t=-F..F} conj(Phi_pq(x)) D_N(x) / N * X_pq[k0' + t],
+ *   E = |P|^2  (Eq. eth),
+ * with tau_pq = (u l + v m + w (n - 1)) / c for (u, v, w) = r_p - r_q (Eq. tau3D,
+ * n = sqrt(1 - l^2 - m^2), c = 299792458 m/s), k0 = fdot tau N / f_s (Eq. f0),
+ * k0' = rint(k0) (ties to even, FP64), x = k0' + t - k0, D_N of Eq. dn and
+ * Phi_pq(x) = exp(-pi i fdot tau (a_p + a_q)) exp(-pi i x (N - 1) / N) (Eq.
+ * phipq1, with a_p = -r_p . (l, m, n - 1) / c the delay of antenna p relative to
+ * the phase centre).  X_w[k] = S_w[k] exp(2 pi i w L k / N) re-references the
+ * pre-integrator's window w (which starts at sample w L; its bins are phase-
+ * referenced to sample 0) to its own first sample.  Bins |k| > kmax contribute
+ * nothing.  Pairs p < q in row-major order, as ddx_chirp_preintegrate writes.
+ * Directions are processed in tiles of 256 consecutive entries of pix_lm: list
+ * neighbouring directions together (e.g. 16 x 16 blocks of a grid) so that a
+ * tile reads few bins per pair. */
+typedef struct ddx_image ddx_image;
+
+/* ant_xyz: HOST [n_ant][3] antenna positions in metres (any common origin);
+ * pix_lm: HOST [n_pix][2] direction cosines with l^2 + m^2 < 1; fdot_hz_s: chirp
+ * rate; samp_rate_hz: f_s; fft_n: N; block_len: L (N / L <= 65535); kmax <= 1023
+ * with 2 kmax + 1 <= N: the bins of the input; half_width: F in 0..8.  Both host
+ * arrays are read during the call only.  Computes the weights on the device
+ * (synchronously) and keeps them: 8 (2F + 1) + 4 bytes per (pair, direction).
+ * DDX_EINVAL for invalid arguments, DDX_ENOMEM, DDX_EDEVICE. */
+int ddx_image_create(int32_t n_ant, const double* ant_xyz, int32_t n_pix, const double* pix_lm,
+                     double fdot_hz_s, double samp_rate_hz, int32_t fft_n, int32_t block_len,
+                     int32_t kmax, int32_t half_width, ddx_image** out);
+
+/* Images made by a run over n_rows input rows with step w_step: ceil(n_rows / w_step). */
+int ddx_image_output_count(const ddx_image* h, int64_t n_rows, int32_t w_step, int64_t* n_images);
+
+/* d_bins: DEVICE [n_rows][pairs][2 kmax + 1] complex64, row r = pre-integrator
+ * window first_window + r (a slice of ddx_chirp_preintegrate's output).  Images
+ * are made for rows 0, w_step, 2 w_step, ...: d_p DEVICE [n_images][n_pix]
+ * complex64 (P) and d_e DEVICE [n_images][n_pix] float (E); either may be NULL,
+ * not both.  Asynchronous on hip_stream; caller-owned buffers must stay valid
+ * until the stream passes this work.  n_rows = 0 is a no-op.  DDX_EINVAL for
+ * negative counts, w_step < 1 or NULL buffers; DDX_EUNSUPPORTED if the grid would
+ * exceed 2^31 workgroups; DDX_EDEVICE on a launch failure. */
+int ddx_image_run(ddx_image* h, const void* d_bins, int64_t n_rows, int64_t first_window, int32_t w_step,
+                  void* d_p, void* d_e, void* hip_stream);
+
+/* Synchronise the device and free the plan's memory.  NULL is a no-op. */
+int ddx_image_destroy(ddx_image* h);
+const char* ddx_image_last_error(const ddx_image* h);
+
 /* Synchronise the plan's last stream and free plan-owned memory.  NULL is a no-op. */
 int ddx_plan_destroy(ddx_plan* plan);
 

@@ -103,6 +103,14 @@ SIGNATURES = {
     "ddx_chirp_bank_run": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p], ct.c_int),
     "ddx_chirp_bank_destroy": ([ct.c_void_p], ct.c_int),
     "ddx_chirp_bank_last_error": ([ct.c_void_p], ct.c_char_p),
+    "ddx_image_create": ([ct.c_int32, ct.POINTER(ct.c_double), ct.c_int32, ct.POINTER(ct.c_double), ct.c_double,
+                          ct.c_double, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_void_p)],
+                         ct.c_int),
+    "ddx_image_output_count": ([ct.c_void_p, ct.c_int64, ct.c_int32, ct.POINTER(ct.c_int64)], ct.c_int),
+    "ddx_image_run": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int64, ct.c_int32, ct.c_void_p, ct.c_void_p,
+                       ct.c_void_p], ct.c_int),
+    "ddx_image_destroy": ([ct.c_void_p], ct.c_int),
+    "ddx_image_last_error": ([ct.c_void_p], ct.c_char_p),
     "ddx_plan_destroy": ([ct.c_void_p], ct.c_int),
     "ddx_strerror": ([ct.c_int], ct.c_char_p),
     "ddx_last_error": ([ct.c_void_p], ct.c_char_p),
@@ -511,6 +519,69 @@ class ChirpBank:
     def close(self):
         if getattr(self, "_h", None):
             lib().ddx_chirp_bank_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Image:
+    """The post-integrator detection image of include/ddx.h (ddx_image_*): P and
+    E = |P|^2 per window and direction from the pre-integrator's bins."""
+
+    def __init__(self, ant_xyz, pix_lm, fdot, samp_rate, fft_n, block_len, kmax, half_width):
+        ant = np.ascontiguousarray(ant_xyz, dtype=np.float64)
+        pix = np.ascontiguousarray(pix_lm, dtype=np.float64)
+        if ant.ndim != 2 or ant.shape[1] != 3 or pix.ndim != 2 or pix.shape[1] != 2:
+            raise DdxError(EINVAL, "ant_xyz must be [M, 3] and pix_lm [n_pix, 2]")
+        dp = ct.POINTER(ct.c_double)
+        h = ct.c_void_p()
+        rc = lib().ddx_image_create(ant.shape[0], ant.ctypes.data_as(dp), pix.shape[0], pix.ctypes.data_as(dp),
+                                    float(fdot), float(samp_rate), fft_n, block_len, kmax, half_width, ct.byref(h))
+        if rc != OK:
+            raise DdxError(rc, "ddx_image_create")
+        self._h = h
+        self.n_ant, self.n_pix, self.kmax = ant.shape[0], pix.shape[0], kmax
+
+    def _check(self, rc, what):
+        if rc != OK:
+            raise DdxError(rc, "%s: %s" % (what, lib().ddx_image_last_error(self._h).decode()))
+
+    def output_count(self, n_rows, w_step=1):
+        n = ct.c_int64()
+        self._check(lib().ddx_image_output_count(self._h, int(n_rows), int(w_step), ct.byref(n)),
+                    "ddx_image_output_count")
+        return n.value
+
+    def run(self, bins, first_window=0, w_step=1, want_p=True, want_e=True, stream=None):
+        """bins: device complex64 [rows, pairs, 2 kmax + 1] (pre-integrator windows
+        first_window ..); returns (P complex64 [images, n_pix] or None, E float32 or None)."""
+        import torch
+        pairs = self.n_ant * (self.n_ant - 1) // 2
+        if bins.dtype != torch.complex64 or bins.dim() != 3 or tuple(bins.shape[1:]) != (pairs, 2 * self.kmax + 1):
+            raise DdxError(EINVAL, "bins must be complex64 [rows, %d, %d]" % (pairs, 2 * self.kmax + 1))
+        bins = bins.contiguous()
+        n_img = self.output_count(bins.shape[0], w_step)
+        p = torch.empty((n_img, self.n_pix), dtype=torch.complex64, device=bins.device) if want_p else None
+        e = torch.empty((n_img, self.n_pix), dtype=torch.float32, device=bins.device) if want_e else None
+        self._check(lib().ddx_image_run(self._h, ct.c_void_p(bins.data_ptr()), bins.shape[0], int(first_window),
+                                        int(w_step), ct.c_void_p(p.data_ptr() if p is not None else None),
+                                        ct.c_void_p(e.data_ptr() if e is not None else None),
+                                        _stream_handle(stream)), "ddx_image_run")
+        return p, e
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ddx_image_destroy(self._h)
             self._h = None
 
     def __enter__(self):

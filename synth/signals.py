@@ -41,6 +41,19 @@ def antenna_positions(rng, m, radius_m):
     return np.stack([r * np.cos(th), r * np.sin(th)], axis=-1)
 
 
+def direction_grid(lmax, n, block=16):
+    """n x n direction cosines (l, m) evenly over [-lmax, lmax]^2, [n * n, 2], listed
+    in block x block tiles of neighbouring directions."""
+    ax = np.linspace(-lmax, lmax, n)
+    out = []
+    for bi in range(0, n, block):
+        for bj in range(0, n, block):
+            for i in range(bi, min(n, bi + block)):
+                for j in range(bj, min(n, bj + block)):
+                    out.append((ax[i], ax[j]))
+    return np.array(out, dtype=np.float64)
+
+
 def _smear(f_c, f_s, dm, k_dm):
     hi, lo = f_c + 0.5 * f_s, f_c - 0.5 * f_s
     early = k_dm * dm * (1.0 / (f_c * f_c) - 1.0 / (hi * hi)) * f_s

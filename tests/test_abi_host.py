@@ -190,3 +190,37 @@ def test_chirp_bank_create_rejects_invalid_arguments():
     assert L.ddx_chirp_bank_run(None, None, ct.c_int64(0), None, None) == binding.EINVAL
     assert L.ddx_chirp_bank_set_pair_bins(None, None) == binding.EINVAL
     assert L.ddx_chirp_set_pair_bins(None, None) == binding.EINVAL
+
+
+def test_image_create_rejects_invalid_arguments():
+    L = ct.CDLL(ddx.LIB_PATH)
+    dp = ct.POINTER(ct.c_double)
+    ant = np.zeros((4, 3))
+    ant[:, 0] = np.arange(4) * 100.0
+    pix = np.array([[0.01, 0.02], [0.0, 0.0]])
+    good = dict(n_ant=4, n_pix=2, fdot=1e10, fs=1e6, N=256, L=16, kmax=10, F=2)
+
+    def create(ant=ant, pix=pix, **kw):
+        a = dict(good, **kw)
+        h = ct.c_void_p()
+        ant = np.ascontiguousarray(ant, dtype=np.float64)
+        pix = np.ascontiguousarray(pix, dtype=np.float64)
+        rc = L.ddx_image_create(ct.c_int32(a["n_ant"]), ant.ctypes.data_as(dp), ct.c_int32(a["n_pix"]),
+                                pix.ctypes.data_as(dp), ct.c_double(a["fdot"]), ct.c_double(a["fs"]),
+                                ct.c_int32(a["N"]), ct.c_int32(a["L"]), ct.c_int32(a["kmax"]), ct.c_int32(a["F"]),
+                                ct.byref(h))
+        assert not h.value
+        return rc
+
+    for kw in [dict(n_ant=1), dict(n_pix=0), dict(N=250), dict(L=0), dict(kmax=-1), dict(kmax=1024, N=4096),
+               dict(kmax=200), dict(F=9), dict(F=-1), dict(fs=0.0), dict(fdot=float("inf")), dict(N=2 ** 20, L=8)]:
+        assert create(**kw) == binding.EINVAL, kw
+    assert create(pix=np.array([[0.8, 0.7], [0.0, 0.0]])) == binding.EINVAL   # l^2 + m^2 >= 1
+    assert create(pix=np.array([[np.nan, 0.0], [0.0, 0.0]])) == binding.EINVAL
+    bad = ant.copy()
+    bad[2, 1] = np.inf
+    assert create(ant=bad) == binding.EINVAL
+    assert L.ddx_image_destroy(None) == binding.OK
+    assert L.ddx_image_run(None, None, ct.c_int64(0), ct.c_int64(0), ct.c_int32(1), None, None, None) == binding.EINVAL
+    n = ct.c_int64()
+    assert L.ddx_image_output_count(None, ct.c_int64(5), ct.c_int32(2), ct.byref(n)) == binding.EINVAL
