@@ -399,7 +399,7 @@ typedef struct ddx_image ddx_image;
 
 /* ant_xyz: HOST [n_ant][3] antenna positions in metres (any common origin);
  * pix_lm: HOST [n_pix][2] direction cosines with l^2 + m^2 < 1; fdot_hz_s: chirp
- * rate; samp_rate_hz: f_s; fft_n: N; block_len: L (N / L <= 65535); kmax <= 1023
+ * rate; samp_rate_hz: f_s; fft_n: N; block_len: L (N / L <= 65535); kmax <= 640
  * with 2 kmax + 1 <= N: the bins of the input; half_width: F in 0..8.  Both host
  * arrays are read during the call only.  Computes the weights on the device
  * (synchronously) and keeps them: 8 (2F + 1) + 4 bytes per (pair, direction).

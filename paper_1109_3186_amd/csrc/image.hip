@@ -38,7 +38,8 @@ namespace img {
 
 constexpr int kPixTile = 256;            // directions per workgroup, one per thread
 constexpr int kMaxHalfWidth = 8;         // F <= 8: at most 17 taps
-constexpr int kLdsBytes = 64 * 1024;     // staged bins per workgroup
+constexpr int kLdsBytes = 64 * 1024;     // largest staging of one pair per workgroup
+constexpr int kLdsStage = 28 * 1024;     // staging target: five workgroups per CU
 constexpr double kLight = 299792458.0;   // m / s
 
 struct WeightArgs {
@@ -121,8 +122,27 @@ struct ImageArgs {
 };
 
 // grid: n_ptiles * ceil(n_img / WT) workgroups of 256 threads (window tile slowest);
-// dynamic LDS: pb pairs x WT windows x smax bins of float2.
+// one tap: acc[i] += w X[window i] for the WT windows of a staged bin
 template <int WT>
+__device__ __forceinline__ void mac_tap(float2 (&acc)[WT], float2 w, const float2* bin) {
+  const float4* col = reinterpret_cast<const float4*>(bin);
+#pragma unroll
+  for (int i = 0; i < WT; i += 2) {
+    const float4 x = col[i / 2];  // windows i and i + 1
+    acc[i].x = fmaf(w.x, x.x, fmaf(-w.y, x.y, acc[i].x));
+    acc[i].y = fmaf(w.x, x.y, fmaf(w.y, x.x, acc[i].y));
+    acc[i + 1].x = fmaf(w.x, x.z, fmaf(-w.y, x.w, acc[i + 1].x));
+    acc[i + 1].y = fmaf(w.x, x.w, fmaf(w.y, x.z, acc[i + 1].y));
+  }
+}
+
+// dynamic LDS: pb pairs x smax bins x (WT + 2) windows of float2: the windows of a bin
+// are adjacent, so a thread reads two windows per 16-byte load at fixed offsets, and
+// the 2-entry pad puts neighbouring bins 4 banks apart (no conflicts between the
+// bins that the lanes of a wave read).  TAPS > 0: the tap count is fixed and the
+// weights of the next pair are loaded while the current one is summed (the weights
+// stream from HBM once per window tile); TAPS = 0: any count, loaded at use.
+template <int WT, int TAPS>
 __global__ __launch_bounds__(256) void k_image(ImageArgs a) {
   extern __shared__ float2 xs[];
   __shared__ uint32_t wmod[WT];
@@ -136,6 +156,18 @@ __global__ __launch_bounds__(256) void k_image(ImageArgs a) {
 #pragma unroll
   for (int i = 0; i < WT; ++i) acc[i] = make_float2(0.f, 0.f);
   const int64_t row = (int64_t)a.nbl * a.K;  // elements per window row of s
+  constexpr int NT = TAPS > 0 ? TAPS : 1;
+  float2 wn[NT];  // weights and first bin of the next pair (TAPS > 0)
+  int jn = 0;
+  auto fetch = [&](int b) {
+    if (TAPS > 0 && live && b < a.nbl) {
+      jn = a.j0[(int64_t)b * a.n_pix + pix];
+      const float2* gp = a.g + (int64_t)b * TAPS * a.n_pix + pix;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) wn[t] = gp[(int64_t)t * a.n_pix];
+    }
+  };
+  fetch(0);
 
   for (int b0 = 0; b0 < a.nbl; b0 += a.pb) {
     const int nb = min(a.pb, a.nbl - b0);
@@ -144,7 +176,7 @@ __global__ __launch_bounds__(256) void k_image(ImageArgs a) {
     for (int sl = 0; sl < nb; ++sl) {
       const int b = b0 + sl;
       const int2 sp = a.span[(int64_t)b * a.n_ptiles + pt];
-      float2* dst = xs + (size_t)sl * WT * a.smax;
+      float2* dst = xs + (size_t)sl * a.smax * (WT + 2);
       for (int e = tid; e < WT * sp.y; e += kPixTile) {
         const int wl = e / sp.y, jj = e - wl * sp.y;
         const int j = sp.x + jj;
@@ -154,7 +186,7 @@ __global__ __launch_bounds__(256) void k_image(ImageArgs a) {
           const float2 r = a.root[(wmod[wl] * a.kmod[j]) % (uint32_t)a.R];
           x = make_float2(v.x * r.x - v.y * r.y, v.x * r.y + v.y * r.x);
         }
-        dst[wl * a.smax + jj] = x;
+        dst[jj * (WT + 2) + wl] = x;
       }
     }
     __syncthreads();
@@ -162,18 +194,24 @@ __global__ __launch_bounds__(256) void k_image(ImageArgs a) {
       for (int sl = 0; sl < nb; ++sl) {
         const int b = b0 + sl;
         const int lo = a.span[(int64_t)b * a.n_ptiles + pt].x;
-        const int jb = a.j0[(int64_t)b * a.n_pix + pix];
-        const float2* src = xs + (size_t)sl * WT * a.smax;
-        const float2* gp = a.g + (int64_t)b * a.taps * a.n_pix + pix;
-        for (int t = 0; t < a.taps; ++t) {
-          const float2 w = gp[(int64_t)t * a.n_pix];
-          const int jj = min(max(jb + t, 0), a.K - 1) - lo;  // inside the span by construction
-          const float2* col = src + jj;
+        const float2* src = xs + (size_t)sl * a.smax * (WT + 2);
+        if constexpr (TAPS > 0) {
+          float2 wc[NT];
 #pragma unroll
-          for (int i = 0; i < WT; ++i) {
-            const float2 x = col[i * a.smax];
-            acc[i].x = fmaf(w.x, x.x, fmaf(-w.y, x.y, acc[i].x));
-            acc[i].y = fmaf(w.x, x.y, fmaf(w.y, x.x, acc[i].y));
+          for (int t = 0; t < NT; ++t) wc[t] = wn[t];
+          const int jb = jn;
+          fetch(b + 1);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            const int jj = min(max(jb + t, 0), a.K - 1) - lo;  // inside the span by construction
+            mac_tap<WT>(acc, wc[t], src + jj * (WT + 2));
+          }
+        } else {
+          const int jb = a.j0[(int64_t)b * a.n_pix + pix];
+          const float2* gp = a.g + (int64_t)b * a.taps * a.n_pix + pix;
+          for (int t = 0; t < a.taps; ++t) {
+            const int jj = min(max(jb + t, 0), a.K - 1) - lo;
+            mac_tap<WT>(acc, gp[(int64_t)t * a.n_pix], src + jj * (WT + 2));
           }
         }
       }
@@ -246,8 +284,16 @@ void image_release(ddx_image* h) {
   h->allocs.clear();
 }
 
+// build options: windows per thread, and the fixed-tap kernels with weight prefetch
+#ifndef DDX_IMG_WT
+#define DDX_IMG_WT 32
+#endif
+#ifndef DDX_IMG_PREFETCH
+#define DDX_IMG_PREFETCH 1
+#endif
+
 int window_tile(const ddx_image* h) {
-  return (int64_t)32 * h->smax * (int64_t)sizeof(float2) <= img::kLdsBytes ? 32 : 4;
+  return (int64_t)(DDX_IMG_WT + 2) * h->smax * (int64_t)sizeof(float2) <= img::kLdsBytes ? DDX_IMG_WT : 4;
 }
 
 }  // namespace
@@ -260,7 +306,7 @@ int ddx_image_create(int32_t n_ant, const double* ant_xyz, int32_t n_pix, const 
   if (!out) return DDX_EINVAL;
   *out = nullptr;
   if (n_ant < 2 || n_ant > 1024 || !ant_xyz || n_pix < 1 || !pix_lm || block_len < 1 || fft_n < block_len ||
-      fft_n % block_len != 0 || fft_n / block_len > 65535 || kmax < 0 || kmax > 1023 || 2 * kmax + 1 > fft_n ||
+      fft_n % block_len != 0 || fft_n / block_len > 65535 || kmax < 0 || kmax > 640 || 2 * kmax + 1 > fft_n ||
       half_width < 0 || half_width > img::kMaxHalfWidth || !std::isfinite(fdot_hz_s) ||
       !(samp_rate_hz > 0.0) || !std::isfinite(samp_rate_hz))
     return DDX_EINVAL;
@@ -352,16 +398,28 @@ int ddx_image_run(ddx_image* h, const void* d_bins, int64_t n_rows, int64_t firs
   const int wt = window_tile(h);
   const int64_t n_wtiles = (n_img + wt - 1) / wt;
   if (n_wtiles * h->n_ptiles > INT32_MAX) return ifail(&h->err, DDX_EUNSUPPORTED, "too many images in one call");
-  const int per_pair = wt * h->smax * (int)sizeof(float2);
-  const int pb = std::max(1, std::min(h->nbl, std::min(64, img::kLdsBytes / per_pair)));
+  const int per_pair = (wt + 2) * h->smax * (int)sizeof(float2);
+  const int pb = std::max(1, std::min(h->nbl, std::min(64, img::kLdsStage / per_pair)));
   img::ImageArgs a{(const float2*)d_bins, h->g, h->j0, h->span, h->root, h->kmod, (float2*)d_p, (float*)d_e,
                    first_window, n_img, w_step, h->n_pix, h->nbl, h->n_ptiles, h->K, h->taps, h->R, h->smax, pb};
   const size_t lds = (size_t)pb * per_pair;
   const dim3 grid((unsigned)(n_wtiles * h->n_ptiles));
-  if (wt == 32)
-    hipLaunchKernelGGL(img::k_image<32>, grid, dim3(img::kPixTile), lds, (hipStream_t)hip_stream, a);
+  const hipStream_t st = (hipStream_t)hip_stream;
+  const dim3 blk(img::kPixTile);
+  if (wt != DDX_IMG_WT)
+    hipLaunchKernelGGL((img::k_image<4, 0>), grid, blk, lds, st, a);
+  else if (!DDX_IMG_PREFETCH)
+    hipLaunchKernelGGL((img::k_image<DDX_IMG_WT, 0>), grid, blk, lds, st, a);
+  else if (h->taps == 1)
+    hipLaunchKernelGGL((img::k_image<DDX_IMG_WT, 1>), grid, blk, lds, st, a);
+  else if (h->taps == 3)
+    hipLaunchKernelGGL((img::k_image<DDX_IMG_WT, 3>), grid, blk, lds, st, a);
+  else if (h->taps == 5)
+    hipLaunchKernelGGL((img::k_image<DDX_IMG_WT, 5>), grid, blk, lds, st, a);
+  else if (h->taps == 7)
+    hipLaunchKernelGGL((img::k_image<DDX_IMG_WT, 7>), grid, blk, lds, st, a);
   else
-    hipLaunchKernelGGL(img::k_image<4>, grid, dim3(img::kPixTile), lds, (hipStream_t)hip_stream, a);
+    hipLaunchKernelGGL((img::k_image<DDX_IMG_WT, 0>), grid, blk, lds, st, a);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return ifail(&h->err, DDX_EDEVICE, "k_image: %s", hipGetErrorString(e));
   return DDX_OK;

@@ -24,6 +24,7 @@ from .signals import (  # noqa: F401
     noise_complex,
     to_ci8,
     antenna_positions,
+    direction_grid,
     dispersed_segment,
     inject_pulse,
     pulse_wave,

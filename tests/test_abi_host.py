@@ -212,7 +212,7 @@ def test_image_create_rejects_invalid_arguments():
         assert not h.value
         return rc
 
-    for kw in [dict(n_ant=1), dict(n_pix=0), dict(N=250), dict(L=0), dict(kmax=-1), dict(kmax=1024, N=4096),
+    for kw in [dict(n_ant=1), dict(n_pix=0), dict(N=250), dict(L=0), dict(kmax=-1), dict(kmax=641, N=4096),
                dict(kmax=200), dict(F=9), dict(F=-1), dict(fs=0.0), dict(fdot=float("inf")), dict(N=2 ** 20, L=8)]:
         assert create(**kw) == binding.EINVAL, kw
     assert create(pix=np.array([[0.8, 0.7], [0.0, 0.0]])) == binding.EINVAL   # l^2 + m^2 >= 1
