@@ -33,15 +33,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
+DEDISP_SOURCES = ("fft.hpp", "kernels.hpp", "ddx.hip", "tiles.hpp", "cnn_kernels.hpp", "cnn.hip")
+IMAGE_SOURCES = ("image.hip",)
+
+
+def kernel_source_hash(sources=DEDISP_SOURCES):
     h = hashlib.sha256()
-    for f in ("fft.hpp", "kernels.hpp", "ddx.hip", "tiles.hpp", "cnn_kernels.hpp", "cnn.hip"):
+    for f in sources:
         with open(os.path.join(ROOT, "paper_1109_3186_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, sources=DEDISP_SOURCES):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
@@ -49,7 +53,7 @@ def measured_traffic(kernel, workload):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("source_hash") != kernel_source_hash():
+    if t.get("source_hash") != kernel_source_hash(sources):
         return None
     return t.get("bytes_per_launch")
 
@@ -306,8 +310,8 @@ def image_leg(args, dev, bins, pos2d, N, L, kmax):
     rec = {"directions": int(pix.shape[0]), "images": int(n_img), "half_width": F, "w_step": w_step,
            "ms_per_call": round(ms, 3), "direction_pair_images_per_s": pix.shape[0] * pairs * n_img / (ms / 1e3),
            "roofline": {"bound": "alu", "achieved": round(tf, 2), "peak": PEAKS["fp32_vector_tflops"],
-                        "unit": "TFLOP/s", "frac": round(tf / PEAKS["fp32_vector_tflops"], 4), "traffic": None,
-                        "kernel": "k_image"}}
+                        "unit": "TFLOP/s", "frac": round(tf / PEAKS["fp32_vector_tflops"], 4),
+                        "traffic": measured_traffic("image", "chirp", IMAGE_SOURCES), "kernel": "k_image"}}
     if not args.no_cpu_baseline:
         from threadpoolctl import threadpool_limits
 

@@ -121,7 +121,19 @@ struct ImageArgs {
   int32_t n_pix, nbl, n_ptiles, K, taps, R, smax, pb;
 };
 
-// grid: n_ptiles * ceil(n_img / WT) workgroups of 256 threads (window tile slowest);
+// grid: n_ptiles * ceil(n_img / WT) workgroups of 256 threads (mapped by tile_of);
+// Workgroup -> (direction tile, window tile).  Workgroups are dealt to the eight XCDs
+// in turn (id mod 8); the remap gives each XCD a contiguous run of the tile order,
+// window tile fastest, so the window tiles of one direction tile run on one XCD at
+// about the same time and read that tile's weights (the dominant traffic) through
+// the same L2.  The last total mod 8 workgroups keep their own index.
+__device__ __forceinline__ void tile_of(int id, int n_ptiles, int n_wtiles, int& pt, int& wt) {
+  const int whole = (n_ptiles * n_wtiles) & ~7;
+  const int v = id < whole ? (id & 7) * (whole >> 3) + (id >> 3) : id;
+  pt = v / n_wtiles;
+  wt = v - pt * n_wtiles;
+}
+
 // one tap: acc[i] += w X[window i] for the WT windows of a staged bin
 template <int WT>
 __device__ __forceinline__ void mac_tap(float2 (&acc)[WT], float2 w, const float2* bin) {
@@ -147,8 +159,9 @@ __global__ __launch_bounds__(256) void k_image(ImageArgs a) {
   extern __shared__ float2 xs[];
   __shared__ uint32_t wmod[WT];
   const int tid = threadIdx.x;
-  const int pt = blockIdx.x % a.n_ptiles;
-  const int64_t img0 = (int64_t)(blockIdx.x / a.n_ptiles) * WT;
+  int pt, wt;
+  tile_of(blockIdx.x, a.n_ptiles, (int)((a.n_img + WT - 1) / WT), pt, wt);
+  const int64_t img0 = (int64_t)wt * WT;
   const int pix = pt * kPixTile + tid;
   const bool live = pix < a.n_pix;
   if (tid < WT) wmod[tid] = (uint32_t)((a.first + (img0 + tid) * a.w_step) % a.R);
