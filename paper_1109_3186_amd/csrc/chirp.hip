@@ -14,7 +14,8 @@
 //   V_k = (P + Q) + i (T - R),   V_-k = (P - Q) + i (R + T),
 // one FMA per sum and sample, half the work of two separate complex products.  Per
 // block the partial DFTs of all pairs are then a product [pairs x L] x [L x (kmax+1)]
-// in 64 x 64 tiles, the mixing fused into the staging of the pair operand.
+// in 64 x 64 tiles on the FP32 matrix cores, each pair mixed as it feeds them from
+// its tile's antennas staged in LDS.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -37,101 +38,107 @@ constexpr int kChunk = 32;   // samples per LDS chunk
 
 struct PartialArgs {
   const float2* s;        // [M][n] complex samples
-  const int2* pq;         // [nbl] (p, q)
   const float2* w;        // [L_pad][K_pad] (c, d) of w_k[n] = c - i d, k = klist[j]
   const float2* ph;       // [R][K_pad] (c, d) of the block phase of bin klist[j]
   const int2* cols;       // [n_list] columns of V for +k and -k (-1: none, k = 0)
-  const int* klist;       // [n_list] the listed bins k >= 0, ascending
-  const int* tile_bins;   // [n_ptiles] largest bin budget of a pair tile
+  const int2* act;        // [n_act] (pair tile, bin tile) with bins inside the tile's budgets
+  const int* tile_ant;    // [n_ptiles][2 kTileP] antennas that a pair tile reads
+  const int* tile_nant;   // [n_ptiles] their count
+  const int2* loc;        // [nbl] (p, q) as indices into the tile's antenna list
   float2* v;              // [nb][nbl][Kc] partial DFTs (pairs in budget order)
   int64_t n_samp;         // samples per antenna row of s
-  int32_t nbl, n_list, Kc, K_pad, L, R, n_ptiles, n_ktiles;
+  int32_t nbl, n_list, Kc, K_pad, L, R, n_act;
 };
 
-// grid: nb * n_ptiles * n_ktiles workgroups of 256 threads (block slowest).
-// Thread (tp, tk) = (tid / 16, tid % 16) accumulates pairs 4 tp .. 4 tp + 3 of the
-// tile against the listed bins +-klist[4 tk .. 4 tk + 3] of the tile.
-__global__ __launch_bounds__(256) void k_partial(PartialArgs a) {
-  __shared__ float2 xs[kChunk][kTileP];
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// Workgroups are dealt to the eight XCDs in turn (id mod 8).  Numbering the work
+// so that each XCD gets a contiguous run of blocks keeps the tiles of one block
+// (which read the same antenna samples) on one L2.  The last total mod 8 keep
+// their id.
+__device__ __forceinline__ int xcd_order(int id, int total) {
+  const int whole = total & ~7;
+  return id < whole ? (id & 7) * (whole >> 3) + (id >> 3) : id;
+}
+
+// grid: nb * n_act workgroups of 256 threads (block slowest, in the order of
+// xcd_order), one per block and active (pair tile, bin tile): tiles whose bins all
+// lie beyond the bin budgets of their pairs are left out of the grid on the host
+// (an early exit in the kernel instead left whole shader engines idle: the skipped
+// tiles fell on every other engine).  The product runs on the FP32 matrix cores (v_mfma_f32_32x32x2_f32: twice the
+// FP32 rate of unpacked vector FMAs, FP32 products and sums).  The four sums are
+// four real products of the tile: P = a c, Q = b d, R = a d, T = b c,
+// each [32 pairs x 2 samples] x [2 samples x 32 bins] per instruction.  The staging
+// reads the tile's antennas as rows of consecutive samples (coalesced) and mixes
+// each pair when it feeds the matrix core, instead of gathering s_p and s_q per
+// pair.  Wave w
+// owns pairs 32 (w / 2) .. and listed bins 32 (w % 2) .. of the 64 x 64 tile.
+// Lane l supplies pair (or bin) l % 32 of sample l / 32 of each sample pair and
+// holds, of each 32 x 32 result, bin l % 32 of the pairs 8 (v / 4) + 4 (l / 32)
+// + v % 4, v < 16.
+__global__ __launch_bounds__(256) void k_partial_mfma(PartialArgs a) {
+  // the tile's antennas (at most two per pair), kChunk samples each, padded by one
+  // entry so that the lanes' different antennas fall in different banks
+  __shared__ float2 sa[2 * kTileP][kChunk + 1];
   __shared__ float2 ws[kChunk][kTileK];
   const int tid = threadIdx.x;
-  const int kt = blockIdx.x % a.n_ktiles;
-  const int pt = (blockIdx.x / a.n_ktiles) % a.n_ptiles;
-  const int m = blockIdx.x / (a.n_ktiles * a.n_ptiles);
+  const int id = xcd_order(blockIdx.x, gridDim.x);
+  const int2 tile = a.act[id % a.n_act];
+  const int pt = tile.x, kt = tile.y;
+  const int m = id / a.n_act;
   const int p0 = pt * kTileP, k0 = kt * kTileK;
-  // pairs are sorted by bin budget: a tile whose smallest bin exceeds every budget
-  // of its pairs has nothing to compute (the CIC writes those bins as zero)
-  if (k0 < a.n_list && a.klist[k0] > a.tile_bins[pt]) return;
-  const int tp = tid >> 4, tk = tid & 15;
+  const int wv = tid >> 6, lane = tid & 63;
+  const int wp = (wv >> 1) * 32, wk = (wv & 1) * 32;
+  const int r = lane & 31, h = lane >> 5;
   const int64_t base = (int64_t)m * a.L;
-  float4 acc[4][4];  // (P, Q, R, T) per pair and bin pair
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = make_float4(0.f, 0.f, 0.f, 0.f);
+  const int na = a.tile_nant[pt];
+  const int* ants = a.tile_ant + pt * 2 * kTileP;
+  const int my_pair = p0 + wp + r;
+  const int2 lc = my_pair < a.nbl ? a.loc[my_pair] : make_int2(0, 0);
+  const float live = my_pair < a.nbl ? 1.f : 0.f;
+  v16f P = {}, Q = {}, R = {}, T = {};
 
   for (int n0 = 0; n0 < a.L; n0 += kChunk) {
     __syncthreads();
-    // stage x[n][pair] = s_p conj(s_q) (zero past the block or past the last pair)
-#pragma unroll
-    for (int r = 0; r < (kChunk * kTileP) / 256; ++r) {
-      const int e = tid + 256 * r;
-      const int n = e / kTileP, pl = e % kTileP;
-      const int pair = p0 + pl;
-      float2 x = make_float2(0.f, 0.f);
-      if (pair < a.nbl && n0 + n < a.L) {
-        const int2 pq = a.pq[pair];
-        const float2 sp = a.s[(int64_t)pq.x * a.n_samp + base + n0 + n];
-        const float2 sq = a.s[(int64_t)pq.y * a.n_samp + base + n0 + n];
-        x = make_float2(sp.x * sq.x + sp.y * sq.y, sp.y * sq.x - sp.x * sq.y);
-      }
-      xs[n][pl] = x;
+    // the antennas' samples: rows of kChunk consecutive samples, coalesced
+    for (int e = tid; e < na * kChunk; e += 256) {
+      const int ai = e / kChunk, n = e % kChunk;
+      float2 v = make_float2(0.f, 0.f);
+      if (n0 + n < a.L) v = a.s[(int64_t)ants[ai] * a.n_samp + base + n0 + n];
+      sa[ai][n] = v;
     }
-    // stage w[n][k] (the table is zero past L and past K)
 #pragma unroll
-    for (int r = 0; r < (kChunk * kTileK) / 256; ++r) {
-      const int e = tid + 256 * r;
+    for (int q = 0; q < (kChunk * kTileK) / 256; ++q) {
+      const int e = tid + 256 * q;
       const int n = e / kTileK, kl = e % kTileK;
       ws[n][kl] = a.w[(int64_t)(n0 + n) * a.K_pad + k0 + kl];
     }
     __syncthreads();
 #pragma unroll 4
-    for (int n = 0; n < kChunk; ++n) {
-      float2 xv[4], wv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) xv[i] = xs[n][4 * tp + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) wv[j] = ws[n][4 * tk + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          acc[i][j].x = fmaf(xv[i].x, wv[j].x, acc[i][j].x);  // P += a c
-          acc[i][j].y = fmaf(xv[i].y, wv[j].y, acc[i][j].y);  // Q += b d
-          acc[i][j].z = fmaf(xv[i].x, wv[j].y, acc[i][j].z);  // R += a d
-          acc[i][j].w = fmaf(xv[i].y, wv[j].x, acc[i][j].w);  // T += b c
-        }
+    for (int n = 0; n < kChunk; n += 2) {
+      // x = s_p conj(s_q) of the lane's pair and sample, mixed at the operand
+      const float2 sp = sa[lc.x][n + h], sq = sa[lc.y][n + h];
+      const float xr = live * (sp.x * sq.x + sp.y * sq.y), xi = live * (sp.y * sq.x - sp.x * sq.y);
+      const float2 wt = ws[n + h][wk + r];
+      P = __builtin_amdgcn_mfma_f32_32x32x2f32(xr, wt.x, P, 0, 0, 0);
+      Q = __builtin_amdgcn_mfma_f32_32x32x2f32(xi, wt.y, Q, 0, 0, 0);
+      R = __builtin_amdgcn_mfma_f32_32x32x2f32(xr, wt.y, R, 0, 0, 0);
+      T = __builtin_amdgcn_mfma_f32_32x32x2f32(xi, wt.x, T, 0, 0, 0);
     }
   }
-  // V_+-k, times the block phase exp(-+ i phi) = c -+ i d, stored at columns cols[jl]
-  const float2* ph = a.ph + (int64_t)(m % a.R) * a.K_pad;
+  const int jl = k0 + wk + r;
+  if (jl >= a.n_list) return;
+  const float2 f = a.ph[(int64_t)(m % a.R) * a.K_pad + jl];
+  const int2 col = a.cols[jl];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int jl = k0 + 4 * tk + j;
-    if (jl >= a.n_list) continue;
-    const float2 f = ph[jl];
-    const int2 col = a.cols[jl];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int pair = p0 + 4 * tp + i;
-      if (pair >= a.nbl) continue;
-      const float4 u = acc[i][j];
-      const float pr = u.x + u.y, pi = u.w - u.z;  // V_k
-      const float nr = u.x - u.y, ni = u.z + u.w;  // V_-k
-      float2* row = a.v + ((int64_t)m * a.nbl + pair) * a.Kc;
-      row[col.x] = make_float2(pr * f.x + pi * f.y, pi * f.x - pr * f.y);
-      if (col.y >= 0) row[col.y] = make_float2(nr * f.x - ni * f.y, ni * f.x + nr * f.y);
-    }
+  for (int v = 0; v < 16; ++v) {
+    const int pair = p0 + wp + 8 * (v >> 2) + 4 * h + (v & 3);
+    if (pair >= a.nbl) continue;
+    const float pr = P[v] + Q[v], pi = T[v] - R[v];  // V_k
+    const float nr = P[v] - Q[v], ni = R[v] + T[v];  // V_-k
+    float2* row = a.v + ((int64_t)m * a.nbl + pair) * a.Kc;
+    row[col.x] = make_float2(pr * f.x + pi * f.y, pi * f.x - pr * f.y);
+    if (col.y >= 0) row[col.y] = make_float2(nr * f.x - ni * f.y, ni * f.x + nr * f.y);
   }
 }
 
@@ -219,17 +226,21 @@ struct Stage {
   float2* ph = nullptr;  // [R][K_pad]
   int2* cols = nullptr;  // [n_list]
   int* cmap = nullptr;   // [Kc] output bin index of each column of V
-  int* klist = nullptr;  // [n_list] the listed bins k >= 0
+  std::vector<int> klist;  // [n_list] the listed bins k >= 0 (host)
+  int2* act = nullptr;   // [n_act] active (pair tile, bin tile), see set_active
+  int n_act = 0;
 };
 
 struct Common {
   int M = 0, L = 0, kmax = 0, K = 0, L_pad = 0, nbl = 0;
   int64_t max_samples = 0, max_blocks = 0;
-  int2* pq = nullptr;           // [nbl] pairs in budget order (descending)
   int* perm = nullptr;          // [nbl] budget order -> row-major pair index
   int* budget = nullptr;        // [nbl] bin budget, budget order
   int* budget_canon = nullptr;  // [nbl] bin budget, row-major pair order
-  int* tile_bins = nullptr;     // [pair tiles] largest budget of the tile
+  std::vector<int> tile_bins;   // [pair tiles] largest budget of the tile (host)
+  int* tile_ant = nullptr;      // [pair tiles][2 kTileP] antennas read by the tile
+  int* tile_nant = nullptr;     // [pair tiles] their count
+  int2* loc = nullptr;          // [nbl] (p, q) as indices into the tile's antennas
   float2* v = nullptr;   // [max_blocks][nbl][max Kc]
   std::vector<void*> allocs;
   std::string err;
@@ -263,7 +274,6 @@ int upload(Common& c, T** dst, const std::vector<T>& src) {
 void release(Common& c) {
   for (void* p : c.allocs) (void)hipFree(p);
   c.allocs.clear();
-  c.pq = nullptr;
   c.v = nullptr;
 }
 
@@ -272,6 +282,32 @@ float2 twiddle_cd(int64_t num, int n) {
   const int64_t r = ((num % n) + n) % n;
   const double ang = 2.0 * M_PI * (double)r / (double)n;
   return make_float2((float)std::cos(ang), (float)std::sin(ang));
+}
+
+// The (pair tile, bin tile) pairs of a stage that hold a bin within the largest
+// budget of the tile's pairs, bin tile fastest; uploaded to the stage's list
+// (allocated once at its largest size).  Synchronous.
+int set_active(Common& c, Stage& st) {
+  const int n_ptiles = (c.nbl + chirp::kTileP - 1) / chirp::kTileP;
+  const int n_ktiles = st.K_pad / chirp::kTileK;
+  std::vector<int2> act;
+  for (int pt = 0; pt < n_ptiles; ++pt)
+    for (int kt = 0; kt < n_ktiles; ++kt) {
+      const int k0 = kt * chirp::kTileK;
+      if (k0 < st.n_list && st.klist[k0] > c.tile_bins[pt]) continue;
+      act.push_back(make_int2(pt, kt));
+    }
+  if (!st.act) {
+    std::vector<int2> all((size_t)n_ptiles * n_ktiles, make_int2(0, 0));
+    int rc = upload(c, &st.act, all);
+    if (rc) return rc;
+  }
+  if (hipMemcpy(st.act, act.data(), act.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    return cfail(&c.err, DDX_EDEVICE, "tile list upload failed");
+  }
+  st.n_act = (int)act.size();
+  return DDX_OK;
 }
 
 // A stage of length n for the bins k >= 0 in klist; columns of V: +k then -k
@@ -300,9 +336,34 @@ int make_stage(Common& c, int n, const std::vector<int>& klist, Stage& st) {
   st.Kc = (int)cmap.size();
   int rc;
   if ((rc = upload(c, &st.w, w)) || (rc = upload(c, &st.ph, ph)) || (rc = upload(c, &st.cols, cols)) ||
-      (rc = upload(c, &st.cmap, cmap)) || (rc = upload(c, &st.klist, klist.empty() ? std::vector<int>{0} : klist)))
+      (rc = upload(c, &st.cmap, cmap)))
     return rc;
-  return DDX_OK;
+  st.klist = klist;
+  return set_active(c, st);
+}
+
+// The distinct antennas of each tile of kTileP consecutive pairs (pair order pq),
+// and each pair's (p, q) as indices into its tile's list.
+void tile_antennas(const std::vector<int2>& pq, int n_ant, std::vector<int>& ants, std::vector<int>& nant,
+                   std::vector<int2>& loc) {
+  const int n_tiles = ((int)pq.size() + chirp::kTileP - 1) / chirp::kTileP;
+  ants.assign((size_t)n_tiles * 2 * chirp::kTileP, 0);
+  nant.assign(n_tiles, 0);
+  loc.assign(pq.size(), make_int2(0, 0));
+  std::vector<int> slot(n_ant, -1);
+  for (int t = 0; t < n_tiles; ++t) {
+    std::fill(slot.begin(), slot.end(), -1);
+    int cnt = 0;
+    for (int i = t * chirp::kTileP; i < std::min((int)pq.size(), (t + 1) * chirp::kTileP); ++i) {
+      for (int ant : {pq[i].x, pq[i].y})
+        if (slot[ant] < 0) {
+          slot[ant] = cnt;
+          ants[(size_t)t * 2 * chirp::kTileP + cnt++] = ant;
+        }
+      loc[i] = make_int2(slot[pq[i].x], slot[pq[i].y]);
+    }
+    nant[t] = cnt;
+  }
 }
 
 int make_common(Common& c, int n_ant, int block_len, int kmax, int64_t max_samples, int max_kc) {
@@ -319,10 +380,14 @@ int make_common(Common& c, int n_ant, int block_len, int kmax, int64_t max_sampl
     for (int q = p + 1; q < n_ant; ++q) pq.push_back(make_int2(p, q));
   std::vector<int> perm(c.nbl), budget(c.nbl, kmax);
   for (int i = 0; i < c.nbl; ++i) perm[i] = i;
-  std::vector<int> tiles((c.nbl + chirp::kTileP - 1) / chirp::kTileP, kmax);
+  c.tile_bins.assign((c.nbl + chirp::kTileP - 1) / chirp::kTileP, kmax);
+  std::vector<int> ants, nant;
+  std::vector<int2> loc;
+  tile_antennas(pq, n_ant, ants, nant, loc);
   int rc;
-  if ((rc = upload(c, &c.pq, pq)) || (rc = upload(c, &c.perm, perm)) || (rc = upload(c, &c.budget, budget)) ||
-      (rc = upload(c, &c.budget_canon, budget)) || (rc = upload(c, &c.tile_bins, tiles)))
+  if ((rc = upload(c, &c.perm, perm)) || (rc = upload(c, &c.budget, budget)) ||
+      (rc = upload(c, &c.budget_canon, budget)) ||
+      (rc = upload(c, &c.tile_ant, ants)) || (rc = upload(c, &c.tile_nant, nant)) || (rc = upload(c, &c.loc, loc)))
     return rc;
   const size_t vb = (size_t)c.max_blocks * c.nbl * max_kc * sizeof(float2);
   if (hipMalloc((void**)&c.v, std::max<size_t>(vb, 256)) != hipSuccess) {
@@ -339,12 +404,13 @@ int run_stage(Common& c, const Stage& st, const float2* volts, int64_t n, float2
   const int64_t nb = n / c.L;
   chirp::PartialArgs a{};
   a.s = volts;
-  a.pq = c.pq;
   a.w = st.w;
   a.ph = st.ph;
   a.cols = st.cols;
-  a.klist = st.klist;
-  a.tile_bins = c.tile_bins;
+  a.act = st.act;
+  a.tile_ant = c.tile_ant;
+  a.tile_nant = c.tile_nant;
+  a.loc = c.loc;
   a.v = c.v;
   a.n_samp = n;
   a.nbl = c.nbl;
@@ -353,13 +419,13 @@ int run_stage(Common& c, const Stage& st, const float2* volts, int64_t n, float2
   a.K_pad = st.K_pad;
   a.L = c.L;
   a.R = st.R;
-  a.n_ptiles = (c.nbl + chirp::kTileP - 1) / chirp::kTileP;
-  a.n_ktiles = st.K_pad / chirp::kTileK;
-  const int64_t grid = nb * a.n_ptiles * a.n_ktiles;
+  a.n_act = st.n_act;
+  const int64_t grid = nb * st.n_act;
   if (grid > INT32_MAX) return cfail(&c.err, DDX_EUNSUPPORTED, "too many blocks in one call");
-  hipLaunchKernelGGL(chirp::k_partial, dim3((unsigned)grid), dim3(256), 0, s, a);
+  // no active tile: every listed bin lies beyond every budget, and the CIC writes zeros
+  if (grid > 0) hipLaunchKernelGGL(chirp::k_partial_mfma, dim3((unsigned)grid), dim3(256), 0, s, a);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return cfail(&c.err, DDX_EDEVICE, "k_partial: %s", hipGetErrorString(e));
+  if (e != hipSuccess) return cfail(&c.err, DDX_EDEVICE, "k_partial_mfma: %s", hipGetErrorString(e));
   const int64_t cols = (int64_t)c.nbl * st.Kc;
   // segments of at least 256 blocks (the R-block restart costs R / seg extra reads), at most 65535
   const int64_t seg = std::max<int64_t>(256, (nb + 65534) / 65535);
@@ -398,15 +464,20 @@ int set_budgets(Common& c, const int32_t* host) {
     bs[i] = budget[perm[i]];
     tiles[i / chirp::kTileP] = std::max(tiles[i / chirp::kTileP], bs[i]);
   }
+  std::vector<int> ants, nant;
+  std::vector<int2> loc;
+  tile_antennas(pq, c.M, ants, nant, loc);
   if (hipDeviceSynchronize() != hipSuccess ||
-      hipMemcpy(c.pq, pq.data(), pq.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c.tile_ant, ants.data(), ants.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c.tile_nant, nant.data(), nant.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c.loc, loc.data(), loc.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c.perm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c.budget, bs.data(), bs.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c.budget_canon, budget.data(), budget.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c.tile_bins, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(c.budget_canon, budget.data(), budget.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipGetLastError();
     return cfail(&c.err, DDX_EDEVICE, "bin budget upload failed");
   }
+  c.tile_bins = tiles;
   return DDX_OK;
 }
 
@@ -469,12 +540,15 @@ int ddx_chirp_preintegrate(ddx_chirp* h, const void* d_volts, int64_t n, void* d
 
 int ddx_chirp_set_pair_bins(ddx_chirp* h, const int32_t* kmax_pair) {
   if (!h) return DDX_EINVAL;
-  return set_budgets(h->c, kmax_pair);
+  const int rc = set_budgets(h->c, kmax_pair);
+  return rc ? rc : set_active(h->c, h->st);
 }
 
 int ddx_chirp_bank_set_pair_bins(ddx_chirp_bank* b, const int32_t* kmax_pair) {
   if (!b) return DDX_EINVAL;
-  return set_budgets(b->c, kmax_pair);
+  int rc = set_budgets(b->c, kmax_pair);
+  for (size_t d = 0; !rc && d < b->st.size(); ++d) rc = set_active(b->c, b->st[d]);
+  return rc;
 }
 
 const char* ddx_chirp_last_error(const ddx_chirp* h) { return h ? h->c.err.c_str() : "NULL pre-integrator"; }

@@ -130,19 +130,32 @@ def test_pair_bin_budgets(gpu, kind):
     assert err <= TOL
 
 
-def test_bank_with_pair_bin_budgets(gpu):
+@pytest.mark.parametrize("kind", ["random", "zero"])
+def test_bank_with_pair_bin_budgets(gpu, kind):
+    """Budgets on a bank; 'zero' keeps only bin 0, so the lengths d > 1 (whose bin 0
+    is factorised) launch no partial-DFT tile at all.  Clearing the budgets again
+    restores the full output."""
     m_ant, n0, n_len, L, kmax = 10, 64, 8, 16, 20
     rng = np.random.Generator(np.random.PCG64(121))
     s = synth.noise_complex(rng, (m_ant, (n0 * n_len // L + 5) * L))
-    budgets = rng.integers(0, kmax + 1, m_ant * (m_ant - 1) // 2).astype(np.int32)
+    nbl = m_ant * (m_ant - 1) // 2
+    if kind == "random":
+        budgets = rng.integers(0, kmax + 1, nbl).astype(np.int32)
+    else:
+        budgets = np.zeros(nbl, dtype=np.int32)
     x = torch.from_numpy(np.ascontiguousarray(s.astype(np.complex64))).to("cuda:0")
     with ChirpBank(m_ant, n0, n_len, L, kmax, max_samples=s.shape[1]) as b:
         b.set_pair_bins(budgets)
         got = [o.cpu().numpy() for o in b.run(x)]
-    for d, g in enumerate(got, start=1):
+        b.set_pair_bins(None)
+        full = [o.cpu().numpy() for o in b.run(x)]
+    for d, (g, f) in enumerate(zip(got, full), start=1):
         ref = och.preintegrate(s, n0 * d, L, kmax, pair_kmax=budgets)
         err = np.max(np.abs(g - ref)) / np.sqrt(np.mean(np.abs(ref) ** 2))
         assert err <= TOL, (d, err)
+        ref = och.preintegrate(s, n0 * d, L, kmax)
+        err = np.max(np.abs(f - ref)) / np.sqrt(np.mean(np.abs(ref) ** 2))
+        assert err <= TOL, (d, "cleared", err)
 
 
 def test_pair_bin_budget_rejected(gpu):
