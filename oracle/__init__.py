@@ -20,7 +20,10 @@ what Bannister & Cornwell (2011), "The Chirpolator and The Chimageator", define:
   the DFT factorisation across lengths and the shared negative-bin products;
 * in ``oracle.imaging``, the post-integrator detection image P(theta) and
   E(theta) (Sec. 3.3, 3.4, App. A.1): 3-D baseline delays, the tone bin k0',
-  the matched filter over 2F + 1 bins and the vector sum over pairs.
+  the matched filter over 2F + 1 bins and the vector sum over pairs;
+* in ``oracle.incoherent``, classical incoherent dedispersion of power beams
+  (Sec. 2.3.1, 2.4.1): brute force over the delays of Eq. dmdelay, and the tree
+  method for linear sweeps.
 
 Everything is numpy in float64 / complex128.  The oracle shares no code with the
 GPU path; only the seeded input generators (package ``synth``) serve both.
