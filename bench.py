@@ -328,6 +328,81 @@ def image_leg(args, dev, bins, pos2d, N, L, kmax):
     return rec
 
 
+def run_incoherent(args, dev):
+    """Classical incoherent dedispersion (Sec. 2.3.1) of a power-beam spectrogram
+    (Sec. 2.4.1): 1024 channels over 1.2-1.5 GHz (channel 0 highest), 2^18 samples of
+    uniform random power, 1024 trials.  Brute force: DMs 0..1000 evenly, delays from
+    Eq. dmdelay with the sample time that makes the largest delay 1023 samples.  Tree:
+    its 1024 linear sweeps (delay 0..1023 across the band), the same span.  One step
+    = one call of each; HIP events on the launch stream."""
+    import numpy as np
+    import torch
+
+    from paper_1109_3186_amd import incoherent_dedisperse, incoherent_delays, tree_dedisperse
+    C, T, D, k_dm = 1024, 1 << 18, 1024, 4.148808e15
+    f = 1.5e9 - (0.3e9 / C) * (np.arange(C) + 0.5)
+    dms = np.linspace(0.0, 1000.0, D)
+    t_samp = k_dm * 1000.0 * (1.0 / f.min() ** 2 - 1.0 / f.max() ** 2) / 1023.0
+    dl_h = incoherent_delays(f, t_samp, dms, k_dm)
+    g = torch.Generator(device=dev)
+    g.manual_seed(1113)
+    power = torch.rand((C, T), dtype=torch.float32, device=dev, generator=g)
+    dl = torch.from_numpy(dl_h).to(dev)
+    n_out = T - int(dl_h.max())
+    out = torch.empty((C, T), dtype=torch.float32, device=dev)
+    work = torch.empty_like(out)
+
+    def timed(run):
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    ms_tree = timed(lambda: tree_dedisperse(power, out=out, work=work))
+    ms_brute = timed(lambda: incoherent_dedisperse(power, dl, n_out))
+    tree_units = C * T * C / (ms_tree / 1e3)
+    brute_units = C * n_out * D / (ms_brute / 1e3)
+    # tree: the fused first five stages read and write every row once, each later
+    # stage reads two rows and writes one
+    stages = int(np.log2(C))
+    staged = 8.0 * C * T + 12.0 * C * T * (stages - 5)
+    gbs = staged / (ms_tree / 1e3) / 1e9
+    log("incoherent: tree %.2f ms (%.3e units/s, %.0f GB/s staged); brute force %.2f ms (%.3e units/s)" % (
+        ms_tree, tree_units, gbs, ms_brute, brute_units))
+    cpu = None
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import incoherent as oinc
+        sub = power[:64, :16384].cpu().numpy().astype(np.float64)
+        with threadpool_limits(1):
+            tc = time.perf_counter()
+            oinc.tree(sub)
+            tc = time.perf_counter() - tc
+        cpu = {"value": 64 * 16384 * 64 / tc, "unit": "channel-samples*trials/s", "cores": 1, "kind": "oracle",
+               "sample": "tree over 64 channels x 16384 samples (64 sweeps), FP64 numpy on one thread, %.2f s" % tc}
+    rec = {"metric": "channel-samples x trials/s, tree incoherent dedispersion", "value": tree_units,
+           "unit": "channel-samples*trials/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms_tree, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "incoherent dedispersion: 1024 ch x 2^18 samples, 1024 trials", "n_chan": C,
+                      "samples": T, "trials": D, "parallelism": "none (1 GPU)"},
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
+                        "frac": round(gbs / PEAKS["hbm_gbs"], 4), "traffic": None,
+                        "kernel": "k_tree_fused + k_tree_stage (one call)"},
+           "cpu_baseline": cpu,
+           "brute_force": {"ms_per_call": round(ms_brute, 3), "units_per_s": brute_units, "n_out": n_out,
+                           "adds_per_s": C * n_out * D / (ms_brute / 1e3),
+                           "tree_speedup_per_trial_sample": round(tree_units / brute_units, 1)}}
+    print(json.dumps(rec), flush=True)
+
+
 def run_c3(args, dev):
     """The batched sparse-array workload: 256 antennas, 32 x 1 MHz channels at
     0.7-0.732 GHz, 2^18 ci8 samples, per-channel DM grids of 512..1536 trials over
@@ -477,9 +552,10 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal measurement")
     ap.add_argument("--wave-units", type=int, default=0, help="schedule: units per wave (0 = automatic)")
     ap.add_argument("--dm-group", type=int, default=0, help="schedule: DMs per block group (0 = automatic)")
-    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "chirp"],
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "chirp", "incoherent"],
                     help="c1: 36-antenna headline workload (default); c3: 256-antenna batched sparse array; "
-                         "chirp: the Chirpolator pre-integrator")
+                         "chirp: the Chirpolator pre-integrator and image; incoherent: classical incoherent "
+                         "dedispersion of a power spectrogram (brute force and tree)")
     ap.add_argument("--autotune", action="store_true", help="use the autotuned lengths and schedule (cached)")
     ap.add_argument("--passes", type=int, default=0, help="c3: DM-window passes (0 = ceil(sum D / 512))")
     ap.add_argument("--channels", type=int, default=0,
@@ -503,6 +579,8 @@ def main():
         return run_c3(args, dev)
     if args.workload == "chirp":
         return run_chirp(args, dev)
+    if args.workload == "incoherent":
+        return run_incoherent(args, dev)
     if args.copy_calibration:
         src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)
         dst = torch.mul(src, 1.0)  # reads and writes copy_calibration MiB each

@@ -426,6 +426,44 @@ int ddx_image_run(ddx_image* h, const void* d_bins, int64_t n_rows, int64_t firs
 int ddx_image_destroy(ddx_image* h);
 const char* ddx_image_last_error(const ddx_image* h);
 
+/* ---- Classical incoherent dedispersion of power beams (Sec. 2.3.1, 2.4.1) -------
+ * Stateless calls; every device buffer is caller-owned; asynchronous on
+ * hip_stream.  Power spectrograms are [C][n_t] FP32 rows, channel 0 the least
+ * delayed (highest frequency); samples past n_t count as zero. */
+
+/* Power beam (Sec. 2.4.1): d_power[c][t] = sum over antennas a and the n_int
+ * samples n of interval t of |x_{c,a}[n]|^2, t < floor(n_samp / n_int).
+ * d_volts: DEVICE [n_chan][n_ant][n_samp] complex64.  DDX_EINVAL for invalid
+ * sizes (n_chan <= 65535) or NULL buffers. */
+int ddx_power_beam(const void* d_volts, int32_t n_chan, int32_t n_ant, int64_t n_samp, int32_t n_int,
+                   float* d_power, void* hip_stream);
+
+/* Dispersion delays in whole samples relative to the highest channel (Eq.
+ * dmdelay): delays[c][d] = rint(k_dm DM_d (f_c^-2 - f_top^-2) / t_samp_s), FP64,
+ * ties to even.  chan_freq_hz [n_chan], dm [n_dm] and delays [n_chan][n_dm] are
+ * HOST arrays.  DDX_EINVAL for non-positive frequencies or sample time, negative
+ * or non-finite DMs; DDX_EUNSUPPORTED if a delay exceeds 2^31 - 1 samples. */
+int ddx_incoherent_delays(int32_t n_chan, const double* chan_freq_hz, double t_samp_s, int32_t n_dm,
+                          const double* dm, double k_dm, int32_t* delays);
+
+/* Brute-force incoherent dedispersion (Sec. 2.3.1): d_out[d][t] = sum_c
+ * d_power[c][t + d_delays[c][d]] for t < n_out (samples outside [0, n_t) count as
+ * zero).  d_delays: DEVICE [n_chan][n_dm] int32; d_out: DEVICE [n_dm][n_out].
+ * DDX_EINVAL for invalid sizes or NULL buffers, DDX_EUNSUPPORTED above 262140 DMs
+ * per call. */
+int ddx_incoherent_dedisperse(const float* d_power, int32_t n_chan, int64_t n_t, const int32_t* d_delays,
+                              int32_t n_dm, float* d_out, int64_t n_out, void* hip_stream);
+
+/* The tree method the paper cites for incoherent dedispersion (Sec. 2.3.1, linear
+ * dispersion): for n_chan = 2^k channels (1 .. 32768), d_out[j][t] (j < n_chan) is
+ * the sum of the channels along sweep j, whose delay runs from 0 at channel 0 to j
+ * at the last channel: log2(n_chan) merging stages, each adding sweep floor(j/2)
+ * of the first half of a group to sweep floor(j/2) of its second half advanced by
+ * j - floor(j/2) samples.  d_out, d_work: DEVICE [n_chan][n_t] FP32; d_work is
+ * scratch (may be NULL when n_chan is 1, 2 or 32).  DDX_EINVAL otherwise. */
+int ddx_tree_dedisperse(const float* d_power, int32_t n_chan, int64_t n_t, float* d_out, float* d_work,
+                        void* hip_stream);
+
 /* Synchronise the plan's last stream and free plan-owned memory.  NULL is a no-op. */
 int ddx_plan_destroy(ddx_plan* plan);
 

@@ -6,7 +6,8 @@ ctypes binding (binding.py).  There is no CPU fallback: without the built
 library every call raises.
 """
 from .binding import (  # noqa: F401
-    Plan, Cnn, Chirp, ChirpBank, Image, DdxError, lib, LIB_PATH, SIGNATURES,
+    Plan, Cnn, Chirp, ChirpBank, Image, incoherent_delays, power_beam, incoherent_dedisperse, tree_dedisperse,
+    DdxError, lib, LIB_PATH, SIGNATURES,
     OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ESIZE, EFULL, EUNSUPPORTED,
     IN_CI8, IN_CF32, CORR_F32, CORR_F16, CORR_E4M3, OUT_PACKED, OUT_FULL, FLUSH,
 )

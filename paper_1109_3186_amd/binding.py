@@ -111,6 +111,13 @@ SIGNATURES = {
                        ct.c_void_p], ct.c_int),
     "ddx_image_destroy": ([ct.c_void_p], ct.c_int),
     "ddx_image_last_error": ([ct.c_void_p], ct.c_char_p),
+    "ddx_power_beam": ([ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_int64, ct.c_int32, ct.c_void_p, ct.c_void_p],
+                       ct.c_int),
+    "ddx_incoherent_delays": ([ct.c_int32, ct.POINTER(ct.c_double), ct.c_double, ct.c_int32,
+                               ct.POINTER(ct.c_double), ct.c_double, ct.POINTER(ct.c_int32)], ct.c_int),
+    "ddx_incoherent_dedisperse": ([ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_void_p, ct.c_int32, ct.c_void_p,
+                                   ct.c_int64, ct.c_void_p], ct.c_int),
+    "ddx_tree_dedisperse": ([ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p], ct.c_int),
     "ddx_plan_destroy": ([ct.c_void_p], ct.c_int),
     "ddx_strerror": ([ct.c_int], ct.c_char_p),
     "ddx_last_error": ([ct.c_void_p], ct.c_char_p),
@@ -595,3 +602,65 @@ class Image:
             self.close()
         except Exception:
             pass
+
+
+def incoherent_delays(chan_freq_hz, t_samp_s, dms, k_dm=4.148808e15):
+    """Dispersion delays in samples relative to the highest channel, int32 [C, D]."""
+    f = np.ascontiguousarray(chan_freq_hz, dtype=np.float64)
+    d = np.ascontiguousarray(dms, dtype=np.float64)
+    out = np.empty((f.size, d.size), dtype=np.int32)
+    dp = ct.POINTER(ct.c_double)
+    rc = lib().ddx_incoherent_delays(f.size, f.ctypes.data_as(dp), float(t_samp_s), d.size, d.ctypes.data_as(dp),
+                                     float(k_dm), out.ctypes.data_as(ct.POINTER(ct.c_int32)))
+    if rc != OK:
+        raise DdxError(rc, "ddx_incoherent_delays")
+    return out
+
+
+def power_beam(volts, n_int, stream=None):
+    """volts: device complex64 [C, M, S]; returns device float32 [C, S // n_int]."""
+    import torch
+    if volts.dtype != torch.complex64 or volts.dim() != 3:
+        raise DdxError(EINVAL, "volts must be complex64 [C, M, S]")
+    volts = volts.contiguous()
+    C, M, S = volts.shape
+    out = torch.empty((C, S // n_int), dtype=torch.float32, device=volts.device)
+    rc = lib().ddx_power_beam(ct.c_void_p(volts.data_ptr()), C, M, S, int(n_int), ct.c_void_p(out.data_ptr()),
+                              _stream_handle(stream))
+    if rc != OK:
+        raise DdxError(rc, "ddx_power_beam")
+    return out
+
+
+def incoherent_dedisperse(power, delays, n_out, stream=None):
+    """power: device float32 [C, T]; delays: device int32 [C, D]; returns [D, n_out]."""
+    import torch
+    if power.dtype != torch.float32 or power.dim() != 2 or delays.dtype != torch.int32 or \
+            tuple(delays.shape[:1]) != (power.shape[0],):
+        raise DdxError(EINVAL, "power must be float32 [C, T] and delays int32 [C, D]")
+    power, delays = power.contiguous(), delays.contiguous()
+    out = torch.empty((delays.shape[1], int(n_out)), dtype=torch.float32, device=power.device)
+    rc = lib().ddx_incoherent_dedisperse(ct.c_void_p(power.data_ptr()), power.shape[0], power.shape[1],
+                                         ct.c_void_p(delays.data_ptr()), delays.shape[1],
+                                         ct.c_void_p(out.data_ptr()), int(n_out), _stream_handle(stream))
+    if rc != OK:
+        raise DdxError(rc, "ddx_incoherent_dedisperse")
+    return out
+
+
+def tree_dedisperse(power, out=None, work=None, stream=None):
+    """The tree method on device float32 [C, T] (C a power of two); returns [C, T]."""
+    import torch
+    if power.dtype != torch.float32 or power.dim() != 2:
+        raise DdxError(EINVAL, "power must be float32 [C, T]")
+    power = power.contiguous()
+    if out is None:
+        out = torch.empty_like(power)
+    if work is None:
+        work = torch.empty_like(power)
+    rc = lib().ddx_tree_dedisperse(ct.c_void_p(power.data_ptr()), power.shape[0], power.shape[1],
+                                   ct.c_void_p(out.data_ptr()), ct.c_void_p(work.data_ptr()),
+                                   _stream_handle(stream))
+    if rc != OK:
+        raise DdxError(rc, "ddx_tree_dedisperse")
+    return out

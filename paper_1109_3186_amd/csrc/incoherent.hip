@@ -1,0 +1,224 @@
+// Classical incoherent dedispersion of power beams on gfx950 (Bannister & Cornwell
+// 2011, Sec. 2.3.1 and 2.4.1): the power beam (detected power summed over antennas
+// and integrated), brute-force dedispersion over the delays of Eq. dmdelay, and the
+// tree method for linear sweeps.
+//
+//   p[c][t]   = sum_a sum_{n in [t n_int, (t + 1) n_int)} |x_{c,a}[n]|^2
+//   out[d][t] = sum_c p[c][t + delay[c][d]]                 (brute force, t < n_out)
+//   tree: log2 C merging stages; merging two groups of n/2 channels into n, sweep j
+//         = sweep floor(j/2) of the first + sweep floor(j/2) of the second advanced
+//         by j - floor(j/2) samples, so sweep j delays channel 0 by 0 and the last
+//         channel by j (linear dispersion, the assumption of the tree method).
+//
+// Channel 0 is the least delayed (highest frequency); samples past the end count
+// as zero.  All three are memory-bound streams: the brute force reads each power
+// sample once per DM through L1/L2 (neighbouring DMs read neighbouring samples),
+// the tree reads two rows and writes one per stage, the first stages fused in LDS.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "ddx.h"
+
+namespace inc {
+
+constexpr int kThreads = 256;
+constexpr int kDmPerThread = 4;     // brute force: DMs summed by one thread
+constexpr int kFuseLog = 5;         // tree: the first 5 stages (groups of 32 channels) in LDS
+constexpr int kFuseRows = 1 << kFuseLog;
+constexpr int kTreeTile = 256;      // tree: samples per fused tile
+
+// grid: (ceil(n_out / 256), ceil(n_dm / kDmPerThread)); thread = one sample t for
+// kDmPerThread consecutive DMs.
+__global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p, int32_t C, int64_t n_t,
+                                                    const int32_t* __restrict__ delays, int32_t n_dm,
+                                                    float* __restrict__ out, int64_t n_out) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int d0 = blockIdx.y * kDmPerThread;
+  if (t >= n_out) return;
+  float acc[kDmPerThread] = {};
+  for (int c = 0; c < C; ++c) {
+    const float* row = p + (int64_t)c * n_t;
+    const int32_t* dl = delays + (int64_t)c * n_dm;
+#pragma unroll
+    for (int i = 0; i < kDmPerThread; ++i) {
+      if (d0 + i < n_dm) {
+        const int64_t s = t + dl[d0 + i];
+        acc[i] += (s >= 0 && s < n_t) ? row[s] : 0.f;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kDmPerThread; ++i)
+    if (d0 + i < n_dm) out[(int64_t)(d0 + i) * n_out + t] = acc[i];
+}
+
+// The first kFuseLog tree stages of one group of 32 channels over a tile of
+// kTreeTile samples, in LDS.  A stage advances the second half by at most n/2
+// samples, so the tile reads kTreeTile + 31 samples of each channel (zero past the
+// end).  Rows of the group are combined in place, stage by stage.
+// grid: (ceil(n_t / kTreeTile), C / 32) x 256.
+__global__ __launch_bounds__(kThreads) void k_tree_fused(const float* __restrict__ in, float* __restrict__ out,
+                                                         int64_t n_t) {
+  constexpr int W = kTreeTile + kFuseRows;        // samples held per row (tile + halo)
+  __shared__ float buf[2][kFuseRows][W];
+  const int g = blockIdx.y;
+  const int64_t t0 = (int64_t)blockIdx.x * kTreeTile;
+  for (int e = threadIdx.x; e < kFuseRows * W; e += kThreads) {
+    const int r = e / W, x = e % W;
+    const int64_t t = t0 + x;
+    buf[0][r][x] = t < n_t ? in[((int64_t)g * kFuseRows + r) * n_t + t] : 0.f;
+  }
+  int cur = 0;
+#pragma unroll
+  for (int st = 1; st <= kFuseLog; ++st) {
+    const int n = 1 << st;
+    __syncthreads();
+    for (int e = threadIdx.x; e < kFuseRows * W; e += kThreads) {
+      const int r = e / W, x = e % W;
+      const int j = r % n, base = r - j;
+      const int h = j >> 1, s = j - h;
+      const float a = buf[cur][base + h][x];
+      const float b = x + s < W ? buf[cur][base + n / 2 + h][x + s] : 0.f;
+      buf[cur ^ 1][r][x] = a + b;
+    }
+    cur ^= 1;
+  }
+  __syncthreads();
+  // the halo columns past x = kTreeTile - 1 are incomplete after the shifts; only
+  // the tile itself is written
+  for (int e = threadIdx.x; e < kFuseRows * kTreeTile; e += kThreads) {
+    const int r = e / kTreeTile, x = e % kTreeTile;
+    const int64_t t = t0 + x;
+    if (t < n_t) out[((int64_t)g * kFuseRows + r) * n_t + t] = buf[cur][r][x];
+  }
+}
+
+// One later tree stage: groups of n = 2 half rows; row = g n + j.
+// grid: (ceil(n_t / 256), C) x 256.
+__global__ __launch_bounds__(kThreads) void k_tree_stage(const float* __restrict__ in, float* __restrict__ out,
+                                                         int64_t n_t, int32_t n) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= n_t) return;
+  const int row = blockIdx.y;
+  const int j = row % n, base = row - j;
+  const int h = j >> 1, s = j - h;
+  const float a = in[(int64_t)(base + h) * n_t + t];
+  const float b = t + s < n_t ? in[(int64_t)(base + n / 2 + h) * n_t + t + s] : 0.f;
+  out[(int64_t)row * n_t + t] = a + b;
+}
+
+// p[c][t] = sum over antennas and the n_int samples of interval t of |x|^2.
+// grid: (ceil(n_out / 256), C) x 256; thread = one interval.
+__global__ __launch_bounds__(kThreads) void k_power_beam(const float2* __restrict__ x, int32_t M, int64_t S,
+                                                         int32_t n_int, float* __restrict__ p, int64_t n_out) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= n_out) return;
+  const int c = blockIdx.y;
+  float acc = 0.f;
+  for (int a = 0; a < M; ++a) {
+    const float2* row = x + ((int64_t)c * M + a) * S + t * n_int;
+    for (int n = 0; n < n_int; ++n) {
+      const float2 v = row[n];
+      acc = fmaf(v.x, v.x, fmaf(v.y, v.y, acc));
+    }
+  }
+  p[(int64_t)c * n_out + t] = acc;
+}
+
+}  // namespace inc
+
+extern "C" {
+
+int ddx_incoherent_delays(int32_t n_chan, const double* chan_freq_hz, double t_samp_s, int32_t n_dm,
+                          const double* dm, double k_dm, int32_t* delays) {
+  if (n_chan < 1 || !chan_freq_hz || !(t_samp_s > 0.0) || n_dm < 1 || !dm || !delays || !(k_dm >= 0.0))
+    return DDX_EINVAL;
+  double top = chan_freq_hz[0];
+  for (int c = 0; c < n_chan; ++c) {
+    if (!(chan_freq_hz[c] > 0.0) || !std::isfinite(chan_freq_hz[c])) return DDX_EINVAL;
+    top = std::max(top, chan_freq_hz[c]);
+  }
+  for (int d = 0; d < n_dm; ++d)
+    if (!(dm[d] >= 0.0) || !std::isfinite(dm[d])) return DDX_EINVAL;
+  for (int c = 0; c < n_chan; ++c)
+    for (int d = 0; d < n_dm; ++d) {
+      const double sec = k_dm * dm[d] * (1.0 / (chan_freq_hz[c] * chan_freq_hz[c]) - 1.0 / (top * top));
+      const double v = std::nearbyint(sec / t_samp_s);
+      if (!(v <= (double)INT32_MAX)) return DDX_EUNSUPPORTED;
+      delays[(int64_t)c * n_dm + d] = (int32_t)v;
+    }
+  return DDX_OK;
+}
+
+int ddx_incoherent_dedisperse(const float* d_power, int32_t n_chan, int64_t n_t, const int32_t* d_delays,
+                              int32_t n_dm, float* d_out, int64_t n_out, void* hip_stream) {
+  if (n_chan < 1 || n_t < 0 || n_dm < 1 || n_out < 0 || !d_power || !d_delays || !d_out) return DDX_EINVAL;
+  if (n_out == 0) return DDX_OK;
+  const int64_t gx = (n_out + inc::kThreads - 1) / inc::kThreads;
+  const int64_t gy = (n_dm + inc::kDmPerThread - 1) / inc::kDmPerThread;
+  if (gx > INT32_MAX || gy > 65535) return DDX_EUNSUPPORTED;
+  hipLaunchKernelGGL(inc::k_brute, dim3((unsigned)gx, (unsigned)gy), dim3(inc::kThreads), 0, (hipStream_t)hip_stream,
+                     d_power, n_chan, n_t, d_delays, n_dm, d_out, n_out);
+  return hipGetLastError() == hipSuccess ? DDX_OK : DDX_EDEVICE;
+}
+
+int ddx_tree_dedisperse(const float* d_power, int32_t n_chan, int64_t n_t, float* d_out, float* d_work,
+                        void* hip_stream) {
+  if (n_chan < 1 || n_chan > 32768 || (n_chan & (n_chan - 1)) || n_t < 0 || !d_power || !d_out) return DDX_EINVAL;
+  if (n_t == 0) return DDX_OK;
+  const hipStream_t s = (hipStream_t)hip_stream;
+  int stages = 0;
+  while ((1 << stages) < n_chan) ++stages;
+  const int fused = n_chan >= inc::kFuseRows ? inc::kFuseLog : 0;
+  const int rest = stages - fused;
+  // work is needed whenever a stage does not write out directly
+  if ((fused ? rest >= 1 : stages >= 2) && !d_work) return DDX_EINVAL;
+  const int64_t gx = (n_t + inc::kThreads - 1) / inc::kThreads;
+  if (gx > INT32_MAX) return DDX_EUNSUPPORTED;
+  // the stages after the fused ones alternate between out and work, ending in out
+  float* first = (rest % 2 == 0) ? d_out : d_work;
+  if (n_chan >= inc::kFuseRows) {
+    const int64_t tx = (n_t + inc::kTreeTile - 1) / inc::kTreeTile;
+    hipLaunchKernelGGL(inc::k_tree_fused, dim3((unsigned)tx, (unsigned)(n_chan / inc::kFuseRows)),
+                       dim3(inc::kThreads), 0, s, d_power, first, n_t);
+  } else {
+    // fewer than 32 channels: every stage on its own, power -> ... -> out
+    const float* src = d_power;
+    for (int st = 1; st <= stages; ++st) {
+      float* dst = ((stages - st) % 2 == 0) ? d_out : d_work;
+      hipLaunchKernelGGL(inc::k_tree_stage, dim3((unsigned)gx, (unsigned)n_chan), dim3(inc::kThreads), 0, s, src,
+                         dst, n_t, 1 << st);
+      src = dst;
+    }
+    if (stages == 0)
+      if (hipMemcpyAsync(d_out, d_power, (size_t)n_t * sizeof(float), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return DDX_EDEVICE;
+    return hipGetLastError() == hipSuccess ? DDX_OK : DDX_EDEVICE;
+  }
+  const float* src = first;
+  for (int st = fused + 1; st <= stages; ++st) {
+    float* dst = (src == d_out) ? d_work : d_out;
+    hipLaunchKernelGGL(inc::k_tree_stage, dim3((unsigned)gx, (unsigned)n_chan), dim3(inc::kThreads), 0, s, src, dst,
+                       n_t, 1 << st);
+    src = dst;
+  }
+  return hipGetLastError() == hipSuccess ? DDX_OK : DDX_EDEVICE;
+}
+
+int ddx_power_beam(const void* d_volts, int32_t n_chan, int32_t n_ant, int64_t n_samp, int32_t n_int, float* d_power,
+                   void* hip_stream) {
+  if (n_chan < 1 || n_chan > 65535 || n_ant < 1 || n_samp < 0 || n_int < 1 || !d_volts || !d_power)
+    return DDX_EINVAL;
+  const int64_t n_out = n_samp / n_int;
+  if (n_out == 0) return DDX_OK;
+  const int64_t gx = (n_out + inc::kThreads - 1) / inc::kThreads;
+  if (gx > INT32_MAX) return DDX_EUNSUPPORTED;
+  hipLaunchKernelGGL(inc::k_power_beam, dim3((unsigned)gx, (unsigned)n_chan), dim3(inc::kThreads), 0,
+                     (hipStream_t)hip_stream, (const float2*)d_volts, n_ant, n_samp, n_int, d_power, n_out);
+  return hipGetLastError() == hipSuccess ? DDX_OK : DDX_EDEVICE;
+}
+
+}  // extern "C"

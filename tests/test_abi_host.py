@@ -224,3 +224,26 @@ def test_image_create_rejects_invalid_arguments():
     assert L.ddx_image_run(None, None, ct.c_int64(0), ct.c_int64(0), ct.c_int32(1), None, None, None) == binding.EINVAL
     n = ct.c_int64()
     assert L.ddx_image_output_count(None, ct.c_int64(5), ct.c_int32(2), ct.byref(n)) == binding.EINVAL
+
+
+def test_incoherent_delays_match_the_oracle_and_validate():
+    """The host delay table (Eq. dmdelay, FP64, ties to even) equals the oracle's
+    bit for bit; invalid arguments are rejected before any device work."""
+    from oracle import incoherent as oinc
+    f = 1.2005e9 + 1e6 * np.arange(64)[::-1]
+    dms = np.arange(256) * 2000.0 / 256
+    got = binding.incoherent_delays(f, 1e-3, dms)
+    assert np.array_equal(got, oinc.dm_delays(f, 1e-3, dms))
+    with pytest.raises(binding.DdxError):
+        binding.incoherent_delays(f, 0.0, dms)
+    with pytest.raises(binding.DdxError):
+        binding.incoherent_delays(f, 1e-3, [-1.0])
+    L = ct.CDLL(ddx.LIB_PATH)
+    assert L.ddx_tree_dedisperse(None, ct.c_int32(64), ct.c_int64(10), None, None, None) == binding.EINVAL
+    dummy = ct.c_void_p(8)   # never dereferenced: the size check fails first
+    assert L.ddx_tree_dedisperse(dummy, ct.c_int32(48), ct.c_int64(10), dummy, dummy, None) == binding.EINVAL
+    assert L.ddx_tree_dedisperse(dummy, ct.c_int32(64), ct.c_int64(10), dummy, None, None) == binding.EINVAL
+    assert L.ddx_incoherent_dedisperse(None, ct.c_int32(4), ct.c_int64(10), None, ct.c_int32(2), None,
+                                       ct.c_int64(5), None) == binding.EINVAL
+    assert L.ddx_power_beam(None, ct.c_int32(4), ct.c_int32(2), ct.c_int64(10), ct.c_int32(2), None,
+                            None) == binding.EINVAL
