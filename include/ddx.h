@@ -449,7 +449,7 @@ int ddx_incoherent_delays(int32_t n_chan, const double* chan_freq_hz, double t_s
 /* Brute-force incoherent dedispersion (Sec. 2.3.1): d_out[d][t] = sum_c
  * d_power[c][t + d_delays[c][d]] for t < n_out (samples outside [0, n_t) count as
  * zero).  d_delays: DEVICE [n_chan][n_dm] int32; d_out: DEVICE [n_dm][n_out].
- * DDX_EINVAL for invalid sizes or NULL buffers, DDX_EUNSUPPORTED above 262140 DMs
+ * DDX_EINVAL for invalid sizes or NULL buffers, DDX_EUNSUPPORTED above 2097120 DMs
  * per call. */
 int ddx_incoherent_dedisperse(const float* d_power, int32_t n_chan, int64_t n_t, const int32_t* d_delays,
                               int32_t n_dm, float* d_out, int64_t n_out, void* hip_stream);

@@ -11,9 +11,10 @@
 //         channel by j (linear dispersion, the assumption of the tree method).
 //
 // Channel 0 is the least delayed (highest frequency); samples past the end count
-// as zero.  All three are memory-bound streams: the brute force reads each power
-// sample once per DM through L1/L2 (neighbouring DMs read neighbouring samples),
-// the tree reads two rows and writes one per stage, the first stages fused in LDS.
+// as zero.  The brute force stages each channel's samples for a tile of 32 DMs in
+// LDS (one staged sample serves every DM of the tile); the tree is a memory-bound
+// stream, two rows read and one written per stage, its first five stages fused in
+// LDS.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -25,34 +26,81 @@
 namespace inc {
 
 constexpr int kThreads = 256;
-constexpr int kDmPerThread = 4;     // brute force: DMs summed by one thread
+constexpr int kDmTile = 32;         // brute force: DMs per workgroup (and per thread)
+constexpr int kChanGroup = 8;       // brute force: channels staged per LDS round
+constexpr int kSpan = 512;          // brute force: staged samples per channel
 constexpr int kFuseLog = 5;         // tree: the first 5 stages (groups of 32 channels) in LDS
 constexpr int kFuseRows = 1 << kFuseLog;
-constexpr int kTreeTile = 256;      // tree: samples per fused tile
+constexpr int kTreeTile = 224;      // tree: samples per fused tile (tile + 32 halo = 256, 64 KB of LDS)
 
-// grid: (ceil(n_out / 256), ceil(n_dm / kDmPerThread)); thread = one sample t for
-// kDmPerThread consecutive DMs.
+// grid: (ceil(n_out / 256), ceil(n_dm / kDmTile)); thread = one sample t for the
+// kDmTile DMs of the workgroup.  The workgroup's outputs read, per channel, the
+// samples t0 + [min delay, max delay + 255] over its DMs: staged in LDS for
+// kChanGroup channels at a time (each staged sample then serves every DM of the
+// tile), or read from global memory for a channel whose delays spread over more
+// than kSpan - 256 samples across the tile.
 __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p, int32_t C, int64_t n_t,
                                                     const int32_t* __restrict__ delays, int32_t n_dm,
                                                     float* __restrict__ out, int64_t n_out) {
-  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const int d0 = blockIdx.y * kDmPerThread;
-  if (t >= n_out) return;
-  float acc[kDmPerThread] = {};
-  for (int c = 0; c < C; ++c) {
-    const float* row = p + (int64_t)c * n_t;
-    const int32_t* dl = delays + (int64_t)c * n_dm;
+  __shared__ float buf[kChanGroup][kSpan];
+  __shared__ int lo_s[kChanGroup], hi_s[kChanGroup];
+  const int64_t t0 = (int64_t)blockIdx.x * kThreads;
+  const int64_t t = t0 + threadIdx.x;
+  const int d0 = blockIdx.y * kDmTile;
+  const int nd = min(kDmTile, n_dm - d0);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float acc[kDmTile] = {};
+  for (int c0 = 0; c0 < C; c0 += kChanGroup) {
+    const int nc = min(kChanGroup, C - c0);
+    __syncthreads();
+    // the delay range of each channel over the tile's DMs: one wave per channel,
+    // lane i holding DM d0 + i, min and max by butterfly
+    for (int ci = wv; ci < nc; ci += kThreads / 64) {
+      const int32_t* dl = delays + (int64_t)(c0 + ci) * n_dm + d0;
+      int lo = lane < nd ? dl[lane] : INT32_MAX;
+      int hi = lane < nd ? dl[lane] : INT32_MIN;
+      for (int o = 16; o > 0; o >>= 1) {
+        lo = min(lo, __shfl_xor(lo, o));
+        hi = max(hi, __shfl_xor(hi, o));
+      }
+      if (lane == 0) {
+        lo_s[ci] = lo;
+        hi_s[ci] = hi;
+      }
+    }
+    __syncthreads();
+    for (int ci = 0; ci < nc; ++ci) {
+      const int lo = lo_s[ci], hi = hi_s[ci];
+      if (hi - lo + kThreads > kSpan) continue;   // read from global below
+      const float* row = p + (int64_t)(c0 + ci) * n_t;
+      for (int x = threadIdx.x; x < hi - lo + kThreads; x += kThreads) {
+        const int64_t s = t0 + lo + x;
+        buf[ci][x] = (s >= 0 && s < n_t) ? row[s] : 0.f;
+      }
+    }
+    __syncthreads();
+    for (int ci = 0; ci < nc; ++ci) {
+      const int32_t* dl = delays + (int64_t)(c0 + ci) * n_dm + d0;
+      const int lo = lo_s[ci], hi = hi_s[ci];
+      if (hi - lo + kThreads <= kSpan) {
 #pragma unroll
-    for (int i = 0; i < kDmPerThread; ++i) {
-      if (d0 + i < n_dm) {
-        const int64_t s = t + dl[d0 + i];
-        acc[i] += (s >= 0 && s < n_t) ? row[s] : 0.f;
+        for (int i = 0; i < kDmTile; ++i)
+          if (i < nd) acc[i] += buf[ci][threadIdx.x + dl[i] - lo];
+      } else {
+        const float* row = p + (int64_t)(c0 + ci) * n_t;
+#pragma unroll
+        for (int i = 0; i < kDmTile; ++i)
+          if (i < nd) {
+            const int64_t s = t + dl[i];
+            acc[i] += (s >= 0 && s < n_t) ? row[s] : 0.f;
+          }
       }
     }
   }
+  if (t >= n_out) return;
 #pragma unroll
-  for (int i = 0; i < kDmPerThread; ++i)
-    if (d0 + i < n_dm) out[(int64_t)(d0 + i) * n_out + t] = acc[i];
+  for (int i = 0; i < kDmTile; ++i)
+    if (i < nd) out[(int64_t)(d0 + i) * n_out + t] = acc[i];
 }
 
 // The first kFuseLog tree stages of one group of 32 channels over a tile of
@@ -96,18 +144,24 @@ __global__ __launch_bounds__(kThreads) void k_tree_fused(const float* __restrict
   }
 }
 
-// One later tree stage: groups of n = 2 half rows; row = g n + j.
-// grid: (ceil(n_t / 256), C) x 256.
+// One later tree stage: groups of n = 2 half rows; row = g n + j.  Each thread
+// makes kStageVec samples 256 apart (the advanced row is read unaligned).
+// grid: (ceil(n_t / (256 kStageVec)), C) x 256.
+constexpr int kStageVec = 4;
 __global__ __launch_bounds__(kThreads) void k_tree_stage(const float* __restrict__ in, float* __restrict__ out,
                                                          int64_t n_t, int32_t n) {
-  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (t >= n_t) return;
   const int row = blockIdx.y;
   const int j = row % n, base = row - j;
   const int h = j >> 1, s = j - h;
-  const float a = in[(int64_t)(base + h) * n_t + t];
-  const float b = t + s < n_t ? in[(int64_t)(base + n / 2 + h) * n_t + t + s] : 0.f;
-  out[(int64_t)row * n_t + t] = a + b;
+  const float* ra = in + (int64_t)(base + h) * n_t;
+  const float* rb = in + (int64_t)(base + n / 2 + h) * n_t;
+  float* ro = out + (int64_t)row * n_t;
+  const int64_t t0 = (int64_t)blockIdx.x * kThreads * kStageVec + threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < kStageVec; ++i) {
+    const int64_t t = t0 + (int64_t)i * kThreads;  // each load instruction coalesced
+    if (t < n_t) ro[t] = ra[t] + (t + s < n_t ? rb[t + s] : 0.f);
+  }
 }
 
 // p[c][t] = sum over antennas and the n_int samples of interval t of |x|^2.
@@ -158,7 +212,7 @@ int ddx_incoherent_dedisperse(const float* d_power, int32_t n_chan, int64_t n_t,
   if (n_chan < 1 || n_t < 0 || n_dm < 1 || n_out < 0 || !d_power || !d_delays || !d_out) return DDX_EINVAL;
   if (n_out == 0) return DDX_OK;
   const int64_t gx = (n_out + inc::kThreads - 1) / inc::kThreads;
-  const int64_t gy = (n_dm + inc::kDmPerThread - 1) / inc::kDmPerThread;
+  const int64_t gy = (n_dm + inc::kDmTile - 1) / inc::kDmTile;
   if (gx > INT32_MAX || gy > 65535) return DDX_EUNSUPPORTED;
   hipLaunchKernelGGL(inc::k_brute, dim3((unsigned)gx, (unsigned)gy), dim3(inc::kThreads), 0, (hipStream_t)hip_stream,
                      d_power, n_chan, n_t, d_delays, n_dm, d_out, n_out);
@@ -176,7 +230,7 @@ int ddx_tree_dedisperse(const float* d_power, int32_t n_chan, int64_t n_t, float
   const int rest = stages - fused;
   // work is needed whenever a stage does not write out directly
   if ((fused ? rest >= 1 : stages >= 2) && !d_work) return DDX_EINVAL;
-  const int64_t gx = (n_t + inc::kThreads - 1) / inc::kThreads;
+  const int64_t gx = (n_t + (int64_t)inc::kThreads * inc::kStageVec - 1) / ((int64_t)inc::kThreads * inc::kStageVec);
   if (gx > INT32_MAX) return DDX_EUNSUPPORTED;
   // the stages after the fused ones alternate between out and work, ending in out
   float* first = (rest % 2 == 0) ? d_out : d_work;

@@ -3,7 +3,7 @@ ddx_incoherent_dedisperse, ddx_tree_dedisperse; Sec. 2.3.1, 2.4.1) against the
 FP64 oracle (oracle/incoherent.py).  The tree is checked bit for bit on integer
 power (every partial sum is exact in FP32), for channel counts below, at and above
 the 32-channel group fused in LDS, sample counts that are not a multiple of the
-256-sample tile, and an odd and even number of later stages.  The brute force and
+224-sample tile, and an odd and even number of later stages.  The brute force and
 the power beam are FP32 sums: held to 1e-6 of the sums' scale."""
 import numpy as np
 import pytest
@@ -39,13 +39,16 @@ def test_tree_recovers_an_impulse_on_a_sweep(gpu):
     assert got[j0, t0] == C and got.max() == C
 
 
-@pytest.mark.parametrize("C,D,T,cut", [(48, 37, 3000, True), (7, 5, 400, False), (256, 64, 2500, True)])
-def test_brute_force_matches_oracle(gpu, C, D, T, cut):
+@pytest.mark.parametrize("C,D,extra,cut", [(48, 37, 700, True), (7, 5, 300, False), (256, 64, 1000, True)])
+def test_brute_force_matches_oracle(gpu, C, D, extra, cut):
+    """T = the largest delay + extra; cut: only outputs whose every sample exists,
+    else all T outputs (the later ones sum zeros past the end)."""
     rng = np.random.Generator(np.random.PCG64(600 + C))
     f = 1.2e9 + 1e6 * np.arange(C)[::-1]
     dms = np.sort(rng.uniform(0, 800, D))
     dl = incoherent_delays(f, 1e-4, dms)
     assert np.array_equal(dl, oinc.dm_delays(f, 1e-4, dms))
+    T = int(dl.max()) + extra
     n_out = T - int(dl.max()) if cut else T
     p = rng.random((C, T))
     say("brute force: C %d D %d T %d n_out %d" % (C, D, T, n_out))
