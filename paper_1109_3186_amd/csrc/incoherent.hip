@@ -31,7 +31,7 @@ constexpr int kChanGroup = 8;       // brute force: channels staged per LDS roun
 constexpr int kSpan = 512;          // brute force: staged samples per channel
 constexpr int kFuseLog = 5;         // tree: the first 5 stages (groups of 32 channels) in LDS
 constexpr int kFuseRows = 1 << kFuseLog;
-constexpr int kTreeTile = 224;      // tree: samples per fused tile (tile + 32 halo = 256, 64 KB of LDS)
+constexpr int kTreeTile = 224;      // tree: samples per fused tile (tile + 32 halo = 256 per row)
 
 // grid: (ceil(n_out / 256), ceil(n_dm / kDmTile)); thread = one sample t for the
 // kDmTile DMs of the workgroup.  The workgroup's outputs read, per channel, the
@@ -44,6 +44,7 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p,
                                                     float* __restrict__ out, int64_t n_out) {
   __shared__ float buf[kChanGroup][kSpan];
   __shared__ int lo_s[kChanGroup], hi_s[kChanGroup];
+  __shared__ int dls[kChanGroup][kDmTile];   // the group's delays for the tile's DMs
   const int64_t t0 = (int64_t)blockIdx.x * kThreads;
   const int64_t t = t0 + threadIdx.x;
   const int d0 = blockIdx.y * kDmTile;
@@ -57,8 +58,10 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p,
     // lane i holding DM d0 + i, min and max by butterfly
     for (int ci = wv; ci < nc; ci += kThreads / 64) {
       const int32_t* dl = delays + (int64_t)(c0 + ci) * n_dm + d0;
-      int lo = lane < nd ? dl[lane] : INT32_MAX;
-      int hi = lane < nd ? dl[lane] : INT32_MIN;
+      const int mine = lane < nd ? dl[lane] : 0;
+      if (lane < kDmTile) dls[ci][lane] = mine;
+      int lo = lane < nd ? mine : INT32_MAX;
+      int hi = lane < nd ? mine : INT32_MIN;
       for (int o = 16; o > 0; o >>= 1) {
         lo = min(lo, __shfl_xor(lo, o));
         hi = max(hi, __shfl_xor(hi, o));
@@ -80,20 +83,21 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p,
     }
     __syncthreads();
     for (int ci = 0; ci < nc; ++ci) {
-      const int32_t* dl = delays + (int64_t)(c0 + ci) * n_dm + d0;
+      const int* dl = dls[ci];   // zero past nd: those sums are never written
       const int lo = lo_s[ci], hi = hi_s[ci];
       if (hi - lo + kThreads <= kSpan) {
+        // dl[i] lies in [lo, hi] for i < nd; the clamp keeps the unused i >= nd
+        // (dl = 0) inside the staged span too
+        const float* b = buf[ci] + threadIdx.x - lo;
 #pragma unroll
-        for (int i = 0; i < kDmTile; ++i)
-          if (i < nd) acc[i] += buf[ci][threadIdx.x + dl[i] - lo];
+        for (int i = 0; i < kDmTile; ++i) acc[i] += b[min(max(dl[i], lo), hi)];
       } else {
         const float* row = p + (int64_t)(c0 + ci) * n_t;
 #pragma unroll
-        for (int i = 0; i < kDmTile; ++i)
-          if (i < nd) {
-            const int64_t s = t + dl[i];
-            acc[i] += (s >= 0 && s < n_t) ? row[s] : 0.f;
-          }
+        for (int i = 0; i < kDmTile; ++i) {
+          const int64_t s = t + dl[i];
+          acc[i] += (s >= 0 && s < n_t) ? row[s] : 0.f;
+        }
       }
     }
   }
@@ -111,36 +115,53 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p,
 __global__ __launch_bounds__(kThreads) void k_tree_fused(const float* __restrict__ in, float* __restrict__ out,
                                                          int64_t n_t) {
   constexpr int W = kTreeTile + kFuseRows;        // samples held per row (tile + halo)
-  __shared__ float buf[2][kFuseRows][W];
+  constexpr int PER = kFuseRows * W / kThreads;   // elements per thread
+  // one buffer (32 KB, so that four workgroups share a CU): each stage reads its
+  // inputs into registers, then writes the stage's rows back after a barrier
+  __shared__ float buf[kFuseRows][W];
   const int g = blockIdx.y;
   const int64_t t0 = (int64_t)blockIdx.x * kTreeTile;
-  for (int e = threadIdx.x; e < kFuseRows * W; e += kThreads) {
+  float v[PER];
+  // all the tile's loads are issued before the first store (memory-level parallelism)
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * kThreads;
     const int r = e / W, x = e % W;
     const int64_t t = t0 + x;
-    buf[0][r][x] = t < n_t ? in[((int64_t)g * kFuseRows + r) * n_t + t] : 0.f;
+    v[q] = t < n_t ? in[((int64_t)g * kFuseRows + r) * n_t + t] : 0.f;
   }
-  int cur = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * kThreads;
+    buf[e / W][e % W] = v[q];
+  }
 #pragma unroll
   for (int st = 1; st <= kFuseLog; ++st) {
     const int n = 1 << st;
     __syncthreads();
-    for (int e = threadIdx.x; e < kFuseRows * W; e += kThreads) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * kThreads;
       const int r = e / W, x = e % W;
       const int j = r % n, base = r - j;
       const int h = j >> 1, s = j - h;
-      const float a = buf[cur][base + h][x];
-      const float b = x + s < W ? buf[cur][base + n / 2 + h][x + s] : 0.f;
-      buf[cur ^ 1][r][x] = a + b;
+      v[q] = buf[base + h][x] + (x + s < W ? buf[base + n / 2 + h][x + s] : 0.f);
     }
-    cur ^= 1;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * kThreads;
+      buf[e / W][e % W] = v[q];
+    }
   }
-  __syncthreads();
   // the halo columns past x = kTreeTile - 1 are incomplete after the shifts; only
-  // the tile itself is written
-  for (int e = threadIdx.x; e < kFuseRows * kTreeTile; e += kThreads) {
-    const int r = e / kTreeTile, x = e % kTreeTile;
+  // the tile itself is written (straight from the registers)
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * kThreads;
+    const int r = e / W, x = e % W;
     const int64_t t = t0 + x;
-    if (t < n_t) out[((int64_t)g * kFuseRows + r) * n_t + t] = buf[cur][r][x];
+    if (x < kTreeTile && t < n_t) out[((int64_t)g * kFuseRows + r) * n_t + t] = v[q];
   }
 }
 
