@@ -35,6 +35,7 @@ def log(*a):
 
 DEDISP_SOURCES = ("fft.hpp", "kernels.hpp", "ddx.hip", "tiles.hpp", "cnn_kernels.hpp", "cnn.hip")
 IMAGE_SOURCES = ("image.hip",)
+INCOHERENT_SOURCES = ("incoherent.hip",)
 
 
 def kernel_source_hash(sources=DEDISP_SOURCES):
@@ -368,10 +369,10 @@ def run_incoherent(args, dev):
     ms_brute = timed(lambda: incoherent_dedisperse(power, dl, n_out))
     tree_units = C * T * C / (ms_tree / 1e3)
     brute_units = C * n_out * D / (ms_brute / 1e3)
-    # tree: the fused first five stages read and write every row once, each later
-    # stage reads two rows and writes one
+    # tree: the fused first five stages read and write every row once, and so does
+    # each later stage (each input row feeds two output rows, read once through L2)
     stages = int(np.log2(C))
-    staged = 8.0 * C * T + 12.0 * C * T * (stages - 5)
+    staged = 8.0 * C * T * (1 + stages - 5)
     gbs = staged / (ms_tree / 1e3) / 1e9
     log("incoherent: tree %.2f ms (%.3e units/s, %.0f GB/s staged); brute force %.2f ms (%.3e units/s)" % (
         ms_tree, tree_units, gbs, ms_brute, brute_units))
@@ -394,7 +395,8 @@ def run_incoherent(args, dev):
            "config": {"workload": "incoherent dedispersion: 1024 ch x 2^18 samples, 1024 trials", "n_chan": C,
                       "samples": T, "trials": D, "parallelism": "none (1 GPU)"},
            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
-                        "frac": round(gbs / PEAKS["hbm_gbs"], 4), "traffic": None,
+                        "frac": round(gbs / PEAKS["hbm_gbs"], 4),
+                        "traffic": measured_traffic("tree", "incoherent", INCOHERENT_SOURCES),
                         "kernel": "k_tree_fused + k_tree_stage (one call)"},
            "cpu_baseline": cpu,
            "brute_force": {"ms_per_call": round(ms_brute, 3), "units_per_s": brute_units, "n_out": n_out,
