@@ -121,3 +121,36 @@ def test_end_to_end_on_bin_chirp(gpu):
         say("F %d: P at the source %.6e + %.2e i (ideal %.0f)" % (F, p[0, 2].real, p[0, 2].imag, ideal))
         assert abs(p[0, 2] - ideal) <= 1e-5 * ideal
         assert int(np.argmax(e[0])) == 2
+
+
+def test_bank_and_image_end_to_end(gpu):
+    """The Chirpolator on the device end to end: plane-wave chirp voltages through
+    the GPU bank of window lengths (with its factorisation) and the GPU image of
+    each length with its own chirp rate; the fraction of the ideal coherent sum
+    peaks at the true length and direction, and every length's image matches the
+    oracle's bank + image on the same voltages."""
+    import test_oracle_imaging as toi
+    from oracle import chirpolator as och
+    from paper_1109_3186_amd import ChirpBank
+    s, pos, grid, f_s, n0, n_len, d_true, L, kmax, w0 = toi._bank_scene(41)
+    x = torch.from_numpy(np.ascontiguousarray(s.astype(np.complex64))).to("cuda:0")
+    with ChirpBank(6, n0, n_len, L, kmax, max_samples=s.shape[1]) as b:
+        outs = b.run(x)
+        ref_bank = och.bank_direct(s, n0, n_len, L, kmax)
+        best = []
+        for d, (S, R) in enumerate(zip(outs, ref_bank), start=1):
+            fdot = f_s * f_s / (n0 * d)
+            with Image(pos, np.array(grid), fdot, f_s, n0 * d, L, kmax, 2) as h:
+                p, _ = h.run(S[w0:w0 + 1].contiguous(), first_window=w0, want_e=False)
+                torch.cuda.synchronize()
+            p = p.cpu().numpy()
+            ref = oim.image(R[w0:w0 + 1], pos, grid, fdot, f_s, n0 * d, L, kmax, 2, first_window=w0)
+            scale = n0 * d * 15
+            err = np.max(np.abs(p - ref)) / scale
+            say("length %d: max |P - oracle| / (N pairs) %.2e, best fraction %.3f" % (
+                d, err, np.abs(p).max() / scale))
+            assert err <= 1e-5
+            frac = np.abs(p[0]) / scale
+            best.append((frac.max(), d, int(np.argmax(frac))))
+    top = max(best)
+    assert top[1] == d_true and top[2] == 4 and top[0] > 0.7

@@ -133,3 +133,36 @@ def test_rows_follow_window_index():
     for i in range(3):
         Pi = im.image(S[3 * i:3 * i + 1], pos, pix, 1e10, F_S, N, L, kmax, 1, first_window=5 + 3 * i)
         np.testing.assert_allclose(P[i], Pi[0], rtol=1e-13)
+
+
+def _bank_scene(seed):
+    """Six antennas within 1.5 km, a chirp of rate f_s^2 / N_true (it sweeps the
+    whole band in one window of N_true samples, Sec. 3.2) from (l0, m0) whose
+    quadratic origin is at the start of window w0."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f_s, n0, n_len, d_true, L, kmax, w0 = 8e6, 64, 4, 3, 16, 12, 2
+    pos = _random_3d(rng, 6, 1500.0, 10.0)
+    l0, m0 = 0.06, -0.04
+    fdot = f_s * f_s / (n0 * d_true)
+    n_samp = n0 * n_len + (w0 + 2) * L
+    s, _ = _plane_wave_chirp(pos, n_samp, fdot, f_s, l0, m0, w0 * L)
+    grid = [(l0 + dl, m0 + dm) for dl in (-0.02, 0.0, 0.02) for dm in (-0.02, 0.0, 0.02)]
+    return s, pos, grid, f_s, n0, n_len, d_true, L, kmax, w0
+
+
+def test_bank_and_image_find_the_chirp_rate_and_direction():
+    """The Chirpolator end to end on the CPU: the bank of window lengths n0 d (one per
+    chirp rate, fdot_d = f_s^2 / (n0 d)) and the image of each length's window w0
+    with its own rate.  Each length's |P| is compared as a fraction of its ideal
+    coherent sum N_d M (M - 1) / 2 (Eq. pthsum), which grows with N_d: the largest
+    fraction is at the true length and the true direction, and is near 1 there."""
+    s, pos, grid, f_s, n0, n_len, d_true, L, kmax, w0 = _bank_scene(41)
+    bank = ch.bank_direct(s, n0, n_len, L, kmax)
+    npairs = 15
+    best = []
+    for d, S in enumerate(bank, start=1):
+        P = im.image(S[w0:w0 + 1], pos, grid, f_s * f_s / (n0 * d), f_s, n0 * d, L, kmax, 2, first_window=w0)
+        frac = np.abs(P[0]) / (n0 * d * npairs)
+        best.append((frac.max(), d, int(np.argmax(frac))))
+    top = max(best)
+    assert top[1] == d_true and top[2] == 4 and top[0] > 0.7
