@@ -23,7 +23,10 @@ what Bannister & Cornwell (2011), "The Chirpolator and The Chimageator", define:
   the matched filter over 2F + 1 bins and the vector sum over pairs;
 * in ``oracle.incoherent``, classical incoherent dedispersion of power beams
   (Sec. 2.3.1, 2.4.1): brute force over the delays of Eq. dmdelay, and the tree
-  method for linear sweeps.
+  method for linear sweeps;
+* in ``oracle.chimageator``, the Chimageator on a uniform linear array (Sec. 4):
+  gridding of redundant spacings, block integration, the spatial DFT and the
+  phase-corrected trajectory sums.
 
 Everything is numpy in float64 / complex128.  The oracle shares no code with the
 GPU path; only the seeded input generators (package ``synth``) serve both.
