@@ -464,6 +464,33 @@ int ddx_incoherent_dedisperse(const float* d_power, int32_t n_chan, int64_t n_t,
 int ddx_tree_dedisperse(const float* d_power, int32_t n_chan, int64_t n_t, float* d_out, float* d_work,
                         void* hip_stream);
 
+/* ---- The Chimageator on a uniform linear array (Sec. 4) --------------------------
+ * Stateless calls; caller-owned device buffers; asynchronous on hip_stream.
+ * Antenna p sits at p times the spacing along the line. */
+
+/* Pre-integrator: for every complete block m of L = block_len samples,
+ *   G_l[m] = w_l / L sum_{p < M - l} sum_{n in block m} s_p[n] s_{p+l}[n]^*  (l = 1 .. M - 1;
+ *            w_l = 1 / (M - l) if natural_weights, else 1: the gridding of Sec. 4),
+ *   Y_k[m] = sum_l G_l[m] exp(-2 pi i k l / N_s), k < N_s  (the spatial DFT).
+ * d_volts: DEVICE [n_ant][n] complex64; d_y: DEVICE [floor(n / L)][N_s] complex64.
+ * 2 <= n_ant <= 257; N_s a power of two <= 1024.  DDX_EINVAL otherwise. */
+int ddx_chimg_preintegrate(const void* d_volts, int32_t n_ant, int64_t n, int32_t block_len, int32_t n_s,
+                           int32_t natural_weights, void* d_y, void* hip_stream);
+
+/* Trajectory sums (Eq. chimg_pth) for trials i (end bin k_end[i], duration
+ * t_blocks[i] blocks) from every start block m0:
+ *   P[i][m0] = sum_{m=m0}^{m0+T-1} conj(Phi(x_m)) Y_{k_m}[m],
+ *   k0 = k_end ((m - m0) L + (L - 1) / 2) / (T L)  (the block average at its mean
+ *   sample), k_m = rint(k0) mod N_s (FP64, ties to even), x_m = k0 - rint(k0),
+ *   Phi(x) = exp(pi i M x / N_s);
+ * zero where m0 + T > n_blocks.  d_y as written by ddx_chimg_preintegrate; d_k_end
+ * (double) and d_t_blocks (int32): DEVICE [n_trials]; d_p: DEVICE [n_trials]
+ * [n_blocks] complex64.  DDX_EINVAL for invalid sizes or NULL buffers,
+ * DDX_EUNSUPPORTED above 65535 trials per call. */
+int ddx_chimg_trajectories(const void* d_y, int64_t n_blocks, int32_t n_ant, int32_t n_s, int32_t block_len,
+                           const double* d_k_end, const int32_t* d_t_blocks, int32_t n_trials, void* d_p,
+                           void* hip_stream);
+
 /* Synchronise the plan's last stream and free plan-owned memory.  NULL is a no-op. */
 int ddx_plan_destroy(ddx_plan* plan);
 

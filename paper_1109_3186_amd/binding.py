@@ -118,6 +118,10 @@ SIGNATURES = {
     "ddx_incoherent_dedisperse": ([ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_void_p, ct.c_int32, ct.c_void_p,
                                    ct.c_int64, ct.c_void_p], ct.c_int),
     "ddx_tree_dedisperse": ([ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p], ct.c_int),
+    "ddx_chimg_preintegrate": ([ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p,
+                                ct.c_void_p], ct.c_int),
+    "ddx_chimg_trajectories": ([ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p,
+                                ct.c_int32, ct.c_void_p, ct.c_void_p], ct.c_int),
     "ddx_plan_destroy": ([ct.c_void_p], ct.c_int),
     "ddx_strerror": ([ct.c_int], ct.c_char_p),
     "ddx_last_error": ([ct.c_void_p], ct.c_char_p),
@@ -664,3 +668,37 @@ def tree_dedisperse(power, out=None, work=None, stream=None):
     if rc != OK:
         raise DdxError(rc, "ddx_tree_dedisperse")
     return out
+
+
+def chimg_preintegrate(volts, block_len, n_s, natural=True, stream=None):
+    """The Chimageator pre-integrator on a uniform linear array: volts device
+    complex64 [M, n]; returns device complex64 Y [n // block_len, n_s]."""
+    import torch
+    if volts.dtype != torch.complex64 or volts.dim() != 2:
+        raise DdxError(EINVAL, "volts must be complex64 [M, n]")
+    volts = volts.contiguous()
+    M, n = volts.shape
+    y = torch.empty((n // block_len, n_s), dtype=torch.complex64, device=volts.device)
+    rc = lib().ddx_chimg_preintegrate(ct.c_void_p(volts.data_ptr()), M, n, int(block_len), int(n_s),
+                                      1 if natural else 0, ct.c_void_p(y.data_ptr()), _stream_handle(stream))
+    if rc != OK:
+        raise DdxError(rc, "ddx_chimg_preintegrate")
+    return y
+
+
+def chimg_trajectories(y, n_ant, block_len, k_end, t_blocks, stream=None):
+    """Trajectory sums P [trials, blocks] (complex64, device) for trials (k_end[i],
+    t_blocks[i]) over the pre-integrator output y [blocks, n_s]."""
+    import torch
+    if y.dtype != torch.complex64 or y.dim() != 2:
+        raise DdxError(EINVAL, "y must be complex64 [blocks, n_s]")
+    y = y.contiguous()
+    ke = torch.as_tensor(np.asarray(k_end, dtype=np.float64), device=y.device)
+    tb = torch.as_tensor(np.asarray(t_blocks, dtype=np.int32), device=y.device)
+    p = torch.empty((ke.numel(), y.shape[0]), dtype=torch.complex64, device=y.device)
+    rc = lib().ddx_chimg_trajectories(ct.c_void_p(y.data_ptr()), y.shape[0], int(n_ant), y.shape[1], int(block_len),
+                                      ct.c_void_p(ke.data_ptr()), ct.c_void_p(tb.data_ptr()), ke.numel(),
+                                      ct.c_void_p(p.data_ptr()), _stream_handle(stream))
+    if rc != OK:
+        raise DdxError(rc, "ddx_chimg_trajectories")
+    return p

@@ -5,7 +5,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", f) for f in ("ddx.hip", "cnn.hip", "chirp.hip", "image.hip", "incoherent.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("ddx.hip", "cnn.hip", "chirp.hip", "image.hip", "incoherent.hip", "chimg.hip")]
 LIB = os.path.join(HERE, "libddx.so")
 
 # Packed-FP32 VALU instructions are kept out of the generated code.

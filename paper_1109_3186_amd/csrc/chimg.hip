@@ -1,0 +1,149 @@
+// The Chimageator on a uniform linear array (Bannister & Cornwell 2011, Sec. 4) on
+// gfx950: mixing and gridding of redundant spacings, integration over blocks of L
+// samples (the pre-integrator), the spatial DFT of each block, and the
+// phase-corrected trajectory sums of the post-integrator (Eq. chimg_pth).
+//
+//   G_l[m]  = w_l / L sum_{p < M - l} sum_{n in block m} s_p[n] s_{p+l}[n]^*,  l = 1 .. M - 1
+//             (natural weights w_l = 1 / (M - l), or uniform w_l = 1)
+//   Y_k[m]  = sum_l G_l[m] exp(-2 pi i k l / N_s),  k < N_s
+//   P[i][m0] = sum_{m=m0}^{m0+T_i-1} conj(Phi(x_m)) Y_{k_m}[m],  k0 = k_end,i ((m - m0) L
+//             + (L - 1) / 2) / (T_i L), k_m = rint(k0) mod N_s, x_m = k0 - rint(k0),
+//             Phi(x) = exp(pi i M x / N_s)
+//
+// A block's gridded products are a small correlation (M antennas x L samples), so
+// one workgroup makes one block: the block's samples in LDS, one thread per
+// spacing, then one thread per spatial bin with a twiddle table in LDS.  The
+// trajectory sums are gathers along a line in (block, bin): one thread per (trial,
+// start block), the bin decided in FP64 like the plain definition.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "ddx.h"
+
+namespace chimg {
+
+constexpr int kThreads = 256;
+constexpr int kMaxAnt = kThreads + 1;     // spacings 1 .. M - 1, one thread each
+constexpr int kMaxBins = 1024;            // N_s
+constexpr int kStage = 5120;              // complex samples staged per round (40 KB)
+
+// grid: nb workgroups of 256 threads, one per block m.
+__global__ __launch_bounds__(kThreads) void k_pre(const float2* __restrict__ s, int32_t M, int64_t n, int32_t L,
+                                                  int32_t n_s, int32_t natural, float2* __restrict__ y) {
+  __shared__ float2 xs[kStage];
+  __shared__ float2 g[kMaxAnt];
+  __shared__ float2 tw[kMaxBins];
+  const int m = blockIdx.x;
+  const int tid = threadIdx.x;
+  for (int r = tid; r < n_s; r += kThreads) {
+    float sn, cs;
+    sincospif(2.0f * (float)r / (float)n_s, &sn, &cs);   // r / n_s exact for n_s a power of two
+    tw[r] = make_float2(cs, -sn);                        // exp(-2 pi i r / N_s)
+  }
+  const int l = tid + 1;   // this thread's spacing
+  float2 acc = make_float2(0.f, 0.f);
+  const int chunk = max(1, kStage / M);
+  for (int n0 = 0; n0 < L; n0 += chunk) {
+    const int len = min(chunk, L - n0);
+    __syncthreads();
+    for (int e = tid; e < M * len; e += kThreads) {
+      const int p = e / len, j = e - p * len;
+      xs[p * len + j] = s[(int64_t)p * n + (int64_t)m * L + n0 + j];
+    }
+    __syncthreads();
+    if (l < M) {
+      for (int p = 0; p + l < M; ++p) {
+        const float2* a = xs + p * len;
+        const float2* b = xs + (p + l) * len;
+        for (int j = 0; j < len; ++j) {   // a b^*
+          acc.x = fmaf(a[j].x, b[j].x, fmaf(a[j].y, b[j].y, acc.x));
+          acc.y = fmaf(a[j].y, b[j].x, fmaf(-a[j].x, b[j].y, acc.y));
+        }
+      }
+    }
+  }
+  if (l < M) {
+    const float w = (natural ? 1.0f / (float)(M - l) : 1.0f) / (float)L;
+    g[l - 1] = make_float2(acc.x * w, acc.y * w);
+  }
+  __syncthreads();
+  for (int k = tid; k < n_s; k += kThreads) {
+    float2 v = make_float2(0.f, 0.f);
+    for (int q = 1; q < M; ++q) {
+      const float2 a = g[q - 1];
+      const float2 t = tw[(int)(((int64_t)k * q) % n_s)];
+      v.x = fmaf(a.x, t.x, fmaf(-a.y, t.y, v.x));
+      v.y = fmaf(a.x, t.y, fmaf(a.y, t.x, v.y));
+    }
+    y[(int64_t)m * n_s + k] = v;
+  }
+}
+
+// grid: (ceil(nb / 256), n_trials) x 256; thread = start block m0 of trial i.
+__global__ __launch_bounds__(kThreads) void k_traj(const float2* __restrict__ y, int64_t nb, int32_t M,
+                                                   int32_t n_s, int32_t L, const double* __restrict__ k_end,
+                                                   const int32_t* __restrict__ t_blocks, float2* __restrict__ p) {
+  const int64_t m0 = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (m0 >= nb) return;
+  const int i = blockIdx.y;
+  const int tb = t_blocks[i];
+  const double ke = k_end[i];
+  float2 acc = make_float2(0.f, 0.f);
+  if (tb >= 1 && m0 + tb <= nb) {
+    for (int q = 0; q < tb; ++q) {
+      double k0;
+      {
+#pragma clang fp contract(off)
+        // the plain definition's operation order, so that rint(k0) is decided alike
+        k0 = ke * ((double)((int64_t)q * L) + (L - 1) / 2.0) / (double)((int64_t)tb * L);
+      }
+      const double kr = rint(k0);
+      const float x = (float)(k0 - kr);
+      int64_t kb = (int64_t)kr % n_s;
+      if (kb < 0) kb += n_s;
+      float sn, cs;
+      sincospif(-(float)M * x / (float)n_s, &sn, &cs);    // conj(Phi(x))
+      const float2 v = y[(m0 + q) * n_s + kb];
+      acc.x += v.x * cs - v.y * sn;
+      acc.y += v.x * sn + v.y * cs;
+    }
+  }
+  p[(int64_t)i * nb + m0] = acc;
+}
+
+}  // namespace chimg
+
+extern "C" {
+
+int ddx_chimg_preintegrate(const void* d_volts, int32_t n_ant, int64_t n, int32_t block_len, int32_t n_s,
+                           int32_t natural_weights, void* d_y, void* hip_stream) {
+  if (n_ant < 2 || n_ant > chimg::kMaxAnt || n < 0 || block_len < 1 || n_s < 1 || n_s > chimg::kMaxBins ||
+      (n_s & (n_s - 1)) || !d_volts || !d_y)
+    return DDX_EINVAL;
+  const int64_t nb = n / block_len;
+  if (nb == 0) return DDX_OK;
+  if (nb > INT32_MAX) return DDX_EUNSUPPORTED;
+  hipLaunchKernelGGL(chimg::k_pre, dim3((unsigned)nb), dim3(chimg::kThreads), 0, (hipStream_t)hip_stream,
+                     (const float2*)d_volts, n_ant, n, block_len, n_s, natural_weights ? 1 : 0, (float2*)d_y);
+  return hipGetLastError() == hipSuccess ? DDX_OK : DDX_EDEVICE;
+}
+
+int ddx_chimg_trajectories(const void* d_y, int64_t n_blocks, int32_t n_ant, int32_t n_s, int32_t block_len,
+                           const double* d_k_end, const int32_t* d_t_blocks, int32_t n_trials, void* d_p,
+                           void* hip_stream) {
+  if (!d_y || n_blocks < 0 || n_ant < 2 || n_s < 1 || block_len < 1 || !d_k_end || !d_t_blocks || n_trials < 1 ||
+      !d_p)
+    return DDX_EINVAL;
+  if (n_blocks == 0) return DDX_OK;
+  const int64_t gx = (n_blocks + chimg::kThreads - 1) / chimg::kThreads;
+  if (gx > INT32_MAX || n_trials > 65535) return DDX_EUNSUPPORTED;
+  hipLaunchKernelGGL(chimg::k_traj, dim3((unsigned)gx, (unsigned)n_trials), dim3(chimg::kThreads), 0,
+                     (hipStream_t)hip_stream, (const float2*)d_y, n_blocks, n_ant, n_s, block_len, d_k_end, d_t_blocks,
+                     (float2*)d_p);
+  return hipGetLastError() == hipSuccess ? DDX_OK : DDX_EDEVICE;
+}
+
+}  // extern "C"

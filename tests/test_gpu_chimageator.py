@@ -1,0 +1,60 @@
+"""GPU parity of the Chimageator on a uniform linear array (ddx_chimg_*, Sec. 4)
+against the FP64 oracle (oracle/chimageator.py): the pre-integrator (gridding,
+block integration, spatial DFT) for natural and uniform weights, antenna counts up
+to the 257 limit, blocks longer than one LDS round; the trajectory sums for ragged
+trial sets and starts near the end; and end to end, a chirp on the array found at
+its slope, end bin and start.  Bound: FP32 sums -> 1e-5 of the outputs' scale."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import say
+from oracle import chimageator as ocg
+from paper_1109_3186_amd import chimg_preintegrate, chimg_trajectories
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a.astype(np.complex64))).to("cuda:0")
+
+
+@pytest.mark.parametrize("M,L,n_s,extra,natural", [(8, 16, 16, 5, True), (33, 40, 64, 0, False),
+                                                   (257, 24, 256, 3, True), (16, 700, 32, 11, True)])
+def test_preintegrator_matches_oracle(gpu, M, L, n_s, extra, natural):
+    s = synth.noise_complex(np.random.Generator(np.random.PCG64(800 + M)), (M, 7 * L + extra))
+    say("chimageator pre: M %d L %d N_s %d" % (M, L, n_s))
+    got = chimg_preintegrate(_dev(s), L, n_s, natural).cpu().numpy()
+    ref = ocg.spatial_dft(ocg.grid_blocks(s, L, "natural" if natural else "uniform"), n_s)
+    assert got.shape == ref.shape
+    err = np.max(np.abs(got - ref)) / np.sqrt(np.mean(np.abs(ref) ** 2))
+    say("max error / rms %.3e" % err)
+    assert err <= 1e-5
+
+
+def test_trajectories_match_oracle(gpu):
+    rng = np.random.Generator(np.random.PCG64(810))
+    M, n_s, L, nb = 12, 32, 8, 60
+    Y = synth.noise_complex(rng, (nb, n_s))
+    trials = [(9.0, 24), (5.3, 40), (-3.7, 7), (31.2, 60), (0.0, 1), (12.5, 61)]
+    got = chimg_trajectories(_dev(Y), M, L, [t[0] for t in trials], [t[1] for t in trials]).cpu().numpy()
+    ref = ocg.trajectories(Y, M, n_s, trials, L)
+    err = np.max(np.abs(got - ref)) / np.sqrt(max(t[1] for t in trials))
+    say("trajectories: max error / sqrt(T) %.3e" % err)
+    assert err <= 1e-5
+    assert np.all(got[5] == 0)        # the 61-block trial fits nowhere in 60 blocks
+
+
+def test_chirp_found_end_to_end(gpu):
+    import test_oracle_chimageator as toc
+    M, n_s, L, f_s = 16, 32, 16, 1e6
+    tb, m0, k_end = 24, 5, 9.0
+    tau1 = k_end / (n_s * f_s)
+    s = toc.ula_chirp(M, (m0 + tb + 6) * L, f_s, tb * L, tau1, m0 * L)
+    y = chimg_preintegrate(_dev(s), L, n_s)
+    trials = [(k_end + dk, tb + dt) for dk in (-1.0, 0.0, 1.0) for dt in (-6, 0, 6)]
+    P = np.abs(chimg_trajectories(y, M, L, [t[0] for t in trials], [t[1] for t in trials]).cpu().numpy())
+    i, m = np.unravel_index(np.argmax(P), P.shape)
+    say("best trial %s at block %d: |P| %.1f of %d" % (trials[i], m, P[i, m], (M - 1) * tb))
+    assert trials[i] == (k_end, tb) and m == m0 and P[i, m] > 0.85 * (M - 1) * tb

@@ -4,9 +4,7 @@ spacings (a library routine), the phase term against the closed form of a spatia
 tone's DFT, and the trajectory sum of a chirp arriving on a uniform linear array,
 whose mixed products are synthesised here from the antennas' arrival times: the
 true (end bin, duration, start) gives the largest |P| of a grid of trials and
-nearly the ideal (M - 1) T_b (the synthetic chirp is unending, so trials are
-compared at other slopes, end bins and starts, not at longer runs of the same
-slope)."""
+nearly the ideal (M - 1) T_b."""
 import numpy as np
 import pytest
 
@@ -52,10 +50,13 @@ def test_phase_of_a_spatial_tone():
 
 def ula_chirp(M, n_samp, f_s, t_samples, tau1, start):
     """Voltages of a chirp sweeping the band f_s in t_samples samples (fdot = f_s^2 /
-    t_samples), starting at sample `start`, reaching antenna p a time p tau1 late."""
+    t_samples), starting at sample `start` and lasting t_samples samples, reaching
+    antenna p a time p tau1 late (zero outside its duration at each antenna)."""
     fdot = f_s * f_s / t_samples
     t = (np.arange(n_samp) - start) / f_s
-    return np.exp(1j * np.pi * fdot * (t[None, :] - (np.arange(M) * tau1)[:, None]) ** 2)
+    tp = t[None, :] - (np.arange(M) * tau1)[:, None]
+    on = (tp >= 0) & (tp < t_samples / f_s)
+    return np.where(on, np.exp(1j * np.pi * fdot * tp ** 2), 0)
 
 
 def test_trajectory_finds_the_chirp():
@@ -77,6 +78,11 @@ def test_trajectory_finds_the_chirp():
         assert abs(cg.trajectory(Y, M, n_s, k_end, tb, m0 + dm, L)) < abs(best)
     P = cg.trajectories(Y, M, n_s, [(k_end, tb), (k_end + 2, tb)], L)
     assert int(np.argmax(np.abs(P[0]))) == m0 and np.all(P[:, Y.shape[0] - tb + 1:] == 0)
+    # over a grid of end bins x durations and every start, the true trial wins
+    trials = [(k_end + dk, tb + dt) for dk in (-1.0, 0.0, 1.0) for dt in (-6, 0, 6)]
+    Pg = np.abs(cg.trajectories(Y, M, n_s, trials, L))
+    i, m = np.unravel_index(np.argmax(Pg), Pg.shape)
+    assert trials[i] == (k_end, tb) and m == m0
 
 
 @pytest.mark.parametrize("k_end,tb", [(9.0, 24), (5.3, 40), (17.0, 11)])
