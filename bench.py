@@ -405,6 +405,61 @@ def run_incoherent(args, dev):
     print(json.dumps(rec), flush=True)
 
 
+def run_chimg(args, dev):
+    """The Chimageator (Sec. 4) on a uniform linear array of 64 antennas: 2^22
+    unit-variance complex samples, blocks of L = 64 samples (65 536 blocks), a
+    128-bin spatial DFT, and trajectory sums for 256 trials (end bins -32..31 x
+    durations 64, 128, 256, 512 blocks) from every start block.  One step = the
+    pre-integrator call + the trajectory call; HIP events on the launch stream."""
+    import numpy as np
+    import torch
+
+    from paper_1109_3186_amd import chimg_preintegrate, chimg_trajectories
+    M, n, L, n_s = 64, 1 << 22, 64, 128
+    g = torch.Generator(device=dev)
+    g.manual_seed(1114)
+    volts = torch.randn((M, n), dtype=torch.complex64, device=dev, generator=g)
+    trials = [(float(ke), tb) for tb in (64, 128, 256, 512) for ke in range(-32, 32)]
+    ke = [t[0] for t in trials]
+    tb = [t[1] for t in trials]
+
+    def timed(run):
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    y = chimg_preintegrate(volts, L, n_s)
+    ms_pre = timed(lambda: chimg_preintegrate(volts, L, n_s))
+    ms_traj = timed(lambda: chimg_trajectories(y, M, L, ke, tb))
+    nb = n // L
+    macs = nb * L * M * (M - 1) / 2.0                  # gridded products per call
+    tf = 8.0 * macs / (ms_pre / 1e3) / 1e12
+    gathers = sum(max(0, nb - t + 1) * t for t in tb)
+    log("chimg: pre %.2f ms (%.1f TFLOP/s of products), trajectories %.2f ms (%.3e gathers/s)" % (
+        ms_pre, tf, ms_traj, gathers / (ms_traj / 1e3)))
+    rec = {"metric": "antenna-samples/s through the Chimageator pre-integrator", "value": M * n / (ms_pre / 1e3),
+           "unit": "antenna-samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms_pre + ms_traj, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "Chimageator: 64-antenna uniform line, 2^22 samples, L 64, 128 bins, 256 trials",
+                      "n_ant": M, "samples": n, "block_len": L, "n_bins": n_s, "trials": len(trials),
+                      "parallelism": "none (1 GPU)"},
+           "roofline": {"bound": "alu", "achieved": round(tf, 2), "peak": PEAKS["fp32_vector_tflops"],
+                        "unit": "TFLOP/s", "frac": round(tf / PEAKS["fp32_vector_tflops"], 4), "traffic": None,
+                        "kernel": "k_pre (gridded products + spatial DFT)"},
+           "cpu_baseline": None,
+           "trajectories": {"ms_per_call": round(ms_traj, 3), "gathers_per_s": gathers / (ms_traj / 1e3),
+                            "trials": len(trials)}}
+    print(json.dumps(rec), flush=True)
+
+
 def run_c3(args, dev):
     """The batched sparse-array workload: 256 antennas, 32 x 1 MHz channels at
     0.7-0.732 GHz, 2^18 ci8 samples, per-channel DM grids of 512..1536 trials over
@@ -554,10 +609,11 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal measurement")
     ap.add_argument("--wave-units", type=int, default=0, help="schedule: units per wave (0 = automatic)")
     ap.add_argument("--dm-group", type=int, default=0, help="schedule: DMs per block group (0 = automatic)")
-    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "chirp", "incoherent"],
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "chirp", "incoherent", "chimg"],
                     help="c1: 36-antenna headline workload (default); c3: 256-antenna batched sparse array; "
                          "chirp: the Chirpolator pre-integrator and image; incoherent: classical incoherent "
-                         "dedispersion of a power spectrogram (brute force and tree)")
+                         "dedispersion of a power spectrogram (brute force and tree); chimg: the Chimageator on a "
+                         "uniform linear array")
     ap.add_argument("--autotune", action="store_true", help="use the autotuned lengths and schedule (cached)")
     ap.add_argument("--passes", type=int, default=0, help="c3: DM-window passes (0 = ceil(sum D / 512))")
     ap.add_argument("--channels", type=int, default=0,
@@ -583,6 +639,8 @@ def main():
         return run_chirp(args, dev)
     if args.workload == "incoherent":
         return run_incoherent(args, dev)
+    if args.workload == "chimg":
+        return run_chimg(args, dev)
     if args.copy_calibration:
         src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)
         dst = torch.mul(src, 1.0)  # reads and writes copy_calibration MiB each

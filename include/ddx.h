@@ -472,7 +472,8 @@ int ddx_tree_dedisperse(const float* d_power, int32_t n_chan, int64_t n_t, float
  *   G_l[m] = w_l / L sum_{p < M - l} sum_{n in block m} s_p[n] s_{p+l}[n]^*  (l = 1 .. M - 1;
  *            w_l = 1 / (M - l) if natural_weights, else 1: the gridding of Sec. 4),
  *   Y_k[m] = sum_l G_l[m] exp(-2 pi i k l / N_s), k < N_s  (the spatial DFT).
- * d_volts: DEVICE [n_ant][n] complex64; d_y: DEVICE [floor(n / L)][N_s] complex64.
+ * d_volts: DEVICE [n_ant][n] complex64; d_y: DEVICE [N_s][floor(n / L)] complex64
+ * (bin-major: a trajectory reads along blocks).
  * 2 <= n_ant <= 257; N_s a power of two <= 1024.  DDX_EINVAL otherwise. */
 int ddx_chimg_preintegrate(const void* d_volts, int32_t n_ant, int64_t n, int32_t block_len, int32_t n_s,
                            int32_t natural_weights, void* d_y, void* hip_stream);

@@ -672,13 +672,13 @@ def tree_dedisperse(power, out=None, work=None, stream=None):
 
 def chimg_preintegrate(volts, block_len, n_s, natural=True, stream=None):
     """The Chimageator pre-integrator on a uniform linear array: volts device
-    complex64 [M, n]; returns device complex64 Y [n // block_len, n_s]."""
+    complex64 [M, n]; returns device complex64 Y [n_s, n // block_len] (bin-major)."""
     import torch
     if volts.dtype != torch.complex64 or volts.dim() != 2:
         raise DdxError(EINVAL, "volts must be complex64 [M, n]")
     volts = volts.contiguous()
     M, n = volts.shape
-    y = torch.empty((n // block_len, n_s), dtype=torch.complex64, device=volts.device)
+    y = torch.empty((n_s, n // block_len), dtype=torch.complex64, device=volts.device)
     rc = lib().ddx_chimg_preintegrate(ct.c_void_p(volts.data_ptr()), M, n, int(block_len), int(n_s),
                                       1 if natural else 0, ct.c_void_p(y.data_ptr()), _stream_handle(stream))
     if rc != OK:
@@ -688,15 +688,15 @@ def chimg_preintegrate(volts, block_len, n_s, natural=True, stream=None):
 
 def chimg_trajectories(y, n_ant, block_len, k_end, t_blocks, stream=None):
     """Trajectory sums P [trials, blocks] (complex64, device) for trials (k_end[i],
-    t_blocks[i]) over the pre-integrator output y [blocks, n_s]."""
+    t_blocks[i]) over the pre-integrator output y [n_s, blocks]."""
     import torch
     if y.dtype != torch.complex64 or y.dim() != 2:
-        raise DdxError(EINVAL, "y must be complex64 [blocks, n_s]")
+        raise DdxError(EINVAL, "y must be complex64 [n_s, blocks]")
     y = y.contiguous()
     ke = torch.as_tensor(np.asarray(k_end, dtype=np.float64), device=y.device)
     tb = torch.as_tensor(np.asarray(t_blocks, dtype=np.int32), device=y.device)
-    p = torch.empty((ke.numel(), y.shape[0]), dtype=torch.complex64, device=y.device)
-    rc = lib().ddx_chimg_trajectories(ct.c_void_p(y.data_ptr()), y.shape[0], int(n_ant), y.shape[1], int(block_len),
+    p = torch.empty((ke.numel(), y.shape[1]), dtype=torch.complex64, device=y.device)
+    rc = lib().ddx_chimg_trajectories(ct.c_void_p(y.data_ptr()), y.shape[1], int(n_ant), y.shape[0], int(block_len),
                                       ct.c_void_p(ke.data_ptr()), ct.c_void_p(tb.data_ptr()), ke.numel(),
                                       ct.c_void_p(p.data_ptr()), _stream_handle(stream))
     if rc != OK:

@@ -11,8 +11,9 @@
 //             Phi(x) = exp(pi i M x / N_s)
 //
 // A block's gridded products are a small correlation (M antennas x L samples), so
-// one workgroup makes one block: the block's samples in LDS, one thread per
-// spacing, then one thread per spatial bin with a twiddle table in LDS.  The
+// one workgroup makes one block: the block's samples in LDS, each thread a
+// (spacing, sample phase) share of the products, then one thread per spatial bin
+// with a twiddle table in LDS.  The
 // trajectory sums are gathers along a line in (block, bin): one thread per (trial,
 // start block), the bin decided in FP64 like the plain definition.
 #include <hip/hip_runtime.h>
@@ -26,7 +27,7 @@
 namespace chimg {
 
 constexpr int kThreads = 256;
-constexpr int kMaxAnt = kThreads + 1;     // spacings 1 .. M - 1, one thread each
+constexpr int kMaxAnt = kThreads + 1;     // spacings 1 .. M - 1, at least one thread each
 constexpr int kMaxBins = 1024;            // N_s
 constexpr int kStage = 5120;              // complex samples staged per round (40 KB)
 
@@ -43,7 +44,10 @@ __global__ __launch_bounds__(kThreads) void k_pre(const float2* __restrict__ s, 
     sincospif(2.0f * (float)r / (float)n_s, &sn, &cs);   // r / n_s exact for n_s a power of two
     tw[r] = make_float2(cs, -sn);                        // exp(-2 pi i r / N_s)
   }
-  const int l = tid + 1;   // this thread's spacing
+  // thread (spacing l, phase ph): the samples j = ph, ph + S, ... of every pair at
+  // spacing l, S = floor(256 / (M - 1)) phases so that all threads work
+  const int S = max(1, kThreads / (M - 1));
+  const int l = tid / S + 1, ph = tid % S;
   float2 acc = make_float2(0.f, 0.f);
   const int chunk = max(1, kStage / M);
   for (int n0 = 0; n0 < L; n0 += chunk) {
@@ -58,16 +62,27 @@ __global__ __launch_bounds__(kThreads) void k_pre(const float2* __restrict__ s, 
       for (int p = 0; p + l < M; ++p) {
         const float2* a = xs + p * len;
         const float2* b = xs + (p + l) * len;
-        for (int j = 0; j < len; ++j) {   // a b^*
+        for (int j = ph; j < len; j += S) {   // a b^*
           acc.x = fmaf(a[j].x, b[j].x, fmaf(a[j].y, b[j].y, acc.x));
           acc.y = fmaf(a[j].y, b[j].x, fmaf(-a[j].x, b[j].y, acc.y));
         }
       }
     }
   }
-  if (l < M) {
-    const float w = (natural ? 1.0f / (float)(M - l) : 1.0f) / (float)L;
-    g[l - 1] = make_float2(acc.x * w, acc.y * w);
+  // the phases of each spacing, summed in a fixed order
+  __syncthreads();
+  float2* part = xs;   // the staged samples are no longer needed
+  if (l < M) part[tid] = acc;
+  __syncthreads();
+  if (tid < M - 1) {
+    float2 v = make_float2(0.f, 0.f);
+    for (int q = 0; q < S; ++q) {
+      const float2 a = part[tid * S + q];
+      v.x += a.x;
+      v.y += a.y;
+    }
+    const float w = (natural ? 1.0f / (float)(M - 1 - tid) : 1.0f) / (float)L;
+    g[tid] = make_float2(v.x * w, v.y * w);
   }
   __syncthreads();
   for (int k = tid; k < n_s; k += kThreads) {
@@ -78,27 +93,35 @@ __global__ __launch_bounds__(kThreads) void k_pre(const float2* __restrict__ s, 
       v.x = fmaf(a.x, t.x, fmaf(-a.y, t.y, v.x));
       v.y = fmaf(a.x, t.y, fmaf(a.y, t.x, v.y));
     }
-    y[(int64_t)m * n_s + k] = v;
+    y[(int64_t)k * gridDim.x + m] = v;   // bin-major: a trajectory reads along blocks
   }
 }
 
-// grid: (ceil(nb / 256), n_trials) x 256; thread = start block m0 of trial i.
+// grid: (ceil(nb / 256), n_trials) x 256; thread = start block m0 of trial i.  The
+// bin k_q and phase conj(Phi(x_q)) of step q depend on the trial only: they are
+// made once per workgroup in LDS (kSteps at a time), and every thread then reads
+// Y[k_q][m0 + q], contiguous across the threads.
+constexpr int kSteps = 1024;
 __global__ __launch_bounds__(kThreads) void k_traj(const float2* __restrict__ y, int64_t nb, int32_t M,
                                                    int32_t n_s, int32_t L, const double* __restrict__ k_end,
                                                    const int32_t* __restrict__ t_blocks, float2* __restrict__ p) {
+  __shared__ int kq[kSteps];
+  __shared__ float2 cq[kSteps];
   const int64_t m0 = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (m0 >= nb) return;
   const int i = blockIdx.y;
   const int tb = t_blocks[i];
   const double ke = k_end[i];
+  const bool live = tb >= 1 && m0 + tb <= nb;
   float2 acc = make_float2(0.f, 0.f);
-  if (tb >= 1 && m0 + tb <= nb) {
-    for (int q = 0; q < tb; ++q) {
+  for (int q0 = 0; q0 < tb; q0 += kSteps) {
+    const int nq = min(kSteps, tb - q0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < nq; q += kThreads) {
       double k0;
       {
 #pragma clang fp contract(off)
         // the plain definition's operation order, so that rint(k0) is decided alike
-        k0 = ke * ((double)((int64_t)q * L) + (L - 1) / 2.0) / (double)((int64_t)tb * L);
+        k0 = ke * ((double)((int64_t)(q0 + q) * L) + (L - 1) / 2.0) / (double)((int64_t)tb * L);
       }
       const double kr = rint(k0);
       const float x = (float)(k0 - kr);
@@ -106,12 +129,20 @@ __global__ __launch_bounds__(kThreads) void k_traj(const float2* __restrict__ y,
       if (kb < 0) kb += n_s;
       float sn, cs;
       sincospif(-(float)M * x / (float)n_s, &sn, &cs);    // conj(Phi(x))
-      const float2 v = y[(m0 + q) * n_s + kb];
-      acc.x += v.x * cs - v.y * sn;
-      acc.y += v.x * sn + v.y * cs;
+      kq[q] = (int)kb;
+      cq[q] = make_float2(cs, sn);
+    }
+    __syncthreads();
+    if (live) {
+      for (int q = 0; q < nq; ++q) {
+        const float2 v = y[(int64_t)kq[q] * nb + m0 + q0 + q];
+        const float2 c = cq[q];
+        acc.x += v.x * c.x - v.y * c.y;
+        acc.y += v.x * c.y + v.y * c.x;
+      }
     }
   }
-  p[(int64_t)i * nb + m0] = acc;
+  if (m0 < nb) p[(int64_t)i * nb + m0] = acc;
 }
 
 }  // namespace chimg

@@ -25,7 +25,7 @@ def _dev(a):
 def test_preintegrator_matches_oracle(gpu, M, L, n_s, extra, natural):
     s = synth.noise_complex(np.random.Generator(np.random.PCG64(800 + M)), (M, 7 * L + extra))
     say("chimageator pre: M %d L %d N_s %d" % (M, L, n_s))
-    got = chimg_preintegrate(_dev(s), L, n_s, natural).cpu().numpy()
+    got = chimg_preintegrate(_dev(s), L, n_s, natural).cpu().numpy().T
     ref = ocg.spatial_dft(ocg.grid_blocks(s, L, "natural" if natural else "uniform"), n_s)
     assert got.shape == ref.shape
     err = np.max(np.abs(got - ref)) / np.sqrt(np.mean(np.abs(ref) ** 2))
@@ -38,7 +38,7 @@ def test_trajectories_match_oracle(gpu):
     M, n_s, L, nb = 12, 32, 8, 60
     Y = synth.noise_complex(rng, (nb, n_s))
     trials = [(9.0, 24), (5.3, 40), (-3.7, 7), (31.2, 60), (0.0, 1), (12.5, 61)]
-    got = chimg_trajectories(_dev(Y), M, L, [t[0] for t in trials], [t[1] for t in trials]).cpu().numpy()
+    got = chimg_trajectories(_dev(Y.T), M, L, [t[0] for t in trials], [t[1] for t in trials]).cpu().numpy()
     ref = ocg.trajectories(Y, M, n_s, trials, L)
     err = np.max(np.abs(got - ref)) / np.sqrt(max(t[1] for t in trials))
     say("trajectories: max error / sqrt(T) %.3e" % err)
@@ -58,3 +58,17 @@ def test_chirp_found_end_to_end(gpu):
     i, m = np.unravel_index(np.argmax(P), P.shape)
     say("best trial %s at block %d: |P| %.1f of %d" % (trials[i], m, P[i, m], (M - 1) * tb))
     assert trials[i] == (k_end, tb) and m == m0 and P[i, m] > 0.85 * (M - 1) * tb
+
+
+def test_long_trajectories_span_several_step_tables(gpu):
+    """Trials longer than one LDS table of steps (1024): the steps are made in
+    rounds."""
+    rng = np.random.Generator(np.random.PCG64(820))
+    M, n_s, L, nb = 8, 16, 4, 1100
+    Y = synth.noise_complex(rng, (nb, n_s))
+    trials = [(7.7, 1050), (-5.0, 1025)]
+    got = chimg_trajectories(_dev(Y.T), M, L, [t[0] for t in trials], [t[1] for t in trials]).cpu().numpy()
+    ref = ocg.trajectories(Y, M, n_s, trials, L)
+    err = np.max(np.abs(got - ref)) / np.sqrt(1050)
+    say("long trajectories: max error / sqrt(T) %.3e" % err)
+    assert err <= 1e-5
