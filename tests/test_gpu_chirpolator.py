@@ -164,3 +164,22 @@ def test_pair_bin_budget_rejected(gpu):
         with pytest.raises(DdxError):
             c.set_pair_bins(np.array([4, 5, 1], dtype=np.int32))
         c.set_pair_bins(None)
+
+
+def test_many_antennas_per_pair_tile(gpu):
+    """100 antennas: a tile of 64 pairs reads up to 65 antennas in row-major order and
+    up to 128 once random budgets reorder the pairs (the staged-antenna limit)."""
+    m_ant, n_win, L, kmax = 100, 64, 16, 3
+    rng = np.random.Generator(np.random.PCG64(130))
+    s = synth.noise_complex(rng, (m_ant, (n_win // L + 3) * L))
+    x = torch.from_numpy(np.ascontiguousarray(s.astype(np.complex64))).to("cuda:0")
+    budgets = rng.integers(0, kmax + 1, m_ant * (m_ant - 1) // 2).astype(np.int32)
+    with Chirp(m_ant, n_win, L, kmax, max_samples=s.shape[1]) as c:
+        full = c.preintegrate(x).cpu().numpy()
+        c.set_pair_bins(budgets)
+        part = c.preintegrate(x).cpu().numpy()
+    for got, bud in ((full, None), (part, budgets)):
+        ref = och.preintegrate(s, n_win, L, kmax, pair_kmax=bud)
+        err = np.max(np.abs(got - ref)) / np.sqrt(np.mean(np.abs(ref) ** 2))
+        say("100 antennas (%s): max error / rms %.3e" % ("budgets" if bud is not None else "full", err))
+        assert err <= TOL
