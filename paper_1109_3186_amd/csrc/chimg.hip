@@ -97,6 +97,90 @@ __global__ __launch_bounds__(kThreads) void k_pre(const float2* __restrict__ s, 
   }
 }
 
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// The same pre-integrator for M <= 64 with the pair products on the FP32 matrix
+// cores: per block, C = X X^H over its L samples (X the M x L block, rows padded to
+// 64), Re C = Xr Xr^T + Xi Xi^T and Im C = Xi Xr^T - Xr Xi^T as
+// v_mfma_f32_32x32x2_f32 products (two samples per instruction), wave w making the
+// 32 x 32 quadrant (w / 2, w % 2) (the lower-left one is not needed).  C is then
+// written to LDS and each spacing's diagonal summed in a fixed order, so results
+// do not depend on scheduling.  Lane l supplies antenna l % 32 of the quadrant's
+// rows (A) or columns (B) at sample l / 32 of each pair of samples and holds C at
+// column l % 32, rows 8 (v / 4) + 4 (l / 32) + v % 4.
+// grid: nb workgroups of 256 threads.
+__global__ __launch_bounds__(kThreads) void k_pre_mfma(const float2* __restrict__ s, int32_t M, int64_t n, int32_t L,
+                                                       int32_t n_s, int32_t natural, float2* __restrict__ y) {
+  constexpr int R = 64;                 // padded antenna rows
+  constexpr int CH = kStage / R;        // samples per staging round (80)
+  __shared__ float2 xs[kStage];         // [R][CH] samples, then C [R][R + 1]
+  __shared__ float2 g[R];
+  __shared__ float2 tw[kMaxBins];
+  const int m = blockIdx.x;
+  const int tid = threadIdx.x;
+  for (int r = tid; r < n_s; r += kThreads) {
+    float sn, cs;
+    sincospif(2.0f * (float)r / (float)n_s, &sn, &cs);
+    tw[r] = make_float2(cs, -sn);
+  }
+  const int wv = tid >> 6, lane = tid & 63;
+  const int rp = (wv >> 1) * 32, cq = (wv & 1) * 32;
+  const int i = lane & 31, h = lane >> 5;
+  const bool used = !(rp == 32 && cq == 0);
+  v16f re = {}, im = {};
+  for (int n0 = 0; n0 < L; n0 += CH) {
+    const int len = min(CH, L - n0);
+    __syncthreads();
+    for (int e = tid; e < R * CH; e += kThreads) {
+      const int p = e / CH, j = e - p * CH;
+      xs[e] = (p < M && j < len) ? s[(int64_t)p * n + (int64_t)m * L + n0 + j] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    if (used) {
+      for (int j = 0; j < len; j += 2) {   // samples past len are staged as zero
+        const float2 a = xs[(rp + i) * CH + j + h];
+        const float2 b = xs[(cq + i) * CH + j + h];
+        re = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, re, 0, 0, 0);
+        re = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, re, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.x, im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.x, b.y, im, 0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();
+  float2* C = xs;                       // [R][R + 1]
+  if (used) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int row = rp + 8 * (v >> 2) + 4 * h + (v & 3);
+      C[row * (R + 1) + cq + i] = make_float2(re[v], im[v]);
+    }
+  }
+  __syncthreads();
+  if (tid < M - 1) {
+    const int l = tid + 1;
+    float2 v = make_float2(0.f, 0.f);
+    for (int p = 0; p + l < M; ++p) {
+      const float2 c = C[p * (R + 1) + p + l];
+      v.x += c.x;
+      v.y += c.y;
+    }
+    const float w = (natural ? 1.0f / (float)(M - l) : 1.0f) / (float)L;
+    g[tid] = make_float2(v.x * w, v.y * w);
+  }
+  __syncthreads();
+  for (int k = tid; k < n_s; k += kThreads) {
+    float2 v = make_float2(0.f, 0.f);
+    for (int q = 1; q < M; ++q) {
+      const float2 a = g[q - 1];
+      const float2 t = tw[(int)(((int64_t)k * q) % n_s)];
+      v.x = fmaf(a.x, t.x, fmaf(-a.y, t.y, v.x));
+      v.y = fmaf(a.x, t.y, fmaf(a.y, t.x, v.y));
+    }
+    y[(int64_t)k * gridDim.x + m] = v;
+  }
+}
+
 // grid: (ceil(nb / 256), n_trials) x 256; thread = start block m0 of trial i.  The
 // bin k_q and phase conj(Phi(x_q)) of step q depend on the trial only: they are
 // made once per workgroup in LDS (kSteps at a time), and every thread then reads
@@ -157,8 +241,13 @@ int ddx_chimg_preintegrate(const void* d_volts, int32_t n_ant, int64_t n, int32_
   const int64_t nb = n / block_len;
   if (nb == 0) return DDX_OK;
   if (nb > INT32_MAX) return DDX_EUNSUPPORTED;
-  hipLaunchKernelGGL(chimg::k_pre, dim3((unsigned)nb), dim3(chimg::kThreads), 0, (hipStream_t)hip_stream,
-                     (const float2*)d_volts, n_ant, n, block_len, n_s, natural_weights ? 1 : 0, (float2*)d_y);
+  // up to 64 antennas: the pair products on the matrix cores; more: on the vector units
+  if (n_ant <= 64)
+    hipLaunchKernelGGL(chimg::k_pre_mfma, dim3((unsigned)nb), dim3(chimg::kThreads), 0, (hipStream_t)hip_stream,
+                       (const float2*)d_volts, n_ant, n, block_len, n_s, natural_weights ? 1 : 0, (float2*)d_y);
+  else
+    hipLaunchKernelGGL(chimg::k_pre, dim3((unsigned)nb), dim3(chimg::kThreads), 0, (hipStream_t)hip_stream,
+                       (const float2*)d_volts, n_ant, n, block_len, n_s, natural_weights ? 1 : 0, (float2*)d_y);
   return hipGetLastError() == hipSuccess ? DDX_OK : DDX_EDEVICE;
 }
 
