@@ -28,29 +28,31 @@ namespace inc {
 constexpr int kThreads = 256;
 constexpr int kDmTile = 32;         // brute force: DMs per workgroup (and per thread)
 constexpr int kChanGroup = 8;       // brute force: channels staged per LDS round
-constexpr int kSpan = 512;          // brute force: staged samples per channel
+constexpr int kOut = 2;             // brute force: outputs per thread, 256 apart
+constexpr int kSpan = 768;          // brute force: staged samples per channel (tile 512 + spread 256)
 constexpr int kFuseLog = 5;         // tree: the first 5 stages (groups of 32 channels) in LDS
 constexpr int kFuseRows = 1 << kFuseLog;
 constexpr int kTreeTile = 224;      // tree: samples per fused tile (tile + 32 halo = 256 per row)
 
-// grid: (ceil(n_out / 256), ceil(n_dm / kDmTile)); thread = one sample t for the
-// kDmTile DMs of the workgroup.  The workgroup's outputs read, per channel, the
-// samples t0 + [min delay, max delay + 255] over its DMs: staged in LDS for
+// grid: (ceil(n_out / 512), ceil(n_dm / kDmTile)); thread = samples t and t + 256
+// for the kDmTile DMs of the workgroup.  The workgroup's outputs read, per
+// channel, the samples t0 + [min delay, max delay + 511] over its DMs: staged in LDS for
 // kChanGroup channels at a time (each staged sample then serves every DM of the
 // tile), or read from global memory for a channel whose delays spread over more
-// than kSpan - 256 samples across the tile.
+// than kSpan - 512 samples across the tile.
 __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p, int32_t C, int64_t n_t,
                                                     const int32_t* __restrict__ delays, int32_t n_dm,
                                                     float* __restrict__ out, int64_t n_out) {
   __shared__ float buf[kChanGroup][kSpan];
   __shared__ int lo_s[kChanGroup], hi_s[kChanGroup];
   __shared__ int dls[kChanGroup][kDmTile];   // the group's delays for the tile's DMs
-  const int64_t t0 = (int64_t)blockIdx.x * kThreads;
-  const int64_t t = t0 + threadIdx.x;
+  constexpr int TILE = kThreads * kOut;
+  const int64_t t0 = (int64_t)blockIdx.x * TILE;
+  const int64_t t = t0 + threadIdx.x;     // and t + 256
   const int d0 = blockIdx.y * kDmTile;
   const int nd = min(kDmTile, n_dm - d0);
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  float acc[kDmTile] = {};
+  float acc[kOut][kDmTile] = {};
   for (int c0 = 0; c0 < C; c0 += kChanGroup) {
     const int nc = min(kChanGroup, C - c0);
     __syncthreads();
@@ -74,9 +76,9 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p,
     __syncthreads();
     for (int ci = 0; ci < nc; ++ci) {
       const int lo = lo_s[ci], hi = hi_s[ci];
-      if (hi - lo + kThreads > kSpan) continue;   // read from global below
+      if (hi - lo + TILE > kSpan) continue;   // read from global below
       const float* row = p + (int64_t)(c0 + ci) * n_t;
-      for (int x = threadIdx.x; x < hi - lo + kThreads; x += kThreads) {
+      for (int x = threadIdx.x; x < hi - lo + TILE; x += kThreads) {
         const int64_t s = t0 + lo + x;
         buf[ci][x] = (s >= 0 && s < n_t) ? row[s] : 0.f;
       }
@@ -85,26 +87,37 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p,
     for (int ci = 0; ci < nc; ++ci) {
       const int* dl = dls[ci];   // zero past nd: those sums are never written
       const int lo = lo_s[ci], hi = hi_s[ci];
-      if (hi - lo + kThreads <= kSpan) {
+      if (hi - lo + TILE <= kSpan) {
         // dl[i] lies in [lo, hi] for i < nd; the clamp keeps the unused i >= nd
-        // (dl = 0) inside the staged span too
+        // (dl = 0) inside the staged span too.  One address serves both outputs.
         const float* b = buf[ci] + threadIdx.x - lo;
 #pragma unroll
-        for (int i = 0; i < kDmTile; ++i) acc[i] += b[min(max(dl[i], lo), hi)];
+        for (int i = 0; i < kDmTile; ++i) {
+          const float* bi = b + min(max(dl[i], lo), hi);
+#pragma unroll
+          for (int o = 0; o < kOut; ++o) acc[o][i] += bi[o * kThreads];
+        }
       } else {
         const float* row = p + (int64_t)(c0 + ci) * n_t;
 #pragma unroll
         for (int i = 0; i < kDmTile; ++i) {
-          const int64_t s = t + dl[i];
-          acc[i] += (s >= 0 && s < n_t) ? row[s] : 0.f;
+#pragma unroll
+          for (int o = 0; o < kOut; ++o) {
+            const int64_t s = t + o * kThreads + dl[i];
+            acc[o][i] += (s >= 0 && s < n_t) ? row[s] : 0.f;
+          }
         }
       }
     }
   }
-  if (t >= n_out) return;
 #pragma unroll
-  for (int i = 0; i < kDmTile; ++i)
-    if (i < nd) out[(int64_t)(d0 + i) * n_out + t] = acc[i];
+  for (int o = 0; o < kOut; ++o) {
+    const int64_t to = t + o * kThreads;
+    if (to >= n_out) continue;
+#pragma unroll
+    for (int i = 0; i < kDmTile; ++i)
+      if (i < nd) out[(int64_t)(d0 + i) * n_out + to] = acc[o][i];
+  }
 }
 
 // The first kFuseLog tree stages of one group of 32 channels over a tile of
@@ -232,7 +245,8 @@ int ddx_incoherent_dedisperse(const float* d_power, int32_t n_chan, int64_t n_t,
                               int32_t n_dm, float* d_out, int64_t n_out, void* hip_stream) {
   if (n_chan < 1 || n_t < 0 || n_dm < 1 || n_out < 0 || !d_power || !d_delays || !d_out) return DDX_EINVAL;
   if (n_out == 0) return DDX_OK;
-  const int64_t gx = (n_out + inc::kThreads - 1) / inc::kThreads;
+  const int64_t tile = (int64_t)inc::kThreads * inc::kOut;
+  const int64_t gx = (n_out + tile - 1) / tile;
   const int64_t gy = (n_dm + inc::kDmTile - 1) / inc::kDmTile;
   if (gx > INT32_MAX || gy > 65535) return DDX_EUNSUPPORTED;
   hipLaunchKernelGGL(inc::k_brute, dim3((unsigned)gx, (unsigned)gy), dim3(inc::kThreads), 0, (hipStream_t)hip_stream,
