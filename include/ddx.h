@@ -427,9 +427,10 @@ int ddx_image_destroy(ddx_image* h);
 const char* ddx_image_last_error(const ddx_image* h);
 
 /* ---- Classical incoherent dedispersion of power beams (Sec. 2.3.1, 2.4.1) -------
- * Stateless calls; every device buffer is caller-owned; asynchronous on
- * hip_stream.  Power spectrograms are [C][n_t] FP32 rows, channel 0 the least
- * delayed (highest frequency); samples past n_t count as zero. */
+ * Stateless calls; every device buffer is caller-owned and must not overlap another
+ * buffer of the same call; asynchronous on hip_stream.  Power spectrograms are
+ * [C][n_t] FP32 rows, channel 0 the least delayed (highest frequency); samples past
+ * n_t count as zero. */
 
 /* Power beam (Sec. 2.4.1): d_power[c][t] = sum over antennas a and the n_int
  * samples n of interval t of |x_{c,a}[n]|^2, t < floor(n_samp / n_int).
@@ -465,8 +466,8 @@ int ddx_tree_dedisperse(const float* d_power, int32_t n_chan, int64_t n_t, float
                         void* hip_stream);
 
 /* ---- The Chimageator on a uniform linear array (Sec. 4) --------------------------
- * Stateless calls; caller-owned device buffers; asynchronous on hip_stream.
- * Antenna p sits at p times the spacing along the line. */
+ * Stateless calls; caller-owned device buffers that must not overlap; asynchronous
+ * on hip_stream.  Antenna p sits at p times the spacing along the line. */
 
 /* Pre-integrator: for every complete block m of L = block_len samples,
  *   G_l[m] = w_l / L sum_{p < M - l} sum_{n in block m} s_p[n] s_{p+l}[n]^*  (l = 1 .. M - 1;
