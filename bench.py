@@ -454,10 +454,29 @@ def run_chimg(args, dev):
            "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": PEAKS["fp32_mfma_tflops"],
                         "unit": "TFLOP/s", "frac": round(tf / PEAKS["fp32_mfma_tflops"], 4), "traffic": None,
                         "kernel": "k_pre_mfma (pair products on FP32 MFMA + spatial DFT)"},
-           "cpu_baseline": None,
+           "cpu_baseline": chimg_cpu_baseline(args, volts, L, n_s),
            "trajectories": {"ms_per_call": round(ms_traj, 3), "gathers_per_s": gathers / (ms_traj / 1e3),
                             "trials": len(trials)}}
     print(json.dumps(rec), flush=True)
+
+
+def chimg_cpu_baseline(args, volts, L, n_s):
+    """The FP64 oracle's Chimageator pre-integrator on the first 256 blocks, one thread."""
+    if args.no_cpu_baseline:
+        return None
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import chimageator as ocg
+    nb = 256
+    s = volts[:, :nb * L].cpu().numpy().astype(np.complex128)
+    with threadpool_limits(1):
+        tc = time.perf_counter()
+        ocg.spatial_dft(ocg.grid_blocks(s, L), n_s)
+        tc = time.perf_counter() - tc
+    return {"value": s.shape[0] * nb * L / tc, "unit": "antenna-samples/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d blocks of %d samples, all %d antennas, FP64 numpy on one thread, %.2f s" % (
+                nb, L, s.shape[0], tc)}
 
 
 def run_c3(args, dev):
