@@ -9,7 +9,7 @@ multiply + inverse FFT for every DM, cross-multiply and integrate-and-dump of
 all 666 baselines, and the fetch of every dump record into device memory.
 The input is resident in HBM before the timed region.
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the library has no multi-GPU path.
 """
 import argparse
 import hashlib
@@ -641,7 +641,7 @@ def main():
                     help="before the steps, run one elementwise copy kernel of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (requested %d)" % args.gpus,
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (requested %d)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
