@@ -14,7 +14,7 @@
 //   V_k = (P + Q) + i (T - R),   V_-k = (P - Q) + i (R + T),
 // one FMA per sum and sample, half the work of two separate complex products.  Per
 // block the partial DFTs of all pairs are then a product [pairs x L] x [L x (kmax+1)]
-// in 64 x 64 tiles on the FP32 matrix cores, each pair mixed as it feeds them from
+// in 128-pair x 32-bin tiles on the FP32 matrix cores, each pair mixed as it feeds them from
 // its tile's antennas staged in LDS.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -32,8 +32,11 @@
 
 namespace chirp {
 
-constexpr int kTileP = 64;   // pairs per output tile
-constexpr int kTileK = 64;   // bins per output tile
+#ifndef DDX_CHIRP_TILE_P
+#define DDX_CHIRP_TILE_P 128
+#endif
+constexpr int kTileP = DDX_CHIRP_TILE_P;   // pairs per output tile
+constexpr int kTileK = 4096 / kTileP;      // bins per output tile (4 waves of 32 x 32)
 constexpr int kChunk = 32;   // samples per LDS chunk
 
 struct PartialArgs {
@@ -47,7 +50,7 @@ struct PartialArgs {
   const int2* loc;        // [nbl] (p, q) as indices into the tile's antenna list
   float2* v;              // [nb][nbl][Kc] partial DFTs (pairs in budget order)
   int64_t n_samp;         // samples per antenna row of s
-  int32_t nbl, n_list, Kc, K_pad, L, R, n_act;
+  int32_t nbl, n_list, Kc, K_pad, L, R, n_act, sa_rows;
 };
 
 typedef float v16f __attribute__((ext_vector_type(16)));
@@ -71,16 +74,19 @@ __device__ __forceinline__ int xcd_order(int id, int total) {
 // each [32 pairs x 2 samples] x [2 samples x 32 bins] per instruction.  The staging
 // reads the tile's antennas as rows of consecutive samples (coalesced) and mixes
 // each pair when it feeds the matrix core, instead of gathering s_p and s_q per
-// pair.  Wave w
-// owns pairs 32 (w / 2) .. and listed bins 32 (w % 2) .. of the 64 x 64 tile.
+// pair.  Wave w owns pairs 32 (w / WK) .. and listed bins 32 (w % WK) .. of the
+// tile (WK = kTileK / 32 waves along the bins; 32-bin tiles let per-pair budgets
+// skip bins in finer steps).
 // Lane l supplies pair (or bin) l % 32 of sample l / 32 of each sample pair and
 // holds, of each 32 x 32 result, bin l % 32 of the pairs 8 (v / 4) + 4 (l / 32)
 // + v % 4, v < 16.
 __global__ __launch_bounds__(256) void k_partial_mfma(PartialArgs a) {
-  // the tile's antennas (at most two per pair), kChunk samples each, padded by one
-  // entry so that the lanes' different antennas fall in different banks
-  __shared__ float2 sa[2 * kTileP][kChunk + 1];
-  __shared__ float2 ws[kChunk][kTileK];
+  // dynamic LDS: the tile's antennas (sa_rows >= their count, at most two per pair),
+  // kChunk samples each, padded by one entry so that the lanes' different antennas
+  // fall in different banks; then the W rows of the chunk, kChunk x kTileK
+  extern __shared__ float2 lds[];
+  float2* sa = lds;
+  float2* ws = lds + a.sa_rows * (kChunk + 1);
   const int tid = threadIdx.x;
   const int id = xcd_order(blockIdx.x, gridDim.x);
   const int2 tile = a.act[id % a.n_act];
@@ -88,7 +94,8 @@ __global__ __launch_bounds__(256) void k_partial_mfma(PartialArgs a) {
   const int m = id / a.n_act;
   const int p0 = pt * kTileP, k0 = kt * kTileK;
   const int wv = tid >> 6, lane = tid & 63;
-  const int wp = (wv >> 1) * 32, wk = (wv & 1) * 32;
+  constexpr int WK = kTileK / 32;     // waves along the bins
+  const int wp = (wv / WK) * 32, wk = (wv % WK) * 32;
   const int r = lane & 31, h = lane >> 5;
   const int64_t base = (int64_t)m * a.L;
   const int na = a.tile_nant[pt];
@@ -105,21 +112,21 @@ __global__ __launch_bounds__(256) void k_partial_mfma(PartialArgs a) {
       const int ai = e / kChunk, n = e % kChunk;
       float2 v = make_float2(0.f, 0.f);
       if (n0 + n < a.L) v = a.s[(int64_t)ants[ai] * a.n_samp + base + n0 + n];
-      sa[ai][n] = v;
+      sa[ai * (kChunk + 1) + n] = v;
     }
 #pragma unroll
     for (int q = 0; q < (kChunk * kTileK) / 256; ++q) {
       const int e = tid + 256 * q;
       const int n = e / kTileK, kl = e % kTileK;
-      ws[n][kl] = a.w[(int64_t)(n0 + n) * a.K_pad + k0 + kl];
+      ws[n * kTileK + kl] = a.w[(int64_t)(n0 + n) * a.K_pad + k0 + kl];
     }
     __syncthreads();
 #pragma unroll 4
     for (int n = 0; n < kChunk; n += 2) {
       // x = s_p conj(s_q) of the lane's pair and sample, mixed at the operand
-      const float2 sp = sa[lc.x][n + h], sq = sa[lc.y][n + h];
+      const float2 sp = sa[lc.x * (kChunk + 1) + n + h], sq = sa[lc.y * (kChunk + 1) + n + h];
       const float xr = live * (sp.x * sq.x + sp.y * sq.y), xi = live * (sp.y * sq.x - sp.x * sq.y);
-      const float2 wt = ws[n + h][wk + r];
+      const float2 wt = ws[(n + h) * kTileK + wk + r];
       P = __builtin_amdgcn_mfma_f32_32x32x2f32(xr, wt.x, P, 0, 0, 0);
       Q = __builtin_amdgcn_mfma_f32_32x32x2f32(xi, wt.y, Q, 0, 0, 0);
       R = __builtin_amdgcn_mfma_f32_32x32x2f32(xr, wt.y, R, 0, 0, 0);
@@ -240,6 +247,7 @@ struct Common {
   std::vector<int> tile_bins;   // [pair tiles] largest budget of the tile (host)
   int* tile_ant = nullptr;      // [pair tiles][2 kTileP] antennas read by the tile
   int* tile_nant = nullptr;     // [pair tiles] their count
+  int na_max = 1;               // the largest count
   int2* loc = nullptr;          // [nbl] (p, q) as indices into the tile's antennas
   float2* v = nullptr;   // [max_blocks][nbl][max Kc]
   std::vector<void*> allocs;
@@ -384,6 +392,7 @@ int make_common(Common& c, int n_ant, int block_len, int kmax, int64_t max_sampl
   std::vector<int> ants, nant;
   std::vector<int2> loc;
   tile_antennas(pq, n_ant, ants, nant, loc);
+  c.na_max = std::max(1, *std::max_element(nant.begin(), nant.end()));
   int rc;
   if ((rc = upload(c, &c.perm, perm)) || (rc = upload(c, &c.budget, budget)) ||
       (rc = upload(c, &c.budget_canon, budget)) ||
@@ -420,10 +429,12 @@ int run_stage(Common& c, const Stage& st, const float2* volts, int64_t n, float2
   a.L = c.L;
   a.R = st.R;
   a.n_act = st.n_act;
+  a.sa_rows = c.na_max;
   const int64_t grid = nb * st.n_act;
   if (grid > INT32_MAX) return cfail(&c.err, DDX_EUNSUPPORTED, "too many blocks in one call");
   // no active tile: every listed bin lies beyond every budget, and the CIC writes zeros
-  if (grid > 0) hipLaunchKernelGGL(chirp::k_partial_mfma, dim3((unsigned)grid), dim3(256), 0, s, a);
+  const size_t lds = ((size_t)c.na_max * (chirp::kChunk + 1) + chirp::kChunk * chirp::kTileK) * sizeof(float2);
+  if (grid > 0) hipLaunchKernelGGL(chirp::k_partial_mfma, dim3((unsigned)grid), dim3(256), lds, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return cfail(&c.err, DDX_EDEVICE, "k_partial_mfma: %s", hipGetErrorString(e));
   const int64_t cols = (int64_t)c.nbl * st.Kc;
@@ -467,6 +478,7 @@ int set_budgets(Common& c, const int32_t* host) {
   std::vector<int> ants, nant;
   std::vector<int2> loc;
   tile_antennas(pq, c.M, ants, nant, loc);
+  const int na_max = std::max(1, *std::max_element(nant.begin(), nant.end()));
   if (hipDeviceSynchronize() != hipSuccess ||
       hipMemcpy(c.tile_ant, ants.data(), ants.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c.tile_nant, nant.data(), nant.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
@@ -478,6 +490,7 @@ int set_budgets(Common& c, const int32_t* host) {
     return cfail(&c.err, DDX_EDEVICE, "bin budget upload failed");
   }
   c.tile_bins = tiles;
+  c.na_max = na_max;
   return DDX_OK;
 }
 
