@@ -438,12 +438,21 @@ def run_chimg(args, dev):
     y = chimg_preintegrate(volts, L, n_s)
     ms_pre = timed(lambda: chimg_preintegrate(volts, L, n_s))
     ms_traj = timed(lambda: chimg_trajectories(y, M, L, ke, tb))
+    # the same number of trials as 64 gradients x 4 durations: one pass per gradient
+    # (partial sums) against the 256 trajectories summed separately
+    from paper_1109_3186_amd import chimg_gradient_sums
+    grads = [ke_ / 512.0 for ke_ in range(-32, 32)]
+    lens = [64, 128, 256, 512]
+    ms_grad = timed(lambda: chimg_gradient_sums(y, M, L, grads, lens))
+    ms_sep = timed(lambda: chimg_trajectories(y, M, L, [g_ * t_ for t_ in lens for g_ in grads],
+                                              [t_ for t_ in lens for _ in grads]))
     nb = n // L
     macs = nb * L * M * (M - 1) / 2.0                  # gridded products per call
     tf = 8.0 * macs / (ms_pre / 1e3) / 1e12
     gathers = sum(max(0, nb - t + 1) * t for t in tb)
-    log("chimg: pre %.2f ms (%.1f TFLOP/s of products), trajectories %.2f ms (%.3e gathers/s)" % (
-        ms_pre, tf, ms_traj, gathers / (ms_traj / 1e3)))
+    log("chimg: pre %.2f ms (%.1f TFLOP/s of products), trajectories %.2f ms (%.3e gathers/s); "
+        "gradient partial sums %.2f ms against %.2f ms separately" % (
+            ms_pre, tf, ms_traj, gathers / (ms_traj / 1e3), ms_grad, ms_sep))
     rec = {"metric": "antenna-samples/s through the Chimageator pre-integrator", "value": M * n / (ms_pre / 1e3),
            "unit": "antenna-samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms_pre + ms_traj, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -456,7 +465,9 @@ def run_chimg(args, dev):
                         "kernel": "k_pre_mfma (pair products on FP32 MFMA + spatial DFT)"},
            "cpu_baseline": chimg_cpu_baseline(args, volts, L, n_s),
            "trajectories": {"ms_per_call": round(ms_traj, 3), "gathers_per_s": gathers / (ms_traj / 1e3),
-                            "trials": len(trials)}}
+                            "trials": len(trials)},
+           "gradient_sums": {"gradients": len(grads), "durations": lens, "ms_per_call": round(ms_grad, 3),
+                             "separate_ms": round(ms_sep, 3), "speedup": round(ms_sep / ms_grad, 2)}}
     print(json.dumps(rec), flush=True)
 
 

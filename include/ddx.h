@@ -493,6 +493,19 @@ int ddx_chimg_trajectories(const void* d_y, int64_t n_blocks, int32_t n_ant, int
                            const double* d_k_end, const int32_t* d_t_blocks, int32_t n_trials, void* d_p,
                            void* hip_stream);
 
+/* Trajectories of a common gradient (App. B, optimising the imaging step): for
+ * gradients g_i (bins per block) and durations lengths[j] (blocks, ascending, >= 1),
+ *   P[i][j][m0] = sum_{q < lengths[j]} conj(Phi(x_q)) Y_{k_q}[m0 + q],
+ *   k0(q) = g_i (q L + (L - 1) / 2) / L, k_q = rint(k0) mod N_s (FP64, ties to even),
+ * i.e. the trajectory that ends at bin g_i lengths[j] after lengths[j] blocks; every
+ * duration is a partial sum of one pass along the line.  Zero where m0 + lengths[j]
+ * > n_blocks.  d_grad (double) [n_grad], d_lengths (int32) [n_len]: DEVICE; d_p:
+ * DEVICE [n_grad][n_len][n_blocks] complex64.  Durations out of order leave their
+ * outputs unwritten.  Errors as for ddx_chimg_trajectories. */
+int ddx_chimg_gradient_sums(const void* d_y, int64_t n_blocks, int32_t n_ant, int32_t n_s, int32_t block_len,
+                            const double* d_grad, int32_t n_grad, const int32_t* d_lengths, int32_t n_len, void* d_p,
+                            void* hip_stream);
+
 /* Synchronise the plan's last stream and free plan-owned memory.  NULL is a no-op. */
 int ddx_plan_destroy(ddx_plan* plan);
 

@@ -79,3 +79,24 @@ def trajectories(Y, M, n_s, trials, L):
         for m0 in range(0, nb - tb + 1):
             P[i, m0] = trajectory(Y, M, n_s, k_end, tb, m0, L)
     return P
+
+
+def gradient_sums(Y, M, n_s, grads, lengths, L):
+    """App. B, optimising the imaging step: trajectories with the same gradient g
+    (bins per block) share their path, so every duration is a partial sum of the
+    longest.  P[i][j][m0] = sum_{q < lengths[j]} conj(Phi(x_q)) Y_{k_q}[m0 + q] with
+    k0(q) = g_i (q L + (L - 1) / 2) / L (the block average at its mean sample),
+    zero where m0 + lengths[j] > blocks.  Written as separate sums, one per length."""
+    Y = np.asarray(Y)
+    nb = Y.shape[0]
+    P = np.zeros((len(grads), len(lengths), nb), dtype=np.complex128)
+    for i, g in enumerate(grads):
+        for j, T in enumerate(lengths):
+            for m0 in range(0, nb - T + 1):
+                total = 0j
+                for q in range(T):
+                    k0 = g * (q * L + (L - 1) / 2.0) / L
+                    kr = np.rint(k0)
+                    total += np.conj(phase(k0 - kr, M, n_s)) * Y[m0 + q, int(kr) % n_s]
+                P[i, j, m0] = total
+    return P

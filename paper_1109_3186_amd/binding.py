@@ -122,6 +122,8 @@ SIGNATURES = {
                                 ct.c_void_p], ct.c_int),
     "ddx_chimg_trajectories": ([ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p,
                                 ct.c_int32, ct.c_void_p, ct.c_void_p], ct.c_int),
+    "ddx_chimg_gradient_sums": ([ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p,
+                                 ct.c_int32, ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p], ct.c_int),
     "ddx_plan_destroy": ([ct.c_void_p], ct.c_int),
     "ddx_strerror": ([ct.c_int], ct.c_char_p),
     "ddx_last_error": ([ct.c_void_p], ct.c_char_p),
@@ -701,4 +703,26 @@ def chimg_trajectories(y, n_ant, block_len, k_end, t_blocks, stream=None):
                                       ct.c_void_p(p.data_ptr()), _stream_handle(stream))
     if rc != OK:
         raise DdxError(rc, "ddx_chimg_trajectories")
+    return p
+
+
+def chimg_gradient_sums(y, n_ant, block_len, grads, lengths, stream=None):
+    """Partial sums along common-gradient trajectories: P [grads, lengths, blocks]
+    (complex64, device) over y [n_s, blocks]; lengths ascending."""
+    import torch
+    if y.dtype != torch.complex64 or y.dim() != 2:
+        raise DdxError(EINVAL, "y must be complex64 [n_s, blocks]")
+    ln = np.asarray(lengths, dtype=np.int32)
+    if ln.size == 0 or np.any(ln < 1) or np.any(np.diff(ln) < 0):
+        raise DdxError(EINVAL, "lengths must be ascending and >= 1")
+    y = y.contiguous()
+    gr = torch.as_tensor(np.asarray(grads, dtype=np.float64), device=y.device)
+    lt = torch.as_tensor(ln, device=y.device)
+    p = torch.empty((gr.numel(), lt.numel(), y.shape[1]), dtype=torch.complex64, device=y.device)
+    rc = lib().ddx_chimg_gradient_sums(ct.c_void_p(y.data_ptr()), y.shape[1], int(n_ant), y.shape[0],
+                                       int(block_len), ct.c_void_p(gr.data_ptr()), gr.numel(),
+                                       ct.c_void_p(lt.data_ptr()), lt.numel(), ct.c_void_p(p.data_ptr()),
+                                       _stream_handle(stream))
+    if rc != OK:
+        raise DdxError(rc, "ddx_chimg_gradient_sums")
     return p

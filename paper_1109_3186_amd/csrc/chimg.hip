@@ -229,6 +229,63 @@ __global__ __launch_bounds__(kThreads) void k_traj(const float2* __restrict__ y,
   if (m0 < nb) p[(int64_t)i * nb + m0] = acc;
 }
 
+// Trajectories sharing a gradient g (bins per block) lie on one line, so the sums
+// for several durations are partial sums of the longest (the paper's optimisation
+// of the imaging step): one pass along the line per (gradient, start), the running
+// sum written out each time the step count reaches a requested duration.
+// lengths: ascending.  grid: (ceil(nb / 256), n_grad) x 256.
+__global__ __launch_bounds__(kThreads) void k_grad(const float2* __restrict__ y, int64_t nb, int32_t M, int32_t n_s,
+                                                   int32_t L, const double* __restrict__ grad,
+                                                   const int32_t* __restrict__ lengths, int32_t n_len,
+                                                   float2* __restrict__ p) {
+  __shared__ int kq[kSteps];
+  __shared__ float2 cq[kSteps];
+  const int64_t m0 = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int i = blockIdx.y;
+  const double g = grad[i];
+  const int tmax = lengths[n_len - 1];
+  float2 acc = make_float2(0.f, 0.f);
+  int jn = 0;                  // next duration to write
+  int next = lengths[0];       // its step count
+  for (int q0 = 0; q0 < tmax; q0 += kSteps) {
+    const int nq = min(kSteps, tmax - q0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < nq; q += kThreads) {
+      double k0;
+      {
+#pragma clang fp contract(off)
+        k0 = g * ((double)((int64_t)(q0 + q) * L) + (L - 1) / 2.0) / (double)L;
+      }
+      const double kr = rint(k0);
+      const float x = (float)(k0 - kr);
+      int64_t kb = (int64_t)kr % n_s;
+      if (kb < 0) kb += n_s;
+      float sn, cs;
+      sincospif(-(float)M * x / (float)n_s, &sn, &cs);    // conj(Phi(x))
+      kq[q] = (int)kb;
+      cq[q] = make_float2(cs, sn);
+    }
+    __syncthreads();
+    if (m0 < nb) {
+      // steps inside the blocks, then none: the remaining durations only get zeros
+      const int nin = (int)min((int64_t)nq, max((int64_t)0, nb - m0 - q0));
+      for (int q = 0; q < nq; ++q) {
+        if (q < nin) {
+          const float2 v = y[(int64_t)kq[q] * nb + m0 + q0 + q];
+          const float2 c = cq[q];
+          acc.x += v.x * c.x - v.y * c.y;
+          acc.y += v.x * c.y + v.y * c.x;
+        }
+        if (q0 + q + 1 == next) {
+          const float2 out = m0 + next <= nb ? acc : make_float2(0.f, 0.f);
+          for (; jn < n_len && lengths[jn] == next; ++jn) p[((int64_t)i * n_len + jn) * nb + m0] = out;
+          next = jn < n_len ? lengths[jn] : INT32_MAX;
+        }
+      }
+    }
+  }
+}
+
 }  // namespace chimg
 
 extern "C" {
@@ -263,6 +320,21 @@ int ddx_chimg_trajectories(const void* d_y, int64_t n_blocks, int32_t n_ant, int
   hipLaunchKernelGGL(chimg::k_traj, dim3((unsigned)gx, (unsigned)n_trials), dim3(chimg::kThreads), 0,
                      (hipStream_t)hip_stream, (const float2*)d_y, n_blocks, n_ant, n_s, block_len, d_k_end, d_t_blocks,
                      (float2*)d_p);
+  return hipGetLastError() == hipSuccess ? DDX_OK : DDX_EDEVICE;
+}
+
+int ddx_chimg_gradient_sums(const void* d_y, int64_t n_blocks, int32_t n_ant, int32_t n_s, int32_t block_len,
+                            const double* d_grad, int32_t n_grad, const int32_t* d_lengths, int32_t n_len, void* d_p,
+                            void* hip_stream) {
+  if (!d_y || n_blocks < 0 || n_ant < 2 || n_s < 1 || block_len < 1 || !d_grad || n_grad < 1 || !d_lengths ||
+      n_len < 1 || !d_p)
+    return DDX_EINVAL;
+  if (n_blocks == 0) return DDX_OK;
+  const int64_t gx = (n_blocks + chimg::kThreads - 1) / chimg::kThreads;
+  if (gx > INT32_MAX || n_grad > 65535) return DDX_EUNSUPPORTED;
+  hipLaunchKernelGGL(chimg::k_grad, dim3((unsigned)gx, (unsigned)n_grad), dim3(chimg::kThreads), 0,
+                     (hipStream_t)hip_stream, (const float2*)d_y, n_blocks, n_ant, n_s, block_len, d_grad, d_lengths,
+                     n_len, (float2*)d_p);
   return hipGetLastError() == hipSuccess ? DDX_OK : DDX_EDEVICE;
 }
 

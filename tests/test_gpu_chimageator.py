@@ -72,3 +72,23 @@ def test_long_trajectories_span_several_step_tables(gpu):
     err = np.max(np.abs(got - ref)) / np.sqrt(1050)
     say("long trajectories: max error / sqrt(T) %.3e" % err)
     assert err <= 1e-5
+
+
+def test_gradient_sums_match_oracle(gpu):
+    """App. B partial sums: every duration of a common-gradient line from one pass,
+    including durations past one step table and past the end of the blocks."""
+    from paper_1109_3186_amd import chimg_gradient_sums
+    rng = np.random.Generator(np.random.PCG64(830))
+    M, n_s, L, nb = 10, 32, 8, 1100
+    Y = synth.noise_complex(rng, (nb, n_s))
+    grads, lengths = [0.37, -0.81, 0.0], [1, 3, 3, 40, 1030, 1200]
+    got = chimg_gradient_sums(_dev(Y.T), M, L, grads, lengths).cpu().numpy()
+    ref = ocg.gradient_sums(Y, M, n_s, grads, lengths[:4], L)
+    err = np.max(np.abs(got[:, :4] - ref)) / np.sqrt(40)
+    say("gradient sums (short): max error / sqrt(T) %.3e" % err)
+    assert err <= 1e-5
+    for i, g in enumerate(grads):             # the long duration against the trajectory form
+        for m0 in (0, 33, nb - 1030):
+            r = ocg.trajectory(Y, M, n_s, g * 1030, 1030, m0, L)
+            assert abs(got[i, 4, m0] - r) / np.sqrt(1030) <= 1e-5
+    assert np.all(got[:, 5] == 0)             # 1200 blocks fit nowhere in 1100

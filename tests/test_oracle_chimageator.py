@@ -106,3 +106,19 @@ def test_trajectory_of_exact_spatial_tones(k_end, tb):
         x = n_s * u - np.rint(n_s * u)
         expect += (M - 1) if x == 0 else np.sin(np.pi * (M - 1) * x / n_s) / np.sin(np.pi * x / n_s)
     assert abs(P - expect) < 1e-9 * (M - 1) * tb
+
+
+def test_gradient_sums_are_the_trajectories_of_each_duration():
+    """App. B: for a gradient g, the duration-T sum is the trajectory ending at bin
+    k_end = g T after T blocks (the same line in (block, bin))."""
+    rng = _rng(31)
+    M, n_s, L, nb = 10, 32, 8, 40
+    Y = rng.normal(size=(nb, n_s)) + 1j * rng.normal(size=(nb, n_s))
+    grads, lengths = [0.37, -0.81, 1.93], [3, 10, 25]
+    P = cg.gradient_sums(Y, M, n_s, grads, lengths, L)
+    for i, g in enumerate(grads):
+        for j, T in enumerate(lengths):
+            for m0 in (0, 7, nb - T):
+                ref = cg.trajectory(Y, M, n_s, g * T, T, m0, L)
+                assert abs(P[i, j, m0] - ref) < 1e-10 * T
+            assert np.all(P[i, j, nb - T + 1:] == 0)
