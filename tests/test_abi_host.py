@@ -247,3 +247,31 @@ def test_incoherent_delays_match_the_oracle_and_validate():
                                        ct.c_int64(5), None) == binding.EINVAL
     assert L.ddx_power_beam(None, ct.c_int32(4), ct.c_int32(2), ct.c_int64(10), ct.c_int32(2), None,
                             None) == binding.EINVAL
+
+
+def test_chimageator_entry_points_validate():
+    L = ct.CDLL(ddx.LIB_PATH)
+    d = ct.c_void_p(8)   # never dereferenced: the argument checks fail first
+    assert L.ddx_chimg_preintegrate(d, ct.c_int32(1), ct.c_int64(100), ct.c_int32(4), ct.c_int32(16), ct.c_int32(1),
+                                    d, None) == binding.EINVAL            # one antenna
+    assert L.ddx_chimg_preintegrate(d, ct.c_int32(258), ct.c_int64(100), ct.c_int32(4), ct.c_int32(16),
+                                    ct.c_int32(1), d, None) == binding.EINVAL   # above 257
+    assert L.ddx_chimg_preintegrate(d, ct.c_int32(8), ct.c_int64(100), ct.c_int32(4), ct.c_int32(24), ct.c_int32(1),
+                                    d, None) == binding.EINVAL            # N_s not a power of two
+    assert L.ddx_chimg_preintegrate(d, ct.c_int32(8), ct.c_int64(100), ct.c_int32(4), ct.c_int32(2048),
+                                    ct.c_int32(1), d, None) == binding.EINVAL   # N_s above 1024
+    assert L.ddx_chimg_trajectories(None, ct.c_int64(10), ct.c_int32(8), ct.c_int32(16), ct.c_int32(4), d, d,
+                                    ct.c_int32(1), d, None) == binding.EINVAL
+    assert L.ddx_chimg_gradient_sums(d, ct.c_int64(10), ct.c_int32(8), ct.c_int32(16), ct.c_int32(4), d,
+                                     ct.c_int32(0), d, ct.c_int32(1), d, None) == binding.EINVAL
+    with pytest.raises(binding.DdxError):
+        binding.chimg_gradient_sums(_FakeTensor(), 8, 4, [0.1], [5, 3])
+
+
+class _FakeTensor:
+    """Stands in for a device tensor in a check that fails before any device work."""
+    import torch as _t
+    dtype = _t.complex64
+
+    def dim(self):
+        return 2
