@@ -479,6 +479,27 @@ int ddx_tree_dedisperse(const float* d_power, int32_t n_chan, int64_t n_t, float
 int ddx_chimg_preintegrate(const void* d_volts, int32_t n_ant, int64_t n, int32_t block_len, int32_t n_s,
                            int32_t natural_weights, void* d_y, void* hip_stream);
 
+/* Gridding of a line of antennas at arbitrary ascending positions (Sec. 4: an
+ * arbitrary array interpolated onto the regular grid): pair p < q goes to cell l =
+ * rint((x_q - x_p) / spacing) (ties to even) when 1 <= l <= n_cells.  HOST arrays:
+ * positions [n_ant] (2 <= n_ant <= 64, strictly ascending), cell_ptr [n_cells + 1]
+ * (cell l's pairs are entries cell_ptr[l - 1] .. cell_ptr[l] - 1), cell_pairs
+ * [2 x n_ant (n_ant - 1) / 2] as (p, q) int32 pairs, row-major within a cell;
+ * *n_pairs = the pairs kept.  DDX_EINVAL for invalid arguments. */
+int ddx_chimg_cells(int32_t n_ant, const double* positions, double spacing, int32_t n_cells, int32_t* cell_ptr,
+                    int32_t* cell_pairs, int32_t* n_pairs);
+
+/* The pre-integrator over such cells, natural weights (1 / the pairs in the cell,
+ * zero for an empty cell): G_l[m] = 1 / (count_l L) sum_{(p,q) in cell l} sum_{n in
+ * block m} s_p[n] s_q[n]^*, Y_k[m] = sum_{l=1}^{n_cells} G_l[m] exp(-2 pi i k l /
+ * N_s).  d_cell_ptr, d_cell_pairs: DEVICE copies of the arrays above (0 <= p < q <
+ * n_ant); d_y: DEVICE [N_s][floor(n / L)].  For the trajectories the cells are a
+ * line of n_cells + 1 elements: pass n_ant = n_cells + 1 there.  2 <= n_ant <= 64,
+ * n_cells <= 1024, N_s a power of two <= 1024; DDX_EINVAL otherwise. */
+int ddx_chimg_preintegrate_cells(const void* d_volts, int32_t n_ant, int64_t n, int32_t block_len, int32_t n_s,
+                                 int32_t n_cells, const int32_t* d_cell_ptr, const int32_t* d_cell_pairs, void* d_y,
+                                 void* hip_stream);
+
 /* Trajectory sums (Eq. chimg_pth) for trials i (end bin k_end[i], duration
  * t_blocks[i] blocks) from every start block m0:
  *   P[i][m0] = sum_{m=m0}^{m0+T-1} conj(Phi(x_m)) Y_{k_m}[m],

@@ -100,3 +100,35 @@ def gradient_sums(Y, M, n_s, grads, lengths, L):
                     total += np.conj(phase(k0 - kr, M, n_s)) * Y[m0 + q, int(kr) % n_s]
                 P[i, j, m0] = total
     return P
+
+
+def nearest_cells(x, spacing):
+    """Gridding of a line of antennas at ascending positions x (Sec. 4: an arbitrary
+    array interpolated onto the regular grid of spacings): pair p < q goes to cell
+    l = rint((x_q - x_p) / spacing) (ties to even); cells l >= 1 are kept.  Returns
+    {l: [(p, q), ...]} with the pairs in row-major order."""
+    x = np.asarray(x, dtype=np.float64)
+    cells = {}
+    for p in range(x.size):
+        for q in range(p + 1, x.size):
+            l = int(np.rint((x[q] - x[p]) / spacing))
+            if l >= 1:
+                cells.setdefault(l, []).append((p, q))
+    return cells
+
+
+def grid_blocks_cells(s, L, cells, n_cells):
+    """G[m][l - 1] = 1 / (count_l L) sum_{(p, q) in cell l} sum_{n in block m}
+    s_p[n] s_q[n]^* for l = 1 .. n_cells (zero for empty cells): natural weights
+    over the pairs that fall in a cell.  The spatial DFT and trajectories then
+    treat the cells as a line of n_cells + 1 elements (M = n_cells + 1 in Phi)."""
+    s = np.asarray(s, dtype=np.complex128)
+    nb = s.shape[1] // L
+    G = np.zeros((nb, n_cells), dtype=np.complex128)
+    for l, prs in cells.items():
+        if l > n_cells:
+            continue
+        for p, q in prs:
+            x = s[p, :nb * L] * np.conj(s[q, :nb * L])
+            G[:, l - 1] += x.reshape(nb, L).sum(axis=1) / (len(prs) * L)
+    return G

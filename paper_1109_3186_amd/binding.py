@@ -124,6 +124,10 @@ SIGNATURES = {
                                 ct.c_int32, ct.c_void_p, ct.c_void_p], ct.c_int),
     "ddx_chimg_gradient_sums": ([ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p,
                                  ct.c_int32, ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p], ct.c_int),
+    "ddx_chimg_cells": ([ct.c_int32, ct.POINTER(ct.c_double), ct.c_double, ct.c_int32, ct.POINTER(ct.c_int32),
+                         ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)], ct.c_int),
+    "ddx_chimg_preintegrate_cells": ([ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32,
+                                      ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p], ct.c_int),
     "ddx_plan_destroy": ([ct.c_void_p], ct.c_int),
     "ddx_strerror": ([ct.c_int], ct.c_char_p),
     "ddx_last_error": ([ct.c_void_p], ct.c_char_p),
@@ -726,3 +730,39 @@ def chimg_gradient_sums(y, n_ant, block_len, grads, lengths, stream=None):
     if rc != OK:
         raise DdxError(rc, "ddx_chimg_gradient_sums")
     return p
+
+
+def chimg_cells(positions, spacing, n_cells):
+    """Cells of a line of antennas at ascending positions: (cell_ptr [n_cells + 1],
+    cell_pairs [n_pairs, 2]) int32 host arrays (see ddx_chimg_cells)."""
+    x = np.ascontiguousarray(positions, dtype=np.float64)
+    ptr = np.zeros(int(n_cells) + 1, dtype=np.int32)
+    prs = np.zeros((max(1, x.size * (x.size - 1) // 2), 2), dtype=np.int32)
+    cnt = ct.c_int32()
+    ip = ct.POINTER(ct.c_int32)
+    rc = lib().ddx_chimg_cells(x.size, x.ctypes.data_as(ct.POINTER(ct.c_double)), float(spacing), int(n_cells),
+                               ptr.ctypes.data_as(ip), prs.ctypes.data_as(ip), ct.byref(cnt))
+    if rc != OK:
+        raise DdxError(rc, "ddx_chimg_cells")
+    return ptr, prs[:cnt.value]
+
+
+def chimg_preintegrate_cells(volts, block_len, n_s, cell_ptr, cell_pairs, stream=None):
+    """The Chimageator pre-integrator over gridding cells (ddx_chimg_preintegrate_cells):
+    volts device complex64 [M, n]; returns device complex64 Y [n_s, n // block_len]."""
+    import torch
+    if volts.dtype != torch.complex64 or volts.dim() != 2:
+        raise DdxError(EINVAL, "volts must be complex64 [M, n]")
+    volts = volts.contiguous()
+    M, n = volts.shape
+    ptr = torch.as_tensor(np.ascontiguousarray(cell_ptr, dtype=np.int32), device=volts.device)
+    prs = torch.as_tensor(np.ascontiguousarray(cell_pairs, dtype=np.int32).reshape(-1, 2), device=volts.device)
+    if prs.numel() == 0:
+        prs = torch.zeros((1, 2), dtype=torch.int32, device=volts.device)
+    y = torch.empty((n_s, n // block_len), dtype=torch.complex64, device=volts.device)
+    rc = lib().ddx_chimg_preintegrate_cells(ct.c_void_p(volts.data_ptr()), M, n, int(block_len), int(n_s),
+                                            ptr.numel() - 1, ct.c_void_p(ptr.data_ptr()), ct.c_void_p(prs.data_ptr()),
+                                            ct.c_void_p(y.data_ptr()), _stream_handle(stream))
+    if rc != OK:
+        raise DdxError(rc, "ddx_chimg_preintegrate_cells")
+    return y

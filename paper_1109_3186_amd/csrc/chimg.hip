@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "ddx.h"
 
@@ -108,13 +109,19 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 // do not depend on scheduling.  Lane l supplies antenna l % 32 of the quadrant's
 // rows (A) or columns (B) at sample l / 32 of each pair of samples and holds C at
 // column l % 32, rows 8 (v / 4) + 4 (l / 32) + v % 4.
+// CELLS: the pairs are gridded onto cells given as lists (cell_ptr [n_cells + 1],
+// cell_pairs [(p, q)]) with natural weights instead of the line's spacings.
 // grid: nb workgroups of 256 threads.
+template <bool CELLS>
 __global__ __launch_bounds__(kThreads) void k_pre_mfma(const float2* __restrict__ s, int32_t M, int64_t n, int32_t L,
-                                                       int32_t n_s, int32_t natural, float2* __restrict__ y) {
+                                                       int32_t n_s, int32_t natural, const int32_t* __restrict__ cell_ptr,
+                                                       const int2* __restrict__ cell_pairs, int32_t n_cells,
+                                                       float2* __restrict__ y) {
   constexpr int R = 64;                 // padded antenna rows
   constexpr int CH = kStage / R;        // samples per staging round (80)
+  constexpr int NG = CELLS ? kMaxBins : R;
   __shared__ float2 xs[kStage];         // [R][CH] samples, then C [R][R + 1]
-  __shared__ float2 g[R];
+  __shared__ float2 g[NG];
   __shared__ float2 tw[kMaxBins];
   const int m = blockIdx.x;
   const int tid = threadIdx.x;
@@ -157,21 +164,39 @@ __global__ __launch_bounds__(kThreads) void k_pre_mfma(const float2* __restrict_
     }
   }
   __syncthreads();
-  if (tid < M - 1) {
-    const int l = tid + 1;
-    float2 v = make_float2(0.f, 0.f);
-    for (int p = 0; p + l < M; ++p) {
-      const float2 c = C[p * (R + 1) + p + l];
-      v.x += c.x;
-      v.y += c.y;
+  int n_g;   // gridded cells 1 .. n_g
+  if (CELLS) {
+    n_g = n_cells;
+    for (int c = tid; c < n_cells; c += kThreads) {
+      const int b0 = cell_ptr[c], b1 = cell_ptr[c + 1];
+      float2 v = make_float2(0.f, 0.f);
+      for (int b = b0; b < b1; ++b) {
+        const int2 pq = cell_pairs[b];   // 0 <= p < q < M by contract; clamped to the tile
+        const float2 cc = C[min(max(pq.x, 0), R - 1) * (R + 1) + min(max(pq.y, 0), R - 1)];
+        v.x += cc.x;
+        v.y += cc.y;
+      }
+      const float w = b1 > b0 ? 1.0f / ((float)(b1 - b0) * (float)L) : 0.f;
+      g[c] = make_float2(v.x * w, v.y * w);
     }
-    const float w = (natural ? 1.0f / (float)(M - l) : 1.0f) / (float)L;
-    g[tid] = make_float2(v.x * w, v.y * w);
+  } else {
+    n_g = M - 1;
+    if (tid < M - 1) {
+      const int l = tid + 1;
+      float2 v = make_float2(0.f, 0.f);
+      for (int p = 0; p + l < M; ++p) {
+        const float2 c = C[p * (R + 1) + p + l];
+        v.x += c.x;
+        v.y += c.y;
+      }
+      const float w = (natural ? 1.0f / (float)(M - l) : 1.0f) / (float)L;
+      g[tid] = make_float2(v.x * w, v.y * w);
+    }
   }
   __syncthreads();
   for (int k = tid; k < n_s; k += kThreads) {
     float2 v = make_float2(0.f, 0.f);
-    for (int q = 1; q < M; ++q) {
+    for (int q = 1; q <= n_g; ++q) {
       const float2 a = g[q - 1];
       const float2 t = tw[(int)(((int64_t)k * q) % n_s)];
       v.x = fmaf(a.x, t.x, fmaf(-a.y, t.y, v.x));
@@ -300,11 +325,56 @@ int ddx_chimg_preintegrate(const void* d_volts, int32_t n_ant, int64_t n, int32_
   if (nb > INT32_MAX) return DDX_EUNSUPPORTED;
   // up to 64 antennas: the pair products on the matrix cores; more: on the vector units
   if (n_ant <= 64)
-    hipLaunchKernelGGL(chimg::k_pre_mfma, dim3((unsigned)nb), dim3(chimg::kThreads), 0, (hipStream_t)hip_stream,
-                       (const float2*)d_volts, n_ant, n, block_len, n_s, natural_weights ? 1 : 0, (float2*)d_y);
+    hipLaunchKernelGGL((chimg::k_pre_mfma<false>), dim3((unsigned)nb), dim3(chimg::kThreads), 0,
+                       (hipStream_t)hip_stream, (const float2*)d_volts, n_ant, n, block_len, n_s,
+                       natural_weights ? 1 : 0, nullptr, nullptr, 0, (float2*)d_y);
   else
     hipLaunchKernelGGL(chimg::k_pre, dim3((unsigned)nb), dim3(chimg::kThreads), 0, (hipStream_t)hip_stream,
                        (const float2*)d_volts, n_ant, n, block_len, n_s, natural_weights ? 1 : 0, (float2*)d_y);
+  return hipGetLastError() == hipSuccess ? DDX_OK : DDX_EDEVICE;
+}
+
+int ddx_chimg_cells(int32_t n_ant, const double* positions, double spacing, int32_t n_cells, int32_t* cell_ptr,
+                    int32_t* cell_pairs, int32_t* n_pairs) {
+  if (n_ant < 2 || n_ant > 64 || !positions || !(spacing > 0.0) || !std::isfinite(spacing) || n_cells < 1 ||
+      n_cells > chimg::kMaxBins || !cell_ptr || !cell_pairs || !n_pairs)
+    return DDX_EINVAL;
+  for (int p = 0; p < n_ant; ++p)
+    if (!std::isfinite(positions[p]) || (p > 0 && !(positions[p] > positions[p - 1]))) return DDX_EINVAL;
+  // counting pass, then the pairs of each cell in row-major order
+  for (int c = 0; c <= n_cells; ++c) cell_ptr[c] = 0;
+  for (int p = 0; p < n_ant; ++p)
+    for (int q = p + 1; q < n_ant; ++q) {
+      const double l = std::nearbyint((positions[q] - positions[p]) / spacing);
+      if (l >= 1.0 && l <= (double)n_cells) ++cell_ptr[(int)l];
+    }
+  for (int c = 0; c < n_cells; ++c) cell_ptr[c + 1] += cell_ptr[c];
+  std::vector<int32_t> fill(cell_ptr, cell_ptr + n_cells);
+  for (int p = 0; p < n_ant; ++p)
+    for (int q = p + 1; q < n_ant; ++q) {
+      const double l = std::nearbyint((positions[q] - positions[p]) / spacing);
+      if (l >= 1.0 && l <= (double)n_cells) {
+        const int b = fill[(int)l - 1]++;
+        cell_pairs[2 * b] = p;
+        cell_pairs[2 * b + 1] = q;
+      }
+    }
+  *n_pairs = cell_ptr[n_cells];
+  return DDX_OK;
+}
+
+int ddx_chimg_preintegrate_cells(const void* d_volts, int32_t n_ant, int64_t n, int32_t block_len, int32_t n_s,
+                                 int32_t n_cells, const int32_t* d_cell_ptr, const int32_t* d_cell_pairs, void* d_y,
+                                 void* hip_stream) {
+  if (n_ant < 2 || n_ant > 64 || n < 0 || block_len < 1 || n_s < 1 || n_s > chimg::kMaxBins || (n_s & (n_s - 1)) ||
+      n_cells < 1 || n_cells > chimg::kMaxBins || !d_volts || !d_cell_ptr || !d_cell_pairs || !d_y)
+    return DDX_EINVAL;
+  const int64_t nb = n / block_len;
+  if (nb == 0) return DDX_OK;
+  if (nb > INT32_MAX) return DDX_EUNSUPPORTED;
+  hipLaunchKernelGGL((chimg::k_pre_mfma<true>), dim3((unsigned)nb), dim3(chimg::kThreads), 0, (hipStream_t)hip_stream,
+                     (const float2*)d_volts, n_ant, n, block_len, n_s, 1, d_cell_ptr, (const int2*)d_cell_pairs,
+                     n_cells, (float2*)d_y);
   return hipGetLastError() == hipSuccess ? DDX_OK : DDX_EDEVICE;
 }
 

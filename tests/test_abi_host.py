@@ -275,3 +275,18 @@ class _FakeTensor:
 
     def dim(self):
         return 2
+
+
+def test_chimageator_cells_match_the_oracle():
+    """The host cell table equals the oracle's gridding of the same positions."""
+    from oracle import chimageator as ocg
+    rng = np.random.Generator(np.random.PCG64(77))
+    x = np.sort(rng.uniform(0, 600.0, 12))
+    x = x[np.concatenate([[True], np.diff(x) > 0])]
+    ptr, prs = binding.chimg_cells(x, 25.0, 20)
+    ref = ocg.nearest_cells(x, 25.0)
+    for l in range(1, 21):
+        got = [tuple(p) for p in prs[ptr[l - 1]:ptr[l]]]
+        assert got == ref.get(l, []), l
+    with pytest.raises(binding.DdxError):
+        binding.chimg_cells([0.0, 5.0, 3.0], 1.0, 4)      # not ascending

@@ -92,3 +92,42 @@ def test_gradient_sums_match_oracle(gpu):
             r = ocg.trajectory(Y, M, n_s, g * 1030, 1030, m0, L)
             assert abs(got[i, 4, m0] - r) / np.sqrt(1030) <= 1e-5
     assert np.all(got[:, 5] == 0)             # 1200 blocks fit nowhere in 1100
+
+
+def test_cell_gridding_matches_oracle(gpu):
+    """Gridding onto cells: a uniform line reproduces the spacing path; a sparse,
+    jittered line matches the oracle's cell gridding, and the chirp on it is found
+    end to end (trajectories over the cells as a line of n_cells + 1 elements)."""
+    from paper_1109_3186_amd import chimg_cells, chimg_preintegrate_cells
+    rng = np.random.Generator(np.random.PCG64(840))
+    M, L, n_s = 9, 16, 32
+    s = synth.noise_complex(rng, (M, 6 * L + 3))
+    ptr, prs = chimg_cells(np.arange(M) * 40.0, 40.0, M - 1)
+    got = chimg_preintegrate_cells(_dev(s), L, n_s, ptr, prs).cpu().numpy()
+    spc = chimg_preintegrate(_dev(s), L, n_s).cpu().numpy()
+    assert np.max(np.abs(got - spc)) <= 1e-5 * np.sqrt(np.mean(np.abs(spc) ** 2))
+
+    pos_idx = np.array([0, 1, 3, 4, 7, 8, 11, 15, 16, 20])
+    x = pos_idx * 30.0 + rng.uniform(-4, 4, pos_idx.size)
+    ptr, prs = chimg_cells(x, 30.0, 20)
+    s = synth.noise_complex(rng, (pos_idx.size, 5 * L))
+    got = chimg_preintegrate_cells(_dev(s), L, 64, ptr, prs).cpu().numpy().T
+    ref = ocg.spatial_dft(ocg.grid_blocks_cells(s, L, ocg.nearest_cells(x, 30.0), 20), 64)
+    err = np.max(np.abs(got - ref)) / np.sqrt(np.mean(np.abs(ref) ** 2))
+    say("cell gridding: max error / rms %.3e" % err)
+    assert err <= 1e-5
+
+    M2, n_s2, L2, f_s = 10, 64, 16, 1e6
+    tb, m0, k_end = 20, 4, 11.0
+    tau1 = k_end / (n_s2 * f_s)
+    fdot = f_s * f_s / (tb * L2)
+    t = (np.arange((m0 + tb + 6) * L2) - m0 * L2) / f_s
+    tp = t[None, :] - (pos_idx * tau1)[:, None]
+    sc = np.where((tp >= 0) & (tp < tb * L2 / f_s), np.exp(1j * np.pi * fdot * tp ** 2), 0)
+    ptr, prs = chimg_cells(pos_idx * 30.0, 30.0, 20)
+    y = chimg_preintegrate_cells(_dev(sc), L2, n_s2, ptr, prs)
+    trials = [(k_end + dk, tb + dt) for dk in (-1.0, 0.0, 1.0) for dt in (-5, 0, 5)]
+    P = np.abs(chimg_trajectories(y, 21, L2, [t_[0] for t_ in trials], [t_[1] for t_ in trials]).cpu().numpy())
+    i, m = np.unravel_index(np.argmax(P), P.shape)
+    say("sparse line: best trial %s at block %d" % (trials[i], m))
+    assert trials[i] == (k_end, tb) and m == m0

@@ -122,3 +122,39 @@ def test_gradient_sums_are_the_trajectories_of_each_duration():
                 ref = cg.trajectory(Y, M, n_s, g * T, T, m0, L)
                 assert abs(P[i, j, m0] - ref) < 1e-10 * T
             assert np.all(P[i, j, nb - T + 1:] == 0)
+
+
+def test_cell_gridding_reduces_to_the_uniform_line():
+    """Antennas at integer multiples of the spacing: the cells are the spacings and
+    the cell gridding is the uniform-line gridding with natural weights; jittered
+    positions keep each pair in its cell."""
+    rng = _rng(40)
+    M, L = 7, 6
+    s = rng.normal(size=(M, 5 * L)) + 1j * rng.normal(size=(M, 5 * L))
+    cells = cg.nearest_cells(np.arange(M) * 25.0, 25.0)
+    assert sorted(cells) == list(range(1, M)) and all(len(cells[l]) == M - l for l in cells)
+    np.testing.assert_allclose(cg.grid_blocks_cells(s, L, cells, M - 1), cg.grid_blocks(s, L), atol=1e-13)
+    jit = np.arange(M) * 25.0 + rng.uniform(-5, 5, M)
+    assert cg.nearest_cells(jit, 25.0) == cells
+
+
+def test_cell_gridding_of_a_sparse_line_finds_the_chirp():
+    """A non-uniform line (some positions missing, some doubled spacings): the
+    chirp's spatial tone is still a tone over the cells, and the trajectory at the
+    true end bin, duration and start is the largest over a grid of trials."""
+    M, n_s, L, f_s = 10, 64, 16, 1e6
+    tb, m0, k_end = 20, 4, 11.0
+    pos_idx = np.array([0, 1, 3, 4, 7, 8, 11, 15, 16, 20])          # in units of the spacing
+    tau1 = k_end / (n_s * f_s)
+    fdot = f_s * f_s / (tb * L)
+    n = (m0 + tb + 6) * L
+    t = (np.arange(n) - m0 * L) / f_s
+    tp = t[None, :] - (pos_idx * tau1)[:, None]
+    s = np.where((tp >= 0) & (tp < tb * L / f_s), np.exp(1j * np.pi * fdot * tp ** 2), 0)
+    cells = cg.nearest_cells(pos_idx * 30.0, 30.0)
+    Y = cg.spatial_dft(cg.grid_blocks_cells(s, L, cells, 20), n_s)
+    trials = [(k_end + dk, tb + dt) for dk in (-1.0, 0.0, 1.0) for dt in (-5, 0, 5)]
+    # the phase of the sum over cells 1 .. 20 is that of a 21-element line
+    P = np.abs(cg.trajectories(Y, 21, n_s, trials, L))
+    i, m = np.unravel_index(np.argmax(P), P.shape)
+    assert trials[i] == (k_end, tb) and m == m0
