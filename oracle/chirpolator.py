@@ -213,3 +213,16 @@ def bank_factorised(s, n0, n_len, L, kmax):
                 full[w, :, j] = sum(short[w + (p - 1 - i) * rs, :, kmax + int(k) // p] for i in range(p))
         out.append(full)
     return out
+
+
+def gauss_sum(a, L):
+    """G(a, L) = sum_{n=0}^{L-1} exp(2 pi i a n^2) (App. A.2, Eq. gaussum): the sum of a
+    chirp over L samples that starts at the centre of a DFT bin; the coherence loss
+    is eta = |G(a, L)| / L."""
+    n = np.arange(L, dtype=np.float64)
+    return complex(np.sum(np.exp(2j * np.pi * a * n * n)))
+
+
+def coherence_loss(a, L):
+    """eta = |G(a, L)| / L."""
+    return abs(gauss_sum(a, L)) / L

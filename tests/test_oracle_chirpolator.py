@@ -140,3 +140,26 @@ def test_bank_factorisation_at_block_resolution():
         np.testing.assert_allclose(b, a, atol=1e-10)
     n_fact = sum(1 for d in range(1, n_len + 1) for k in range(-kmax, kmax + 1) if math.gcd(abs(k), d) > 1)
     assert n_fact == 23
+
+
+@pytest.mark.parametrize("c", [5, 6, 7, 8, 12, 13, 31, 64])
+def test_gauss_sum_closed_forms(c):
+    """G(1/c, c) is the quadratic Gauss sum: sqrt(c), 0, i sqrt(c) or (1 + i) sqrt(c)
+    for c = 1, 2, 3, 0 mod 4; G(0, L) = L and |G(a, L)| < L otherwise (App. A.2)."""
+    g = ch.gauss_sum(1.0 / c, c)
+    expect = {1: np.sqrt(c), 2: 0.0, 3: 1j * np.sqrt(c), 0: (1 + 1j) * np.sqrt(c)}[c % 4]
+    assert abs(g - expect) < 1e-9 * c
+    assert abs(ch.gauss_sum(0.0, c) - c) < 1e-12
+    assert ch.coherence_loss(0.3 / c ** 2, c) < 1.0
+
+
+def test_coherence_loss_falls_with_the_block_length():
+    """For a fixed chirp rate a, longer blocks lose more (eta decreasing in L), and
+    eta is the magnitude of the k = 0 block partial DFT of the chirp over L."""
+    a = 2e-6
+    etas = [ch.coherence_loss(a, L) for L in (64, 256, 512, 1024)]
+    assert all(x > y for x, y in zip(etas, etas[1:])) and etas[0] > 0.99
+    L = 300
+    x = np.exp(2j * np.pi * a * np.arange(L) ** 2)
+    v = ch.block_partial_dft(x, L, L, [0])[0, 0]
+    assert abs(abs(v) / L - ch.coherence_loss(a, L)) < 1e-12
