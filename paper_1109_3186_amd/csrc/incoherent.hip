@@ -45,7 +45,8 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p,
                                                     float* __restrict__ out, int64_t n_out) {
   __shared__ float buf[kChanGroup][kSpan];
   __shared__ int lo_s[kChanGroup], hi_s[kChanGroup];
-  __shared__ int dls[kChanGroup][kDmTile];   // the group's delays for the tile's DMs
+  __shared__ int dls[kChanGroup][kDmTile];   // the group's delays for the tile's DMs, as
+                                             // byte offsets from the channel's least delay
   constexpr int TILE = kThreads * kOut;
   const int64_t t0 = (int64_t)blockIdx.x * TILE;
   const int64_t t = t0 + threadIdx.x;     // and t + 256
@@ -61,7 +62,6 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p,
     for (int ci = wv; ci < nc; ci += kThreads / 64) {
       const int32_t* dl = delays + (int64_t)(c0 + ci) * n_dm + d0;
       const int mine = lane < nd ? dl[lane] : 0;
-      if (lane < kDmTile) dls[ci][lane] = mine;
       int lo = lane < nd ? mine : INT32_MAX;
       int hi = lane < nd ? mine : INT32_MIN;
       for (int o = 16; o > 0; o >>= 1) {
@@ -72,6 +72,8 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p,
         lo_s[ci] = lo;
         hi_s[ci] = hi;
       }
+      // every lane of the 32 holds the range now; DMs past nd read offset 0
+      if (lane < kDmTile) dls[ci][lane] = lane < nd ? (mine - lo) * (int)sizeof(float) : 0;
     }
     __syncthreads();
     for (int ci = 0; ci < nc; ++ci) {
@@ -85,15 +87,14 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p,
     }
     __syncthreads();
     for (int ci = 0; ci < nc; ++ci) {
-      const int* dl = dls[ci];   // zero past nd: those sums are never written
+      const int* off = dls[ci];   // byte offsets in [0, 4 (hi - lo)]; 0 past nd (never written out)
       const int lo = lo_s[ci], hi = hi_s[ci];
       if (hi - lo + TILE <= kSpan) {
-        // dl[i] lies in [lo, hi] for i < nd; the clamp keeps the unused i >= nd
-        // (dl = 0) inside the staged span too.  One address serves both outputs.
-        const float* b = buf[ci] + threadIdx.x - lo;
+        // one address per DM serves both outputs (256 samples apart)
+        const char* b = reinterpret_cast<const char*>(buf[ci] + threadIdx.x);
 #pragma unroll
         for (int i = 0; i < kDmTile; ++i) {
-          const float* bi = b + min(max(dl[i], lo), hi);
+          const float* bi = reinterpret_cast<const float*>(b + off[i]);
 #pragma unroll
           for (int o = 0; o < kOut; ++o) acc[o][i] += bi[o * kThreads];
         }
@@ -101,9 +102,10 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p,
         const float* row = p + (int64_t)(c0 + ci) * n_t;
 #pragma unroll
         for (int i = 0; i < kDmTile; ++i) {
+          const int d = lo + off[i] / (int)sizeof(float);
 #pragma unroll
           for (int o = 0; o < kOut; ++o) {
-            const int64_t s = t + o * kThreads + dl[i];
+            const int64_t s = t + o * kThreads + d;
             acc[o][i] += (s >= 0 && s < n_t) ? row[s] : 0.f;
           }
         }
