@@ -30,6 +30,8 @@ constexpr int kDmTile = 32;         // brute force: DMs per workgroup (and per t
 constexpr int kChanGroup = 8;       // brute force: channels staged per LDS round
 constexpr int kOut = 2;             // brute force: outputs per thread, 256 apart
 constexpr int kSpan = 768;          // brute force: staged samples per channel (tile 512 + spread 256)
+constexpr int kStage = kSpan / kThreads;   // brute force: staged samples per thread and channel
+static_assert(kSpan % kThreads == 0, "the staging covers the span in whole rounds");
 constexpr int kFuseLog = 5;         // tree: the first 5 stages (groups of 32 channels) in LDS
 constexpr int kFuseRows = 1 << kFuseLog;
 constexpr int kTreeTile = 224;      // tree: samples per fused tile (tile + 32 halo = 256 per row)
@@ -76,14 +78,32 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p,
       if (lane < kDmTile) dls[ci][lane] = lane < nd ? (mine - lo) * (int)sizeof(float) : 0;
     }
     __syncthreads();
-    for (int ci = 0; ci < nc; ++ci) {
-      const int lo = lo_s[ci], hi = hi_s[ci];
-      if (hi - lo + TILE > kSpan) continue;   // read from global below
-      const float* row = p + (int64_t)(c0 + ci) * n_t;
-      for (int x = threadIdx.x; x < hi - lo + TILE; x += kThreads) {
-        const int64_t s = t0 + lo + x;
-        buf[ci][x] = (s >= 0 && s < n_t) ? row[s] : 0.f;
+    {
+      // every load of the round is issued before the first LDS store (the loads'
+      // latency overlaps); a channel read from global below stages nothing, and
+      // the unused tail of a span is zero-filled
+      // per channel a uniform base (sample t0 + lo) and uniform limits on x: the
+      // samples x_lo <= x < x_hi exist and belong to the span
+      float v[kChanGroup][kStage];
+#pragma unroll
+      for (int ci = 0; ci < kChanGroup; ++ci) {
+        const int lo = __builtin_amdgcn_readfirstlane(lo_s[ci]);   // stale past nc: unused
+        const int n = __builtin_amdgcn_readfirstlane(hi_s[ci]) - lo + TILE;
+        const bool staged = ci < nc && n <= kSpan;
+        const int64_t b = t0 + lo;
+        const int x_lo = (int)std::min<int64_t>(kSpan, std::max<int64_t>(0, -b));
+        const int x_hi = staged ? (int)std::max<int64_t>(0, std::min<int64_t>(n, n_t - b)) : 0;
+        const float* src = p + (int64_t)(c0 + ci) * n_t + b;   // read only at x_lo <= x < x_hi
+#pragma unroll
+        for (int q = 0; q < kStage; ++q) {
+          const int x = threadIdx.x + q * kThreads;
+          v[ci][q] = (x >= x_lo && x < x_hi) ? src[x] : 0.f;
+        }
       }
+#pragma unroll
+      for (int ci = 0; ci < kChanGroup; ++ci)
+#pragma unroll
+        for (int q = 0; q < kStage; ++q) buf[ci][threadIdx.x + q * kThreads] = v[ci][q];
     }
     __syncthreads();
     for (int ci = 0; ci < nc; ++ci) {
@@ -108,6 +128,9 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p,
             const int64_t s = t + o * kThreads + d;
             acc[o][i] += (s >= 0 && s < n_t) ? row[s] : 0.f;
           }
+          // one DM's loads at a time: this rare path must not set the register
+          // budget (and with it the occupancy) of the staged path
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
