@@ -79,11 +79,11 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p,
     }
     __syncthreads();
     {
-      // every load of the round is issued before the first LDS store (the loads'
-      // latency overlaps); a channel read from global below stages nothing, and
-      // the unused tail of a span is zero-filled
-      // per channel a uniform base (sample t0 + lo) and uniform limits on x: the
-      // samples x_lo <= x < x_hi exist and belong to the span
+      // every load of the round is issued before the first LDS store, so that
+      // the loads' latencies overlap; a channel read from global below stages
+      // nothing, and the unused tail of a span is zero-filled.  Per channel a
+      // uniform base (sample t0 + lo) and uniform limits on x: the samples
+      // x_lo <= x < x_hi exist and belong to the span
       float v[kChanGroup][kStage];
 #pragma unroll
       for (int ci = 0; ci < kChanGroup; ++ci) {
@@ -128,8 +128,7 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p,
             const int64_t s = t + o * kThreads + d;
             acc[o][i] += (s >= 0 && s < n_t) ? row[s] : 0.f;
           }
-          // one DM's loads at a time: this rare path must not set the register
-          // budget (and with it the occupancy) of the staged path
+          // one DM's loads at a time (this rare path keeps few loads in flight)
           __builtin_amdgcn_sched_barrier(0);
         }
       }
