@@ -86,6 +86,7 @@ def tree(power):
                 b = rows[g * n + n // 2 + h]        # second half: group 2g + 1
                 s = j - h
                 out[g * n + j] = a
-                out[g * n + j, :n_t - s] += b[s:]
+                if s < n_t:                         # advanced past the end: adds nothing
+                    out[g * n + j, :n_t - s] += b[s:]
         rows = out
     return rows

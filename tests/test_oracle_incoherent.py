@@ -16,8 +16,9 @@ def _rng(seed):
     return np.random.Generator(np.random.PCG64(seed))
 
 
-@pytest.mark.parametrize("C,T", [(1, 7), (2, 9), (8, 40), (32, 70)])
+@pytest.mark.parametrize("C,T", [(1, 7), (2, 9), (8, 40), (32, 70), (16, 3), (64, 20)])
 def test_tree_equals_brute_force_with_its_delays(C, T):
+    """Also with fewer samples than the largest sweep shift (those reads are zero)."""
     p = _rng(C).integers(0, 100, (C, T)).astype(np.float64)
     out = inc.tree(p)
     delays = np.array([inc.tree_delays(C, j) for j in range(C)]).T    # [C][sweeps]
