@@ -370,9 +370,10 @@ def run_incoherent(args, dev):
     tree_units = C * T * C / (ms_tree / 1e3)
     brute_units = C * n_out * D / (ms_brute / 1e3)
     # tree: the fused first five stages read and write every row once, and so does
-    # each later stage (each input row feeds two output rows, read once through L2)
+    # each later pass of two stages (one alone if their count is odd; each input
+    # row feeds four output rows, read once through L2)
     stages = int(np.log2(C))
-    staged = 8.0 * C * T * (1 + stages - 5)
+    staged = 8.0 * C * T * (1 + (stages - 5 + 1) // 2)
     gbs = staged / (ms_tree / 1e3) / 1e9
     log("incoherent: tree %.2f ms (%.3e units/s, %.0f GB/s staged); brute force %.2f ms (%.3e units/s)" % (
         ms_tree, tree_units, gbs, ms_brute, brute_units))
@@ -400,7 +401,7 @@ def run_incoherent(args, dev):
            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
                         "frac": round(gbs / PEAKS["hbm_gbs"], 4),
                         "traffic": measured_traffic("tree", "incoherent", INCOHERENT_SOURCES),
-                        "kernel": "k_tree_fused + k_tree_stage (one call)"},
+                        "kernel": "k_tree_fused + k_tree_stage2 + k_tree_stage (one call)"},
            "cpu_baseline": cpu,
            "brute_force": {"ms_per_call": round(ms_brute, 3), "units_per_s": brute_units, "n_out": n_out,
                            "adds_per_s": C * n_out * D / (ms_brute / 1e3),

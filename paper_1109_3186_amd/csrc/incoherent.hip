@@ -13,8 +13,8 @@
 // Channel 0 is the least delayed (highest frequency); samples past the end count
 // as zero.  The brute force stages each channel's samples for a tile of 32 DMs in
 // LDS (one staged sample serves every DM of the tile); the tree is a memory-bound
-// stream, two rows read and one written per stage, its first five stages fused in
-// LDS.
+// stream, its first five stages fused in LDS and the later ones two per pass, each
+// pass reading and writing every row once.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -222,6 +222,43 @@ __global__ __launch_bounds__(kThreads) void k_tree_stage(const float* __restrict
   }
 }
 
+// Two later tree stages in one pass: groups of n/4 rows -> n/2 -> n.  Output rows
+// j = 4k .. 4k + 3 of a group of n all come from the four input rows k of its
+// quarters (A, B, C, D); with h = j >> 1, s = j - h and s2 = h - (h >> 1) (k or
+// k + 1), row j = [A + B advanced by s2] + [C + D advanced by s2] advanced by s, each
+// bracket the intermediate row, summed in the order the two stages would, so the
+// result is bit-identical to two single stages.  One thread makes the four output
+// rows of kStageVec samples 256 apart: the four input rows are read once from HBM,
+// and the loads the four rows share are issued once.  (A generic pass of K stages,
+// 2^K shifted reads per output, ran slower for K = 2 and for K = 3.)
+// grid: (ceil(n_t / (256 kStageVec)), C / 4) x 256.
+__global__ __launch_bounds__(kThreads) void k_tree_stage2(const float* __restrict__ in, float* __restrict__ out,
+                                                          int64_t n_t, int32_t n) {
+  const int q = blockIdx.y, nq = n / 4;
+  const int k = q % nq;
+  const int64_t base = (int64_t)(q - k) * 4;   // first row of the group of n
+  const float* ra = in + (base + k) * n_t;
+  const float* rb = in + (base + nq + k) * n_t;
+  const float* rc = in + (base + 2 * nq + k) * n_t;
+  const float* rd = in + (base + 3 * nq + k) * n_t;
+  float* ro = out + (base + 4 * k) * n_t;
+  const int64_t t0 = (int64_t)blockIdx.x * kThreads * kStageVec + threadIdx.x;
+  // the value of an input row at sample u, zero past the end
+  auto at = [n_t](const float* r, int64_t u) { return u < n_t ? r[u] : 0.f; };
+#pragma unroll
+  for (int i = 0; i < kStageVec; ++i) {
+    const int64_t t = t0 + (int64_t)i * kThreads;
+    if (t >= n_t) continue;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = 4 * k + e, h = j >> 1, s = j - h, s2 = h - (h >> 1);
+      const float first = ra[t] + at(rb, t + s2);
+      const float second = t + s < n_t ? rc[t + s] + at(rd, t + s + s2) : 0.f;
+      ro[(int64_t)e * n_t + t] = first + second;
+    }
+  }
+}
+
 // p[c][t] = sum over antennas and the n_int samples of interval t of |x|^2.
 // grid: (ceil(n_out / 256), C) x 256; thread = one interval.
 __global__ __launch_bounds__(kThreads) void k_power_beam(const float2* __restrict__ x, int32_t M, int64_t S,
@@ -291,8 +328,11 @@ int ddx_tree_dedisperse(const float* d_power, int32_t n_chan, int64_t n_t, float
   if ((fused ? rest >= 1 : stages >= 2) && !d_work) return DDX_EINVAL;
   const int64_t gx = (n_t + (int64_t)inc::kThreads * inc::kStageVec - 1) / ((int64_t)inc::kThreads * inc::kStageVec);
   if (gx > INT32_MAX) return DDX_EUNSUPPORTED;
-  // the stages after the fused ones alternate between out and work, ending in out
-  float* first = (rest % 2 == 0) ? d_out : d_work;
+  // the stages after the fused ones run two per pass (the last alone if their count
+  // is odd), alternating between out and work and ending in out.  (Three per pass
+  // moves a third less but reads seven shifted rows per output: slower.)
+  const int passes = (rest + 1) / 2;
+  float* first = (passes % 2 == 0) ? d_out : d_work;
   if (n_chan >= inc::kFuseRows) {
     const int64_t tx = (n_t + inc::kTreeTile - 1) / inc::kTreeTile;
     hipLaunchKernelGGL(inc::k_tree_fused, dim3((unsigned)tx, (unsigned)(n_chan / inc::kFuseRows)),
@@ -312,10 +352,14 @@ int ddx_tree_dedisperse(const float* d_power, int32_t n_chan, int64_t n_t, float
     return hipGetLastError() == hipSuccess ? DDX_OK : DDX_EDEVICE;
   }
   const float* src = first;
-  for (int st = fused + 1; st <= stages; ++st) {
+  for (int st = fused + 1; st <= stages; st += 2) {
     float* dst = (src == d_out) ? d_work : d_out;
-    hipLaunchKernelGGL(inc::k_tree_stage, dim3((unsigned)gx, (unsigned)n_chan), dim3(inc::kThreads), 0, s, src, dst,
-                       n_t, 1 << st);
+    if (st + 1 <= stages)
+      hipLaunchKernelGGL(inc::k_tree_stage2, dim3((unsigned)gx, (unsigned)(n_chan / 4)), dim3(inc::kThreads), 0, s,
+                         src, dst, n_t, 1 << (st + 1));
+    else
+      hipLaunchKernelGGL(inc::k_tree_stage, dim3((unsigned)gx, (unsigned)n_chan), dim3(inc::kThreads), 0, s, src, dst,
+                         n_t, 1 << st);
     src = dst;
   }
   return hipGetLastError() == hipSuccess ? DDX_OK : DDX_EDEVICE;

@@ -22,8 +22,10 @@ def _dev(a, dtype):
 
 
 @pytest.mark.parametrize("C,T", [(1, 300), (2, 257), (4, 1000), (16, 513), (32, 700), (64, 1000), (128, 300),
-                                 (1024, 4100)])
+                                 (256, 1100), (512, 700), (2048, 1500), (1024, 4100), (256, 90), (1024, 300)])
 def test_tree_is_exact_on_integer_power(gpu, C, T):
+    """Every mix of later passes (one, two and three stages: 64 .. 2048 channels),
+    and fewer samples than the largest sweep shift."""
     p = np.random.Generator(np.random.PCG64(500 + C)).integers(0, 64, (C, T)).astype(np.float64)
     say("tree: C %d T %d" % (C, T))
     got = tree_dedisperse(_dev(p, np.float32)).cpu().numpy()
