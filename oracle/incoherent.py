@@ -45,16 +45,19 @@ def dm_delays(freqs_hz, t_samp_s, dms, k_dm=4.148808e15):
 
 
 def brute_force(power, delays, n_out):
-    """out[d][t] = sum_c power[c][t + delays[c][d]], t < n_out (zero past the end)."""
+    """out[d][t] = sum_c power[c][t + delays[c][d]], t < n_out (samples before the
+    first or past the last count as zero)."""
     p = np.asarray(power, dtype=np.float64)
     dl = np.asarray(delays, dtype=np.int64)
     C, n_t = p.shape
     out = np.zeros((dl.shape[1], n_out))
     for d in range(dl.shape[1]):
         for c in range(C):
-            lo = dl[c, d]
-            seg = p[c, lo:min(n_t, lo + n_out)]
-            out[d, :seg.size] += seg
+            lo = int(dl[c, d])
+            t0 = max(0, -lo)                        # outputs before t0 read before sample 0
+            s0, s1 = t0 + lo, min(n_t, lo + n_out)  # the samples that exist
+            if s1 > s0:
+                out[d, t0:t0 + s1 - s0] += p[c, s0:s1]
     return out
 
 

@@ -80,3 +80,21 @@ def test_power_beam_is_the_detected_sum():
         for t in range(6):
             ref = sum(abs(v[c, a, n]) ** 2 for a in range(4) for n in range(8 * t, 8 * t + 8))
             assert abs(p[c, t] - ref) < 1e-10
+
+
+def test_brute_force_is_the_plain_sum_for_any_delays():
+    """Brute force on tiny inputs against the per-element definition, with delays
+    before the first sample, past the last and spread widely."""
+    rng = _rng(77)
+    C, T, D = 5, 23, 9
+    p = rng.random((C, T))
+    dl = rng.integers(-30, 30, (C, D))
+    for n_out in (1, 17, 40):
+        ref = np.zeros((D, n_out))
+        for d in range(D):
+            for t in range(n_out):
+                for c in range(C):
+                    s = t + dl[c, d]
+                    if 0 <= s < T:
+                        ref[d, t] += p[c, s]
+        assert np.allclose(inc.brute_force(p, dl, n_out), ref, rtol=0, atol=1e-12)
