@@ -61,6 +61,20 @@ def test_brute_force_matches_oracle(gpu, C, D, extra, cut):
     assert err <= 1e-6
 
 
+@pytest.mark.parametrize("C,D,T,n_out", [(40, 70, 900, 1200), (9, 33, 2000, 1100)])
+def test_brute_force_any_delays(gpu, C, D, T, n_out):
+    """Delays before the first sample and past the last, and channels whose delays
+    spread beyond the staged span (read from global memory) next to staged ones."""
+    rng = np.random.Generator(np.random.PCG64(610 + C))
+    dl = rng.integers(-400, 400, (C, D)).astype(np.int32)
+    dl[::3] = rng.integers(-40, 40, (len(dl[::3]), D))      # narrow channels: staged
+    p = rng.random((C, T))
+    say("brute force, any delays: C %d D %d T %d n_out %d" % (C, D, T, n_out))
+    got = incoherent_dedisperse(_dev(p, np.float32), _dev(dl, np.int32), n_out).cpu().numpy()
+    ref = oinc.brute_force(p, dl, n_out)
+    assert np.max(np.abs(got - ref)) / C <= 1e-6
+
+
 def test_brute_force_recovers_a_dispersed_impulse(gpu):
     C, D = 64, 33
     f = 1.2005e9 + 1e6 * np.arange(C)[::-1]
