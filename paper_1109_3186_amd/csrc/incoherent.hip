@@ -47,14 +47,17 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p,
                                                     float* __restrict__ out, int64_t n_out) {
   __shared__ float buf[kChanGroup][kSpan];
   __shared__ int lo_s[kChanGroup], hi_s[kChanGroup];
-  __shared__ int dls[kChanGroup][kDmTile];   // the group's delays for the tile's DMs, as
-                                             // byte offsets from the channel's least delay
+  __shared__ unsigned dls[kChanGroup][kDmTile];   // the group's delays for the tile's DMs,
+                                                  // as offsets from the channel's least delay
   constexpr int TILE = kThreads * kOut;
   const int64_t t0 = (int64_t)blockIdx.x * TILE;
   const int64_t t = t0 + threadIdx.x;     // and t + 256
   const int d0 = blockIdx.y * kDmTile;
   const int nd = min(kDmTile, n_dm - d0);
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // a channel is staged iff its delays spread over at most kSpan - TILE samples
+  // (lo <= hi, so the unsigned difference is the exact spread, with no overflow)
+  auto fits = [](int lo, int hi) { return (unsigned)hi - (unsigned)lo <= (unsigned)(kSpan - TILE); };
   float acc[kOut][kDmTile] = {};
   for (int c0 = 0; c0 < C; c0 += kChanGroup) {
     const int nc = min(kChanGroup, C - c0);
@@ -74,8 +77,9 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p,
         lo_s[ci] = lo;
         hi_s[ci] = hi;
       }
-      // every lane of the 32 holds the range now; DMs past nd read offset 0
-      if (lane < kDmTile) dls[ci][lane] = lane < nd ? (mine - lo) * (int)sizeof(float) : 0;
+      // every lane of the 32 holds the range now; DMs past nd read offset 0.  As
+      // unsigned, mine - lo is exact for any int32 delays
+      if (lane < kDmTile) dls[ci][lane] = lane < nd ? (unsigned)mine - (unsigned)lo : 0u;
     }
     __syncthreads();
     {
@@ -88,8 +92,9 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p,
 #pragma unroll
       for (int ci = 0; ci < kChanGroup; ++ci) {
         const int lo = __builtin_amdgcn_readfirstlane(lo_s[ci]);   // stale past nc: unused
-        const int n = __builtin_amdgcn_readfirstlane(hi_s[ci]) - lo + TILE;
-        const bool staged = ci < nc && n <= kSpan;
+        const int hi = __builtin_amdgcn_readfirstlane(hi_s[ci]);
+        const bool staged = ci < nc && fits(lo, hi);
+        const int n = staged ? hi - lo + TILE : 0;
         const int64_t b = t0 + lo;
         const int x_lo = (int)std::min<int64_t>(kSpan, std::max<int64_t>(0, -b));
         const int x_hi = staged ? (int)std::max<int64_t>(0, std::min<int64_t>(n, n_t - b)) : 0;
@@ -107,14 +112,14 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p,
     }
     __syncthreads();
     for (int ci = 0; ci < nc; ++ci) {
-      const int* off = dls[ci];   // byte offsets in [0, 4 (hi - lo)]; 0 past nd (never written out)
+      const unsigned* off = dls[ci];   // in [0, hi - lo]; 0 past nd (never written out)
       const int lo = lo_s[ci], hi = hi_s[ci];
-      if (hi - lo + TILE <= kSpan) {
+      if (fits(lo, hi)) {
         // one address per DM serves both outputs (256 samples apart)
-        const char* b = reinterpret_cast<const char*>(buf[ci] + threadIdx.x);
+        const float* b = buf[ci] + threadIdx.x;
 #pragma unroll
         for (int i = 0; i < kDmTile; ++i) {
-          const float* bi = reinterpret_cast<const float*>(b + off[i]);
+          const float* bi = b + off[i];
 #pragma unroll
           for (int o = 0; o < kOut; ++o) acc[o][i] += bi[o * kThreads];
         }
@@ -122,7 +127,7 @@ __global__ __launch_bounds__(kThreads) void k_brute(const float* __restrict__ p,
         const float* row = p + (int64_t)(c0 + ci) * n_t;
 #pragma unroll
         for (int i = 0; i < kDmTile; ++i) {
-          const int d = lo + off[i] / (int)sizeof(float);
+          const int d = (int)((unsigned)lo + off[i]);   // the delay itself, exactly
 #pragma unroll
           for (int o = 0; o < kOut; ++o) {
             const int64_t s = t + o * kThreads + d;

@@ -61,13 +61,18 @@ def test_brute_force_matches_oracle(gpu, C, D, extra, cut):
     assert err <= 1e-6
 
 
-@pytest.mark.parametrize("C,D,T,n_out", [(40, 70, 900, 1200), (9, 33, 2000, 1100)])
-def test_brute_force_any_delays(gpu, C, D, T, n_out):
+@pytest.mark.parametrize("C,D,T,n_out,extreme", [(40, 70, 900, 1200, False), (9, 33, 2000, 1100, False),
+                                                 (12, 40, 700, 700, True)])
+def test_brute_force_any_delays(gpu, C, D, T, n_out, extreme):
     """Delays before the first sample and past the last, and channels whose delays
-    spread beyond the staged span (read from global memory) next to staged ones."""
+    spread beyond the staged span (read from global memory) next to staged ones;
+    extreme: delays near +-2^30, spreads that overflow 32-bit byte offsets."""
     rng = np.random.Generator(np.random.PCG64(610 + C))
     dl = rng.integers(-400, 400, (C, D)).astype(np.int32)
     dl[::3] = rng.integers(-40, 40, (len(dl[::3]), D))      # narrow channels: staged
+    if extreme:
+        dl[1::3] = np.where(rng.random((len(dl[1::3]), D)) < 0.5, -1, 1) * (1 << 30) + dl[1::3]
+        dl[2, :5] = [0, 2 ** 31 - 1, -2 ** 31, 5, -7]
     p = rng.random((C, T))
     say("brute force, any delays: C %d D %d T %d n_out %d" % (C, D, T, n_out))
     got = incoherent_dedisperse(_dev(p, np.float32), _dev(dl, np.int32), n_out).cpu().numpy()
