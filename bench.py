@@ -244,11 +244,11 @@ def run_chirp(args, dev):
                 "speedup": round(ms_direct / ms_bank, 3), "factorised_fraction": round(frac, 4)}
     cpu = None
     if not args.no_cpu_baseline:
-        # the FP64 oracle on one pair over the first 1024 blocks, one thread
+        # the FP64 oracle on one pair over the first 2048 blocks, one thread
         from threadpoolctl import threadpool_limits
 
         from oracle import chirpolator as och
-        nbs = 1024
+        nbs = 2048   # about 10 s of oracle work
         s01 = volts[:2, :nbs * L].cpu().numpy().astype(np.complex128)
         with threadpool_limits(1):
             tc = time.perf_counter()
@@ -317,7 +317,7 @@ def image_leg(args, dev, bins, pos2d, N, L, kmax):
         from threadpoolctl import threadpool_limits
 
         from oracle import imaging as oim
-        sub = pix[:192]   # about 10 s of oracle work
+        sub = pix[:384]   # about 10 s of oracle work
         rows = bins[:1].cpu().numpy().astype(np.complex128)
         with threadpool_limits(1):
             tc = time.perf_counter()
@@ -476,7 +476,7 @@ def run_chimg(args, dev):
 
 
 def chimg_cpu_baseline(args, volts, L, n_s):
-    """The FP64 oracle's Chimageator pre-integrator on the first 16384 blocks (about
+    """The FP64 oracle's Chimageator pre-integrator on the first 32768 blocks (about
     10 s), one thread."""
     if args.no_cpu_baseline:
         return None
@@ -484,7 +484,7 @@ def chimg_cpu_baseline(args, volts, L, n_s):
     from threadpoolctl import threadpool_limits
 
     from oracle import chimageator as ocg
-    nb = 16384
+    nb = 32768
     s = volts[:, :nb * L].cpu().numpy().astype(np.complex128)
     with threadpool_limits(1):
         tc = time.perf_counter()
