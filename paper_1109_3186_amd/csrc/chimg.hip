@@ -138,9 +138,21 @@ __global__ __launch_bounds__(kThreads) void k_pre_mfma(const float2* __restrict_
   for (int n0 = 0; n0 < L; n0 += CH) {
     const int len = min(CH, L - n0);
     __syncthreads();
-    for (int e = tid; e < R * CH; e += kThreads) {
-      const int p = e / CH, j = e - p * CH;
-      xs[e] = (p < M && j < len) ? s[(int64_t)p * n + (int64_t)m * L + n0 + j] : make_float2(0.f, 0.f);
+    {
+      // all the round's loads are issued before the first LDS store (their
+      // latencies overlap)
+      static_assert(R * CH % kThreads == 0, "the staging covers the tile in whole rounds");
+      constexpr int PER = R * CH / kThreads;
+      float2 v[PER];
+      const float2* sm = s + (int64_t)m * L + n0;
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = tid + u * kThreads;
+        const int p = e / CH, j = e - p * CH;
+        v[u] = (p < M && j < len) ? sm[(int64_t)p * n + j] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < PER; ++u) xs[tid + u * kThreads] = v[u];
     }
     __syncthreads();
     if (used) {
