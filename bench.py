@@ -36,6 +36,7 @@ def log(*a):
 DEDISP_SOURCES = ("fft.hpp", "kernels.hpp", "ddx.hip", "tiles.hpp", "cnn_kernels.hpp", "cnn.hip")
 IMAGE_SOURCES = ("image.hip",)
 INCOHERENT_SOURCES = ("incoherent.hip",)
+CHIMG_SOURCES = ("chimg.hip",)
 
 
 def kernel_source_hash(sources=DEDISP_SOURCES):
@@ -465,7 +466,8 @@ def run_chimg(args, dev):
                       "n_ant": M, "samples": n, "block_len": L, "n_bins": n_s, "trials": len(trials),
                       "parallelism": "none (1 GPU)"},
            "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": PEAKS["fp32_mfma_tflops"],
-                        "unit": "TFLOP/s", "frac": round(tf / PEAKS["fp32_mfma_tflops"], 4), "traffic": None,
+                        "unit": "TFLOP/s", "frac": round(tf / PEAKS["fp32_mfma_tflops"], 4),
+                        "traffic": measured_traffic("pre", "chimg", CHIMG_SOURCES),
                         "kernel": "k_pre_mfma (pair products on FP32 MFMA + spatial DFT)"},
            "cpu_baseline": chimg_cpu_baseline(args, volts, L, n_s),
            "trajectories": {"ms_per_call": round(ms_traj, 3), "gathers_per_s": gathers / (ms_traj / 1e3),
