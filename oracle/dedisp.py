@@ -183,7 +183,11 @@ def run_oracle(volts, chan_freqs, f_s, dm_lists, dump_len, blockings, sideband=1
     volts: [C, M, S] complex (or [C, M, 2S] interleaved int8).
     dm_lists[c]: trial DMs of channel c.  blockings[c]: dict with fft_len,
     valid and lead (the plan's blocking).  quant: None, "e4m3" or "f16" to
-    emulate the correlator input format with per-channel scale scales[c].
+    emulate the reduced-precision correlator inputs with per-channel scale
+    scales[c]: the cross products V_ij (i != j) are those of the rounded
+    voltages quantize(y s) / s^2, while the autocorrelations V_ii keep the
+    unrounded voltages' power (reading: only the products between antennas
+    take the narrow format; total power is formed at full precision).
     chans / dm_index restrict the work to some channels / DM indices.
     Returns {(c, d): V[dumps, M(M+1)/2]} complex128.
     """
@@ -199,12 +203,15 @@ def run_oracle(volts, chan_freqs, f_s, dm_lists, dump_len, blockings, sideband=1
         for d in ds:
             h = chirp(chan_freqs[c], f_s, bl["fft_len"], dms[d], sideband, k_dm)
             y = dedisperse_stream(x, h, bl["fft_len"], bl["valid"], bl["lead"])
+            v = correlate_dumps(y, dump_len)
             if quant is not None:
+                # cross products from the rounded inputs; the autocorrelations
+                # (total power) stay those of the unrounded voltages
                 s = float(scales[c])
-                y = quantize(y * s, quant)
-                v = correlate_dumps(y, dump_len) / (s * s)
-            else:
-                v = correlate_dumps(y, dump_len)
+                vq = correlate_dumps(quantize(y * s, quant), dump_len) / (s * s)
+                idx = np.arange(v.shape[-1])
+                vq[:, idx, idx] = v[:, idx, idx]
+                v = vq
             out[(c, d)] = pack_upper(v)
     return out
 
@@ -226,7 +233,16 @@ def channel_delays(chan_freqs, dms, f_s, k_dm=K_DM, f_ref=None):
     return delta, shift
 
 
-def dump_times(n_dumps, dump_len, f_s, first_dump=0):
-    """Centre time (s) of each dump after the first sample of the stream."""
+def dump_times(n_dumps, dump_len, f_s, first_dump=0, delay_s=0.0):
+    """Time (s) of each dump, measured from the stream's first sample.
+
+    Reading (the paper only names the integrate-and-dump cadence, Sec. 5.1):
+    sample n is taken at n / f_s, and a dump stands at the mean time of the L
+    samples it sums, (m L + (L - 1) / 2) / f_s.  Because the dedispersed
+    voltages are index-aligned with the input, that is when the dump's signal
+    reached the channel centre; subtracting delay_s = K DM / f_c^2 (the channel
+    centre's delay behind infinite frequency, Eq. dmdelay) refers the dump to
+    infinite frequency, the same time in every channel.
+    """
     m = np.arange(first_dump, first_dump + n_dumps, dtype=np.float64)
-    return (m * dump_len + 0.5 * dump_len) / f_s
+    return (m * dump_len + 0.5 * (dump_len - 1)) / f_s - delay_s

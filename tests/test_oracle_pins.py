@@ -415,3 +415,124 @@ def test_quantised_correlation_error_scale():
     vh = oracle.correlate_dumps(oracle.quantize(x / 16.0, "f16"), 1000) * 256.0
     assert np.max(np.abs(vh - v) / norm) < 1e-4
 
+
+
+# --- dump times (bookkeeping of Sec. 5.1's integrate-and-dump, Eq. dmdelay) ----------------
+
+
+@pytest.mark.parametrize("L,f_s,first", [(1000, 1e6, 0), (64, 1e6, 1000), (7, 2.5e5, 3)])
+def test_dump_times_are_mean_sample_times(L, f_s, first):
+    """Each dump's time is the mean of its samples' times n / f_s (brute force)."""
+    t = oracle.dump_times(5, L, f_s, first_dump=first)
+    for i, m in enumerate(range(first, first + 5)):
+        samples = [n / f_s for n in range(m * L, (m + 1) * L)]
+        assert abs(t[i] - math.fsum(samples) / L) <= 1e-15 * max(1.0, abs(t[i]))
+
+
+def test_dump_times_referred_to_infinite_frequency():
+    """A noise-free pulse emitted at one time, dedispersed at its DM in three channels,
+    lands in each channel's dump whose time referred to infinite frequency (dump time
+    minus the channel's K DM / f_c^2 delay) is that emission time, within half a dump."""
+    f_s, dm, L, w = 1e6, 300.0, 100, 100
+    fcs = np.array([1.2005e9, 1.2315e9, 1.2635e9])
+    f_ref = float(fcs.max())
+    n0 = 200000
+    t_emit = (n0 + 0.5 * (w - 1)) / f_s - oracle.K_DM * dm / f_ref ** 2
+    rng = _rng(16)
+    wave = synth.pulse_wave(rng, w, 50.0, 1.0)
+    delay, _ = oracle.channel_delays(fcs, [dm], f_s)
+    for c, f_c in enumerate(fcs):
+        x = np.zeros((1, 1 << 19), dtype=np.complex128)
+        synth.inject_pulse(x, f_c, f_s, dm, n0, wave, f_ref=f_ref, phases=np.zeros(1))
+        bl = oracle.blocking(f_c, f_s, dm, L)
+        y = oracle.dedisperse_stream(x, oracle.chirp(f_c, f_s, bl["fft_len"], dm), bl["fft_len"], bl["valid"],
+                                     bl["lead"])
+        v = oracle.correlate_dumps(y, L)[:, 0, 0].real
+        m = int(np.argmax(v))
+        t = oracle.dump_times(1, L, f_s, first_dump=m, delay_s=delay[c, 0])[0]
+        assert abs(t - t_emit) <= 0.5 * L / f_s, (c, t, t_emit)
+        # the pulse's power centroid, referred to infinite frequency, is the emitted
+        # waveform's own power centroid
+        pw = np.abs(wave) ** 2
+        t_cen = (n0 + np.sum(pw * np.arange(w)) / np.sum(pw)) / f_s - oracle.K_DM * dm / f_ref ** 2
+        p = np.abs(y[0]) ** 2
+        cen = np.sum(p * np.arange(p.size)) / np.sum(p) / f_s - delay[c, 0]
+        assert abs(cen - t_cen) <= 0.5 / f_s, (c, cen, t_cen)
+
+
+# --- the quantised branch of the oracle (reduced-precision correlator inputs) ----------------
+
+
+def _small_int_stream(seed, m_ant=3, s=3000, lim=15):
+    rng = _rng(seed)
+    return (rng.integers(-lim, lim + 1, (1, m_ant, s)) + 1j * rng.integers(-lim, lim + 1, (1, m_ant, s)))
+
+
+@pytest.mark.parametrize("quant", ["e4m3", "f16"])
+def test_quantised_branch_exact_when_representable(quant):
+    """At DM 0 the dedispersed voltages are the integer inputs; with |x| <= 15 every x s
+    (s a power of two) is exactly representable, so the quantised oracle equals the plain one."""
+    x = _small_int_stream(17)
+    bl = [oracle.blocking(1.3e9, 1e6, 10.0, 100, 1024)]
+    plain = oracle.run_oracle(x, [1.3e9], 1e6, [[0.0]], 100, bl)[(0, 0)]
+    for s in (1.0, 2.0, 8.0):
+        q = oracle.run_oracle(x, [1.3e9], 1e6, [[0.0]], 100, bl, quant=quant, scales=[s])[(0, 0)]
+        np.testing.assert_allclose(q, plain, rtol=0, atol=1e-9)
+
+
+def _nearest_code_value(v, table):
+    best = None
+    for val in table:
+        if np.isnan(val):
+            continue
+        if best is None or abs(val - v) < abs(best - v):
+            best = val
+    return best
+
+
+def test_quantised_branch_brute_force():
+    """DM > 0 on a tiny stream: quantise every dedispersed sample by exhaustive search of
+    the 254 finite E4M3 values (no ties at these inputs), form V by explicit loops
+    (cross products of the rounded values / s^2, autos of the unrounded ones)."""
+    rng = _rng(18)
+    m_ant, s_len, L = 2, 300, 50
+    x = synth.noise_complex(rng, (1, m_ant, s_len), power=50.0)
+    dm = 30.0
+    bl = oracle.blocking(1.3e9, 1e6, dm, L, 256)
+    scale = 4.0
+    got = oracle.run_oracle(x, [1.3e9], 1e6, [[dm]], L, [bl], quant="e4m3", scales=[scale])[(0, 0)]
+    y = oracle.dedisperse_stream(x[0], oracle.chirp(1.3e9, 1e6, 256, dm), 256, bl["valid"], bl["lead"])
+    table = oracle.e4m3_decode_table()
+    q = np.empty_like(y)
+    for p in range(m_ant):
+        for n in range(s_len):
+            q[p, n] = (_nearest_code_value(y[p, n].real * scale, table)
+                       + 1j * _nearest_code_value(y[p, n].imag * scale, table))
+    b = 0
+    for i in range(m_ant):
+        for j in range(i, m_ant):
+            for m in range(s_len // L):
+                if i == j:
+                    ref = sum(abs(y[i, n]) ** 2 for n in range(m * L, (m + 1) * L))
+                else:
+                    ref = sum(q[i, n] * np.conj(q[j, n]) for n in range(m * L, (m + 1) * L)) / scale ** 2
+                assert abs(got[m, b] - ref) <= 1e-9 * abs(ref) + 1e-9
+            b += 1
+
+
+@pytest.mark.parametrize("quant", ["e4m3", "f16"])
+def test_quantised_branch_scale_covariance(quant):
+    """Doubling a power-of-two scale moves every normal rounded value by exactly one
+    binade (nothing saturates at these levels), so V changes only through the few
+    samples within the formats' subnormal range of zero: far below 1e-5 of
+    sqrt(V_ii V_jj), while a wrong power of s would change it by a factor of two."""
+    rng = _rng(19)
+    x = synth.noise_complex(rng, (1, 4, 4000), power=256.0)
+    bl = [oracle.blocking(1.25e9, 1e6, 200.0, 1000)]
+    base = 2.0 if quant == "e4m3" else 0.25
+    a = oracle.run_oracle(x, [1.25e9], 1e6, [[200.0]], 1000, bl, quant=quant, scales=[base])[(0, 0)]
+    b = oracle.run_oracle(x, [1.25e9], 1e6, [[200.0]], 1000, bl, quant=quant, scales=[2 * base])[(0, 0)]
+    iu, ju = np.triu_indices(4)
+    auto = a[:, iu == ju].real
+    norm = np.sqrt(auto[:, iu] * auto[:, ju])
+    assert np.max(np.abs(a - b) / norm) <= 1e-5

@@ -107,3 +107,34 @@ def test_tile_peaks_at_the_injected_dm():
     tile = P.tile_from_prefix(P.power_prefix(x), shift, 1024, s // 1024)
     d, t = np.unravel_index(np.argmax(tile), tile.shape)
     assert d == 16 and abs(t - n0 // 1024) <= 10
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient g the bias-corrected moments are g and g^2 at every step,
+    so t steps move each weight by exactly t lr g / (|g| + eps)."""
+    g = np.array([0.5, -4.0, 1e-3, 2.0])
+    params = {"a": np.array([1.0, -2.0, 3.0, 0.25])}
+    state = {}
+    lr, eps = 0.01, 1e-8
+    for t in range(1, 7):
+        P.adam_step(params, {"a": g.copy()}, state, lr=lr, eps=eps)
+        expect = np.array([1.0, -2.0, 3.0, 0.25]) - t * lr * g / (np.abs(g) + eps)
+        np.testing.assert_allclose(params["a"], expect, rtol=0, atol=1e-12)
+
+
+def test_adam_matches_library_over_several_steps():
+    """Six steps with changing gradients from a nonzero start against torch.optim.Adam
+    (an independent implementation of the same Kingma & Ba recurrence)."""
+    import torch
+    rng = _rng(46)
+    w0 = rng.standard_normal(7)
+    grads = [rng.standard_normal(7) * (k + 1) for k in range(6)]
+    params = {"w": w0.copy()}
+    state = {}
+    tw = torch.tensor(w0.copy(), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([tw], lr=0.05, betas=(0.8, 0.95), eps=1e-6)
+    for g in grads:
+        P.adam_step(params, {"w": g}, state, lr=0.05, beta1=0.8, beta2=0.95, eps=1e-6)
+        tw.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        np.testing.assert_allclose(params["w"], tw.detach().numpy(), rtol=0, atol=1e-13)
