@@ -77,25 +77,57 @@ def build_input(p, dev, chunk):
     return chunks, pulses, fc
 
 
-def cpu_baseline(chunks, fc, dms, lay, p, n_dm):
-    """The FP64 oracle on channel 0, n_dm DMs (first and last of the grid), all
-    antennas, the whole time span; units/s scaled to the metric's unit."""
+def host_cpu():
+    """Host threads available to this process (at most 16, the CPU share of one GPU)
+    and the CPU model."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return min(16, avail), avail, model
+
+
+def cpu_baseline(chunks, fc, dms, lay, p, per_thread):
+    """The FP64 oracle on all host threads: channel 0, `per_thread` DM trials per
+    thread spread over the grid, all antennas, the whole time span; units/s scaled to
+    the metric's unit.  numpy's FFTs and matrix products release the GIL, so one
+    Python thread per DM trial runs in parallel (each with single-threaded BLAS)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
+    from threadpoolctl import threadpool_limits
 
     import oracle
+    threads, avail, model = host_cpu()
     x = np.concatenate([c[0].cpu().numpy() for c in chunks], axis=-1)[None]
     bl = [{"fft_len": int(lay["fft_len"][0]), "valid": int(lay["valid"][0]), "lead": int(lay["lead"][0])}]
-    from threadpoolctl import threadpool_limits
-    ds = [0, len(dms) - 1][:n_dm] if n_dm <= 2 else [int(v) for v in np.linspace(0, len(dms) - 1, n_dm).round()]
-    with threadpool_limits(limits=1):  # the BLAS matrix products of the dumps on one thread, like the FFTs
+    n_dm = min(len(dms), threads * per_thread)
+    ds = [int(v) for v in np.linspace(0, len(dms) - 1, n_dm).round()]
+    parts = [ds[i::threads] for i in range(threads)]
+
+    def work(part):
+        return oracle.run_oracle(x, fc[:1], p["f_s"], [dms], p["dump_len"], bl, chans=[0], dm_index=part)
+
+    with threadpool_limits(limits=1):
         t0 = time.time()
-        out = oracle.run_oracle(x, fc[:1], p["f_s"], [dms], p["dump_len"], bl, chans=[0], dm_index=ds)
+        with ThreadPoolExecutor(threads) as ex:
+            outs = [o for o in ex.map(work, [q for q in parts if q])]
         el = time.time() - t0
-    nd = next(iter(out.values())).shape[0]
+    nd = next(iter(outs[0].values())).shape[0]
     units = p["m_ant"] * nd * p["dump_len"] * len(ds)
-    return {"value": units / el, "unit": UNIT, "cores": 1, "kind": "oracle",
-            "sample": "channel 0 x %d DMs (trials %s) x %d antennas x %d samples, FP64 numpy on one thread, "
-                      "%.1f s" % (len(ds), ds, p["m_ant"], p["samples"], el)}
+    return {"value": units / el, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "sample": "channel 0 x %d DMs spread over the grid x %d antennas x %d samples, FP64 numpy, one DM "
+                      "per thread at a time on %d threads, %.1f s" % (len(ds), p["m_ant"], p["samples"], threads, el),
+            "host": {"nproc": avail, "threads_used": threads, "cpu_model": model}}
 
 
 def learned_form(make_plan, dms, chunks, pulses, p, out, steps, plain_ms):
@@ -498,6 +530,21 @@ def chimg_cpu_baseline(args, volts, L, n_s):
 
 
 def run_c3(args, dev):
+    print(json.dumps(c3_measure(dev, args.steps, args.warmup, args.corr, args.autotune, args.passes)), flush=True)
+
+
+def c3_one_step(dev):
+    """One timed step of the 256-antenna workload (after one warm-up step), for the
+    default run's JSON line."""
+    rec = c3_measure(dev, 1, 1, "f32", False, 0)
+    keep = ("value", "unit", "ms_per_step", "steps", "warmup", "dtype", "config")
+    out = {k: rec[k] for k in keep}
+    out["dominant"] = {k: rec["roofline"][k] for k in ("bound", "achieved", "peak", "unit", "frac", "kernel")}
+    out["kernels_ms_per_step"] = {k: v["ms_per_step"] for k, v in rec["roofline"]["kernels"].items()}
+    return out
+
+
+def c3_measure(dev, steps, warmup, corr, use_autotune, n_passes):
     """The batched sparse-array workload: 256 antennas, 32 x 1 MHz channels at
     0.7-0.732 GHz, 2^18 ci8 samples, per-channel DM grids of 512..1536 trials over
     0-3000 (transform lengths 2^17 / 2^18, two-pass).  Its 2.26 TB of visibilities
@@ -521,16 +568,16 @@ def run_c3(args, dev):
     s, L, M = p["samples"], p["dump_len"], p["m_ant"]
     dms = [synth.dm_grid(n, p["dm_max"]) for n in p["n_dm"]]
     kw = {}
-    if args.autotune:
-        tuned = autotune.tune(M, fc, p["f_s"], L, dms, corr_dtype=args.corr, max_block=s, log=log)
+    if use_autotune:
+        tuned = autotune.tune(M, fc, p["f_s"], L, dms, corr_dtype=corr, max_block=s, log=log)
         kw = autotune.plan_kwargs(tuned)
         log("tuned (%s): lengths %s wave %d group %d" % (tuned["source"], sorted(set(tuned["fft_len"])),
                                                           tuned["wave_units"], tuned["dm_group"]))
-    passes = args.passes or math.ceil(sum(p["n_dm"]) / 512)
+    passes = n_passes or math.ceil(sum(p["n_dm"]) / 512)
     windows = [np.array_split(np.arange(n), passes) for n in p["n_dm"]]
     max_pairs = max(sum(len(windows[c][k]) for c in range(p["n_chan"])) for k in range(passes))
     ring = s // L + 2
-    plan = Plan(M, fc, p["f_s"], L, max_block_samples=s, in_dtype="ci8", corr_dtype=args.corr, out_mode="packed",
+    plan = Plan(M, fc, p["f_s"], L, max_block_samples=s, in_dtype="ci8", corr_dtype=corr, out_mode="packed",
                 compact_records=True, max_record_pairs=max_pairs, ring_dumps=ring, **kw)
     for c, d in enumerate(dms):
         plan.set_dm_trials(d, chan=c)
@@ -559,53 +606,145 @@ def run_c3(args, dev):
             got += nd
         return got
 
-    for w in range(args.warmup):
+    for w in range(warmup):
         step()
         torch.cuda.synchronize()
-        log("warmup %d done" % w)
+        log("C3 warmup %d done" % w)
     plan.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         got = step()
-        log("step %d enqueued" % k)
+        log("C3 step %d enqueued" % k)
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms = (time.perf_counter() - t0) * 1e3 / steps
     prof = plan.profile()
     plan.set_profiling(False)
     n_dumps = got // passes
     units = M * n_dumps * L * sum(p["n_dm"])
     value = units / (ms / 1e3)
     log("C3 per step: %.1f ms, %.3e units/s; kernels: %s" % (
-        ms, value, {k: round(v["time_ms"] / args.steps, 1) for k, v in prof.items()}))
-    roofline = roofline_of(prof, args)
+        ms, value, {k: round(v["time_ms"] / steps, 1) for k, v in prof.items()}))
+    roofline = roofline_of(prof, argparse.Namespace(workload="c3", corr=corr, steps=steps))
     rec = {
-        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": args.corr, "data": "synthetic",
+        "dtype": corr, "data": "synthetic",
         "config": {"workload": "256 ant x 32 ch x 2^18 ci8 samples, 512..1536 DMs per channel 0-3000, "
                                "N %s, 1 ms dumps, %d DM-window passes" % (
                                    "/".join(str(n) for n in sorted(set(int(v) for v in lay["fft_len"]))), passes),
                    "n_ant": M, "n_chan": p["n_chan"], "samples": s, "n_dm_total": int(sum(p["n_dm"])),
-                   "dump_len": L, "passes": passes, "input": "ci8", "corr": args.corr,
+                   "dump_len": L, "passes": passes, "input": "ci8", "corr": corr,
                    "schedule": {"wave_units": lay["wave_units"], "dm_group": lay["dm_group"],
-                                "autotuned": bool(args.autotune)}, "parallelism": "none (1 GPU)"},
+                                "autotuned": bool(use_autotune)}, "parallelism": "none (1 GPU)"},
         "roofline": roofline, "cpu_baseline": None, "learned": None,
     }
-    print(json.dumps(rec), flush=True)
     plan.close()
+    del x, out
+    torch.cuda.empty_cache()
+    return rec
 
 
-def roofline_of(prof, args):
+SAMPLED_PAIRS = [(0, 255), (31, 128), (63, 0), (63, 201)]
+
+
+def run_stream(plan, chunks, out, pairs=None, lay=None):
+    """One pass of the stream through a plan (reset, every chunk, fetch into `out`);
+    with `pairs`, host copies of those (channel, DM) records.  Returns (dumps, kept)."""
+    plan.reset_stream()
+    got = 0
+    keep = {k: [] for k in (pairs or [])}
+    for i, ch in enumerate(chunks):
+        plan.process_block(ch, flush=(i == len(chunks) - 1))
+        _, nd, _ = plan.fetch(out=out)
+        got += nd
+        if pairs and nd:
+            v = out[:nd].view(nd, -1, lay["n_baselines"])
+            for (c, d) in pairs:
+                keep[(c, d)].append(v[:, int(lay["record_pos"][lay["dm_offset"][c] + d])].cpu().numpy())
+    import numpy as np
+    return got, {k: np.concatenate(v) for k, v in keep.items()}
+
+
+def error_table(kept, host, fc, dms, lay, p):
+    """Normalised errors |dV_ij| / sqrt(V_ii V_jj) of sampled (channel, DM) records
+    against the FP64 oracle (one thread per pair)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    bl = [{"fft_len": int(lay["fft_len"][c]), "valid": int(lay["valid"][c]), "lead": int(lay["lead"][c])}
+          for c in range(lay["n_chan"])]
+    iu, ju = np.triu_indices(p["m_ant"])
+
+    def one(cd):
+        c, d = cd
+        ref = oracle.run_oracle(host[c][None], fc[c:c + 1], p["f_s"], [dms], p["dump_len"], [bl[c]], chans=[0],
+                                dm_index=[d])[(0, d)]
+        auto = ref[:, iu == ju].real
+        norm = np.sqrt(auto[:, iu] * auto[:, ju])
+        return d, (np.abs(kept[cd].astype(np.complex128) - ref) / norm).ravel()
+
+    with threadpool_limits(limits=1), ThreadPoolExecutor(len(kept)) as ex:
+        res = list(ex.map(one, list(kept)))
+    e = np.concatenate([r for d, r in res if d != 0] or [np.zeros(1)])
+    z = np.concatenate([r for d, r in res if d == 0] or [np.zeros(1)])
+    return {"pairs": [list(k) for k in kept], "visibilities": int(e.size + z.size), "max_dm_gt0": float(e.max()),
+            "p999_dm_gt0": float(np.quantile(e, 0.999)), "rms_dm_gt0": float(np.sqrt(np.mean(e ** 2))),
+            "max_dm0": float(z.max()), "max": float(max(e.max(), z.max()))}
+
+
+def precision_forms(forms, make_plan, dms, chunks, host, fc, p, steps):
+    """The reduced-precision correlator inputs on the same stream: per form, one
+    untimed pass whose sampled records give the error table against the FP64 oracle,
+    then `steps` timed passes (library event timings per kernel kind)."""
+    import torch
+    res = {}
+    for corr in forms:
+        plan = make_plan(corr_dtype=corr)
+        plan.set_dm_trials(dms)
+        lay = plan.layout()
+        out = torch.empty((lay["ring_dumps"], lay["record_elems"]), dtype=torch.complex64, device="cuda")
+        _, kept = run_stream(plan, chunks, out, SAMPLED_PAIRS, lay)
+        torch.cuda.synchronize()
+        plan.set_profiling(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            n_dumps, _ = run_stream(plan, chunks, out)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        prof = plan.profile()
+        plan.set_profiling(False)
+        lay = plan.layout()
+        plan.close()
+        del out
+        units = p["m_ant"] * n_dumps * p["dump_len"] * p["n_chan"] * p["n_dm"]
+        err = error_table(kept, host, fc, dms, lay, p)
+        dd = prof.get("dedisperse", {"time_ms": 0.0, "flops": 0.0})
+        rec = {"value": units / (ms / 1e3), "ms_per_step": ms, "steps": steps,
+               "kernels_ms_per_step": {k: round(v["time_ms"] / steps, 1) for k, v in prof.items() if v["launches"]},
+               "dedisperse_tflops": round(dd["flops"] / max(dd["time_ms"], 1e-9) / 1e9, 2),
+               "scales": sorted(set(float(v) for v in lay["scale"])), "errors_vs_fp64_oracle": err}
+        log("%s form: %.1f ms/step, %.3e units/s; error max %.3e (DM > 0 99.9%% %.3e, DM 0 %.3e)" % (
+            corr, ms, rec["value"], err["max"], err["p999_dm_gt0"], err["max_dm0"]))
+        res[corr] = rec
+    return res
+
+
+def roofline_of(prof, args, p=None, ms_step=None):
     """Roofline of the dominant kernel kind from the library's event timings.
 
-    Dedispersion (A4): bound by HBM at these sizes (5.9 flop per staged byte, below
-    the FP32 ridge of 19.7): achieved = staged bytes per launch (a spectrum read per
-    unit and antenna, the chirps, the dedispersed voltages written: 8 N / V + b_y per
-    unit) / launch time; its algorithmic FLOP rate against the VALU peak is given
-    beside it.  Correlator (A6): MFMA, against the peak of its input format.
-    `traffic` = HBM bytes per launch from the committed counter run (null if the
-    kernels changed since)."""
+    Dedispersion (A4: chirp multiply, inverse FFT, discard) runs on the FP32 vector
+    units: achieved = its algorithmic FLOP per launch (5 N log2 N / V + 6 N / V per
+    unit, times the V M units of each of the launch's (channel, DM, block) units) /
+    its average launch duration, against the 157.3 TFLOP/s FP32 vector peak.  Beside
+    it: the HBM rate from the committed FETCH_SIZE / WRITE_SIZE counters (`traffic`,
+    bytes per launch; null if the kernel sources changed since), and the staged-byte
+    model (a spectrum read per unit and antenna, the chirps, the voltages written),
+    labelled as a model.  Correlator (A6, dominant at 256 antennas): MFMA, against
+    the peak of its input format."""
     dom = max(prof, key=lambda k: prof[k]["time_ms"])
     d = prof[dom]
     n = max(d["launches"], 1)
@@ -618,14 +757,22 @@ def roofline_of(prof, args):
         r = {"bound": "mfma", "achieved": round(tflops, 2), "peak": peak, "unit": "TFLOP/s",
              "frac": round(tflops / peak, 4)}
     else:
+        r = {"bound": "alu", "achieved": round(tflops, 2), "peak": PEAKS["fp32_vector_tflops"], "unit": "TFLOP/s",
+             "frac": round(tflops / PEAKS["fp32_vector_tflops"], 4)}
         gbs = d["bytes"] / n / per_launch_s / 1e9
-        r = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
-             "frac": round(gbs / PEAKS["hbm_gbs"], 4),
-             "alu": {"achieved": round(tflops, 2), "peak": PEAKS["fp32_vector_tflops"], "unit": "TFLOP/s",
-                     "frac": round(tflops / PEAKS["fp32_vector_tflops"], 4)}}
+        r["staged_model"] = {"gbs": round(gbs, 1), "frac_of_hbm": round(gbs / PEAKS["hbm_gbs"], 4),
+                             "note": "modelled bytes (8 N / V + b_y per unit), not measured"}
     r.update({"traffic": traffic, "kernel": dom, "avg_launch_ms": round(per_launch_s * 1e3, 4)})
     if traffic:
-        r["traffic_gbs"] = round(traffic / per_launch_s / 1e9, 1)
+        r["hbm_counters"] = {"gbs": round(traffic / per_launch_s / 1e9, 1),
+                             "frac": round(traffic / per_launch_s / 1e9 / PEAKS["hbm_gbs"], 4),
+                             "source": "profiles/traffic_%s_%s.json" % (dom, args.workload)}
+    if p is not None and ms_step:
+        # the method's own minimum bytes: the input once and the visibilities out
+        units = p["units"]
+        alg = p["input_bytes"] + p["vis_bytes"]
+        r["path_algorithmic_bytes"] = {"bytes_per_step": alg, "per_unit": round(alg / units, 4),
+                                       "gbs": round(alg / (ms_step / 1e3) / 1e9, 1)}
     r["kernels"] = {k: {"ms_per_step": round(v["time_ms"] / args.steps, 2),
                         "launches_per_step": v["launches"] // args.steps,
                         "tflops": round(v["flops"] / max(v["time_ms"], 1e-9) / 1e9, 2),
@@ -642,7 +789,12 @@ def main():
     ap.add_argument("--corr", default="f32", choices=["f32", "f16", "e4m3"])
     ap.add_argument("--chunk", type=int, default=1 << 18, help="samples per process_block call")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-dms", type=int, default=12, help="DM trials of the oracle's timed slice")
+    ap.add_argument("--cpu-dms-per-thread", type=int, default=12,
+                    help="DM trials per host thread in the oracle's timed slice")
+    ap.add_argument("--forms", default="f16,e4m3",
+                    help="reduced-precision correlator inputs measured after the main form (comma list, '' = none)")
+    ap.add_argument("--form-steps", type=int, default=3, help="timed passes per reduced-precision form")
+    ap.add_argument("--no-c3", action="store_true", help="skip the one-step 256-antenna leg of the default run")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal measurement")
     ap.add_argument("--wave-units", type=int, default=0, help="schedule: units per wave (0 = automatic)")
     ap.add_argument("--dm-group", type=int, default=0, help="schedule: DMs per block group (0 = automatic)")
@@ -699,8 +851,10 @@ def main():
         log("tuned (%s): lengths %s wave %d group %d" % (tuned["source"], sorted(set(tuned["fft_len"])),
                                                           tuned["wave_units"], tuned["dm_group"]))
     def make_plan(**extra):
+        opts = dict(kw, corr_dtype=args.corr)
+        opts.update(extra)
         return Plan(p["m_ant"], fc, p["f_s"], p["dump_len"], max_block_samples=args.chunk, in_dtype="ci8",
-                    corr_dtype=args.corr, out_mode="packed", **kw, **extra)
+                    out_mode="packed", **opts)
 
     plan = make_plan()
     plan.set_dm_trials(dms)
@@ -739,14 +893,24 @@ def main():
     log("per step: %.1f ms, %.3e units/s; kernels: %s" % (
         ms, value, {k: round(v["time_ms"] / args.steps, 1) for k, v in prof.items()}))
 
-    roofline = roofline_of(prof, args)
+    path = {"units": units, "input_bytes": 2.0 * p["m_ant"] * p["n_chan"] * p["samples"],
+            "vis_bytes": 8.0 * n_dumps * p["n_chan"] * p["n_dm"] * lay["n_baselines"]}
+    roofline = roofline_of(prof, args, path, ms)
     learned = None
     if not args.no_learned:
         learned = learned_form(make_plan, dms, chunks, pulses, p, out, args.steps, ms)
+    del out
+    plan.close()
+    forms = None
+    if args.forms and args.corr == "f32" and not args.channels:
+        host = {c: np.concatenate([ch[c].cpu().numpy() for ch in chunks], axis=-1)
+                for c in sorted({c for c, _ in SAMPLED_PAIRS})}
+        forms = precision_forms([f for f in args.forms.split(",") if f], make_plan, dms, chunks, host, fc, p,
+                                args.form_steps)
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on a slice")
-        cpu = cpu_baseline(chunks, fc, dms, lay, p, args.cpu_dms)
+        cpu = cpu_baseline(chunks, fc, dms, lay, p, args.cpu_dms_per_thread)
     rec = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -756,10 +920,13 @@ def main():
                    "n_ant": p["m_ant"], "n_chan": p["n_chan"], "samples": p["samples"], "n_dm": p["n_dm"],
                    "dump_len": p["dump_len"], "fft_len": int(lay["fft_len"][0]), "chunk": args.chunk,
                    "input": "ci8", "corr": args.corr, "parallelism": "none (1 GPU)"},
-        "roofline": roofline, "cpu_baseline": cpu, "learned": learned,
+        "roofline": roofline, "cpu_baseline": cpu, "learned": learned, "precision_forms": forms,
     }
+    if not args.no_c3 and args.corr == "f32" and not args.channels:
+        del chunks
+        torch.cuda.empty_cache()
+        rec["c3_step"] = c3_one_step(dev)
     print(json.dumps(rec), flush=True)
-    plan.close()
 
 
 if __name__ == "__main__":

@@ -124,6 +124,12 @@ typedef struct ddx_layout {
   int32_t dm_group;            /* DMs per block group in use */
   int32_t compact_records;     /* as in the descriptor */
   int32_t pad;
+  /* Dump times (Sec. 5.1's integrate-and-dump cadence): dump m of channel c stands at
+   * dump_t0_s + m dump_period_s seconds after the stream's first sample at the
+   * channel centre, and at that minus delay_s[(c, d)] referred to infinite frequency
+   * (see ddx_dump_times). */
+  double dump_t0_s;            /* (L - 1) / (2 f_s): the mean time of dump 0's samples */
+  double dump_period_s;        /* L / f_s */
 } ddx_layout;
 
 /* Create a plan from a descriptor (copied; the caller's arrays may be freed).
@@ -162,6 +168,20 @@ int ddx_set_active_dms(ddx_plan* plan, int32_t chan, const uint8_t* mask);
  * plan-owned host memory valid until the next ddx_set_dm_trials or
  * ddx_plan_destroy.  Requires ddx_set_dm_trials for every channel (ESTATE). */
 int ddx_get_layout(const ddx_plan* plan, ddx_layout* out);
+
+/* Times of dumps first_dump .. first_dump + n_dumps - 1 of channel chan at its DM
+ * trial dm_index, in FP64 seconds from the stream's first sample (the bookkeeping
+ * of the integrate-and-dump of Sec. 5.1 with the delay law of Eq. dmdelay).
+ * Reading: sample n is taken at n / f_s and a dump stands at the mean time of its L
+ * samples, t_m = (m L + (L - 1) / 2) / f_s; the dedispersed voltages are
+ * index-aligned with the input, so t_m is when the dump's signal passed the channel
+ * centre.  refer_infinite != 0 subtracts the centre's delay K DM / f_c^2 behind
+ * infinite frequency, which puts one dispersed pulse at the same time in every
+ * channel.  out: caller-owned HOST array of n_dumps doubles.  Errors: EINVAL (NULL
+ * out with n_dumps > 0, chan or dm_index out of range, first_dump or n_dumps < 0),
+ * ESTATE (DM trials not set). */
+int ddx_dump_times(const ddx_plan* plan, int32_t chan, int32_t dm_index, int64_t first_dump, int64_t n_dumps,
+                   int32_t refer_infinite, double* out);
 
 /* Append n >= 0 samples per (channel, antenna) to the stream and enqueue all
  * work they complete on hip_stream (asynchronous).

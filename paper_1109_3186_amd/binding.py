@@ -48,6 +48,7 @@ class Layout(ct.Structure):
         ("record_elems", ct.c_int64), ("samples_in", ct.c_int64), ("dumps_ready", ct.c_int64),
         ("dumps_fetched", ct.c_int64), ("ring_dumps", ct.c_int64), ("device_bytes", ct.c_size_t),
         ("wave_units", ct.c_int32), ("dm_group", ct.c_int32), ("compact_records", ct.c_int32), ("pad", ct.c_int32),
+        ("dump_t0_s", ct.c_double), ("dump_period_s", ct.c_double),
     ]
 
 
@@ -66,6 +67,8 @@ SIGNATURES = {
     "ddx_set_dm_trials": ([ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_double), ct.c_int32], ct.c_int),
     "ddx_set_active_dms": ([ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_uint8)], ct.c_int),
     "ddx_get_layout": ([ct.c_void_p, ct.POINTER(Layout)], ct.c_int),
+    "ddx_dump_times": ([ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_int64, ct.c_int64, ct.c_int32,
+                        ct.POINTER(ct.c_double)], ct.c_int),
     "ddx_process_block": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_void_p], ct.c_int),
     "ddx_fetch_visibilities": ([ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.POINTER(ct.c_int64),
                                 ct.POINTER(ct.c_int64), ct.c_void_p], ct.c_int),
@@ -248,7 +251,15 @@ class Plan:
             "samples_in": lay.samples_in, "dumps_ready": lay.dumps_ready, "dumps_fetched": lay.dumps_fetched,
             "ring_dumps": lay.ring_dumps, "device_bytes": lay.device_bytes, "wave_units": lay.wave_units,
             "dm_group": lay.dm_group, "compact_records": lay.compact_records,
+            "dump_t0_s": lay.dump_t0_s, "dump_period_s": lay.dump_period_s,
         }
+
+    def dump_times(self, chan, dm_index, first_dump, n_dumps, refer_infinite=False):
+        """FP64 times (s) of dumps first_dump .. first_dump + n_dumps - 1 (ddx_dump_times)."""
+        out = np.zeros(max(int(n_dumps), 0), dtype=np.float64)
+        self._check(lib().ddx_dump_times(self._h, chan, dm_index, first_dump, n_dumps, int(bool(refer_infinite)),
+                                         out.ctypes.data_as(ct.POINTER(ct.c_double))), "ddx_dump_times")
+        return out
 
     def process_block(self, volts, flush=False, stream=None):
         """volts: torch device tensor, int8 [C, M, 2n] (ci8) or complex64 [C, M, n] (cf32), contiguous."""

@@ -32,10 +32,7 @@
 
 namespace chirp {
 
-#ifndef DDX_CHIRP_TILE_P
-#define DDX_CHIRP_TILE_P 128
-#endif
-constexpr int kTileP = DDX_CHIRP_TILE_P;   // pairs per output tile
+constexpr int kTileP = 128;                // pairs per output tile
 constexpr int kTileK = 4096 / kTileP;      // bins per output tile (4 waves of 32 x 32)
 constexpr int kChunk = 32;   // samples per LDS chunk
 

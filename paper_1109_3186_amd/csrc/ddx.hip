@@ -102,6 +102,8 @@ struct ddx_plan {
   float2* chirp = nullptr;     // [wave_units][max N]
   void* ybuf = nullptr;        // [wave_units][M][y_stride]
   int64_t y_stride = 0;
+  float* power = nullptr;      // binary16 / E4M3: [wave_units][M][pw_stride] per-dump power
+  int pw_stride = 0;
   float2* ring = nullptr;
   int64_t ring_dumps = 0;
   double* gtab = nullptr;      // [sum N_c] FP64 g_c[k]
@@ -191,6 +193,7 @@ void free_device(ddx_plan* p) {
   p->spec = p->tb = p->chirp = p->ring = nullptr;
   p->spec_elems = p->tb_elems = 0;
   p->ybuf = nullptr;
+  p->power = nullptr;
   p->gtab = nullptr;
   p->scale_dev = nullptr;
   p->scale_part = nullptr;
@@ -335,6 +338,11 @@ hipError_t launch_dedisp(int logn, int corr_dtype, const ddx::DedispArgs& a, hip
       else hipLaunchKernelGGL(ddx::k_dedisperse_big_b<2>, gb, dim3(256), 0, s, ag);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
+      if (corr_dtype != DDX_CORR_F32) {  // per-dump power, before the next group reuses the rows
+        hipLaunchKernelGGL(ddx::k_dump_power_rows, dim3(ag.n_units * ag.n_ant), dim3(256), 0, s, ag);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
     }
     return hipSuccess;
   }
@@ -516,6 +524,10 @@ int setup_device(ddx_plan* p) {
   p->wave_units = (int)std::min<int64_t>(p->wave_units, std::max<int64_t>(max_units, 1));
   // + 256 bytes: the correlator's pair loads may read one sample past a unit's rows
   if ((rc = dev_alloc(p, &p->ybuf, per_unit * p->wave_units + 256))) return rc;
+  p->pw_stride = maxv / p->L;
+  if (p->corr_dtype != DDX_CORR_F32 &&
+      (rc = dev_alloc(p, (void**)&p->power, (size_t)p->wave_units * p->M * p->pw_stride * sizeof(float))))
+    return rc;
 
   if ((rc = dev_alloc(p, (void**)&p->chirp, (size_t)p->wave_units * maxn * sizeof(float2)))) return rc;
   // two-pass transforms: intermediate rows of one wave (dedispersion); the forward
@@ -731,6 +743,26 @@ int ddx_get_layout(const ddx_plan* pc, ddx_layout* o) {
   o->wave_units = p->wave_units;
   o->dm_group = p->dm_group;
   o->compact_records = p->compact;
+  o->dump_t0_s = 0.5 * (double)(p->L - 1) / p->fs;
+  o->dump_period_s = (double)p->L / p->fs;
+  return DDX_OK;
+}
+
+int ddx_dump_times(const ddx_plan* pc, int32_t chan, int32_t dm_index, int64_t first_dump, int64_t n_dumps,
+                   int32_t refer_infinite, double* out) {
+  if (!pc) return DDX_EINVAL;
+  ddx_plan* p = const_cast<ddx_plan*>(pc);
+  if (!p->ready) return fail(p, DDX_ESTATE, "set DM trials for every channel first");
+  if (chan < 0 || chan >= p->C) return fail(p, DDX_EINVAL, "channel %d outside [0, %d)", chan, p->C);
+  const int nd = (int)p->ch[chan].dm.size();
+  if (dm_index < 0 || dm_index >= nd) return fail(p, DDX_EINVAL, "DM index %d outside [0, %d)", dm_index, nd);
+  if (first_dump < 0 || n_dumps < 0) return fail(p, DDX_EINVAL, "negative dump range");
+  if (n_dumps > 0 && !out) return fail(p, DDX_EINVAL, "null output");
+  const double delay = refer_infinite ? p->lay_delay[p->dm_off[chan] + dm_index] : 0.0;
+  for (int64_t i = 0; i < n_dumps; ++i) {
+    const double m = (double)(first_dump + i);
+    out[i] = (m * p->L + 0.5 * (p->L - 1)) / p->fs - delay;
+  }
   return DDX_OK;
 }
 
@@ -1052,6 +1084,9 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
     da.y = p->ybuf;
     da.tb = p->tb;
     da.units = units_dev + wv.u0;
+    da.power = p->power;
+    da.dump_len = p->L;
+    da.pw_stride = p->pw_stride;
     da.y_stride = p->y_stride;
     da.n_ant = p->M;
     da.n_units = (int)wv.nu;
@@ -1065,6 +1100,8 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
     ca.ring = p->ring;
     ca.units = units_dev + wv.u0;
     ca.scale = p->scale_dev;
+    ca.power = p->power;
+    ca.pw_stride = p->pw_stride;
     ca.y_stride = p->y_stride;
     ca.rec_elems = p->rec_elems;
     ca.ring_dumps = p->ring_dumps;

@@ -17,10 +17,6 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
-#ifndef DDX_LOAD_FENCE
-#define DDX_LOAD_FENCE 1
-#endif
-
 namespace ddx {
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -289,13 +285,11 @@ __device__ __forceinline__ void fft_workgroup(float2* v, float* lds, int t, Load
 #pragma unroll
     for (int r = 0; r < G::R0; ++r) v[u * G::R0 + in_reg<G::R0>(r)] = load(t + z + u * G::T + r * (G::N / G::R0));
     dft_reg<G::R0, S>(v + u * G::R0);
-#if DDX_LOAD_FENCE
     // loads of the next group wait for this group's butterflies (register pressure)
     if (u + 1 < G::P / G::R0) {
       pin_regs<G::R0>(v + u * G::R0);
       z = opaque_zero(v[u * G::R0].x);
     }
-#endif
   }
   if constexpr (G::NP > 1) Passes<PL, S, 1, G::R0>::run(v, lds, t);
 }

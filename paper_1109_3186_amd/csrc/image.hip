@@ -297,16 +297,11 @@ void image_release(ddx_image* h) {
   h->allocs.clear();
 }
 
-// build options: windows per thread, and the fixed-tap kernels with weight prefetch
-#ifndef DDX_IMG_WT
-#define DDX_IMG_WT 32
-#endif
-#ifndef DDX_IMG_PREFETCH
-#define DDX_IMG_PREFETCH 1
-#endif
+// windows per thread (a staged bin row of WT + 2 windows must fit the LDS budget, else 4)
+constexpr int kImgWt = 32;
 
 int window_tile(const ddx_image* h) {
-  return (int64_t)(DDX_IMG_WT + 2) * h->smax * (int64_t)sizeof(float2) <= img::kLdsBytes ? DDX_IMG_WT : 4;
+  return (int64_t)(kImgWt + 2) * h->smax * (int64_t)sizeof(float2) <= img::kLdsBytes ? kImgWt : 4;
 }
 
 }  // namespace
@@ -419,20 +414,18 @@ int ddx_image_run(ddx_image* h, const void* d_bins, int64_t n_rows, int64_t firs
   const dim3 grid((unsigned)(n_wtiles * h->n_ptiles));
   const hipStream_t st = (hipStream_t)hip_stream;
   const dim3 blk(img::kPixTile);
-  if (wt != DDX_IMG_WT)
+  if (wt != kImgWt)
     hipLaunchKernelGGL((img::k_image<4, 0>), grid, blk, lds, st, a);
-  else if (!DDX_IMG_PREFETCH)
-    hipLaunchKernelGGL((img::k_image<DDX_IMG_WT, 0>), grid, blk, lds, st, a);
   else if (h->taps == 1)
-    hipLaunchKernelGGL((img::k_image<DDX_IMG_WT, 1>), grid, blk, lds, st, a);
+    hipLaunchKernelGGL((img::k_image<kImgWt, 1>), grid, blk, lds, st, a);
   else if (h->taps == 3)
-    hipLaunchKernelGGL((img::k_image<DDX_IMG_WT, 3>), grid, blk, lds, st, a);
+    hipLaunchKernelGGL((img::k_image<kImgWt, 3>), grid, blk, lds, st, a);
   else if (h->taps == 5)
-    hipLaunchKernelGGL((img::k_image<DDX_IMG_WT, 5>), grid, blk, lds, st, a);
+    hipLaunchKernelGGL((img::k_image<kImgWt, 5>), grid, blk, lds, st, a);
   else if (h->taps == 7)
-    hipLaunchKernelGGL((img::k_image<DDX_IMG_WT, 7>), grid, blk, lds, st, a);
+    hipLaunchKernelGGL((img::k_image<kImgWt, 7>), grid, blk, lds, st, a);
   else
-    hipLaunchKernelGGL((img::k_image<DDX_IMG_WT, 0>), grid, blk, lds, st, a);
+    hipLaunchKernelGGL((img::k_image<kImgWt, 0>), grid, blk, lds, st, a);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return ifail(&h->err, DDX_EDEVICE, "k_image: %s", hipGetErrorString(e));
   return DDX_OK;

@@ -7,13 +7,6 @@
 
 #include "fft.hpp"
 
-#ifndef DDX_NT_STORE
-#define DDX_NT_STORE 1
-#endif
-#ifndef DDX_RANGED_STORE
-#define DDX_RANGED_STORE 1
-#endif
-
 namespace ddx {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -207,7 +200,6 @@ __device__ __forceinline__ bool unit_row(int lin, int n_units, int n_rows, int t
 // the next workgroups re-read).
 template <class T>
 __device__ __forceinline__ void store_stream(T* p, T v) {
-#if DDX_NT_STORE
   if constexpr (sizeof(T) == 8) {
     typedef float f2v __attribute__((ext_vector_type(2)));
     __builtin_nontemporal_store(*reinterpret_cast<const f2v*>(&v), reinterpret_cast<f2v*>(p));
@@ -216,14 +208,6 @@ __device__ __forceinline__ void store_stream(T* p, T v) {
   } else {
     __builtin_nontemporal_store(*reinterpret_cast<const unsigned short*>(&v), reinterpret_cast<unsigned short*>(p));
   }
-#else
-  *p = v;
-#endif
-}
-
-template <class T>
-__device__ __forceinline__ void store_stream_at(T* base, unsigned byte_off, T v) {
-  store_stream(reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off), v);
 }
 
 // Buffer resource over `bytes` bytes at `base` (raw, stride 0, 32-bit data format).
@@ -235,7 +219,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t range_rsrc(void* base, unsigne
 
 template <class T>
 __device__ __forceinline__ void store_ranged(__amdgpu_buffer_rsrc_t r, unsigned byte_off, T v) {
-  constexpr int aux = DDX_NT_STORE ? 2 : 0;  // 2: non-temporal
+  constexpr int aux = 2;  // non-temporal
   if constexpr (sizeof(T) == 8) {
     typedef unsigned int u2v __attribute__((ext_vector_type(2)));
     __builtin_amdgcn_raw_buffer_store_b64(*reinterpret_cast<const u2v*>(&v), r, byte_off, 0, aux);
@@ -262,11 +246,46 @@ struct DedispArgs {
   void* y;
   float2* tb;           // two-pass transforms: intermediate rows
   const UnitItem* units;
+  float* power;         // binary16 / E4M3 outputs: per-dump power of the unrounded s_c y
   int64_t y_stride;
   int32_t n_ant, n_units, logr, tile;
   int32_t ant0;         // two-pass transforms: first antenna of the launch's group (n_ant antennas)
+  int32_t dump_len;     // L
+  int32_t pw_stride;    // power values per antenna row (dumps per block, V_max / L)
   int32_t pad;
 };
+
+// Power row of antenna p of a unit: the unit's y rows are [M][y_stride] from u.y,
+// and its power rows [M][pw_stride] sit at the same row index.
+__device__ __forceinline__ float* power_row(float* power, const UnitItem& u, int64_t y_stride, int pw_stride, int p) {
+  return power + (u.y / y_stride + p) * (int64_t)pw_stride;
+}
+
+// Per-dump sums of `valid` values s(j), j < valid (valid a multiple of L), into
+// out[m] = sum_{j in [m L, (m+1) L)} s(j), in a fixed order (so the result does not
+// depend on scheduling): for L >= 64 (and workgroups of whole waves) one wave per
+// dump, lane l summing s(m L + l + 64 i) in i order, then a butterfly over the 64
+// lanes; otherwise one thread per dump summing in j order.
+template <int NT, class S>
+__device__ __forceinline__ void dump_sums(S s, int valid, int L, float* out, int t) {
+  const int nd = valid / L;
+  if (NT >= 64 && L >= 64) {
+    const int wave = t >> 6, lane = t & 63;
+    for (int m = wave; m < nd; m += (NT >= 64 ? NT / 64 : 1)) {
+      float acc = 0.f;
+      for (int i = lane; i < L; i += 64) acc += s(m * L + i);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+      if (lane == 0) out[m] = acc;
+    }
+  } else {
+    for (int m = t; m < nd; m += NT) {
+      float acc = 0.f;
+      for (int i = 0; i < L; ++i) acc += s(m * L + i);
+      out[m] = acc;
+    }
+  }
+}
 
 template <int LOGN, int OUT>
 __global__ __launch_bounds__((Geo<DedispPlan<LOGN, OUT>>::T)) void k_dedisperse(DedispArgs a) {
@@ -286,7 +305,6 @@ __global__ __launch_bounds__((Geo<DedispPlan<LOGN, OUT>>::T)) void k_dedisperse(
   // output addresses are formed only now (otherwise they are hoisted and held in registers)
   YT* y = reinterpret_cast<YT*>(a.y) + w.y + (size_t)p * a.y_stride;
   const int z = opaque_zero(v[0].x);
-#if DDX_RANGED_STORE
   // points outside [lead, lead + V) get the offset V (unsigned wrap included) and are dropped
   const __amdgpu_buffer_rsrc_t yr = range_rsrc(y, (unsigned)w.valid * (unsigned)sizeof(YT));
 #pragma unroll
@@ -294,18 +312,18 @@ __global__ __launch_bounds__((Geo<DedispPlan<LOGN, OUT>>::T)) void k_dedisperse(
 #pragma unroll
     for (int q = 0; q < G::RL; ++q) {
       const unsigned j = min((unsigned)(t + z + u * G::T + q * (G::N / G::RL) - w.lead), (unsigned)w.valid);
-      store_ranged(yr, j * (unsigned)sizeof(YT), convert_y<OUT>(v[u * G::RL + out_reg<G::RL>(q)]));
+      const float2 o = v[u * G::RL + out_reg<G::RL>(q)];
+      store_ranged(yr, j * (unsigned)sizeof(YT), convert_y<OUT>(o));
+      // binary16 / E4M3: |s y|^2 of the unrounded point staged by output index in LDS
+      // (free since the last exchange; discarded points all land on slot V, never read)
+      if constexpr (OUT != 0) lds[j] = fmaf(o.x, o.x, o.y * o.y);
     }
-#else
-#pragma unroll
-  for (int u = 0; u < G::P / G::RL; ++u)
-#pragma unroll
-    for (int q = 0; q < G::RL; ++q) {
-      const unsigned j = (unsigned)(t + z + u * G::T + q * (G::N / G::RL) - w.lead);  // kept iff j < V
-      if (j < (unsigned)w.valid)
-        store_stream_at(y, j * (unsigned)sizeof(YT), convert_y<OUT>(v[u * G::RL + out_reg<G::RL>(q)]));
-    }
-#endif
+  if constexpr (OUT != 0) {
+    // total power of each dump, summed in a fixed order
+    __syncthreads();
+    dump_sums<G::T>([&](int j) { return lds[j]; }, w.valid, a.dump_len,
+                    power_row(a.power, w, a.y_stride, a.pw_stride, p), t);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -321,10 +339,7 @@ __global__ __launch_bounds__((Geo<DedispPlan<LOGN, OUT>>::T)) void k_dedisperse(
 // then an R-point DFT per n2 (k_dedisperse_big_b), which writes y in natural order.
 constexpr int kBigLog = 15;
 constexpr int kBigN = 1 << kBigLog;
-#ifndef DDX_ROWS_WIDE
-#define DDX_ROWS_WIDE 0
-#endif
-using RowPlan = typename std::conditional<DDX_ROWS_WIDE != 0, Plan15Wide, Plan<kBigLog>>::type;
+using RowPlan = Plan<kBigLog>;
 
 // exp(S 2 pi i num / 2^(15 + logr)) for 0 <= num < 2^(15 + logr), reduced exactly
 template <int S>
@@ -405,7 +420,7 @@ __global__ __launch_bounds__(Geo<Plan<kBigLog>>::T) void k_dedisperse_big_a(Dedi
 }
 
 template <int R, int OUT>
-__device__ __forceinline__ void dedisperse_big_b(const float2* t0, int n2, int lead, int valid,
+__device__ __forceinline__ void dedisperse_big_b(float2* t0, int n2, int lead, int valid,
                                                  typename YType<OUT>::T* y) {
   float2 v[R];
 #pragma unroll
@@ -416,6 +431,15 @@ __device__ __forceinline__ void dedisperse_big_b(const float2* t0, int n2, int l
     const int n = n1 * kBigN + n2;
     if (n >= lead && n < lead + valid) store_stream(y + (n - lead), convert_y<OUT>(v[out_reg<R>(n1)]));
   }
+  if constexpr (OUT != 0) {
+    // |s y[n]|^2 into the slot this thread alone read (row n1, column n2 = index n of
+    // the unit's rows in natural order), for k_dump_power_rows
+#pragma unroll
+    for (int n1 = 0; n1 < R; ++n1) {
+      const float2 o = v[out_reg<R>(n1)];
+      t0[(size_t)n1 * kBigN + n2] = make_float2(fmaf(o.x, o.x, o.y * o.y), 0.f);
+    }
+  }
 }
 
 // Inverse pass B: R-point DFT over k1, overlap-save discard, output conversion.
@@ -425,12 +449,23 @@ __global__ __launch_bounds__(256) void k_dedisperse_big_b(DedispArgs a) {
   const int n2 = blockIdx.x * 256 + threadIdx.x;
   const int p = blockIdx.y / a.n_units;
   const UnitItem w = a.units[blockIdx.y % a.n_units];
-  const float2* t0 = a.tb + w.tb + ((size_t)p << (kBigLog + a.logr));
+  float2* t0 = a.tb + w.tb + ((size_t)p << (kBigLog + a.logr));
   typedef typename YType<OUT>::T YT;
   YT* y = reinterpret_cast<YT*>(a.y) + w.y + (size_t)(a.ant0 + p) * a.y_stride;
   if (a.logr == 1) dedisperse_big_b<2, OUT>(t0, n2, w.lead, w.valid, y);
   else if (a.logr == 2) dedisperse_big_b<4, OUT>(t0, n2, w.lead, w.valid, y);
   else dedisperse_big_b<8, OUT>(t0, n2, w.lead, w.valid, y);
+}
+
+// Per-dump power of the two-pass outputs (binary16 / E4M3): sums of the |s y[n]|^2
+// that k_dedisperse_big_b left at index n of each unit's rows, n = lead + j.
+// grid: n_units * n_ant workgroups of 256 (unit fastest), antennas ant0 + p.
+__global__ __launch_bounds__(256) void k_dump_power_rows(DedispArgs a) {
+  const int u = blockIdx.x % a.n_units, p = blockIdx.x / a.n_units;
+  const UnitItem w = a.units[u];
+  const float2* t0 = a.tb + w.tb + ((size_t)p << (kBigLog + a.logr)) + w.lead;
+  dump_sums<256>([&](int j) { return t0[j].x; }, w.valid, a.dump_len,
+                 power_row(a.power, w, a.y_stride, a.pw_stride, a.ant0 + p), threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -488,8 +523,9 @@ typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 // [Re y_0 .. Re y_{M-1}, Im y_0 .. Im y_{M-1}] over the L samples of the dump
 // (the stored voltages are s y, s = the channel's correlator-input scale),
 // G = A A^T on MFMA over the upper 16x16 tiles, FP32 accumulation, then
-//   Re V_ij = (G[i][j] + G[M+i][M+j]) / s^2,  Im V_ij = (G[j][M+i] - G[i][M+j]) / s^2.
-// Samples are staged through LDS in chunks of kCorrKC with two chunks in flight:
+//   Re V_ij = (G[i][j] + G[M+i][M+j]) / s^2,  Im V_ij = (G[j][M+i] - G[i][M+j]) / s^2,
+// except that with binary16 / E4M3 inputs V_ii is the dump's power of the unrounded
+// voltages (from the dedispersion kernel) / s^2.  Samples are staged through LDS in chunks of kCorrKC with two chunks in flight:
 // chunk k + 2's loads are issued while chunk k is staged, before its MFMAs.
 // grid: n_units * max_dumps workgroups of 256 threads (4 waves), one per
 // (unit, dump); workgroups past a unit's last dump exit at once.
@@ -498,16 +534,20 @@ struct CorrArgs {
   float2* ring;
   const UnitItem* units;
   const float* scale;    // [C] correlator-input scales s_c (all formats)
+  const float* power;    // binary16 / E4M3 inputs: per-dump power rows (the autocorrelations)
   int64_t y_stride;      // samples per antenna row of y
   int64_t rec_elems;     // complex values per dump record
   int64_t ring_dumps;    // ring capacity in dumps
   int32_t max_dumps;     // dumps per unit covered by the grid
   int32_t n_ant, dump_len, nbl, out_mode;
+  int32_t pw_stride;     // power values per antenna row
+  int32_t pad;
 };
 
 // The (unit, dump) of workgroup `item`; false when the unit has fewer dumps.
 struct CorrJob {
   int64_t yoff;      // element offset in y of the dump's first sample, antenna 0
+  int64_t prow;      // offset of the dump's power value of antenna 0 (antenna i at + i pw_stride)
   float2* out;       // the (channel, DM) slot of the dump's record
   int32_t chan;
   int32_t dump_off;  // samples from the unit's row start to the dump's first sample
@@ -517,6 +557,7 @@ __device__ __forceinline__ bool corr_job(const CorrArgs& a, int item, CorrJob& j
   const int m = item % a.max_dumps;
   if (m >= w.n_dumps) return false;
   j.yoff = w.y + (int64_t)m * a.dump_len;
+  j.prow = (w.y / a.y_stride) * a.pw_stride + m;
   j.out = a.ring + ((w.dump0 + m) % a.ring_dumps) * a.rec_elems + w.rec;
   j.chan = w.chan;
   j.dump_off = m * a.dump_len;
@@ -729,15 +770,17 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
       int i = 0, rem = b;
       while (rem >= M - i) { rem -= M - i; ++i; }
       const int j = i + rem;
-      const float re = gram[i * C::GP + j] + gram[(M + i) * C::GP + M + j];
+      float re = gram[i * C::GP + j] + gram[(M + i) * C::GP + M + j];
       const float im = gram[j * C::GP + M + i] - gram[i * C::GP + M + j];
+      if (T != 0 && i == j) re = a.power[w.prow + (int64_t)i * a.pw_stride];  // full-precision autos
       out[b] = make_float2(re * inv, im * inv);
     }
   } else {
     for (int b = tid; b < M * M; b += 256) {
       const int i = b / M, j = b % M;
       const int lo = i < j ? i : j, hi = i < j ? j : i;
-      const float re = gram[lo * C::GP + hi] + gram[(M + lo) * C::GP + M + hi];
+      float re = gram[lo * C::GP + hi] + gram[(M + lo) * C::GP + M + hi];
+      if (T != 0 && i == j) re = a.power[w.prow + (int64_t)i * a.pw_stride];  // full-precision autos
       const float im = gram[hi * C::GP + M + lo] - gram[lo * C::GP + M + hi];
       out[b] = make_float2(re * inv, (i <= j ? im : -im) * inv);
     }
@@ -953,7 +996,9 @@ __global__ __launch_bounds__(corr_block_threads(BA)) void k_correlate_blocks(Cor
         const int i = I * BA + (rg * RT + x) * 16 + 4 * (lane >> 4) + r;
         const int j = J * BA + (cg * 4 + q) * 16 + (lane & 15);
         if (i >= M || j >= M || j < i) continue;
-        const float re = are[x][q][r] * inv, im = (i == j) ? 0.f : aim[x][q][r] * inv;  // autos are real
+        float re = are[x][q][r] * inv;
+        const float im = (i == j) ? 0.f : aim[x][q][r] * inv;  // autos are real
+        if (T != 0 && i == j) re = a.power[w.prow + (int64_t)i * a.pw_stride] * inv;  // full-precision autos
         if (a.out_mode == 0) {
           out[(int64_t)i * M - (int64_t)i * (i - 1) / 2 + (j - i)] = make_float2(re, im);
         } else {

@@ -91,10 +91,9 @@ def test_c1_sampled_parity_and_pulses(c1_input):
         assert abs(best - true) <= 1.0 + 1e-9
 
 
-# E4M3 keeps three mantissa bits: over ~2e6 visibilities its largest normalised
-# error lands just above 1e-2 (measured 1.14e-2), its 99.9th percentile near 5e-3;
-# the bound is on the 99.9th percentile, the maximum is reported.  binary16 stays
-# two orders of magnitude inside.
+# Reduced-precision inputs round only the products between antennas; the
+# autocorrelations are the dumps' power of the unrounded voltages.  The bound is on
+# the maximum over every sampled visibility, the DM 0 trial included.
 @pytest.mark.parametrize("corr,bound", [("e4m3", 1e-2), ("f16", 1e-4)])
 def test_c1_quantised_error_table(c1_input, corr, bound):
     p, chunks, pulses, fc, host = c1_input
@@ -115,9 +114,8 @@ def test_c1_quantised_error_table(c1_input, corr, bound):
     say("%s vs FP64 oracle over %d visibilities (DM > 0): max %.3e, 99.9%% %.3e, rms %.3e; DM 0: max %.3e; "
         "scales %s" % (corr, e.size, e.max(), np.quantile(e, 0.999), np.sqrt(np.mean(e ** 2)), z.max(),
                        np.unique(lay["scale"])))
-    assert np.quantile(e, 0.999) <= bound
-    assert e.max() <= 2 * bound
-    assert z.max() <= 5 * bound
+    assert e.max() <= bound
+    assert z.max() <= bound
 
 
 def test_c1_learned_proposal(c1_input):

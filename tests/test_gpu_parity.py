@@ -29,6 +29,47 @@ def test_c0_full_parity_and_pulse(gpu, c0):
     err = compare_with_oracle(c0, vis, lay)
     say("C0 max normalised error %.3e" % err)
     assert err <= TOL
+    # the injected pulse (DM 50 = trial 8, S/N 20, 100 us): at 1.4 GHz one trial
+    # spacing smears the pulse by at most ~19 samples, well inside a 64-sample dump,
+    # so dump-resolution power resolves the DM only to a few trials; the best trial
+    # lies within 3 of the truth and is the oracle's best trial on the same statistic
+    best = _best_trial(vis, lay, 8, 16)
+    ref = oracle.run_oracle(c0["volts"], c0["chan_freqs"], 1e6, c0["dm_lists"], 64, blockings(lay))
+    ref_best = _best_trial(np.concatenate([ref[(0, d)] for d in range(16)], axis=1), dict(lay, record_pos=np.arange(16)),
+                           8, 16)
+    say("C0 pulse: best trial %d (oracle %d, injected 8)" % (best, ref_best))
+    assert abs(best - 8) <= 3 and best == ref_best
+
+
+def _best_trial(vis, lay, m_ant, n_dm):
+    """Argmax over trials of a robust S/N: per trial the incoherent power (sum of the
+    autocorrelations) in a two-dump boxcar, its maximum over the stream against the
+    median and scaled MAD."""
+    iu, ju = np.triu_indices(m_ant)
+    snr = []
+    for d in range(n_dm):
+        pw = select(vis, lay, 0, d)[:, iu == ju].real.sum(axis=1)
+        q = pw[:-1] + pw[1:]
+        med = np.median(q)
+        snr.append((q.max() - med) / (1.4826 * np.median(np.abs(q - med))))
+    return int(np.argmax(snr))
+
+
+def test_noisy_pulse_recovered_within_one_trial(gpu):
+    """Pulse recovery with noise (S/N 20, 100 us, DM 50 = trial 8 of 16 over 0-100) in
+    a 1 MHz channel at 0.7005 GHz, where one trial spacing smears the pulse by ~150
+    samples, more than a dump: the best trial is within one of the injected DM."""
+    rng = np.random.Generator(np.random.PCG64(1201))
+    fc = 0.7005e9
+    x = synth.noise_complex(rng, (1, 8, 65536))
+    wave = synth.pulse_wave(rng, 100, 20.0, 1.0)
+    synth.inject_pulse(x[0], fc, 1e6, 50.0, 30000, wave, f_ref=fc, phases=2 * np.pi * rng.random(8))
+    cfg = {"volts": x.astype(np.complex64), "chan_freqs": np.array([fc]), "f_s": 1e6,
+           "dm_lists": [synth.dm_grid(16, 100.0)], "dump_len": 64}
+    vis, lay = run_gpu(cfg)
+    best = _best_trial(vis, lay, 8, 16)
+    say("0.7 GHz noisy pulse: best trial %d (injected 8)" % best)
+    assert abs(best - 8) <= 1
 
 
 def test_pulse_recovery_noise_free(gpu):
@@ -61,6 +102,27 @@ def test_plan_blocking_matches_oracle_rule(gpu):
     delta, shift = oracle.channel_delays(cfg["chan_freqs"], cfg["dm_lists"][0], 1e6)
     np.testing.assert_allclose(lay["delay_s"][:4], delta[0], rtol=1e-15)
     assert np.array_equal(lay["shift"][lay["dm_offset"][2]:lay["dm_offset"][2] + 4], shift[2])
+
+
+def test_dump_times_match_oracle(gpu):
+    """The exported dump times (at the channel centre and referred to infinite
+    frequency) equal the oracle's bookkeeping."""
+    from paper_1109_3186_amd import Plan
+    fc = synth.chan_freqs(1.2e9, 3, 1e6)
+    dms = np.array([0.0, 150.0, 1999.0])
+    with Plan(2, fc, 1e6, 1000, max_block_samples=1 << 16) as p:
+        p.set_dm_trials(dms)
+        lay = p.layout()
+        assert lay["dump_t0_s"] == 499.5e-6 and lay["dump_period_s"] == 1e-3
+        delta, _ = oracle.channel_delays(fc, dms, 1e6)
+        for c in range(3):
+            for d in range(3):
+                for refer in (False, True):
+                    got = p.dump_times(c, d, 7, 5, refer_infinite=refer)
+                    ref = oracle.dump_times(5, 1000, 1e6, first_dump=7, delay_s=delta[c, d] if refer else 0.0)
+                    np.testing.assert_allclose(got, ref, rtol=1e-15, atol=1e-15)
+        with pytest.raises(Exception):
+            p.dump_times(3, 0, 0, 1)
 
 
 @pytest.mark.parametrize("out_mode", ["packed", "full"])

@@ -6,11 +6,11 @@ rounding midpoint may round the other way: such flips are counted), and the
 unquantised FP64 oracle (bound 1e-2 normalised at 1 ms dumps for E4M3, 1e-4 for
 binary16).
 
-The DM = 0 trial is reported apart: there the dedispersed voltages equal the
-integer int8 inputs, many of which sit exactly on E4M3 rounding midpoints once
-scaled, so the FP32 round trip of the FFT decides the tie (the emulation always
-rounds ties to even), and three mantissa bits on integer data give up to ~1.5e-2
-normalised error against FP64 even in the emulation.
+The DM = 0 trial is compared with the exact oracle only: there the dedispersed
+voltages equal the integer int8 inputs, many of which sit exactly on E4M3
+rounding midpoints once scaled, so the FP32 round trip of the FFT decides the tie
+(the emulation always rounds ties to even).  The autocorrelations are the
+unrounded voltages' power on both sides, so the 1e-2 bound holds at DM 0 too.
 
 The FP8 MFMA itself is not exact: measured on this hardware, each 32-term block
 of products carries a systematic relative error of ~5e-5 of its magnitude (FP16
@@ -49,7 +49,7 @@ def test_quantised_inputs_rule_scale(gpu, quant):
     else:
         assert np.sqrt(np.mean(emu ** 2)) <= 2e-4 and emu.max() <= 5e-3
     assert exact.max() <= (1e-2 if quant == "e4m3" else 1e-4)
-    assert dm0.max() <= (5e-2 if quant == "e4m3" else 1e-4)
+    assert dm0.max() <= (1e-2 if quant == "e4m3" else 1e-4)
 
 
 def test_explicit_scale(gpu):

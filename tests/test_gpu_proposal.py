@@ -89,6 +89,61 @@ def test_cnn_forward_backward_adam_match_oracle(gpu):
     net.close()
 
 
+def test_cnn_adam_several_steps_match_oracle(gpu):
+    """Adam past its first step: (1) with the gradients held fixed, k steps move every
+    weight by exactly k lr g / (|g| + eps) (the bias-corrected moments are g and g^2 at
+    every step); (2) four steps of forward, backward and Adam from the same start on
+    the GPU and in the oracle, each side with its own gradients, stay together."""
+    import torch
+
+    from paper_1109_3186_amd import Cnn
+    from paper_1109_3186_amd.proposal import unflatten
+    rng = np.random.Generator(np.random.PCG64(47))
+    d, L, nt = 16, 128, 2
+    tiles = rng.standard_normal((nt, d, L)) * 3 + 10
+    tiles[1, 9, 70:75] += 25
+    params = P.init_params(48)
+    labels = (rng.random(nt * d) < 0.3).astype(np.float64)
+    t_dev = torch.from_numpy(tiles.astype(np.float32)).to(gpu)
+    lab_dev = torch.from_numpy(labels.astype(np.float32)).to(gpu)
+    # (1) fixed gradients
+    net = Cnn(d, L, nt)
+    net.set_weights(_flat(params))
+    net.forward(t_dev)
+    net.loss(lab_dev)
+    net.backward()
+    w0 = net.get_weights().astype(np.float64)
+    g = net.get_grads().astype(np.float64)
+    lr, eps = 1e-3, 1e-8
+    for k in range(1, 5):
+        net.adam(lr=lr, eps=eps)
+        expect = w0 - k * lr * g / (np.abs(g) + eps)
+        err = np.max(np.abs(net.get_weights() - expect))
+        say("fixed-gradient Adam step %d: max |w - closed form| %.2e" % (k, err))
+        assert err <= 2e-6
+    net.close()
+    # (2) trajectories; eps large enough that gradient rounding moves a step by < lr 1e-2
+    lr, eps = 1e-3, 1e-2
+    net = Cnn(d, L, nt)
+    net.set_weights(_flat(params))
+    x = np.concatenate([P.rows3(P.standardise(tiles[i])) for i in range(nt)])
+    ref = {k: v.copy() for k, v in params.items()}
+    state = {}
+    for step in range(4):
+        net.forward(t_dev)
+        net.loss(lab_dev)
+        net.backward()
+        net.adam(lr=lr, eps=eps)
+        score, cache = P.forward(ref, x)
+        _, ds = P.loss_and_grad(score, labels)
+        P.adam_step(ref, P.backward(ref, cache, ds), state, lr=lr, eps=eps)
+        got = unflatten(net.get_weights())
+        err = max(float(np.max(np.abs(got[k] - ref[k]))) for k in ref)
+        say("Adam trajectory step %d: max |w_gpu - w_oracle| %.2e" % (step + 1, err))
+        assert err <= 1e-4
+    net.close()
+
+
 def test_overfit_tiny_batch(gpu):
     """Training on two fixed tiles drives the loss down and ranks the labelled rows first."""
     import torch

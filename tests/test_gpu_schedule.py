@@ -31,6 +31,33 @@ def test_two_pass_transform_lengths(gpu, n):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("quant,L", [("e4m3", 1000), ("f16", 40)])
+def test_two_pass_quantised_autocorrelations(gpu, quant, L):
+    """Reduced-precision inputs at a two-pass length: the autocorrelations are the
+    unrounded voltages' power (summed from the intermediate rows, including dumps
+    shorter than a wave), equal to the exact oracle's within 1e-5; cross products
+    within the format's bound."""
+    cfg = synth.make_small(seed=66, m_ant=5, n_chan=1, s=3 * (1 << 16) + 4321, f_lo=1.3e9, f_s=1e6, n_dm=3,
+                           dm_max=500.0, dump_len=L, ci8=True, n_pulses=1)
+    say("two-pass N 2^16, %s inputs, L %d" % (quant, L))
+    vis, lay = run_gpu(cfg, in_dtype="ci8", corr=quant, fft_len=1 << 16)
+    from gpu_helpers import blockings
+    bl = blockings(lay)
+    ref = oracle.run_oracle(cfg["volts"], cfg["chan_freqs"], 1e6, cfg["dm_lists"], L, bl)
+    iu, ju = np.triu_indices(5)
+    worst_auto = worst = 0.0
+    for (c, d), v in ref.items():
+        got = select(vis, lay, c, d).astype(np.complex128)
+        auto = v[:, iu == ju].real
+        norm = np.sqrt(auto[:, iu] * auto[:, ju])
+        e = np.abs(got - v) / norm
+        worst_auto = max(worst_auto, float(e[:, iu == ju].max()))
+        worst = max(worst, float(e.max()))
+    say("%s: autos max %.2e, all max %.2e" % (quant, worst_auto, worst))
+    assert worst_auto <= TOL
+    assert worst <= (1e-2 if quant == "e4m3" else 1e-3 if L < 100 else 1e-4)
+
+
 def test_mixed_lengths_one_plan(gpu):
     """Channels with 2^12-, 2^15- and 2^17-point blocks and uneven DM lists in one plan,
     streamed in uneven chunks."""
