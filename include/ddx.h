@@ -485,6 +485,17 @@ int ddx_incoherent_dedisperse(const float* d_power, int32_t n_chan, int64_t n_t,
 int ddx_tree_dedisperse(const float* d_power, int32_t n_chan, int64_t n_t, float* d_out, float* d_work,
                         void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): ddx_tree_dedisperse with
+ * its workspace in a static device array of DDX_TREE_STATIC_MAX floats (64 MiB per
+ * GPU, held until the process ends) instead of d_work; same kernels, same results.
+ * Allocates nothing.  n_chan * n_t > DDX_TREE_STATIC_MAX: DDX_ESIZE, nothing
+ * enqueued.  Every call on one GPU shares that GPU's array: calls that overlap on
+ * one GPU (other streams, other threads) race.  Other errors as ddx_tree_dedisperse,
+ * and DDX_EDEVICE if the array's device address cannot be found. */
+#define DDX_TREE_STATIC_MAX (16 * 1024 * 1024)
+int ddx_tree_dedisperse_static(const float* d_power, int32_t n_chan, int64_t n_t, float* d_out, void* hip_stream);
+
 /* ---- The Chimageator on a uniform linear array (Sec. 4) --------------------------
  * Stateless calls; caller-owned device buffers that must not overlap; asynchronous
  * on hip_stream.  Antenna p sits at p times the spacing along the line. */

@@ -7,6 +7,7 @@ library every call raises.
 """
 from .binding import (  # noqa: F401
     Plan, Cnn, Chirp, ChirpBank, Image, incoherent_delays, power_beam, incoherent_dedisperse, tree_dedisperse,
+    tree_dedisperse_static, TREE_STATIC_MAX,
     chimg_preintegrate, chimg_trajectories, chimg_gradient_sums, chimg_cells, chimg_preintegrate_cells,
     DdxError, lib, LIB_PATH, SIGNATURES,
     OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ESIZE, EFULL, EUNSUPPORTED,

@@ -121,6 +121,7 @@ SIGNATURES = {
     "ddx_incoherent_dedisperse": ([ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_void_p, ct.c_int32, ct.c_void_p,
                                    ct.c_int64, ct.c_void_p], ct.c_int),
     "ddx_tree_dedisperse": ([ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p], ct.c_int),
+    "ddx_tree_dedisperse_static": ([ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_void_p, ct.c_void_p], ct.c_int),
     "ddx_chimg_preintegrate": ([ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p,
                                 ct.c_void_p], ct.c_int),
     "ddx_chimg_trajectories": ([ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p,
@@ -684,6 +685,24 @@ def tree_dedisperse(power, out=None, work=None, stream=None):
                                    _stream_handle(stream))
     if rc != OK:
         raise DdxError(rc, "ddx_tree_dedisperse")
+    return out
+
+
+TREE_STATIC_MAX = 16 * 1024 * 1024
+
+
+def tree_dedisperse_static(power, out, stream=None):
+    """The tree method with the library's static workspace (no allocation by the
+    library or here): device float32 power [C, T] and out [C, T], C T <= TREE_STATIC_MAX."""
+    import torch
+    if power.dtype != torch.float32 or power.dim() != 2 or not power.is_contiguous():
+        raise DdxError(EINVAL, "power must be contiguous float32 [C, T]")
+    if out.shape != power.shape or out.dtype != torch.float32 or not out.is_contiguous():
+        raise DdxError(EINVAL, "out must be contiguous float32 of power's shape")
+    rc = lib().ddx_tree_dedisperse_static(ct.c_void_p(power.data_ptr()), power.shape[0], power.shape[1],
+                                          ct.c_void_p(out.data_ptr()), _stream_handle(stream))
+    if rc != OK:
+        raise DdxError(rc, "ddx_tree_dedisperse_static")
     return out
 
 

@@ -20,6 +20,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <vector>
 
 #include "ddx.h"
 
@@ -368,6 +370,50 @@ int ddx_tree_dedisperse(const float* d_power, int32_t n_chan, int64_t n_t, float
     src = dst;
   }
   return hipGetLastError() == hipSuccess ? DDX_OK : DDX_EDEVICE;
+}
+
+}  // extern "C"
+
+// Workspace of ddx_tree_dedisperse_static: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never passes `scratch` itself (in
+// host code it names a host-side stand-in); it uses the device address that
+// hipGetSymbolAddress returns, looked up once per device on the first call there.
+namespace {
+constexpr size_t kStaticWorkFloats = DDX_TREE_STATIC_MAX;
+__device__ __align__(256) float scratch[kStaticWorkFloats];
+std::mutex g_scratch_mu;
+std::vector<float*> g_scratch_ptr;  // per device ordinal, null until looked up
+
+int scratch_address(float** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return DDX_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((size_t)dev >= g_scratch_ptr.size()) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return DDX_EDEVICE;
+    }
+    g_scratch_ptr[dev] = static_cast<float*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return DDX_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int ddx_tree_dedisperse_static(const float* d_power, int32_t n_chan, int64_t n_t, float* d_out, void* hip_stream) {
+  if (n_chan < 1 || n_t < 0 || !d_power || !d_out) return DDX_EINVAL;
+  if ((uint64_t)n_chan * (uint64_t)n_t > kStaticWorkFloats) return DDX_ESIZE;
+  if (n_t == 0) return DDX_OK;
+  float* work = nullptr;
+  const int rc = scratch_address(&work);
+  if (rc) return rc;
+  // every tree pass writes each workspace row in full before a later pass reads it,
+  // so nothing needs clearing between calls
+  return ddx_tree_dedisperse(d_power, n_chan, n_t, d_out, work, hip_stream);
 }
 
 int ddx_power_beam(const void* d_volts, int32_t n_chan, int32_t n_ant, int64_t n_samp, int32_t n_int, float* d_power,
