@@ -73,6 +73,7 @@ def build_input(p, dev, chunk):
         chunks.append(x[..., 2 * s0:2 * s1].contiguous())
     del x
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()  # the generator's temporaries go back to the device for the plans
     log("input built in %.1f s: %d chunks" % (time.time() - t0, len(chunks)))
     return chunks, pulses, fc
 
@@ -178,6 +179,126 @@ def learned_form(make_plan, dms, chunks, pulses, p, out, steps, plain_ms):
             "note": "tile + network + active-DM sweep on the same stream, records of the proposed DMs only; "
                     "recall = injected pulses whose DM trial "
                     "(either neighbour) is active"}
+
+
+def recall_study(dev, n_streams=100, seed0=5000, log_every=10):
+    """Voltage-level recall of the learned proposal over n_streams streams of the
+    36-antenna workload's shape (10 pulses each: S/N 20, 100 us, random DM, time
+    and position; seeds seed0 + i): power tile + network + device top-k alone, with
+    the full sweep as the judge of its misses only.  Also compares each stream's
+    voltage-generated tile with the power-model tile of the same pulses (the
+    shortcut the network was trained on): the pulses' standardised peak heights and
+    the standard deviation of the tile away from them."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1109_3186_amd import Plan
+    from paper_1109_3186_amd.proposal import Proposal, load_weights
+    p0 = synth.c1_params()
+    fc = synth.chan_freqs(p0["f_lo"], p0["n_chan"], p0["f_s"])
+    dms = synth.dm_grid(p0["n_dm"], p0["dm_max"])
+    dstep = p0["dm_max"] / p0["n_dm"]
+    wpath = os.path.join(ROOT, "paper_1109_3186_amd", "proposal_weights.npz")
+    plan = Plan(p0["m_ant"], fc, p0["f_s"], p0["dump_len"], max_block_samples=1 << 18, in_dtype="ci8",
+                compact_records=True)
+    plan.set_dm_trials(dms)
+    prop = Proposal(plan, load_weights(wpath), budget=0.1)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed0)
+    rng = np.random.Generator(np.random.PCG64(seed0))
+    hits = tot = fallbacks = 0
+    missed = []
+    peaks_v, peaks_m, sd_v, sd_m = [], [], [], []
+    t0 = time.time()
+
+    def zscore(t):
+        t = t.double()
+        return ((t - t.mean()) / t.std()).cpu().numpy()
+
+    for i in range(n_streams):
+        p = dict(p0, seed=seed0 + i)
+        x, pulses, _, _ = synth.make_stream_device(p, dev)
+        mask, _, fb = prop.select(x)
+        del x
+        fallbacks += int(fb)
+        zv = zscore(prop.tile)
+        power, _, _ = synth.power_batch(p, 1, 32, rng, gen, dev, pulses_given=[pulses])
+        zm = zscore(plan.tiles_from_power(power, 32, 1024, 1024)[0])
+        del power
+        keep = np.ones(zv.shape, bool)
+        for q in pulses:
+            d0 = q["dm"] / dstep
+            hit = bool(mask[math.floor(d0)] or mask[min(math.ceil(d0), p0["n_dm"] - 1)])
+            tot += 1
+            hits += int(hit)
+            if not hit:
+                missed.append((i, q))
+            r, b = int(round(d0)), (q["n0"] + q["width"] // 2) // 1024
+            rs, bs = slice(max(r - 2, 0), r + 3), slice(max(b - 2, 0), b + 3)
+            peaks_v.append(float(zv[rs, bs].max()))
+            peaks_m.append(float(zm[rs, bs].max()))
+            keep[max(r - 12, 0):r + 13, :] = False
+        sd_v.append(float(zv[keep].std()))
+        sd_m.append(float(zm[keep].std()))
+        if (i + 1) % log_every == 0:
+            log("recall study: %d streams, %d/%d pulses kept, %d fallbacks, %.0f s" % (
+                i + 1, hits, tot, fallbacks, time.time() - t0))
+    prop.close()
+    plan.close()
+    torch.cuda.empty_cache()
+    # the full sweep judges each miss: is the pulse found within one trial of its DM
+    # by the autocorrelation power at the dump where each trial places it?
+    judged = []
+    if missed:
+        full = Plan(p0["m_ant"], fc, p0["f_s"], p0["dump_len"], max_block_samples=1 << 18, in_dtype="ci8")
+        full.set_dm_trials(dms)
+        lay = full.layout()
+        shift = lay["shift"].reshape(p0["n_chan"], p0["n_dm"])
+        iu, ju = np.triu_indices(p0["m_ant"])
+        auto_idx = torch.tensor(np.nonzero(iu == ju)[0], device=dev)
+        for i in sorted({i for i, _ in missed}):
+            x, _, _, _ = synth.make_stream_device(dict(p0, seed=seed0 + i), dev)
+            full.reset_stream()
+            pw = []
+            for s0 in range(0, p0["samples"], 1 << 18):
+                full.process_block(x[..., 2 * s0:2 * (s0 + (1 << 18))].contiguous(),
+                                   flush=s0 + (1 << 18) >= p0["samples"])
+                _, nd, vis = full.fetch()
+                if nd:
+                    pw.append(vis.view(nd, -1, lay["n_baselines"]).index_select(2, auto_idx).real.sum(dim=2)
+                              .cpu().numpy())
+            del x
+            pw = np.concatenate(pw).reshape(-1, p0["n_chan"], p0["n_dm"])
+            for j, q in missed:
+                if j != i:
+                    continue
+                score = np.zeros(p0["n_dm"])
+                for d in range(p0["n_dm"]):
+                    m = (q["n0"] + q["width"] // 2 + shift[:, d]) // p0["dump_len"]
+                    ok = m < pw.shape[0]
+                    score[d] = pw[m[ok], np.nonzero(ok)[0], d].sum()
+                judged.append({"stream": i, "dm": q["dm"], "sweep_finds": bool(abs(np.argmax(score) - q["dm"] / dstep)
+                                                                                <= 1.0 + 1e-9)})
+        full.close()
+    recoverable = tot - sum(1 for j in judged if not j["sweep_finds"])
+    pv, pm = np.array(peaks_v), np.array(peaks_m)
+    rec = {"streams": n_streams, "pulses": tot, "kept": hits, "recall": hits / tot,
+           "recall_of_sweep_recoverable": hits / max(recoverable, 1), "misses_judged_by_full_sweep": judged,
+           "fallbacks": fallbacks, "seconds": round(time.time() - t0, 1),
+           "tile_validation": {"peak_z_voltage_median": round(float(np.median(pv)), 3),
+                               "peak_z_power_model_median": round(float(np.median(pm)), 3),
+                               "peak_ratio_median": round(float(np.median(pv / pm)), 4),
+                               "peak_ratio_p10_p90": [round(float(np.quantile(pv / pm, 0.1)), 4),
+                                                      round(float(np.quantile(pv / pm, 0.9)), 4)],
+                               "noise_sd_voltage": round(float(np.mean(sd_v)), 4),
+                               "noise_sd_power_model": round(float(np.mean(sd_m)), 4),
+                               "tiles": n_streams}}
+    log("recall study: %d/%d pulses kept (%.4f), %d misses judged by the full sweep, tiles: %s" % (
+        hits, tot, hits / tot, len(judged), rec["tile_validation"]))
+    return rec
 
 
 def run_chirp(args, dev):
@@ -564,6 +685,7 @@ def c3_measure(dev, steps, warmup, corr, use_autotune, n_passes):
     t0 = time.time()
     x, pulses, fc, pos = synth.make_stream_device(p, dev)
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()  # the generator's temporaries go back to the device for the plan
     log("C3 input built in %.1f s" % (time.time() - t0))
     s, L, M = p["samples"], p["dump_len"], p["m_ant"]
     dms = [synth.dm_grid(n, p["dm_max"]) for n in p["n_dm"]]
@@ -795,6 +917,8 @@ def main():
                     help="reduced-precision correlator inputs measured after the main form (comma list, '' = none)")
     ap.add_argument("--form-steps", type=int, default=3, help="timed passes per reduced-precision form")
     ap.add_argument("--no-c3", action="store_true", help="skip the one-step 256-antenna leg of the default run")
+    ap.add_argument("--recall-streams", type=int, default=100,
+                    help="voltage streams of the learned proposal's recall study (10 pulses each; 0 = skip)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal measurement")
     ap.add_argument("--wave-units", type=int, default=0, help="schedule: units per wave (0 = automatic)")
     ap.add_argument("--dm-group", type=int, default=0, help="schedule: DMs per block group (0 = automatic)")
@@ -901,6 +1025,16 @@ def main():
         learned = learned_form(make_plan, dms, chunks, pulses, p, out, args.steps, ms)
     del out
     plan.close()
+    c3 = None
+    if not args.no_c3 and args.corr == "f32" and not args.channels:
+        import gc
+        gc.collect()
+        torch.cuda.empty_cache()
+        free, total = torch.cuda.mem_get_info()
+        log("device memory before the 256-antenna leg: %.1f GB free of %.1f GB" % (free / 1e9, total / 1e9))
+        c3 = c3_one_step(dev)
+    if learned is not None and args.recall_streams > 0 and not args.channels:
+        learned["recall_study"] = recall_study(dev, args.recall_streams)
     forms = None
     if args.forms and args.corr == "f32" and not args.channels:
         host = {c: np.concatenate([ch[c].cpu().numpy() for ch in chunks], axis=-1)
@@ -920,12 +1054,8 @@ def main():
                    "n_ant": p["m_ant"], "n_chan": p["n_chan"], "samples": p["samples"], "n_dm": p["n_dm"],
                    "dump_len": p["dump_len"], "fft_len": int(lay["fft_len"][0]), "chunk": args.chunk,
                    "input": "ci8", "corr": args.corr, "parallelism": "none (1 GPU)"},
-        "roofline": roofline, "cpu_baseline": cpu, "learned": learned, "precision_forms": forms,
+        "roofline": roofline, "cpu_baseline": cpu, "learned": learned, "precision_forms": forms, "c3_step": c3,
     }
-    if not args.no_c3 and args.corr == "f32" and not args.channels:
-        del chunks
-        torch.cuda.empty_cache()
-        rec["c3_step"] = c3_one_step(dev)
     print(json.dumps(rec), flush=True)
 
 

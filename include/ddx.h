@@ -53,7 +53,11 @@ extern "C" {
 
 /* Correlator input formats (the dedispersed voltages). */
 #define DDX_CORR_F32 0  /* FP32 voltages; products from a two-term binary16 split (hi*hi + hi*lo
-                           + lo*hi) on FP16 MFMA, FP32 accumulate: FP32-level accuracy */
+                           + lo*hi) on FP16 MFMA, FP32 accumulate: normalised visibility error
+                           ~1e-6 (a plain FP32 sum would give ~1e-7).  The split's range follows
+                           each (channel, DM, block): a block whose largest component of s y
+                           exceeds 2^15 is split at a smaller power of two, so later level
+                           changes cannot overflow binary16 */
 #define DDX_CORR_F16 1  /* voltages x scale rounded to IEEE binary16 (RNE, saturating) */
 #define DDX_CORR_E4M3 2 /* voltages x scale rounded to OCP FP8 E4M3 (RNE, saturating to +-448) */
 
@@ -163,6 +167,22 @@ int ddx_set_dm_trials(ddx_plan* plan, int32_t chan, const double* dm_pc_cm3, int
  * Host state only: no device work and no synchronisation; the next
  * ddx_process_block takes the new set. */
 int ddx_set_active_dms(ddx_plan* plan, int32_t chan, const uint8_t* mask);
+
+/* The learned proposal's selection (the proposal is this project's, not the
+ * paper's): from per-DM logits d_scores[D] (DEVICE FP32, e.g. ddx_cnn_forward's
+ * output) activate the k highest-scoring DMs -- ties to the lower DM index, NaN
+ * lowest -- or, when more than k logits exceed logit_threshold (the proposal cannot
+ * keep every candidate), every DM: the fallback to the full sweep.  The ranking
+ * runs on the device in one workgroup; the mask and the fallback flag are then
+ * copied to the host and hip_stream is synchronised (the next ddx_process_block
+ * lists its work on the host), and the mask is applied as by ddx_set_active_dms
+ * (same state rules).  chan = -1 applies one mask to every channel (all must have
+ * the same D).  d_mask_out: optional DEVICE uint8 [D] that receives the mask;
+ * fallback: optional host int32.  Errors: EINVAL (NULL scores, k < 1, channel out
+ * of range), EUNSUPPORTED (D > 16384, or chan = -1 with differing D_c), ESTATE,
+ * EDEVICE. */
+int ddx_select_active_dms(ddx_plan* plan, int32_t chan, const float* d_scores, int32_t k, float logit_threshold,
+                          uint8_t* d_mask_out, int32_t* fallback, void* hip_stream);
 
 /* Export the blocking, tables and stream counters.  Pointers refer to
  * plan-owned host memory valid until the next ddx_set_dm_trials or

@@ -67,6 +67,8 @@ SIGNATURES = {
     "ddx_set_dm_trials": ([ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_double), ct.c_int32], ct.c_int),
     "ddx_set_active_dms": ([ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_uint8)], ct.c_int),
     "ddx_get_layout": ([ct.c_void_p, ct.POINTER(Layout)], ct.c_int),
+    "ddx_select_active_dms": ([ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_int32, ct.c_float, ct.c_void_p,
+                               ct.POINTER(ct.c_int32), ct.c_void_p], ct.c_int),
     "ddx_dump_times": ([ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_int64, ct.c_int64, ct.c_int32,
                         ct.POINTER(ct.c_double)], ct.c_int),
     "ddx_process_block": ([ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_void_p], ct.c_int),
@@ -228,6 +230,21 @@ class Plan:
             m = np.ascontiguousarray(mask, dtype=np.uint8)
             ptr = m.ctypes.data_as(ct.POINTER(ct.c_uint8))
         self._check(lib().ddx_set_active_dms(self._h, chan, ptr), "ddx_set_active_dms")
+
+    def select_active_dms(self, scores, k, logit_threshold=0.0, chan=-1, mask_out=None, stream=None):
+        """Device top-k of per-DM logits (ddx_select_active_dms): activates the k best
+        DMs, or all of them when more than k logits exceed logit_threshold.  scores:
+        device float32 [D].  Returns (mask: device uint8 [D], fallback: bool)."""
+        import torch
+        if scores.dtype != torch.float32 or not scores.is_cuda or not scores.is_contiguous():
+            raise ValueError("scores must be a contiguous float32 device tensor")
+        if mask_out is None:
+            mask_out = torch.empty(scores.numel(), dtype=torch.uint8, device=scores.device)
+        fb = ct.c_int32(0)
+        self._check(lib().ddx_select_active_dms(self._h, chan, ct.c_void_p(scores.data_ptr()), int(k),
+                                                float(logit_threshold), ct.c_void_p(mask_out.data_ptr()),
+                                                ct.byref(fb), _stream_handle(stream)), "ddx_select_active_dms")
+        return mask_out, bool(fb.value)
 
     def layout(self):
         lay = Layout()

@@ -103,6 +103,10 @@ struct ddx_plan {
   void* ybuf = nullptr;        // [wave_units][M][y_stride]
   int64_t y_stride = 0;
   float* power = nullptr;      // binary16 / E4M3: [wave_units][M][pw_stride] per-dump power
+  float* l1 = nullptr;         // FP32: [forward items][M][8] row sums of |Re X| + |Im X| of one call
+  float* bound = nullptr;      // FP32: [forward items] bound on the block's |Re y|, |Im y| (input units)
+  uint8_t* sel_dev = nullptr;  // proposal selection: mask [kTopkMax] + flag (device)
+  uint8_t* sel_host = nullptr; // pinned host copy
   int pw_stride = 0;
   float2* ring = nullptr;
   int64_t ring_dumps = 0;
@@ -183,6 +187,8 @@ void free_device(ddx_plan* p) {
       p->stage_ev[i] = nullptr;
     }
     if (p->stage[i]) (void)hipHostFree(p->stage[i]);
+    if (i == 0 && p->sel_host) (void)hipHostFree(p->sel_host);
+    if (i == 0) p->sel_host = nullptr;
     p->stage[i] = nullptr;
     p->stage_used[i] = false;
   }
@@ -194,6 +200,8 @@ void free_device(ddx_plan* p) {
   p->spec_elems = p->tb_elems = 0;
   p->ybuf = nullptr;
   p->power = nullptr;
+  p->l1 = p->bound = nullptr;
+  p->sel_dev = nullptr;
   p->gtab = nullptr;
   p->scale_dev = nullptr;
   p->scale_part = nullptr;
@@ -302,7 +310,7 @@ hipError_t launch_forward_big(int logn, int in_dtype, ddx::FwdArgs a, const ddx:
   if (e != hipSuccess) return e;
   const unsigned rows = (unsigned)((size_t)n_items * a.n_ant << logr);
   hipLaunchKernelGGL(ddx::k_fft_rows, dim3(rows), dim3(ddx::Geo<ddx::RowPlan>::T), fft_lds_bytes<ddx::kBigLog>(), s,
-                     (const float2*)tb, a.spec + first_host->spec);
+                     (const float2*)tb, a.spec + first_host->spec, a.l1, logr);
   return hipGetLastError();
 }
 
@@ -529,6 +537,7 @@ int setup_device(ddx_plan* p) {
       (rc = dev_alloc(p, (void**)&p->power, (size_t)p->wave_units * p->M * p->pw_stride * sizeof(float))))
     return rc;
 
+
   if ((rc = dev_alloc(p, (void**)&p->chirp, (size_t)p->wave_units * maxn * sizeof(float2)))) return rc;
   // two-pass transforms: intermediate rows of one wave (dedispersion); the forward
   // transform runs its items in chunks of the same size
@@ -539,6 +548,10 @@ int setup_device(ddx_plan* p) {
   p->ring_dumps = p->ring_req ? p->ring_req
                               : (p->max_block + p->L - 1) / p->L + (2 * (int64_t)maxn + maxv) / p->L + 4;
   if ((rc = dev_alloc(p, (void**)&p->ring, (size_t)p->ring_dumps * p->cap_pairs * p->nbl * sizeof(float2)))) return rc;
+  if (p->corr_dtype == DDX_CORR_F32) {
+    if ((rc = dev_alloc(p, (void**)&p->l1, (size_t)max_fwd * p->M * 8 * sizeof(float)))) return rc;
+    if ((rc = dev_alloc(p, (void**)&p->bound, (size_t)max_fwd * sizeof(float)))) return rc;
+  }
   // work lists of one call
   p->items_cap = align_up(max_fwd * sizeof(ddx::FwdItem)) + align_up(max_units * sizeof(ddx::UnitItem)) +
                  align_up(max_units * sizeof(ddx::ChirpItem)) + align_up(max_zero * sizeof(ddx::ZeroItem)) +
@@ -699,6 +712,41 @@ int ddx_set_active_dms(ddx_plan* p, int32_t chan, const uint8_t* mask) {
   return DDX_OK;
 }
 
+int ddx_select_active_dms(ddx_plan* p, int32_t chan, const float* d_scores, int32_t k, float logit_threshold,
+                          uint8_t* d_mask_out, int32_t* fallback, void* hip_stream) {
+  if (!p) return DDX_EINVAL;
+  if (!p->ready) return fail(p, DDX_ESTATE, "set DM trials first");
+  if (chan < -1 || chan >= p->C) return fail(p, DDX_EINVAL, "channel %d out of range", chan);
+  if (!d_scores || k < 1) return fail(p, DDX_EINVAL, "NULL scores or k = %d < 1", k);
+  const int c0 = chan < 0 ? 0 : chan, c1 = chan < 0 ? p->C : chan + 1;
+  const int n = (int)p->ch[c0].dm.size();
+  for (int c = c0; c < c1; ++c)
+    if ((int)p->ch[c].dm.size() != n) return fail(p, DDX_EUNSUPPORTED, "channels hold different DM counts");
+  if (n > ddx::kTopkMax) return fail(p, DDX_EUNSUPPORTED, "%d DMs exceed %d", n, ddx::kTopkMax);
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (!p->sel_dev) {
+    const size_t bytes = align_up((size_t)ddx::kTopkMax + sizeof(int32_t));
+    int rc = dev_alloc(p, (void**)&p->sel_dev, bytes);
+    if (rc) return rc;
+    if (hipHostMalloc((void**)&p->sel_host, bytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      p->sel_host = nullptr;
+      return fail(p, DDX_ENOMEM, "pinned selection buffer");
+    }
+  }
+  // [mask: n bytes][pad to 4][flag]
+  int32_t* flag_dev = reinterpret_cast<int32_t*>(p->sel_dev + ddx::kTopkMax);
+  hipLaunchKernelGGL(ddx::k_topk_mask, dim3(1), dim3(1024), 0, s, d_scores, n, k, logit_threshold, p->sel_dev,
+                     flag_dev);
+  HIPCHECK(p, hipGetLastError());
+  if (d_mask_out) HIPCHECK(p, hipMemcpyAsync(d_mask_out, p->sel_dev, n, hipMemcpyDeviceToDevice, s));
+  HIPCHECK(p, hipMemcpyAsync(p->sel_host, p->sel_dev, ddx::kTopkMax + sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(p, hipStreamSynchronize(s));
+  const int32_t above = *reinterpret_cast<const int32_t*>(p->sel_host + ddx::kTopkMax);
+  if (fallback) *fallback = above > k ? 1 : 0;
+  return ddx_set_active_dms(p, chan, p->sel_host);
+}
+
 int ddx_get_layout(const ddx_plan* pc, ddx_layout* o) {
   if (!pc || !o) return DDX_EINVAL;
   ddx_plan* p = const_cast<ddx_plan*>(pc);
@@ -810,6 +858,7 @@ void build_lists(ddx_plan* p, const std::vector<int64_t>& b_end, const std::vect
         it.tb = logn > ddx::kBigLog ? (int64_t)(((w.fwd.size() - fl.i0) % chunk) * per) : 0;
         it.hist_start = c.hist_start;
         it.chan = i;
+        it.logn = logn;
         w.fwd.push_back(it);
         off += (int64_t)per;
       }
@@ -881,6 +930,7 @@ void build_lists(ddx_plan* p, const std::vector<int64_t>& b_end, const std::vect
             u.valid = c.valid;
             u.lead = c.lead;
             u.n_dumps = (int32_t)(last - first);
+            u.fwd = (int32_t)sidx;
             w.units.push_back(u);
             ++cur.nu;
             cur.max_dumps = std::max(cur.max_dumps, u.n_dumps);
@@ -1048,6 +1098,7 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
     const double nn = 1 << fl.logn;
     if (fl.logn <= ddx::kBigLog) {
       fa.items = fwd_dev + fl.i0;
+      fa.l1 = p->l1 ? p->l1 + fl.i0 * p->M * 8 : nullptr;
       HIPCHECK(p, timed(p, s, DDX_K_FORWARD, (double)fl.n * p->M * fft_flops(nn),
                         (double)fl.n * p->M * nn * (in_bytes(p->in_dtype) + 8.0),
                         [&] { return launch_forward(fl.logn, p->in_dtype, fa, (int)fl.n, s); }));
@@ -1059,11 +1110,20 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
         const size_t cnt = std::min(chunk, fl.n - i0);
         const std::vector<ddx::FwdItem>& fv = w.fwd;
         fa.items = fwd_dev + fl.i0 + i0;
+        fa.l1 = p->l1 ? p->l1 + (fl.i0 + i0) * p->M * 8 : nullptr;
         HIPCHECK(p, timed(p, s, DDX_K_FORWARD, (double)cnt * p->M * fft_flops(nn),
                           (double)cnt * p->M * nn * (in_bytes(p->in_dtype) + 8.0),
                           [&] { return launch_forward_big(fl.logn, p->in_dtype, fa, &fv[fl.i0 + i0], (int)cnt, p->tb, s); }));
       }
     }
+  }
+
+  if (p->bound && !w.fwd.empty()) {  // FP32 correlator inputs: each block's bound on |y|
+    HIPCHECK(p, timed(p, s, DDX_K_OTHER, 0.0, (double)w.fwd.size() * p->M * 32.0, [&] {
+      hipLaunchKernelGGL(ddx::k_item_bound, dim3((unsigned)w.fwd.size()), dim3(256), 0, s, (const ddx::FwdItem*)fwd_dev,
+                         (const float*)p->l1, p->M, p->bound);
+      return hipGetLastError();
+    }));
   }
 
   // waves: chirps, dedispersion, correlation.  (A second stream for the correlator,
@@ -1101,6 +1161,7 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
     ca.units = units_dev + wv.u0;
     ca.scale = p->scale_dev;
     ca.power = p->power;
+    ca.bound = p->bound;
     ca.pw_stride = p->pw_stride;
     ca.y_stride = p->y_stride;
     ca.rec_elems = p->rec_elems;

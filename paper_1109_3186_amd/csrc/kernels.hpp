@@ -70,9 +70,9 @@ struct FwdItem {        // one overlap-save block of one channel, all M antennas
   int64_t win0;         // absolute sample index of the block window's first sample
   int64_t spec;         // spectrum of antenna 0 (antenna p at + p N)
   int64_t tb;           // two-pass transforms: intermediate rows of antenna 0 (antenna p at + p N)
-  int64_t hist_start;   // absolute sample index of the channel's history element 0
+  int64_t hist_start;   // absolute index of the channel's history element 0
   int32_t chan;
-  int32_t pad;
+  int32_t logn;         // N = 2^logn
 };
 struct ChirpItem {      // one (channel, DM) of a wave
   int64_t g;            // the channel's g table
@@ -91,6 +91,8 @@ struct UnitItem {       // one (channel, DM, block), all M antennas
   int64_t rec;          // offset of the (channel, DM) slot within a dump record
   int32_t chan, valid, lead;
   int32_t n_dumps;      // complete dumps of the block this call
+  int32_t fwd;          // the block's forward item in this call's list
+  int32_t pad;
 };
 struct ZeroItem {       // the inactive-DM slots of one (channel, dump) record
   int64_t rec;          // offset of the dump's record in the ring
@@ -105,8 +107,38 @@ struct FwdArgs {
   Source src;
   const FwdItem* items;
   float2* spec;
+  float* l1;            // FP32 correlator inputs: per (item, antenna) 8 row sums of |Re X| + |Im X|
   int32_t n_ant;
+  int32_t pad;
 };
+
+// Sum over a workgroup of one value per thread, in a fixed order (butterfly within
+// each wave, then the waves in order); the result is valid in thread 0.  red: NT/64
+// floats of LDS that no thread still reads.
+template <int NT>
+__device__ __forceinline__ float block_sum(float v, float* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if constexpr (NT <= 64) {
+    return v;
+  } else {
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float t = 0.f;
+    if (threadIdx.x == 0)
+      for (int i = 0; i < NT / 64; ++i) t += red[i];
+    return t;
+  }
+}
+
+// sum of |Re| + |Im| of a thread's points, in register order
+template <int P>
+__device__ __forceinline__ float l1_of(const float2* v) {
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < P; ++i) s += fabsf(v[i].x) + fabsf(v[i].y);
+  return s;
+}
 
 template <int LOGN, int IN>
 __global__ __launch_bounds__(Geo<Plan<LOGN>>::T) void k_forward(FwdArgs a) {
@@ -126,6 +158,37 @@ __global__ __launch_bounds__(Geo<Plan<LOGN>>::T) void k_forward(FwdArgs a) {
   for (int u = 0; u < G::P / G::RL; ++u)
 #pragma unroll
     for (int q = 0; q < G::RL; ++q) out[t + u * G::T + q * (G::N / G::RL)] = v[u * G::RL + out_reg<G::RL>(q)];
+  if (a.l1) {  // LDS is free after the last exchange
+    const float tot = block_sum<G::T>(l1_of<G::P>(v), lds);
+    if (t == 0) a.l1[(size_t)blockIdx.x * 8] = tot;  // (item, antenna) = blockIdx.x, row 0 of 8
+  }
+}
+
+// Bound on the dedispersed voltages of each forward item (FP32 correlator inputs):
+// for every DM, |y[n]| <= (1/N) sum_k |X_k H_k| with |H_k| = 1 and |X_k| <=
+// |Re X_k| + |Im X_k|, so bound[item] = (max over antennas of that L1 sum) / N
+// bounds every |Re y|, |Im y| of the block in input units (the stored values carry
+// the channel's scale s on top).  The max does not depend on order; the row sums of
+// a two-pass spectrum are added in row order.  grid: n_items workgroups of 256.
+__global__ __launch_bounds__(256) void k_item_bound(const FwdItem* __restrict__ items, const float* __restrict__ l1,
+                                                    int32_t n_ant, float* __restrict__ bound) {
+  __shared__ float red[256];
+  const FwdItem w = items[blockIdx.x];
+  const int rows = w.logn > 15 ? 1 << (w.logn - 15) : 1;
+  float m = 0.f;
+  for (int p = threadIdx.x; p < n_ant; p += 256) {
+    const float* r = l1 + ((size_t)blockIdx.x * n_ant + p) * 8;
+    float s = 0.f;
+    for (int k = 0; k < rows; ++k) s += r[k];
+    m = fmaxf(m, s);
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bound[blockIdx.x] = red[0] * exp2f(-(float)w.logn);
 }
 
 // ---------------------------------------------------------------------------
@@ -376,8 +439,11 @@ __global__ __launch_bounds__(256) void k_forward_big_pre(FwdArgs a, float2* __re
 }
 
 // Forward 2^15-point FFT of n_rows consecutive rows: dst[r 2^15 + k] from src[r 2^15 + n].
+// Row r is row k1 = r & (R - 1) of (item, antenna) r >> logr, counted from the launch's
+// first item; with l1, the row's sum of |Re X| + |Im X| goes to l1[(r >> logr) 8 + k1].
 // grid: n_rows workgroups.
-__global__ __launch_bounds__(Geo<RowPlan>::T) void k_fft_rows(const float2* __restrict__ src, float2* __restrict__ dst) {
+__global__ __launch_bounds__(Geo<RowPlan>::T) void k_fft_rows(const float2* __restrict__ src, float2* __restrict__ dst,
+                                                              float* __restrict__ l1, int32_t logr) {
   using G = Geo<RowPlan>;
   extern __shared__ float lds[];
   const int t = threadIdx.x;
@@ -389,6 +455,10 @@ __global__ __launch_bounds__(Geo<RowPlan>::T) void k_fft_rows(const float2* __re
   for (int u = 0; u < G::P / G::RL; ++u)
 #pragma unroll
     for (int q = 0; q < G::RL; ++q) out[t + u * G::T + q * (G::N / G::RL)] = v[u * G::RL + out_reg<G::RL>(q)];
+  if (l1) {
+    const float tot = block_sum<G::T>(l1_of<G::P>(v), lds);
+    if (t == 0) l1[(size_t)(blockIdx.x >> logr) * 8 + (blockIdx.x & ((1 << logr) - 1))] = tot;
+  }
 }
 
 // Inverse pass A over a wave of units of one length N = 2^(15 + logr), for the
@@ -535,6 +605,7 @@ struct CorrArgs {
   const UnitItem* units;
   const float* scale;    // [C] correlator-input scales s_c (all formats)
   const float* power;    // binary16 / E4M3 inputs: per-dump power rows (the autocorrelations)
+  const float* bound;    // FP32 inputs: per forward item, a bound on |Re y|, |Im y| (see k_item_bound)
   int64_t y_stride;      // samples per antenna row of y
   int64_t rec_elems;     // complex values per dump record
   int64_t ring_dumps;    // ring capacity in dumps
@@ -551,6 +622,7 @@ struct CorrJob {
   float2* out;       // the (channel, DM) slot of the dump's record
   int32_t chan;
   int32_t dump_off;  // samples from the unit's row start to the dump's first sample
+  float g;           // FP32 inputs: power of two putting the unit's largest |s y| at <= 2^15
 };
 __device__ __forceinline__ bool corr_job(const CorrArgs& a, int item, CorrJob& j) {
   const UnitItem w = a.units[item / a.max_dumps];
@@ -561,6 +633,13 @@ __device__ __forceinline__ bool corr_job(const CorrArgs& a, int item, CorrJob& j
   j.out = a.ring + ((w.dump0 + m) % a.ring_dumps) * a.rec_elems + w.rec;
   j.chan = w.chan;
   j.dump_off = m * a.dump_len;
+  // FP32 inputs: a block whose level grew past the first block's scale is split at
+  // a smaller power of two, so binary16 hi = rn(g s y) cannot overflow
+  j.g = 1.f;
+  if (a.bound) {
+    const float top = a.bound[w.fwd] * a.scale[w.chan];
+    while (top * j.g > 32768.f) j.g *= 0.5f;
+  }
   return true;
 }
 
@@ -599,6 +678,18 @@ __device__ __forceinline__ typename CorrIn<T>::Pair clip_pair(typename CorrIn<T>
     if (!second) v.y = 0u;
   } else {
     if (!second) v &= 0xffffu;
+  }
+  return v;
+}
+
+// FP32 pairs times the unit's range factor g (a power of two: exact); other formats as stored
+template <int T>
+__device__ __forceinline__ typename CorrIn<T>::Pair scale_pair(typename CorrIn<T>::Pair v, float g) {
+  if constexpr (T == 0) {
+    v.x *= g;
+    v.y *= g;
+    v.z *= g;
+    v.w *= g;
   }
   return v;
 }
@@ -694,7 +785,7 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
     const int e = tid + 256 * i;
     if (e < pairs) {
       const int p = e / (kCorrKC / 2), k = 2 * (e % (kCorrKC / 2));
-      store_pair<T, Ld::PLANE>(at, Ld::at(p, k), Ld::at(M + p, k), clip_pair<T>(v, k0 + k + 1 < L));
+      store_pair<T, Ld::PLANE>(at, Ld::at(p, k), Ld::at(M + p, k), scale_pair<T>(clip_pair<T>(v, k0 + k + 1 < L), w.g));
     }
   };
   auto mfma_chunk = [&]() {
@@ -762,7 +853,7 @@ __global__ __launch_bounds__(256) void k_correlate(CorrArgs a) {
     }
   }
   __syncthreads();
-  const float inv = 1.f / (s_in * s_in);  // s is a power of two: exact
+  const float inv = 1.f / (s_in * s_in * w.g * w.g);  // powers of two: exact
   float2* out = w.out;
   if (a.out_mode == 0) {
     for (int b = tid; b < a.nbl; b += 256) {
@@ -882,7 +973,7 @@ __global__ __launch_bounds__(corr_block_threads(BA)) void k_correlate_blocks(Cor
     const int e = tid + NTH * i;
     const int la = e / (kCorrKC / 2), k = 2 * (e % (kCorrKC / 2));
     const int rr = row_re(la), ri = rr + BA;
-    store_pair<T, PLANE>(at, rr * KP + k, ri * KP + k, clip_pair<T>(v, k0 + k + 1 < L));
+    store_pair<T, PLANE>(at, rr * KP + k, ri * KP + k, scale_pair<T>(clip_pair<T>(v, k0 + k + 1 < L), w.g));
   };
   auto frag = [&](int plane, int row, int kr) -> Frag {
     return *reinterpret_cast<const Frag*>(&at[plane * PLANE + row * KP + kr]);
@@ -985,7 +1076,7 @@ __global__ __launch_bounds__(corr_block_threads(BA)) void k_correlate_blocks(Cor
       }
     }
   }
-  const float inv = 1.f / (s_in * s_in);
+  const float inv = 1.f / (s_in * s_in * w.g * w.g);
   float2* out = w.out;
 #pragma unroll
   for (int x = 0; x < RT; ++x)
@@ -1052,6 +1143,39 @@ __global__ __launch_bounds__(64) void k_scale_final(const ScaleItem* items, cons
   for (int p = 0; p < n_ant; ++p) tot += part[(int64_t)blockIdx.x * n_ant + p];
   const double var = tot / (2.0 * n_ant * (double)w.n);
   scale[w.chan] = var > 0 ? (float)exp2(rint(log2((double)target / sqrt(var)))) : 1.f;
+}
+
+// Top-k selection of the learned proposal: mask[d] = 1 for the k largest scores
+// (ties to the lower index; NaN below every number), or 1 for every d when more
+// than k scores exceed `thr` (the fallback); flag[0] = the number above `thr`.
+// One workgroup of 1024 threads; scores staged in LDS (n <= 16384).
+constexpr int kTopkMax = 16384;
+__global__ __launch_bounds__(1024) void k_topk_mask(const float* __restrict__ scores, int32_t n, int32_t k,
+                                                    float thr, uint8_t* __restrict__ mask, int32_t* __restrict__ flag) {
+  __shared__ float s[kTopkMax];
+  __shared__ int above;
+  if (threadIdx.x == 0) above = 0;
+  for (int d = threadIdx.x; d < n; d += 1024) {
+    const float v = scores[d];
+    s[d] = v != v ? -INFINITY : v;
+  }
+  __syncthreads();
+  int cnt = 0;
+  for (int d = threadIdx.x; d < n; d += 1024) {
+    const float v = s[d];
+    int rank = 0;  // scores ahead of d: larger, or equal at a lower index
+    for (int e = 0; e < n; ++e) {
+      const float w = s[e];
+      rank += (w > v) || (w == v && e < d);
+    }
+    mask[d] = rank < k ? 1 : 0;
+    cnt += (scores[d] > thr) ? 1 : 0;  // NaN never counts
+  }
+  atomicAdd(&above, cnt);  // integer sum: the order does not matter
+  __syncthreads();
+  if (above > k)
+    for (int d = threadIdx.x; d < n; d += 1024) mask[d] = 1;
+  if (threadIdx.x == 0) flag[0] = above;
 }
 
 // Zero the record slots of inactive DMs for the dumps of one call.

@@ -3,11 +3,11 @@ tile, and run coherent dedispersion + correlation only on the best-ranked ones.
 
 Steps (all on the GPU through the C ABI): the power tile of the whole stream
 (`ddx_power_tile`, the incoherent dedispersion of power beams), the network's
-score of every DM row (`ddx_cnn_forward`), then the active-DM mask of the plan
-(`ddx_set_active_dms`) restricted to the ceil(budget D) best rows.  Fallback to
-the full sweep: when more rows than the budget score above the decision
-threshold (probability > threshold), the proposal cannot keep all candidates
-and the plan runs every DM.  Ranking happens on the host over D scores.
+score of every DM row (`ddx_cnn_forward`), then the device top-k of the
+scores sets the plan's active DMs (`ddx_select_active_dms`) to the ceil(budget
+D) best rows.  Fallback to the full sweep: when more rows than the budget score
+above the decision threshold (probability > threshold), the proposal cannot keep
+all candidates and the plan runs every DM.
 """
 import math
 
@@ -56,17 +56,15 @@ class Proposal:
         self.scores = None
 
     def select(self, volts, stream=None):
-        """Score the stream's DM rows; returns (mask uint8 [D], scores [D], fallback)."""
+        """Score the stream's DM rows and set the plan's active DMs (the library
+        synchronises `stream` before returning); returns (mask uint8 [D] on the host,
+        scores [D] on the device, fallback)."""
         self.tile = self.plan.power_tile(volts, self.bin_len, self.n_bins, out=self.tile, stream=stream)
         self.scores = self.net.forward(self.tile[None], scores=self.scores, stream=stream)
-        s = self.scores.cpu().numpy().astype(np.float64)
-        mask = np.zeros(self.n_dm, dtype=np.uint8)
-        mask[np.argsort(-s, kind="stable")[:self.k]] = 1
-        prob = 1.0 / (1.0 + np.exp(-s))
-        fallback = int(np.sum(prob > self.threshold)) > self.k
-        if fallback:
-            mask[:] = 1
-        return mask, s, fallback
+        logit = math.log(self.threshold / (1.0 - self.threshold))
+        self.mask, fallback = self.plan.select_active_dms(self.scores, self.k, logit, mask_out=getattr(self, "mask", None),
+                                                          stream=stream)
+        return self.mask.cpu().numpy(), self.scores, fallback
 
     def close(self):
         self.net.close()

@@ -40,9 +40,12 @@ def sample_pulses(rng, n_samples, fc, f_s, dm_max, snr_range, width, n_pulses):
     return out
 
 
-def power_batch(p, n_tiles, fine, rng, gen, device, pulse_frac=0.5, snr_range=(5.0, 50.0), max_pulses=3):
+def power_batch(p, n_tiles, fine, rng, gen, device, pulse_frac=0.5, snr_range=(5.0, 50.0), max_pulses=3,
+                pulses_given=None):
     """Fine-bin beam power [n_tiles, C, U] (torch float32 on `device`), DM labels
-    [n_tiles, D] and the pulse lists, for workload parameters p (see c1_params)."""
+    [n_tiles, D] and the pulse lists, for workload parameters p (see c1_params).
+    pulses_given: optional list (one per tile) of pulse lists (dm, n0, snr, width)
+    to inject instead of random ones."""
     import torch
 
     m_ant, n_chan, s, f_s = p["m_ant"], p["n_chan"], p["samples"], p["f_s"]
@@ -58,8 +61,11 @@ def power_batch(p, n_tiles, fine, rng, gen, device, pulse_frac=0.5, snr_range=(5
     grid = torch.arange(units + 1, device=device, dtype=torch.float64)
     pulses = []
     for t in range(n_tiles):
-        npul = 0 if rng.random() < (1.0 - pulse_frac) else int(rng.integers(1, max_pulses + 1))
-        pl = sample_pulses(rng, s, fc, f_s, p["dm_max"], snr_range, p["width"], npul)
+        if pulses_given is not None:
+            pl = pulses_given[t]
+        else:
+            npul = 0 if rng.random() < (1.0 - pulse_frac) else int(rng.integers(1, max_pulses + 1))
+            pl = sample_pulses(rng, s, fc, f_s, p["dm_max"], snr_range, p["width"], npul)
         pulses.append(pl)
         for q in pl:
             energy = m_ant * math.sqrt(q["width"]) * q["snr"] * var

@@ -220,6 +220,44 @@ def c3_params():
             "radius_m": 2500.0, "seed": 1112}
 
 
+def pulse_channels_device(pl, fc, f_s, f_ref, pos, noise_power, device, k_dm=K_DM_SKY, chan_ids=None):
+    """One pulse as received in every channel of fc by every antenna, on a torch
+    device in float64: the model of dispersed_segment_device (cold-plasma response
+    minus its constant phase, whole-sample shift plus fractional ramp, geometric
+    delays at the full sky frequency) with one segment length for all channels.
+    The waveform of row c comes from PCG64(wave_seed + chan_ids[c]) (chan_ids:
+    the channels' indices in their stream, default 0, 1, ...).
+    Returns (offsets [C] int, seg complex128 tensor [C, M, Nseg]): segment c is
+    added to the stream of channel c from sample n0 + offsets[c]."""
+    import torch
+
+    fc = np.asarray(fc, dtype=np.float64)
+    w, dm = pl["width"], pl["dm"]
+    delays = (pos[:, 0] * pl["lm"][0] + pos[:, 1] * pl["lm"][1]) / C_LIGHT
+    gmax = float(np.max(np.abs(delays))) * f_s
+    early, late = _smear(fc, f_s, dm, k_dm)
+    centre = k_dm * dm * (1.0 / (fc * fc) - 1.0 / (f_ref * f_ref)) * f_s
+    ishift = np.floor(centre).astype(np.int64)
+    frac = centre - ishift
+    pad = np.ceil(early + gmax).astype(np.int64) + 256
+    span = pad + w + np.ceil(late + gmax + 1.0).astype(np.int64) + 256
+    nseg = 1 << int(math.ceil(math.log2(2 * int(span.max()))))
+    buf = np.zeros((len(fc), nseg), dtype=np.complex128)
+    ids = range(len(fc)) if chan_ids is None else chan_ids
+    for c, cid in enumerate(ids):
+        wrng = np.random.Generator(np.random.PCG64(pl["wave_seed"] + int(cid)))
+        buf[c, pad[c]:pad[c] + w] = pulse_wave(wrng, w, pl["snr"], noise_power)
+    spec = torch.fft.fft(torch.from_numpy(buf).to(device), dim=-1)
+    f = torch.from_numpy(np.fft.fftfreq(nseg, 1.0 / f_s)).to(device)[None, :]
+    fct = torch.from_numpy(fc).to(device)[:, None]
+    # K DM (1/nu - 1/f_c + f/f_c^2) written without the cancelling terms
+    cyc = k_dm * dm * (f / (fct * fct) - f / (fct * (fct + f))) - f * torch.from_numpy(frac / f_s).to(device)[:, None]
+    ph = cyc[:, None, :] - (fct + f)[:, None, :] * torch.from_numpy(np.asarray(delays, np.float64)).to(device)[None, :, None]
+    ph = torch.remainder(ph, 1.0) * (2.0 * math.pi)
+    seg = torch.fft.ifft(spec[:, None, :] * torch.polar(torch.ones_like(ph), ph), dim=-1)
+    return ishift - pad, seg
+
+
 def make_stream_device(p, device, chans=None):
     """Build the complex-int8 stream [C, M, 2S] of workload ``p`` on a torch device.
 
@@ -246,26 +284,32 @@ def make_stream_device(p, device, chans=None):
         n0 = int(rng.integers(lo, max(hi, lo + 1)))
         pulses.append({"dm": dm, "n0": n0, "width": p["width"], "snr": p["snr"], "lm": (l, mm),
                        "wave_seed": int(rng.integers(0, 2 ** 31))})
-    chans = range(n_chan) if chans is None else chans
+    chans = list(range(n_chan) if chans is None else chans)
     out = torch.empty((len(chans), m_ant, 2 * s), dtype=torch.int8, device=device)
+    re = torch.empty((len(chans), m_ant, s), dtype=torch.float32, device=device)
+    im = torch.empty_like(re)
     for ci, c in enumerate(chans):
         g = torch.Generator(device=device)
         g.manual_seed(p["seed"] * 1000 + int(c))
-        re = torch.randn((m_ant, s), generator=g, device=device, dtype=torch.float32) * p["sigma"]
-        im = torch.randn((m_ant, s), generator=g, device=device, dtype=torch.float32) * p["sigma"]
-        for pl in pulses:
-            wrng = np.random.Generator(np.random.PCG64(pl["wave_seed"] + int(c)))
-            wave = pulse_wave(wrng, pl["width"], pl["snr"], power)
-            delays = (pos[:, 0] * pl["lm"][0] + pos[:, 1] * pl["lm"][1]) / C_LIGHT
-            off, seg = dispersed_segment_device(wave, fc[c], f_s, pl["dm"], f_ref, delays, device)
-            a = pl["n0"] + off
-            lo, hi = max(a, 0), min(a + seg.shape[-1], s)
-            if hi > lo:
-                part = seg[:, lo - a:hi - a]
-                re[:, lo:hi] += part.real.to(torch.float32)
-                im[:, lo:hi] += part.imag.to(torch.float32)
+        re[ci] = torch.randn((m_ant, s), generator=g, device=device, dtype=torch.float32) * p["sigma"]
+        im[ci] = torch.randn((m_ant, s), generator=g, device=device, dtype=torch.float32) * p["sigma"]
+    # channels in groups small enough that one group's segments stay near 1 GiB
+    group = max(1, 1024 // m_ant)
+    for pl in pulses:
+        for g0 in range(0, len(chans), group):
+            sub = chans[g0:g0 + group]
+            off, seg = pulse_channels_device(dict(pl, snr=p["snr"]), fc[sub], f_s, f_ref, pos, power, device,
+                                             chan_ids=sub)
+            for k in range(len(sub)):
+                ci = g0 + k
+                a = pl["n0"] + int(off[k])
+                lo, hi = max(a, 0), min(a + seg.shape[-1], s)
+                if hi > lo:
+                    part = seg[k, :, lo - a:hi - a]
+                    re[ci, :, lo:hi] += part.real.to(torch.float32)
+                    im[ci, :, lo:hi] += part.imag.to(torch.float32)
             del seg
-        out[ci, :, 0::2] = torch.clamp(torch.round(re), -127, 127).to(torch.int8)
-        out[ci, :, 1::2] = torch.clamp(torch.round(im), -127, 127).to(torch.int8)
-        del re, im
+    out[..., 0::2] = torch.clamp(torch.round(re), -127, 127).to(torch.int8)
+    out[..., 1::2] = torch.clamp(torch.round(im), -127, 127).to(torch.int8)
+    del re, im
     return out, pulses, fc, pos

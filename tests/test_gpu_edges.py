@@ -157,3 +157,41 @@ def test_device_side_statuses(gpu):
         with pytest.raises(DdxError) as e:
             p.set_dm_trials(cfg["dm_lists"][0])
         assert e.value.status == ddx.ENOMEM
+
+
+def test_f32_split_range_follows_level_changes(gpu):
+    """FP32 correlator inputs whose level rises 10^4 times after the first block window
+    (which set the scale), plus one sample at 10^5 sigma: the binary16 split of each
+    unit is ranged from its own largest value, so nothing overflows.  Dumps of blocks
+    whose windows hold one level stay within 1e-5 (normalised) of the FP64 oracle;
+    dumps of the blocks whose windows straddle the 80 dB step carry the FP32
+    transform's error at that dynamic range (a single-precision FFT emulation of the
+    oracle gives up to 9e-5 there), held to 1e-3."""
+    import oracle
+    from gpu_helpers import blockings
+    cfg = synth.make_small(seed=71, m_ant=4, n_chan=2, s=40000, f_lo=1.25e9, f_s=1e6, n_dm=3, dm_max=300.0,
+                           dump_len=500, n_pulses=0)
+    step = 12000
+    x = cfg["volts"].astype(np.complex128)
+    x[..., step:] *= 1e4
+    x[1, 2, 30001] = (1e5 / np.sqrt(2)) * (1 + 1j)
+    cfg = dict(cfg, volts=x.astype(np.complex64))
+    vis, lay = run_gpu(cfg)
+    assert np.all(np.isfinite(vis))
+    bl = blockings(lay)
+    iu, ju = np.triu_indices(4)
+    clean = mixed = 0.0
+    for c in range(2):
+        ref = oracle.run_oracle(cfg["volts"], cfg["chan_freqs"], 1e6, cfg["dm_lists"], 500, bl, chans=[c])
+        v_, n_, lead = bl[c]["valid"], bl[c]["fft_len"], bl[c]["lead"]
+        blk = np.arange(vis.shape[0]) * 500 // v_          # block of each dump
+        straddle = (blk * v_ - lead <= step) & (step < blk * v_ - lead + n_)
+        for (cc, d), v in ref.items():
+            auto = v[:, iu == ju].real
+            e = (np.abs(select(vis, lay, cc, d).astype(np.complex128) - v) / np.sqrt(auto[:, iu] * auto[:, ju])).max(1)
+            clean = max(clean, float(e[~straddle].max()))
+            mixed = max(mixed, float(e[straddle].max()))
+    say("level step 1e4 and a 1e5 sigma sample: max normalised error %.3e (one-level blocks), %.3e (blocks across "
+        "the step); scales %s" % (clean, mixed, lay["scale"]))
+    assert clean <= 1e-5
+    assert mixed <= 1e-3

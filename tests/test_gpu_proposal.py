@@ -190,10 +190,12 @@ def _recall(scores, pulses, k, dstep):
 
 
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained weights (run python -m paper_1109_3186_amd.train_proposal)")
-def test_trained_network_recall_and_gain(gpu):
-    """Recall at the top 10% of DM rows on held-out tiles (S/N 5-50): the trained
-    network against the untrained one and against the method without a network
-    (rank rows by their maximum standardised tile value)."""
+@pytest.mark.parametrize("snr", [(5.0, 50.0), (5.0, 10.0)])
+def test_trained_network_recall_and_gain(gpu, snr):
+    """Recall at the top 10% of DM rows on held-out tiles: the trained network against
+    the untrained one and against the method without a network (rank rows by their
+    maximum standardised tile value), over the training S/N range and at S/N 5-10,
+    where the row maximum is weakest."""
     import torch
 
     from paper_1109_3186_amd import Cnn
@@ -201,9 +203,9 @@ def test_trained_network_recall_and_gain(gpu):
     from paper_1109_3186_amd.train_proposal import he_init, make_plan
     p = synth.c1_params()
     plan = make_plan(p)
-    rng = np.random.Generator(np.random.PCG64(9001))
+    rng = np.random.Generator(np.random.PCG64(9001 if snr[1] > 10 else 9002))
     gen = torch.Generator(device=gpu)
-    gen.manual_seed(9001)
+    gen.manual_seed(9001 if snr[1] > 10 else 9002)
     nets = {"trained": load_weights(WEIGHTS), "untrained": he_init(1114)}
     k = int(math.ceil(0.1 * p["n_dm"]))
     res = {n: [] for n in list(nets) + ["rowmax"]}
@@ -213,7 +215,8 @@ def test_trained_network_recall_and_gain(gpu):
         cnns[name] = Cnn(p["n_dm"], 1024, 8)
         cnns[name].set_weights(w)
     for b in range(50):
-        power, labels, pulses = synth.power_batch(p, 8, 32, rng, gen, gpu, pulse_frac=1.0, max_pulses=1)
+        power, labels, pulses = synth.power_batch(p, 8, 32, rng, gen, gpu, pulse_frac=1.0, max_pulses=1,
+                                                  snr_range=snr)
         tiles = plan.tiles_from_power(power, 32, 1024, 1024)
         for name, net in cnns.items():
             res[name].append(net.forward(tiles).cpu().numpy().reshape(8, -1))
@@ -224,11 +227,46 @@ def test_trained_network_recall_and_gain(gpu):
     for name in res:
         sc = np.concatenate(res[name])
         out[name] = _recall(sc, allpulses, k, p["dm_max"] / p["n_dm"])
-    say("recall at top %d of %d rows over %d pulses: %s" % (k, p["n_dm"], out["trained"][1],
-                                                             {n: round(v[0], 4) for n, v in out.items()}))
-    assert out["trained"][0] >= 0.99
-    assert out["trained"][0] >= out["untrained"][0] + 0.2
+    say("S/N %s: recall at top %d of %d rows over %d pulses: %s" % (snr, k, p["n_dm"], out["trained"][1],
+                                                                    {n: round(v[0], 4) for n, v in out.items()}))
+    if snr[1] > 10:
+        assert out["trained"][0] >= 0.99
+        assert out["trained"][0] >= out["untrained"][0] + 0.2
     assert out["trained"][0] >= out["rowmax"][0]
     for n in cnns.values():
         n.close()
     plan.close()
+
+
+def test_device_topk_selection(gpu):
+    """ddx_select_active_dms: the k best logits (ties to the lower DM, NaN last) become
+    the plan's active DMs, as a stable descending sort of the same FP32 values gives;
+    more than k logits above the threshold switch every DM on (fallback)."""
+    import torch
+
+    from paper_1109_3186_amd import Plan
+    fc = synth.chan_freqs(1.2e9, 2, 1e6)
+    rng = np.random.Generator(np.random.PCG64(49))
+    n = 256
+    with Plan(2, fc, 1e6, 1000, max_block_samples=1 << 15, compact_records=True, max_record_pairs=2 * n) as p:
+        p.set_dm_trials(synth.dm_grid(n, 2000.0))
+        for trial in range(3):
+            s = rng.standard_normal(n).astype(np.float32) - 3.0
+            s[rng.integers(0, n, 20)] = np.float32(-1.25)      # ties
+            s[rng.integers(0, n, 3)] = np.nan
+            k = int(rng.integers(1, 40))
+            mask, fb = p.select_active_dms(torch.from_numpy(s).to(gpu), k, logit_threshold=0.0)
+            key = np.where(np.isnan(s), -np.inf, s)
+            ref = np.zeros(n, np.uint8)
+            ref[np.argsort(-key, kind="stable")[:k]] = 1
+            assert not fb and np.array_equal(mask.cpu().numpy(), ref), trial
+            lay = p.layout()
+            for c in range(2):
+                active = lay["record_pos"][lay["dm_offset"][c]:lay["dm_offset"][c + 1]] >= 0
+                assert np.array_equal(active, ref.astype(bool))
+        s = np.full(n, -5.0, np.float32)
+        s[:30] = 1.0                                            # 30 above the threshold
+        mask, fb = p.select_active_dms(torch.from_numpy(s).to(gpu), 26, logit_threshold=0.0)
+        assert fb and mask.cpu().numpy().all()
+        mask, fb = p.select_active_dms(torch.from_numpy(s).to(gpu), 30, logit_threshold=0.0)
+        assert not fb and mask.cpu().numpy().sum() == 30
