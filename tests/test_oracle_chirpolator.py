@@ -163,3 +163,10 @@ def test_coherence_loss_falls_with_the_block_length():
     x = np.exp(2j * np.pi * a * np.arange(L) ** 2)
     v = ch.block_partial_dft(x, L, L, [0])[0, 0]
     assert abs(abs(v) / L - ch.coherence_loss(a, L)) < 1e-12
+
+
+def test_pair_bin_budgets_hand_example():
+    """A 3-4-5 triangle: baselines 3, 4 and 5 (pairs (0,1), (0,2), (1,2)), k_max 10:
+    budgets ceil(10 b / 5) = 6, 8, 10."""
+    pos = np.array([[0.0, 0.0], [3.0, 0.0], [0.0, 4.0]])
+    assert list(ch.pair_bin_budgets(pos, 10)) == [6, 8, 10]

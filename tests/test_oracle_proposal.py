@@ -1,4 +1,6 @@
 """Pins of the proposal oracle (tiles, CNN forward/backward, Adam) on the CPU."""
+import math
+
 import numpy as np
 import pytest
 
@@ -138,3 +140,27 @@ def test_adam_matches_library_over_several_steps():
         tw.grad = torch.tensor(g, dtype=torch.float64)
         opt.step()
         np.testing.assert_allclose(params["w"], tw.detach().numpy(), rtol=0, atol=1e-13)
+
+
+def test_standardise_and_row_triples_brute_force():
+    """standardise: zero mean, unit (population) deviation over the whole tile, checked
+    on a hand example; rows3: row d's input is rows d-1, d, d+1 with the edge rows
+    repeated, checked element by element."""
+    t = np.array([[1.0, 3.0], [5.0, 7.0]])      # mean 4, population sd sqrt(5)
+    np.testing.assert_allclose(P.standardise(t), (t - 4.0) / math.sqrt(5.0), rtol=0, atol=1e-15)
+    z = np.arange(12.0).reshape(4, 3)
+    r = P.rows3(z)
+    for d in range(4):
+        for j, dd in enumerate((max(d - 1, 0), d, min(d + 1, 3))):
+            assert np.array_equal(r[d, j], z[dd])
+
+
+def test_pack_upper_brute_force():
+    import oracle
+    m = 5
+    v = np.arange(m * m).reshape(m, m) + 1j
+    got = oracle.pack_upper(v)
+    want = [v[i, j] for i in range(m) for j in range(i, m)]
+    assert np.array_equal(got, want)
+    assert all(oracle.packed_index(i, j, m) == k for k, (i, j) in
+               enumerate((i, j) for i in range(m) for j in range(i, m)))
