@@ -132,3 +132,132 @@ def grid_blocks_cells(s, L, cells, n_cells):
             x = s[p, :nb * L] * np.conj(s[q, :nb * L])
             G[:, l - 1] += x.reshape(nb, L).sum(axis=1) / (len(prs) * L)
     return G
+
+
+# ---- App. B "Spectral smearing": the trajectory widened by 2F bins -------------------
+
+
+def tone_amplitude(x, M, n_s):
+    """S(x) = sin(pi (M - 1) x / N_s) / sin(pi x / N_s) (S(0) = M - 1): with Phi(x) the
+    response Y_k = Phi(x) S(x) of the spacings l = 1 .. M - 1 to a spatial tone at
+    k0 = k + x (the geometric sum written out)."""
+    x = np.asarray(x, dtype=np.float64)
+    num = np.sin(np.pi * (M - 1) * x / n_s)
+    den = np.sin(np.pi * x / n_s)
+    safe = np.where(np.abs(den) < 1e-300, 1.0, den)
+    return np.where(np.abs(den) < 1e-300, float(M - 1), num / safe)
+
+
+def trajectory_widened(Y, M, n_s, k_end, t_blocks, m0, L, F):
+    """App. B, spectral smearing: at every step the 2F + 1 bins around the trajectory,
+    k_m + t (t = -F .. F, k_m = rint(k0)), each weighted by the matched filter of the
+    spatial tone, conj(Phi(x_t)) S(x_t) / (M - 1) with x_t = k0 - (k_m + t) (the
+    reading of the Chirpolator's 2F + 1 taps, Sec. 3.4, on the spatial DFT).  At an
+    integer k0 the F = 0 weight is 1, as in Eq. chimg_pth."""
+    Y = np.asarray(Y)
+    total = 0j
+    for m in range(m0, m0 + t_blocks):
+        k0 = k_end * ((m - m0) * L + (L - 1) / 2.0) / (t_blocks * L)
+        kr = np.rint(k0)
+        for t in range(-F, F + 1):
+            x = k0 - (kr + t)
+            w = np.conj(phase(x, M, n_s)) * tone_amplitude(x, M, n_s) / (M - 1)
+            total += w * Y[m, int(kr + t) % n_s]
+    return total
+
+
+# ---- App. B "Sampling": per-trajectory integration ------------------------------------
+
+
+def sampling_blocks(k_end, t_blocks, kappa_t0):
+    """Blocks per integrated sample of a trajectory: it is sampled kappa_t =
+    max(1, |k_end| kappa_t0) times over its duration (the oversampling proportional to
+    the end bin, App. B; at least once), i.e. every t_blocks / kappa_t blocks, taken as
+    max(1, floor(t_blocks / kappa_t)) whole blocks."""
+    kappa_t = max(1.0, abs(k_end) * kappa_t0)
+    return max(1, int(np.floor(t_blocks / kappa_t)))
+
+
+def trajectory_sampled(Y, M, n_s, k_end, t_blocks, m0, L, a):
+    """App. B, sampling: the spatial spectra integrated over a blocks (Y'_k[j] =
+    sum_{r < a} Y_k[m0 + j a + r], the integrate-and-dump of Eq. Yk), then the
+    phase-corrected trajectory over the floor(t_blocks / a) integrated samples, each
+    at the mean time of its a L samples.  a = 1 is `trajectory`."""
+    Y = np.asarray(Y)
+    total = 0j
+    for j in range(t_blocks // a):
+        k0 = k_end * (j * a * L + (a * L - 1) / 2.0) / (t_blocks * L)
+        kr = np.rint(k0)
+        k = int(kr) % n_s
+        ysum = sum(Y[m0 + j * a + r, k] for r in range(a))
+        total += np.conj(phase(k0 - kr, M, n_s)) * ysum
+    return total
+
+
+# ---- Sec. 4 step 4 and App. B gridding: a two-dimensional array ------------------------
+
+
+def nearest_cells_2d(pos, spacing):
+    """Gridding of a planar array (Sec. 4: an arbitrary array interpolated onto a
+    regular grid): pair p < q goes to cell c = rint((r_q - r_p) / spacing) per axis
+    (ties to even).  Only one half plane is kept, cu > 0 or (cu = 0 and cv > 0) (the
+    other half holds the conjugate products); a pair whose cell falls in the other
+    half is stored the other way round, (q, p), in cell -c.  Cells (0, 0) are dropped.
+    Returns {(cu, cv): [(p, q), ...]} with the pairs in row-major order of p < q."""
+    pos = np.asarray(pos, dtype=np.float64)
+    cells = {}
+    for p in range(pos.shape[0]):
+        for q in range(p + 1, pos.shape[0]):
+            cu, cv = (int(v) for v in np.rint((pos[q] - pos[p]) / spacing))
+            a, b = p, q
+            if cu < 0 or (cu == 0 and cv < 0):
+                cu, cv, a, b = -cu, -cv, q, p
+            if (cu, cv) != (0, 0):
+                cells.setdefault((cu, cv), []).append((a, b))
+    return cells
+
+
+def grid_blocks_2d(s, L, cells, n_s):
+    """G[m][cu][cv mod N_s] = 1 / (count_c L) sum_{(a, b) in cell c} sum_{n in block m}
+    s_a[n] s_b[n]^* (natural weights over the pairs in a cell) on an N_s x N_s grid, the
+    cells' coordinates taken modulo N_s (as the spatial DFT sees them)."""
+    s = np.asarray(s, dtype=np.complex128)
+    nb = s.shape[1] // L
+    G = np.zeros((nb, n_s, n_s), dtype=np.complex128)
+    for (cu, cv), prs in cells.items():
+        for a, b in prs:
+            x = s[a, :nb * L] * np.conj(s[b, :nb * L])
+            G[:, cu % n_s, cv % n_s] += x.reshape(nb, L).sum(axis=1) / (len(prs) * L)
+    return G
+
+
+def spatial_dft_2d(G, n_s):
+    """Y[m][ku][kv] = sum_{cu, cv} G[m][cu][cv] exp(-2 pi i (ku cu + kv cv) / N_s),
+    as two one-dimensional DFT matrices."""
+    G = np.asarray(G, dtype=np.complex128)
+    k = np.arange(n_s)
+    W = np.exp(-2j * np.pi * ((np.outer(k, k) % n_s) / n_s))
+    return np.einsum("uc,mcd,vd->muv", W, G, W)
+
+
+def response_2d(cells, xu, xv, n_s):
+    """R(x) = sum over the occupied cells c of exp(2 pi i (xu cu + xv cv) / N_s): the
+    spatial DFT of a unit tone of one cycle per N_s / k0 cells, read at bin k0 - x."""
+    return sum(np.exp(2j * np.pi * (xu * cu + xv * cv) / n_s) for (cu, cv) in cells)
+
+
+def trajectory_2d(Y, cells, n_s, k_end, t_blocks, m0, L):
+    """Eq. chimg_pth on the planar grid: at step m the trajectory's bin is k0 = k_end
+    (m - m0 + ...) / T per axis (k_end = (ku, kv) the end bins), the image bin is
+    rint(k0) mod N_s per axis, and the phase correction is that of the occupied cells'
+    tone response, conj(R(x)) / |R(x)| (for a uniform line, conj(Phi(x)))."""
+    Y = np.asarray(Y)
+    total = 0j
+    for m in range(m0, m0 + t_blocks):
+        f = ((m - m0) * L + (L - 1) / 2.0) / (t_blocks * L)
+        k0u, k0v = k_end[0] * f, k_end[1] * f
+        ru, rv = np.rint(k0u), np.rint(k0v)
+        R = response_2d(cells, k0u - ru, k0v - rv, n_s)
+        w = np.conj(R) / abs(R) if abs(R) > 0 else 0.0
+        total += w * Y[m, int(ru) % n_s, int(rv) % n_s]
+    return total
