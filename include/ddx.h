@@ -578,6 +578,68 @@ int ddx_chimg_gradient_sums(const void* d_y, int64_t n_blocks, int32_t n_ant, in
                             const double* d_grad, int32_t n_grad, const int32_t* d_lengths, int32_t n_len, void* d_p,
                             void* hip_stream);
 
+/* App. B's sampling rule: a trajectory ending at bin k_end after t_blocks blocks is
+ * sampled kappa_t = max(1, |k_end| kappa_t0) times (the oversampling proportional to
+ * the end bin; at least once); returns the whole blocks per integrated sample,
+ * max(1, floor(t_blocks / kappa_t)) (host, FP64), or DDX_EINVAL (t_blocks < 1,
+ * kappa_t0 < 0 or not finite). */
+int ddx_chimg_sampling_blocks(double k_end, int32_t t_blocks, double kappa_t0);
+
+/* App. B's widened and sampled trajectories (spectral smearing, sampling): for
+ * trials i (end bin k_end[i], duration t_blocks[i] blocks, a_i = d_a_blocks[i] blocks
+ * per integrated sample, or 1 for all when d_a_blocks is NULL), from every start
+ * block m0, over the J = floor(T / a) integrated samples j (the block average of
+ * sample j stands at its mean sample, k0 = k_end (j a L + (a L - 1) / 2) / (T L), k_j
+ * = rint(k0) in FP64, ties to even):
+ *   half_width F = 0:  P = sum_j conj(Phi(x_j)) Y'_{k_j}[j]  (Eq. chimg_pth),
+ *   F >= 1:            P = sum_j sum_{t=-F..F} conj(Phi(x)) S(x) / (M - 1) Y'_{k_j+t}[j],
+ *                      x = k0 - (k_j + t), S(x) = sin(pi (M - 1) x / N_s) / sin(pi x / N_s)
+ *                      (the matched filter of a spatial tone over 2F + 1 bins),
+ * with Y'_k[j] = sum_{r < a} Y_k[m0 + j a + r] and bins taken mod N_s; zero where m0 +
+ * T > n_blocks.  Buffers as ddx_chimg_trajectories; d_a_blocks: DEVICE int32
+ * [n_trials] or NULL.  DDX_EINVAL for invalid sizes, NULL buffers or F > 16. */
+int ddx_chimg_trajectories_ext(const void* d_y, int64_t n_blocks, int32_t n_ant, int32_t n_s, int32_t block_len,
+                               const double* d_k_end, const int32_t* d_t_blocks, const int32_t* d_a_blocks,
+                               int32_t half_width, int32_t n_trials, void* d_p, void* hip_stream);
+
+/* Gridding of a planar array (Sec. 4 step 4; App. B's gridding): pair p < q goes to
+ * the cell c = rint((r_q - r_p) / spacing) per axis (ties to even); cells are kept in
+ * one half plane, cu > 0 or (cu = 0, cv > 0), a pair whose offset falls in the other
+ * half being stored turned round, (q, p) in cell -c; the cell (0, 0) is dropped.
+ * HOST arrays: positions [n_ant][2] (x, y) (2 <= n_ant <= 64), cell_ptr [max_cells +
+ * 1], cell_pairs [2 x n_ant (n_ant - 1) / 2] as (a, b) int32 pairs (the product s_a
+ * s_b^*), cell_uv [2 x max_cells] as (cu, cv).  Cells ascend in (cu, cv); each cell's
+ * pairs keep the row-major order of p < q.  *n_cells, *n_pairs: the cells and pairs
+ * written.  DDX_ESIZE if more than max_cells cells, DDX_EINVAL otherwise. */
+int ddx_chimg_cells_2d(int32_t n_ant, const double* positions, double spacing, int32_t max_cells, int32_t* n_cells,
+                       int32_t* cell_ptr, int32_t* cell_pairs, int32_t* cell_uv, int32_t* n_pairs);
+
+/* Planar pre-integrator: per complete block m of L samples, the cells' natural-weight
+ * averages G_c[m] = 1 / (count_c L) sum_{(a, b) in c} sum_{n in block m} s_a[n]
+ * s_b[n]^*, then the 2-D spatial DFT
+ *   Y[ku N_s + kv][m] = sum_c G_c[m] exp(-2 pi i (ku cu + kv cv) / N_s),  ku, kv < N_s.
+ * Cell tables as written by ddx_chimg_cells_2d, on the DEVICE.  d_y: DEVICE [N_s^2]
+ * [floor(n / L)] complex64.  2 <= n_ant <= 64, N_s a power of two <= 256, n_cells <=
+ * 1024; DDX_EINVAL otherwise. */
+int ddx_chimg_preintegrate_2d(const void* d_volts, int32_t n_ant, int64_t n, int32_t block_len, int32_t n_s,
+                              int32_t n_cells, const int32_t* d_cell_ptr, const int32_t* d_cell_pairs,
+                              const int32_t* d_cell_uv, void* d_y, void* hip_stream);
+
+/* Planar trajectories (Eq. chimg_pth on the plane): for trials i with end bins
+ * d_k_end[2 i], d_k_end[2 i + 1] (double) and durations t_blocks[i] <= max_t, from every
+ * start block m0:
+ *   P[i][m0] = sum_{q < T} conj(R(x_q)) / |R(x_q)| Y[bu N_s + bv][m0 + q],
+ *   k0 = k_end f per axis, f = (q L + (L - 1) / 2) / (T L), (bu, bv) = rint(k0) mod N_s
+ *   (FP64, ties to even), x_q = k0 - rint(k0), R(x) = sum over the occupied cells of
+ *   exp(2 pi i (xu cu + xv cv) / N_s) (the cells' response to a unit tone);
+ * zero where m0 + T > n_blocks.  d_table_bins (int32) and d_table_w (complex64)
+ * [n_trials][max_t]: DEVICE workspace for the step tables (written, then read).
+ * DDX_EINVAL for invalid sizes or NULL buffers; a trial with T > max_t gives zeros. */
+int ddx_chimg_trajectories_2d(const void* d_y, int64_t n_blocks, int32_t n_s, int32_t block_len, int32_t n_cells,
+                              const int32_t* d_cell_uv, const double* d_k_end, const int32_t* d_t_blocks,
+                              int32_t n_trials, int32_t max_t, int32_t* d_table_bins, void* d_table_w, void* d_p,
+                              void* hip_stream);
+
 /* Synchronise the plan's last stream and free plan-owned memory.  NULL is a no-op. */
 int ddx_plan_destroy(ddx_plan* plan);
 

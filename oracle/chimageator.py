@@ -148,21 +148,22 @@ def tone_amplitude(x, M, n_s):
     return np.where(np.abs(den) < 1e-300, float(M - 1), num / safe)
 
 
-def trajectory_widened(Y, M, n_s, k_end, t_blocks, m0, L, F):
+def trajectory_widened(Y, M, n_s, k_end, t_blocks, m0, L, F, a=1):
     """App. B, spectral smearing: at every step the 2F + 1 bins around the trajectory,
     k_m + t (t = -F .. F, k_m = rint(k0)), each weighted by the matched filter of the
     spatial tone, conj(Phi(x_t)) S(x_t) / (M - 1) with x_t = k0 - (k_m + t) (the
     reading of the Chirpolator's 2F + 1 taps, Sec. 3.4, on the spatial DFT).  At an
-    integer k0 the F = 0 weight is 1, as in Eq. chimg_pth."""
+    integer k0 the F = 0 weight is 1, as in Eq. chimg_pth.  a > 1: the steps are the
+    integrated samples of App. B's sampling, as in `trajectory_sampled`."""
     Y = np.asarray(Y)
     total = 0j
-    for m in range(m0, m0 + t_blocks):
-        k0 = k_end * ((m - m0) * L + (L - 1) / 2.0) / (t_blocks * L)
+    for j in range(t_blocks // a):
+        k0 = k_end * (j * a * L + (a * L - 1) / 2.0) / (t_blocks * L)
         kr = np.rint(k0)
         for t in range(-F, F + 1):
             x = k0 - (kr + t)
             w = np.conj(phase(x, M, n_s)) * tone_amplitude(x, M, n_s) / (M - 1)
-            total += w * Y[m, int(kr + t) % n_s]
+            total += w * sum(Y[m0 + j * a + r, int(kr + t) % n_s] for r in range(a))
     return total
 
 

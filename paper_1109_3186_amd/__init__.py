@@ -9,6 +9,7 @@ from .binding import (  # noqa: F401
     Plan, Cnn, Chirp, ChirpBank, Image, incoherent_delays, power_beam, incoherent_dedisperse, tree_dedisperse,
     tree_dedisperse_static, TREE_STATIC_MAX,
     chimg_preintegrate, chimg_trajectories, chimg_gradient_sums, chimg_cells, chimg_preintegrate_cells,
+    chimg_sampling_blocks, chimg_trajectories_ext, chimg_cells_2d, chimg_preintegrate_2d, chimg_trajectories_2d,
     DdxError, lib, LIB_PATH, SIGNATURES,
     OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ESIZE, EFULL, EUNSUPPORTED,
     IN_CI8, IN_CF32, CORR_F32, CORR_F16, CORR_E4M3, OUT_PACKED, OUT_FULL, FLUSH,

@@ -124,6 +124,18 @@ SIGNATURES = {
                                    ct.c_int64, ct.c_void_p], ct.c_int),
     "ddx_tree_dedisperse": ([ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p], ct.c_int),
     "ddx_tree_dedisperse_static": ([ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_void_p, ct.c_void_p], ct.c_int),
+    "ddx_chimg_sampling_blocks": ([ct.c_double, ct.c_int32, ct.c_double], ct.c_int),
+    "ddx_chimg_trajectories_ext": ([ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p,
+                                    ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p],
+                                   ct.c_int),
+    "ddx_chimg_cells_2d": ([ct.c_int32, ct.POINTER(ct.c_double), ct.c_double, ct.c_int32, ct.POINTER(ct.c_int32),
+                            ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32),
+                            ct.POINTER(ct.c_int32)], ct.c_int),
+    "ddx_chimg_preintegrate_2d": ([ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32,
+                                   ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p], ct.c_int),
+    "ddx_chimg_trajectories_2d": ([ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p,
+                                   ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p,
+                                   ct.c_void_p, ct.c_void_p], ct.c_int),
     "ddx_chimg_preintegrate": ([ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p,
                                 ct.c_void_p], ct.c_int),
     "ddx_chimg_trajectories": ([ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p,
@@ -813,3 +825,92 @@ def chimg_preintegrate_cells(volts, block_len, n_s, cell_ptr, cell_pairs, stream
     if rc != OK:
         raise DdxError(rc, "ddx_chimg_preintegrate_cells")
     return y
+
+
+def chimg_sampling_blocks(k_end, t_blocks, kappa_t0):
+    """Blocks per integrated sample of a trajectory (ddx_chimg_sampling_blocks)."""
+    r = lib().ddx_chimg_sampling_blocks(float(k_end), int(t_blocks), float(kappa_t0))
+    if r < 0:
+        raise DdxError(r, "ddx_chimg_sampling_blocks")
+    return r
+
+
+def chimg_trajectories_ext(y, n_ant, block_len, k_end, t_blocks, a_blocks=None, half_width=0, stream=None):
+    """Widened (2F + 1 bins, F = half_width) and sampled (a_blocks per integrated
+    sample) trajectory sums P [trials, blocks] (complex64, device) over y [n_s, blocks]."""
+    import torch
+    if y.dtype != torch.complex64 or y.dim() != 2:
+        raise DdxError(EINVAL, "y must be complex64 [n_s, blocks]")
+    y = y.contiguous()
+    ke = torch.as_tensor(np.asarray(k_end, dtype=np.float64), device=y.device)
+    tb = torch.as_tensor(np.asarray(t_blocks, dtype=np.int32), device=y.device)
+    ab = None if a_blocks is None else torch.as_tensor(np.asarray(a_blocks, dtype=np.int32), device=y.device)
+    p = torch.empty((ke.numel(), y.shape[1]), dtype=torch.complex64, device=y.device)
+    rc = lib().ddx_chimg_trajectories_ext(ct.c_void_p(y.data_ptr()), y.shape[1], int(n_ant), y.shape[0],
+                                          int(block_len), ct.c_void_p(ke.data_ptr()), ct.c_void_p(tb.data_ptr()),
+                                          None if ab is None else ct.c_void_p(ab.data_ptr()), int(half_width),
+                                          ke.numel(), ct.c_void_p(p.data_ptr()), _stream_handle(stream))
+    if rc != OK:
+        raise DdxError(rc, "ddx_chimg_trajectories_ext")
+    return p
+
+
+def chimg_cells_2d(positions, spacing, max_cells=1024):
+    """Planar gridding tables (ddx_chimg_cells_2d): (cell_ptr, cell_pairs [pairs, 2],
+    cell_uv [cells, 2]) as int32 numpy arrays."""
+    pos = np.ascontiguousarray(positions, dtype=np.float64)
+    m = pos.shape[0]
+    ptr = np.zeros(max_cells + 1, dtype=np.int32)
+    pairs = np.zeros(max(m * (m - 1), 2), dtype=np.int32)
+    uv = np.zeros(2 * max_cells, dtype=np.int32)
+    nc, npairs = ct.c_int32(0), ct.c_int32(0)
+    rc = lib().ddx_chimg_cells_2d(m, pos.ctypes.data_as(ct.POINTER(ct.c_double)), float(spacing), int(max_cells),
+                                  ct.byref(nc), ptr.ctypes.data_as(ct.POINTER(ct.c_int32)),
+                                  pairs.ctypes.data_as(ct.POINTER(ct.c_int32)),
+                                  uv.ctypes.data_as(ct.POINTER(ct.c_int32)), ct.byref(npairs))
+    if rc != OK:
+        raise DdxError(rc, "ddx_chimg_cells_2d")
+    return ptr[:nc.value + 1].copy(), pairs[:2 * npairs.value].reshape(-1, 2).copy(), uv[:2 * nc.value].reshape(-1,
+                                                                                                             2).copy()
+
+
+def chimg_preintegrate_2d(volts, block_len, n_s, cells, stream=None):
+    """Planar pre-integrator: volts device complex64 [M, n], cells from chimg_cells_2d;
+    returns device complex64 Y [n_s * n_s, n // block_len] (bin ku n_s + kv)."""
+    import torch
+    if volts.dtype != torch.complex64 or volts.dim() != 2:
+        raise DdxError(EINVAL, "volts must be complex64 [M, n]")
+    volts = volts.contiguous()
+    M, n = volts.shape
+    ptr, pairs, uv = (torch.as_tensor(np.ascontiguousarray(a), device=volts.device) for a in cells)
+    y = torch.empty((n_s * n_s, n // block_len), dtype=torch.complex64, device=volts.device)
+    rc = lib().ddx_chimg_preintegrate_2d(ct.c_void_p(volts.data_ptr()), M, n, int(block_len), int(n_s),
+                                         uv.shape[0], ct.c_void_p(ptr.data_ptr()), ct.c_void_p(pairs.data_ptr()),
+                                         ct.c_void_p(uv.data_ptr()), ct.c_void_p(y.data_ptr()), _stream_handle(stream))
+    if rc != OK:
+        raise DdxError(rc, "ddx_chimg_preintegrate_2d")
+    return y
+
+
+def chimg_trajectories_2d(y, n_s, block_len, cell_uv, k_end, t_blocks, stream=None):
+    """Planar trajectory sums P [trials, blocks] (complex64, device) over the planar
+    pre-integrator's y; k_end [trials, 2] end bins (ku, kv)."""
+    import torch
+    if y.dtype != torch.complex64 or y.dim() != 2 or y.shape[0] != n_s * n_s:
+        raise DdxError(EINVAL, "y must be complex64 [n_s * n_s, blocks]")
+    y = y.contiguous()
+    ke = torch.as_tensor(np.ascontiguousarray(k_end, dtype=np.float64).reshape(-1, 2), device=y.device)
+    tbn = np.asarray(t_blocks, dtype=np.int32)
+    tb = torch.as_tensor(tbn, device=y.device)
+    uv = torch.as_tensor(np.ascontiguousarray(cell_uv, dtype=np.int32), device=y.device)
+    max_t = int(tbn.max())
+    bins = torch.empty((tbn.size, max_t), dtype=torch.int32, device=y.device)
+    w = torch.empty((tbn.size, max_t), dtype=torch.complex64, device=y.device)
+    p = torch.empty((tbn.size, y.shape[1]), dtype=torch.complex64, device=y.device)
+    rc = lib().ddx_chimg_trajectories_2d(ct.c_void_p(y.data_ptr()), y.shape[1], int(n_s), int(block_len),
+                                         uv.shape[0], ct.c_void_p(uv.data_ptr()), ct.c_void_p(ke.data_ptr()),
+                                         ct.c_void_p(tb.data_ptr()), tbn.size, max_t, ct.c_void_p(bins.data_ptr()),
+                                         ct.c_void_p(w.data_ptr()), ct.c_void_p(p.data_ptr()), _stream_handle(stream))
+    if rc != OK:
+        raise DdxError(rc, "ddx_chimg_trajectories_2d")
+    return p

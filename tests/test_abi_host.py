@@ -19,7 +19,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "dd
 def _declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(ddx_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(ddx_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -290,3 +290,21 @@ def test_chimageator_cells_match_the_oracle():
         assert got == ref.get(l, []), l
     with pytest.raises(binding.DdxError):
         binding.chimg_cells([0.0, 5.0, 3.0], 1.0, 4)      # not ascending
+
+
+def test_planar_cells_and_sampling_rule_on_the_host():
+    """ddx_chimg_cells_2d and ddx_chimg_sampling_blocks are host code: against the
+    oracle's nearest cells (half plane, turned pairs, cell order) and its sampling rule."""
+    from oracle import chimageator as ocg
+    rng = np.random.Generator(np.random.PCG64(870))
+    for m, jitter in [(7, 0.0), (30, 9.0)]:
+        pos = rng.integers(0, 9, (m, 2)) * 30.0 + rng.uniform(-jitter, jitter, (m, 2))
+        ptr, pairs, uv = ddx.chimg_cells_2d(pos, 30.0)
+        got = {(int(uv[c, 0]), int(uv[c, 1])): [tuple(int(v) for v in pairs[b]) for b in range(ptr[c], ptr[c + 1])]
+               for c in range(uv.shape[0])}
+        ref = ocg.nearest_cells_2d(pos, 30.0)
+        assert got == ref and [tuple(r) for r in uv] == sorted(ref)
+    with pytest.raises(ddx.DdxError):
+        ddx.chimg_cells_2d(rng.uniform(0, 1000, (20, 2)), 1.0, max_cells=10)
+    for args in [(9.0, 240, 5.0), (0.0, 240, 5.0), (100.0, 240, 5.0), (-3.3, 77, 2.5)]:
+        assert ddx.chimg_sampling_blocks(*args) == ocg.sampling_blocks(*args)

@@ -300,3 +300,14 @@ def test_planar_trajectory_finds_a_chirp():
         assert abs(cg.trajectory_2d(Y, cells, n_s, k_end + np.array(dk), tb, m0, L)) < best
     for dt, dm in ((6, 0), (-6, 0), (0, 2), (0, -2)):
         assert abs(cg.trajectory_2d(Y, cells, n_s, k_end, tb + dt, m0 + dm, L)) < best
+
+
+def test_widened_and_sampled_together_is_widening_the_integrated_blocks():
+    """The widened sum over integrated samples equals the widened sum run on blocks
+    integrated beforehand (the coarse blocks being a L samples long)."""
+    rng = _rng(36)
+    M, n_s, L, a, tb, m0 = 10, 32, 4, 3, 21, 5
+    Y = rng.normal(size=(40, n_s)) + 1j * rng.normal(size=(40, n_s))
+    coarse = np.stack([Y[m0 + j * a:m0 + (j + 1) * a].sum(axis=0) for j in range(tb // a)])
+    ref = cg.trajectory_widened(coarse, M, n_s, 7.7, tb // a, 0, a * L, 2)
+    assert abs(cg.trajectory_widened(Y, M, n_s, 7.7, tb, m0, L, 2, a=a) - ref) < 1e-10
