@@ -10,7 +10,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libddx.so")
+# DDX_LIB_PATH selects another build of the same library (the host-sanitizer
+# build of the host-side checks); by default the in-tree libddx.so.
+LIB_PATH = os.environ.get("DDX_LIB_PATH") or os.path.join(HERE, "libddx.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ESIZE, EFULL, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 IN_CI8, IN_CF32 = 0, 1
@@ -159,7 +161,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError("libddx.so not built: run __graft_entry__.build() (or python -m paper_1109_3186_amd.build)")
+            raise RuntimeError("%s not built: run __graft_entry__.build() (or python -m paper_1109_3186_amd.build)" % LIB_PATH)
         L = ct.CDLL(LIB_PATH)
         for name, (args, res) in SIGNATURES.items():
             f = getattr(L, name)
