@@ -252,7 +252,11 @@ int blocking(ddx_plan* p, Chan& c, int fft_req) {
 // ---- kernel dispatch over template parameters ------------------------------------------
 
 template <int LOGN>
-size_t fft_lds_bytes() { return sizeof(float) * ddx::Geo<ddx::Plan<LOGN>>::LDS_FLOATS; }
+size_t fft_lds_bytes() {
+  static_assert(LOGN != 15 || ddx::Geo<ddx::Plan15Wide>::LDS_TOTAL == ddx::Geo<ddx::Plan<15>>::LDS_TOTAL,
+                "both 32768-point plans take the same LDS");
+  return sizeof(float) * ddx::Geo<ddx::Plan<LOGN>>::LDS_TOTAL;
+}
 
 template <int LOGN>
 hipError_t launch_forward_n(int in_dtype, const ddx::FwdArgs& a, int n_items, hipStream_t s) {

@@ -9,6 +9,9 @@
 // (j / NS) NS R + k + q NS.  Between passes the points travel through LDS, real
 // parts then imaginary parts, so that N = 32768 fits the 160 KB of one CU.
 //
+// A launch provides Geo<PL>::LDS_TOTAL floats of dynamic LDS: the exchange area and,
+// for the larger plans, the second pass's twiddle table after it.
+//
 // Load pattern of the first pass and store pattern of the last pass are both
 // "point (t + u T) + r N / R", i.e. coalesced across threads (held in register
 // u R + in_reg(r) before a pass's DFT, u R + out_reg(q) after it), and the output
@@ -117,8 +120,11 @@ template <> struct Plan<9> : PlanDef<9, 16, 3, 16, 16, 2> {};
 template <> struct Plan<10> : PlanDef<10, 16, 3, 16, 16, 4> {};
 template <> struct Plan<11> : PlanDef<11, 16, 3, 16, 16, 8> {};
 template <> struct Plan<12> : PlanDef<12, 16, 3, 16, 16, 16> {};
-template <> struct Plan<13> : PlanDef<13, 16, 4, 16, 16, 16, 2> {};
-template <> struct Plan<14> : PlanDef<14, 16, 4, 16, 16, 16, 4> {};
+// 2^13 and 2^14 as three passes of 32 points per thread (256 and 512 threads):
+// measured 7-10 % faster per point than four passes of 16 (two or more
+// workgroups share a CU either way).
+template <> struct Plan<13> : PlanDef<13, 32, 3, 32, 32, 8> {};
+template <> struct Plan<14> : PlanDef<14, 32, 3, 32, 32, 16> {};
 template <> struct Plan<15> : PlanDef<15, 64, 3, 32, 32, 32> {};
 // 32768 points over 1024 threads of 32 points: four waves per SIMD at 128 VGPRs
 // instead of two at ~205, for kernels whose register use allows it.
@@ -133,6 +139,12 @@ template <class PL> struct Geo {
   static constexpr int RL = PL::R[NP - 1];
   // LDS floats for one half-exchange (one pad word per 32 against bank conflicts)
   static constexpr int LDS_FLOATS = N + N / 32;
+  // Twiddles of the second pass (stride R0, radix R1) from a table in LDS when it
+  // costs at most two entries per thread to fill: TAB[r][k] = exp(S 2 pi i r k /
+  // (R0 R1)), r < R1, k < R0, placed after the exchange area.
+  static constexpr bool TABLE = NP >= 2 && PL::R[0] * PL::R[1] <= 2 * T;
+  static constexpr int TAB_FLOATS = TABLE ? 2 * PL::R[0] * PL::R[1] : 0;
+  static constexpr int LDS_TOTAL = LDS_FLOATS + TAB_FLOATS;  // floats a launch must provide
 };
 
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 5); }
@@ -261,6 +273,41 @@ __device__ __forceinline__ void pass(float2* v, int t) {
   }
 }
 
+// Fill the second pass's twiddle table (Geo::TABLE): entry r NS + k, NS = R0, is
+// exp(S 2 pi i r k / (NS R)) from its exactly reduced angle, so every twiddle of
+// that pass carries one rounding of the transcendental unit instead of up to four
+// from products.  Made visible by the first exchange's barrier.
+template <class PL, int S>
+__device__ __forceinline__ void fill_twiddle_table(float* lds, int t) {
+  using G = Geo<PL>;
+  constexpr int NS = PL::R[0], R = PL::R[1], E = NS * R;
+  float2* tab = reinterpret_cast<float2*>(lds + G::LDS_FLOATS);
+#pragma unroll
+  for (int e = 0; e < (E + G::T - 1) / G::T; ++e) {
+    const int i = t + e * G::T;
+    if (E % G::T == 0 || i < E) tab[i] = twiddle<ilog2(E), S>((i / NS) * (i % NS));
+  }
+}
+
+// The second pass with its twiddles read from the table (stride NS = R0).
+template <class PL, int R, int NS, int S>
+__device__ __forceinline__ void pass_table(float2* v, const float* lds, int t) {
+  using G = Geo<PL>;
+  const float2* tab = reinterpret_cast<const float2*>(lds + G::LDS_FLOATS);
+  int z = 0;
+#pragma unroll
+  for (int u = 0; u < G::P / R; ++u) {
+    const float2* row = tab + ((t + z + u * G::T) & (NS - 1));
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[u * R + in_reg<R>(r)] = cmul(v[u * R + in_reg<R>(r)], row[r * NS]);
+    dft_reg<R, S>(v + u * R);
+    if (u + 1 < G::P / R) {
+      pin_regs<R>(v + u * R);
+      z = opaque_zero(v[u * R].x);
+    }
+  }
+}
+
 // Passes 1.. of the transform (pass 0 is done by the caller, fused with its loads).
 template <class PL, int S, int PASS, int NS>
 struct Passes {
@@ -268,7 +315,8 @@ struct Passes {
     constexpr int RP = PL::R[PASS - 1];
     constexpr int R = PL::R[PASS];
     exchange<PL, RP, NS / RP, R>(v, lds, t);
-    pass<PL, R, NS, S>(v, t);
+    if constexpr (PASS == 1 && Geo<PL>::TABLE) pass_table<PL, R, NS, S>(v, lds, t);
+    else pass<PL, R, NS, S>(v, t);
     if constexpr (PASS + 1 < PL::NP) Passes<PL, S, PASS + 1, NS * R>::run(v, lds, t);
   }
 };
@@ -279,6 +327,7 @@ struct Passes {
 template <class PL, int S, class Load>
 __device__ __forceinline__ void fft_workgroup(float2* v, float* lds, int t, Load load) {
   using G = Geo<PL>;
+  if constexpr (G::TABLE) fill_twiddle_table<PL, S>(lds, t);
   int z = 0;
 #pragma unroll
   for (int u = 0; u < G::P / G::R0; ++u) {

@@ -293,12 +293,12 @@ __device__ __forceinline__ void store_ranged(__amdgpu_buffer_rsrc_t r, unsigned 
   }
 }
 
-// FFT plan of k_dedisperse: the 1024-thread form of the 32768-point plan for the
-// binary16 and E4M3 outputs (their VALU work gains from the extra waves: 2293 ->
-// 2077 ms per 36-antenna E4M3 step), the 512-thread form for FP32 output, which
-// measured no faster with it.
+// FFT plan of k_dedisperse: the 1024-thread form of the 32768-point plan (four
+// waves per SIMD instead of two hide more of the loads and exchanges: 2.41 against
+// 2.61 ps per transform point for the FP32 output, measured with the second pass's
+// twiddles from LDS; E4M3 2293 -> 2077 ms per 36-antenna step).
 template <int LOGN, int OUT>
-using DedispPlan = typename std::conditional<LOGN == 15 && OUT != 0, Plan15Wide, Plan<LOGN>>::type;
+using DedispPlan = typename std::conditional<LOGN == 15, Plan15Wide, Plan<LOGN>>::type;
 
 // Chirp multiply, inverse FFT and overlap-save discard for a wave of units.
 // grid: order_units(n_units, tile) x M workgroups (see unit_row).
