@@ -110,7 +110,8 @@ def cpu_baseline(chunks, fc, dms, lay, p, per_thread):
     import oracle
     threads, avail, model = host_cpu()
     x = np.concatenate([c[0].cpu().numpy() for c in chunks], axis=-1)[None]
-    bl = [{"fft_len": int(lay["fft_len"][0]), "valid": int(lay["valid"][0]), "lead": int(lay["lead"][0])}]
+    from paper_1109_3186_amd import layout_blockings
+    bl = layout_blockings(lay)[:1]
     n_dm = min(len(dms), threads * per_thread)
     ds = [int(v) for v in np.linspace(0, len(dms) - 1, n_dm).round()]
     parts = [ds[i::threads] for i in range(threads)]
@@ -797,8 +798,8 @@ def error_table(kept, host, fc, dms, lay, p):
     from threadpoolctl import threadpool_limits
 
     import oracle
-    bl = [{"fft_len": int(lay["fft_len"][c]), "valid": int(lay["valid"][c]), "lead": int(lay["lead"][c])}
-          for c in range(lay["n_chan"])]
+    from paper_1109_3186_amd import layout_blockings
+    bl = layout_blockings(lay)
     iu, ju = np.triu_indices(p["m_ant"])
 
     def one(cd):

@@ -90,6 +90,9 @@ typedef struct ddx_desc {
   int32_t compact_records;     /* 0: every (channel, DM) in every record; 1: only the active ones */
   int32_t max_record_pairs;    /* compact records: capacity in (channel, DM) pairs, 0 = all */
   int64_t ring_dumps;          /* device dump ring capacity in dumps, 0 = enough for any call */
+  /* Blocking (see ddx_set_dm_trials): */
+  int32_t dm_classes;          /* 0: each channel's DMs in classes by the cost model; 1: one class per channel */
+  int32_t pad;
 } ddx_desc;
 
 /* Scale rule when chan_scale is NULL (all correlator formats; the scale keeps
@@ -107,9 +110,9 @@ typedef struct ddx_layout {
   int32_t n_ant, n_chan, n_baselines, dump_len, out_mode, corr_dtype, in_dtype, sideband;
   double samp_rate_hz, k_dm;
   const double* chan_freq_hz;  /* [C] */
-  const int32_t* fft_len;      /* [C] N_c */
-  const int32_t* valid;        /* [C] V_c: outputs kept per block, a multiple of L */
-  const int32_t* lead;         /* [C] block b reads samples [b V_c - lead_c, b V_c - lead_c + N_c) */
+  const int32_t* fft_len;      /* [C] N_c of the class holding the channel's largest DM */
+  const int32_t* valid;        /* [C] V_c of that class: outputs kept per block, a multiple of L */
+  const int32_t* lead;         /* [C] lead_c of that class (the scale rule's window is [0, N_c - lead_c)) */
   const int32_t* n_dm;         /* [C] D_c trial DMs */
   const int64_t* dm_offset;    /* [C+1] prefix sums of D_c: index of (c, d) in the per-DM tables */
   const double* dm;            /* [dm_offset[C]] trial DMs, channel-major */
@@ -134,6 +137,12 @@ typedef struct ddx_layout {
    * (see ddx_dump_times). */
   double dump_t0_s;            /* (L - 1) / (2 f_s): the mean time of dump 0's samples */
   double dump_period_s;        /* L / f_s */
+  /* Blocking of every (channel, DM): that of its class (see ddx_set_dm_trials). */
+  const int32_t* dm_fft_len;   /* [dm_offset[C]] N */
+  const int32_t* dm_valid;     /* [dm_offset[C]] V, a multiple of L */
+  const int32_t* dm_lead;      /* [dm_offset[C]] lead: block b reads samples [b V - lead, b V - lead + N) */
+  int32_t n_classes;           /* blocking classes over all channels */
+  int32_t pad2;
 } ddx_layout;
 
 /* Create a plan from a descriptor (copied; the caller's arrays may be freed).
@@ -144,17 +153,37 @@ int ddx_plan_create(const ddx_desc* desc, ddx_plan** out);
 /* Set the trial DMs of one channel (chan >= 0) or of all (chan = -1): n_dm >= 1
  * finite values >= 0 in any order and spacing (uniform, or the geometric banks
  * of Appendix A.4, Eq. Ti).  When every channel has its list, fixes the
- * blocking of each channel from the largest DM:
- *   - half-overlap A_c = ceil(max intra-channel smear) in samples, where the top
- *     edge f_c + f_s/2 arrives K DM (f_c^-2 - (f_c + f_s/2)^-2) before the
- *     centre and the bottom edge K DM ((f_c - f_s/2)^-2 - f_c^-2) after it
- *     (Eq. dmdelay);
- *   - N_c = the descriptor's FFT length, or the smallest power of two >= 256
- *     keeping at least half of each block (N_c <= 2^18);
- *   - V_c = L floor((N_c - 2 A_c) / L), lead_c = floor((N_c - V_c)/2);
+ * overlap-save blocking (the paper fixes none; Sec. 2.3.2 only asks for the
+ * convolution with the inverse of the medium's response):
+ *   - the half overlap a DM needs, A(DM) = ceil(max intra-channel smear) in
+ *     samples, where the top edge f_c + f_s/2 arrives K DM (f_c^-2 - (f_c +
+ *     f_s/2)^-2) before the centre and the bottom edge K DM ((f_c - f_s/2)^-2 -
+ *     f_c^-2) after it (Eq. dmdelay);
+ *   - a class of DMs shares one blocking, that of its largest DM: FFT length N,
+ *     V = L floor((N - 2 A) / L) outputs kept per block, lead = floor((N - V)/2);
+ *   - with the descriptor's FFT length for the channel, or dm_classes = 1, all
+ *     of the channel's DMs form one class, with that length or else the smallest
+ *     power of two >= 256 keeping at least half of each block;
+ *   - otherwise the channel's DMs, sorted, are cut into classes at multiples of
+ *     16 DMs, choosing the cuts and each class's N (2^8 .. 2^18) to minimise a
+ *     model of device time per output sample, sum over classes of (n_dm t_inv(N)
+ *     + t_fwd(N)) N / V, with t_inv and t_fwd the measured times per transform
+ *     point of the inverse (per DM) and forward (per block) transforms.  Low DMs
+ *     then run shorter transforms with less overlap.  Every (channel, DM)'s
+ *     blocking is exported by ddx_get_layout; the visibilities of a DM depend only
+ *     on its own blocking;
  * builds the FP64 tables and allocates device memory.  Returns ESTATE after the
- * first ddx_process_block, EUNSUPPORTED for N_c > 2^18, EINVAL if V_c < L. */
+ * first ddx_process_block, EUNSUPPORTED for N > 2^18, EINVAL if V < L. */
 int ddx_set_dm_trials(ddx_plan* plan, int32_t chan, const double* dm_pc_cm3, int32_t n_dm);
+
+/* The blocking ddx_set_dm_trials chooses for channel chan of a descriptor, computed
+ * on the host alone (no plan, no device): for each of the n_dm DMs (HOST array,
+ * rules as for ddx_set_dm_trials) the FFT length, kept outputs and lead of its
+ * class, written to caller HOST arrays of n_dm entries.  Returns the number of
+ * classes (>= 1), or EINVAL (bad descriptor or arguments, V < L) / EUNSUPPORTED
+ * (N > 2^18) as ddx_set_dm_trials would. */
+int ddx_plan_blocking(const ddx_desc* desc, int32_t chan, const double* dm_pc_cm3, int32_t n_dm, int32_t* fft_len,
+                      int32_t* valid, int32_t* lead);
 
 /* Restrict dedispersion and correlation of channel chan (-1 = all) to the DMs
  * with mask[d] != 0 (mask has D_c entries; NULL = all active).  Blocking is
@@ -207,10 +236,11 @@ int ddx_dump_times(const ddx_plan* plan, int32_t chan, int32_t dm_index, int64_t
  * work they complete on hip_stream (asynchronous).
  *   d_volts: DEVICE pointer, layout [C][M][n] samples of in_dtype, owned by the
  *            caller and valid until the stream has passed this work.
- * Block b of channel c covers output samples [b V_c, (b+1) V_c) and reads input
- * [b V_c - lead_c, b V_c - lead_c + N_c); samples before 0 are zero.  A block
- * runs once its whole input window has arrived, so results do not depend on
- * how the stream is split into calls.  flags & DDX_FLUSH zero-pads after the
+ * Block b of a class (the blocking N, V, lead of its DMs, ddx_set_dm_trials)
+ * covers output samples [b V, (b+1) V) and reads input [b V - lead, b V - lead
+ * + N); samples before 0 are zero.  A block runs once its whole input window has
+ * arrived, and no block of a channel runs before its scale window [0, N_c -
+ * lead_c) has, so results do not depend on how the stream is split into calls.  flags & DDX_FLUSH zero-pads after the
  * last sample, runs the remaining blocks and ends the stream (later calls:
  * ESTATE).  Per block and active DM d:
  *   X = DFT_N(x_b) (unnormalised, exp(-2 pi i k n / N));
@@ -223,12 +253,12 @@ int ddx_dump_times(const ddx_plan* plan, int32_t chan, int32_t dm_index, int64_t
  * A trailing partial dump is dropped.
  *
  * Schedule: one call lists its work for all channels at once and copies the
- * lists to the device: the (channel, block) items of the forward transforms
- * (one launch per transform length), and the units (channel, active DM, block)
- * in the order channel, DM group, block, DM.  Units are cut into waves of
- * wave_units (a wave holds one transform length); each wave is one chirp launch,
- * one dedispersion launch (two for N_c > 2^15) and one correlator launch over
- * all its units' dumps, whatever channels and DMs they belong to.
+ * lists to the device: the (class, block) items of the forward transforms (one
+ * launch per transform length), and the units (class, active DM, block) in the
+ * order transform length, class, DM group, block, DM.  Units are cut into waves
+ * of wave_units (a wave holds one transform length); each wave is one chirp
+ * launch, one dedispersion launch (two for N > 2^15) and one correlator launch
+ * over all its units' dumps, whatever channels and DMs they belong to.
  *
  * Errors: EINVAL (n < 0, n >
  * max_block_samples, NULL volts with n > 0), ESTATE (no DM trials, stream

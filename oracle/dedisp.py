@@ -182,7 +182,8 @@ def run_oracle(volts, chan_freqs, f_s, dm_lists, dump_len, blockings, sideband=1
 
     volts: [C, M, S] complex (or [C, M, 2S] interleaved int8).
     dm_lists[c]: trial DMs of channel c.  blockings[c]: dict with fft_len,
-    valid and lead (the plan's blocking).  quant: None, "e4m3" or "f16" to
+    valid and lead (the plan's blocking), or a list of such dicts, one per DM
+    of the channel (each DM filtered with its own blocking).  quant: None, "e4m3" or "f16" to
     emulate the reduced-precision correlator inputs with per-channel scale
     scales[c]: the cross products V_ij (i != j) are those of the rounded
     voltages quantize(y s) / s^2, while the autocorrelations V_ii keep the
@@ -201,8 +202,9 @@ def run_oracle(volts, chan_freqs, f_s, dm_lists, dump_len, blockings, sideband=1
         dms = dm_lists[c]
         ds = range(len(dms)) if dm_index is None else dm_index
         for d in ds:
-            h = chirp(chan_freqs[c], f_s, bl["fft_len"], dms[d], sideband, k_dm)
-            y = dedisperse_stream(x, h, bl["fft_len"], bl["valid"], bl["lead"])
+            b = bl[d] if isinstance(bl, (list, tuple)) else bl
+            h = chirp(chan_freqs[c], f_s, b["fft_len"], dms[d], sideband, k_dm)
+            y = dedisperse_stream(x, h, b["fft_len"], b["valid"], b["lead"])
             v = correlate_dumps(y, dump_len)
             if quant is not None:
                 # cross products from the rounded inputs; the autocorrelations

@@ -6,7 +6,7 @@ ctypes binding (binding.py).  There is no CPU fallback: without the built
 library every call raises.
 """
 from .binding import (  # noqa: F401
-    Plan, Cnn, Chirp, ChirpBank, Image, incoherent_delays, power_beam, incoherent_dedisperse, tree_dedisperse,
+    Plan, plan_blocking, layout_blockings, Cnn, Chirp, ChirpBank, Image, incoherent_delays, power_beam, incoherent_dedisperse, tree_dedisperse,
     tree_dedisperse_static, TREE_STATIC_MAX,
     chimg_preintegrate, chimg_trajectories, chimg_gradient_sums, chimg_cells, chimg_preintegrate_cells,
     chimg_sampling_blocks, chimg_trajectories_ext, chimg_cells_2d, chimg_preintegrate_2d, chimg_trajectories_2d,

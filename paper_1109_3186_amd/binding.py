@@ -34,6 +34,7 @@ class Desc(ct.Structure):
         ("out_mode", ct.c_int32), ("chan_scale", ct.POINTER(ct.c_float)),
         ("wave_units", ct.c_int32), ("dm_group", ct.c_int32), ("compact_records", ct.c_int32),
         ("max_record_pairs", ct.c_int32), ("ring_dumps", ct.c_int64),
+        ("dm_classes", ct.c_int32), ("pad", ct.c_int32),
     ]
 
 
@@ -51,6 +52,8 @@ class Layout(ct.Structure):
         ("dumps_fetched", ct.c_int64), ("ring_dumps", ct.c_int64), ("device_bytes", ct.c_size_t),
         ("wave_units", ct.c_int32), ("dm_group", ct.c_int32), ("compact_records", ct.c_int32), ("pad", ct.c_int32),
         ("dump_t0_s", ct.c_double), ("dump_period_s", ct.c_double),
+        ("dm_fft_len", ct.POINTER(ct.c_int32)), ("dm_valid", ct.POINTER(ct.c_int32)),
+        ("dm_lead", ct.POINTER(ct.c_int32)), ("n_classes", ct.c_int32), ("pad2", ct.c_int32),
     ]
 
 
@@ -68,6 +71,8 @@ SIGNATURES = {
     "ddx_plan_create": ([ct.POINTER(Desc), ct.POINTER(ct.c_void_p)], ct.c_int),
     "ddx_set_dm_trials": ([ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_double), ct.c_int32], ct.c_int),
     "ddx_set_active_dms": ([ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_uint8)], ct.c_int),
+    "ddx_plan_blocking": ([ct.POINTER(Desc), ct.c_int32, ct.POINTER(ct.c_double), ct.c_int32,
+                           ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)], ct.c_int),
     "ddx_get_layout": ([ct.c_void_p, ct.POINTER(Layout)], ct.c_int),
     "ddx_select_active_dms": ([ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_int32, ct.c_float, ct.c_void_p,
                                ct.POINTER(ct.c_int32), ct.c_void_p], ct.c_int),
@@ -191,7 +196,8 @@ class Plan:
 
     def __init__(self, n_ant, chan_freqs, samp_rate, dump_len, max_block_samples, *, sideband=1, in_dtype="ci8",
                  corr_dtype="f32", fft_len=None, k_dm=0.0, max_device_bytes=0, out_mode="packed", chan_scale=None,
-                 wave_units=0, dm_group=0, compact_records=False, max_record_pairs=0, ring_dumps=0):
+                 wave_units=0, dm_group=0, compact_records=False, max_record_pairs=0, ring_dumps=0,
+                 dm_classes="auto"):
         L = lib()
         fc = np.ascontiguousarray(chan_freqs, dtype=np.float64)
         self._fc = fc
@@ -219,6 +225,8 @@ class Plan:
         d.compact_records = 1 if compact_records else 0
         d.max_record_pairs = int(max_record_pairs)
         d.ring_dumps = int(ring_dumps)
+        # "auto": each channel's DMs in blocking classes by the cost model; "single": one per channel
+        d.dm_classes = {"auto": 0, "single": 1}[dm_classes]
         h = ct.c_void_p()
         rc = L.ddx_plan_create(ct.byref(d), ct.byref(h))
         if rc != OK:
@@ -284,6 +292,8 @@ class Plan:
             "ring_dumps": lay.ring_dumps, "device_bytes": lay.device_bytes, "wave_units": lay.wave_units,
             "dm_group": lay.dm_group, "compact_records": lay.compact_records,
             "dump_t0_s": lay.dump_t0_s, "dump_period_s": lay.dump_period_s,
+            "dm_fft_len": arr(lay.dm_fft_len, nd, np.int64), "dm_valid": arr(lay.dm_valid, nd, np.int64),
+            "dm_lead": arr(lay.dm_lead, nd, np.int64), "n_classes": lay.n_classes,
         }
 
     def dump_times(self, chan, dm_index, first_dump, n_dumps, refer_infinite=False):
@@ -655,6 +665,42 @@ class Image:
             self.close()
         except Exception:
             pass
+
+
+def layout_blockings(lay):
+    """Per channel, the list of its DMs' blockings ({fft_len, valid, lead}, each that
+    of the DM's class) from a Plan.layout() dict."""
+    off = lay["dm_offset"]
+    return [[{"fft_len": int(lay["dm_fft_len"][k]), "valid": int(lay["dm_valid"][k]), "lead": int(lay["dm_lead"][k])}
+             for k in range(off[c], off[c + 1])] for c in range(lay["n_chan"])]
+
+
+def plan_blocking(chan_freqs, samp_rate, dump_len, dms, chan=0, fft_len=None, k_dm=0.0, dm_classes="auto"):
+    """Per-DM overlap-save blocking a plan would choose for channel chan, on the host
+    (ddx_plan_blocking).  Returns (fft_len, valid, lead) int arrays of len(dms) and
+    the number of classes."""
+    fc = np.ascontiguousarray(chan_freqs, dtype=np.float64)
+    d = Desc()
+    d.n_ant = 1
+    d.n_chan = len(fc)
+    d.chan_freq_hz = fc.ctypes.data_as(ct.POINTER(ct.c_double))
+    d.samp_rate_hz = samp_rate
+    d.sideband = 1
+    d.dump_len = dump_len
+    d.k_dm = k_dm
+    d.max_block_samples = 1
+    if fft_len is not None:
+        fl = np.ascontiguousarray(np.broadcast_to(fft_len, fc.shape), dtype=np.int32)
+        d.fft_len = fl.ctypes.data_as(ct.POINTER(ct.c_int32))
+    d.dm_classes = {"auto": 0, "single": 1}[dm_classes]
+    a = np.ascontiguousarray(dms, dtype=np.float64)
+    n, v, l = (np.zeros(len(a), dtype=np.int32) for _ in range(3))
+    p32 = ct.POINTER(ct.c_int32)
+    rc = lib().ddx_plan_blocking(ct.byref(d), chan, a.ctypes.data_as(ct.POINTER(ct.c_double)), len(a),
+                                 n.ctypes.data_as(p32), v.ctypes.data_as(p32), l.ctypes.data_as(p32))
+    if rc < 0:
+        raise DdxError(rc, "ddx_plan_blocking")
+    return n.astype(np.int64), v.astype(np.int64), l.astype(np.int64), rc
 
 
 def incoherent_delays(chan_freq_hz, t_samp_s, dms, k_dm=4.148808e15):

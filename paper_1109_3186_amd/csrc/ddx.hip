@@ -27,6 +27,19 @@ constexpr int kMaxStackedAnt = 64;  // stacked-row Gram kernel up to 2 M = 128 r
 constexpr int kMaxCorrAnt = 1024;   // antenna-block kernel beyond
 constexpr int kDefaultDmGroup = 16;
 constexpr size_t kAutoYBytes = size_t(2) << 30;  // dedispersed voltages of one wave, automatic schedule
+// Automatic blocking (see ddx_set_dm_trials): the DMs of a channel, sorted, are cut
+// into classes, each with the overlap-save blocking of its own largest DM, choosing
+// the cuts and every class's N to minimise the modelled device time per output
+// sample, sum over classes of (n_dm kDedispPs + kForwardPs) N / V (one inverse
+// transform per DM, one forward transform, per block and antenna).  Picoseconds
+// per transform point of the dedispersion and forward kernels for N = 2^8 .. 2^18
+// (FP32 output, complex int8 input, 36 antennas; measured on gfx950 with the
+// library's own profiling; 2^8 and 2^9 taken as 2^10).
+constexpr double kDedispPs[11] = {2.42, 2.42, 2.42, 2.28, 2.10, 2.01, 2.27, 2.85, 6.17, 6.55, 6.67};
+constexpr double kForwardPs[11] = {3.38, 3.38, 3.38, 3.53, 3.59, 5.34, 6.10, 9.06, 7.83, 7.37, 7.56};
+// Cuts fall on multiples of this many sorted DMs, so that the DM groups of a block
+// keep sharing its spectrum in L2.
+constexpr int kClassStep = 16;
 // Scale rule targets: E4M3 puts sigma near 32, so even after the power-of-two
 // rounding (up to x sqrt 2) about 10 sigma, and the int8 extreme 127 at sigma 16,
 // stay below its largest finite value 448; binary16 puts sigma near 4 (far from
@@ -39,12 +52,26 @@ struct Chan {
   double fc = 0;
   std::vector<double> dm;       // trial DMs
   std::vector<uint8_t> active;  // per DM
-  int fft_len = 0, logn = 0, valid = 0, lead = 0;
   float scale = 1.f;
+  std::vector<int> grp;         // its blocking classes (indices into ddx_plan::grp), by DM
+  int cover = 0;                // the class holding its largest DM
+  int win = 0;                  // N - lead of that class: the scale rule's window
+  // stream state
+  bool scaled = false;     // correlator-input scale of this stream computed
+  int64_t hist_start = 0;  // absolute index of history element 0
+};
+
+// One overlap-save blocking: a class of one channel's DMs.
+struct Grp {
+  int chan = 0;
+  std::vector<int> dms;         // the channel's DM indices in the class, ascending
+  int fft_len = 0, logn = 0, valid = 0, lead = 0;
+  int64_t gtab = 0;             // offset of the class's FP64 g table
+  int32_t slot0 = 0;            // its run of the slot table: active slots, then inactive ones
+  int32_t n_active = 0;
   // stream state
   int64_t blocks_done = 0;
   int64_t dumps_done = 0;
-  int64_t hist_start = 0;  // absolute index of history element 0
 };
 
 // Host copies of one call's work lists, packed into one upload.
@@ -75,11 +102,14 @@ struct ddx_plan {
   bool have_scale = false;
   int wave_req = 0, group_req = 0, compact = 0, max_pairs_req = 0;
   int64_t ring_req = 0;
+  int classes_req = 0;
   std::vector<Chan> ch;
+  std::vector<Grp> grp;
   int nbl = 0;
   // derived
   bool ready = false, started = false, flushed = false;
   std::vector<int32_t> lay_fft, lay_valid, lay_lead, lay_ndm;
+  std::vector<int32_t> lay_dm_fft, lay_dm_valid, lay_dm_lead;  // per (channel, DM): its class's blocking
   std::vector<int64_t> dm_off, lay_shift;
   std::vector<double> lay_dm, lay_delay, lay_fc;
   std::vector<float> lay_scale;
@@ -110,10 +140,8 @@ struct ddx_plan {
   int pw_stride = 0;
   float2* ring = nullptr;
   int64_t ring_dumps = 0;
-  double* gtab = nullptr;      // [sum N_c] FP64 g_c[k]
-  std::vector<int64_t> gtab_off;
-  std::vector<int32_t> slots;    // [sum D_c] per channel: active record slots, then inactive ones
-  std::vector<int> n_active;
+  double* gtab = nullptr;      // [sum over classes of N] FP64 g[k]
+  std::vector<int32_t> slots;    // [sum D_c] per class: active record slots, then inactive ones
   float* scale_dev = nullptr;    // [C]
   double* scale_part = nullptr;  // [C][M] partial power sums of the scale rule
   char* items_dev = nullptr;     // work lists of one call
@@ -220,32 +248,109 @@ void free_device(ddx_plan* p) {
 size_t in_bytes(int in_dtype) { return in_dtype == DDX_IN_CI8 ? 2 : 8; }
 size_t y_bytes(int corr_dtype) { return corr_dtype == DDX_CORR_F32 ? 8 : corr_dtype == DDX_CORR_F16 ? 4 : 2; }
 
-// Overlap-save blocking of one channel (reading stated in ddx.h).
-int blocking(ddx_plan* p, Chan& c, int fft_req) {
-  double dmax = 0;
-  for (double d : c.dm) dmax = std::max(dmax, d);
-  const double hi = c.fc + 0.5 * p->fs, lo = c.fc - 0.5 * p->fs;
-  const double inv_c = 1.0 / (c.fc * c.fc);
-  const double early = p->kdm * dmax * (inv_c - 1.0 / (hi * hi)) * p->fs;
-  const double late = p->kdm * dmax * (1.0 / (lo * lo) - inv_c) * p->fs;
-  const double amax = std::ceil(std::max(early, late));
-  if (!(amax < 1e9)) return fail(p, DDX_EUNSUPPORTED, "dispersion smear %.3g samples too long", amax);
-  const int64_t a = (int64_t)amax;
-  auto kept = [&](int64_t n) { int64_t r = n - 2 * a; return r < 0 ? int64_t(-1) : p->L * (r / p->L); };
-  int64_t n = fft_req;
+// Overlap-save blocking (reading stated in ddx.h at ddx_set_dm_trials).
+// Half overlap of one DM: the larger intra-channel smear, in samples, rounded up.
+double half_overlap(const ddx_plan* p, double fc, double dm) {
+  const double hi = fc + 0.5 * p->fs, lo = fc - 0.5 * p->fs;
+  const double inv_c = 1.0 / (fc * fc);
+  const double early = p->kdm * dm * (inv_c - 1.0 / (hi * hi)) * p->fs;
+  const double late = p->kdm * dm * (1.0 / (lo * lo) - inv_c) * p->fs;
+  return std::ceil(std::max(early, late));
+}
+
+// Outputs kept per block of length n with half overlap a (a multiple of L), -1 if none.
+int64_t kept(const ddx_plan* p, int64_t n, int64_t a) {
+  const int64_t r = n - 2 * a;
+  return r < 0 ? int64_t(-1) : p->L * (r / p->L);
+}
+
+// Blocking of class g for half overlap a and FFT length n (0: the smallest power
+// of two >= 256 that keeps at least half of each block).
+int set_blocking(ddx_plan* p, Grp& g, int64_t a, int64_t n) {
   if (n == 0) {
     n = 256;
-    while (kept(n) < n / 2 && n <= (int64_t(1) << 30)) n *= 2;
+    while (kept(p, n, a) < n / 2 && n <= (int64_t(1) << 30)) n *= 2;
   }
-  const int64_t v = kept(n);
+  const int64_t v = kept(p, n, a);
   if (v < p->L) return fail(p, DDX_EINVAL, "FFT length %lld too short for overlap %lld and dump %d", (long long)n, (long long)(2 * a), p->L);
   if (n > (int64_t(1) << kMaxLogN))
     return fail(p, DDX_EUNSUPPORTED, "FFT length %lld > %d not supported", (long long)n, 1 << kMaxLogN);
-  c.fft_len = (int)n;
-  c.logn = std::max(ilog2i(n), kMinLogN);
-  if ((1 << c.logn) != n) return fail(p, DDX_EUNSUPPORTED, "FFT length %lld < 256", (long long)n);
-  c.valid = (int)v;
-  c.lead = (int)((n - v) / 2);
+  g.fft_len = (int)n;
+  g.logn = std::max(ilog2i(n), kMinLogN);
+  if ((1 << g.logn) != n) return fail(p, DDX_EUNSUPPORTED, "FFT length %lld < 256", (long long)n);
+  g.valid = (int)v;
+  g.lead = (int)((n - v) / 2);
+  return DDX_OK;
+}
+
+// Split channel ci's DMs into blocking classes (appended to out).  A requested FFT
+// length, or one class per channel, keeps every DM in one class with the blocking
+// of the largest DM; otherwise the cuts and lengths minimise the cost model above
+// by dynamic programming over the sorted DMs.
+int plan_channel(ddx_plan* p, int ci, std::vector<Grp>& out) {
+  const Chan& c = p->ch[ci];
+  const int D = (int)c.dm.size();
+  std::vector<int> order(D);
+  for (int i = 0; i < D; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return c.dm[x] < c.dm[y]; });
+  std::vector<double> a(D);
+  for (int k = 0; k < D; ++k) a[k] = half_overlap(p, c.fc, c.dm[order[k]]);
+  if (!(a[D - 1] < 1e9)) return fail(p, DDX_EUNSUPPORTED, "dispersion smear %.3g samples too long", a[D - 1]);
+  std::vector<int> ends, lens;  // class k covers sorted DMs [ends[k-1], ends[k]) with length lens[k]
+  const int fft_req = p->fft_req[ci];
+  if (fft_req || p->classes_req == 1) {
+    ends.push_back(D);
+    lens.push_back(fft_req);
+  } else {
+    const int step = std::max(kClassStep, (D + 255) / 256);
+    std::vector<int> pos;
+    for (int k = step; k < D; k += step) pos.push_back(k);
+    pos.push_back(D);
+    const double inf = HUGE_VAL;
+    const size_t np = pos.size();
+    std::vector<double> best(np, inf);
+    std::vector<int> from(np, -1), blen(np, 0);
+    for (size_t jj = 0; jj < np; ++jj) {
+      const int j = pos[jj];
+      const int64_t aj = (int64_t)a[j - 1];
+      for (int ii = -1; ii < (int)jj; ++ii) {
+        const double base = ii < 0 ? 0.0 : best[ii];
+        if (!(base < inf)) continue;
+        const int n = j - (ii < 0 ? 0 : pos[ii]);
+        for (int l = kMinLogN; l <= kMaxLogN; ++l) {
+          const int64_t N = int64_t(1) << l, v = kept(p, N, aj);
+          if (v < p->L) continue;
+          const double cost = base + (n * kDedispPs[l - kMinLogN] + kForwardPs[l - kMinLogN]) * (double)N / (double)v;
+          if (cost < best[jj]) {
+            best[jj] = cost;
+            from[jj] = ii;
+            blen[jj] = l;
+          }
+        }
+      }
+    }
+    if (!(best[np - 1] < inf)) {  // no length holds the largest DM's overlap: the rule's own error
+      Grp g;
+      int rc = set_blocking(p, g, (int64_t)a[D - 1], 0);
+      return rc ? rc : fail(p, DDX_EUNSUPPORTED, "no FFT length up to %d holds the overlap", 1 << kMaxLogN);
+    }
+    for (int jj = (int)np - 1; jj >= 0; jj = from[jj]) {
+      ends.push_back(pos[jj]);
+      lens.push_back(1 << blen[jj]);
+    }
+    std::reverse(ends.begin(), ends.end());
+    std::reverse(lens.begin(), lens.end());
+  }
+  for (size_t k = 0; k < ends.size(); ++k) {
+    const int i = k ? ends[k - 1] : 0, j = ends[k];
+    Grp g;
+    g.chan = ci;
+    g.dms.assign(order.begin() + i, order.begin() + j);
+    std::sort(g.dms.begin(), g.dms.end());
+    int rc = set_blocking(p, g, (int64_t)a[j - 1], lens[k]);
+    if (rc) return rc;
+    out.push_back(std::move(g));
+  }
   return DDX_OK;
 }
 
@@ -444,9 +549,10 @@ void build_layout(ddx_plan* p) {
   p->lay_shift.clear();
   for (int i = 0; i < p->C; ++i) {
     Chan& c = p->ch[i];
-    p->lay_fft[i] = c.fft_len;
-    p->lay_valid[i] = c.valid;
-    p->lay_lead[i] = c.lead;
+    const Grp& cv = p->grp[c.cover];
+    p->lay_fft[i] = cv.fft_len;
+    p->lay_valid[i] = cv.valid;
+    p->lay_lead[i] = cv.lead;
     p->lay_ndm[i] = (int32_t)c.dm.size();
     p->lay_scale[i] = c.scale;
     p->lay_fc[i] = c.fc;
@@ -458,44 +564,54 @@ void build_layout(ddx_plan* p) {
       p->lay_shift.push_back((int64_t)std::nearbyint(p->kdm * d * (inv - invt) * p->fs));
     }
   }
+  const int64_t total = p->dm_off[p->C];
+  p->lay_dm_fft.assign(total, 0);
+  p->lay_dm_valid.assign(total, 0);
+  p->lay_dm_lead.assign(total, 0);
+  for (const Grp& g : p->grp)
+    for (int d : g.dms) {
+      const int64_t k = p->dm_off[g.chan] + d;
+      p->lay_dm_fft[k] = g.fft_len;
+      p->lay_dm_valid[k] = g.valid;
+      p->lay_dm_lead[k] = g.lead;
+    }
 }
 
 // Record slots of the active DMs (compact records: active pairs numbered in
-// order; full records: dm_offset[c] + d) and the per-channel slot table (active
-// slots first, then inactive ones, which k_zero_dm clears).  Host state only:
-// the next ddx_process_block copies what its kernels need.
+// (channel, DM) order; full records: dm_offset[c] + d) and the per-class slot
+// table (each class's active slots first, then its inactive ones, which k_zero_dm
+// clears).  Host state only: the next ddx_process_block copies what its kernels need.
 void update_active(ddx_plan* p) {
   const int64_t total = p->dm_off[p->C];
-  std::vector<int32_t>& slots = p->slots;
-  slots.assign(total, 0);
   p->rec_pos.assign(total, -1);
-  p->n_active.assign(p->C, 0);
   int64_t next = 0;
   for (int i = 0; i < p->C; ++i) {
     Chan& c = p->ch[i];
     const int64_t o = p->dm_off[i];
-    int na = 0;
-    for (size_t d = 0; d < c.dm.size(); ++d) {
-      if (!c.active[d]) continue;
-      const int32_t pos = (int32_t)(p->compact ? next++ : o + (int64_t)d);
-      p->rec_pos[o + d] = pos;
-      slots[o + na++] = pos;
-    }
-    int k = na;
     for (size_t d = 0; d < c.dm.size(); ++d)
-      if (!c.active[d]) {
-        if (!p->compact) p->rec_pos[o + d] = (int32_t)(o + d);
-        slots[o + k++] = (int32_t)(o + d);
-      }
-    p->n_active[i] = na;
+      if (c.active[d]) p->rec_pos[o + d] = (int32_t)(p->compact ? next++ : o + (int64_t)d);
+      else if (!p->compact) p->rec_pos[o + d] = (int32_t)(o + d);
+  }
+  std::vector<int32_t>& slots = p->slots;
+  slots.assign(total, 0);
+  int32_t k = 0;
+  for (Grp& g : p->grp) {
+    const Chan& c = p->ch[g.chan];
+    const int64_t o = p->dm_off[g.chan];
+    g.slot0 = k;
+    for (int d : g.dms)
+      if (c.active[d]) slots[k++] = p->rec_pos[o + d];
+    g.n_active = k - g.slot0;
+    for (int d : g.dms)
+      if (!c.active[d]) slots[k++] = (int32_t)(o + d);
   }
   p->rec_pairs = p->compact ? next : total;
   p->rec_elems = p->rec_pairs * p->nbl;
 }
 
-// Largest number of blocks of channel c that one call can run: the history (< N)
+// Largest number of blocks of class g that one call can run: the history (< N)
 // plus the chunk, plus one for rounding.
-int64_t max_blocks(const ddx_plan* p, const Chan& c) { return (p->max_block + c.fft_len) / c.valid + 2; }
+int64_t max_blocks(const ddx_plan* p, const Grp& g) { return (p->max_block + g.fft_len) / g.valid + 2; }
 
 size_t align_up(size_t n) { return (n + 255) & ~size_t(255); }
 
@@ -505,17 +621,17 @@ int setup_device(ddx_plan* p) {
   int rc;
   int maxn = 0, maxv = 0, maxd = 0;
   int64_t sum_n = 0, spec_elems = 0, max_units = 0, max_fwd = 0, max_zero = 0, big_rows = 0;
-  for (auto& c : p->ch) {
-    maxn = std::max(maxn, c.fft_len);
-    maxv = std::max(maxv, c.valid);
-    maxd = std::max(maxd, (int)c.dm.size());
-    sum_n += c.fft_len;
-    const int64_t nb = max_blocks(p, c);
-    spec_elems += (int64_t)p->M * nb * c.fft_len;
+  for (auto& c : p->ch) maxd = std::max(maxd, (int)c.dm.size());
+  for (auto& g : p->grp) {
+    maxn = std::max(maxn, g.fft_len);
+    maxv = std::max(maxv, g.valid);
+    sum_n += g.fft_len;
+    const int64_t nb = max_blocks(p, g);
+    spec_elems += (int64_t)p->M * nb * g.fft_len;
     max_fwd += nb;
-    max_units += nb * (int64_t)c.dm.size();
-    max_zero += nb * c.valid / p->L + 1;
-    if (c.logn > ddx::kBigLog) big_rows = std::max<int64_t>(big_rows, (int64_t)p->M * c.fft_len);
+    max_units += nb * (int64_t)g.dms.size();
+    max_zero += nb * g.valid / p->L + 1;
+    if (g.logn > ddx::kBigLog) big_rows = std::max<int64_t>(big_rows, (int64_t)p->M * g.fft_len);
   }
   p->hist_cap = maxn;
   const size_t ib = in_bytes(p->in_dtype);
@@ -569,17 +685,18 @@ int setup_device(ddx_plan* p) {
     }
     HIPCHECK(p, hipEventCreateWithFlags(&p->stage_ev[i], hipEventDisableTiming));
   }
-  // FP64 tables
-  p->gtab_off.assign(p->C + 1, 0);
+  // FP64 tables: g[k] of every class (its channel's frequency, its length)
   std::vector<double> g(sum_n);
-  for (int i = 0; i < p->C; ++i) {
-    Chan& c = p->ch[i];
-    p->gtab_off[i + 1] = p->gtab_off[i] + c.fft_len;
-    const int n = c.fft_len;
+  int64_t goff = 0;
+  for (Grp& gr : p->grp) {
+    const double fc = p->ch[gr.chan].fc;
+    const int n = gr.fft_len;
+    gr.gtab = goff;
     for (int k = 0; k < n; ++k) {
       const double f = p->sideband * (double)(k < n / 2 ? k : k - n) * (p->fs / n);
-      g[p->gtab_off[i] + k] = (f * f) / (c.fc * c.fc * (c.fc + f));
+      g[goff + k] = (f * f) / (fc * fc * (fc + f));
     }
+    goff += n;
   }
   if ((rc = dev_alloc(p, (void**)&p->gtab, g.size() * sizeof(double)))) return rc;
   if ((rc = dev_alloc(p, (void**)&p->scale_dev, p->C * sizeof(float)))) return rc;
@@ -628,6 +745,7 @@ int ddx_plan_create(const ddx_desc* d, ddx_plan** out) {
   if (d->k_dm < 0 || !std::isfinite(d->k_dm)) return DDX_EINVAL;
   if (d->wave_units < 0 || d->dm_group < 0 || d->max_record_pairs < 0 || d->ring_dumps < 0) return DDX_EINVAL;
   if (d->compact_records != 0 && d->compact_records != 1) return DDX_EINVAL;
+  if (d->dm_classes != 0 && d->dm_classes != 1) return DDX_EINVAL;
   for (int c = 0; c < d->n_chan; ++c) {
     const double f = d->chan_freq_hz[c];
     if (!std::isfinite(f) || !(f > 0.5 * d->samp_rate_hz)) return DDX_EINVAL;
@@ -653,6 +771,7 @@ int ddx_plan_create(const ddx_desc* d, ddx_plan** out) {
   p->compact = d->compact_records;
   p->max_pairs_req = d->max_record_pairs;
   p->ring_req = d->ring_dumps;
+  p->classes_req = d->dm_classes;
   p->nbl = d->out_mode == DDX_OUT_PACKED ? d->n_ant * (d->n_ant + 1) / 2 : d->n_ant * d->n_ant;
   p->ch.resize(p->C);
   p->fft_req.assign(p->C, 0);
@@ -681,14 +800,48 @@ int ddx_set_dm_trials(ddx_plan* p, int32_t chan, const double* dm, int32_t n_dm)
     p->ch[c].active.assign(n_dm, 1);
   }
   bool all = true;
+  std::vector<Grp> grp;
   for (int c = 0; c < p->C; ++c) {
     if (p->ch[c].dm.empty()) { all = false; continue; }
-    int rc = blocking(p, p->ch[c], p->fft_req[c]);
+    int rc = plan_channel(p, c, grp);
     if (rc) { p->ch = saved; return rc; }
   }
   if (!all) { p->ready = false; return DDX_OK; }
+  p->grp = std::move(grp);
+  for (auto& c : p->ch) c.grp.clear();
+  for (int k = 0; k < (int)p->grp.size(); ++k) {
+    Chan& c = p->ch[p->grp[k].chan];
+    c.grp.push_back(k);
+    c.cover = k;  // classes come in DM order: the last holds the largest DM
+    c.win = p->grp[k].fft_len - p->grp[k].lead;
+  }
   int rc = setup_device(p);
   p->ready = rc == DDX_OK;
+  return rc;
+}
+
+int ddx_plan_blocking(const ddx_desc* desc, int32_t chan, const double* dm, int32_t n_dm, int32_t* fft_len,
+                      int32_t* valid, int32_t* lead) {
+  if (!desc || !dm || n_dm < 1 || !fft_len || !valid || !lead) return DDX_EINVAL;
+  if (chan < 0 || chan >= desc->n_chan) return DDX_EINVAL;
+  for (int i = 0; i < n_dm; ++i)
+    if (!std::isfinite(dm[i]) || dm[i] < 0) return DDX_EINVAL;
+  ddx_plan* p = nullptr;
+  int rc = ddx_plan_create(desc, &p);
+  if (rc) return rc;
+  p->ch[chan].dm.assign(dm, dm + n_dm);
+  std::vector<Grp> grp;
+  rc = plan_channel(p, chan, grp);
+  if (rc == DDX_OK) {
+    for (const Grp& g : grp)
+      for (int d : g.dms) {
+        fft_len[d] = g.fft_len;
+        valid[d] = g.valid;
+        lead[d] = g.lead;
+      }
+    rc = (int)grp.size();
+  }
+  delete p;
   return rc;
 }
 
@@ -699,7 +852,7 @@ int ddx_set_active_dms(ddx_plan* p, int32_t chan, const uint8_t* mask) {
   const int c0 = chan < 0 ? 0 : chan, c1 = chan < 0 ? p->C : chan + 1;
   if (p->compact) {
     int64_t done = 0;
-    for (auto& c : p->ch) done = std::max(done, c.dumps_done);
+    for (auto& g : p->grp) done = std::max(done, g.dumps_done);
     if (done > p->dumps_fetched)
       return fail(p, DDX_ESTATE, "compact records: fetch every dump before changing the active DMs");
     int64_t na = 0;
@@ -787,7 +940,7 @@ int ddx_get_layout(const ddx_plan* pc, ddx_layout* o) {
   o->record_elems = p->rec_elems;
   o->samples_in = p->recv;
   int64_t ready = INT64_MAX;
-  for (auto& c : p->ch) ready = std::min(ready, c.dumps_done);
+  for (auto& g : p->grp) ready = std::min(ready, g.dumps_done);
   o->dumps_ready = ready;
   o->dumps_fetched = p->dumps_fetched;
   o->ring_dumps = p->ring_dumps;
@@ -797,6 +950,10 @@ int ddx_get_layout(const ddx_plan* pc, ddx_layout* o) {
   o->compact_records = p->compact;
   o->dump_t0_s = 0.5 * (double)(p->L - 1) / p->fs;
   o->dump_period_s = (double)p->L / p->fs;
+  o->dm_fft_len = p->lay_dm_fft.data();
+  o->dm_valid = p->lay_dm_valid.data();
+  o->dm_lead = p->lay_dm_lead.data();
+  o->n_classes = (int32_t)p->grp.size();
   return DDX_OK;
 }
 
@@ -833,35 +990,36 @@ struct CallLists {
   std::vector<ddx::ScaleItem> scales;
 };
 
-// Build the lists for blocks [b0[c], b_end[c]) of every channel; out_end[c] is the
-// end of the channel's output this call (complete dumps only are correlated).
+// Build the lists for blocks [blocks_done, b_end[k]) of every class k; out_end[k] is
+// the end of the class's output this call (complete dumps only are correlated).
 void build_lists(ddx_plan* p, const std::vector<int64_t>& b_end, const std::vector<int64_t>& out_end, CallLists& w) {
   const int M = p->M;
-  // transform-length classes, ascending
-  std::vector<int> classes;
-  for (int i = 0; i < p->C; ++i)
-    if (b_end[i] > p->ch[i].blocks_done) classes.push_back(p->ch[i].logn);
-  std::sort(classes.begin(), classes.end());
-  classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
-  // forward items and spectrum offsets: class, channel, block.  Two-pass lengths
+  const int G = (int)p->grp.size();
+  // transform lengths that run this call, ascending
+  std::vector<int> lengths;
+  for (int k = 0; k < G; ++k)
+    if (b_end[k] > p->grp[k].blocks_done) lengths.push_back(p->grp[k].logn);
+  std::sort(lengths.begin(), lengths.end());
+  lengths.erase(std::unique(lengths.begin(), lengths.end()), lengths.end());
+  // forward items and spectrum offsets: length, class, block.  Two-pass lengths
   // run in chunks of `chunk` items whose intermediate rows start at offset 0.
-  std::vector<size_t> fwd_first(p->C, 0);
+  std::vector<size_t> fwd_first(G, 0);
   int64_t off = 0;
-  for (int logn : classes) {
+  for (int logn : lengths) {
     FwdLaunch fl{logn, w.fwd.size(), 0};
     const size_t per = (size_t)M << logn;
     const size_t chunk = logn > ddx::kBigLog ? std::max<size_t>(1, p->tb_elems / per) : 1;
-    for (int i = 0; i < p->C; ++i) {
-      Chan& c = p->ch[i];
-      if (c.logn != logn || b_end[i] <= c.blocks_done) continue;
-      fwd_first[i] = w.fwd.size();
-      for (int64_t b = c.blocks_done; b < b_end[i]; ++b) {
+    for (int k = 0; k < G; ++k) {
+      const Grp& g = p->grp[k];
+      if (g.logn != logn || b_end[k] <= g.blocks_done) continue;
+      fwd_first[k] = w.fwd.size();
+      for (int64_t b = g.blocks_done; b < b_end[k]; ++b) {
         ddx::FwdItem it{};
-        it.win0 = b * (int64_t)c.valid - c.lead;
+        it.win0 = b * (int64_t)g.valid - g.lead;
         it.spec = off;
         it.tb = logn > ddx::kBigLog ? (int64_t)(((w.fwd.size() - fl.i0) % chunk) * per) : 0;
-        it.hist_start = c.hist_start;
-        it.chan = i;
+        it.hist_start = p->ch[g.chan].hist_start;
+        it.chan = g.chan;
         it.logn = logn;
         w.fwd.push_back(it);
         off += (int64_t)per;
@@ -870,40 +1028,43 @@ void build_lists(ddx_plan* p, const std::vector<int64_t>& b_end, const std::vect
     fl.n = w.fwd.size() - fl.i0;
     w.fwd_launch.push_back(fl);
   }
-  // units: class, channel, DM group, block, DM; waves of wave_units within a class
+  // units: length, class, DM group, block, DM; waves of wave_units within a length
   std::vector<int32_t> slot_of(p->dm_off[p->C], -1);
   std::vector<int64_t> slot_wave(p->dm_off[p->C], -1);
   std::vector<int64_t> spec_wave(w.fwd.size(), -1);
-  const int64_t maxn = *std::max_element(p->lay_fft.begin(), p->lay_fft.end());
-  for (int logn : classes) {
+  int64_t maxn = 0;
+  for (const Grp& g : p->grp) maxn = std::max<int64_t>(maxn, g.fft_len);
+  for (int logn : lengths) {
     Wave cur{};
     bool open = false;
     auto close = [&]() {
       if (open && cur.nu) w.waves.push_back(cur);
       open = false;
     };
-    for (int i = 0; i < p->C; ++i) {
-      Chan& c = p->ch[i];
-      if (c.logn != logn || b_end[i] <= c.blocks_done) continue;
-      // the channel's active DMs, in DM order
+    for (int k = 0; k < G; ++k) {
+      const Grp& g = p->grp[k];
+      if (g.logn != logn || b_end[k] <= g.blocks_done) continue;
+      const int i = g.chan;
+      const Chan& c = p->ch[i];
+      // the class's active DMs, in DM index order
       std::vector<int> act;
-      for (size_t d = 0; d < c.dm.size(); ++d)
-        if (c.active[d]) act.push_back((int)d);
+      for (int d : g.dms)
+        if (c.active[d]) act.push_back(d);
       for (size_t g0 = 0; g0 < act.size(); g0 += p->dm_group) {
         const size_t g1 = std::min(act.size(), g0 + p->dm_group);
-        for (int64_t b = c.blocks_done; b < b_end[i]; ++b) {
-          const int64_t first = b * c.valid / p->L;
-          const int64_t last = std::min(b * c.valid + c.valid, out_end[i]) / p->L;
+        for (int64_t b = g.blocks_done; b < b_end[k]; ++b) {
+          const int64_t first = b * g.valid / p->L;
+          const int64_t last = std::min(b * g.valid + g.valid, out_end[k]) / p->L;
           if (last <= first) continue;
-          for (size_t k = g0; k < g1; ++k) {
-            const int d = act[k];
+          for (size_t q = g0; q < g1; ++q) {
+            const int d = act[q];
             if (!open || cur.nu == (size_t)p->wave_units) {
               close();
               cur = Wave{};
               cur.logn = logn;
               cur.u0 = w.units.size();
               cur.c0 = w.chirps.size();
-              cur.fft_n = c.fft_len;
+              cur.fft_n = g.fft_len;
               open = true;
             }
             const int64_t wid = (int64_t)w.waves.size();
@@ -912,33 +1073,33 @@ void build_lists(ddx_plan* p, const std::vector<int64_t>& b_end, const std::vect
               slot_wave[pair] = wid;
               slot_of[pair] = (int32_t)cur.nc;
               ddx::ChirpItem ci{};
-              ci.g = p->gtab_off[i];
+              ci.g = g.gtab;
               ci.out = (int64_t)cur.nc * maxn;
               ci.kdm = p->kdm * c.dm[d];
-              ci.n = c.fft_len;
-              ci.logr = c.logn > ddx::kBigLog ? c.logn - ddx::kBigLog : 0;
+              ci.n = g.fft_len;
+              ci.logr = g.logn > ddx::kBigLog ? g.logn - ddx::kBigLog : 0;
               ci.chan = i;
               w.chirps.push_back(ci);
               ++cur.nc;
             }
-            const size_t sidx = fwd_first[i] + (size_t)(b - c.blocks_done);
+            const size_t sidx = fwd_first[k] + (size_t)(b - g.blocks_done);
             if (spec_wave[sidx] != wid) { spec_wave[sidx] = wid; ++cur.spectra; }
             ddx::UnitItem u{};
             u.spec = w.fwd[sidx].spec;
             u.chirp = (int64_t)slot_of[pair] * maxn;
             u.y = (int64_t)cur.nu * M * p->y_stride;
-            u.tb = (int64_t)cur.nu * M * c.fft_len;
+            u.tb = (int64_t)cur.nu * M * g.fft_len;
             u.dump0 = first;
             u.rec = (int64_t)p->rec_pos[pair] * p->nbl;
             u.chan = i;
-            u.valid = c.valid;
-            u.lead = c.lead;
+            u.valid = g.valid;
+            u.lead = g.lead;
             u.n_dumps = (int32_t)(last - first);
             u.fwd = (int32_t)sidx;
             w.units.push_back(u);
             ++cur.nu;
             cur.max_dumps = std::max(cur.max_dumps, u.n_dumps);
-            cur.y_samples += (int64_t)M * c.valid;
+            cur.y_samples += (int64_t)M * g.valid;
             cur.dumps += u.n_dumps;
           }
         }
@@ -946,17 +1107,17 @@ void build_lists(ddx_plan* p, const std::vector<int64_t>& b_end, const std::vect
     }
     close();
   }
-  // full records: zero the inactive DMs' slots of every dump the call completes
+  // full records: zero the inactive DMs' slots of every dump a class completes
   if (!p->compact) {
-    for (int i = 0; i < p->C; ++i) {
-      Chan& c = p->ch[i];
-      const int n_in = (int)c.dm.size() - p->n_active[i];
+    for (int k = 0; k < G; ++k) {
+      const Grp& g = p->grp[k];
+      const int n_in = (int)g.dms.size() - g.n_active;
       if (n_in <= 0) continue;
-      const int64_t m0 = c.blocks_done * c.valid / p->L, m1 = out_end[i] / p->L;
+      const int64_t m0 = g.blocks_done * g.valid / p->L, m1 = out_end[k] / p->L;
       for (int64_t m = m0; m < m1; ++m) {
         ddx::ZeroItem z{};
         z.rec = (m % p->ring_dumps) * p->rec_elems;
-        z.pos = (int32_t)(p->dm_off[i] + p->n_active[i]);
+        z.pos = g.slot0 + g.n_active;
         z.n = n_in;
         w.zeros.push_back(z);
       }
@@ -1014,28 +1175,33 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
   const bool flush = flags & DDX_FLUSH;
   const int64_t total = p->recv + n;
 
-  // Blocks each channel can run now, and the dumps they complete.
-  std::vector<int64_t> b_end(p->C), dumps_new(p->C), out_end(p->C);
+  // Blocks each class can run now, and the dumps they complete.  A channel's
+  // classes start once its scale window [0, win) is in (or at the flush), so the
+  // scale rule sees the same samples however the classes are cut.
+  const int G = (int)p->grp.size();
+  std::vector<int64_t> b_end(G), dumps_new(G), out_end(G);
   const int64_t fetched_floor = p->dumps_fetched;
-  for (int i = 0; i < p->C; ++i) {
-    Chan& c = p->ch[i];
+  for (int k = 0; k < G; ++k) {
+    Grp& g = p->grp[k];
     int64_t be;
     if (flush) {
-      be = (total + c.valid - 1) / c.valid;
+      be = (total + g.valid - 1) / g.valid;
+    } else if (total < p->ch[g.chan].win) {
+      be = 0;
     } else {
-      const int64_t lim = total - c.fft_len + c.lead;  // b V <= lim
-      be = lim < 0 ? 0 : lim / c.valid + 1;
+      const int64_t lim = total - g.fft_len + g.lead;  // b V <= lim
+      be = lim < 0 ? 0 : lim / g.valid + 1;
     }
-    be = std::max(be, c.blocks_done);
-    b_end[i] = be;
-    out_end[i] = be * (int64_t)c.valid;
-    if (flush) out_end[i] = std::min(out_end[i], total);
-    dumps_new[i] = std::max(c.dumps_done, out_end[i] / p->L);
-    if (dumps_new[i] - fetched_floor > p->ring_dumps)
-      return fail(p, DDX_EFULL, "channel %d would hold %lld unfetched dumps, ring has %lld", i,
-                  (long long)(dumps_new[i] - fetched_floor), (long long)p->ring_dumps);
-    if (be - c.blocks_done > max_blocks(p, c))
-      return fail(p, DDX_EINVAL, "internal: %lld blocks exceed the spectrum buffer", (long long)(be - c.blocks_done));
+    be = std::max(be, g.blocks_done);
+    b_end[k] = be;
+    out_end[k] = be * (int64_t)g.valid;
+    if (flush) out_end[k] = std::min(out_end[k], total);
+    dumps_new[k] = std::max(g.dumps_done, out_end[k] / p->L);
+    if (dumps_new[k] - fetched_floor > p->ring_dumps)
+      return fail(p, DDX_EFULL, "channel %d would hold %lld unfetched dumps, ring has %lld", g.chan,
+                  (long long)(dumps_new[k] - fetched_floor), (long long)p->ring_dumps);
+    if (be - g.blocks_done > max_blocks(p, g))
+      return fail(p, DDX_EINVAL, "internal: %lld blocks exceed the spectrum buffer", (long long)(be - g.blocks_done));
   }
   if (p->started && p->last_stream != s) HIPCHECK(p, hipStreamSynchronize(p->last_stream));
   p->started = true;
@@ -1043,13 +1209,16 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
 
   CallLists w;
   build_lists(p, b_end, out_end, w);
-  // correlator-input scale of each channel whose first block runs now (window [0, N - lead))
+  // correlator-input scale of each channel whose first blocks run now (window [0, win))
+  std::vector<uint8_t> runs(p->C, 0);
+  for (int k = 0; k < G; ++k)
+    if (b_end[k] > p->grp[k].blocks_done) runs[p->grp[k].chan] = 1;
   if (!p->have_scale)
     for (int i = 0; i < p->C; ++i) {
       Chan& c = p->ch[i];
-      if (b_end[i] <= c.blocks_done || c.blocks_done != 0) continue;
+      if (!runs[i] || c.scaled) continue;
       ddx::ScaleItem si{};
-      si.n = std::min<int64_t>(c.fft_len - c.lead, total);
+      si.n = std::min<int64_t>(c.win, total);
       si.hist_start = c.hist_start;
       si.chan = i;
       w.scales.push_back(si);
@@ -1187,12 +1356,18 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
     }));
   }
 
-  // Carry the unconsumed tail of every row into the other history buffer.
+  // Carry the unconsumed tail of every row into the other history buffer: from the
+  // earliest sample any class of the channel still needs.
   if (!flush) {
     void* dst = p->hist[1 - p->hist_cur];
+    std::vector<int64_t> need(p->C, INT64_MAX);
+    for (int k = 0; k < G; ++k) {
+      const Grp& g = p->grp[k];
+      need[g.chan] = std::min(need[g.chan], std::max<int64_t>(0, b_end[k] * g.valid - g.lead));
+    }
     for (int i = 0; i < p->C; ++i) {
       Chan& c = p->ch[i];
-      const int64_t start = std::max<int64_t>(0, b_end[i] * c.valid - c.lead);
+      const int64_t start = need[i];
       const int64_t len = std::max<int64_t>(0, total - start);
       if (len > p->hist_cap) return fail(p, DDX_EINVAL, "internal: history of %lld samples", (long long)len);
       if (len > 0) {
@@ -1211,10 +1386,12 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
     }
     p->hist_cur = 1 - p->hist_cur;
   }
-  for (int i = 0; i < p->C; ++i) {
-    p->ch[i].blocks_done = b_end[i];
-    p->ch[i].dumps_done = dumps_new[i];
+  for (int k = 0; k < G; ++k) {
+    p->grp[k].blocks_done = b_end[k];
+    p->grp[k].dumps_done = dumps_new[k];
   }
+  for (int i = 0; i < p->C; ++i)
+    if (runs[i]) p->ch[i].scaled = true;
   p->recv = total;
   if (flush) p->flushed = true;
   return DDX_OK;
@@ -1224,7 +1401,7 @@ int ddx_fetch_visibilities(ddx_plan* p, void* out, size_t cap, int64_t* first, i
   if (!p || !first || !nd) return DDX_EINVAL;
   if (!p->ready) return fail(p, DDX_ESTATE, "set DM trials for every channel first");
   int64_t ready = INT64_MAX;
-  for (auto& c : p->ch) ready = std::min(ready, c.dumps_done);
+  for (auto& g : p->grp) ready = std::min(ready, g.dumps_done);
   const int64_t avail = ready - p->dumps_fetched;
   *first = p->dumps_fetched;
   *nd = avail;
@@ -1343,9 +1520,12 @@ int ddx_reset_stream(ddx_plan* p) {
   if (!p->ready) return fail(p, DDX_ESTATE, "set DM trials for every channel first");
   if (p->started) HIPCHECK(p, hipStreamSynchronize(p->last_stream));
   for (auto& c : p->ch) {
-    c.blocks_done = 0;
-    c.dumps_done = 0;
+    c.scaled = false;
     c.hist_start = 0;
+  }
+  for (auto& g : p->grp) {
+    g.blocks_done = 0;
+    g.dumps_done = 0;
   }
   p->recv = 0;
   p->dumps_fetched = 0;

@@ -56,8 +56,9 @@ def run_gpu(cfg, in_dtype="cf32", corr="f32", out_mode="packed", chunks=None, ff
 
 
 def blockings(lay):
-    return [{"fft_len": int(lay["fft_len"][c]), "valid": int(lay["valid"][c]), "lead": int(lay["lead"][c])}
-            for c in range(lay["n_chan"])]
+    """Per channel, the list of every DM's blocking (its class's) from a plan layout."""
+    from paper_1109_3186_amd import layout_blockings
+    return layout_blockings(lay)
 
 
 def select(vis, lay, c, d):

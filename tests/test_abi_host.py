@@ -308,3 +308,54 @@ def test_planar_cells_and_sampling_rule_on_the_host():
         ddx.chimg_cells_2d(rng.uniform(0, 1000, (20, 2)), 1.0, max_cells=10)
     for args in [(9.0, 240, 5.0), (0.0, 240, 5.0), (100.0, 240, 5.0), (-3.3, 77, 2.5)]:
         assert ddx.chimg_sampling_blocks(*args) == ocg.sampling_blocks(*args)
+
+
+def _smear_half(fc, fs, dm):
+    import math
+
+    import oracle
+    early, late = oracle.smear_samples(fc, fs, dm)
+    return int(math.ceil(max(early, late)))
+
+
+@pytest.mark.parametrize("fc,dmax,nd,L", [(1.2e9, 2000.0, 256, 1000), (0.7e9, 3000.0, 1536, 1000),
+                                          (1.4e9, 100.0, 16, 64), (0.732e9, 3000.0, 100, 1000)])
+def test_blocking_classes_on_the_host(fc, dmax, nd, L):
+    """The blocking rule without a device (ddx_plan_blocking).  "single": every DM gets
+    the oracle's rule at the channel's largest DM.  "auto": the DMs, sorted, fall into
+    contiguous classes whose blocking is the oracle's rule at the class's largest DM
+    and the class's own length, so every DM's overlap covers its own smear on both
+    sides; cuts lie at multiples of 16 sorted DMs; a requested FFT length keeps one
+    class."""
+    import oracle
+    from paper_1109_3186_amd import plan_blocking
+    rng = np.random.default_rng(int(fc) % 1000 + nd)
+    dms = rng.permutation(np.linspace(0.0, dmax, nd))  # any order
+    n, v, l, k = plan_blocking([fc], 1e6, L, dms, dm_classes="single")
+    ref = oracle.blocking(fc, 1e6, dms.max(), L)
+    assert k == 1 and set(n) == {ref["fft_len"]} and set(v) == {ref["valid"]} and set(l) == {ref["lead"]}
+    n, v, l, k = plan_blocking([fc], 1e6, L, dms)
+    order = np.argsort(dms, kind="stable")
+    keys = [(n[d], v[d], l[d]) for d in order]
+    cuts = [i for i in range(1, nd) if keys[i] != keys[i - 1]]
+    assert len(cuts) == k - 1 and all(c % 16 == 0 for c in cuts)
+    for lo, hi in zip([0] + cuts, cuts + [nd]):
+        cls = order[lo:hi]
+        r = oracle.blocking(fc, 1e6, dms[cls].max(), L, fft_len=int(n[cls[0]]))
+        assert keys[lo] == (r["fft_len"], r["valid"], r["lead"])
+    for d in range(nd):
+        a = _smear_half(fc, 1e6, dms[d])
+        assert v[d] % L == 0 and v[d] >= L and 256 <= n[d] <= 1 << 18 and n[d] & (n[d] - 1) == 0
+        assert l[d] >= a and n[d] - v[d] - l[d] >= a
+    n2, _, _, k2 = plan_blocking([fc], 1e6, L, dms, fft_len=1 << 15 if dmax < 2500 else 1 << 18)
+    assert k2 == 1 and len(set(n2)) == 1
+
+
+def test_blocking_classes_reject_like_the_plan():
+    from paper_1109_3186_amd import DdxError, plan_blocking
+    with pytest.raises(DdxError):  # smear beyond 2^18
+        plan_blocking([0.3e9], 1e6, 1000, [0.0, 5000.0])
+    with pytest.raises(DdxError):  # negative DM
+        plan_blocking([1.2e9], 1e6, 1000, [-1.0])
+    with pytest.raises(DdxError):  # channel out of range
+        plan_blocking([1.2e9], 1e6, 1000, [1.0], chan=1)

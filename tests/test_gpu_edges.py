@@ -183,10 +183,10 @@ def test_f32_split_range_follows_level_changes(gpu):
     clean = mixed = 0.0
     for c in range(2):
         ref = oracle.run_oracle(cfg["volts"], cfg["chan_freqs"], 1e6, cfg["dm_lists"], 500, bl, chans=[c])
-        v_, n_, lead = bl[c]["valid"], bl[c]["fft_len"], bl[c]["lead"]
-        blk = np.arange(vis.shape[0]) * 500 // v_          # block of each dump
-        straddle = (blk * v_ - lead <= step) & (step < blk * v_ - lead + n_)
         for (cc, d), v in ref.items():
+            v_, n_, lead = bl[c][d]["valid"], bl[c][d]["fft_len"], bl[c][d]["lead"]  # the DM's blocking
+            blk = np.arange(vis.shape[0]) * 500 // v_          # block of each dump
+            straddle = (blk * v_ - lead <= step) & (step < blk * v_ - lead + n_)
             auto = v[:, iu == ju].real
             e = (np.abs(select(vis, lay, cc, d).astype(np.complex128) - v) / np.sqrt(auto[:, iu] * auto[:, ju])).max(1)
             clean = max(clean, float(e[~straddle].max()))

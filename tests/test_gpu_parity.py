@@ -92,13 +92,19 @@ def test_pulse_recovery_noise_free(gpu):
 
 
 def test_plan_blocking_matches_oracle_rule(gpu):
+    """One blocking per channel (dm_classes = "single"): the oracle's rule at the
+    channel's largest DM, for every DM of the channel."""
     cfg = synth.make_small(seed=21, m_ant=3, n_chan=3, s=4000, f_lo=1.2e9, f_s=1e6, n_dm=4, dm_max=400.0,
                            dump_len=100, n_pulses=0)
     cfg["dm_lists"][1] = np.array([0.0, 50.0, 1200.0])
-    vis, lay = run_gpu(cfg)
+    vis, lay = run_gpu(cfg, dm_classes="single")
+    assert lay["n_classes"] == 3
     for c in range(3):
         ref = oracle.blocking(cfg["chan_freqs"][c], 1e6, max(cfg["dm_lists"][c]), 100)
         assert (lay["fft_len"][c], lay["valid"][c], lay["lead"][c]) == (ref["fft_len"], ref["valid"], ref["lead"])
+        for k in range(lay["dm_offset"][c], lay["dm_offset"][c + 1]):
+            assert (lay["dm_fft_len"][k], lay["dm_valid"][k], lay["dm_lead"][k]) == \
+                (ref["fft_len"], ref["valid"], ref["lead"])
     delta, shift = oracle.channel_delays(cfg["chan_freqs"], cfg["dm_lists"][0], 1e6)
     np.testing.assert_allclose(lay["delay_s"][:4], delta[0], rtol=1e-15)
     assert np.array_equal(lay["shift"][lay["dm_offset"][2]:lay["dm_offset"][2] + 4], shift[2])

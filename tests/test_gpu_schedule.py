@@ -65,7 +65,8 @@ def test_mixed_lengths_one_plan(gpu):
                            dump_len=100, ci8=True, n_pulses=1)
     cfg["dm_lists"] = [np.array([0.0, 20.0, 45.0]), np.array([500.0, 10.0]),
                        np.array([0.0, 500.0, 1200.0, 2500.0])]
-    vis, lay = run_gpu(cfg, in_dtype="ci8", chunks=[70000, 1, 130000, 100000], max_block=130000)
+    vis, lay = run_gpu(cfg, in_dtype="ci8", chunks=[70000, 1, 130000, 100000], max_block=130000,
+                       dm_classes="single")
     say("lengths", lay["fft_len"], "valid", lay["valid"])
     assert list(lay["fft_len"]) == [4096, 32768, 131072]
     for c in range(3):
@@ -142,10 +143,67 @@ def test_c3_shape_sampled(gpu):
                            dm_max=3000.0, dump_len=1000, ci8=True, n_pulses=1, radius_m=2500.0)
     cfg["dm_lists"] = [np.array([0.0, 750.0, 1500.0, 2250.0, 2990.0]), np.arange(3) * 3000.0 / 3]
     say("C3 shape: 256 ant, 2 ch at 0.7 GHz, 200000 ci8 samples, DMs 5 + 3 up to 2990")
-    vis, lay = run_gpu(cfg, in_dtype="ci8")
+    vis, lay = run_gpu(cfg, in_dtype="ci8", dm_classes="single")
     say("lengths", lay["fft_len"], "valid", lay["valid"], "dumps", vis.shape[0])
     assert list(lay["fft_len"]) == [1 << 18, 1 << 17]
     assert vis.shape[0] == 200
     err = compare_with_oracle(cfg, vis, lay, pairs=[(0, 4), (1, 1)])
     say("C3 shape max normalised error %.3e" % err)
+    assert err <= TOL
+
+
+def test_dm_classes_match_oracle_and_split_invariance(gpu):
+    """Automatic blocking classes: low DMs take shorter transforms with less overlap.
+    Every DM's blocking is the oracle's rule at its class's largest DM and the
+    class's length; every (channel, DM) matches the oracle run with its own
+    blocking; the classes' different block lengths give the same records however
+    the stream is cut into calls (the same bits for three cuttings)."""
+    cfg = synth.make_small(seed=69, m_ant=4, n_chan=2, s=150000, f_lo=1.2e9, f_s=1e6, n_dm=2, dm_max=50.0,
+                           dump_len=1000, ci8=True, n_pulses=2)
+    cfg["dm_lists"] = [np.linspace(0.0, 2000.0, 64), np.linspace(0.0, 600.0, 48)]
+    ref, lay = run_gpu(cfg, in_dtype="ci8")
+    say("classes", lay["n_classes"], "lengths", sorted(set(lay["dm_fft_len"].tolist())))
+    assert lay["n_classes"] >= 3
+    off = lay["dm_offset"]
+    for c in range(2):
+        dms = cfg["dm_lists"][c]
+        n = lay["dm_fft_len"][off[c]:off[c + 1]]
+        v = lay["dm_valid"][off[c]:off[c + 1]]
+        l = lay["dm_lead"][off[c]:off[c + 1]]
+        keys = set(zip(n.tolist(), v.tolist(), l.tolist()))
+        groups = sorted(([d for d in range(len(dms)) if (n[d], v[d], l[d]) == key] for key in keys),
+                        key=lambda m: min(dms[d] for d in m))
+        top = -1.0
+        for members in groups:
+            key = (n[members[0]], v[members[0]], l[members[0]])
+            dmax = max(dms[d] for d in members)
+            assert min(dms[d] for d in members) > top  # classes are contiguous in DM
+            top = dmax
+            r = oracle.blocking(cfg["chan_freqs"][c], 1e6, dmax, 1000, fft_len=key[0])
+            assert (r["fft_len"], r["valid"], r["lead"]) == key
+        # the channel's own blocking is that of its largest DM's class (scale window)
+        d_top = int(np.argmax(dms))
+        assert (lay["fft_len"][c], lay["valid"][c], lay["lead"][c]) == (n[d_top], v[d_top], l[d_top])
+    pairs = [(0, 0), (0, 10), (0, 40), (0, 63), (1, 5), (1, 47)]
+    err = compare_with_oracle(cfg, ref, lay, pairs=pairs)
+    say("classes max normalised error %.3e" % err)
+    assert err <= TOL
+    for chunks in ([40000, 40000, 70000], [9999, 1, 100000, 40000]):
+        got, _ = run_gpu(cfg, in_dtype="ci8", chunks=chunks, max_block=max(chunks))
+        assert np.array_equal(got, ref), chunks
+
+
+def test_dm_classes_on_the_two_pass_channel(gpu):
+    """256 antennas at 0.7 GHz, 16 DMs up to 60 then 32 up to 2990: the low DMs run a
+    single-pass class, the others two-pass ones; sampled pairs of each against the oracle."""
+    p3 = synth.c3_params()
+    cfg = synth.make_small(seed=70, m_ant=256, n_chan=1, s=200000, f_lo=p3["f_lo"], f_s=1e6, n_dm=2,
+                           dm_max=3000.0, dump_len=1000, ci8=True, n_pulses=1, radius_m=2500.0)
+    cfg["dm_lists"] = [np.concatenate([np.linspace(0.0, 60.0, 16), np.linspace(100.0, 2990.0, 32)])]
+    vis, lay = run_gpu(cfg, in_dtype="ci8")
+    lens = lay["dm_fft_len"]
+    say("classes", lay["n_classes"], "lengths", sorted(set(lens.tolist())))
+    assert lay["n_classes"] >= 2 and lens.min() <= 1 << 15 and lens.max() > 1 << 15
+    err = compare_with_oracle(cfg, vis, lay, pairs=[(0, 0), (0, 15), (0, 47)])
+    say("two-pass classes max normalised error %.3e" % err)
     assert err <= TOL
