@@ -35,8 +35,8 @@ constexpr size_t kAutoYBytes = size_t(2) << 30;  // dedispersed voltages of one 
 // per transform point of the dedispersion and forward kernels for N = 2^8 .. 2^18
 // (FP32 output, complex int8 input, 36 antennas; measured on gfx950 with the
 // library's own profiling; 2^8 and 2^9 taken as 2^10).
-constexpr double kDedispPs[11] = {2.42, 2.42, 2.42, 2.28, 2.10, 2.01, 2.27, 2.85, 6.17, 6.55, 6.67};
-constexpr double kForwardPs[11] = {3.38, 3.38, 3.38, 3.53, 3.59, 5.34, 6.10, 9.06, 7.83, 7.37, 7.56};
+constexpr double kDedispPs[11] = {2.44, 2.44, 2.44, 2.23, 2.05, 2.04, 2.27, 2.89, 6.18, 6.54, 6.55};
+constexpr double kForwardPs[11] = {2.59, 2.59, 2.59, 2.53, 2.77, 3.39, 4.00, 5.63, 7.81, 7.36, 7.48};
 // Cuts fall on multiples of this many sorted DMs, so that the DM groups of a block
 // keep sharing its spectrum in L2.
 constexpr int kClassStep = 16;
@@ -365,7 +365,7 @@ size_t fft_lds_bytes() {
 
 template <int LOGN>
 hipError_t launch_forward_n(int in_dtype, const ddx::FwdArgs& a, int n_items, hipStream_t s) {
-  using G = ddx::Geo<ddx::Plan<LOGN>>;
+  using G = ddx::Geo<ddx::FwdPlan<LOGN>>;
   dim3 grid(n_items * a.n_ant), block(G::T);
   if (in_dtype == DDX_IN_CI8)
     hipLaunchKernelGGL((ddx::k_forward<LOGN, 0>), grid, block, fft_lds_bytes<LOGN>(), s, a);

@@ -140,9 +140,25 @@ __device__ __forceinline__ float l1_of(const float2* v) {
   return s;
 }
 
+// FFT plan of k_forward (the 1024-thread 32768-point form spills here: the kernel
+// holds both input paths).
+template <int LOGN>
+using FwdPlan = Plan<LOGN>;
+
+template <int IN>
+__device__ __forceinline__ float2 sample_at(const void* row, unsigned i) {
+  if constexpr (IN == 0) {
+    const char2 v = at_byte(reinterpret_cast<const char2*>(row), 2u * i);
+    return make_float2((float)v.x, (float)v.y);
+  } else {
+    return at_byte(reinterpret_cast<const float2*>(row), 8u * i);
+  }
+}
+
 template <int LOGN, int IN>
-__global__ __launch_bounds__(Geo<Plan<LOGN>>::T) void k_forward(FwdArgs a) {
-  using G = Geo<Plan<LOGN>>;
+__global__ __launch_bounds__(Geo<FwdPlan<LOGN>>::T) void k_forward(FwdArgs a) {
+  using PL = FwdPlan<LOGN>;
+  using G = Geo<PL>;
   extern __shared__ float lds[];
   const int t = threadIdx.x;
   const int p = blockIdx.x % a.n_ant;
@@ -151,7 +167,17 @@ __global__ __launch_bounds__(Geo<Plan<LOGN>>::T) void k_forward(FwdArgs a) {
   s.row = w.chan * a.n_ant + p;
   s.hist_start = w.hist_start;
   float2 v[G::P];
-  fft_workgroup<Plan<LOGN>, -1>(v, lds, t, [&](int i) { return load_sample<IN>(s, w.win0 + i); });
+  // A window wholly inside this call's chunk (every block but those at a call's
+  // start, the stream's start and the flush) reads its row directly with 32-bit
+  // offsets; the others go through the history / chunk / zero selection per sample.
+  const int64_t rel0 = w.win0 - s.chunk_start;
+  if (rel0 >= 0 && rel0 + G::N <= s.chunk_len) {
+    const char* row = reinterpret_cast<const char*>(s.chunk) +
+                      ((int64_t)s.row * s.chunk_stride + rel0) * (IN == 0 ? 2 : 8);
+    fft_workgroup<PL, -1>(v, lds, t, [&](int i) { return sample_at<IN>(row, (unsigned)i); });
+  } else {
+    fft_workgroup<PL, -1>(v, lds, t, [&](int i) { return load_sample<IN>(s, w.win0 + i); });
+  }
   // output addresses are formed only now (otherwise they are hoisted and held in registers)
   float2* out = a.spec + w.spec + (size_t)p * G::N + opaque_zero(v[0].x);
 #pragma unroll
