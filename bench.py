@@ -60,6 +60,13 @@ def measured_traffic(kernel, workload, sources=DEDISP_SOURCES):
     return t.get("bytes_per_launch")
 
 
+def blocking_desc(lay):
+    """The plan's overlap-save blocking in a few words: the transform lengths in use
+    and the DM classes (each channel's DMs cut into classes with their own length)."""
+    lens = "/".join(str(n) for n in sorted(set(int(v) for v in lay["dm_fft_len"])))
+    return "N %s in %d DM classes over %d channels" % (lens, lay["n_classes"], lay["n_chan"])
+
+
 def build_input(p, dev, chunk):
     import torch
 
@@ -706,8 +713,8 @@ def c3_measure(dev, steps, warmup, corr, use_autotune, n_passes):
         plan.set_dm_trials(d, chan=c)
     lay = plan.layout()
     nbl = lay["n_baselines"]
-    log("C3 plan: lengths %s, %d passes of <= %d pairs, ring %d dumps, %.1f GB device" % (
-        sorted(set(int(n) for n in lay["fft_len"])), passes, max_pairs, ring, lay["device_bytes"] / 1e9))
+    log("C3 plan: %s, %d passes of <= %d pairs, ring %d dumps, %.1f GB device" % (
+        blocking_desc(lay), passes, max_pairs, ring, lay["device_bytes"] / 1e9))
     out = torch.empty((ring, max_pairs * nbl), dtype=torch.complex64, device=dev)
     masks = []
     for k in range(passes):
@@ -754,8 +761,7 @@ def c3_measure(dev, steps, warmup, corr, use_autotune, n_passes):
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": corr, "data": "synthetic",
         "config": {"workload": "256 ant x 32 ch x 2^18 ci8 samples, 512..1536 DMs per channel 0-3000, "
-                               "N %s, 1 ms dumps, %d DM-window passes" % (
-                                   "/".join(str(n) for n in sorted(set(int(v) for v in lay["fft_len"]))), passes),
+                               "%s, 1 ms dumps, %d DM-window passes" % (blocking_desc(lay), passes),
                    "n_ant": M, "n_chan": p["n_chan"], "samples": s, "n_dm_total": int(sum(p["n_dm"])),
                    "dump_len": L, "passes": passes, "input": "ci8", "corr": corr,
                    "schedule": {"wave_units": lay["wave_units"], "dm_group": lay["dm_group"],
@@ -984,8 +990,8 @@ def main():
     plan = make_plan()
     plan.set_dm_trials(dms)
     lay = plan.layout()
-    log("plan: N %d V %d..%d lead %d, ring %d dumps, %.1f GB device, wave %d units, DM group %d" % (
-        lay["fft_len"][0], lay["valid"].min(), lay["valid"].max(), lay["lead"][0], lay["ring_dumps"],
+    log("plan: %s, V %d..%d, ring %d dumps, %.1f GB device, wave %d units, DM group %d" % (
+        blocking_desc(lay), lay["dm_valid"].min(), lay["dm_valid"].max(), lay["ring_dumps"],
         lay["device_bytes"] / 1e9, lay["wave_units"], lay["dm_group"]))
     out = torch.empty((lay["ring_dumps"], lay["record_elems"]), dtype=torch.complex64, device=dev)
 
@@ -1050,10 +1056,11 @@ def main():
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"f32": "f32", "f16": "f16", "e4m3": "e4m3"}[args.corr], "data": "synthetic",
-        "config": {"workload": "36 ant x %d ch x 2^20 ci8 samples, 256 DMs 0-2000, N %d, 1 ms dumps"
-                               % (p["n_chan"], lay["fft_len"][0]),
+        "config": {"workload": "36 ant x %d ch x 2^20 ci8 samples, 256 DMs 0-2000, %s, 1 ms dumps"
+                               % (p["n_chan"], blocking_desc(lay)),
                    "n_ant": p["m_ant"], "n_chan": p["n_chan"], "samples": p["samples"], "n_dm": p["n_dm"],
-                   "dump_len": p["dump_len"], "fft_len": int(lay["fft_len"][0]), "chunk": args.chunk,
+                   "dump_len": p["dump_len"], "fft_len": sorted(set(int(v) for v in lay["dm_fft_len"])),
+                   "dm_classes": int(lay["n_classes"]), "chunk": args.chunk,
                    "input": "ci8", "corr": args.corr, "parallelism": "none (1 GPU)"},
         "roofline": roofline, "cpu_baseline": cpu, "learned": learned, "precision_forms": forms, "c3_step": c3,
     }

@@ -93,6 +93,8 @@ typedef struct ddx_desc {
   /* Blocking (see ddx_set_dm_trials): */
   int32_t dm_classes;          /* 0: each channel's DMs in classes by the cost model; 1: one class per channel */
   int32_t pad;
+  int64_t spectrum_bytes;      /* cap on the spectrum buffer, 0 = 32 GiB: a call runs its classes in
+                                  batches whose spectra fit it (a class larger than it runs alone) */
 } ddx_desc;
 
 /* Scale rule when chan_scale is NULL (all correlator formats; the scale keeps

@@ -34,7 +34,7 @@ class Desc(ct.Structure):
         ("out_mode", ct.c_int32), ("chan_scale", ct.POINTER(ct.c_float)),
         ("wave_units", ct.c_int32), ("dm_group", ct.c_int32), ("compact_records", ct.c_int32),
         ("max_record_pairs", ct.c_int32), ("ring_dumps", ct.c_int64),
-        ("dm_classes", ct.c_int32), ("pad", ct.c_int32),
+        ("dm_classes", ct.c_int32), ("pad", ct.c_int32), ("spectrum_bytes", ct.c_int64),
     ]
 
 
@@ -197,7 +197,7 @@ class Plan:
     def __init__(self, n_ant, chan_freqs, samp_rate, dump_len, max_block_samples, *, sideband=1, in_dtype="ci8",
                  corr_dtype="f32", fft_len=None, k_dm=0.0, max_device_bytes=0, out_mode="packed", chan_scale=None,
                  wave_units=0, dm_group=0, compact_records=False, max_record_pairs=0, ring_dumps=0,
-                 dm_classes="auto"):
+                 dm_classes="auto", spectrum_bytes=0):
         L = lib()
         fc = np.ascontiguousarray(chan_freqs, dtype=np.float64)
         self._fc = fc
@@ -227,6 +227,7 @@ class Plan:
         d.ring_dumps = int(ring_dumps)
         # "auto": each channel's DMs in blocking classes by the cost model; "single": one per channel
         d.dm_classes = {"auto": 0, "single": 1}[dm_classes]
+        d.spectrum_bytes = int(spectrum_bytes)
         h = ct.c_void_p()
         rc = L.ddx_plan_create(ct.byref(d), ct.byref(h))
         if rc != OK:

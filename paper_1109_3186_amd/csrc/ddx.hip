@@ -40,6 +40,11 @@ constexpr double kForwardPs[11] = {2.59, 2.59, 2.59, 2.53, 2.77, 3.39, 4.00, 5.6
 // Cuts fall on multiples of this many sorted DMs, so that the DM groups of a block
 // keep sharing its spectrum in L2.
 constexpr int kClassStep = 16;
+// Spectrum buffer: every class keeps the spectra of the blocks one call runs, so
+// many classes of many antennas would need hundreds of GB; a call runs its
+// classes in batches whose spectra fit this many bytes (or one class, if larger),
+// unless the descriptor gives another cap.
+constexpr int64_t kSpecBudgetBytes = int64_t(32) << 30;
 // Scale rule targets: E4M3 puts sigma near 32, so even after the power-of-two
 // rounding (up to x sqrt 2) about 10 sigma, and the int8 extreme 127 at sigma 16,
 // stay below its largest finite value 448; binary16 puts sigma near 4 (far from
@@ -84,6 +89,7 @@ struct Wave {
   int64_t y_samples;  // dedispersed samples it writes (all antennas)
   int64_t dumps;      // (unit, dump) pairs it correlates
   double fft_n;       // N of its transforms
+  int64_t y_stride;   // elements per antenna row of its dedispersed voltages
 };
 struct FwdLaunch {
   int logn;
@@ -103,6 +109,7 @@ struct ddx_plan {
   int wave_req = 0, group_req = 0, compact = 0, max_pairs_req = 0;
   int64_t ring_req = 0;
   int classes_req = 0;
+  int64_t spec_budget = 0;  // bytes
   std::vector<Chan> ch;
   std::vector<Grp> grp;
   int nbl = 0;
@@ -116,6 +123,10 @@ struct ddx_plan {
   std::vector<int32_t> rec_pos;  // [sum D_c] record slot of (c, d), -1 if not stored
   int64_t rec_pairs = 0, rec_elems = 0, cap_pairs = 0;
   int wave_units = 0, dm_group = 0;
+  // per transform length (index log2 N): units a wave may hold, and the row stride
+  // of its dedispersed voltages (the length's largest V)
+  std::vector<int> wave_cap;
+  std::vector<int64_t> wave_ys;
   // stream
   int64_t recv = 0;
   int64_t dumps_fetched = 0;
@@ -125,7 +136,7 @@ struct ddx_plan {
   void* hist[2] = {nullptr, nullptr};
   int hist_cur = 0;
   int64_t hist_cap = 0;
-  float2* spec = nullptr;      // spectra of every block one call runs, all channels
+  float2* spec = nullptr;      // spectra of the blocks one batch of classes runs
   size_t spec_elems = 0;
   float2* tb = nullptr;        // intermediate rows of the two-pass transforms
   size_t tb_elems = 0;
@@ -620,7 +631,7 @@ int setup_device(ddx_plan* p) {
   build_layout(p);
   int rc;
   int maxn = 0, maxv = 0, maxd = 0;
-  int64_t sum_n = 0, spec_elems = 0, max_units = 0, max_fwd = 0, max_zero = 0, big_rows = 0;
+  int64_t sum_n = 0, spec_elems = 0, spec_one = 0, max_units = 0, max_fwd = 0, max_zero = 0, big_rows = 0;
   for (auto& c : p->ch) maxd = std::max(maxd, (int)c.dm.size());
   for (auto& g : p->grp) {
     maxn = std::max(maxn, g.fft_len);
@@ -628,6 +639,7 @@ int setup_device(ddx_plan* p) {
     sum_n += g.fft_len;
     const int64_t nb = max_blocks(p, g);
     spec_elems += (int64_t)p->M * nb * g.fft_len;
+    spec_one = std::max<int64_t>(spec_one, (int64_t)p->M * nb * g.fft_len);
     max_fwd += nb;
     max_units += nb * (int64_t)g.dms.size();
     max_zero += nb * g.valid / p->L + 1;
@@ -637,7 +649,7 @@ int setup_device(ddx_plan* p) {
   const size_t ib = in_bytes(p->in_dtype);
   for (int i = 0; i < 2; ++i)
     if ((rc = dev_alloc(p, &p->hist[i], (size_t)p->C * p->M * p->hist_cap * ib))) return rc;
-  p->spec_elems = (size_t)spec_elems;
+  p->spec_elems = (size_t)std::max(spec_one, std::min(spec_elems, p->spec_budget / (int64_t)sizeof(float2)));
   if ((rc = dev_alloc(p, (void**)&p->spec, p->spec_elems * sizeof(float2)))) return rc;
   // schedule: DM group and wave size
   p->y_stride = maxv;
@@ -662,6 +674,26 @@ int setup_device(ddx_plan* p) {
   // two-pass transforms: intermediate rows of one wave (dedispersion); the forward
   // transform runs its items in chunks of the same size
   p->tb_elems = (size_t)big_rows * p->wave_units;
+  // Waves of a shorter length hold more units in the same buffers: as many as the
+  // voltages (rows of the length's largest V), the per-dump power, the chirps (N
+  // each) and the two-pass rows allow (a requested wave size is kept as given).
+  p->wave_cap.assign(kMaxLogN + 1, 0);
+  p->wave_ys.assign(kMaxLogN + 1, 0);
+  for (auto& g : p->grp) p->wave_ys[g.logn] = std::max<int64_t>(p->wave_ys[g.logn], g.valid);
+  for (int l = 0; l <= kMaxLogN; ++l) {
+    const int64_t ys = p->wave_ys[l];
+    if (!ys) continue;
+    int64_t cap = p->wave_units;
+    if (!p->wave_req) {
+      const int64_t wu = p->wave_units;
+      cap = wu * p->y_stride / ys;
+      if (p->power) cap = std::min<int64_t>(cap, wu * p->pw_stride / std::max<int64_t>(1, ys / p->L));
+      cap = std::min<int64_t>(cap, wu * maxn / (int64_t(1) << l));
+      if (l > ddx::kBigLog) cap = std::min<int64_t>(cap, (int64_t)p->tb_elems / ((int64_t)p->M << l));
+      cap = std::max<int64_t>(1, std::min<int64_t>(cap, int64_t(1) << 20));
+    }
+    p->wave_cap[l] = (int)cap;
+  }
   if (p->tb_elems && (rc = dev_alloc(p, (void**)&p->tb, p->tb_elems * sizeof(float2)))) return rc;
   // dump ring
   p->cap_pairs = p->compact && p->max_pairs_req ? p->max_pairs_req : p->dm_off[p->C];
@@ -746,6 +778,7 @@ int ddx_plan_create(const ddx_desc* d, ddx_plan** out) {
   if (d->wave_units < 0 || d->dm_group < 0 || d->max_record_pairs < 0 || d->ring_dumps < 0) return DDX_EINVAL;
   if (d->compact_records != 0 && d->compact_records != 1) return DDX_EINVAL;
   if (d->dm_classes != 0 && d->dm_classes != 1) return DDX_EINVAL;
+  if (d->spectrum_bytes < 0) return DDX_EINVAL;
   for (int c = 0; c < d->n_chan; ++c) {
     const double f = d->chan_freq_hz[c];
     if (!std::isfinite(f) || !(f > 0.5 * d->samp_rate_hz)) return DDX_EINVAL;
@@ -772,6 +805,7 @@ int ddx_plan_create(const ddx_desc* d, ddx_plan** out) {
   p->max_pairs_req = d->max_record_pairs;
   p->ring_req = d->ring_dumps;
   p->classes_req = d->dm_classes;
+  p->spec_budget = d->spectrum_bytes ? d->spectrum_bytes : kSpecBudgetBytes;
   p->nbl = d->out_mode == DDX_OUT_PACKED ? d->n_ant * (d->n_ant + 1) / 2 : d->n_ant * d->n_ant;
   p->ch.resize(p->C);
   p->fft_req.assign(p->C, 0);
@@ -980,132 +1014,162 @@ int ddx_dump_times(const ddx_plan* pc, int32_t chan, int32_t dm_index, int64_t f
 namespace {
 
 // One call's work lists (see ddx_process_block in ddx.h).
+// Classes whose spectra share the spectrum buffer at one time: a call runs its
+// batches in turn, each its forward transforms, then its waves.
+struct Batch {
+  size_t l0, nl;  // forward launches [l0, l0 + nl)
+  size_t f0, nf;  // forward items [f0, f0 + nf)
+  size_t w0, nw;  // waves [w0, w0 + nw)
+};
 struct CallLists {
   std::vector<ddx::FwdItem> fwd;
   std::vector<FwdLaunch> fwd_launch;
   std::vector<ddx::UnitItem> units;
   std::vector<ddx::ChirpItem> chirps;
   std::vector<Wave> waves;
+  std::vector<Batch> batches;
   std::vector<ddx::ZeroItem> zeros;
   std::vector<ddx::ScaleItem> scales;
 };
 
 // Build the lists for blocks [blocks_done, b_end[k]) of every class k; out_end[k] is
 // the end of the class's output this call (complete dumps only are correlated).
+// Classes run in (transform length, class) order, cut into batches whose spectra
+// fit the spectrum buffer.
 void build_lists(ddx_plan* p, const std::vector<int64_t>& b_end, const std::vector<int64_t>& out_end, CallLists& w) {
   const int M = p->M;
   const int G = (int)p->grp.size();
-  // transform lengths that run this call, ascending
-  std::vector<int> lengths;
-  for (int k = 0; k < G; ++k)
-    if (b_end[k] > p->grp[k].blocks_done) lengths.push_back(p->grp[k].logn);
-  std::sort(lengths.begin(), lengths.end());
-  lengths.erase(std::unique(lengths.begin(), lengths.end()), lengths.end());
-  // forward items and spectrum offsets: length, class, block.  Two-pass lengths
-  // run in chunks of `chunk` items whose intermediate rows start at offset 0.
-  std::vector<size_t> fwd_first(G, 0);
-  int64_t off = 0;
-  for (int logn : lengths) {
-    FwdLaunch fl{logn, w.fwd.size(), 0};
-    const size_t per = (size_t)M << logn;
-    const size_t chunk = logn > ddx::kBigLog ? std::max<size_t>(1, p->tb_elems / per) : 1;
-    for (int k = 0; k < G; ++k) {
-      const Grp& g = p->grp[k];
-      if (g.logn != logn || b_end[k] <= g.blocks_done) continue;
-      fwd_first[k] = w.fwd.size();
-      for (int64_t b = g.blocks_done; b < b_end[k]; ++b) {
-        ddx::FwdItem it{};
-        it.win0 = b * (int64_t)g.valid - g.lead;
-        it.spec = off;
-        it.tb = logn > ddx::kBigLog ? (int64_t)(((w.fwd.size() - fl.i0) % chunk) * per) : 0;
-        it.hist_start = p->ch[g.chan].hist_start;
-        it.chan = g.chan;
-        it.logn = logn;
-        w.fwd.push_back(it);
-        off += (int64_t)per;
-      }
-    }
-    fl.n = w.fwd.size() - fl.i0;
-    w.fwd_launch.push_back(fl);
-  }
-  // units: length, class, DM group, block, DM; waves of wave_units within a length
+  std::vector<int> run;
+  for (int k = 0; k < G; ++k)  // classes with no active DM need no transforms
+    if (b_end[k] > p->grp[k].blocks_done && p->grp[k].n_active > 0) run.push_back(k);
+  std::stable_sort(run.begin(), run.end(), [&](int x, int y) { return p->grp[x].logn < p->grp[y].logn; });
   std::vector<int32_t> slot_of(p->dm_off[p->C], -1);
   std::vector<int64_t> slot_wave(p->dm_off[p->C], -1);
-  std::vector<int64_t> spec_wave(w.fwd.size(), -1);
-  int64_t maxn = 0;
-  for (const Grp& g : p->grp) maxn = std::max<int64_t>(maxn, g.fft_len);
-  for (int logn : lengths) {
-    Wave cur{};
-    bool open = false;
-    auto close = [&]() {
-      if (open && cur.nu) w.waves.push_back(cur);
-      open = false;
-    };
-    for (int k = 0; k < G; ++k) {
-      const Grp& g = p->grp[k];
-      if (g.logn != logn || b_end[k] <= g.blocks_done) continue;
-      const int i = g.chan;
-      const Chan& c = p->ch[i];
-      // the class's active DMs, in DM index order
-      std::vector<int> act;
-      for (int d : g.dms)
-        if (c.active[d]) act.push_back(d);
-      for (size_t g0 = 0; g0 < act.size(); g0 += p->dm_group) {
-        const size_t g1 = std::min(act.size(), g0 + p->dm_group);
+  std::vector<int64_t> spec_wave;
+  std::vector<size_t> fwd_first(G, 0);
+  size_t r0 = 0;
+  while (r0 < run.size()) {
+    // the batch: classes run[r0, r1) whose spectra fit the buffer (at least one)
+    size_t r1 = r0;
+    int64_t need = 0;
+    while (r1 < run.size()) {
+      const Grp& g = p->grp[run[r1]];
+      const int64_t n = (b_end[run[r1]] - g.blocks_done) * (int64_t)M * g.fft_len;
+      if (r1 > r0 && need + n > (int64_t)p->spec_elems) break;
+      need += n;
+      ++r1;
+    }
+    Batch bt{w.fwd_launch.size(), 0, w.fwd.size(), 0, w.waves.size(), 0};
+    // forward items and spectrum offsets (from the buffer's start): length, class,
+    // block.  Two-pass lengths run in chunks of `chunk` items whose intermediate
+    // rows start at offset 0.
+    int64_t off = 0;
+    for (size_t r = r0; r < r1;) {
+      const int logn = p->grp[run[r]].logn;
+      FwdLaunch fl{logn, w.fwd.size(), 0};
+      const size_t per = (size_t)M << logn;
+      const size_t chunk = logn > ddx::kBigLog ? std::max<size_t>(1, p->tb_elems / per) : 1;
+      for (; r < r1 && p->grp[run[r]].logn == logn; ++r) {
+        const int k = run[r];
+        const Grp& g = p->grp[k];
+        fwd_first[k] = w.fwd.size();
         for (int64_t b = g.blocks_done; b < b_end[k]; ++b) {
-          const int64_t first = b * g.valid / p->L;
-          const int64_t last = std::min(b * g.valid + g.valid, out_end[k]) / p->L;
-          if (last <= first) continue;
-          for (size_t q = g0; q < g1; ++q) {
-            const int d = act[q];
-            if (!open || cur.nu == (size_t)p->wave_units) {
-              close();
-              cur = Wave{};
-              cur.logn = logn;
-              cur.u0 = w.units.size();
-              cur.c0 = w.chirps.size();
-              cur.fft_n = g.fft_len;
-              open = true;
+          ddx::FwdItem it{};
+          it.win0 = b * (int64_t)g.valid - g.lead;
+          it.spec = off;
+          it.tb = logn > ddx::kBigLog ? (int64_t)(((w.fwd.size() - fl.i0) % chunk) * per) : 0;
+          it.hist_start = p->ch[g.chan].hist_start;
+          it.chan = g.chan;
+          it.logn = logn;
+          w.fwd.push_back(it);
+          off += (int64_t)per;
+        }
+      }
+      fl.n = w.fwd.size() - fl.i0;
+      w.fwd_launch.push_back(fl);
+    }
+    spec_wave.resize(w.fwd.size(), -1);
+    // units: length, class, DM group, block, DM; waves of wave_units within a length
+    for (size_t r = r0; r < r1;) {
+      const int logn = p->grp[run[r]].logn;
+      Wave cur{};
+      bool open = false;
+      auto close = [&]() {
+        if (open && cur.nu) w.waves.push_back(cur);
+        open = false;
+      };
+      for (; r < r1 && p->grp[run[r]].logn == logn; ++r) {
+        const int k = run[r];
+        const Grp& g = p->grp[k];
+        const int i = g.chan;
+        const Chan& c = p->ch[i];
+        // the class's active DMs, in DM index order
+        std::vector<int> act;
+        for (int d : g.dms)
+          if (c.active[d]) act.push_back(d);
+        for (size_t g0 = 0; g0 < act.size(); g0 += p->dm_group) {
+          const size_t g1 = std::min(act.size(), g0 + p->dm_group);
+          for (int64_t b = g.blocks_done; b < b_end[k]; ++b) {
+            const int64_t first = b * g.valid / p->L;
+            const int64_t last = std::min(b * g.valid + g.valid, out_end[k]) / p->L;
+            if (last <= first) continue;
+            for (size_t q = g0; q < g1; ++q) {
+              const int d = act[q];
+              if (!open || cur.nu == (size_t)p->wave_cap[logn]) {
+                close();
+                cur = Wave{};
+                cur.logn = logn;
+                cur.u0 = w.units.size();
+                cur.c0 = w.chirps.size();
+                cur.fft_n = g.fft_len;
+                cur.y_stride = p->wave_ys[logn];
+                open = true;
+              }
+              const int64_t wid = (int64_t)w.waves.size();
+              const int64_t pair = p->dm_off[i] + d;
+              if (slot_wave[pair] != wid) {
+                slot_wave[pair] = wid;
+                slot_of[pair] = (int32_t)cur.nc;
+                ddx::ChirpItem ci{};
+                ci.g = g.gtab;
+                ci.out = (int64_t)cur.nc * g.fft_len;
+                ci.kdm = p->kdm * c.dm[d];
+                ci.n = g.fft_len;
+                ci.logr = g.logn > ddx::kBigLog ? g.logn - ddx::kBigLog : 0;
+                ci.chan = i;
+                w.chirps.push_back(ci);
+                ++cur.nc;
+              }
+              const size_t sidx = fwd_first[k] + (size_t)(b - g.blocks_done);
+              if (spec_wave[sidx] != wid) { spec_wave[sidx] = wid; ++cur.spectra; }
+              ddx::UnitItem u{};
+              u.spec = w.fwd[sidx].spec;
+              u.chirp = (int64_t)slot_of[pair] * g.fft_len;
+              u.y = (int64_t)cur.nu * M * cur.y_stride;
+              u.tb = (int64_t)cur.nu * M * g.fft_len;
+              u.dump0 = first;
+              u.rec = (int64_t)p->rec_pos[pair] * p->nbl;
+              u.chan = i;
+              u.valid = g.valid;
+              u.lead = g.lead;
+              u.n_dumps = (int32_t)(last - first);
+              u.fwd = (int32_t)sidx;
+              w.units.push_back(u);
+              ++cur.nu;
+              cur.max_dumps = std::max(cur.max_dumps, u.n_dumps);
+              cur.y_samples += (int64_t)M * g.valid;
+              cur.dumps += u.n_dumps;
             }
-            const int64_t wid = (int64_t)w.waves.size();
-            const int64_t pair = p->dm_off[i] + d;
-            if (slot_wave[pair] != wid) {
-              slot_wave[pair] = wid;
-              slot_of[pair] = (int32_t)cur.nc;
-              ddx::ChirpItem ci{};
-              ci.g = g.gtab;
-              ci.out = (int64_t)cur.nc * maxn;
-              ci.kdm = p->kdm * c.dm[d];
-              ci.n = g.fft_len;
-              ci.logr = g.logn > ddx::kBigLog ? g.logn - ddx::kBigLog : 0;
-              ci.chan = i;
-              w.chirps.push_back(ci);
-              ++cur.nc;
-            }
-            const size_t sidx = fwd_first[k] + (size_t)(b - g.blocks_done);
-            if (spec_wave[sidx] != wid) { spec_wave[sidx] = wid; ++cur.spectra; }
-            ddx::UnitItem u{};
-            u.spec = w.fwd[sidx].spec;
-            u.chirp = (int64_t)slot_of[pair] * maxn;
-            u.y = (int64_t)cur.nu * M * p->y_stride;
-            u.tb = (int64_t)cur.nu * M * g.fft_len;
-            u.dump0 = first;
-            u.rec = (int64_t)p->rec_pos[pair] * p->nbl;
-            u.chan = i;
-            u.valid = g.valid;
-            u.lead = g.lead;
-            u.n_dumps = (int32_t)(last - first);
-            u.fwd = (int32_t)sidx;
-            w.units.push_back(u);
-            ++cur.nu;
-            cur.max_dumps = std::max(cur.max_dumps, u.n_dumps);
-            cur.y_samples += (int64_t)M * g.valid;
-            cur.dumps += u.n_dumps;
           }
         }
       }
+      close();
     }
-    close();
+    bt.nl = w.fwd_launch.size() - bt.l0;
+    bt.nf = w.fwd.size() - bt.f0;
+    bt.nw = w.waves.size() - bt.w0;
+    w.batches.push_back(bt);
+    r0 = r1;
   }
   // full records: zero the inactive DMs' slots of every dump a class completes
   if (!p->compact) {
@@ -1261,13 +1325,16 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
     p->scale_pending = true;
   }
 
-  // forward transforms, one launch per transform length (two-pass lengths in chunks
-  // that fit the intermediate buffer)
+  // batch by batch: forward transforms, one launch per transform length (two-pass
+  // lengths in chunks that fit the intermediate buffer), the blocks' bounds, the waves
   ddx::FwdArgs fa{};
   fa.src = src;
   fa.spec = p->spec;
   fa.n_ant = p->M;
-  for (const FwdLaunch& fl : w.fwd_launch) {
+  const double nbl_h = p->M * (p->M + 1) / 2.0;
+  for (const Batch& bt : w.batches) {
+  for (size_t li = bt.l0; li < bt.l0 + bt.nl; ++li) {
+    const FwdLaunch& fl = w.fwd_launch[li];
     const double nn = 1 << fl.logn;
     if (fl.logn <= ddx::kBigLog) {
       fa.items = fwd_dev + fl.i0;
@@ -1291,10 +1358,11 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
     }
   }
 
-  if (p->bound && !w.fwd.empty()) {  // FP32 correlator inputs: each block's bound on |y|
-    HIPCHECK(p, timed(p, s, DDX_K_OTHER, 0.0, (double)w.fwd.size() * p->M * 32.0, [&] {
-      hipLaunchKernelGGL(ddx::k_item_bound, dim3((unsigned)w.fwd.size()), dim3(256), 0, s, (const ddx::FwdItem*)fwd_dev,
-                         (const float*)p->l1, p->M, p->bound);
+  if (p->bound && bt.nf) {  // FP32 correlator inputs: each block's bound on |y|
+    HIPCHECK(p, timed(p, s, DDX_K_OTHER, 0.0, (double)bt.nf * p->M * 32.0, [&] {
+      hipLaunchKernelGGL(ddx::k_item_bound, dim3((unsigned)bt.nf), dim3(256), 0, s,
+                         (const ddx::FwdItem*)(fwd_dev + bt.f0), (const float*)(p->l1 + bt.f0 * p->M * 8), p->M,
+                         p->bound + bt.f0);
       return hipGetLastError();
     }));
   }
@@ -1302,8 +1370,8 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
   // waves: chirps, dedispersion, correlation.  (A second stream for the correlator,
   // overlapping it with the next wave's dedispersion, measured no faster: both
   // kernels are limited by the same memory system.)
-  const double nbl_h = p->M * (p->M + 1) / 2.0;
-  for (const Wave& wv : w.waves) {
+  for (size_t wi = bt.w0; wi < bt.w0 + bt.nw; ++wi) {
+    const Wave& wv = w.waves[wi];
     const double nn = wv.fft_n;
     HIPCHECK(p, timed(p, s, DDX_K_CHIRP, 0.0, (double)wv.nc * nn * 16.0, [&] {
       hipLaunchKernelGGL(ddx::k_chirp, dim3((unsigned)((wv.fft_n + 255) / 256), (unsigned)wv.nc), dim3(256), 0, s,
@@ -1319,8 +1387,8 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
     da.units = units_dev + wv.u0;
     da.power = p->power;
     da.dump_len = p->L;
-    da.pw_stride = p->pw_stride;
-    da.y_stride = p->y_stride;
+    da.pw_stride = (int32_t)(wv.y_stride / p->L);
+    da.y_stride = wv.y_stride;
     da.n_ant = p->M;
     da.n_units = (int)wv.nu;
     da.logr = wv.logn > ddx::kBigLog ? wv.logn - ddx::kBigLog : 0;
@@ -1335,8 +1403,8 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
     ca.scale = p->scale_dev;
     ca.power = p->power;
     ca.bound = p->bound;
-    ca.pw_stride = p->pw_stride;
-    ca.y_stride = p->y_stride;
+    ca.pw_stride = (int32_t)(wv.y_stride / p->L);
+    ca.y_stride = wv.y_stride;
     ca.rec_elems = p->rec_elems;
     ca.ring_dumps = p->ring_dumps;
     ca.max_dumps = wv.max_dumps;
@@ -1347,6 +1415,7 @@ int ddx_process_block(ddx_plan* p, const void* d_volts, int64_t n, int32_t flags
     HIPCHECK(p, timed(p, s, DDX_K_CORR, (double)wv.dumps * 8.0 * p->L * nbl_h,
                       (double)wv.dumps * ((double)p->L * p->M * y_bytes(p->corr_dtype) + 8.0 * p->nbl),
                       [&] { return launch_corr(p->corr_dtype, ca, (int)wv.nu, s); }));
+  }
   }
   if (!w.zeros.empty()) {
     HIPCHECK(p, timed(p, s, DDX_K_OTHER, 0.0, 8.0 * (double)w.zeros.size() * w.zeros[0].n * p->nbl, [&] {

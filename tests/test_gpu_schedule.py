@@ -191,6 +191,10 @@ def test_dm_classes_match_oracle_and_split_invariance(gpu):
     for chunks in ([40000, 40000, 70000], [9999, 1, 100000, 40000]):
         got, _ = run_gpu(cfg, in_dtype="ci8", chunks=chunks, max_block=max(chunks))
         assert np.array_equal(got, ref), chunks
+    # a spectrum buffer of one class: every class in its own batch, the same bits
+    got, lb = run_gpu(cfg, in_dtype="ci8", spectrum_bytes=1)
+    assert lb["device_bytes"] < lay["device_bytes"]
+    assert np.array_equal(got, ref)
 
 
 def test_dm_classes_on_the_two_pass_channel(gpu):
