@@ -701,8 +701,9 @@ def c3_measure(dev, steps, warmup, corr, use_autotune, n_passes):
     if use_autotune:
         tuned = autotune.tune(M, fc, p["f_s"], L, dms, corr_dtype=corr, max_block=s, log=log)
         kw = autotune.plan_kwargs(tuned)
-        log("tuned (%s): lengths %s wave %d group %d" % (tuned["source"], sorted(set(tuned["fft_len"])),
-                                                          tuned["wave_units"], tuned["dm_group"]))
+        log("tuned (%s): cost model inverse %s ps, forward %s ps per point (N 2^8..2^18), wave %d group %d" % (
+            tuned["source"], [round(v, 2) for v in tuned["cost_ps"][0]], [round(v, 2) for v in tuned["cost_ps"][1]],
+            tuned["wave_units"], tuned["dm_group"]))
     passes = n_passes or math.ceil(sum(p["n_dm"]) / 512)
     windows = [np.array_split(np.arange(n), passes) for n in p["n_dm"]]
     max_pairs = max(sum(len(windows[c][k]) for c in range(p["n_chan"])) for k in range(passes))
@@ -934,7 +935,10 @@ def main():
                          "chirp: the Chirpolator pre-integrator and image; incoherent: classical incoherent "
                          "dedispersion of a power spectrogram (brute force and tree); chimg: the Chimageator on a "
                          "uniform linear array")
-    ap.add_argument("--autotune", action="store_true", help="use the autotuned lengths and schedule (cached)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the blocking cost model and schedule now if the cache has no entry for this device "
+                         "and workload (without it: the committed cache's entry when there is one; the 256-antenna "
+                         "leg only with it)")
     ap.add_argument("--passes", type=int, default=0, help="c3: DM-window passes (0 = ceil(sum D / 512))")
     ap.add_argument("--channels", type=int, default=0,
                     help="run only the first CHANNELS channels (a smaller workload for counter runs; 0 = all)")
@@ -969,18 +973,28 @@ def main():
             args.copy_calibration, args.copy_calibration))
         del src, dst
     p = synth.c1_params()
+    full_fc = synth.chan_freqs(p["f_lo"], p["n_chan"], p["f_s"])
     if args.channels:
         p["n_chan"] = min(args.channels, p["n_chan"])
     chunks, pulses, fc = build_input(p, dev, args.chunk)
     dms = synth.dm_grid(p["n_dm"], p["dm_max"])
     kw = {"wave_units": args.wave_units, "dm_group": args.dm_group}
-    if args.autotune:
+    schedule = {"source": "automatic"}
+    if not (args.wave_units or args.dm_group):
+        # the autotuner's choice for the whole 64-channel workload (also when --channels
+        # runs a part of it, so that counter runs see the headline's launch shapes):
+        # from the committed cache, or measured now with --autotune
         from paper_1109_3186_amd import autotune
-        tuned = autotune.tune(p["m_ant"], fc, p["f_s"], p["dump_len"], [dms] * p["n_chan"], corr_dtype=args.corr,
-                              max_block=args.chunk, log=log)
-        kw = autotune.plan_kwargs(tuned)
-        log("tuned (%s): lengths %s wave %d group %d" % (tuned["source"], sorted(set(tuned["fft_len"])),
-                                                          tuned["wave_units"], tuned["dm_group"]))
+        targs = (p["m_ant"], full_fc, p["f_s"], p["dump_len"], [dms] * len(full_fc))
+        tuned = (autotune.tune(*targs, corr_dtype=args.corr, max_block=args.chunk, log=log) if args.autotune
+                 else autotune.cached(*targs, corr_dtype=args.corr, max_block=args.chunk))
+        if tuned:
+            kw = autotune.plan_kwargs(tuned)
+            schedule = {"source": "autotuned (%s)" % tuned["source"], "wave_units": tuned["wave_units"],
+                        "dm_group": tuned["dm_group"]}
+            log("tuned (%s): cost model inverse %s ps, forward %s ps per point (N 2^8..2^18), wave %d group %d" % (
+                tuned["source"], [round(v, 2) for v in tuned["cost_ps"][0]],
+                [round(v, 2) for v in tuned["cost_ps"][1]], tuned["wave_units"], tuned["dm_group"]))
     def make_plan(**extra):
         opts = dict(kw, corr_dtype=args.corr)
         opts.update(extra)
@@ -1060,7 +1074,7 @@ def main():
                                % (p["n_chan"], blocking_desc(lay)),
                    "n_ant": p["m_ant"], "n_chan": p["n_chan"], "samples": p["samples"], "n_dm": p["n_dm"],
                    "dump_len": p["dump_len"], "fft_len": sorted(set(int(v) for v in lay["dm_fft_len"])),
-                   "dm_classes": int(lay["n_classes"]), "chunk": args.chunk,
+                   "dm_classes": int(lay["n_classes"]), "chunk": args.chunk, "schedule": schedule,
                    "input": "ci8", "corr": args.corr, "parallelism": "none (1 GPU)"},
         "roofline": roofline, "cpu_baseline": cpu, "learned": learned, "precision_forms": forms, "c3_step": c3,
     }

@@ -95,6 +95,10 @@ typedef struct ddx_desc {
   int32_t pad;
   int64_t spectrum_bytes;      /* cap on the spectrum buffer, 0 = 32 GiB: a call runs its classes in
                                   batches whose spectra fit it (a class larger than it runs alone) */
+  const double* cost_ps;       /* [2][11] cost model of the classes: picoseconds per transform point
+                                  of the inverse (row 0) and forward (row 1) transforms for N = 2^8
+                                  .. 2^18, each > 0 (measured by the autotuner); NULL = the built-in
+                                  table (gfx950) */
 } ddx_desc;
 
 /* Scale rule when chan_scale is NULL (all correlator formats; the scale keeps

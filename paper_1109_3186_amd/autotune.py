@@ -1,22 +1,21 @@
 """Autotuner of the plan's tile and schedule parameters, with a JSON cache.
 
 What it chooses, by timing the library on the device (synthetic complex-int8
-noise, the workload's own channels and DM grids):
+noise, the workload's own antennas, channels and DM grids):
 
-* the transform length N_c of each channel: the automatic length (the smallest
-  power of two keeping at least half of each block), half of it when that still
-  keeps a whole dump, and two and four times it up to 2^18.  A longer transform
-  keeps more of each block (V_c / N_c grows) at a higher cost per point; above
-  2^15 it also takes the two-pass path.  Channels whose automatic length agrees
-  are tuned together on the one with the longest dispersion smear;
+* the cost model from which a plan cuts each channel's DMs into blocking classes
+  and picks every class's transform length (ddx_set_dm_trials): the time per
+  transform point of the inverse (chirp multiply, inverse FFT, discard) and of the
+  forward transform at every length 2^8 .. 2^18, from the library's own kernel
+  timings on a stream of the workload's antennas, call size and correlator format;
 * the wave size (units per dedispersion / correlator launch) and the DM group
-  (DMs run back to back on one spectrum block).
+  (DMs run back to back on one spectrum block), by timing whole streams of up to
+  8 of the workload's channels with that cost model in force.
 
 Throughput is measured as antenna-samples x DM trials per second over a whole
 short stream (process_block + fetch into device memory), processed in calls of
-the workload's own size (max_block), so that the block count of each length is
-the one the workload will see.  Results are cached in a JSON file keyed by the
-device, the workload and TUNE_VERSION (raised when the search or the kernels'
+the workload's own size (max_block).  Results are cached in a JSON file keyed by
+the device, the workload and TUNE_VERSION (raised when the search or the kernels'
 trade-offs change), so a later run with the same key costs nothing.
 """
 import hashlib
@@ -27,11 +26,11 @@ import time
 
 import numpy as np
 
-from .binding import DdxError, Plan
+from .binding import DdxError, Plan, plan_blocking
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
-MAX_LEN = 1 << 18
-TUNE_VERSION = 3
+MIN_LOG, MAX_LOG = 8, 18
+TUNE_VERSION = 4
 
 
 def workload_key(n_ant, chan_freqs, samp_rate, dump_len, dm_lists, corr_dtype, in_dtype, max_block):
@@ -78,7 +77,7 @@ def _time_stream(plan, x, repeats=2):
 
 
 def _sample_dms(dms, k):
-    """k trials of a DM list, always including the largest (it fixes the blocking)."""
+    """k trials of a DM list, always including the largest."""
     dms = np.asarray(dms, np.float64)
     if len(dms) <= k:
         return dms
@@ -86,18 +85,71 @@ def _sample_dms(dms, k):
     return dms[idx]
 
 
-def _auto_lengths(n_ant, chan_freqs, samp_rate, dump_len, dm_lists, in_dtype):
-    with Plan(n_ant, chan_freqs, samp_rate, dump_len, max_block_samples=1 << 16, in_dtype=in_dtype) as p:
-        for c, d in enumerate(dm_lists):
-            p.set_dm_trials(_sample_dms(d, 1), chan=c)
-        lay = p.layout()
-        return [int(n) for n in lay["fft_len"]], [int(v) for v in lay["valid"]]
+def measure_costs(n_ant, chan_freq, samp_rate, dump_len, corr_dtype="f32", in_dtype="ci8", max_block=1 << 18,
+                  n_dm=16, log=None):
+    """Picoseconds per transform point of the inverse and forward transforms at N =
+    2^8 .. 2^18, as [[inverse x 11], [forward x 11]], from the library's kernel
+    timings (ddx_set_profiling) on one channel: n_dm trials at DM 0 (a transform's
+    cost does not depend on the chirp's values), a stream of at least four blocks in
+    calls of max_block.  A length too short to keep one dump takes the value of the
+    next measured length (no plan can choose it)."""
+    import torch
+    say = log or (lambda *a: None)
+    inv, fwd = {}, {}
+    for l in range(MIN_LOG, MAX_LOG + 1):
+        n = 1 << l
+        if n < dump_len:
+            continue
+        s = max(4 * n, min(max_block, 1 << 18))
+        mb = min(max_block, s)
+        x = _noise(1, n_ant, s, in_dtype, seed=1112)
+        try:
+            with Plan(n_ant, [chan_freq], samp_rate, dump_len, max_block_samples=mb, in_dtype=in_dtype,
+                      corr_dtype=corr_dtype, fft_len=n, ring_dumps=s // dump_len + 4) as p:
+                p.set_dm_trials(np.zeros(n_dm))
+                _time_stream(p, x, repeats=0)  # warm-up
+                p.set_profiling(True)
+                _time_stream(p, x, repeats=0)
+                pr = p.profile()
+        except DdxError as e:
+            say("length %d: %s" % (n, e))
+            continue
+        finally:
+            del x
+        d, f = pr["dedisperse"], pr["forward"]
+        inv[l] = d["time_ms"] * 1e9 / (d["flops"] / (5 * l + 6))
+        fwd[l] = f["time_ms"] * 1e9 / (f["flops"] / (5 * l))
+        say("length %d: inverse %.3f ps, forward %.3f ps per point" % (n, inv[l], fwd[l]))
+        torch.cuda.synchronize()
+    if not inv:
+        raise RuntimeError("no transform length could be measured")
+    table = [[0.0] * (MAX_LOG - MIN_LOG + 1) for _ in range(2)]
+    for l in range(MAX_LOG, MIN_LOG - 1, -1):
+        nxt = min((k for k in inv if k >= l), default=max(inv))
+        table[0][l - MIN_LOG] = inv.get(l, inv[nxt])
+        table[1][l - MIN_LOG] = fwd.get(l, fwd[nxt])
+    return table
+
+
+def cached(n_ant, chan_freqs, samp_rate, dump_len, dm_lists, corr_dtype="f32", in_dtype="ci8", max_block=1 << 18,
+           cache=DEFAULT_CACHE):
+    """The cached tune() result for the workload on this device, or None (measures nothing)."""
+    key, _ = workload_key(n_ant, chan_freqs, samp_rate, dump_len, dm_lists, corr_dtype, in_dtype, max_block)
+    if not cache or not os.path.exists(cache):
+        return None
+    with open(cache) as f:
+        db = json.load(f)
+    if key not in db:
+        return None
+    r = dict(db[key])
+    r["source"] = "cache"
+    return r
 
 
 def tune(n_ant, chan_freqs, samp_rate, dump_len, dm_lists, corr_dtype="f32", in_dtype="ci8", max_block=1 << 18,
          cache=DEFAULT_CACHE, force=False, dm_sample=16, log=None):
-    """Return {"fft_len": [...], "wave_units": W, "dm_group": G, ...} for the workload,
-    from the cache when present, else by measurement (then cached)."""
+    """Return {"cost_ps": [[...], [...]], "wave_units": W, "dm_group": G, ...} for the
+    workload, from the cache when present, else by measurement (then cached)."""
     say = log or (lambda *a: None)
     key, desc = workload_key(n_ant, chan_freqs, samp_rate, dump_len, dm_lists, corr_dtype, in_dtype, max_block)
     db = {}
@@ -111,56 +163,34 @@ def tune(n_ant, chan_freqs, samp_rate, dump_len, dm_lists, corr_dtype="f32", in_
     t_start = time.time()
     chan_freqs = np.asarray(chan_freqs, np.float64)
     n_chan = len(chan_freqs)
-    auto_n, auto_v = _auto_lengths(n_ant, chan_freqs, samp_rate, dump_len, dm_lists, in_dtype)
-    # 1. transform length per group of channels sharing the automatic length
-    chosen = list(auto_n)
-    length_trials = {}
-    for n0 in sorted(set(auto_n)):
-        members = [c for c in range(n_chan) if auto_n[c] == n0]
-        rep = min(members, key=lambda c: auto_v[c])  # longest smear of the group
-        dms = _sample_dms(dm_lists[rep], dm_sample)
-        cands = [n for n in (n0 // 2, n0, 2 * n0, 4 * n0) if 256 <= n <= MAX_LEN]
-        # the workload's call size when it holds a block of every candidate, else four blocks
-        s = max_block if max_block >= max(cands) else max(4 * max(cands), 1 << 17)
-        x = _noise(1, n_ant, s, in_dtype, seed=1113)
-        rates = {}
-        for n in cands:
-            try:
-                with Plan(n_ant, chan_freqs[rep:rep + 1], samp_rate, dump_len, max_block_samples=s,
-                          in_dtype=in_dtype, corr_dtype=corr_dtype, fft_len=n, ring_dumps=s // dump_len + 4) as p:
-                    p.set_dm_trials(dms)
-                    t = _time_stream(p, x)
-                    rates[n] = n_ant * s * len(dms) / t
-                    say("length %d (channel %d): %.3e units/s" % (n, rep, rates[n]))
-            except DdxError as e:  # too short for the smear, or out of memory
-                say("length %d (channel %d): %s" % (n, rep, e))
-        del x
-        best = max(rates, key=rates.get)
-        length_trials[str(n0)] = {str(k): v for k, v in rates.items()}
-        for c in members:
-            chosen[c] = best
+    # 1. the classes' cost model, on the channel of the longest smear
+    rep = int(np.argmin(chan_freqs))
+    cost = measure_costs(n_ant, float(chan_freqs[rep]), samp_rate, dump_len, corr_dtype, in_dtype, max_block,
+                         log=say)
     # 2. wave size and DM group on up to 8 channels with sampled DMs, as many
     # (channel, DM) pairs as keep the stream's visibilities within a few GB
     sub = list(range(0, n_chan, max(1, n_chan // 8)))[:8]
-    s = max(2 * max(chosen[c] for c in sub), min(max_block, 1 << 18))
+    s = min(max_block, 1 << 18)
     nbl = n_ant * (n_ant + 1) // 2
     ring = s // dump_len + 2
     pairs = max(2 * len(sub), int(8e9 // (ring * nbl * 8)))
     per_chan = max(2, min(4 * dm_sample, pairs // len(sub)))
     dm_sub = [_sample_dms(dm_lists[c], per_chan) for c in sub]
     x = _noise(len(sub), n_ant, s, in_dtype, seed=1114)
+    # bytes one unit occupies in a wave: its voltages (and two-pass rows)
     y_bytes = {"f32": 8, "f16": 4, "e4m3": 2}[corr_dtype]
-    # bytes one unit occupies in a wave (V_c < N_c bounds the dedispersed row)
-    per_unit = n_ant * max(chosen) * y_bytes + (n_ant * max(chosen) * 8 if max(chosen) > (1 << 15) else 0)
+    per_unit = 0
+    for i, c in enumerate(sub):
+        n, v, _, _ = plan_blocking([chan_freqs[c]], samp_rate, dump_len, dm_sub[i], cost_ps=cost)
+        per_unit = max(per_unit, n_ant * int(v.max()) * y_bytes + (n_ant * int(n.max()) * 8 if n.max() > 1 << 15 else 0))
     sched = {}
     for wu in (0, 16, 64, 128, 256, 512):
         if wu and wu * per_unit > 16e9:
             continue
         for dg in (8, 16, 32):
             try:
-                with Plan(n_ant, chan_freqs[sub], samp_rate, dump_len, max_block_samples=s,
-                          in_dtype=in_dtype, corr_dtype=corr_dtype, fft_len=[chosen[c] for c in sub],
-                          wave_units=wu, dm_group=dg, ring_dumps=ring) as p:
+                with Plan(n_ant, chan_freqs[sub], samp_rate, dump_len, max_block_samples=s, in_dtype=in_dtype,
+                          corr_dtype=corr_dtype, cost_ps=cost, wave_units=wu, dm_group=dg, ring_dumps=ring) as p:
                     for i, d in enumerate(dm_sub):
                         p.set_dm_trials(d, chan=i)
                     t = _time_stream(p, x)
@@ -172,9 +202,8 @@ def tune(n_ant, chan_freqs, samp_rate, dump_len, dm_lists, corr_dtype="f32", in_
     del x
     best = max(sched, key=sched.get)
     wu, dg = (int(v) for v in best.split("/"))
-    r = {"fft_len": chosen, "wave_units": wu, "dm_group": dg, "auto_fft_len": auto_n,
-         "length_trials": length_trials, "schedule_trials": sched, "seconds": round(time.time() - t_start, 1),
-         "workload": desc}
+    r = {"cost_ps": cost, "wave_units": wu, "dm_group": dg, "schedule_trials": sched,
+         "seconds": round(time.time() - t_start, 1), "workload": desc}
     if cache:
         db[key] = r
         tmp = cache + ".tmp"
@@ -188,7 +217,7 @@ def tune(n_ant, chan_freqs, samp_rate, dump_len, dm_lists, corr_dtype="f32", in_
 
 def plan_kwargs(tuned):
     """Plan keyword arguments from a tune() result."""
-    return {"fft_len": tuned["fft_len"], "wave_units": tuned["wave_units"], "dm_group": tuned["dm_group"]}
+    return {"cost_ps": tuned["cost_ps"], "wave_units": tuned["wave_units"], "dm_group": tuned["dm_group"]}
 
 
 if __name__ == "__main__":
@@ -209,4 +238,4 @@ if __name__ == "__main__":
     res = tune(p["m_ant"], fc, p["f_s"], p["dump_len"], dms, corr_dtype=a.corr,
                max_block=(1 << 18) if a.workload == "c1" else p["samples"], cache=a.cache, force=a.force,
                log=lambda *m: print(*m, flush=True))
-    print(json.dumps({k: res[k] for k in ("fft_len", "wave_units", "dm_group", "source")}))
+    print(json.dumps({k: res[k] for k in ("cost_ps", "wave_units", "dm_group", "source")}))

@@ -35,6 +35,7 @@ class Desc(ct.Structure):
         ("wave_units", ct.c_int32), ("dm_group", ct.c_int32), ("compact_records", ct.c_int32),
         ("max_record_pairs", ct.c_int32), ("ring_dumps", ct.c_int64),
         ("dm_classes", ct.c_int32), ("pad", ct.c_int32), ("spectrum_bytes", ct.c_int64),
+        ("cost_ps", ct.POINTER(ct.c_double)),
     ]
 
 
@@ -197,7 +198,7 @@ class Plan:
     def __init__(self, n_ant, chan_freqs, samp_rate, dump_len, max_block_samples, *, sideband=1, in_dtype="ci8",
                  corr_dtype="f32", fft_len=None, k_dm=0.0, max_device_bytes=0, out_mode="packed", chan_scale=None,
                  wave_units=0, dm_group=0, compact_records=False, max_record_pairs=0, ring_dumps=0,
-                 dm_classes="auto", spectrum_bytes=0):
+                 dm_classes="auto", spectrum_bytes=0, cost_ps=None):
         L = lib()
         fc = np.ascontiguousarray(chan_freqs, dtype=np.float64)
         self._fc = fc
@@ -228,6 +229,9 @@ class Plan:
         # "auto": each channel's DMs in blocking classes by the cost model; "single": one per channel
         d.dm_classes = {"auto": 0, "single": 1}[dm_classes]
         d.spectrum_bytes = int(spectrum_bytes)
+        if cost_ps is not None:  # [2][11] ps per point (inverse, forward) for N = 2^8 .. 2^18
+            self._cost = np.ascontiguousarray(cost_ps, dtype=np.float64).reshape(22)
+            d.cost_ps = self._cost.ctypes.data_as(ct.POINTER(ct.c_double))
         h = ct.c_void_p()
         rc = L.ddx_plan_create(ct.byref(d), ct.byref(h))
         if rc != OK:
@@ -676,7 +680,8 @@ def layout_blockings(lay):
              for k in range(off[c], off[c + 1])] for c in range(lay["n_chan"])]
 
 
-def plan_blocking(chan_freqs, samp_rate, dump_len, dms, chan=0, fft_len=None, k_dm=0.0, dm_classes="auto"):
+def plan_blocking(chan_freqs, samp_rate, dump_len, dms, chan=0, fft_len=None, k_dm=0.0, dm_classes="auto",
+                  cost_ps=None):
     """Per-DM overlap-save blocking a plan would choose for channel chan, on the host
     (ddx_plan_blocking).  Returns (fft_len, valid, lead) int arrays of len(dms) and
     the number of classes."""
@@ -694,6 +699,9 @@ def plan_blocking(chan_freqs, samp_rate, dump_len, dms, chan=0, fft_len=None, k_
         fl = np.ascontiguousarray(np.broadcast_to(fft_len, fc.shape), dtype=np.int32)
         d.fft_len = fl.ctypes.data_as(ct.POINTER(ct.c_int32))
     d.dm_classes = {"auto": 0, "single": 1}[dm_classes]
+    if cost_ps is not None:
+        cost = np.ascontiguousarray(cost_ps, dtype=np.float64).reshape(22)
+        d.cost_ps = cost.ctypes.data_as(ct.POINTER(ct.c_double))
     a = np.ascontiguousarray(dms, dtype=np.float64)
     n, v, l = (np.zeros(len(a), dtype=np.int32) for _ in range(3))
     p32 = ct.POINTER(ct.c_int32)

@@ -34,7 +34,8 @@ constexpr size_t kAutoYBytes = size_t(2) << 30;  // dedispersed voltages of one 
 // transform per DM, one forward transform, per block and antenna).  Picoseconds
 // per transform point of the dedispersion and forward kernels for N = 2^8 .. 2^18
 // (FP32 output, complex int8 input, 36 antennas; measured on gfx950 with the
-// library's own profiling; 2^8 and 2^9 taken as 2^10).
+// library's own profiling; 2^8 and 2^9 taken as 2^10).  The descriptor may carry
+// another table (the autotuner measures one on the device it runs on).
 constexpr double kDedispPs[11] = {2.44, 2.44, 2.44, 2.23, 2.05, 2.04, 2.27, 2.89, 6.18, 6.54, 6.55};
 constexpr double kForwardPs[11] = {2.59, 2.59, 2.59, 2.53, 2.77, 3.39, 4.00, 5.63, 7.81, 7.36, 7.48};
 // Cuts fall on multiples of this many sorted DMs, so that the DM groups of a block
@@ -110,6 +111,7 @@ struct ddx_plan {
   int64_t ring_req = 0;
   int classes_req = 0;
   int64_t spec_budget = 0;  // bytes
+  double cost_inv[11] = {}, cost_fwd[11] = {};  // blocking cost model, ps per point, N = 2^8 .. 2^18
   std::vector<Chan> ch;
   std::vector<Grp> grp;
   int nbl = 0;
@@ -331,7 +333,7 @@ int plan_channel(ddx_plan* p, int ci, std::vector<Grp>& out) {
         for (int l = kMinLogN; l <= kMaxLogN; ++l) {
           const int64_t N = int64_t(1) << l, v = kept(p, N, aj);
           if (v < p->L) continue;
-          const double cost = base + (n * kDedispPs[l - kMinLogN] + kForwardPs[l - kMinLogN]) * (double)N / (double)v;
+          const double cost = base + (n * p->cost_inv[l - kMinLogN] + p->cost_fwd[l - kMinLogN]) * (double)N / (double)v;
           if (cost < best[jj]) {
             best[jj] = cost;
             from[jj] = ii;
@@ -779,6 +781,9 @@ int ddx_plan_create(const ddx_desc* d, ddx_plan** out) {
   if (d->compact_records != 0 && d->compact_records != 1) return DDX_EINVAL;
   if (d->dm_classes != 0 && d->dm_classes != 1) return DDX_EINVAL;
   if (d->spectrum_bytes < 0) return DDX_EINVAL;
+  if (d->cost_ps)
+    for (int i = 0; i < 22; ++i)
+      if (!(d->cost_ps[i] > 0) || !std::isfinite(d->cost_ps[i])) return DDX_EINVAL;
   for (int c = 0; c < d->n_chan; ++c) {
     const double f = d->chan_freq_hz[c];
     if (!std::isfinite(f) || !(f > 0.5 * d->samp_rate_hz)) return DDX_EINVAL;
@@ -806,6 +811,10 @@ int ddx_plan_create(const ddx_desc* d, ddx_plan** out) {
   p->ring_req = d->ring_dumps;
   p->classes_req = d->dm_classes;
   p->spec_budget = d->spectrum_bytes ? d->spectrum_bytes : kSpecBudgetBytes;
+  for (int i = 0; i < 11; ++i) {
+    p->cost_inv[i] = d->cost_ps ? d->cost_ps[i] : kDedispPs[i];
+    p->cost_fwd[i] = d->cost_ps ? d->cost_ps[11 + i] : kForwardPs[i];
+  }
   p->nbl = d->out_mode == DDX_OUT_PACKED ? d->n_ant * (d->n_ant + 1) / 2 : d->n_ant * d->n_ant;
   p->ch.resize(p->C);
   p->fft_req.assign(p->C, 0);

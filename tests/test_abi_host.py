@@ -359,3 +359,20 @@ def test_blocking_classes_reject_like_the_plan():
         plan_blocking([1.2e9], 1e6, 1000, [-1.0])
     with pytest.raises(DdxError):  # channel out of range
         plan_blocking([1.2e9], 1e6, 1000, [1.0], chan=1)
+
+
+def test_blocking_cost_table_steers_the_classes():
+    """A cost table in the descriptor replaces the built-in one: made cheap only at
+    2^15, every class takes 32768 points; a non-positive entry is rejected."""
+    from paper_1109_3186_amd import DdxError, plan_blocking
+    dms = np.linspace(0.0, 2000.0, 256)
+    cost = np.full((2, 11), 50.0)
+    cost[:, 7] = 1.0
+    n, v, l, k = plan_blocking([1.2e9], 1e6, 1000, dms, cost_ps=cost)
+    assert set(n.tolist()) == {1 << 15}
+    auto_n, _, _, _ = plan_blocking([1.2e9], 1e6, 1000, dms)
+    assert len(set(auto_n.tolist())) > 1
+    bad = cost.copy()
+    bad[1, 3] = 0.0
+    with pytest.raises(DdxError):
+        plan_blocking([1.2e9], 1e6, 1000, dms, cost_ps=bad)
