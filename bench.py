@@ -988,6 +988,9 @@ def main():
         targs = (p["m_ant"], full_fc, p["f_s"], p["dump_len"], [dms] * len(full_fc))
         tuned = (autotune.tune(*targs, corr_dtype=args.corr, max_block=args.chunk, log=log) if args.autotune
                  else autotune.cached(*targs, corr_dtype=args.corr, max_block=args.chunk))
+        if not tuned:
+            key, desc = autotune.workload_key(*targs, args.corr, "ci8", args.chunk)
+            log("no tuned entry for key %s (device %r): automatic schedule" % (key, desc["device"]))
         if tuned:
             kw = autotune.plan_kwargs(tuned)
             schedule = {"source": "autotuned (%s)" % tuned["source"], "wave_units": tuned["wave_units"],

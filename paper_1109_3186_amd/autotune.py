@@ -33,15 +33,26 @@ MIN_LOG, MAX_LOG = 8, 18
 TUNE_VERSION = 4
 
 
-def workload_key(n_ant, chan_freqs, samp_rate, dump_len, dm_lists, corr_dtype, in_dtype, max_block):
+def device_id():
+    """The device as the cache knows it: architecture and compute-unit count (the
+    marketing name the runtime reports depends on an ids file that may be absent)."""
     import torch
+    prop = torch.cuda.get_device_properties(0)
+    return "%s x %d CU" % (prop.gcnArchName.split(":")[0], prop.multi_processor_count)
+
+
+def key_of(desc):
+    return hashlib.sha256(json.dumps(desc, sort_keys=True).encode()).hexdigest()[:24]
+
+
+def workload_key(n_ant, chan_freqs, samp_rate, dump_len, dm_lists, corr_dtype, in_dtype, max_block):
     desc = {
-        "device": torch.cuda.get_device_name(0), "version": TUNE_VERSION, "n_ant": int(n_ant),
+        "device": device_id(), "version": TUNE_VERSION, "n_ant": int(n_ant),
         "chan_freqs": [float(f) for f in chan_freqs], "samp_rate": float(samp_rate), "dump_len": int(dump_len),
         "dms": hashlib.sha256(np.concatenate([np.asarray(d, np.float64) for d in dm_lists]).tobytes()).hexdigest()[:16],
         "n_dm": [int(len(d)) for d in dm_lists], "corr": corr_dtype, "in": in_dtype, "max_block": int(max_block),
     }
-    return hashlib.sha256(json.dumps(desc, sort_keys=True).encode()).hexdigest()[:24], desc
+    return key_of(desc), desc
 
 
 def _noise(n_chan, n_ant, n, in_dtype, seed):
