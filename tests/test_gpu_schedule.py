@@ -211,3 +211,37 @@ def test_dm_classes_on_the_two_pass_channel(gpu):
     err = compare_with_oracle(cfg, vis, lay, pairs=[(0, 0), (0, 15), (0, 47)])
     say("two-pass classes max normalised error %.3e" % err)
     assert err <= TOL
+
+
+def test_dm_classes_with_masks_and_compact_records(gpu):
+    """Several blocking classes per channel with sparse active DMs (whole classes
+    inactive included, which then run no transform): active DMs are bitwise those of
+    the full sweep, inactive ones are zeros in full records, and compact records
+    hold the same bits for the active pairs."""
+    cfg = synth.make_small(seed=71, m_ant=4, n_chan=2, s=120000, f_lo=1.2e9, f_s=1e6, n_dm=2, dm_max=50.0,
+                           dump_len=1000, ci8=True, n_pulses=1)
+    cfg["dm_lists"] = [np.linspace(0.0, 2000.0, 64), np.linspace(0.0, 600.0, 48)]
+    ref, lay = run_gpu(cfg, in_dtype="ci8")
+    assert lay["n_classes"] >= 4
+    off = lay["dm_offset"]
+    # channel 0: a few DMs, none in the top class; channel 1: every fifth DM
+    m0 = np.zeros(64, np.uint8)
+    m0[[0, 3, 17, 30]] = 1
+    m1 = np.zeros(48, np.uint8)
+    m1[::5] = 1
+    keys = list(zip(lay["dm_fft_len"][off[0]:off[1]].tolist(), lay["dm_valid"][off[0]:off[1]].tolist()))
+    assert len({keys[d] for d in np.nonzero(m0)[0]}) < len(set(keys))  # some class wholly inactive
+    masked, lm = run_gpu(cfg, in_dtype="ci8", mask=[m0, m1])
+    for c, m in enumerate([m0, m1]):
+        for d in range(len(m)):
+            got = select(masked, lm, c, d)
+            if m[d]:
+                assert np.array_equal(got, select(ref, lay, c, d)), (c, d)
+            else:
+                assert not np.any(got), (c, d)
+    n_act = int(m0.sum() + m1.sum())
+    comp, lc = run_gpu(cfg, in_dtype="ci8", mask=[m0, m1], compact_records=True, max_record_pairs=n_act)
+    assert lc["record_pairs"] == n_act
+    for c, m in enumerate([m0, m1]):
+        for d in np.nonzero(m)[0]:
+            assert np.array_equal(select(comp, lc, c, int(d)), select(ref, lay, c, int(d)))
