@@ -39,6 +39,21 @@ INCOHERENT_SOURCES = ("incoherent.hip",)
 CHIMG_SOURCES = ("chimg.hip",)
 
 
+# The paper reports no measured numbers: its figures are analytic operation rates,
+# counted as one complex multiply-accumulate per op, for an SKA-like workload
+# (400 MHz, 12 m dishes, 1 km longest baseline, 1.4 GHz, 2 polarisations, DMs 10-1000
+# in a geometric bank of ratio 1.1).  Evaluated here at M = 36 antennas: the
+# Chirpolator's DFT step (Sec. 5.1, App. A.4, with the factorisation's rho_f = 0.61,
+# only the bins a baseline needs); coherent dedispersion over many DMs it only calls
+# prohibitive (Sec. 2.3.2).  Context for the units/s above, not a target.
+PAPER_CONTEXT = {
+    "chirpolator_dft_complex_op_per_s_36_antennas": 4.3e14,
+    "assumptions": "SKA-like: 400 MHz, 12 m dishes, 1 km max baseline, 1.4 GHz, 2 pol, DM 10-1000 (48 trials), "
+                   "1 complex MAC = 1 op, rho_f = 0.61, only the needed bins",
+    "coherent_dedispersion": "no op count: called prohibitive for many DMs",
+}
+
+
 def kernel_source_hash(sources=DEDISP_SOURCES):
     h = hashlib.sha256()
     for f in sources:
@@ -1080,6 +1095,7 @@ def main():
                    "dm_classes": int(lay["n_classes"]), "chunk": args.chunk, "schedule": schedule,
                    "input": "ci8", "corr": args.corr, "parallelism": "none (1 GPU)"},
         "roofline": roofline, "cpu_baseline": cpu, "learned": learned, "precision_forms": forms, "c3_step": c3,
+        "paper_context": PAPER_CONTEXT,
     }
     print(json.dumps(rec), flush=True)
 
