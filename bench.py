@@ -33,7 +33,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-DEDISP_SOURCES = ("fft.hpp", "kernels.hpp", "ddx.hip", "tiles.hpp", "cnn_kernels.hpp", "cnn.hip")
+# the translation unit that holds k_dedisperse and k_correlate (the network's
+# kernels are compiled from cnn.hip alone)
+DEDISP_SOURCES = ("fft.hpp", "kernels.hpp", "ddx.hip", "tiles.hpp")
 IMAGE_SOURCES = ("image.hip",)
 INCOHERENT_SOURCES = ("incoherent.hip",)
 CHIMG_SOURCES = ("chimg.hip",)
