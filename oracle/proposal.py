@@ -151,20 +151,40 @@ def loss_and_grad(score, labels):
     return loss, dscore
 
 
-def backward(params, cache, dscore):
-    """Analytic gradients of the score-weighted sum sum_b dscore[b] score[b]."""
+def backward(params, cache, dscore, decisions=None):
+    """Analytic gradients of the score-weighted sum sum_b dscore[b] score[b].
+
+    decisions: optional {"gates": [4 boolean arrays shaped like the layers'
+    activations], "arg": [B, 32] time indices}: the ReLU gates (which units
+    passed) and the pooling's argmax to take in place of the ones this forward
+    pass took.  Both are discrete decisions made in floating point; a network
+    evaluated in another precision can take a few of them the other way.  With
+    them held fixed the score is the gated network h_l = gate_l (W_l * h_{l-1} +
+    b_l), score = w5 . h4[arg] + b5, whose activations are recomputed here from
+    the cache's input and whose gradients are returned."""
     grads = {}
-    g, arg, acts = cache["g"], cache["arg"], cache["acts"]
+    acts = cache["acts"]
+    if decisions is None:
+        g, arg = cache["g"], cache["arg"]
+        gates = [a > 0 for a in acts[1:]]
+    else:
+        arg = np.asarray(decisions["arg"])
+        gates = [np.asarray(m, dtype=bool) for m in decisions["gates"]]
+        acts = [acts[0]]
+        for li, s in enumerate(STRIDES):
+            acts.append((conv(acts[-1], params["W%d" % (li + 1)], s) + params["b%d" % (li + 1)][None, :, None])
+                        * gates[li])
+    h4 = acts[-1]
+    bi, ci = np.meshgrid(np.arange(h4.shape[0]), np.arange(h4.shape[1]), indexing="ij")
+    if decisions is not None:
+        g = h4[bi, ci, arg]
     grads["w5"] = g.T @ dscore
     grads["b5"] = np.array([dscore.sum()])
     gg = dscore[:, None] * params["w5"][None, :]
-    h4 = acts[-1]
     gh = np.zeros_like(h4)
-    bi, ci = np.meshgrid(np.arange(h4.shape[0]), np.arange(h4.shape[1]), indexing="ij")
     gh[bi, ci, arg] = gg
     for li in range(3, -1, -1):
-        h = acts[li + 1]
-        gpre = gh * (h > 0)
+        gpre = gh * gates[li]
         grads["b%d" % (li + 1)] = gpre.sum(axis=(0, 2))
         gx, gw = conv_backward(acts[li], params["W%d" % (li + 1)], STRIDES[li], gpre)
         grads["W%d" % (li + 1)] = gw

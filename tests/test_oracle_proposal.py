@@ -60,6 +60,54 @@ def test_gradients_match_central_differences():
             assert abs(num - ana) <= 1e-7 + 1e-5 * abs(num), (name, idx, num, ana)
 
 
+def test_backward_with_given_decisions():
+    """backward(..., decisions=...): with the ReLU gates and the pooling's argmax held
+    fixed the score is a polynomial in the parameters, the gated network
+    h_l = gate_l * (W_l * h_{l-1} + b_l), score = w5 . h4[arg] + b5, written out
+    here; the gradients given another network's decisions match its central
+    differences, and given this network's own decisions agree with the plain backward
+    (to the last bits: the same values, in another memory order)."""
+    rng = _rng(21)
+    params = P.init_params(22)
+    for l in range(1, 5):
+        params["b%d" % l] = rng.standard_normal(P.WIDTH) * 0.2
+    x = rng.standard_normal((3, 3, 32))
+    ds = rng.standard_normal(3)
+    s, cache = P.forward(params, x)
+    own = {"gates": [a > 0 for a in cache["acts"][1:]], "arg": cache["arg"]}
+    g0, g1 = P.backward(params, cache, ds), P.backward(params, cache, ds, decisions=own)
+    for k in g0:
+        np.testing.assert_allclose(g1[k], g0[k], rtol=1e-13, atol=0, err_msg=k)
+    # decisions of a perturbed network: some gates and maxima differ from this one's
+    other = {k: v + 0.3 * rng.standard_normal(v.shape) for k, v in params.items()}
+    _, c2 = P.forward(other, x)
+    dec = {"gates": [a > 0 for a in c2["acts"][1:]], "arg": c2["arg"]}
+    flips = sum(int(np.sum(a != b)) for a, b in zip(own["gates"], dec["gates"])) + int(np.sum(own["arg"] != dec["arg"]))
+    assert flips > 0
+    grads = P.backward(params, cache, ds, decisions=dec)
+
+    def gated(pr):
+        h = x
+        for li, st in enumerate(P.STRIDES):
+            h = (P.conv(h, pr["W%d" % (li + 1)], st) + pr["b%d" % (li + 1)][None, :, None]) * dec["gates"][li]
+        bi, ci = np.meshgrid(np.arange(h.shape[0]), np.arange(h.shape[1]), indexing="ij")
+        return float(ds @ (h[bi, ci, dec["arg"]] @ pr["w5"] + pr["b5"][0]))
+
+    h = 1e-5
+    for name in ["W1", "b1", "W2", "b2", "W3", "W4", "b4", "w5", "b5"]:
+        flat = params[name].reshape(-1)
+        for idx in rng.choice(flat.size, size=min(5, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            fp = gated(params)
+            flat[idx] = old - h
+            fm = gated(params)
+            flat[idx] = old
+            num = (fp - fm) / (2 * h)
+            ana = grads[name].reshape(-1)[idx]
+            assert abs(num - ana) <= 1e-8 + 1e-6 * abs(num), (name, idx, num, ana)
+
+
 def test_adam_first_step_moves_by_lr_times_sign():
     params = {"a": np.array([1.0, -2.0, 3.0])}
     grads = {"a": np.array([0.5, -4.0, 1e-3])}
