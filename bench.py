@@ -156,6 +156,16 @@ def cpu_baseline(chunks, fc, dms, lay, p, per_thread):
             "host": {"nproc": avail, "threads_used": threads, "cpu_model": model}}
 
 
+def weights_provenance(path):
+    """How the committed proposal weights were trained (from the file's metadata)."""
+    import json
+
+    import numpy as np
+    with np.load(path) as z:
+        meta = json.loads(str(z["meta"])) if "meta" in z else {}
+    return "trained in %s on %s tiles" % (meta.get("precision", "fp32"), meta.get("tiles", "?"))
+
+
 def learned_form(make_plan, dms, chunks, pulses, p, out, steps, plain_ms):
     """Learned proposal on the same stream: power tile + network + coherent
     processing of the top 10% of DM trials (full sweep if the proposal falls back).
@@ -174,6 +184,7 @@ def learned_form(make_plan, dms, chunks, pulses, p, out, steps, plain_ms):
     plan = make_plan(compact_records=True)
     plan.set_dm_trials(dms)
     prop = Proposal(plan, load_weights(wpath), budget=0.1)
+    prec, wmeta = prop.net.precision, weights_provenance(wpath)
 
     def step():
         plan.reset_stream()
@@ -201,6 +212,7 @@ def learned_form(make_plan, dms, chunks, pulses, p, out, steps, plain_ms):
         ms, plain_ms, int(mask.sum()), fb, sum(hits), len(hits)))
     return {"speedup": plain_ms / ms, "ms_per_step": ms, "active_dms": int(mask.sum()), "n_dm": p["n_dm"],
             "fallback": bool(fb), "recall": sum(hits) / len(hits), "pulses": len(hits),
+            "network": "%s convolutions, weights %s" % (prec, wmeta),
             "note": "tile + network + active-DM sweep on the same stream, records of the proposed DMs only; "
                     "recall = injected pulses whose DM trial "
                     "(either neighbour) is active"}
@@ -231,6 +243,7 @@ def recall_study(dev, n_streams=100, seed0=5000, log_every=10):
                 compact_records=True)
     plan.set_dm_trials(dms)
     prop = Proposal(plan, load_weights(wpath), budget=0.1)
+    network = "%s convolutions, weights %s" % (prop.net.precision, weights_provenance(wpath))
     gen = torch.Generator(device=dev)
     gen.manual_seed(seed0)
     rng = np.random.Generator(np.random.PCG64(seed0))
@@ -312,7 +325,7 @@ def recall_study(dev, n_streams=100, seed0=5000, log_every=10):
     pv, pm = np.array(peaks_v), np.array(peaks_m)
     rec = {"streams": n_streams, "pulses": tot, "kept": hits, "recall": hits / tot,
            "recall_of_sweep_recoverable": hits / max(recoverable, 1), "misses_judged_by_full_sweep": judged,
-           "fallbacks": fallbacks, "seconds": round(time.time() - t0, 1),
+           "fallbacks": fallbacks, "seconds": round(time.time() - t0, 1), "network": network,
            "tile_validation": {"peak_z_voltage_median": round(float(np.median(pv)), 3),
                                "peak_z_power_model_median": round(float(np.median(pm)), 3),
                                "peak_ratio_median": round(float(np.median(pv / pm)), 4),

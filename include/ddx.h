@@ -367,9 +367,30 @@ int ddx_cnn_set_weights(ddx_cnn* net, const float* host_params, int64_t n);
 int ddx_cnn_get_weights(ddx_cnn* net, float* host_params, int64_t n);
 int ddx_cnn_get_grads(ddx_cnn* net, float* host_grads, int64_t n);
 
+/* Arithmetic of the three convolutions (forward, backward data, backward weights).
+ * DDX_CNN_FP32 (the default): FP32 on the vector units.  DDX_CNN_FP16: operands
+ * rounded to IEEE binary16 (RNE) and multiplied on the matrix cores with FP32
+ * accumulation; every operand tile (a layer's weights, a row's window of 64 time
+ * steps of activations or gradients) is first multiplied by a power of two that
+ * puts its largest magnitude in [2^13, 2^14), undone exactly on the FP32 result.
+ * Parameters, biases, pooling, the linear layer, the loss and Adam stay FP32 in
+ * either form.  Changing the precision discards the last forward pass (run
+ * ddx_cnn_forward again before ddx_cnn_loss / ddx_cnn_backward).  DDX_EINVAL for any
+ * other value. */
+#define DDX_CNN_FP32 0
+#define DDX_CNN_FP16 1
+int ddx_cnn_set_precision(ddx_cnn* net, int32_t precision);
+
 /* Scores of every row of n_tiles tiles: d_tiles [n_tiles][n_dm][n_bins] (device),
  * d_scores [n_tiles * n_dm] (device).  Asynchronous on hip_stream. */
 int ddx_cnn_forward(ddx_cnn* net, const float* d_tiles, int32_t n_tiles, float* d_scores, void* hip_stream);
+
+/* Activations of layer 1..4 (after the ReLU) from the last forward pass, copied
+ * to host memory: [rows][32][n_bins / 2^(layer-1)], rows = n_tiles * n_dm; count
+ * must be that size (DDX_EINVAL otherwise, DDX_ESTATE before a forward pass).
+ * Synchronises the device.  The pooling takes, per row and channel, the first
+ * time index of layer 4's maximum. */
+int ddx_cnn_get_activations(ddx_cnn* net, int32_t layer, float* host_acts, int64_t count);
 
 /* After a forward pass: per-row logistic loss softplus(s) - y s into
  * d_loss_rows [rows] and its gradient (sigmoid(s) - y) / rows kept for backward. */

@@ -94,6 +94,8 @@ SIGNATURES = {
     "ddx_cnn_set_weights": ([ct.c_void_p, ct.POINTER(ct.c_float), ct.c_int64], ct.c_int),
     "ddx_cnn_get_weights": ([ct.c_void_p, ct.POINTER(ct.c_float), ct.c_int64], ct.c_int),
     "ddx_cnn_get_grads": ([ct.c_void_p, ct.POINTER(ct.c_float), ct.c_int64], ct.c_int),
+    "ddx_cnn_set_precision": ([ct.c_void_p, ct.c_int32], ct.c_int),
+    "ddx_cnn_get_activations": ([ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_float), ct.c_int64], ct.c_int),
     "ddx_cnn_forward": ([ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p], ct.c_int),
     "ddx_cnn_loss": ([ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p], ct.c_int),
     "ddx_cnn_backward": ([ct.c_void_p, ct.c_void_p], ct.c_int),
@@ -405,7 +407,9 @@ class Plan:
 class Cnn:
     """The DM-proposal network of include/ddx.h (ddx_cnn_*)."""
 
-    def __init__(self, n_dm, n_bins, max_tiles):
+    PRECISIONS = {"fp32": 0, "fp16": 1}
+
+    def __init__(self, n_dm, n_bins, max_tiles, precision="fp32"):
         L = lib()
         n = ct.c_int64()
         L.ddx_cnn_num_params(ct.byref(n))
@@ -416,6 +420,14 @@ class Cnn:
             raise DdxError(rc, "ddx_cnn_create")
         self._h = h
         self.n_dm, self.n_bins, self.max_tiles = n_dm, n_bins, max_tiles
+        self.set_precision(precision)
+
+    def set_precision(self, precision):
+        """'fp32' (vector units) or 'fp16' (binary16 operands on the matrix cores)."""
+        if precision not in self.PRECISIONS:
+            raise ValueError("precision must be one of %s" % sorted(self.PRECISIONS))
+        self._check(lib().ddx_cnn_set_precision(self._h, self.PRECISIONS[precision]), "ddx_cnn_set_precision")
+        self.precision = precision
 
     def _check(self, rc, what):
         if rc != OK:
@@ -436,6 +448,13 @@ class Cnn:
         a = np.empty(self.n_params, dtype=np.float32)
         self._check(lib().ddx_cnn_get_grads(self._h, a.ctypes.data_as(ct.POINTER(ct.c_float)), a.size),
                     "ddx_cnn_get_grads")
+        return a
+
+    def get_activations(self, layer, rows):
+        """Layer 1..4's activations of the last forward pass, float32 [rows, 32, n_bins >> (layer - 1)]."""
+        a = np.empty((rows, 32, self.n_bins >> (layer - 1)), dtype=np.float32)
+        self._check(lib().ddx_cnn_get_activations(self._h, layer, a.ctypes.data_as(ct.POINTER(ct.c_float)), a.size),
+                    "ddx_cnn_get_activations")
         return a
 
     def forward(self, tiles, scores=None, stream=None):

@@ -34,6 +34,9 @@ struct ddx_cnn {
   float *stats = nullptr, *h[4] = {nullptr, nullptr, nullptr, nullptr}, *gh[4] = {nullptr, nullptr, nullptr, nullptr};
   float *g = nullptr, *ds = nullptr, *part = nullptr, *partb = nullptr;
   int32_t* arg = nullptr;
+  int precision = DDX_CNN_FP32;
+  _Float16* wh = nullptr;  // binary16 weights of the FP16 form (k_cnn_weights_h)
+  float* wscale = nullptr;  // their per-layer powers of two
   // state of the last forward
   const float* tiles = nullptr;
   float* scores = nullptr;
@@ -109,6 +112,8 @@ int ddx_cnn_create(int32_t n_dm, int32_t n_bins, int32_t max_tiles, ddx_cnn** ou
   rc |= calloc_dev(n, (void**)&n->ds, R * 4);
   rc |= calloc_dev(n, (void**)&n->part, (size_t)kChunks * kNW * 4);
   rc |= calloc_dev(n, (void**)&n->partb, (size_t)kChunks * kW * 4);
+  rc |= calloc_dev(n, (void**)&n->wh, (size_t)ddx::kCnnHalfTotal * sizeof(_Float16));
+  rc |= calloc_dev(n, (void**)&n->wscale, 4 * sizeof(float));
   if (rc) {
     for (void* a : n->allocs) (void)hipFree(a);
     delete n;
@@ -140,10 +145,30 @@ int ddx_cnn_get_weights(ddx_cnn* n, float* host, int64_t count) {
   return DDX_OK;
 }
 
+int ddx_cnn_set_precision(ddx_cnn* n, int32_t precision) {
+  if (!n) return DDX_EINVAL;
+  if (precision != DDX_CNN_FP32 && precision != DDX_CNN_FP16)
+    return cfail(n, DDX_EINVAL, "precision must be DDX_CNN_FP32 or DDX_CNN_FP16");
+  n->precision = precision;
+  n->have_forward = n->have_loss = false;  // a backward pass follows a forward pass of its own precision
+  return DDX_OK;
+}
+
 int ddx_cnn_get_grads(ddx_cnn* n, float* host, int64_t count) {
   if (!n || !host || count != kNParams) return cfail(n, DDX_EINVAL, "need %lld parameters", (long long)kNParams);
   CCHECK(n, hipDeviceSynchronize());
   CCHECK(n, hipMemcpy(host, n->grads, kNParams * 4, hipMemcpyDeviceToHost));
+  return DDX_OK;
+}
+
+int ddx_cnn_get_activations(ddx_cnn* n, int32_t layer, float* host, int64_t count) {
+  if (!n) return DDX_EINVAL;
+  if (!n->have_forward) return cfail(n, DDX_ESTATE, "run ddx_cnn_forward first");
+  if (layer < 1 || layer > 4 || !host) return cfail(n, DDX_EINVAL, "layer must be 1..4 and the buffer non-null");
+  const int64_t need = (int64_t)n->rows * kW * (n->n_bins >> (layer - 1));
+  if (count != need) return cfail(n, DDX_EINVAL, "layer %d holds %lld values", layer, (long long)need);
+  CCHECK(n, hipDeviceSynchronize());
+  CCHECK(n, hipMemcpy(host, n->h[layer - 1], need * 4, hipMemcpyDeviceToHost));
   return DDX_OK;
 }
 
@@ -156,14 +181,27 @@ int ddx_cnn_forward(ddx_cnn* n, const float* tiles, int32_t n_tiles, float* scor
   hipLaunchKernelGGL(ddx::k_tile_stats, dim3(n_tiles), dim3(1024), 0, s, tiles, (int64_t)n->n_dm * L, n->stats);
   CCHECK(n, hipGetLastError());
   const float* p = n->params;
-  hipLaunchKernelGGL((ddx::k_conv_fwd<3, 1, true>), dim3(L / 64, R), dim3(256), 0, s, tiles, n->stats, n->n_dm, L,
-                     p + kOffW[0], p + kOffB[0], n->h[0]);
+  const bool h16 = n->precision == DDX_CNN_FP16;
+  if (h16) {
+    hipLaunchKernelGGL(ddx::k_cnn_weights_h, dim3(4), dim3(256), 0, s, p, kOffW[0], kOffW[1], kOffW[2], kOffW[3],
+                       n->wh, n->wscale);
+    CCHECK(n, hipGetLastError());
+    hipLaunchKernelGGL((ddx::k_conv_fwd_h<3, 1, true>), dim3(L / 64, R), dim3(256), 0, s, tiles, n->stats, n->n_dm,
+                       L, n->wh + ddx::kCnnHalfOff[0], n->wscale, p + kOffB[0], n->h[0]);
+  } else {
+    hipLaunchKernelGGL((ddx::k_conv_fwd<3, 1, true>), dim3(L / 64, R), dim3(256), 0, s, tiles, n->stats, n->n_dm, L,
+                       p + kOffW[0], p + kOffB[0], n->h[0]);
+  }
   CCHECK(n, hipGetLastError());
   int lin = L;
   for (int l = 1; l < 4; ++l) {
     const int lout = lin / 2;
-    hipLaunchKernelGGL((ddx::k_conv_fwd<kW, 2, false>), dim3((lout + 63) / 64, R), dim3(256), 0, s, n->h[l - 1],
-                       n->stats, n->n_dm, lin, p + kOffW[l], p + kOffB[l], n->h[l]);
+    if (h16)
+      hipLaunchKernelGGL((ddx::k_conv_fwd_h<kW, 2, false>), dim3((lout + 63) / 64, R), dim3(256), 0, s, n->h[l - 1],
+                         n->stats, n->n_dm, lin, n->wh + ddx::kCnnHalfOff[l], n->wscale + l, p + kOffB[l], n->h[l]);
+    else
+      hipLaunchKernelGGL((ddx::k_conv_fwd<kW, 2, false>), dim3((lout + 63) / 64, R), dim3(256), 0, s, n->h[l - 1],
+                         n->stats, n->n_dm, lin, p + kOffW[l], p + kOffB[l], n->h[l]);
     CCHECK(n, hipGetLastError());
     lin = lout;
   }
@@ -205,25 +243,38 @@ int ddx_cnn_backward(ddx_cnn* n, void* stream) {
   CCHECK(n, hipGetLastError());
   const int chunks = kChunks < R ? kChunks : R;
   const int per = (R + chunks - 1) / chunks;
+  const bool h16 = n->precision == DDX_CNN_FP16;  // the forward pass of this precision left n->wh, n->wscale
   for (int l = 3; l >= 0; --l) {
     const int64_t nl = (int64_t)R * kW * len[l];
     hipLaunchKernelGGL(ddx::k_relu_bwd, dim3(blocks(nl)), dim3(256), 0, s, n->gh[l], n->h[l], nl);
     CCHECK(n, hipGetLastError());
     const int nw = l == 0 ? (int)kNW1 : (int)kNW;
     if (l == 0) {
-      hipLaunchKernelGGL((ddx::k_conv_bwd_w<3, 1, true>), dim3(chunks), dim3(256), 0, s, n->gh[0], len[0], n->tiles,
-                         n->stats, n->n_dm, L, R, per, n->part, n->partb);
+      if (h16)
+        hipLaunchKernelGGL((ddx::k_conv_bwd_w_h<3, 1, true>), dim3(chunks), dim3(256), 0, s, n->gh[0], len[0],
+                           n->tiles, n->stats, n->n_dm, L, R, per, n->part, n->partb);
+      else
+        hipLaunchKernelGGL((ddx::k_conv_bwd_w<3, 1, true>), dim3(chunks), dim3(256), 0, s, n->gh[0], len[0],
+                           n->tiles, n->stats, n->n_dm, L, R, per, n->part, n->partb);
     } else {
-      hipLaunchKernelGGL((ddx::k_conv_bwd_w<kW, 2, false>), dim3(chunks), dim3(256), 0, s, n->gh[l], len[l],
-                         n->h[l - 1], n->stats, n->n_dm, len[l - 1], R, per, n->part, n->partb);
+      if (h16)
+        hipLaunchKernelGGL((ddx::k_conv_bwd_w_h<kW, 2, false>), dim3(chunks), dim3(256), 0, s, n->gh[l], len[l],
+                           n->h[l - 1], n->stats, n->n_dm, len[l - 1], R, per, n->part, n->partb);
+      else
+        hipLaunchKernelGGL((ddx::k_conv_bwd_w<kW, 2, false>), dim3(chunks), dim3(256), 0, s, n->gh[l], len[l],
+                           n->h[l - 1], n->stats, n->n_dm, len[l - 1], R, per, n->part, n->partb);
     }
     CCHECK(n, hipGetLastError());
     hipLaunchKernelGGL(ddx::k_reduce_chunks, dim3(blocks(nw + kW)), dim3(256), 0, s, n->part, n->partb, chunks, nw,
                        gr + kOffW[l], gr + kOffB[l]);
     CCHECK(n, hipGetLastError());
     if (l > 0) {
-      hipLaunchKernelGGL((ddx::k_conv_bwd_data<2>), dim3((len[l - 1] + 63) / 64, R), dim3(256), 0, s, n->gh[l], len[l],
-                         p + kOffW[l], len[l - 1], n->gh[l - 1]);
+      if (h16)
+        hipLaunchKernelGGL(ddx::k_conv_bwd_data_h, dim3((len[l - 1] + 63) / 64, R), dim3(256), 0, s, n->gh[l], len[l],
+                           n->wh + ddx::kCnnHalfOff[l] + kNW, n->wscale + l, len[l - 1], n->gh[l - 1]);
+      else
+        hipLaunchKernelGGL((ddx::k_conv_bwd_data<2>), dim3((len[l - 1] + 63) / 64, R), dim3(256), 0, s, n->gh[l],
+                           len[l], p + kOffW[l], len[l - 1], n->gh[l - 1]);
       CCHECK(n, hipGetLastError());
     }
   }

@@ -43,14 +43,14 @@ def load_weights(path):
 class Proposal:
     """Tile -> scores -> active-DM mask for one plan."""
 
-    def __init__(self, plan, weights, budget=0.1, threshold=0.5, bin_len=1024, n_bins=1024):
+    def __init__(self, plan, weights, budget=0.1, threshold=0.5, bin_len=1024, n_bins=1024, precision="fp16"):
         lay = plan.layout()
         self.plan = plan
         self.n_dm = int(lay["n_dm"][0])
         self.k = int(math.ceil(budget * self.n_dm))
         self.threshold = threshold
         self.bin_len, self.n_bins = bin_len, n_bins
-        self.net = Cnn(self.n_dm, n_bins, 1)
+        self.net = Cnn(self.n_dm, n_bins, 1, precision=precision)
         self.net.set_weights(weights)
         self.tile = None
         self.scores = None

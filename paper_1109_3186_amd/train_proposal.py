@@ -46,7 +46,7 @@ def he_init(seed):
     return flatten(params)
 
 
-def train(n_tiles, batch, lr, seed, fine=32, log_every=200, out=None):
+def train(n_tiles, batch, lr, seed, fine=32, log_every=200, out=None, precision="fp32"):
     import numpy as np
     import torch
 
@@ -55,7 +55,7 @@ def train(n_tiles, batch, lr, seed, fine=32, log_every=200, out=None):
     dev = torch.device("cuda:0")
     p = synth.c1_params()
     plan = make_plan(p)
-    net = Cnn(p["n_dm"], 1024, batch)
+    net = Cnn(p["n_dm"], 1024, batch, precision=precision)
     net.set_weights(he_init(seed))
     rng = np.random.Generator(np.random.PCG64(seed))
     gen = torch.Generator(device=dev)
@@ -78,7 +78,8 @@ def train(n_tiles, batch, lr, seed, fine=32, log_every=200, out=None):
     w = net.get_weights()
     if out:
         np.savez(out, params=w, meta=np.array(json.dumps({"tiles": n_tiles, "batch": batch, "lr": lr, "seed": seed,
-                                                          "fine": fine, "seconds": time.time() - t0})))
+                                                          "fine": fine, "precision": precision,
+                                                          "seconds": time.time() - t0})))
     net.close()
     plan.close()
     return w, hist
@@ -90,9 +91,10 @@ def main():
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=1114)
+    ap.add_argument("--precision", choices=["fp32", "fp16"], default="fp32")
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "proposal_weights.npz"))
     a = ap.parse_args()
-    train(a.tiles, a.batch, a.lr, a.seed, out=a.out)
+    train(a.tiles, a.batch, a.lr, a.seed, out=a.out, precision=a.precision)
 
 
 if __name__ == "__main__":

@@ -89,6 +89,96 @@ def test_cnn_forward_backward_adam_match_oracle(gpu):
     net.close()
 
 
+@pytest.mark.parametrize("level", [1.0, 2.0 ** -6])
+def test_cnn_fp16_forward_backward_match_oracle(gpu, level):
+    """FP16 matrix-core form (binary16 operands, FP32 accumulation) against the FP64
+    oracle: scores within 1e-2 of the largest |score|, the mean loss within 1e-2, and
+    every gradient tensor within 1e-2 (relative, norm) of the analytic backward taken
+    through the same ReLU gates and pooling maxima as the kernels' forward pass (a
+    unit whose pre-activation is within binary16 rounding of zero can pass on one
+    side and not the other, and that decision, not the arithmetic, would then decide
+    the difference; the kernels' decisions are read from their activations).  At
+    level 2^-6 each layer's W and b are scaled so that its activations are level^l
+    times the unscaled ones (W_l by level, b_l by level^l) and w5 by level^-4, so the
+    scores are those of the unscaled network while h4 ~ 2^-24 and its gradients sit
+    far below binary16's normal range: only the per-tile power-of-two scales keep
+    the products exact to binary16 precision there."""
+    import torch
+
+    from paper_1109_3186_amd import Cnn
+    from paper_1109_3186_amd.proposal import unflatten
+    rng = np.random.Generator(np.random.PCG64(43))
+    d, L, nt = 16, 128, 2
+    tiles = rng.standard_normal((nt, d, L)) * 3 + 10
+    tiles[0, 5, 40:44] += 30
+    params = P.init_params(44)
+    params["b1"] = rng.standard_normal(32) * 0.1
+    params["b5"] = np.array([0.3])
+    for l in range(1, 5):
+        params["W%d" % l] = params["W%d" % l] * level
+        params["b%d" % l] = params["b%d" % l] * level ** l
+    params["w5"] = params["w5"] * level ** -4
+    labels = (rng.random(nt * d) < 0.3).astype(np.float64)
+    net = Cnn(d, L, nt, precision="fp16")
+    net.set_weights(_flat(params))
+    t_dev = torch.from_numpy(tiles.astype(np.float32)).to(gpu)
+    scores = net.forward(t_dev).cpu().numpy()
+    x = np.concatenate([P.rows3(P.standardise(tiles[i])) for i in range(nt)])
+    ref, cache = P.forward(params, x)
+    serr = np.max(np.abs(scores - ref)) / max(1.0, np.abs(ref).max())
+    loss_rows = net.loss(torch.from_numpy(labels.astype(np.float32)).to(gpu)).cpu().numpy()
+    lref, ds = P.loss_and_grad(ref, labels)
+    say("FP16 level %g: scores max error %.2e of max |score|, loss %.6f vs %.6f" % (level, serr, loss_rows.mean(), lref))
+    assert serr <= 1e-2
+    assert abs(loss_rows.mean() - lref) <= 1e-2 * max(1.0, abs(lref))
+    net.backward()
+    g = unflatten(net.get_grads())
+    acts = [net.get_activations(l, nt * d).astype(np.float64) for l in range(1, 5)]
+    dec = {"gates": [a > 0 for a in acts], "arg": np.argmax(acts[3], axis=2)}
+    flips = sum(int(np.sum(a != (b > 0))) for a, b in zip(dec["gates"], cache["acts"][1:]))
+    say("FP16 level %g: %d ReLU gates and %d maxima taken the other way than in FP64" %
+        (level, flips, int(np.sum(dec["arg"] != cache["arg"]))))
+    gref = P.backward(params, cache, ds, decisions=dec)
+    gown = P.backward(params, cache, ds)
+    worst = 0.0
+    for k in gref:
+        rel = np.linalg.norm(g[k] - gref[k]) / max(np.linalg.norm(gref[k]), 1e-300)
+        own = np.linalg.norm(g[k] - gown[k]) / max(np.linalg.norm(gown[k]), 1e-300)
+        worst = max(worst, rel)
+        say("FP16 level %g grad %s rel %.2e (oracle's own decisions %.2e; |g| %.2e)" %
+            (level, k, rel, own, np.linalg.norm(gref[k])))
+        assert rel <= 1e-2, k
+    assert worst > 1e-7  # binary16 operands: not the FP32 form by mistake
+    net.close()
+
+
+def test_cnn_precision_switch(gpu):
+    """Changing the precision discards the last forward pass; both forms score the
+    same tiles alike (within binary16 rounding), and an unknown value is refused."""
+    import torch
+
+    from paper_1109_3186_amd import Cnn
+    from paper_1109_3186_amd.binding import DdxError
+    rng = np.random.Generator(np.random.PCG64(46))
+    d, L = 32, 256
+    tiles = torch.from_numpy((rng.standard_normal((1, d, L)) * 2 + 5).astype(np.float32)).to(gpu)
+    net = Cnn(d, L, 1)
+    net.set_weights(_flat(P.init_params(46)))
+    s32 = net.forward(tiles).cpu().numpy()
+    net.set_precision("fp16")
+    with pytest.raises(DdxError):
+        net.loss(torch.zeros(d, device=gpu))
+    s16 = net.forward(tiles).cpu().numpy()
+    err = np.max(np.abs(s16 - s32)) / max(1.0, np.abs(s32).max())
+    say("FP16 vs FP32 scores: max %.2e of max |score|" % err)
+    assert 0 < err <= 1e-2
+    with pytest.raises(ValueError):
+        net.set_precision("bf16")
+    from paper_1109_3186_amd.binding import lib
+    assert lib().ddx_cnn_set_precision(net._h, 7) != 0
+    net.close()
+
+
 def test_cnn_adam_several_steps_match_oracle(gpu):
     """Adam past its first step: (1) with the gradients held fixed, k steps move every
     weight by exactly k lr g / (|g| + eps) (the bias-corrected moments are g and g^2 at
@@ -144,7 +234,8 @@ def test_cnn_adam_several_steps_match_oracle(gpu):
     net.close()
 
 
-def test_overfit_tiny_batch(gpu):
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_overfit_tiny_batch(gpu, precision):
     """Training on two fixed tiles drives the loss down and ranks the labelled rows first."""
     import torch
 
@@ -158,7 +249,7 @@ def test_overfit_tiny_batch(gpu):
     power, labels, pulses = synth.power_batch(p, 2, 32, rng, gen, gpu, pulse_frac=1.0, snr_range=(30.0, 40.0),
                                               max_pulses=1)
     tiles = plan.tiles_from_power(power, 32, 1024, 1024)
-    net = Cnn(p["n_dm"], 1024, 2)
+    net = Cnn(p["n_dm"], 1024, 2, precision=precision)
     net.set_weights(he_init(1))
     first = None
     for it in range(150):
@@ -167,7 +258,7 @@ def test_overfit_tiny_batch(gpu):
         first = loss if first is None else first
         net.backward()
         net.adam(lr=3e-3)
-    say("overfit loss %.4f -> %.4f" % (first, loss))
+    say("%s overfit loss %.4f -> %.4f" % (precision, first, loss))
     assert loss < 0.2 * first
     s = scores.cpu().numpy().reshape(2, -1)
     y = labels.cpu().numpy()
@@ -206,13 +297,13 @@ def test_trained_network_recall_and_gain(gpu, snr):
     rng = np.random.Generator(np.random.PCG64(9001 if snr[1] > 10 else 9002))
     gen = torch.Generator(device=gpu)
     gen.manual_seed(9001 if snr[1] > 10 else 9002)
-    nets = {"trained": load_weights(WEIGHTS), "untrained": he_init(1114)}
+    nets = {"trained": load_weights(WEIGHTS), "trained_fp16": load_weights(WEIGHTS), "untrained": he_init(1114)}
     k = int(math.ceil(0.1 * p["n_dm"]))
     res = {n: [] for n in list(nets) + ["rowmax"]}
     allpulses = []
     cnns = {}
     for name, w in nets.items():
-        cnns[name] = Cnn(p["n_dm"], 1024, 8)
+        cnns[name] = Cnn(p["n_dm"], 1024, 8, precision="fp16" if name.endswith("fp16") else "fp32")
         cnns[name].set_weights(w)
     for b in range(50):
         power, labels, pulses = synth.power_batch(p, 8, 32, rng, gen, gpu, pulse_frac=1.0, max_pulses=1,
@@ -229,10 +320,11 @@ def test_trained_network_recall_and_gain(gpu, snr):
         out[name] = _recall(sc, allpulses, k, p["dm_max"] / p["n_dm"])
     say("S/N %s: recall at top %d of %d rows over %d pulses: %s" % (snr, k, p["n_dm"], out["trained"][1],
                                                                     {n: round(v[0], 4) for n, v in out.items()}))
-    if snr[1] > 10:
-        assert out["trained"][0] >= 0.99
-        assert out["trained"][0] >= out["untrained"][0] + 0.2
-    assert out["trained"][0] >= out["rowmax"][0]
+    for name in ("trained", "trained_fp16"):
+        if snr[1] > 10:
+            assert out[name][0] >= 0.99
+            assert out[name][0] >= out["untrained"][0] + 0.2
+        assert out[name][0] >= out["rowmax"][0]
     for n in cnns.values():
         n.close()
     plan.close()
