@@ -46,7 +46,7 @@ def he_init(seed):
     return flatten(params)
 
 
-def train(n_tiles, batch, lr, seed, fine=32, log_every=200, out=None, precision="fp32"):
+def train(n_tiles, batch, lr, seed, fine=32, log_every=200, out=None, precision="fp16"):
     import numpy as np
     import torch
 
@@ -91,7 +91,7 @@ def main():
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=1114)
-    ap.add_argument("--precision", choices=["fp32", "fp16"], default="fp32")
+    ap.add_argument("--precision", choices=["fp32", "fp16"], default="fp16")
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "proposal_weights.npz"))
     a = ap.parse_args()
     train(a.tiles, a.batch, a.lr, a.seed, out=a.out, precision=a.precision)
