@@ -166,7 +166,7 @@ def weights_provenance(path):
     return "trained in %s on %s tiles" % (meta.get("precision", "fp32"), meta.get("tiles", "?"))
 
 
-def learned_form(make_plan, dms, chunks, pulses, p, out, steps, plain_ms):
+def learned_form(make_plan, dms, chunks, pulses, p, out, steps, plain_ms, plan_kw=None):
     """Learned proposal on the same stream: power tile + network + coherent
     processing of the top 10% of DM trials (full sweep if the proposal falls back).
     Its plan keeps compact records, so the visibilities produced and fetched are
@@ -181,8 +181,9 @@ def learned_form(make_plan, dms, chunks, pulses, p, out, steps, plain_ms):
     from paper_1109_3186_amd.proposal import Proposal, load_weights
     wpath = os.path.join(ROOT, "paper_1109_3186_amd", "proposal_weights.npz")
     full = torch.cat(chunks, dim=-1).contiguous()
-    plan = make_plan(compact_records=True)
+    plan = make_plan(compact_records=True, **(plan_kw or {}))
     plan.set_dm_trials(dms)
+    blocking = blocking_desc(plan.layout())
     prop = Proposal(plan, load_weights(wpath), budget=0.1)
     prec, wmeta = prop.net.precision, weights_provenance(wpath)
 
@@ -197,11 +198,20 @@ def learned_form(make_plan, dms, chunks, pulses, p, out, steps, plain_ms):
 
     step()
     torch.cuda.synchronize()
+    plan.set_profiling(True)
     t0 = time.perf_counter()
     for _ in range(steps):
         mask, fb = step()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
+    prof = plan.profile()
+    plan.set_profiling(False)
+    # the selection alone (tile, network, device top-k and the mask's copy), outside the timed steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        prop.select(full)
+    torch.cuda.synchronize()
+    select_ms = (time.perf_counter() - t0) * 1e3 / steps
     dstep = p["dm_max"] / p["n_dm"]
     hits = [int(mask[math.floor(q["dm"] / dstep)] or mask[min(math.ceil(q["dm"] / dstep), p["n_dm"] - 1)])
             for q in pulses]
@@ -212,7 +222,10 @@ def learned_form(make_plan, dms, chunks, pulses, p, out, steps, plain_ms):
         ms, plain_ms, int(mask.sum()), fb, sum(hits), len(hits)))
     return {"speedup": plain_ms / ms, "ms_per_step": ms, "active_dms": int(mask.sum()), "n_dm": p["n_dm"],
             "fallback": bool(fb), "recall": sum(hits) / len(hits), "pulses": len(hits),
-            "network": "%s convolutions, weights %s" % (prec, wmeta),
+            "network": "%s convolutions, weights %s" % (prec, wmeta), "select_ms": round(select_ms, 2),
+            "blocking": blocking,
+            "kernels_ms": {k: round(v["time_ms"] / steps, 1) for k, v in prof.items()},
+            "launches": {k: v["launches"] // steps for k, v in prof.items()},
             "note": "tile + network + active-DM sweep on the same stream, records of the proposed DMs only; "
                     "recall = injected pulses whose DM trial "
                     "(either neighbour) is active"}
@@ -1076,7 +1089,10 @@ def main():
     roofline = roofline_of(prof, args, path, ms)
     learned = None
     if not args.no_learned:
-        learned = learned_form(make_plan, dms, chunks, pulses, p, out, args.steps, ms)
+        # one blocking class per channel: with a tenth of the trials active, each class's
+        # forward transforms serve few DMs, and one 32768-point class measured fastest
+        learned = learned_form(make_plan, dms, chunks, pulses, p, out, args.steps, ms,
+                               plan_kw={"dm_classes": "single"})
     del out
     plan.close()
     c3 = None
