@@ -251,14 +251,14 @@ int ddx_cnn_backward(ddx_cnn* n, void* stream) {
     const int nw = l == 0 ? (int)kNW1 : (int)kNW;
     if (l == 0) {
       if (h16)
-        hipLaunchKernelGGL((ddx::k_conv_bwd_w_h<3, 1, true>), dim3(chunks), dim3(256), 0, s, n->gh[0], len[0],
+        hipLaunchKernelGGL((ddx::k_conv_bwd_w_h<3, 1, true, 256>), dim3(chunks), dim3(256), 0, s, n->gh[0], len[0],
                            n->tiles, n->stats, n->n_dm, L, R, per, n->part, n->partb);
       else
         hipLaunchKernelGGL((ddx::k_conv_bwd_w<3, 1, true>), dim3(chunks), dim3(256), 0, s, n->gh[0], len[0],
                            n->tiles, n->stats, n->n_dm, L, R, per, n->part, n->partb);
     } else {
       if (h16)
-        hipLaunchKernelGGL((ddx::k_conv_bwd_w_h<kW, 2, false>), dim3(chunks), dim3(256), 0, s, n->gh[l], len[l],
+        hipLaunchKernelGGL((ddx::k_conv_bwd_w_h<kW, 2, false, 128>), dim3(chunks), dim3(256), 0, s, n->gh[l], len[l],
                            n->h[l - 1], n->stats, n->n_dm, len[l - 1], R, per, n->part, n->partb);
       else
         hipLaunchKernelGGL((ddx::k_conv_bwd_w<kW, 2, false>), dim3(chunks), dim3(256), 0, s, n->gh[l], len[l],

@@ -152,6 +152,46 @@ def test_cnn_fp16_forward_backward_match_oracle(gpu, level):
     net.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_cnn_ragged_shape_matches_oracle(gpu, precision):
+    """192 bins (layers of 192, 96, 48, 24 steps: every layer ends in a partial
+    64-step tile, and the last is shorter than one), 5 DM rows (edge rows repeated
+    on both sides of every tile), 3 tiles of different levels: scores, and the
+    gradients through the kernels' own gates and maxima, against the FP64 oracle."""
+    import torch
+
+    from paper_1109_3186_amd import Cnn
+    from paper_1109_3186_amd.proposal import unflatten
+    rng = np.random.Generator(np.random.PCG64(50))
+    d, L, nt = 5, 192, 3
+    tiles = rng.standard_normal((nt, d, L)) * np.array([1.0, 30.0, 0.01])[:, None, None] + 7
+    tiles[1, 0, 180:190] += 200.0  # a bump in the last partial tile of an edge row
+    params = P.init_params(51)
+    for l in range(1, 5):
+        params["b%d" % l] = rng.standard_normal(32) * 0.05
+    labels = (rng.random(nt * d) < 0.4).astype(np.float64)
+    net = Cnn(d, L, nt, precision=precision)
+    net.set_weights(_flat(params))
+    scores = net.forward(torch.from_numpy(tiles.astype(np.float32)).to(gpu)).cpu().numpy()
+    x = np.concatenate([P.rows3(P.standardise(tiles[i])) for i in range(nt)])
+    ref, cache = P.forward(params, x)
+    tol = 1e-4 if precision == "fp32" else 1e-2
+    serr = np.max(np.abs(scores - ref)) / max(1.0, np.abs(ref).max())
+    net.loss(torch.from_numpy(labels.astype(np.float32)).to(gpu))
+    net.backward()
+    g = unflatten(net.get_grads())
+    acts = [net.get_activations(l, nt * d).astype(np.float64) for l in range(1, 5)]
+    assert [a.shape[-1] for a in acts] == [192, 96, 48, 24]
+    dec = {"gates": [a > 0 for a in acts], "arg": np.argmax(acts[3], axis=2)}
+    _, ds = P.loss_and_grad(ref, labels)
+    gref = P.backward(params, cache, ds, decisions=dec)
+    worst = max(np.linalg.norm(g[k] - gref[k]) / max(np.linalg.norm(gref[k]), 1e-300) for k in gref)
+    say("%s ragged: scores %.2e, worst gradient %.2e" % (precision, serr, worst))
+    assert serr <= tol
+    assert worst <= (1e-3 if precision == "fp32" else 1e-2)
+    net.close()
+
+
 def test_cnn_precision_switch(gpu):
     """Changing the precision discards the last forward pass; both forms score the
     same tiles alike (within binary16 rounding), and an unknown value is refused."""
