@@ -116,3 +116,67 @@ def quant_errors(cfg, vis, lay, quant, scales, skip_dm0=True):
             emu.append((np.abs(got - vq) / norm).ravel())
             exact.append((np.abs(got - vx) / norm).ravel())
     return np.concatenate(emu), np.concatenate(exact), np.concatenate(dm0)
+
+
+def _complex_volts(v):
+    """[M, S] complex from complex input or [M, 2S] interleaved int8."""
+    v = np.asarray(v)
+    if np.iscomplexobj(v):
+        return v.astype(np.complex128)
+    return v[..., 0::2].astype(np.float64) + 1j * v[..., 1::2].astype(np.float64)
+
+
+def tie_check(cfg, vis, lay, quant, scales, delta_rel=1e-4):
+    """Reduced-precision cross visibilities against the oracle emulating the same
+    rounding, with an allowance for rounding ties.  A scaled voltage component lying
+    within delta of a rounding midpoint (delta = delta_rel x the channel and DM's RMS
+    scaled component: the FP32 dedispersion's own error stays below it, by about an
+    order of magnitude) may round to either neighbour on the GPU; such a tie can move
+    V_ij (i < j) by at most the distance between its two candidates times the other
+    voltage's magnitude (both flipping: plus the product of the two distances).
+    Returns the normalised errors and allowances of every cross visibility (every
+    channel, DM and dump), whether each belongs to a DM-0 trial, the
+    autocorrelations' errors against the unrounded oracle, and the counts of tie
+    components and of all components (DM > 0)."""
+    m_ant = cfg["volts"].shape[1]
+    bl = blockings(lay)
+    iu, ju = np.triu_indices(m_ant)
+    cross = iu != ju
+    L = cfg["dump_len"]
+    errs, allows, autos, dm0 = [], [], [], []
+    n_tie = n_all = 0
+    for c in range(lay["n_chan"]):
+        x = _complex_volts(cfg["volts"][c])
+        s = float(scales[c])
+        ref = oracle.run_oracle(cfg["volts"], cfg["chan_freqs"], cfg["f_s"], cfg["dm_lists"], L, bl,
+                                sideband=int(lay["sideband"]), quant=quant, scales=scales, chans=[c])
+        for d, dm in enumerate(cfg["dm_lists"][c]):
+            b = bl[c][d] if isinstance(bl[c], (list, tuple)) else bl[c]
+            h = oracle.chirp(cfg["chan_freqs"][c], cfg["f_s"], b["fft_len"], dm, int(lay["sideband"]))
+            y = oracle.dedisperse_stream(x, h, b["fft_len"], b["valid"], b["lead"])
+            nd = y.shape[1] // L
+            vs = y[:, :nd * L] * s
+            delta = delta_rel * np.sqrt(np.mean(np.abs(vs) ** 2) / 2.0)
+            q = oracle.quantize(vs, quant)
+            lo = oracle.quantize(vs - delta * (1 + 1j), quant)
+            hi = oracle.quantize(vs + delta * (1 + 1j), quant)
+            dre, dim = np.abs(hi.real - lo.real), np.abs(hi.imag - lo.imag)
+            if dm != 0:
+                n_tie += int(np.count_nonzero(dre) + np.count_nonzero(dim))
+                n_all += 2 * vs.size
+            dq = np.hypot(dre, dim).reshape(m_ant, nd, L)
+            aq = np.abs(q).reshape(m_ant, nd, L)
+            allow = (np.einsum("ind,jnd->nij", dq, aq) + np.einsum("ind,jnd->nij", aq, dq)
+                     + np.einsum("ind,jnd->nij", dq, dq)) / (s * s)
+            v = ref[(c, d)]
+            got = select(vis, lay, c, d).astype(np.complex128)
+            assert got.shape == v.shape
+            auto = v[:, iu == ju].real
+            norm = np.sqrt(auto[:, iu] * auto[:, ju])
+            e = np.abs(got - v) / norm
+            errs.append(e[:, cross].ravel())
+            allows.append((oracle.pack_upper(allow) / norm)[:, cross].ravel())
+            autos.append(e[:, ~cross].ravel())
+            dm0.append(np.full(errs[-1].size, dm == 0))
+    return (np.concatenate(errs), np.concatenate(allows), np.concatenate(dm0), np.concatenate(autos), n_tie,
+            n_all)
