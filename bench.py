@@ -716,14 +716,32 @@ def c3_one_step(dev):
     return out
 
 
-def c3_measure(dev, steps, warmup, corr, use_autotune, n_passes):
-    """The batched sparse-array workload: 256 antennas, 32 x 1 MHz channels at
-    0.7-0.732 GHz, 2^18 ci8 samples, per-channel DM grids of 512..1536 trials over
-    0-3000 (transform lengths 2^17 / 2^18, two-pass).  Its 2.26 TB of visibilities
-    cannot be held, so one step runs the stream once per DM window: every channel's
-    DM list is cut into `passes` contiguous windows, the plan's compact records
-    hold one window's (channel, DM) pairs, and each pass fetches its dumps into a
-    device buffer that the next pass reuses."""
+def c1_schedule(p, full_fc, dms, corr, chunk, measure=False):
+    """Plan options of the 36-antenna workload: the autotuner's choice for the whole
+    64-channel workload (also when only some channels run, so that counter runs
+    see the headline's launch shapes), from the committed cache, or measured now
+    (measure=True); the automatic schedule without an entry.  Returns (plan
+    keyword arguments, a description)."""
+    from paper_1109_3186_amd import autotune
+    targs = (p["m_ant"], full_fc, p["f_s"], p["dump_len"], [dms] * len(full_fc))
+    tuned = (autotune.tune(*targs, corr_dtype=corr, max_block=chunk, log=log) if measure
+             else autotune.cached(*targs, corr_dtype=corr, max_block=chunk))
+    if not tuned:
+        key, desc = autotune.workload_key(*targs, corr, "ci8", chunk)
+        log("no tuned entry for key %s (device %r): automatic schedule" % (key, desc["device"]))
+        return {}, {"source": "automatic"}
+    log("tuned (%s): cost model inverse %s ps, forward %s ps per point (N 2^8..2^18), wave %d group %d" % (
+        tuned["source"], [round(v, 2) for v in tuned["cost_ps"][0]],
+        [round(v, 2) for v in tuned["cost_ps"][1]], tuned["wave_units"], tuned["dm_group"]))
+    return autotune.plan_kwargs(tuned), {"source": "autotuned (%s)" % tuned["source"],
+                                         "wave_units": tuned["wave_units"], "dm_group": tuned["dm_group"]}
+
+
+def c3_setup(dev, corr, use_autotune, n_passes):
+    """The 256-antenna workload's stream (on the device) and its plan in the
+    configuration c3_measure times: every channel's DM list cut into `passes`
+    contiguous windows, compact records holding one window's (channel, DM) pairs.
+    Returns a dict with p, x, fc, dms, plan, lay, passes, windows, masks, out."""
     import math
 
     import numpy as np
@@ -756,10 +774,9 @@ def c3_measure(dev, steps, warmup, corr, use_autotune, n_passes):
     for c, d in enumerate(dms):
         plan.set_dm_trials(d, chan=c)
     lay = plan.layout()
-    nbl = lay["n_baselines"]
     log("C3 plan: %s, %d passes of <= %d pairs, ring %d dumps, %.1f GB device" % (
         blocking_desc(lay), passes, max_pairs, ring, lay["device_bytes"] / 1e9))
-    out = torch.empty((ring, max_pairs * nbl), dtype=torch.complex64, device=dev)
+    out = torch.empty((ring, max_pairs * lay["n_baselines"]), dtype=torch.complex64, device=dev)
     masks = []
     for k in range(passes):
         mk = []
@@ -768,17 +785,38 @@ def c3_measure(dev, steps, warmup, corr, use_autotune, n_passes):
             m[windows[c][k]] = 1
             mk.append(m)
         masks.append(mk)
+    return {"p": p, "x": x, "fc": fc, "dms": dms, "plan": plan, "lay": lay, "passes": passes, "windows": windows,
+            "masks": masks, "out": out}
+
+
+def c3_pass(st, k):
+    """Pass k of the 256-antenna step: the stream once through the plan with DM
+    window k active; returns the number of dumps fetched into st["out"]."""
+    plan = st["plan"]
+    plan.reset_stream()
+    for c in range(st["p"]["n_chan"]):
+        plan.set_active_dms(st["masks"][k][c], chan=c)
+    plan.process_block(st["x"], flush=True)
+    _, nd, _ = plan.fetch(out=st["out"])
+    return nd
+
+
+def c3_measure(dev, steps, warmup, corr, use_autotune, n_passes):
+    """The batched sparse-array workload: 256 antennas, 32 x 1 MHz channels at
+    0.7-0.732 GHz, 2^18 ci8 samples, per-channel DM grids of 512..1536 trials over
+    0-3000 (transform lengths 2^17 / 2^18, two-pass).  Its 2.26 TB of visibilities
+    cannot be held, so one step runs the stream once per DM window: every channel's
+    DM list is cut into `passes` contiguous windows, the plan's compact records
+    hold one window's (channel, DM) pairs, and each pass fetches its dumps into a
+    device buffer that the next pass reuses."""
+    import torch
+
+    st = c3_setup(dev, corr, use_autotune, n_passes)
+    p, x, plan, lay, passes, out = st["p"], st["x"], st["plan"], st["lay"], st["passes"], st["out"]
+    s, L, M = p["samples"], p["dump_len"], p["m_ant"]
 
     def step():
-        got = 0
-        for k in range(passes):
-            plan.reset_stream()
-            for c in range(p["n_chan"]):
-                plan.set_active_dms(masks[k][c], chan=c)
-            plan.process_block(x, flush=True)
-            _, nd, _ = plan.fetch(out=out)
-            got += nd
-        return got
+        return sum(c3_pass(st, k) for k in range(passes))
 
     for w in range(warmup):
         step()
@@ -814,6 +852,7 @@ def c3_measure(dev, steps, warmup, corr, use_autotune, n_passes):
     }
     plan.close()
     del x, out
+    st.clear()
     torch.cuda.empty_cache()
     return rec
 
@@ -1024,23 +1063,7 @@ def main():
     kw = {"wave_units": args.wave_units, "dm_group": args.dm_group}
     schedule = {"source": "automatic"}
     if not (args.wave_units or args.dm_group):
-        # the autotuner's choice for the whole 64-channel workload (also when --channels
-        # runs a part of it, so that counter runs see the headline's launch shapes):
-        # from the committed cache, or measured now with --autotune
-        from paper_1109_3186_amd import autotune
-        targs = (p["m_ant"], full_fc, p["f_s"], p["dump_len"], [dms] * len(full_fc))
-        tuned = (autotune.tune(*targs, corr_dtype=args.corr, max_block=args.chunk, log=log) if args.autotune
-                 else autotune.cached(*targs, corr_dtype=args.corr, max_block=args.chunk))
-        if not tuned:
-            key, desc = autotune.workload_key(*targs, args.corr, "ci8", args.chunk)
-            log("no tuned entry for key %s (device %r): automatic schedule" % (key, desc["device"]))
-        if tuned:
-            kw = autotune.plan_kwargs(tuned)
-            schedule = {"source": "autotuned (%s)" % tuned["source"], "wave_units": tuned["wave_units"],
-                        "dm_group": tuned["dm_group"]}
-            log("tuned (%s): cost model inverse %s ps, forward %s ps per point (N 2^8..2^18), wave %d group %d" % (
-                tuned["source"], [round(v, 2) for v in tuned["cost_ps"][0]],
-                [round(v, 2) for v in tuned["cost_ps"][1]], tuned["wave_units"], tuned["dm_group"]))
+        kw, schedule = c1_schedule(p, full_fc, dms, args.corr, args.chunk, args.autotune)
     def make_plan(**extra):
         opts = dict(kw, corr_dtype=args.corr)
         opts.update(extra)

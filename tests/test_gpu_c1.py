@@ -28,12 +28,18 @@ def c1_input(gpu):
     return p, chunks, pulses, fc, host
 
 
-def _run(p, chunks, fc, corr, pairs=None):
+def _run(p, chunks, fc, corr, pairs=None, extra=None):
     import torch
 
+    import bench
     from paper_1109_3186_amd import Plan
     dms = synth.dm_grid(p["n_dm"], p["dm_max"])
-    plan = Plan(p["m_ant"], fc, p["f_s"], p["dump_len"], max_block_samples=CHUNK, in_dtype="ci8", corr_dtype=corr)
+    # the schedule bench.py runs (the tuned entry of the FP32 workload for every form)
+    kw, schedule = bench.c1_schedule(p, fc, dms, "f32", CHUNK)
+    kw.update(extra or {})
+    say("schedule: %s %s" % (schedule, extra or ""))
+    plan = Plan(p["m_ant"], fc, p["f_s"], p["dump_len"], max_block_samples=CHUNK, in_dtype="ci8", corr_dtype=corr,
+                **kw)
     plan.set_dm_trials(dms)
     lay = plan.layout()
     m = p["m_ant"]
@@ -119,20 +125,25 @@ def test_c1_quantised_error_table(c1_input, corr, bound):
 
 
 def test_c1_learned_proposal(c1_input):
-    """The learned proposal on the full-size stream: every injected pulse's DM trial is
-    kept (or the proposal falls back to the full sweep), and visibilities of the
-    kept DMs are bitwise those of the full sweep."""
+    """The learned proposal on the full-size stream, in the plan configuration bench.py
+    times for it (the tuned schedule, one blocking class per channel): every injected
+    pulse's DM trial is kept (or the proposal falls back to the full sweep), and
+    visibilities of the kept DMs are bitwise those of the full sweep with the same
+    options."""
     import math
     import os
 
     import torch
 
+    import bench
     from paper_1109_3186_amd import Plan
     from paper_1109_3186_amd.proposal import Proposal, load_weights
     p, chunks, pulses, fc, host = c1_input
     wpath = os.path.join(os.path.dirname(os.path.dirname(__file__)), "paper_1109_3186_amd", "proposal_weights.npz")
     dms = synth.dm_grid(p["n_dm"], p["dm_max"])
-    plan = Plan(p["m_ant"], fc, p["f_s"], p["dump_len"], max_block_samples=CHUNK, in_dtype="ci8")
+    kw, _ = bench.c1_schedule(p, fc, dms, "f32", CHUNK)
+    plan = Plan(p["m_ant"], fc, p["f_s"], p["dump_len"], max_block_samples=CHUNK, in_dtype="ci8",
+                dm_classes="single", **kw)
     plan.set_dm_trials(dms)
     full = torch.cat(chunks, dim=-1).contiguous()
     prop = Proposal(plan, load_weights(wpath), budget=0.1)
@@ -156,6 +167,6 @@ def test_c1_learned_proposal(c1_input):
             got[d].append(v[:, lay["dm_offset"][63] + d].cpu().numpy())
     prop.close()
     plan.close()
-    ref, _, _, _ = _run(p, chunks, fc, "f32", pairs=[(63, int(d)) for d in active])
+    ref, _, _, _ = _run(p, chunks, fc, "f32", pairs=[(63, int(d)) for d in active], extra={"dm_classes": "single"})
     for d in active:
         assert np.array_equal(np.concatenate(got[d]), ref[(63, int(d))])
