@@ -26,6 +26,9 @@ UNIT = "antenna-samples*DM-trials/s"
 PEAKS = {  # MI355X published dense peaks
     "hbm_gbs": 8000.0, "fp32_vector_tflops": 157.3, "fp32_mfma_tflops": 157.3, "fp16_mfma_tflops": 2500.0,
     "fp8_mfma_tflops": 5000.0,
+    # FP32 FMA without packed instructions: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+    # (the published vector figure counts two FMAs per lane per cycle, from packed FP32)
+    "fp32_vector_unpacked_tflops": 256 * 4 * 16 * 2 * 2.4e9 / 1e12,
 }
 
 
@@ -971,6 +974,9 @@ def roofline_of(prof, args, p=None, ms_step=None):
     else:
         r = {"bound": "alu", "achieved": round(tflops, 2), "peak": PEAKS["fp32_vector_tflops"], "unit": "TFLOP/s",
              "frac": round(tflops / PEAKS["fp32_vector_tflops"], 4)}
+        up = PEAKS["fp32_vector_unpacked_tflops"]
+        r["unpacked_fp32"] = {"peak": round(up, 1), "frac": round(tflops / up, 4),
+                              "note": "the FP32 FMA rate without packed instructions, which this build does not emit"}
         gbs = d["bytes"] / n / per_launch_s / 1e9
         r["staged_model"] = {"gbs": round(gbs, 1), "frac_of_hbm": round(gbs / PEAKS["hbm_gbs"], 4),
                              "note": "modelled bytes (8 N / V + b_y per unit), not measured"}
