@@ -358,7 +358,8 @@ typedef struct ddx_cnn ddx_cnn;
 int ddx_cnn_num_params(int64_t* n_params);
 
 /* Allocate a network for tiles of n_dm rows and n_bins bins (a multiple of 64),
- * at most max_tiles per call.  Parameters start at zero: set them. */
+ * at most max_tiles per call, n_dm * max_tiles <= 65535 rows (DDX_EINVAL
+ * otherwise).  Parameters start at zero: set them. */
 int ddx_cnn_create(int32_t n_dm, int32_t n_bins, int32_t max_tiles, ddx_cnn** out);
 
 /* Copy parameters from host memory (resets the Adam state) / to host memory;

@@ -23,6 +23,7 @@ constexpr int64_t kOffW5 = kNW1 + kW + 3 * (kNW + kW);
 constexpr int64_t kOffB5 = kOffW5 + kW;
 constexpr int64_t kNParams = kOffB5 + 1;
 constexpr int kChunks = 256;  // row chunks of the weight-gradient reduction
+constexpr int64_t kMaxRows = 65535;  // the convolutions' grids take one y index per row
 
 }  // namespace
 
@@ -89,6 +90,7 @@ int ddx_cnn_num_params(int64_t* n) {
 
 int ddx_cnn_create(int32_t n_dm, int32_t n_bins, int32_t max_tiles, ddx_cnn** out) {
   if (!out || n_dm < 1 || max_tiles < 1 || n_bins < 64 || n_bins % 64 != 0) return DDX_EINVAL;
+  if ((int64_t)n_dm * max_tiles > kMaxRows) return DDX_EINVAL;  // one grid row per DM row
   ddx_cnn* n = new (std::nothrow) ddx_cnn;
   if (!n) return DDX_ENOMEM;
   n->n_dm = n_dm;

@@ -376,3 +376,16 @@ def test_blocking_cost_table_steers_the_classes():
     bad[1, 3] = 0.0
     with pytest.raises(DdxError):
         plan_blocking([1.2e9], 1e6, 1000, dms, cost_ps=bad)
+
+
+def test_cnn_create_rejects_bad_shapes():
+    """ddx_cnn_create validates before touching the device: bins not a multiple of 64,
+    no rows, and more rows than the convolutions' grids take are refused."""
+    import ctypes as ct
+
+    from paper_1109_3186_amd.binding import lib
+    h = ct.c_void_p()
+    for n_dm, n_bins, tiles in ((256, 100, 1), (0, 1024, 1), (256, 1024, 0), (4096, 1024, 16), (65536, 64, 1)):
+        assert lib().ddx_cnn_create(n_dm, n_bins, tiles, ct.byref(h)) == -1, (n_dm, n_bins, tiles)
+    assert lib().ddx_cnn_set_precision(None, 1) == -1
+    assert lib().ddx_cnn_get_activations(None, 1, None, 0) == -1
