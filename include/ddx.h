@@ -84,7 +84,7 @@ typedef struct ddx_desc {
   int32_t out_mode;            /* DDX_OUT_* */
   const float* chan_scale;     /* [C] power-of-two correlator-input scales, or NULL = rule below */
   /* Schedule (all 0 = automatic; see ddx_process_block for the work list): */
-  int32_t wave_units;          /* (channel, DM, block) units per wave, >= 0 */
+  int32_t wave_units;          /* (channel, DM, block) units per wave, 0 (automatic) .. 65535 */
   int32_t dm_group;            /* DMs of one channel run back to back on each block, >= 0 */
   /* Dump records (see ddx_fetch_visibilities): */
   int32_t compact_records;     /* 0: every (channel, DM) in every record; 1: only the active ones */
@@ -338,7 +338,8 @@ int ddx_power_tile(ddx_plan* plan, const void* d_volts, int64_t n, int32_t bin_l
 /* The same tiles for n_tiles streams given as power already summed over antennas
  * and over fine bins of `fine` samples: d_power [n_tiles][C][units] FP32 (device).
  * Shifts are rounded to whole fine bins; bin_len must be a multiple of fine.
- * Output [n_tiles][D][n_bins]. */
+ * Output [n_tiles][D][n_bins].  n_tiles x C <= 65535 and D <= 65535 (EINVAL /
+ * EUNSUPPORTED otherwise). */
 int ddx_power_tile_from_power(ddx_plan* plan, const float* d_power, int32_t n_tiles, int64_t units, int32_t fine,
                               int32_t bin_len, int32_t n_bins, float* d_tiles, void* hip_stream);
 

@@ -423,13 +423,19 @@ hipError_t launch_forward(int logn, int in_dtype, const ddx::FwdArgs& a, int n_i
 hipError_t launch_forward_big(int logn, int in_dtype, ddx::FwdArgs a, const ddx::FwdItem* first_host, int n_items,
                               float2* tb, hipStream_t s) {
   const int logr = logn - ddx::kBigLog;
-  const dim3 gpre(ddx::kBigN / 256, n_items * a.n_ant);
-  if (in_dtype == DDX_IN_CI8)
-    hipLaunchKernelGGL(ddx::k_forward_big_pre<0>, gpre, dim3(256), 0, s, a, tb, logr);
-  else
-    hipLaunchKernelGGL(ddx::k_forward_big_pre<1>, gpre, dim3(256), 0, s, a, tb, logr);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  // the pre-pass grid takes one y index per (item, antenna): at most 65535 per launch
+  const int per = std::max(1, 65535 / a.n_ant);
+  for (int i0 = 0; i0 < n_items; i0 += per) {
+    ddx::FwdArgs ai = a;
+    ai.items = a.items + i0;  // each item carries its own source window and tb offset
+    const dim3 gpre(ddx::kBigN / 256, (unsigned)(std::min(per, n_items - i0) * a.n_ant));
+    if (in_dtype == DDX_IN_CI8)
+      hipLaunchKernelGGL(ddx::k_forward_big_pre<0>, gpre, dim3(256), 0, s, ai, tb, logr);
+    else
+      hipLaunchKernelGGL(ddx::k_forward_big_pre<1>, gpre, dim3(256), 0, s, ai, tb, logr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   const unsigned rows = (unsigned)((size_t)n_items * a.n_ant << logr);
   hipLaunchKernelGGL(ddx::k_fft_rows, dim3(rows), dim3(ddx::Geo<ddx::RowPlan>::T), fft_lds_bytes<ddx::kBigLog>(), s,
                      (const float2*)tb, a.spec + first_host->spec, a.l1, logr);
@@ -778,6 +784,7 @@ int ddx_plan_create(const ddx_desc* d, ddx_plan** out) {
   if (d->out_mode != DDX_OUT_PACKED && d->out_mode != DDX_OUT_FULL) return DDX_EINVAL;
   if (d->k_dm < 0 || !std::isfinite(d->k_dm)) return DDX_EINVAL;
   if (d->wave_units < 0 || d->dm_group < 0 || d->max_record_pairs < 0 || d->ring_dumps < 0) return DDX_EINVAL;
+  if (d->wave_units > 65535) return DDX_EINVAL;  // the chirp launch takes one grid row per (channel, DM) of a wave
   if (d->compact_records != 0 && d->compact_records != 1) return DDX_EINVAL;
   if (d->dm_classes != 0 && d->dm_classes != 1) return DDX_EINVAL;
   if (d->spectrum_bytes < 0) return DDX_EINVAL;
@@ -1560,6 +1567,7 @@ int tile_checks(ddx_plan* p, int bin_len, int n_bins, int fine) {
     if (c.dm != p->ch[0].dm) return fail(p, DDX_EUNSUPPORTED, "tiles need the same DM trials in every channel");
   if (fine < 1 || bin_len < fine || bin_len % fine != 0 || n_bins < 1)
     return fail(p, DDX_EINVAL, "bin_len must be a positive multiple of the fine bin, n_bins >= 1");
+  if ((int)p->ch[0].dm.size() > 65535) return fail(p, DDX_EUNSUPPORTED, "tiles take at most 65535 DM trials");
   return DDX_OK;
 }
 
@@ -1590,6 +1598,8 @@ int ddx_power_tile_from_power(ddx_plan* p, const float* d_power, int32_t n_tiles
   int rc = tile_checks(p, bin_len, n_bins, fine);
   if (rc) return rc;
   if (!d_power || !d_tiles || n_tiles < 1 || units < 1) return fail(p, DDX_EINVAL, "null buffer or empty input");
+  if ((int64_t)n_tiles * p->C > 65535)  // the scans' grids take one y index per (tile, channel) row
+    return fail(p, DDX_EINVAL, "n_tiles x channels must be at most 65535");
   return tiles_from_rows(p, d_power, n_tiles, units, fine, bin_len, n_bins, d_tiles, (hipStream_t)hip_stream);
 }
 

@@ -389,3 +389,15 @@ def test_cnn_create_rejects_bad_shapes():
         assert lib().ddx_cnn_create(n_dm, n_bins, tiles, ct.byref(h)) == -1, (n_dm, n_bins, tiles)
     assert lib().ddx_cnn_set_precision(None, 1) == -1
     assert lib().ddx_cnn_get_activations(None, 1, None, 0) == -1
+
+
+def test_wave_size_above_the_grid_limit_is_refused():
+    """A wave holds at most 65535 units (one chirp grid row per (channel, DM) of a
+    wave): larger requests fail at plan creation, before any device call."""
+    import pytest as _pytest
+
+    from paper_1109_3186_amd import DdxError, Plan
+    with _pytest.raises(DdxError) as e:
+        Plan(4, [1.2e9], 1e6, 1000, max_block_samples=1 << 16, wave_units=65536)
+    assert e.value.status == -1
+    Plan(4, [1.2e9], 1e6, 1000, max_block_samples=1 << 16, wave_units=65535).close()
