@@ -245,3 +245,43 @@ def test_dm_classes_with_masks_and_compact_records(gpu):
     for c, m in enumerate([m0, m1]):
         for d in np.nonzero(m)[0]:
             assert np.array_equal(select(comp, lc, c, int(d)), select(ref, lay, c, int(d)))
+
+
+def test_two_pass_forward_beyond_one_grid(gpu):
+    """256 antennas, 65536-point (two-pass) transforms, one call of 2^24 samples: the
+    forward pre-pass of the call's ~265 blocks needs more (block, antenna) grid rows
+    than one launch takes (65535) and runs in slices; the visibilities are bitwise
+    those of the same stream in four calls (no slicing)."""
+    import torch
+
+    from paper_1109_3186_amd import Plan
+    M, N, L, S = 256, 1 << 16, 16000, 1 << 24
+    fc = np.array([7.0e8])
+    dms = np.array([0.0, 40.0])
+    gen = torch.Generator(device=gpu)
+    gen.manual_seed(72)
+    x = torch.randint(-40, 41, (1, M, 2 * S), generator=gen, dtype=torch.int8, device=gpu)
+
+    def run(chunk, spectrum_bytes):
+        outs = []
+        with Plan(M, fc, 1e6, L, max_block_samples=chunk, in_dtype="ci8", fft_len=N,
+                  spectrum_bytes=spectrum_bytes) as p:
+            p.set_dm_trials(dms)
+            lay = p.layout()
+            for s0 in range(0, S, chunk):
+                p.process_block(x[..., 2 * s0:2 * (s0 + chunk)].contiguous(), flush=(s0 + chunk >= S))
+                _, nd, vis = p.fetch()
+                if nd:
+                    outs.append(vis.clone())
+            torch.cuda.synchronize()
+        return torch.cat(outs), lay
+
+    one, lay = run(S, 48 << 30)
+    blocks = -(-S // int(lay["valid"][0]))
+    say("one call: V %d, ~%d blocks x %d antennas = %d pre-pass rows" % (lay["valid"][0], blocks, M, blocks * M))
+    assert int(lay["fft_len"][0]) == N and blocks * M > 65535
+    four, _ = run(S // 4, 0)
+    assert one.shape == four.shape and one.shape[0] == S // L
+    assert torch.equal(one, four)
+    del one, four, x
+    torch.cuda.empty_cache()
