@@ -976,7 +976,7 @@ def roofline_of(prof, args, p=None, ms_step=None):
              "frac": round(tflops / PEAKS["fp32_vector_tflops"], 4)}
         up = PEAKS["fp32_vector_unpacked_tflops"]
         r["unpacked_fp32"] = {"peak": round(up, 1), "frac": round(tflops / up, 4),
-                              "note": "the FP32 FMA rate without packed instructions, which this build does not emit"}
+                              "note": "the FP32 FMA rate without packed instructions, which the library does not emit"}
         gbs = d["bytes"] / n / per_launch_s / 1e9
         r["staged_model"] = {"gbs": round(gbs, 1), "frac_of_hbm": round(gbs / PEAKS["hbm_gbs"], 4),
                              "note": "modelled bytes (8 N / V + b_y per unit), not measured"}

@@ -45,7 +45,7 @@ extern "C" {
 #define DDX_ESTATE (-4)       /* call not allowed in the plan's current state */
 #define DDX_ESIZE (-5)        /* caller buffer too small */
 #define DDX_EFULL (-6)        /* unfetched dumps would be overwritten */
-#define DDX_EUNSUPPORTED (-7) /* valid request this build does not implement */
+#define DDX_EUNSUPPORTED (-7) /* valid request this library does not implement */
 
 /* Input sample formats: interleaved (re, im). */
 #define DDX_IN_CI8 0  /* int8 re, int8 im: 2 bytes per sample */
