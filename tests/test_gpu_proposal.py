@@ -153,19 +153,21 @@ def test_cnn_fp16_forward_backward_match_oracle(gpu, level):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp16"])
-def test_cnn_ragged_shape_matches_oracle(gpu, precision):
+@pytest.mark.parametrize("d, L", [(5, 192), (3, 64)])
+def test_cnn_ragged_shape_matches_oracle(gpu, precision, d, L):
     """192 bins (layers of 192, 96, 48, 24 steps: every layer ends in a partial
-    64-step tile, and the last is shorter than one), 5 DM rows (edge rows repeated
-    on both sides of every tile), 3 tiles of different levels: scores, and the
-    gradients through the kernels' own gates and maxima, against the FP64 oracle."""
+    64-step tile, and the last is shorter than one) with 5 DM rows, and the smallest
+    shape, 64 bins (64, 32, 16, 8 steps) with 3 rows (edge rows repeated on both
+    sides of every tile); 3 tiles of different levels: scores, and the gradients
+    through the kernels' own gates and maxima, against the FP64 oracle."""
     import torch
 
     from paper_1109_3186_amd import Cnn
     from paper_1109_3186_amd.proposal import unflatten
-    rng = np.random.Generator(np.random.PCG64(50))
-    d, L, nt = 5, 192, 3
+    rng = np.random.Generator(np.random.PCG64(50 + L))
+    nt = 3
     tiles = rng.standard_normal((nt, d, L)) * np.array([1.0, 30.0, 0.01])[:, None, None] + 7
-    tiles[1, 0, 180:190] += 200.0  # a bump in the last partial tile of an edge row
+    tiles[1, 0, L - 12:L - 2] += 200.0  # a bump near the end of an edge row
     params = P.init_params(51)
     for l in range(1, 5):
         params["b%d" % l] = rng.standard_normal(32) * 0.05
@@ -181,12 +183,12 @@ def test_cnn_ragged_shape_matches_oracle(gpu, precision):
     net.backward()
     g = unflatten(net.get_grads())
     acts = [net.get_activations(l, nt * d).astype(np.float64) for l in range(1, 5)]
-    assert [a.shape[-1] for a in acts] == [192, 96, 48, 24]
+    assert [a.shape[-1] for a in acts] == [L, L // 2, L // 4, L // 8]
     dec = {"gates": [a > 0 for a in acts], "arg": np.argmax(acts[3], axis=2)}
     _, ds = P.loss_and_grad(ref, labels)
     gref = P.backward(params, cache, ds, decisions=dec)
     worst = max(np.linalg.norm(g[k] - gref[k]) / max(np.linalg.norm(gref[k]), 1e-300) for k in gref)
-    say("%s ragged: scores %.2e, worst gradient %.2e" % (precision, serr, worst))
+    say("%s %d x %d: scores %.2e, worst gradient %.2e" % (precision, d, L, serr, worst))
     assert serr <= tol
     assert worst <= (1e-3 if precision == "fp32" else 1e-2)
     net.close()
