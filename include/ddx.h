@@ -372,8 +372,8 @@ int ddx_cnn_get_grads(ddx_cnn* net, float* host_grads, int64_t n);
 /* Arithmetic of the three convolutions (forward, backward data, backward weights).
  * DDX_CNN_FP32 (the default): FP32 on the vector units.  DDX_CNN_FP16: operands
  * rounded to IEEE binary16 (RNE) and multiplied on the matrix cores with FP32
- * accumulation; every operand tile (a layer's weights, a row's window of 64 time
- * steps of activations or gradients) is first multiplied by a power of two that
+ * accumulation; every operand tile (a layer's weights, a row's window of 64 to 256
+ * time steps of activations or gradients) is first multiplied by a power of two that
  * puts its largest magnitude in [2^13, 2^14), undone exactly on the FP32 result.
  * Parameters, biases, pooling, the linear layer, the loss and Adam stay FP32 in
  * either form.  Changing the precision discards the last forward pass (run
